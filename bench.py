@@ -1,0 +1,158 @@
+"""Throughput of the two-site MPS update on one MI355X.
+
+Workload: TEBD4 (fourth-order Suzuki fractal of Strang steps) on the XXZ chain,
+L=64, Jxy=1, Jz=0.5, Neel start, dt=0.05, chi_max=256, eps_local=1e-12,
+complex128 chain (FP64 MFMA contractions, FP64 Jacobi SVD).  One step = one
+TEBD4 time step = 15 even/odd layers = 475 two-site updates.  The first W
+steps run untimed (chi grows from 1 towards chi_max), then exactly K steps are
+timed.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype c128|c64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
+FP32_MFMA_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=60)
+    ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1703_00387_amd import api, models
+
+    wl = W.xxz_tebd4_L64()
+    spec = wl.chains[0]
+    updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
+    h = api.Handle(0)
+    ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
+
+    t0 = time.time()
+    done = 0
+    while done < args.warmup:
+        n = min(10, args.warmup - done)
+        api.tebd_step(h, [ch], 4, wl.dt, n, wl.eps_local)
+        torch.cuda.synchronize()
+        done += n
+        print(f"[bench] warmup {done}/{args.warmup} steps, chi_max now {int(ch.chi.max())}, "
+              f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    code, word = h.device_status()
+
+    # snapshot of the state the timed region starts from (for the CPU baseline)
+    snap = ch.to_host() if not args.no_cpu else None
+
+    h.set_option(3, 1.0)
+    h.kernel_stats("theta", reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.tebd_step(h, [ch], 4, wl.dt, args.steps, wl.eps_local)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    elapsed = t2 - t1
+    stats = {k: h.kernel_stats(k) for k in ("theta", "jac_round", "select", "wb_right", "gemm", "prep", "gates")}
+    h.set_option(3, 0.0)
+    code2, word2 = h.device_status()
+    chi = ch.chi.cpu().numpy()
+    n_upd = updates_per_step * args.steps
+    value = n_upd / elapsed
+
+    jr_ms, jr_n, jr_work = stats["jac_round"]
+    th_ms, th_n, th_work = stats["theta"]
+    gm_ms, gm_n, gm_work = stats["gemm"]
+    jr_avg_s = jr_ms * 1e-3 / max(jr_n, 1)
+    jr_ach = (jr_work / max(jr_n, 1)) / jr_avg_s / 1e12 if jr_n else 0.0
+    th_ach = th_work / (th_ms * 1e-3) / 1e12 if th_ms > 0 else 0.0
+    mfma_peak = FP64_PEAK_TFLOPS if args.dtype == "c128" else FP32_MFMA_PEAK_TFLOPS
+    kernel_share = {k: round(v[0] / (elapsed * 1e3), 4) for k, v in stats.items()}
+
+    out = {
+        "metric": "two-site MPS updates/s (TEBD4 XXZ L=64, chi_max=256)",
+        "value": round(value, 2),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128 (FP64 MFMA contractions, FP64 SVD)" if args.dtype == "c128"
+        else "c64 (FP32 MFMA contractions, FP64 SVD)",
+        "data": "synthetic",
+        "config": {"workload": "xxz_tebd4_L64: TEBD4 XXZ L=64 Jxy=1 Jz=0.5 Neel dt=0.05 chi_max=256 eps=1e-12",
+                   "updates_per_step": updates_per_step, "start_step": args.warmup,
+                   "chi_hist": {"max": int(chi.max()), "mean": round(float(chi.mean()), 1),
+                                "n_at_cap": int((chi >= spec.chi_max).sum())}},
+        "roofline": {"kernel": "jac_round_kernel (FP64 block-Jacobi round: Gram + rotation)",
+                     "bound": "alu", "achieved": round(jr_ach, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(jr_ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "avg_launch_us": round(jr_avg_s * 1e6, 2), "launches": jr_n},
+        "mfma": {"kernel": "theta_gate_kernel", "achieved": round(th_ach, 3), "peak": mfma_peak,
+                 "unit": "TFLOP/s", "frac": round(th_ach / mfma_peak, 4)},
+        "kernel_time_share": kernel_share,
+        "device_status": [code, word, code2, word2],
+    }
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, wl, snap, args.cpu_seconds)
+    print(json.dumps(out))
+    h.close()
+
+
+def cpu_baseline(spec, wl, snap, budget_s):
+    """The complex128 oracle's bond update, timed on the host cores on a sample
+    of the very state the GPU's timed region starts from: the bonds of the
+    first layer of a TEBD4 step, largest bond dimension first, until the time
+    budget is used."""
+    import numpy as np
+
+    from oracle import models as om, mps as omps
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:
+        threads = os.cpu_count()
+    B, lam, chi = snap
+    psi = omps.MPS([b.copy() for b in B], [l.copy() for l in lam], spec.d)
+    hs = om.bond_hamiltonians(spec)
+    tau = 0.5 * omps.P4 * wl.dt
+    bonds = sorted(range(0, spec.L - 1, 2), key=lambda b: -min(chi[b], chi[b + 2]))
+    t0 = time.perf_counter()
+    n = 0
+    for b in bonds:
+        omps.apply_bond(psi, b, omps.gate(hs[b], tau), spec.chi_max, wl.eps_local)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 3), "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} odd-bond updates of the TEBD4 first layer at the timed region's start state "
+                      f"(chi up to {int(max(chi))}), largest chi first, {dt:.1f}s"}
+
+
+if __name__ == "__main__":
+    main()

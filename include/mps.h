@@ -1,0 +1,188 @@
+/*
+ * mps.h -- C ABI of libmps, the gfx950 (MI355X) two-site MPS update.
+ *
+ * The library implements the hot path of matrix-product-state time evolution
+ * described in Jaschke, Wall, Carr, "Open source Matrix Product States"
+ * (arXiv:1703.00387):
+ *   theta = A_i . A_{i+1}          (Sec. "Basic concepts", Contractions)
+ *   theta' = G theta or exp(-i tau H_eff) theta
+ *                                  (Secs. "Sornborger-Stewart decomposition",
+ *                                   "Krylov time evolution", App. "Details of
+ *                                   the Krylov method")
+ *   theta' = U S V^dag, cut to chi (Sec. "Basic concepts", Splitting; Eqs.
+ *                                   overlap and elocal; App. "Auxiliary
+ *                                   calculations")
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - complex64  = interleaved (re, im) float; complex128 = interleaved double.
+ * - All arrays are row-major (C order).  Device pointers unless stated.
+ * - Every call is asynchronous on `stream` (a hipStream_t; NULL = default
+ *   stream) and returns an mps_status.  Argument and shape errors return at
+ *   once, before any work is queued; the message is kept in mps_last_error().
+ *   Numerical problems found on the device (non-finite values, a Jacobi or
+ *   Lanczos iteration that did not converge) set bits of a device status word
+ *   that mps_device_status() reads; the call still writes a best-effort
+ *   result.  No C++ exception and no abort crosses this ABI.
+ * - Ownership: the caller owns every input and output buffer.  The handle
+ *   owns a device workspace that it grows with hipMalloc when a call needs
+ *   more (never while the stream is being captured: reserve first with
+ *   mps_reserve); it is freed by mps_destroy.  No pointer passed in is kept
+ *   after a call returns.
+ * - Calls that share one handle must not run concurrently on different
+ *   streams: they share the workspace.
+ */
+#ifndef MPS_H_
+#define MPS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPS_OK = 0,
+  MPS_ERR_INVALID = 1,     /* bad argument (NULL pointer, bad flag, ...)      */
+  MPS_ERR_SHAPE = 2,       /* inconsistent dimensions                         */
+  MPS_ERR_CAPACITY = 3,    /* a size beyond a compiled or declared capacity   */
+  MPS_ERR_NOCONV = 4,      /* iteration did not converge (device status bit)  */
+  MPS_ERR_NONFINITE = 5,   /* NaN/Inf met on the device (device status bit)   */
+  MPS_ERR_HIP = 6,         /* a HIP runtime call failed                       */
+  MPS_ERR_UNSUPPORTED = 7  /* valid request the library does not implement    */
+} mps_status;
+
+/* bits of the device status word */
+#define MPS_DEV_NOCONV_SVD     0x1u
+#define MPS_DEV_NOCONV_LANCZOS 0x2u
+#define MPS_DEV_NONFINITE      0x4u
+
+typedef struct mps_context* mps_handle;
+typedef void* mps_stream; /* hipStream_t */
+
+/* Create a handle bound to HIP device `device` (made current).  */
+mps_status mps_create(mps_handle* h, int device);
+/* Free the handle and its workspace (synchronises the device first). */
+mps_status mps_destroy(mps_handle h);
+/* Message of the last error returned on this handle ("" if none). */
+const char* mps_last_error(mps_handle h);
+/* Make the workspace at least `bytes` large (hipMalloc happens here). */
+mps_status mps_reserve(mps_handle h, size_t bytes);
+/* Synchronise `stream`, return and clear the device status word. */
+mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
+/* Tuning knobs: 0 = Jacobi relative tolerance (default 1e-13),
+ * 1 = Jacobi maximum sweeps (default 30), 2 = Jacobi absolute tolerance
+ * relative to |theta|_F^2 (default 1e-15), 3 = kernel timing on (!= 0) or
+ * off (0): HIP events around every launch of the timed kernels on the call's
+ * stream, plus device counters of the useful work they perform (not inside
+ * captured graphs). */
+mps_status mps_set_option(mps_handle h, int option, double value);
+/* Accumulated timing of one kernel class since the last reset:
+ * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,
+ * 3 = right write-back, 4 = left write-back GEMM, 5 = Jacobi preparation,
+ * 6 = propagators.  total_ms = summed event durations, launches = count,
+ * work = useful flops counted on the device (kernels 0, 1 and 4; else 0).
+ * Synchronises `stream`.  reset != 0 clears all classes afterwards. */
+mps_status mps_kernel_stats(mps_handle h, mps_stream stream, int32_t kernel, double* total_ms,
+                            int64_t* launches, uint64_t* work, int32_t reset);
+
+/*
+ * a1. Bond propagators G_n = exp(-i tau_n h_n)   (the local two-site
+ * propagator, step 2 of the plain TEBD update in App. "Details of the Krylov
+ * method"; built by a Hermitian
+ * Jacobi eigendecomposition h = V diag(e) V^dag in FP64, G = V e^{-i tau e} V^dag).
+ *   hmat  : complex128 [n][dd][dd], Hermitian (dd = d*d <= 32)
+ *   tau   : FP64 [n] (real time step of each propagator)
+ *   G64   : complex64 [n][dd][dd] output (may be NULL)
+ *   G128  : complex128 [n][dd][dd] output (may be NULL)
+ */
+mps_status mps_gates(mps_handle h, mps_stream stream, int32_t n, int32_t dd,
+                     const void* hmat, const double* tau, void* G64, void* G128);
+
+/*
+ * a7. Truncated SVD of one two-site tensor (Sec. "Basic concepts",
+ * Splitting, SVD case; truncation and discarded weight per Eqs. overlap and
+ * elocal; renormalisation of the kept values per App. "Auxiliary calculations").  The SVD runs in FP64 (one-sided block Jacobi).
+ *   theta   : complex128 [m][n] input (not modified), m = chi_l*d_l, n = d_r*chi_r
+ *   chi_max : cap on the kept count k
+ *   eps     : local tolerance: k = min(chi_max, min{k>=1 : sum_{j>k} s_j^2
+ *             <= eps * sum_j s_j^2}); values sorted descending
+ *   U       : complex128 [m][chi_max] (first k columns written)
+ *   S       : FP64 [chi_max] kept singular values, NOT renormalised
+ *   Vh      : complex128 [chi_max][n] (first k rows written)
+ *   k_dev   : int32 [1] kept count; disc_dev : FP64 [1] discarded weight
+ *             sum_{j>k} s_j^2; norm2_dev : FP64 [1] sum_j s_j^2
+ * Limits: m, n <= 4096.
+ */
+mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n,
+                        int64_t chi_max, double eps, void* U, double* S, void* Vh,
+                        int32_t* k_dev, double* disc_dev, double* norm2_dev);
+
+/*
+ * A chain in Vidal/Hastings form (B_i = Gamma_i Lambda_{i+1}, right-canonical):
+ * |psi> = lam_0 B_0 B_1 ... B_{L-1} (Eq. mps with the Schmidt values of
+ * Eq. schmidt on the bonds).  Sites 0..L-1; virtual bond j sits left of site j.
+ *   dtype : MPS_C64 (B complex64, contractions on FP32 MFMA with FP32
+ *           accumulation) or MPS_C128 (B complex128, FP64 MFMA); the SVD,
+ *           Schmidt values and observables are FP64 either way
+ *   B     : L blocks of [chi_max][d][chi_max] of dtype; site i at
+ *           B + i*chi_max*d*chi_max, element (a,s,c) at (a*d+s)*chi_max+c
+ *   lam   : FP64, (L+1) blocks of [chi_max]; lam_0 = lam_L = {1}
+ *   chi   : int32 [L+1] current bond dimensions; chi[0] = chi[L] = 1
+ *   hbond : complex128 [L-1][d*d][d*d]; bond b couples sites b, b+1, with
+ *           row index (s_out*d + t_out) and column index (s_in*d + t_in)
+ *   disc  : FP64 [L-1]; the discarded weight of every update of bond b is
+ *           added to disc[b]
+ */
+#define MPS_C64 0
+#define MPS_C128 1
+
+typedef struct {
+  int32_t L, d, chi_max, dtype;
+  void* B;
+  double* lam;
+  int32_t* chi;
+  const void* hbond;
+  double* disc;
+} mps_chain_desc;
+
+#define MPS_FLAG_GRAPH 0x1u     /* capture the whole call in a hipGraph and replay it */
+#define MPS_FLAG_FIXED_SWEEPS 0x2u /* no host synchronisation inside the call */
+
+/*
+ * a2-a8, a12. n_steps time steps of even/odd Trotter evolution on every chain
+ * (Sec. "Sornborger-Stewart decomposition": the even/odd Suzuki-Trotter
+ * alternative the paper names; order 2 =
+ * Strang splitting: odd bonds tau/2, even bonds tau, odd bonds tau/2; order 4
+ * = five Strang steps with weights p,p,1-4p,p,p, p = 1/(4-4^(1/3)), error
+ * O(dt^4)).  Every update: theta~ = B_b B_{b+1} and theta~' = G theta~ on
+ * FP32 MFMA (complex64), theta' = lam_b theta~' promoted to FP64, FP64 SVD,
+ * truncation by the count rule with eps_local and chi_max, lam_{b+1} =
+ * s/|s_k|, B_{b+1} = V^dag_k, B_b = theta~' V_k / |s_k|.  All bonds of one
+ * layer of all chains are processed together.
+ *   chains : HOST array of n_chains descriptors (device pointers inside)
+ *   flags  : MPS_FLAG_* bits
+ */
+mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                         int32_t n_chains, int32_t order, double dt, int32_t n_steps,
+                         double eps_local, uint32_t flags);
+
+/*
+ * a11. Observables of a Hastings-form chain (Sec. "Observables",
+ * reduced density matrices of Eq. reducedrho):
+ *   site_out[i] = Re sum lam_i[a]^2 conj(B_i[a,s',c]) op1[s',s] B_i[a,s,c]
+ *   bond_out[b] = Re <theta_b| op2_b |theta_b>, theta_b = lam_b B_b B_{b+1}
+ *   entropy_out[b] = -sum_a lam_{b+1}[a]^2 ln lam_{b+1}[a]^2
+ *   op1 : complex128 [d][d] (or NULL); op2 : complex128 [L-1][d*d][d*d] when
+ *         op2_per_bond != 0, else [d*d][d*d] (or NULL)
+ *   outputs FP64 device arrays [L], [L-1], [L-1] (any may be NULL)
+ */
+mps_status mps_observe(mps_handle h, mps_stream stream, const mps_chain_desc* chain,
+                       const void* op1, double* site_out, const void* op2, int32_t op2_per_bond,
+                       double* bond_out, double* entropy_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPS_H_ */

@@ -1,0 +1,81 @@
+"""ctypes binding of libmps.so (argument marshalling only).
+
+Every entry point of include/mps.h is exposed under the same name.  Tensors
+are passed as raw device pointers (``tensor.data_ptr()``) and the current
+PyTorch HIP stream (``torch.cuda.current_stream().cuda_stream``).  The
+library must have been built (``python -m paper_1703_00387_amd.build``); if it
+is missing the import fails loudly -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmps.so")
+
+MPS_OK, MPS_ERR_INVALID, MPS_ERR_SHAPE, MPS_ERR_CAPACITY, MPS_ERR_NOCONV, MPS_ERR_NONFINITE, \
+    MPS_ERR_HIP, MPS_ERR_UNSUPPORTED = range(8)
+STATUS_NAMES = {0: "MPS_OK", 1: "MPS_ERR_INVALID", 2: "MPS_ERR_SHAPE", 3: "MPS_ERR_CAPACITY",
+                4: "MPS_ERR_NOCONV", 5: "MPS_ERR_NONFINITE", 6: "MPS_ERR_HIP", 7: "MPS_ERR_UNSUPPORTED"}
+MPS_DEV_NOCONV_SVD, MPS_DEV_NOCONV_LANCZOS, MPS_DEV_NONFINITE = 0x1, 0x2, 0x4
+MPS_FLAG_GRAPH, MPS_FLAG_FIXED_SWEEPS = 0x1, 0x2
+MPS_C64, MPS_C128 = 0, 1
+
+# every exported symbol that include/mps.h declares
+EXPORTS = ["mps_create", "mps_destroy", "mps_last_error", "mps_reserve", "mps_device_status",
+           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_tebd_step",
+           "mps_observe"]
+
+
+class ChainDesc(C.Structure):
+    _fields_ = [("L", C.c_int32), ("d", C.c_int32), ("chi_max", C.c_int32), ("dtype", C.c_int32),
+                ("B", C.c_void_p), ("lam", C.c_void_p), ("chi", C.c_void_p), ("hbond", C.c_void_p),
+                ("disc", C.c_void_p)]
+
+
+class MPSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1703_00387_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint32
+    sig = {
+        "mps_create": [C.POINTER(vp), C.c_int],
+        "mps_destroy": [vp],
+        "mps_reserve": [vp, C.c_size_t],
+        "mps_device_status": [vp, vp, C.POINTER(u32)],
+        "mps_set_option": [vp, C.c_int, dbl],
+        "mps_kernel_stats": [vp, vp, i32, C.POINTER(dbl), C.POINTER(i64), C.POINTER(C.c_uint64), i32],
+        "mps_gates": [vp, vp, i32, i32, vp, vp, vp, vp],
+        "mps_truncate": [vp, vp, vp, i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp],
+        "mps_tebd_step": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32],
+        "mps_observe": [vp, vp, C.POINTER(ChainDesc), vp, vp, vp, i32, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.mps_last_error.argtypes = [vp]
+    L.mps_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(h, code):
+    if code != MPS_OK:
+        msg = lib().mps_last_error(h)
+        raise MPSError(code, msg.decode() if msg else "")
+    return code

@@ -1,0 +1,531 @@
+// Host side of libmps: handle, workspace, argument checks, and the drivers
+// that queue the kernels of the two-site update on a HIP stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kJacBlock = 16;   // rows per Jacobi block
+constexpr int kFixedSweeps = 14;  // sweeps queued when the host may not synchronise
+
+int jac_nb(int m) {
+  int nb = (m + kJacBlock - 1) / kJacBlock;
+  if (nb < 2) nb = 2;
+  if (nb & 1) nb++;
+  return nb;
+}
+
+// Upload a host array into workspace memory and wait for it (descriptors only).
+template <class T>
+mps_status upload(mps_handle h, hipStream_t s, void* dst, const std::vector<T>& src) {
+  if (src.empty()) return MPS_OK;
+  MPS_TRY_HIP(h, hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  return MPS_OK;
+}
+
+// Run the Jacobi sweeps on mats[0..n) (already prepared on the device).
+mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
+                      bool fixed) {
+  const int nb = nb_cap;
+  const int max_sweeps = fixed ? std::min(kFixedSweeps, h->jac_max_sweeps) : h->jac_max_sweeps;
+  bool done = false;
+  for (int sw = 0; sw < max_sweeps && !done; ++sw) {
+    MPS_TRY_HIP(h, launch_jac_sort(s, mats, n, m_cap));
+    for (int r = 0; r < nb - 1; ++r)
+      PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs,
+                                                              h->profile ? h->stats_dev : nullptr));
+    MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
+    if (!fixed && sw >= 1) {
+      if (h->profile) {
+        mps_status ps = prof_harvest(h, s);
+        if (ps != MPS_OK) return ps;
+      }
+      MPS_TRY_HIP(h, hipMemcpyAsync(h->host_pinned, unconv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      MPS_TRY_HIP(h, hipStreamSynchronize(s));
+      if (h->host_pinned[0] == 0) done = true;
+    }
+  }
+  if (!done) MPS_TRY_HIP(h, launch_jac_flag_noconv(s, unconv, h->status_dev));
+  return MPS_OK;
+}
+
+}  // namespace
+
+void prof_begin(mps_handle h, hipStream_t s, int id) {
+  size_t i = h->ev_pending.size() * 2;
+  while (h->ev_pool.size() < i + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    h->ev_pool.push_back(e);
+  }
+  hipEventRecord(h->ev_pool[i], s);
+  h->ev_pending.push_back({id, (int)i});
+}
+
+void prof_end(mps_handle h, hipStream_t s, int id) {
+  (void)id;
+  if (h->ev_pending.empty()) return;
+  hipEventRecord(h->ev_pool[h->ev_pending.back().second + 1], s);
+}
+
+mps_status prof_harvest(mps_handle h, hipStream_t s) {
+  if (h->ev_pending.empty()) return MPS_OK;
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  for (auto& pr : h->ev_pending) {
+    float ms = 0.f;
+    MPS_TRY_HIP(h, hipEventElapsedTime(&ms, h->ev_pool[pr.second], h->ev_pool[pr.second + 1]));
+    h->k_ms[pr.first] += ms;
+    h->k_launches[pr.first] += 1;
+  }
+  h->ev_pending.clear();
+  return MPS_OK;
+}
+
+mps_status mps_fail(mps_handle h, mps_status code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+mps_status mps_ensure_ws(mps_handle h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return MPS_OK;
+  size_t want = std::max(bytes, h->ws_bytes + h->ws_bytes / 4);
+  if (h->ws) {
+    MPS_TRY_HIP(h, hipDeviceSynchronize());
+    MPS_TRY_HIP(h, hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  hipError_t e = hipMalloc((void**)&h->ws, want);
+  if (e != hipSuccess) {
+    h->ws = nullptr;
+    return mps_fail(h, MPS_ERR_CAPACITY, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+  }
+  h->ws_bytes = want;
+  return MPS_OK;
+}
+
+extern "C" {
+
+mps_status mps_create(mps_handle* out, int device) {
+  if (!out) return MPS_ERR_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MPS_ERR_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return MPS_ERR_HIP;
+  mps_context* h = new (std::nothrow) mps_context();
+  if (!h) return MPS_ERR_CAPACITY;
+  h->device = device;
+  if (hipMalloc((void**)&h->status_dev, 256) != hipSuccess ||
+      hipMemset(h->status_dev, 0, 256) != hipSuccess ||
+      hipHostMalloc((void**)&h->host_pinned, 256, hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return MPS_ERR_HIP;
+  }
+  h->stats_dev = (unsigned long long*)((char*)h->status_dev + 64);
+  *out = h;
+  return MPS_OK;
+}
+
+mps_status mps_destroy(mps_handle h) {
+  if (!h) return MPS_ERR_INVALID;
+  hipSetDevice(h->device);
+  hipDeviceSynchronize();
+  for (auto e : h->ev_pool) hipEventDestroy(e);
+  if (h->ws) hipFree(h->ws);
+  if (h->status_dev) hipFree(h->status_dev);
+  if (h->host_pinned) hipHostFree(h->host_pinned);
+  delete h;
+  return MPS_OK;
+}
+
+const char* mps_last_error(mps_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+mps_status mps_reserve(mps_handle h, size_t bytes) {
+  if (!h) return MPS_ERR_INVALID;
+  return mps_ensure_ws(h, bytes);
+}
+
+mps_status mps_set_option(mps_handle h, int option, double value) {
+  if (!h) return MPS_ERR_INVALID;
+  switch (option) {
+    case 0:
+      if (!(value > 0.0 && value < 1.0)) return mps_fail(h, MPS_ERR_INVALID, "Jacobi tolerance must be in (0,1)");
+      h->jac_tol = value;
+      return MPS_OK;
+    case 1:
+      if (!(value >= 1.0 && value <= 1000.0)) return mps_fail(h, MPS_ERR_INVALID, "sweeps must be in [1,1000]");
+      h->jac_max_sweeps = (int)value;
+      return MPS_OK;
+    case 2:
+      if (!(value >= 0.0 && value < 1.0)) return mps_fail(h, MPS_ERR_INVALID, "absolute tolerance must be in [0,1)");
+      h->jac_abs = value;
+      return MPS_OK;
+    case 3:
+      h->profile = value != 0.0;
+      return MPS_OK;
+    default:
+      return mps_fail(h, MPS_ERR_INVALID, "unknown option");
+  }
+}
+
+mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word) {
+  if (!h || !word) return MPS_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  uint32_t w = 0;
+  MPS_TRY_HIP(h, hipMemcpy(&w, h->status_dev, sizeof(w), hipMemcpyDeviceToHost));
+  MPS_TRY_HIP(h, hipMemset(h->status_dev, 0, sizeof(w)));
+  *word = w;
+  if (w & MPS_DEV_NONFINITE) return mps_fail(h, MPS_ERR_NONFINITE, "non-finite values met on the device");
+  if (w & (MPS_DEV_NOCONV_SVD | MPS_DEV_NOCONV_LANCZOS))
+    return mps_fail(h, MPS_ERR_NOCONV, "an iteration did not converge");
+  return MPS_OK;
+}
+
+mps_status mps_kernel_stats(mps_handle h, mps_stream stream, int32_t kernel, double* total_ms, int64_t* launches,
+                            uint64_t* work, int32_t reset) {
+  if (!h || kernel < 0 || kernel >= MPS_NKERNELS) return MPS_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  mps_status st = prof_harvest(h, s);
+  if (st != MPS_OK) return st;
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  unsigned long long w[MPS_NSTATS];
+  MPS_TRY_HIP(h, hipMemcpy(w, h->stats_dev, sizeof(w), hipMemcpyDeviceToHost));
+  static const int work_slot[MPS_NKERNELS] = {0, 1, -1, -1, 3, -1, -1, -1};
+  if (total_ms) *total_ms = h->k_ms[kernel];
+  if (launches) *launches = h->k_launches[kernel];
+  if (work) *work = work_slot[kernel] >= 0 ? w[work_slot[kernel]] : 0;
+  if (reset) {
+    for (int i = 0; i < MPS_NKERNELS; ++i) {
+      h->k_ms[i] = 0.0;
+      h->k_launches[i] = 0;
+    }
+    MPS_TRY_HIP(h, hipMemset(h->stats_dev, 0, sizeof(w)));
+  }
+  return MPS_OK;
+}
+
+mps_status mps_gates(mps_handle h, mps_stream stream, int32_t n, int32_t dd, const void* hmat, const double* tau,
+                     void* G64, void* G128) {
+  if (!h) return MPS_ERR_INVALID;
+  if (n < 0 || dd < 1 || dd > 32) return mps_fail(h, MPS_ERR_SHAPE, "need n >= 0 and 1 <= dd <= 32");
+  if (n == 0) return MPS_OK;
+  if (!hmat || !tau || (!G64 && !G128)) return mps_fail(h, MPS_ERR_INVALID, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> taus(n);
+  MPS_TRY_HIP(h, hipMemcpyAsync(taus.data(), tau, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  std::vector<GateJob> jobs(n);
+  for (int i = 0; i < n; ++i) {
+    jobs[i].h = (const double2*)hmat + (size_t)i * dd * dd;
+    jobs[i].G64 = G64 ? (float2*)G64 + (size_t)i * dd * dd : nullptr;
+    jobs[i].G128 = G128 ? (double2*)G128 + (size_t)i * dd * dd : nullptr;
+    jobs[i].tau = taus[i];
+  }
+  mps_status st = mps_ensure_ws(h, n * sizeof(GateJob) + 256);
+  if (st != MPS_OK) return st;
+  st = upload(h, s, h->ws, jobs);
+  if (st != MPS_OK) return st;
+  MPS_TRY_HIP(h, launch_gates(s, (const GateJob*)h->ws, n, dd));
+  return MPS_OK;
+}
+
+mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n, int64_t chi_max,
+                        double eps, void* U, double* S, void* Vh, int32_t* k_dev, double* disc_dev,
+                        double* norm2_dev) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!theta || !U || !S || !Vh || !k_dev || !disc_dev || !norm2_dev)
+    return mps_fail(h, MPS_ERR_INVALID, "null pointer");
+  if (m < 1 || n < 1 || chi_max < 1) return mps_fail(h, MPS_ERR_SHAPE, "m, n, chi_max must be >= 1");
+  if (m > 4096 || n > 4096) return mps_fail(h, MPS_ERR_CAPACITY, "m and n are limited to 4096");
+  if (!(eps == eps)) return mps_fail(h, MPS_ERR_INVALID, "eps is NaN");
+  hipStream_t s = (hipStream_t)stream;
+  WsPlan p;
+  size_t oX = p.take<double2>((size_t)m * n);
+  size_t oM = p.take<JacMat>(1);
+  size_t oP = p.take<int32_t>(m);
+  size_t oS = p.take<double>(m);
+  size_t oSel = p.take<SelOut>(1);
+  size_t oU = p.take<int32_t>(4);
+  size_t oR = p.take<int32_t>(m);
+  mps_status st = mps_ensure_ws(h, p.off);
+  if (st != MPS_OK) return st;
+  double2* X = (double2*)(h->ws + oX);
+  JacMat* mat = (JacMat*)(h->ws + oM);
+  MPS_TRY_HIP(h, hipMemcpyAsync(X, theta, (size_t)m * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  JacMat hm;
+  std::memset(&hm, 0, sizeof(hm));
+  hm.X = X;
+  hm.rowmap = (int32_t*)(h->ws + oR);
+  hm.m = (int)m;
+  hm.n = (int)n;
+  hm.ld = (int)n;
+  hm.nb = jac_nb((int)m);
+  hm.kmax = (int)std::min<int64_t>(chi_max, m);
+  std::vector<JacMat> hv(1, hm);
+  st = upload(h, s, mat, hv);
+  if (st != MPS_OK) return st;
+  MPS_TRY_HIP(h, launch_jac_prep_plain(s, mat, 1, h->status_dev));
+  st = run_jacobi(h, s, mat, 1, hm.nb, (int)m, (int32_t*)(h->ws + oU), false);
+  if (st != MPS_OK) return st;
+  SelOut* sel = (SelOut*)(h->ws + oSel);
+  MPS_TRY_HIP(h, launch_select(s, mat, 1, (int32_t*)(h->ws + oP), (double*)(h->ws + oS), (int)m, hm.kmax, eps, sel));
+  MPS_TRY_HIP(h, launch_truncate_out(s, mat, (int32_t*)(h->ws + oP), (double*)(h->ws + oS), sel,
+                                     (const double2*)theta, m, n, chi_max, (double2*)U, S, (double2*)Vh, k_dev,
+                                     disc_dev, norm2_dev));
+  return MPS_OK;
+}
+
+mps_status mps_observe(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* op1,
+                       double* site_out, const void* op2, int32_t op2_per_bond, double* bond_out,
+                       double* entropy_out) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!chain) return mps_fail(h, MPS_ERR_INVALID, "null chain");
+  const mps_chain_desc& c = *chain;
+  if (c.L < 2 || c.d < 1 || c.d > 5 || c.chi_max < 1) return mps_fail(h, MPS_ERR_SHAPE, "bad chain shape");
+  if (c.dtype != MPS_C64 && c.dtype != MPS_C128) return mps_fail(h, MPS_ERR_INVALID, "bad dtype");
+  if (c.d * c.chi_max > 2560) return mps_fail(h, MPS_ERR_CAPACITY, "observe needs d*chi_max <= 2560");
+  if (!c.B || !c.lam || !c.chi) return mps_fail(h, MPS_ERR_INVALID, "null chain pointer");
+  MPS_TRY_HIP(h, launch_observe((hipStream_t)stream, c, (const double2*)op1, site_out, (const double2*)op2,
+                                op2_per_bond, bond_out, entropy_out));
+  return MPS_OK;
+}
+
+mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
+                         int32_t order, double dt, int32_t n_steps, double eps_local, uint32_t flags) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!chains || n_chains < 1) return mps_fail(h, MPS_ERR_INVALID, "need at least one chain");
+  if (order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 2 or 4");
+  if (n_steps < 0) return mps_fail(h, MPS_ERR_INVALID, "n_steps < 0");
+  if (!(dt == dt) || !(eps_local == eps_local)) return mps_fail(h, MPS_ERR_INVALID, "NaN argument");
+  if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS)) return mps_fail(h, MPS_ERR_INVALID, "unknown flag");
+  hipStream_t s = (hipStream_t)stream;
+  const bool graph = flags & MPS_FLAG_GRAPH;
+  // no event timing inside a captured graph
+  struct ProfGuard {
+    mps_handle h;
+    bool saved;
+    ~ProfGuard() { h->profile = saved; }
+  } guard{h, h->profile};
+  if (graph) h->profile = false;
+  const bool fixed = graph || (flags & MPS_FLAG_FIXED_SWEEPS);
+  if (graph && s == nullptr) return mps_fail(h, MPS_ERR_INVALID, "graph capture needs a non-default stream");
+  const int d = chains[0].d;
+  const int dtype = chains[0].dtype;
+  if (dtype != MPS_C64 && dtype != MPS_C128) return mps_fail(h, MPS_ERR_INVALID, "dtype must be MPS_C64 or MPS_C128");
+  const bool c128 = dtype == MPS_C128;
+  const size_t esz = c128 ? sizeof(double2) : sizeof(float2);
+  int chi_cap = 0;
+  for (int c = 0; c < n_chains; ++c) {
+    const mps_chain_desc& ch = chains[c];
+    if (ch.d != d) return mps_fail(h, MPS_ERR_SHAPE, "all chains must share d");
+    if (ch.dtype != dtype) return mps_fail(h, MPS_ERR_INVALID, "all chains must share dtype");
+    if (ch.L < 2 || ch.d < 1 || ch.d > 5 || ch.chi_max < 1)
+      return mps_fail(h, MPS_ERR_SHAPE, "bad chain shape (need L >= 2, 1 <= d <= 5, chi_max >= 1)");
+    if ((int64_t)ch.d * ch.chi_max > 4096) return mps_fail(h, MPS_ERR_CAPACITY, "d*chi_max is limited to 4096");
+    if (!ch.B || !ch.lam || !ch.chi || !ch.hbond || !ch.disc) return mps_fail(h, MPS_ERR_INVALID, "null chain pointer");
+    chi_cap = std::max(chi_cap, ch.chi_max);
+  }
+  if (n_steps == 0) return MPS_OK;
+  const int dd = d * d;
+
+  // time-step classes and the layer sequence of one step
+  std::vector<double> taus;
+  std::vector<std::pair<int, int>> layers;  // (parity 0 = odd bonds b=0,2,..., class)
+  if (order == 2) {
+    taus = {0.5 * dt, dt};
+    layers = {{0, 0}, {1, 1}, {0, 0}};
+  } else {
+    const double p = 1.0 / (4.0 - std::cbrt(4.0));
+    taus = {0.5 * p * dt, p * dt, 0.5 * (1.0 - 4.0 * p) * dt, (1.0 - 4.0 * p) * dt};
+    const int cls[5] = {0, 0, 2, 0, 0};
+    for (int st = 0; st < 5; ++st) {
+      layers.push_back({0, cls[st]});
+      layers.push_back({1, cls[st] + 1});
+      layers.push_back({0, cls[st]});
+    }
+  }
+  const int n_cls = (int)taus.size();
+
+  // workspace plan
+  WsPlan p;
+  size_t gate_elems = 0;
+  for (int c = 0; c < n_chains; ++c) gate_elems += (size_t)n_cls * (chains[c].L - 1) * dd * dd;
+  size_t oG = p.take<double2>(gate_elems);
+  size_t n_jobs = 0;
+  for (int c = 0; c < n_chains; ++c) n_jobs += (size_t)n_cls * (chains[c].L - 1);
+  size_t oJobs = p.take<GateJob>(n_jobs);
+  // per parity: items and their workspace slots
+  size_t n_par[2] = {0, 0}, slot_bytes[2] = {0, 0};
+  for (int c = 0; c < n_chains; ++c) {
+    const mps_chain_desc& ch = chains[c];
+    size_t sq = (size_t)ch.d * ch.chi_max * ch.d * ch.chi_max;
+    for (int b = 0; b < ch.L - 1; ++b) {
+      int par = b & 1;
+      n_par[par]++;
+      slot_bytes[par] += ((sq * sizeof(double2) + 255) & ~size_t(255)) + ((sq * esz + 255) & ~size_t(255)) +
+                         (((size_t)ch.chi_max * ch.d * ch.chi_max * esz + 255) & ~size_t(255));
+    }
+  }
+  const size_t max_items = std::max(n_par[0], n_par[1]);
+  size_t oSlots = p.take<char>(std::max(slot_bytes[0], slot_bytes[1]) + 256);
+  size_t oItems = p.take<BondItem>((n_par[0] + n_par[1]) * n_cls);
+  size_t oMats = p.take<JacMat>(max_items);
+  size_t oSel = p.take<SelOut>(max_items);
+  size_t oProbs = p.take<GemmProb>(max_items);
+  const int m_cap = d * chi_cap;
+  size_t oPerm = p.take<int32_t>(max_items * m_cap);
+  size_t oS2 = p.take<double>(max_items * m_cap);
+  size_t oUnc = p.take<int32_t>(4);
+  size_t oRow = p.take<int32_t>(max_items * m_cap);
+  mps_status st = mps_ensure_ws(h, p.off);
+  if (st != MPS_OK) return st;
+  char* ws = h->ws;
+
+  // gates: G[chain][class][bond]
+  std::vector<GateJob> jobs;
+  jobs.reserve(n_jobs);
+  std::vector<size_t> gate_base(n_chains);
+  size_t goff = 0;
+  for (int c = 0; c < n_chains; ++c) {
+    gate_base[c] = goff;
+    for (int k = 0; k < n_cls; ++k)
+      for (int b = 0; b < chains[c].L - 1; ++b) {
+        GateJob j;
+        j.h = (const double2*)chains[c].hbond + (size_t)b * dd * dd;
+        j.G64 = c128 ? nullptr : (float2*)(ws + oG) + goff;
+        j.G128 = c128 ? (double2*)(ws + oG) + goff : nullptr;
+        j.tau = taus[k];
+        jobs.push_back(j);
+        goff += (size_t)dd * dd;
+      }
+  }
+  st = upload(h, s, ws + oJobs, jobs);
+  if (st != MPS_OK) return st;
+  PROF_LAUNCH(h, s, MPS_K_GATES, launch_gates(s, (const GateJob*)(ws + oJobs), (int)jobs.size(), dd));
+
+  // bond items: for every (parity, class) a contiguous array
+  std::vector<BondItem> items;
+  std::vector<size_t> start(2 * n_cls), count(2 * n_cls);
+  for (int par = 0; par < 2; ++par) {
+    for (int k = 0; k < n_cls; ++k) {
+      start[par * n_cls + k] = items.size();
+      char* slot = ws + oSlots;
+      for (int c = 0; c < n_chains; ++c) {
+        const mps_chain_desc& ch = chains[c];
+        const size_t site = (size_t)ch.chi_max * ch.d * ch.chi_max;
+        const size_t sq = (size_t)ch.d * ch.chi_max * ch.d * ch.chi_max;
+        // largest chains first: their updates are the most expensive
+        for (int b = par; b < ch.L - 1; b += 2) {
+          BondItem it;
+          it.Bl = (char*)ch.B + (size_t)b * site * esz;
+          it.Br = (char*)ch.B + (size_t)(b + 1) * site * esz;
+          it.lam_l = ch.lam + (size_t)b * ch.chi_max;
+          it.lam_m = ch.lam + (size_t)(b + 1) * ch.chi_max;
+          it.chi = ch.chi;
+          it.G = (const char*)(ws + oG) + (gate_base[c] + ((size_t)k * (ch.L - 1) + b) * dd * dd) * esz;
+          it.disc = ch.disc;
+          it.X = (double2*)slot;
+          slot += (sq * sizeof(double2) + 255) & ~size_t(255);
+          it.T = slot;
+          slot += (sq * esz + 255) & ~size_t(255);
+          it.Vh = slot;
+          slot += ((size_t)ch.chi_max * ch.d * ch.chi_max * esz + 255) & ~size_t(255);
+          it.b = b;
+          it.d = ch.d;
+          it.chi_max = ch.chi_max;
+          it.pad = 0;
+          items.push_back(it);
+        }
+      }
+      count[par * n_cls + k] = items.size() - start[par * n_cls + k];
+    }
+  }
+  st = upload(h, s, ws + oItems, items);
+  if (st != MPS_OK) return st;
+
+  BondItem* dItems = (BondItem*)(ws + oItems);
+  JacMat* mats = (JacMat*)(ws + oMats);
+  SelOut* sel = (SelOut*)(ws + oSel);
+  GemmProb* probs = (GemmProb*)(ws + oProbs);
+  int32_t* perm = (int32_t*)(ws + oPerm);
+  double* s2 = (double*)(ws + oS2);
+  int32_t* unconv = (int32_t*)(ws + oUnc);
+  const int nb_cap = jac_nb(m_cap);
+
+  auto run_step = [&]() -> mps_status {
+    for (auto& ly : layers) {
+      const int idx = ly.first * n_cls + ly.second;
+      const int n = (int)count[idx];
+      if (n == 0) continue;
+      BondItem* it = dItems + start[idx];
+      const bool prof = h->profile;
+      unsigned long long* stats = prof ? h->stats_dev : nullptr;
+      if (prof) prof_begin(h, s, MPS_K_THETA);
+      MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_cap, c128, stats));
+      if (prof) prof_end(h, s, MPS_K_THETA);
+      if (prof) prof_begin(h, s, MPS_K_PREP);
+      MPS_TRY_HIP(h, launch_jac_prep_bonds(s, it, mats, n, kJacBlock, (int32_t*)(ws + oRow), m_cap, h->status_dev));
+      if (prof) prof_end(h, s, MPS_K_PREP);
+      mps_status r = run_jacobi(h, s, mats, n, nb_cap, m_cap, unconv, fixed);
+      if (r != MPS_OK) return r;
+      if (prof) prof_begin(h, s, MPS_K_SELECT);
+      MPS_TRY_HIP(h, launch_select(s, mats, n, perm, s2, m_cap, chi_cap, eps_local, sel));
+      if (prof) prof_end(h, s, MPS_K_SELECT);
+      if (prof) prof_begin(h, s, MPS_K_WB_RIGHT);
+      MPS_TRY_HIP(h, launch_wb_right(s, it, n, mats, perm, s2, m_cap, sel, chi_cap, d, c128));
+      if (prof) prof_end(h, s, MPS_K_WB_RIGHT);
+      MPS_TRY_HIP(h, launch_wb_left_probs(s, it, n, sel, probs));
+      if (prof) prof_begin(h, s, MPS_K_GEMM);
+      MPS_TRY_HIP(h, launch_gemm_bt_conj(s, probs, n, m_cap, chi_cap, c128, stats));
+      if (prof) prof_end(h, s, MPS_K_GEMM);
+      if (prof) {
+        mps_status ps = prof_harvest(h, s);
+        if (ps != MPS_OK) return ps;
+      }
+    }
+    return MPS_OK;
+  };
+
+  if (!graph) {
+    for (int stp = 0; stp < n_steps; ++stp) {
+      st = run_step();
+      if (st != MPS_OK) return st;
+    }
+    return MPS_OK;
+  }
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  MPS_TRY_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  st = run_step();
+  hipError_t ec = hipStreamEndCapture(s, &g);
+  if (st != MPS_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (ec != hipSuccess) return mps_fail(h, MPS_ERR_HIP, std::string("capture: ") + hipGetErrorString(ec));
+  hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    hipGraphDestroy(g);
+    return mps_fail(h, MPS_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(ei));
+  }
+  for (int stp = 0; stp < n_steps; ++stp) {
+    hipError_t el = hipGraphLaunch(ge, s);
+    if (el != hipSuccess) {
+      hipGraphExecDestroy(ge);
+      hipGraphDestroy(g);
+      return mps_fail(h, MPS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(el));
+    }
+  }
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  hipGraphExecDestroy(ge);
+  hipGraphDestroy(g);
+  return MPS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// Internal declarations shared by the libmps translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mps.h"
+
+#define MPS_NKERNELS 8
+#define MPS_NSTATS 8
+// kernel classes timed by the optional profiler (ids of mps_kernel_stats)
+#define MPS_K_THETA 0
+#define MPS_K_JAC_ROUND 1
+#define MPS_K_SELECT 2
+#define MPS_K_WB_RIGHT 3
+#define MPS_K_GEMM 4
+#define MPS_K_PREP 5
+#define MPS_K_GATES 6
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct mps_context {
+  int device = 0;
+  char* ws = nullptr;          // device workspace owned by the handle
+  size_t ws_bytes = 0;
+  uint32_t* status_dev = nullptr;  // device status word (MPS_DEV_* bits)
+  std::string err;
+  double jac_tol = 1e-13;      // relative orthogonality tolerance of the Jacobi SVD
+  double jac_abs = 1e-15;      // absolute tolerance, relative to |theta|_F^2
+  int jac_max_sweeps = 30;
+  // pinned host scratch for small readbacks
+  int32_t* host_pinned = nullptr;
+  // optional per-kernel timing with HIP events on the launch stream
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pending;  // (kernel id, first event index)
+  double k_ms[MPS_NKERNELS] = {0};
+  long long k_launches[MPS_NKERNELS] = {0};
+  unsigned long long* stats_dev = nullptr;  // device work counters [MPS_NSTATS]
+};
+
+// kernel timing helpers (host)
+void prof_begin(mps_handle h, hipStream_t s, int id);
+void prof_end(mps_handle h, hipStream_t s, int id);
+mps_status prof_harvest(mps_handle h, hipStream_t s);
+
+#define PROF_LAUNCH(h, s, id, call)                    \
+  do {                                                 \
+    if ((h)->profile) prof_begin((h), (s), (id));      \
+    MPS_TRY_HIP((h), (call));                          \
+    if ((h)->profile) prof_end((h), (s), (id));        \
+  } while (0)
+
+mps_status mps_fail(mps_handle h, mps_status code, const std::string& msg);
+mps_status mps_ensure_ws(mps_handle h, size_t bytes);
+
+#define MPS_TRY_HIP(h, call)                                                         \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return mps_fail((h), MPS_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Bump allocator that first measures, then carves the handle workspace.
+struct WsPlan {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t count) {
+    size_t o = (off + 255) & ~size_t(255);
+    off = o + count * sizeof(T);
+    return o;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// ---------------------------------------------------------------------------
+// descriptors passed to kernels (device memory)
+// ---------------------------------------------------------------------------
+
+// One two-site update of a Hastings-form chain (bond b joins sites b, b+1).
+// Complex element type T of the chain (float2 = complex64 or double2 =
+// complex128) applies to B, G, T and Vh.
+struct BondItem {
+  void* Bl;              // site b tensor, [chi_max][d][chi_max] (read, then rewritten)
+  void* Br;              // site b+1 tensor
+  const double* lam_l;   // Schmidt values left of site b (virtual bond b)
+  double* lam_m;         // virtual bond b+1 (output)
+  int32_t* chi;          // chain's chi array; chi[b], chi[b+1], chi[b+2]
+  const void* G;         // gate [d*d][d*d]
+  double* disc;          // chain's per-bond discarded weight accumulator (entry b)
+  double2* X;            // workspace: theta' complex128 [(d chi_max)^2]
+  void* T;               // workspace: theta~' [(d chi_max)^2]
+  void* Vh;              // workspace: kept V^dag rows [chi_max][d chi_max]
+  int32_t b, d, chi_max, pad;
+};
+
+// One propagator to build: G = exp(-i tau h).
+struct GateJob {
+  const double2* h;
+  float2* G64;      // optional complex64 output
+  double2* G128;    // optional complex128 output
+  double tau;
+};
+
+// One matrix handled by the batched Jacobi SVD (rows are orthogonalised).
+struct JacMat {
+  double2* X;      // [m][ld] complex128, rows of length n
+  int32_t* rowmap; // [m] row order used to form blocks (rows sorted by norm each sweep)
+  int32_t m, n, ld, nb;  // rows, columns, leading dim, number of row blocks (even)
+  int32_t conv, rot;     // converged flag, rotations applied in the running sweep
+  int32_t kmax, pad;     // cap on the kept count (0 = use the launch constant)
+  double fro2;           // |X|_F^2 at the start
+};
+
+// Output of the selection step (sorted singular values, count rule).
+struct SelOut {
+  int32_t k;      // kept count
+  int32_t m;      // rows considered
+  double disc;    // discarded weight
+  double norm2;   // sum of all s^2
+  double nk;      // sqrt(sum of kept s^2)
+};
+
+// One complex GEMM problem C = alpha * A * op(B), dims may live on the device.
+struct GemmProb {
+  const void* A;
+  const void* B;
+  void* C;
+  int32_t M, N, K;         // used when the matching *_dev pointer is null
+  int32_t lda, ldb, ldc;
+  const int32_t* M_dev;    // optional: M = M_mul * (*M_dev)
+  const int32_t* N_dev;
+  const int32_t* K_dev;
+  int32_t M_mul, N_mul, K_mul;
+  const double* inv_alpha_dev;  // optional: alpha = 1 / (*inv_alpha_dev)
+  double alpha;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+hipError_t launch_gates(hipStream_t s, const GateJob* jobs, int n, int dd);
+hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, bool c128,
+                        unsigned long long* stats);
+hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
+                                 int32_t* rowmap_ws, int m_cap, uint32_t* status);
+hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status);
+hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round,
+                            double tol, double abs_tol, unsigned long long* stats);
+hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged);
+hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap);
+hipError_t launch_jac_flag_noconv(hipStream_t s, const int32_t* unconverged, uint32_t* status);
+hipError_t launch_select(hipStream_t s, JacMat* mats, int n_mats, int32_t* perm_ws, double* s2_ws,
+                         int m_cap, int kmax_const, double eps, SelOut* out);
+hipError_t launch_wb_right(hipStream_t s, const BondItem* items, int n_items, const JacMat* mats,
+                           const int32_t* perm_ws, const double* s2_ws, int m_cap, const SelOut* sel,
+                           int chi_cap, int d, bool c128);
+hipError_t launch_wb_left_probs(hipStream_t s, const BondItem* items, int n_items, const SelOut* sel,
+                                GemmProb* probs);
+hipError_t launch_gemm_bt_conj(hipStream_t s, const GemmProb* probs, int n_probs, int M_cap, int N_cap, bool c128,
+                               unsigned long long* stats);
+hipError_t launch_gemm_nn(hipStream_t s, const GemmProb* probs, int n_probs, int M_cap, int N_cap, bool c128,
+                          unsigned long long* stats);
+hipError_t launch_truncate_out(hipStream_t s, const JacMat* mat, const int32_t* perm, const double* s2,
+                               const SelOut* sel, const double2* theta, int64_t m, int64_t n,
+                               int64_t chi_max, double2* U, double* S, double2* Vh, int32_t* k_dev,
+                               double* disc_dev, double* norm2_dev);
+hipError_t launch_observe(hipStream_t s, const mps_chain_desc& c, const double2* op1, double* site_out,
+                          const double2* op2, int op2_per_bond, double* bond_out, double* entropy_out);

@@ -1,0 +1,558 @@
+// K3: batched truncated SVD in FP64 by one-sided block Jacobi.
+//
+// The SVD split with truncation of Sec. "Basic concepts" (Splitting; Eqs.
+// overlap and elocal).  For theta' (m x n) the rows are orthogonalised by
+// unitary combinations: Z theta' has orthogonal rows s_j v_j^dag, so each
+// converged row divided by its norm is a row of V^dag and its norm is a
+// singular value.  U is never formed on the TEBD path (the Hastings
+// write-back needs V only).
+//
+// Rows are grouped in blocks of 16.  A round pairs every block with another
+// by the circle method; one workgroup per pair forms the 32x32 Gram matrix of
+// its two blocks in FP64, diagonalises it with the LDS Jacobi solver
+// (G = Q D Q^dag) and replaces the 32 rows x_p by y_j = sum_p Q[p][j] x_p.
+// A sweep is nb-1 rounds; sweeps repeat until a whole sweep applies no
+// rotation (a pair is left alone when every |G_pq| <= max(abs_tol*|X|_F^2,
+// tol*sqrt(G_pp G_qq))).
+// Selection sorts the row norms descending and applies the count rule
+//   k = min(k_max, min{k >= 1 : sum_{j>k} s_j^2 <= eps sum_j s_j^2}).
+#include <algorithm>
+
+#include "common.h"
+#include "jacobi_small.h"
+
+#define JB 16   // rows per block
+#define JCW 64  // columns staged per chunk
+
+__device__ __forceinline__ void jac_pair(int nb, int r, int p, int& I, int& J) {
+  if (p == 0) {
+    I = nb - 1;
+    J = r;
+  } else {
+    I = (r + p) % (nb - 1);
+    J = (r - p + nb - 1) % (nb - 1);
+  }
+}
+
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double mat_fro2(const double2* X, int m, int n, int ld, double* red) {
+  double acc = 0.0;
+  for (size_t i = threadIdx.x; i < (size_t)m * n; i += blockDim.x) {
+    size_t r = i / n, c = i % n;
+    double2 v = X[r * ld + c];
+    acc += v.x * v.x + v.y * v.y;
+  }
+  return block_sum(acc, red);
+}
+
+__global__ __launch_bounds__(256) void jac_prep_bonds_kernel(const BondItem* __restrict__ items,
+                                                             JacMat* __restrict__ mats, int bs,
+                                                             int32_t* rowmap_ws, int m_cap, uint32_t* status) {
+  __shared__ double red[256];
+  const BondItem it = items[blockIdx.x];
+  const int d = it.d;
+  const int m = it.chi[it.b] * d, n = d * it.chi[it.b + 2];
+  double2* X = it.X;
+  double f2 = mat_fro2(X, m, n, n, red);
+  if (threadIdx.x == 0) {
+    JacMat M;
+    M.X = X;
+    M.rowmap = rowmap_ws + (size_t)blockIdx.x * m_cap;
+    M.m = m;
+    M.n = n;
+    M.ld = n;
+    int nb = (m + bs - 1) / bs;
+    if (nb < 2) nb = 2;
+    if (nb & 1) nb++;
+    M.nb = nb;
+    M.rot = 0;
+    M.kmax = it.chi_max;
+    M.pad = 0;
+    M.fro2 = f2;
+    M.conv = (f2 == f2 && f2 < 1e300) ? 0 : 1;
+    if (M.conv) atomicOr(status, MPS_DEV_NONFINITE);
+    mats[blockIdx.x] = M;
+  }
+}
+
+__global__ __launch_bounds__(256) void jac_prep_plain_kernel(JacMat* __restrict__ mats, uint32_t* status) {
+  __shared__ double red[256];
+  JacMat* M = mats + blockIdx.x;
+  double f2 = mat_fro2(M->X, M->m, M->n, M->ld, red);
+  if (threadIdx.x == 0) {
+    M->fro2 = f2;
+    M->rot = 0;
+    M->conv = (f2 == f2 && f2 < 1e300) ? 0 : 1;
+    if (M->conv) atomicOr(status, MPS_DEV_NONFINITE);
+  }
+}
+
+__global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
+                                                        double abs_tol, unsigned long long* stats) {
+  __shared__ double2 Xs[32 * (JCW + 1)];
+  __shared__ double2 G[JS_N * JS_LD];
+  __shared__ double2 Q[JS_N * JS_LD];
+  __shared__ double4 rot[16];
+  __shared__ int flag;
+  __shared__ int need;
+  JacMat* M = mats + blockIdx.y;
+  if (M->conv) return;
+  const int nb = M->nb, p = blockIdx.x;
+  if (2 * p >= nb || round >= nb - 1) return;
+  const int m = M->m, n = M->n, ld = M->ld;
+  double2* X = M->X;
+  int I, J;
+  jac_pair(nb, round, p, I, J);
+  const int tid = threadIdx.x;
+  // local row r (0..31) -> matrix row, or -1 when beyond m
+  const int32_t* rmap = M->rowmap;
+  auto grow = [&](int r) -> int {
+    int g = (r < JB) ? I * JB + r : J * JB + (r - JB);
+    return g < m ? rmap[g] : -1;
+  };
+
+  // ---- Gram matrix of the 32 rows: G[p][q] = <x_p, x_q> -------------------
+  const int grp = tid >> 6, bt = tid & 63, pb = bt >> 3, qb = bt & 7;
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+  for (int c0 = 0; c0 < n; c0 += JCW) {
+    for (int idx = tid; idx < 32 * JCW; idx += 256) {
+      int r = idx / JCW, cc = idx % JCW;
+      int g = grow(r);
+      double2 v = make_double2(0.0, 0.0);
+      if (g >= 0 && c0 + cc < n) v = X[(size_t)g * ld + c0 + cc];
+      Xs[r * (JCW + 1) + cc] = v;
+    }
+    __syncthreads();
+    for (int cc = grp * 16; cc < grp * 16 + 16; ++cc) {
+      double2 xp[4], xq[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xp[i] = Xs[(pb * 4 + i) * (JCW + 1) + cc];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xq[j] = Xs[(qb * 4 + j) * (JCW + 1) + cc];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j].x += xp[i].x * xq[j].x + xp[i].y * xq[j].y;
+          acc[i][j].y += xp[i].x * xq[j].y - xp[i].y * xq[j].x;
+        }
+    }
+    __syncthreads();
+  }
+  // reduce the four column-group partials
+  double2* part = Xs;  // 2 x 1024 entries of scratch
+  if (grp >= 2)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) part[(grp - 2) * 1024 + (pb * 4 + i) * 32 + qb * 4 + j] = acc[i][j];
+  __syncthreads();
+  if (grp < 2)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) acc[i][j] = cadd(acc[i][j], part[grp * 1024 + (pb * 4 + i) * 32 + qb * 4 + j]);
+  __syncthreads();
+  if (grp == 1)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) part[(pb * 4 + i) * 32 + qb * 4 + j] = acc[i][j];
+  __syncthreads();
+  if (grp == 0)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        G[(pb * 4 + i) * JS_LD + qb * 4 + j] = cadd(acc[i][j], part[(pb * 4 + i) * 32 + qb * 4 + j]);
+  if (tid == 0) need = 0;
+  __syncthreads();
+
+  // ---- is any pair of the 32 rows still not orthogonal? --------------------
+  // A pair counts as orthogonal when |G_pq| <= max(tol sqrt(G_pp G_qq),
+  // abs_tol |X|_F^2): the absolute floor bounds the error of every squared
+  // singular value by about abs_tol |X|_F^2 and guarantees termination.
+  const double abs_thr = abs_tol * M->fro2;
+  for (int i = tid; i < 32 * 32; i += 256) {
+    int r = i >> 5, c = i & 31;
+    if (r < c) {
+      double2 g = G[r * JS_LD + c];
+      double ag = sqrt(g.x * g.x + g.y * g.y);
+      double thr = fmax(abs_thr, tol * sqrt(fabs(G[r * JS_LD + r].x * G[c * JS_LD + c].x)));
+      if (ag > thr) need = 1;
+    }
+  }
+  __syncthreads();
+  // work counters: Gram 32x32 complex MACs per column, rotation the same
+  if (tid == 0 && stats) atomicAdd(&stats[1], 8192ull * n * (need ? 2ull : 1ull));
+  if (!need) return;
+
+  herm_jacobi32(G, Q, 32, 0.25 * abs_thr, 0.1 * tol, 12, rot, &flag);
+
+  // ---- rotate the rows: y_j = sum_p Q[p][j] x_p ----------------------------
+  int rows[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) rows[r] = grow(r);
+  for (int c = tid; c < n; c += 256) {
+    double2 x[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) x[r] = rows[r] >= 0 ? X[(size_t)rows[r] * ld + c] : make_double2(0.0, 0.0);
+#pragma unroll 1
+    for (int j = 0; j < 32; ++j) {
+      if (rows[j] < 0) continue;
+      double2 y = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < 32; ++r) {
+        double2 q = Q[r * JS_LD + j];
+        y.x += q.x * x[r].x - q.y * x[r].y;
+        y.y += q.x * x[r].y + q.y * x[r].x;
+      }
+      X[(size_t)rows[j] * ld + c] = y;
+    }
+  }
+  if (tid == 0) atomicAdd(&M->rot, 1);
+}
+
+__global__ void jac_sweep_end_kernel(JacMat* __restrict__ mats, int n_mats, int32_t* unconverged) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int local = 0;
+  for (int i = threadIdx.x; i < n_mats; i += blockDim.x) {
+    JacMat* M = mats + i;
+    if (!M->conv) {
+      if (M->rot == 0) M->conv = 1;
+      else local++;
+      M->rot = 0;
+    }
+  }
+  atomicAdd(&cnt, local);
+  __syncthreads();
+  if (threadIdx.x == 0) *unconverged = cnt;
+}
+
+// Order the rows by decreasing norm before a sweep, so that blocks hold rows
+// of similar magnitude (the Gram-based inner solve resolves small rows
+// accurately only in blocks without much larger ones; de Rijk's sorting idea
+// for one-sided Jacobi).  One workgroup per matrix.
+__global__ __launch_bounds__(256) void jac_sort_kernel(JacMat* __restrict__ mats, int m_cap) {
+  extern __shared__ double dyn2[];
+  double* s2 = dyn2;
+  JacMat* M = mats + blockIdx.x;
+  if (M->conv) return;
+  const int m = M->m, n = M->n, ld = M->ld, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int r = wave; r < m; r += 4) {
+    double a = 0.0;
+    for (int c = lane; c < n; c += 64) {
+      double2 v = M->X[(size_t)r * ld + c];
+      a += v.x * v.x + v.y * v.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (lane == 0) s2[r] = (a >= 0.0 && a <= 1.0e300) ? a : -1.0;
+  }
+  __syncthreads();
+  for (int j = tid; j < m; j += 256) {
+    double v = s2[j];
+    int rank = 0;
+    for (int i = 0; i < m; ++i) {
+      double w = s2[i];
+      rank += (w > v) || (w == v && i < j);
+    }
+    M->rowmap[rank] = j;
+  }
+}
+
+__global__ void jac_flag_noconv_kernel(const int32_t* unconverged, uint32_t* status) {
+  if (*unconverged > 0) atomicOr(status, MPS_DEV_NOCONV_SVD);
+}
+
+// ---------------------------------------------------------------------------
+// selection: row norms, descending order, count rule
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void select_kernel(const JacMat* __restrict__ mats, int32_t* perm_ws,
+                                                     double* s2_ws, int m_cap, int kmax_const, double eps,
+                                                     SelOut* out) {
+  extern __shared__ double dyn[];
+  double* s2 = dyn;                       // [m_cap]
+  int* perm = (int*)(dyn + m_cap);        // [m_cap]
+  const JacMat M = mats[blockIdx.x];
+  const int m = M.m, n = M.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int r = wave; r < m; r += 4) {
+    double a = 0.0;
+    for (int c = lane; c < n; c += 64) {
+      double2 v = M.X[(size_t)r * M.ld + c];
+      a += v.x * v.x + v.y * v.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (lane == 0) s2[r] = a;
+  }
+  __syncthreads();
+  // NaN or negative entries (only possible from non-finite input, already
+  // flagged by the preparation) sort last as -1, so the ranks below form a
+  // permutation of 0..m-1 under any input.
+  for (int j = tid; j < m; j += 256) {
+    double v = s2[j];
+    if (!(v >= 0.0) || !(v <= 1.0e300)) s2[j] = -1.0;
+  }
+  __syncthreads();
+  for (int j = tid; j < m; j += 256) {
+    double v = s2[j];
+    int rank = 0;
+    for (int i = 0; i < m; ++i) {
+      double w = s2[i];
+      rank += (w > v) || (w == v && i < j);
+    }
+    perm[rank] = j;
+  }
+  __syncthreads();
+  int32_t* P = perm_ws + (size_t)blockIdx.x * m_cap;
+  double* S = s2_ws + (size_t)blockIdx.x * m_cap;
+  for (int r = tid; r < m; r += 256) {
+    P[r] = perm[r];
+    S[r] = fmax(s2[perm[r]], 0.0);
+  }
+  if (tid == 0) {
+    int kmax = M.kmax > 0 ? M.kmax : kmax_const;
+    double total = 0.0;
+    for (int r = m - 1; r >= 0; --r) total += fmax(s2[perm[r]], 0.0);
+    int k = m;
+    double tail = 0.0;
+    if (eps >= 0.0) {
+      for (int kk = m - 1; kk >= 1; --kk) {
+        double t2 = tail + fmax(s2[perm[kk]], 0.0);
+        if (t2 <= eps * total) {
+          tail = t2;
+          k = kk;
+        } else {
+          break;
+        }
+      }
+    }
+    if (k > kmax) k = kmax;
+    if (k < 1) k = 1;
+    double disc = 0.0, kept = 0.0;
+    for (int r = m - 1; r >= k; --r) disc += fmax(s2[perm[r]], 0.0);
+    for (int r = k - 1; r >= 0; --r) kept += fmax(s2[perm[r]], 0.0);
+    SelOut o;
+    o.k = k;
+    o.m = m;
+    o.disc = disc;
+    o.norm2 = total;
+    o.nk = kept > 0.0 ? sqrt(kept) : 1.0;
+    out[blockIdx.x] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// write-back of the right site and the Schmidt values (Hastings form)
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void wb_right_kernel(const BondItem* __restrict__ items,
+                                                       const JacMat* __restrict__ mats,
+                                                       const int32_t* __restrict__ perm_ws,
+                                                       const double* __restrict__ s2_ws, int m_cap,
+                                                       const SelOut* __restrict__ sel, int d) {
+  const BondItem it = items[blockIdx.y];
+  const JacMat M = mats[blockIdx.y];
+  const SelOut so = sel[blockIdx.y];
+  const int k = so.k, n = M.n, chr = n / d;
+  const int32_t* P = perm_ws + (size_t)blockIdx.y * m_cap;
+  const double* S2 = s2_ws + (size_t)blockIdx.y * m_cap;
+  T* Vh = (T*)it.Vh;
+  T* Br = (T*)it.Br;
+  const int chi_max = it.chi_max;
+  const size_t total = (size_t)k * n;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
+    int j = (int)(idx / n), col = (int)(idx % n);
+    double s = sqrt(S2[j]);
+    double inv = s > 0.0 ? 1.0 / s : 0.0;
+    int pj = P[j];
+    pj = (pj >= 0 && pj < M.m) ? pj : 0;
+    double2 x = M.X[(size_t)pj * M.ld + col];
+    T v;
+    v.x = x.x * inv;
+    v.y = x.y * inv;
+    int vv = col / chr, c = col % chr;
+    Br[((size_t)j * d + vv) * chi_max + c] = v;
+    Vh[idx] = v;
+  }
+  if (blockIdx.x == 0) {
+    for (int j = threadIdx.x; j < k; j += 256) it.lam_m[j] = sqrt(S2[j]) / so.nk;
+    if (threadIdx.x == 0) {
+      it.chi[it.b + 1] = k;
+      it.disc[it.b] += so.disc;
+    }
+  }
+}
+
+// Fill the write-back GEMM problems B_b = theta~' Vh^dag / n_k on the device.
+__global__ void wb_left_probs_kernel(const BondItem* __restrict__ items, int n_items,
+                                     const SelOut* __restrict__ sel, GemmProb* probs) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const BondItem it = items[i];
+  const int m = it.chi[it.b] * it.d;
+  GemmProb p;
+  const int ncols = it.d * it.chi[it.b + 2];
+  p.A = it.T;
+  p.B = it.Vh;
+  p.C = it.Bl;
+  p.M = m;
+  p.N = sel[i].k;
+  p.K = ncols;
+  p.lda = ncols;
+  p.ldb = ncols;
+  p.ldc = it.chi_max;
+  p.M_dev = p.N_dev = p.K_dev = nullptr;
+  p.M_mul = p.N_mul = p.K_mul = 1;
+  p.inv_alpha_dev = &sel[i].nk;
+  p.alpha = 1.0;
+  probs[i] = p;
+}
+
+// ---------------------------------------------------------------------------
+// outputs of the stand-alone truncation entry point (complex128 U, S, Vh)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void trunc_vh_kernel(const JacMat* mat, const int32_t* P, const double* S2,
+                                                       const SelOut* sel, int64_t n, int64_t chi_max,
+                                                       double2* Vh, double* S, int32_t* k_dev,
+                                                       double* disc_dev, double* norm2_dev) {
+  const SelOut so = *sel;
+  const int k = so.k;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < (size_t)k * n;
+       idx += (size_t)gridDim.x * 256) {
+    int j = (int)(idx / n), col = (int)(idx % n);
+    double s = sqrt(S2[j]);
+    double inv = s > 0.0 ? 1.0 / s : 0.0;
+    int pj = P[j];
+    pj = (pj >= 0 && pj < mat->m) ? pj : 0;
+    double2 x = mat->X[(size_t)pj * mat->ld + col];
+    Vh[(size_t)j * n + col] = make_double2(x.x * inv, x.y * inv);
+  }
+  if (blockIdx.x == 0) {
+    for (int j = threadIdx.x; j < k; j += 256) S[j] = sqrt(S2[j]);
+    if (threadIdx.x == 0) {
+      *k_dev = k;
+      *disc_dev = so.disc;
+      *norm2_dev = so.norm2;
+    }
+  }
+}
+
+// U[i][j] = sum_c theta[i][c] conj(Vh[j][c]) / s_j  (FP64)
+__global__ __launch_bounds__(256) void trunc_u_kernel(const double2* theta, const double2* Vh, const double* S,
+                                                      const SelOut* sel, int64_t m, int64_t n, int64_t chi_max,
+                                                      double2* U) {
+  const int k = sel->k;
+  const size_t total = (size_t)m * k;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
+    int i = (int)(idx / k), j = (int)(idx % k);
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t c = 0; c < n; ++c) {
+      double2 a = theta[(size_t)i * n + c], v = Vh[(size_t)j * n + c];
+      acc.x += a.x * v.x + a.y * v.y;
+      acc.y += a.y * v.x - a.x * v.y;
+    }
+    double s = S[j];
+    double inv = s > 0.0 ? 1.0 / s : 0.0;
+    U[(size_t)i * chi_max + j] = make_double2(acc.x * inv, acc.y * inv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
+                                 int32_t* rowmap_ws, int m_cap, uint32_t* status) {
+  if (n_items <= 0) return hipSuccess;
+  jac_prep_bonds_kernel<<<n_items, 256, 0, s>>>(items, mats, bs, rowmap_ws, m_cap, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status) {
+  if (n_mats <= 0) return hipSuccess;
+  jac_prep_plain_kernel<<<n_mats, 256, 0, s>>>(mats, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round, double tol,
+                            double abs_tol, unsigned long long* stats) {
+  if (n_mats <= 0) return hipSuccess;
+  dim3 grid(nb_cap / 2, n_mats);
+  jac_round_kernel<<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged) {
+  jac_sweep_end_kernel<<<1, 256, 0, s>>>(mats, n_mats, unconverged);
+  return hipGetLastError();
+}
+
+hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap) {
+  if (n_mats <= 0) return hipSuccess;
+  jac_sort_kernel<<<n_mats, 256, (size_t)m_cap * sizeof(double), s>>>(mats, m_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_jac_flag_noconv(hipStream_t s, const int32_t* unconverged, uint32_t* status) {
+  jac_flag_noconv_kernel<<<1, 1, 0, s>>>(unconverged, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(hipStream_t s, JacMat* mats, int n_mats, int32_t* perm_ws, double* s2_ws, int m_cap,
+                         int kmax_const, double eps, SelOut* out) {
+  if (n_mats <= 0) return hipSuccess;
+  size_t shm = (size_t)m_cap * (sizeof(double) + sizeof(int));
+  if (shm > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)select_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  select_kernel<<<n_mats, 256, shm, s>>>(mats, perm_ws, s2_ws, m_cap, kmax_const, eps, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_wb_right(hipStream_t s, const BondItem* items, int n_items, const JacMat* mats,
+                           const int32_t* perm_ws, const double* s2_ws, int m_cap, const SelOut* sel, int chi_cap,
+                           int d, bool c128) {
+  if (n_items <= 0) return hipSuccess;
+  size_t cap = (size_t)chi_cap * d * chi_cap;
+  int gx = (int)((cap + 255) / 256);
+  if (gx > 64) gx = 64;
+  dim3 grid(gx, n_items);
+  if (c128)
+    wb_right_kernel<double2><<<grid, 256, 0, s>>>(items, mats, perm_ws, s2_ws, m_cap, sel, d);
+  else
+    wb_right_kernel<float2><<<grid, 256, 0, s>>>(items, mats, perm_ws, s2_ws, m_cap, sel, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_wb_left_probs(hipStream_t s, const BondItem* items, int n_items, const SelOut* sel,
+                                GemmProb* probs) {
+  if (n_items <= 0) return hipSuccess;
+  wb_left_probs_kernel<<<(n_items + 63) / 64, 64, 0, s>>>(items, n_items, sel, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_truncate_out(hipStream_t s, const JacMat* mat, const int32_t* perm, const double* s2,
+                               const SelOut* sel, const double2* theta, int64_t m, int64_t n, int64_t chi_max,
+                               double2* U, double* S, double2* Vh, int32_t* k_dev, double* disc_dev,
+                               double* norm2_dev) {
+  int g1 = (int)((std::min<int64_t>(chi_max, m) * n + 255) / 256);
+  if (g1 > 1024) g1 = 1024;
+  if (g1 < 1) g1 = 1;
+  trunc_vh_kernel<<<g1, 256, 0, s>>>(mat, perm, s2, sel, n, chi_max, Vh, S, k_dev, disc_dev, norm2_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int g2 = (int)((m * std::min<int64_t>(chi_max, m) + 255) / 256);
+  if (g2 > 4096) g2 = 4096;
+  if (g2 < 1) g2 = 1;
+  trunc_u_kernel<<<g2, 256, 0, s>>>(theta, Vh, S, sel, m, n, chi_max, U);
+  return hipGetLastError();
+}
