@@ -9,8 +9,8 @@
 
 namespace {
 
-constexpr int kJacBlock = 16;   // rows per Jacobi block
-constexpr int kFixedSweeps = 14;  // sweeps queued when the host may not synchronise
+constexpr int kJacBlock = 32;   // rows per Jacobi block
+constexpr int kFixedSweeps = 20;  // sweeps queued when the host may not synchronise
 
 int jac_nb(int m) {
   int nb = (m + kJacBlock - 1) / kJacBlock;
@@ -37,7 +37,7 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
   for (int sw = 0; sw < max_sweeps && !done; ++sw) {
     MPS_TRY_HIP(h, launch_jac_sort(s, mats, n, m_cap));
     for (int r = 0; r < nb - 1; ++r)
-      PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs,
+      PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs, h->jac_inner_sweeps,
                                                               h->profile ? h->stats_dev : nullptr));
     MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
     if (!fixed && sw >= 1) {
@@ -167,6 +167,10 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
       return MPS_OK;
     case 3:
       h->profile = value != 0.0;
+      return MPS_OK;
+    case 4:
+      if (!(value >= 1.0 && value <= 64.0)) return mps_fail(h, MPS_ERR_INVALID, "inner sweeps must be in [1,64]");
+      h->jac_inner_sweeps = (int)value;
       return MPS_OK;
     default:
       return mps_fail(h, MPS_ERR_INVALID, "unknown option");

@@ -7,10 +7,12 @@
 // singular value.  U is never formed on the TEBD path (the Hastings
 // write-back needs V only).
 //
-// Rows are grouped in blocks of 16.  A round pairs every block with another
-// by the circle method; one workgroup per pair forms the 32x32 Gram matrix of
-// its two blocks in FP64, diagonalises it with the LDS Jacobi solver
-// (G = Q D Q^dag) and replaces the 32 rows x_p by y_j = sum_p Q[p][j] x_p.
+// Rows are grouped in blocks of 32 (after sorting them by norm at the start of
+// every sweep).  A round pairs every block with another by the circle method;
+// one workgroup per pair forms the 64x64 Gram matrix of its two blocks on FP64
+// MFMA, partly diagonalises it with the LDS Jacobi solver (G ~= Q D Q^dag, a
+// few sweeps) and replaces the 64 rows x_p by y_j = sum_p Q[p][j] x_p (FP64
+// MFMA again).
 // A sweep is nb-1 rounds; sweeps repeat until a whole sweep applies no
 // rotation (a pair is left alone when every |G_pq| <= max(abs_tol*|X|_F^2,
 // tol*sqrt(G_pp G_qq))).
@@ -20,9 +22,10 @@
 
 #include "common.h"
 #include "jacobi_small.h"
+#include "mfma_tile.h"
 
-#define JB 16   // rows per block
-#define JCW 64  // columns staged per chunk
+#define JB 32   // rows per block
+#define JP 64   // rows per block pair (panel)
 
 __device__ __forceinline__ void jac_pair(int nb, int r, int p, int& I, int& J) {
   if (p == 0) {
@@ -100,11 +103,14 @@ __global__ __launch_bounds__(256) void jac_prep_plain_kernel(JacMat* __restrict_
 }
 
 __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
-                                                        double abs_tol, unsigned long long* stats) {
-  __shared__ double2 Xs[32 * (JCW + 1)];
-  __shared__ double2 G[JS_N * JS_LD];
-  __shared__ double2 Q[JS_N * JS_LD];
-  __shared__ double4 rot[16];
+                                                        double abs_tol, int inner_sweeps, unsigned long long* stats) {
+  // Both arrays hold a [JP][JP+1] matrix (4160 elements) or four staging
+  // buffers of [TBK][TLD] (4352 elements); sized for the larger.
+  constexpr int kLdsElems = (JP * (JP + 1) > 4 * TBK * TLD) ? JP * (JP + 1) : 4 * TBK * TLD;
+  __shared__ double2 G[kLdsElems];  // Gram matrix; staging of the update afterwards
+  __shared__ double2 Q[kLdsElems];  // staging of the Gram; then the panel rotation
+  __shared__ double4 rot[JP / 2];
+  __shared__ int rows_s[JP];
   __shared__ int flag;
   __shared__ int need;
   JacMat* M = mats + blockIdx.y;
@@ -115,107 +121,138 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   double2* X = M->X;
   int I, J;
   jac_pair(nb, round, p, I, J);
-  const int tid = threadIdx.x;
-  // local row r (0..31) -> matrix row, or -1 when beyond m
-  const int32_t* rmap = M->rowmap;
-  auto grow = [&](int r) -> int {
-    int g = (r < JB) ? I * JB + r : J * JB + (r - JB);
-    return g < m ? rmap[g] : -1;
-  };
-
-  // ---- Gram matrix of the 32 rows: G[p][q] = <x_p, x_q> -------------------
-  const int grp = tid >> 6, bt = tid & 63, pb = bt >> 3, qb = bt & 7;
-  double2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
-  for (int c0 = 0; c0 < n; c0 += JCW) {
-    for (int idx = tid; idx < 32 * JCW; idx += 256) {
-      int r = idx / JCW, cc = idx % JCW;
-      int g = grow(r);
-      double2 v = make_double2(0.0, 0.0);
-      if (g >= 0 && c0 + cc < n) v = X[(size_t)g * ld + c0 + cc];
-      Xs[r * (JCW + 1) + cc] = v;
-    }
-    __syncthreads();
-    for (int cc = grp * 16; cc < grp * 16 + 16; ++cc) {
-      double2 xp[4], xq[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) xp[i] = Xs[(pb * 4 + i) * (JCW + 1) + cc];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xq[j] = Xs[(qb * 4 + j) * (JCW + 1) + cc];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j].x += xp[i].x * xq[j].x + xp[i].y * xq[j].y;
-          acc[i][j].y += xp[i].x * xq[j].y - xp[i].y * xq[j].x;
-        }
-    }
-    __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  if (tid < JP) {
+    int g = (tid < JB) ? I * JB + tid : J * JB + (tid - JB);
+    rows_s[tid] = g < m ? M->rowmap[g] : -1;
   }
-  // reduce the four column-group partials
-  double2* part = Xs;  // 2 x 1024 entries of scratch
-  if (grp >= 2)
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) part[(grp - 2) * 1024 + (pb * 4 + i) * 32 + qb * 4 + j] = acc[i][j];
-  __syncthreads();
-  if (grp < 2)
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) acc[i][j] = cadd(acc[i][j], part[grp * 1024 + (pb * 4 + i) * 32 + qb * 4 + j]);
-  __syncthreads();
-  if (grp == 1)
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) part[(pb * 4 + i) * 32 + qb * 4 + j] = acc[i][j];
-  __syncthreads();
-  if (grp == 0)
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j)
-        G[(pb * 4 + i) * JS_LD + qb * 4 + j] = cadd(acc[i][j], part[(pb * 4 + i) * 32 + qb * 4 + j]);
   if (tid == 0) need = 0;
   __syncthreads();
 
-  // ---- is any pair of the 32 rows still not orthogonal? --------------------
+  // ---- Gram matrix of the 64 rows on FP64 MFMA: G[i][j] = <x_i, x_j> --------
+  // The next 16-column chunk is loaded into registers while the current one is
+  // multiplied (two LDS buffers).
+  {
+    double2* As0 = Q;
+    double2* Bs0 = Q + TBK * TLD;
+    double2* As1 = Q + 2 * TBK * TLD;
+    double2* Bs1 = Q + 3 * TBK * TLD;
+    AccTile<double2> acc;
+    acc_zero<double2>(acc);
+    const int i = tid >> 2, kq = (tid & 3) * 4;
+    const int gi = rows_s[i];
+    const double2* xr = X + (size_t)(gi >= 0 ? gi : 0) * ld;
+    double2 v[4];
+    auto load = [&](int c0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int c = c0 + kq + e;
+        v[e] = (gi >= 0 && c < n) ? xr[c] : make_double2(0.0, 0.0);
+      }
+    };
+    auto store = [&](double2* As, double2* Bs) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        As[(kq + e) * TLD + i] = make_double2(v[e].x, -v[e].y);
+        Bs[(kq + e) * TLD + i] = v[e];
+      }
+    };
+    load(0);
+    store(As0, Bs0);
+    __syncthreads();
+    int buf = 0;
+    for (int c0 = 0; c0 < n; c0 += TBK) {
+      const bool more = c0 + TBK < n;
+      if (more) load(c0 + TBK);
+      mma_chunk<double2>(buf ? As1 : As0, buf ? Bs1 : Bs0, acc, wm, wn, lane);
+      if (more) store(buf ? As0 : As1, buf ? Bs0 : Bs1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    acc_to_lds<double2>(acc, G, JP + 1, wm, wn, lane);
+  }
+  __syncthreads();
+
+  // ---- is any pair of the 64 rows still not orthogonal? --------------------
   // A pair counts as orthogonal when |G_pq| <= max(tol sqrt(G_pp G_qq),
   // abs_tol |X|_F^2): the absolute floor bounds the error of every squared
   // singular value by about abs_tol |X|_F^2 and guarantees termination.
   const double abs_thr = abs_tol * M->fro2;
-  for (int i = tid; i < 32 * 32; i += 256) {
-    int r = i >> 5, c = i & 31;
+  for (int e = tid; e < JP * JP; e += 256) {
+    int r = e / JP, c = e % JP;
     if (r < c) {
-      double2 g = G[r * JS_LD + c];
+      double2 g = G[r * (JP + 1) + c];
       double ag = sqrt(g.x * g.x + g.y * g.y);
-      double thr = fmax(abs_thr, tol * sqrt(fabs(G[r * JS_LD + r].x * G[c * JS_LD + c].x)));
+      double thr = fmax(abs_thr, tol * sqrt(fabs(G[r * (JP + 1) + r].x * G[c * (JP + 1) + c].x)));
       if (ag > thr) need = 1;
     }
   }
   __syncthreads();
-  // work counters: Gram 32x32 complex MACs per column, rotation the same
-  if (tid == 0 && stats) atomicAdd(&stats[1], 8192ull * n * (need ? 2ull : 1ull));
+  // work counters: Gram 64x64 complex MACs per column, rotation the same
+  if (tid == 0 && stats) atomicAdd(&stats[1], 32768ull * n * (need ? 2ull : 1ull));
   if (!need) return;
 
-  herm_jacobi32(G, Q, 32, 0.25 * abs_thr, 0.1 * tol, 12, rot, &flag);
+  herm_jacobi<JP>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
 
-  // ---- rotate the rows: y_j = sum_p Q[p][j] x_p ----------------------------
-  int rows[32];
+  // ---- rotate the rows: y_j = sum_p Q[p][j] x_p, 64 columns at a time -------
+  // As[k][j] = Q[p0+k][j] comes from LDS; Bs[k][c] = X[row_{p0+k}][c0+c] is
+  // prefetched into registers one chunk ahead.
+  {
+    double2* As0 = G;
+    double2* Bs0 = G + TBK * TLD;
+    double2* As1 = G + 2 * TBK * TLD;
+    double2* Bs1 = G + 3 * TBK * TLD;
+    const int k = tid >> 4, q4 = (tid & 15) * 4;
+    double2 v[4];
+    auto load = [&](int c0, int p0) {
+      int g = rows_s[p0 + k];
+      const double2* xr = X + (size_t)(g >= 0 ? g : 0) * ld;
 #pragma unroll
-  for (int r = 0; r < 32; ++r) rows[r] = grow(r);
-  for (int c = tid; c < n; c += 256) {
-    double2 x[32];
-#pragma unroll
-    for (int r = 0; r < 32; ++r) x[r] = rows[r] >= 0 ? X[(size_t)rows[r] * ld + c] : make_double2(0.0, 0.0);
-#pragma unroll 1
-    for (int j = 0; j < 32; ++j) {
-      if (rows[j] < 0) continue;
-      double2 y = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int r = 0; r < 32; ++r) {
-        double2 q = Q[r * JS_LD + j];
-        y.x += q.x * x[r].x - q.y * x[r].y;
-        y.y += q.x * x[r].y + q.y * x[r].x;
+      for (int e = 0; e < 4; ++e) {
+        int c = c0 + q4 + e;
+        v[e] = (g >= 0 && c < n) ? xr[c] : make_double2(0.0, 0.0);
       }
-      X[(size_t)rows[j] * ld + c] = y;
+    };
+    auto store = [&](double2* As, double2* Bs, int p0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        As[k * TLD + q4 + e] = Q[(p0 + k) * (JP + 1) + q4 + e];
+        Bs[k * TLD + q4 + e] = v[e];
+      }
+    };
+    const int nsteps = ((n + TBN - 1) / TBN) * (JP / TBK);  // (column block, p-chunk) pairs
+    load(0, 0);
+    store(As0, Bs0, 0);
+    __syncthreads();
+    AccTile<double2> acc;
+    acc_zero<double2>(acc);
+    int buf = 0;
+    for (int st = 0; st < nsteps; ++st) {
+      const int c0 = (st / (JP / TBK)) * TBN, p0 = (st % (JP / TBK)) * TBK;
+      const bool more = st + 1 < nsteps;
+      const int c1 = ((st + 1) / (JP / TBK)) * TBN, p1 = ((st + 1) % (JP / TBK)) * TBK;
+      if (more) load(c1, p1);
+      mma_chunk<double2>(buf ? As1 : As0, buf ? Bs1 : Bs0, acc, wm, wn, lane);
+      if (p0 + TBK == JP) {
+        // the column block is complete: write its 64 rows (no later chunk reads
+        // these columns), then start the next block from zero
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              int row = wm + i * 16 + Cx<double2>::acc_row(lane, r);
+              int col = c0 + wn + j * 16 + (lane & 15);
+              int g = rows_s[row];
+              if (g >= 0 && col < n) X[(size_t)g * ld + col] = make_double2(acc.re[i][j][r], acc.im[i][j][r]);
+            }
+        acc_zero<double2>(acc);
+      }
+      if (more) store(buf ? As0 : As1, buf ? Bs0 : Bs1, p1);
+      __syncthreads();
+      buf ^= 1;
     }
   }
   if (tid == 0) atomicAdd(&M->rot, 1);
@@ -482,10 +519,10 @@ hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32
 }
 
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round, double tol,
-                            double abs_tol, unsigned long long* stats) {
+                            double abs_tol, int inner_sweeps, unsigned long long* stats) {
   if (n_mats <= 0) return hipSuccess;
   dim3 grid(nb_cap / 2, n_mats);
-  jac_round_kernel<<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, stats);
+  jac_round_kernel<<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, stats);
   return hipGetLastError();
 }
 
