@@ -28,11 +28,13 @@ HBM_PEAK_GBS = 8000.0
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=140)
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
+    ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -51,6 +53,12 @@ def main():
     h = api.Handle(0)
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
 
+    start_step = 0
+    if args.load_state:
+        st = torch.load(args.load_state, weights_only=True)
+        for k in ("B", "lam", "chi", "disc"):
+            getattr(ch, k).copy_(st[k].to(getattr(ch, k).device))
+        start_step = int(st["step"])
     t0 = time.time()
     done = 0
     while done < args.warmup:
@@ -61,6 +69,9 @@ def main():
         print(f"[bench] warmup {done}/{args.warmup} steps, chi_max now {int(ch.chi.max())}, "
               f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     code, word = h.device_status()
+    start_step += args.warmup
+    if args.save_state:
+        torch.save({"B": ch.B, "lam": ch.lam, "chi": ch.chi, "disc": ch.disc, "step": start_step}, args.save_state)
 
     # snapshot of the state the timed region starts from (for the CPU baseline)
     snap = ch.to_host() if not args.no_cpu else None
@@ -104,7 +115,7 @@ def main():
         else "c64 (FP32 MFMA contractions, FP64 SVD)",
         "data": "synthetic",
         "config": {"workload": "xxz_tebd4_L64: TEBD4 XXZ L=64 Jxy=1 Jz=0.5 Neel dt=0.05 chi_max=256 eps=1e-12",
-                   "updates_per_step": updates_per_step, "start_step": args.warmup,
+                   "updates_per_step": updates_per_step, "start_step": start_step,
                    "chi_hist": {"max": int(chi.max()), "mean": round(float(chi.mean()), 1),
                                 "n_at_cap": int((chi >= spec.chi_max).sum())}},
         "roofline": {"kernel": "jac_round_kernel (FP64 block-Jacobi round: Gram + rotation)",

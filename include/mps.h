@@ -76,7 +76,7 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * relative to |theta|_F^2 (default 1e-15), 3 = kernel timing on (!= 0) or
  * off (0): HIP events around every launch of the timed kernels on the call's
  * stream, plus device counters of the useful work they perform (not inside
- * captured graphs), 4 = sweeps of the 32x32 inner eigensolve per Jacobi block
+ * captured graphs), 4 = sweeps of the 64x64 inner eigensolve per Jacobi block
  * pair (default 1). */
 mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
