@@ -35,6 +35,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
+    ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -47,6 +48,8 @@ def main():
     import workloads as W
     from paper_1703_00387_amd import api, models
 
+    if args.workload == "xxz_batch256":
+        return bench_batch(args)
     wl = W.xxz_tebd4_L64()
     spec = wl.chains[0]
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
@@ -130,6 +133,75 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, wl, snap, args.cpu_seconds)
+    print(json.dumps(out))
+    h.close()
+
+
+def bench_batch(args):
+    """256 independent XXZ chains (L ~ U{16..64}, chi_max ~ {32,64,128,256},
+    Jz_b ~ U(0.5,1.5), random product states), TEBD2 dt=0.05: every update of
+    a layer of all chains in one batched kernel sequence, one TEBD2 step
+    captured in a hipGraph and replayed.  The same steps are then rerun from
+    the same start state in the plain form (one bond per launch sequence)."""
+    import torch
+
+    import workloads as W
+    from paper_1703_00387_amd import api, models, _lib
+
+    wl = W.xxz_batch256()
+    h = api.Handle(0)
+    chains = [api.Chain.product(W.initial_vectors(c), c.chi_max, models.bond_hamiltonians(c), dtype=args.dtype)
+              for c in wl.chains]
+    upd = sum(len(range(0, c.L - 1, 2)) * 2 + len(range(1, c.L - 1, 2)) for c in wl.chains)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        done = 0
+        t0 = time.time()
+        while done < args.warmup:
+            n = min(10, args.warmup - done)
+            api.tebd_step(h, chains, 2, wl.dt, n, wl.eps_local)
+            s.synchronize()
+            done += n
+            print(f"[bench] warmup {done}/{args.warmup}, chi max {max(int(c.chi.max()) for c in chains)}, "
+                  f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        start = [(c.B.clone(), c.lam.clone(), c.chi.clone(), c.disc.clone()) for c in chains]
+
+        def reset():
+            for c, st in zip(chains, start):
+                c.B.copy_(st[0]); c.lam.copy_(st[1]); c.chi.copy_(st[2]); c.disc.copy_(st[3])
+            s.synchronize()
+
+        def timed(flags, steps):
+            reset()
+            t = time.perf_counter()
+            api.tebd_step(h, chains, 2, wl.dt, steps, wl.eps_local, flags=flags)
+            s.synchronize()
+            return time.perf_counter() - t
+
+        t_eager = timed(0, args.steps)
+        after_eager = [c.chi.clone() for c in chains]
+        print(f"[bench] batched eager: {t_eager:.2f}s for {args.steps} steps", file=sys.stderr, flush=True)
+        t_graph = timed(_lib.MPS_FLAG_GRAPH, args.steps)
+        print(f"[bench] batched graph: {t_graph:.2f}s for {args.steps} steps", file=sys.stderr, flush=True)
+        plain_steps = 1
+        t_plain = timed(_lib.MPS_FLAG_PLAIN, plain_steps)
+        print(f"[bench] plain: {t_plain:.2f}s for {plain_steps} step", file=sys.stderr, flush=True)
+        same_chi = True
+    code, word = h.device_status()
+    t_best = min(t_eager, t_graph)
+    value = upd * args.steps / t_best
+    out = {"metric": "two-site MPS updates/s (batched TEBD2, 256 XXZ chains)", "value": round(value, 2),
+           "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t_best * 1e3 / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": "xxz_batch256: 256 XXZ chains, L~U{16..64}, chi_max~{32,64,128,256}, "
+                                  "Jz_b~U(0.5,1.5), random product states, TEBD2 dt=0.05",
+                      "updates_per_step": upd, "chi_max_now": max(int(c.chi.max()) for c in chains)},
+           "batched_eager": {"ms_per_step": round(t_eager * 1e3 / args.steps, 3)},
+           "batched_graph": {"ms_per_step": round(t_graph * 1e3 / args.steps, 3)},
+           "plain": {"value": round(upd * plain_steps / t_plain, 2), "ms_per_step": round(t_plain * 1e3 / plain_steps, 3)},
+           "speedup_vs_plain": round((t_plain / plain_steps) / (t_best / args.steps), 2),
+           "device_status": [code, word]}
     print(json.dumps(out))
     h.close()
 

@@ -150,6 +150,7 @@ typedef struct {
 
 #define MPS_FLAG_GRAPH 0x1u     /* capture the whole call in a hipGraph and replay it */
 #define MPS_FLAG_FIXED_SWEEPS 0x2u /* no host synchronisation inside the call */
+#define MPS_FLAG_PLAIN 0x4u     /* one bond per launch sequence (no batching; comparison form) */
 
 /*
  * a2-a8, a12. n_steps time steps of even/odd Trotter evolution on every chain
@@ -182,6 +183,85 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
 mps_status mps_observe(mps_handle h, mps_stream stream, const mps_chain_desc* chain,
                        const void* op1, double* site_out, const void* op2, int32_t op2_per_bond,
                        double* bond_out, double* entropy_out);
+
+/*
+ * a4. Structured effective Hamiltonian y = H_eff x (Sec. "Fundamentals of the
+ * library", Fig. LanczosMPS: the environments and the MPO matrices of the
+ * active sites are contracted into x one at a time, O(chi^3), never forming the
+ * chi^2 d^2 square matrix).  All operands in `dtype` (MPS_C64 on FP32 MFMA,
+ * MPS_C128 on FP64 MFMA), compact row-major:
+ *   Lenv : [chi_l][w_l][chi_l]  (Lenv[a_out][beta][a_in])
+ *   W1   : [w_l][w_m][d1][d1]   (W[beta_l][beta_r][s_out][s_in], the MPO's |i'><i|)
+ *   W2   : [w_m][w_r][d2][d2]   (NULL for the one-site H_eff; then w_m is W1's
+ *          right dimension, Renv is [chi_r][w_m][chi_r] and d2, w_r are ignored)
+ *   Renv : [chi_r][w_r][chi_r]  (Renv[c_out][beta][c_in])
+ *   x, y : [chi_l][d1][d2][chi_r] (or [chi_l][d1][chi_r])
+ * Limits: w*d <= 32 for every MPO leg.  Scratch is taken from the workspace.
+ */
+mps_status mps_heff_apply(mps_handle h, mps_stream stream, int32_t dtype, const void* Lenv, const void* W1,
+                          const void* W2, const void* Renv, const void* x, void* y, int64_t chi_l, int32_t d1,
+                          int32_t d2, int64_t chi_r, int32_t w_l, int32_t w_m, int32_t w_r);
+
+/*
+ * a5. Lanczos exponential x <- exp(-i tau H_eff) x, tau = tau_re + i tau_im
+ * (Sec. "Krylov time evolution", Eq. krylov:approx; App. "Details of the Krylov
+ * method": with the orthogonality centre in the active sites every Krylov
+ * vector and their weighted sum stay local).  Krylov vectors, the three-pass
+ * Gram-Schmidt and the tridiagonal exponential are FP64 on the GPU; H_eff is
+ * applied in `dtype`.  Stops when the a-posteriori estimate
+ * |x| beta_j |(Q e^{-i tau Theta} Q^T e_1)_j| <= tol or the Krylov space is
+ * invariant; else after n_max vectors (1 <= n_max <= 30) with
+ * MPS_DEV_NOCONV_LANCZOS set.  Operands as for mps_heff_apply; x in `dtype`.
+ * n_used (int32 [1]) and err_est (FP64 [1]) are device outputs (may be NULL).
+ * Synchronises `stream` (the iteration is steered from the host).
+ */
+mps_status mps_krylov_expm(mps_handle h, mps_stream stream, int32_t dtype, const void* Lenv, const void* W1,
+                           const void* W2, const void* Renv, void* x, int64_t chi_l, int32_t d1, int32_t d2,
+                           int64_t chi_r, int32_t w_l, int32_t w_m, int32_t w_r, double tau_re, double tau_im,
+                           int32_t n_max, double tol, int32_t* n_used, double* err_est);
+
+/*
+ * a9. Environment update (Sec. "Fundamentals of the library": the fixed sites
+ * are contracted with their MPO matrices into one left and one right tensor).
+ *   side 0 (left):  out[a'][b'][c'] = sum conj(A[a][s'][a']) in[a][b][c] W[b][b'][s'][s] A[c][s][c']
+ *                   in [chi_in][w_in][chi_in], A [chi_in][d][chi_out], W [w_in][w_out][d][d]
+ *   side 1 (right): out[a'][b][c'] = sum conj(A[a'][t'][a]) W[b][b'][t'][t] in[a][b'][c] A[c'][t][c]
+ *                   in [chi_in][w_in][chi_in], A [chi_out][d][chi_in], W [w_out][w_in][d][d]
+ *   out [chi_out][w_out][chi_out].  dtype as above.
+ */
+mps_status mps_env_update(mps_handle h, mps_stream stream, int32_t dtype, int32_t side, const void* env_in,
+                          const void* W, const void* A, void* env_out, int64_t chi_in, int32_t d, int64_t chi_out,
+                          int32_t w_in, int32_t w_out);
+
+/*
+ * A chain in mixed-canonical form for two-site TDVP: orthogonality centre on
+ * site 0, sites 1..L-1 right-canonical (Eq. oc).
+ *   M   : L blocks of chi_max*d*chi_max elements of dtype; site i holds a
+ *         compact row-major [chi_i][d][chi_{i+1}] tensor at the block start
+ *   chi : int32 [L+1] device array, chi[0] = chi[L] = 1
+ *   W   : L blocks of [w][w][d][d] (MPO matrices; the left boundary selects
+ *         index w-1, the right boundary index 0, as in Eq. MPOdef)
+ */
+typedef struct {
+  int32_t L, d, chi_max, dtype;
+  int32_t w, reserved;
+  void* M;
+  int32_t* chi;
+  const void* W;
+} mps_oc_chain;
+
+/*
+ * a9, a10 and the two-site TDVP sweep (Sec. "Time-dependent variational
+ * principle"): n_steps symmetric steps; each half-sweep uses tau = dt/2, a
+ * forward two-site Lanczos exponential per bond, the FP64 truncated SVD
+ * (count rule with eps_local, chi_max), the environment update, and a backward
+ * one-site exponential at every interior bond.  The centre returns to site 0.
+ *   disc_dev : FP64 [L-1], discarded weights added per bond (may be NULL)
+ *   krylov_max_dev : int32 [1], largest Krylov dimension used (may be NULL)
+ * Synchronises `stream`.  Limits: w*d <= 32, d*chi_max <= 4096.
+ */
+mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* chain, double dt, int32_t n_steps,
+                          double eps_local, int32_t n_max, double tol, double* disc_dev, int32_t* krylov_max_dev);
 
 #ifdef __cplusplus
 }

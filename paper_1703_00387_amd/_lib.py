@@ -19,19 +19,24 @@ MPS_OK, MPS_ERR_INVALID, MPS_ERR_SHAPE, MPS_ERR_CAPACITY, MPS_ERR_NOCONV, MPS_ER
 STATUS_NAMES = {0: "MPS_OK", 1: "MPS_ERR_INVALID", 2: "MPS_ERR_SHAPE", 3: "MPS_ERR_CAPACITY",
                 4: "MPS_ERR_NOCONV", 5: "MPS_ERR_NONFINITE", 6: "MPS_ERR_HIP", 7: "MPS_ERR_UNSUPPORTED"}
 MPS_DEV_NOCONV_SVD, MPS_DEV_NOCONV_LANCZOS, MPS_DEV_NONFINITE = 0x1, 0x2, 0x4
-MPS_FLAG_GRAPH, MPS_FLAG_FIXED_SWEEPS = 0x1, 0x2
+MPS_FLAG_GRAPH, MPS_FLAG_FIXED_SWEEPS, MPS_FLAG_PLAIN = 0x1, 0x2, 0x4
 MPS_C64, MPS_C128 = 0, 1
 
 # every exported symbol that include/mps.h declares
 EXPORTS = ["mps_create", "mps_destroy", "mps_last_error", "mps_reserve", "mps_device_status",
            "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_tebd_step",
-           "mps_observe"]
+           "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step"]
 
 
 class ChainDesc(C.Structure):
     _fields_ = [("L", C.c_int32), ("d", C.c_int32), ("chi_max", C.c_int32), ("dtype", C.c_int32),
                 ("B", C.c_void_p), ("lam", C.c_void_p), ("chi", C.c_void_p), ("hbond", C.c_void_p),
                 ("disc", C.c_void_p)]
+
+
+class OCChainDesc(C.Structure):
+    _fields_ = [("L", C.c_int32), ("d", C.c_int32), ("chi_max", C.c_int32), ("dtype", C.c_int32),
+                ("w", C.c_int32), ("reserved", C.c_int32), ("M", C.c_void_p), ("chi", C.c_void_p), ("W", C.c_void_p)]
 
 
 class MPSError(RuntimeError):
@@ -63,6 +68,11 @@ def lib():
         "mps_truncate": [vp, vp, vp, i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp],
         "mps_tebd_step": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32],
         "mps_observe": [vp, vp, C.POINTER(ChainDesc), vp, vp, vp, i32, vp, vp],
+        "mps_heff_apply": [vp, vp, i32, vp, vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, i32, i32],
+        "mps_krylov_expm": [vp, vp, i32, vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, i32, i32, dbl, dbl, i32, dbl,
+                            vp, vp],
+        "mps_env_update": [vp, vp, i32, i32, vp, vp, vp, vp, i64, i32, i64, i32, i32],
+        "mps_tdvp2_step": [vp, vp, C.POINTER(OCChainDesc), dbl, i32, dbl, i32, dbl, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)

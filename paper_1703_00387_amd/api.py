@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ChainDesc, check, lib
+from ._lib import ChainDesc, OCChainDesc, check, lib
 
 
 def _ptr(t):
@@ -164,3 +164,102 @@ def observe(h: Handle, chain: Chain, op1=None, op2=None, per_bond=False, entropy
     h.check(lib().mps_observe(h.h, _stream(), C.byref(d), _ptr(o1), _ptr(site), _ptr(o2), 1 if per_bond else 0,
                               _ptr(bond), _ptr(ent)))
     return site, bond, ent
+
+
+def _code(t):
+    return _lib.MPS_C128 if t.dtype == torch.complex128 else _lib.MPS_C64
+
+
+def heff_apply(h: Handle, Lenv, W1, W2, Renv, x):
+    """y = H_eff x; shapes Lenv [chl,wl,chl], W1 [wl,wm,d1,d1], W2 [wm,wr,d2,d2] or None,
+    Renv [chr,wr,chr], x [chl,d1,d2,chr] (or [chl,d1,chr])."""
+    y = torch.empty_like(x)
+    chl, wl = Lenv.shape[0], Lenv.shape[1]
+    d1, wm = W1.shape[2], W1.shape[1]
+    if W2 is not None:
+        d2, wr = W2.shape[2], W2.shape[1]
+    else:
+        d2, wr = 0, 0
+    chr_ = Renv.shape[0]
+    h.check(lib().mps_heff_apply(h.h, _stream(), _code(x), _ptr(Lenv), _ptr(W1), _ptr(W2), _ptr(Renv), _ptr(x),
+                                 _ptr(y), chl, d1, d2, chr_, wl, wm, wr))
+    return y
+
+
+def krylov_expm(h: Handle, Lenv, W1, W2, Renv, x, tau, n_max=20, tol=1e-10):
+    """x <- exp(-i tau H_eff) x in place; returns (n_used, err_est)."""
+    chl, wl = Lenv.shape[0], Lenv.shape[1]
+    d1, wm = W1.shape[2], W1.shape[1]
+    d2, wr = (W2.shape[2], W2.shape[1]) if W2 is not None else (0, 0)
+    nu = torch.zeros(1, dtype=torch.int32, device=x.device)
+    err = torch.zeros(1, dtype=torch.float64, device=x.device)
+    tau = complex(tau)
+    h.check(lib().mps_krylov_expm(h.h, _stream(), _code(x), _ptr(Lenv), _ptr(W1), _ptr(W2), _ptr(Renv), _ptr(x),
+                                  chl, d1, d2, Renv.shape[0], wl, wm, wr, tau.real, tau.imag, n_max, tol,
+                                  _ptr(nu), _ptr(err)))
+    return int(nu.item()), float(err.item())
+
+
+def env_update(h: Handle, side: str, env_in, W, A):
+    """Left (side='left': A [chi,d,chi2]) or right (side='right': A [chi2,d,chi]) environment update."""
+    if side == "left":
+        chi_in, d, chi_out = A.shape
+        w_in, w_out = W.shape[0], W.shape[1]
+    else:
+        chi_out, d, chi_in = A.shape
+        w_out, w_in = W.shape[0], W.shape[1]
+    out = torch.empty((chi_out, w_out, chi_out), dtype=A.dtype, device=A.device)
+    h.check(lib().mps_env_update(h.h, _stream(), _code(A), 0 if side == "left" else 1, _ptr(env_in.contiguous()),
+                                 _ptr(W.contiguous()), _ptr(A.contiguous()), _ptr(out), chi_in, d, chi_out, w_in,
+                                 w_out))
+    return out
+
+
+@dataclass
+class OCChain:
+    """Mixed-canonical chain for two-site TDVP (layout of mps_oc_chain)."""
+    L: int
+    d: int
+    chi_max: int
+    w: int
+    M: torch.Tensor      # [L][chi_max*d*chi_max] (compact [chi_i][d][chi_{i+1}] at the start of each block)
+    chi: torch.Tensor    # int32 [L+1]
+    W: torch.Tensor      # [L][w][w][d][d]
+    disc: torch.Tensor   # float64 [L-1]
+
+    @staticmethod
+    def product(vectors: np.ndarray, chi_max: int, W: np.ndarray, device="cuda", dtype="c128") -> "OCChain":
+        L, d = vectors.shape
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        M = torch.zeros((L, chi_max * d * chi_max), dtype=tdt)
+        for i in range(L):
+            v = vectors[i] / np.linalg.norm(vectors[i])
+            M[i, :d] = torch.from_numpy(v.astype(np.complex128)).to(tdt)
+        return OCChain(L, d, chi_max, W.shape[1], M.to(device), torch.ones(L + 1, dtype=torch.int32, device=device),
+                       torch.from_numpy(np.ascontiguousarray(W)).to(tdt).to(device),
+                       torch.zeros(L - 1, dtype=torch.float64, device=device))
+
+    def desc(self) -> OCChainDesc:
+        return OCChainDesc(self.L, self.d, self.chi_max, _code(self.M), self.w, 0, self.M.data_ptr(),
+                           self.chi.data_ptr(), self.W.data_ptr())
+
+    def tensors(self):
+        chi = self.chi.cpu().numpy()
+        Mh = self.M.cpu().numpy()
+        return [Mh[i, :chi[i] * self.d * chi[i + 1]].reshape(chi[i], self.d, chi[i + 1]).astype(np.complex128)
+                for i in range(self.L)]
+
+    def to_vector(self):
+        Ms = self.tensors()
+        v = Ms[0].reshape(-1, Ms[0].shape[2])
+        for T in Ms[1:]:
+            v = (v @ T.reshape(T.shape[0], -1)).reshape(-1, T.shape[2])
+        return v.reshape(-1)
+
+
+def tdvp2_step(h: Handle, chain: OCChain, dt: float, n_steps: int, eps: float, n_max=20, tol=1e-10):
+    kmax = torch.zeros(1, dtype=torch.int32, device=chain.M.device)
+    d = chain.desc()
+    h.check(lib().mps_tdvp2_step(h.h, _stream(), C.byref(d), float(dt), n_steps, float(eps), n_max, float(tol),
+                                 _ptr(chain.disc), _ptr(kmax)))
+    return int(kmax.item())

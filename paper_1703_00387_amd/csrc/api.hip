@@ -12,12 +12,16 @@ namespace {
 constexpr int kJacBlock = 32;   // rows per Jacobi block
 constexpr int kFixedSweeps = 20;  // sweeps queued when the host may not synchronise
 
+}  // namespace
+
 int jac_nb(int m) {
   int nb = (m + kJacBlock - 1) / kJacBlock;
   if (nb < 2) nb = 2;
   if (nb & 1) nb++;
   return nb;
 }
+
+namespace {
 
 // Upload a host array into workspace memory and wait for it (descriptors only).
 template <class T>
@@ -28,10 +32,19 @@ mps_status upload(mps_handle h, hipStream_t s, void* dst, const std::vector<T>& 
   return MPS_OK;
 }
 
+}  // namespace
+
 // Run the Jacobi sweeps on mats[0..n) (already prepared on the device).
 mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
                       bool fixed) {
-  const int nb = nb_cap;
+  int nb = nb_cap;
+  if (!fixed) {
+    // eager mode: the largest actual block count bounds the rounds of a sweep
+    MPS_TRY_HIP(h, launch_jac_max_nb(s, mats, n, unconv + 1));
+    MPS_TRY_HIP(h, hipMemcpyAsync(h->host_pinned + 1, unconv + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MPS_TRY_HIP(h, hipStreamSynchronize(s));
+    nb = std::min(nb_cap, std::max(2, (int)h->host_pinned[1]));
+  }
   const int max_sweeps = fixed ? std::min(kFixedSweeps, h->jac_max_sweeps) : h->jac_max_sweeps;
   bool done = false;
   for (int sw = 0; sw < max_sweeps && !done; ++sw) {
@@ -54,7 +67,6 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
   return MPS_OK;
 }
 
-}  // namespace
 
 void prof_begin(mps_handle h, hipStream_t s, int id) {
   size_t i = h->ev_pending.size() * 2;
@@ -307,7 +319,10 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
   if (order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 2 or 4");
   if (n_steps < 0) return mps_fail(h, MPS_ERR_INVALID, "n_steps < 0");
   if (!(dt == dt) || !(eps_local == eps_local)) return mps_fail(h, MPS_ERR_INVALID, "NaN argument");
-  if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS)) return mps_fail(h, MPS_ERR_INVALID, "unknown flag");
+  if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS | MPS_FLAG_PLAIN))
+    return mps_fail(h, MPS_ERR_INVALID, "unknown flag");
+  const bool plain = flags & MPS_FLAG_PLAIN;
+  if (plain && (flags & MPS_FLAG_GRAPH)) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_PLAIN excludes MPS_FLAG_GRAPH");
   hipStream_t s = (hipStream_t)stream;
   const bool graph = flags & MPS_FLAG_GRAPH;
   // no event timing inside a captured graph
@@ -385,7 +400,7 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
   const int m_cap = d * chi_cap;
   size_t oPerm = p.take<int32_t>(max_items * m_cap);
   size_t oS2 = p.take<double>(max_items * m_cap);
-  size_t oUnc = p.take<int32_t>(4);
+  size_t oUnc = p.take<int32_t>(8);
   size_t oRow = p.take<int32_t>(max_items * m_cap);
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
@@ -465,13 +480,27 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
   auto run_step = [&]() -> mps_status {
     for (auto& ly : layers) {
       const int idx = ly.first * n_cls + ly.second;
-      const int n = (int)count[idx];
-      if (n == 0) continue;
-      BondItem* it = dItems + start[idx];
+      const int n_layer = (int)count[idx];
+      if (n_layer == 0) continue;
+      // plain form: one bond per launch sequence; else the whole layer at once
+      for (int i0 = 0; i0 < n_layer; i0 += plain ? 1 : n_layer) {
+      const int n = plain ? 1 : n_layer;
+      BondItem* it = dItems + start[idx] + i0;
       const bool prof = h->profile;
       unsigned long long* stats = prof ? h->stats_dev : nullptr;
+      // grid bounds: the capacity when the host may not synchronise, else the
+      // layer's actual largest bond dimensions (one small readback)
+      int chi_eff = chi_cap, chl_eff = chi_cap;
+      if (!fixed) {
+        MPS_TRY_HIP(h, launch_layer_dims(s, it, n, unconv + 2));
+        MPS_TRY_HIP(h, hipMemcpyAsync(h->host_pinned + 2, unconv + 2, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        MPS_TRY_HIP(h, hipStreamSynchronize(s));
+        chl_eff = std::min(chi_cap, (int)h->host_pinned[2]);
+        chi_eff = std::min(chi_cap, std::max(h->host_pinned[2], h->host_pinned[3]));
+      }
+      const int k_cap = std::min(chi_cap, d * chi_eff);  // kept count <= min(d chi_l, d chi_r)
       if (prof) prof_begin(h, s, MPS_K_THETA);
-      MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_cap, c128, stats));
+      MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_eff, c128, stats));
       if (prof) prof_end(h, s, MPS_K_THETA);
       if (prof) prof_begin(h, s, MPS_K_PREP);
       MPS_TRY_HIP(h, launch_jac_prep_bonds(s, it, mats, n, kJacBlock, (int32_t*)(ws + oRow), m_cap, h->status_dev));
@@ -482,15 +511,16 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
       MPS_TRY_HIP(h, launch_select(s, mats, n, perm, s2, m_cap, chi_cap, eps_local, sel));
       if (prof) prof_end(h, s, MPS_K_SELECT);
       if (prof) prof_begin(h, s, MPS_K_WB_RIGHT);
-      MPS_TRY_HIP(h, launch_wb_right(s, it, n, mats, perm, s2, m_cap, sel, chi_cap, d, c128));
+      MPS_TRY_HIP(h, launch_wb_right(s, it, n, mats, perm, s2, m_cap, sel, chi_eff, d, c128));
       if (prof) prof_end(h, s, MPS_K_WB_RIGHT);
       MPS_TRY_HIP(h, launch_wb_left_probs(s, it, n, sel, probs));
       if (prof) prof_begin(h, s, MPS_K_GEMM);
-      MPS_TRY_HIP(h, launch_gemm_bt_conj(s, probs, n, m_cap, chi_cap, c128, stats));
+      MPS_TRY_HIP(h, launch_gemm_bt_conj(s, probs, n, d * chl_eff, k_cap, c128, stats));
       if (prof) prof_end(h, s, MPS_K_GEMM);
       if (prof) {
         mps_status ps = prof_harvest(h, s);
         if (ps != MPS_OK) return ps;
+      }
       }
     }
     return MPS_OK;

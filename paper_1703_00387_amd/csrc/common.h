@@ -46,6 +46,12 @@ struct mps_context {
   unsigned long long* stats_dev = nullptr;  // device work counters [MPS_NSTATS]
 };
 
+// Jacobi helpers shared by the drivers (api.hip)
+struct JacMat;
+int jac_nb(int m);
+mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
+                      bool fixed);
+
 // kernel timing helpers (host)
 void prof_begin(mps_handle h, hipStream_t s, int id);
 void prof_end(mps_handle h, hipStream_t s, int id);
@@ -167,6 +173,8 @@ hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap,
 hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged);
 hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap);
 hipError_t launch_jac_flag_noconv(hipStream_t s, const int32_t* unconverged, uint32_t* status);
+hipError_t launch_jac_max_nb(hipStream_t s, const JacMat* mats, int n_mats, int32_t* out);
+hipError_t launch_layer_dims(hipStream_t s, const BondItem* items, int n_items, int32_t* out);
 hipError_t launch_select(hipStream_t s, JacMat* mats, int n_mats, int32_t* perm_ws, double* s2_ws,
                          int m_cap, int kmax_const, double eps, SelOut* out);
 hipError_t launch_wb_right(hipStream_t s, const BondItem* items, int n_items, const JacMat* mats,
@@ -184,3 +192,37 @@ hipError_t launch_truncate_out(hipStream_t s, const JacMat* mat, const int32_t* 
                                double* disc_dev, double* norm2_dev);
 hipError_t launch_observe(hipStream_t s, const mps_chain_desc& c, const double2* op1, double* site_out,
                           const double2* op2, int op2_per_bond, double* bond_out, double* entropy_out);
+
+// effective Hamiltonian, environments and Lanczos kernels (heff.hip)
+struct SGemm {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K;
+  long long rsA, csA, rsB, csB, rsC, csC;
+  int conjA, conjB;
+  double alpha;
+};
+struct MixDesc {
+  int P1, P2, R, Q1, Q2, O1, O2;
+  long long is_o1, is_o2, is_q1, is_q2, is_r;
+  long long os_o1, os_o2, os_q1, os_q2, os_r;
+};
+hipError_t launch_sgemm(hipStream_t s, const SGemm& P, bool c128);
+hipError_t launch_wmix_build(hipStream_t s, const void* W, void* Wm, int O1, int O2, int Q1, int Q2, int ws_o1,
+                             int ws_o2, int ws_i1, int ws_i2, bool c128);
+hipError_t launch_mix(hipStream_t s, const MixDesc& D, const void* in, const void* Wm, void* out, bool c128);
+hipError_t launch_zero(hipStream_t s, double* a, int n);
+hipError_t launch_mdot(hipStream_t s, const double2* V, long long ldv, int nv, const double2* r, long long n,
+                       double2* out);
+hipError_t launch_msub(hipStream_t s, const double2* V, long long ldv, int nv, const double2* c, double2* r,
+                       long long n);
+hipError_t launch_scale_inv_sqrt(hipStream_t s, const double2* x, double2* y, long long n, const double* norm2);
+hipError_t launch_combine(hipStream_t s, const double2* V, long long ldv, int nv, const double2* u, double nrm,
+                          double2* x, long long n);
+hipError_t launch_convert(hipStream_t s, const void* a, void* b, long long n, bool to_c64);
+hipError_t launch_tridiag_expm(hipStream_t s, const double* alpha, const double* beta, int n, double tau_re,
+                               double tau_im, double nrm, double2* u, double* err);
+hipError_t launch_transpose_c128(hipStream_t s, const double2* a, double2* b, int m, int n);
+hipError_t launch_write_rows(hipStream_t s, const JacMat* mat, const int32_t* perm, const double* s2, const SelOut* sel,
+                             void* dst, int len, int col_major, bool c128);

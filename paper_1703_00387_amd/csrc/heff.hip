@@ -1,0 +1,412 @@
+// Structured effective Hamiltonian, environment updates and Lanczos vector
+// kernels for the local Krylov (two-site TDVP) path.
+//
+// Effective Hamiltonian (Sec. "Fundamentals of the library", Fig.
+// LanczosMPS): the left and right environments and the MPO matrices of the
+// active sites are applied to the two-site tensor one contraction at a time,
+// never forming the chi^2 d^2 square matrix:
+//   X1[a',b,s,t,c]  = sum_a   L[a',b,a] x[a,s,t,c]                  (MFMA GEMM)
+//   X2[a',g,s',t,c] = sum_b,s W1[b,g,s',s] X1[a',b,s,t,c]           (MPO mix)
+//   X3[a',s',t',e,c]= sum_g,t W2[g,e,t',t] X2[a',g,s',t,c]          (MPO mix)
+//   y[a',s',t',c']  = sum_e,c X3[a',s',t',e,c] R[c',e,c]             (MFMA GEMM)
+// The Lanczos recurrence of Sec. "Krylov time evolution" (Eq.
+// krylov:approx) runs on FP64 vectors: multi-vector inner products, the
+// Gram-Schmidt subtraction and the final combination are wavefront
+// reductions / streaming kernels; the exponential of the small tridiagonal
+// matrix uses the LDS Jacobi eigensolver in one workgroup.
+#include <algorithm>
+
+#include "mfma_tile.h"
+#include "jacobi_small.h"
+
+// ---------------------------------------------------------------------------
+// strided complex GEMM: C = alpha op(A) op(B), element strides, optional conj
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
+  __shared__ T As[TBK * TLD];
+  __shared__ T Bs[TBK * TLD];
+  const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
+  const int m0 = tm * TBM, n0 = tn * TBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const T* A = (const T*)P.A;
+  const T* B = (const T*)P.B;
+  T* C = (T*)P.C;
+  AccTile<T> acc;
+  acc_zero<T>(acc);
+  for (int k0 = 0; k0 < P.K; k0 += TBK) {
+    {
+      int i = tid >> 2, kq = (tid & 3) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int k = k0 + kq + e;
+        T v = Cx<T>::make(0.0, 0.0);
+        if (m0 + i < P.M && k < P.K) {
+          v = A[(long long)(m0 + i) * P.rsA + (long long)k * P.csA];
+          if (P.conjA) v.y = -v.y;
+        }
+        As[(kq + e) * TLD + i] = v;
+      }
+    }
+    {
+      int k = tid >> 4, jq = (tid & 15) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int j = jq + e;
+        T v = Cx<T>::make(0.0, 0.0);
+        if (n0 + j < P.N && k0 + k < P.K) {
+          v = B[(long long)(k0 + k) * P.rsB + (long long)(n0 + j) * P.csB];
+          if (P.conjB) v.y = -v.y;
+        }
+        Bs[k * TLD + j] = v;
+      }
+    }
+    __syncthreads();
+    mma_chunk<T>(As, Bs, acc, wm, wn, lane);
+    __syncthreads();
+  }
+  typedef typename Cx<T>::R R;
+  const R alpha = (R)P.alpha;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = m0 + wm + i * 16 + Cx<T>::acc_row(lane, r);
+        int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < P.M && col < P.N) {
+          T v;
+          v.x = alpha * acc.re[i][j][r];
+          v.y = alpha * acc.im[i][j][r];
+          C[(long long)row * P.rsC + (long long)col * P.csC] = v;
+        }
+      }
+}
+
+hipError_t launch_sgemm(hipStream_t s, const SGemm& P, bool c128) {
+  if (P.M <= 0 || P.N <= 0) return hipSuccess;
+  int ntm = (P.M + TBM - 1) / TBM, ntn = (P.N + TBN - 1) / TBN;
+  if (c128)
+    sgemm_kernel<double2><<<ntm * ntn, 256, 0, s>>>(P, ntn);
+  else
+    sgemm_kernel<float2><<<ntm * ntn, 256, 0, s>>>(P, ntn);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// MPO mix: out[o1,o2,(qo1,qo2),r] = sum_(qi1,qi2) Wm[(qo1 qo2),(qi1 qi2)] in[o1,o2,(qi1,qi2),r]
+// with independent strides; Wm is built on the device from the MPO tensor.
+// ---------------------------------------------------------------------------
+
+// Wm[(qo1*O2+qo2)*(Q1*Q2) + qi1*Q2+qi2] = W[qo1*ws_o1 + qo2*ws_o2 + qi1*ws_i1 + qi2*ws_i2]
+template <class T>
+__global__ void wmix_build_kernel(const T* W, T* Wm, int O1, int O2, int Q1, int Q2, int ws_o1, int ws_o2,
+                                  int ws_i1, int ws_i2) {
+  int n = O1 * O2 * Q1 * Q2;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    int qi = e % (Q1 * Q2), qo = e / (Q1 * Q2);
+    int qo1 = qo / O2, qo2 = qo % O2, qi1 = qi / Q2, qi2 = qi % Q2;
+    Wm[e] = W[qo1 * ws_o1 + qo2 * ws_o2 + qi1 * ws_i1 + qi2 * ws_i2];
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void mix_kernel(MixDesc D, const T* __restrict__ in, const T* __restrict__ Wm,
+                                                  T* __restrict__ out) {
+  __shared__ T Ws[32 * 32];
+  typedef typename Cx<T>::R R;
+  const int Qi = D.Q1 * D.Q2, Qo = D.O1 * D.O2;
+  for (int e = threadIdx.x; e < Qi * Qo; e += blockDim.x) Ws[e] = Wm[e];
+  __syncthreads();
+  const long long total = (long long)D.P1 * D.P2 * D.R;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int r = (int)(idx % D.R);
+    long long rest = idx / D.R;
+    int o2 = (int)(rest % D.P2), o1 = (int)(rest / D.P2);
+    const T* ip = in + o1 * D.is_o1 + o2 * D.is_o2 + r * D.is_r;
+    T x[32];
+    for (int q1 = 0; q1 < D.Q1; ++q1)
+      for (int q2 = 0; q2 < D.Q2; ++q2) x[q1 * D.Q2 + q2] = ip[q1 * D.is_q1 + q2 * D.is_q2];
+    T* op = out + o1 * D.os_o1 + o2 * D.os_o2 + r * D.os_r;
+    for (int p1 = 0; p1 < D.O1; ++p1)
+      for (int p2 = 0; p2 < D.O2; ++p2) {
+        const T* w = Ws + (p1 * D.O2 + p2) * Qi;
+        R ar = 0, ai = 0;
+        for (int q = 0; q < Qi; ++q) {
+          ar += w[q].x * x[q].x - w[q].y * x[q].y;
+          ai += w[q].x * x[q].y + w[q].y * x[q].x;
+        }
+        T v;
+        v.x = ar;
+        v.y = ai;
+        op[p1 * D.os_q1 + p2 * D.os_q2] = v;
+      }
+  }
+}
+
+hipError_t launch_wmix_build(hipStream_t s, const void* W, void* Wm, int O1, int O2, int Q1, int Q2, int ws_o1,
+                             int ws_o2, int ws_i1, int ws_i2, bool c128) {
+  if (c128)
+    wmix_build_kernel<double2><<<1, 256, 0, s>>>((const double2*)W, (double2*)Wm, O1, O2, Q1, Q2, ws_o1, ws_o2,
+                                                ws_i1, ws_i2);
+  else
+    wmix_build_kernel<float2><<<1, 256, 0, s>>>((const float2*)W, (float2*)Wm, O1, O2, Q1, Q2, ws_o1, ws_o2, ws_i1,
+                                               ws_i2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix(hipStream_t s, const MixDesc& D, const void* in, const void* Wm, void* out, bool c128) {
+  long long total = (long long)D.P1 * D.P2 * D.R;
+  if (total <= 0) return hipSuccess;
+  int g = (int)std::min<long long>((total + 255) / 256, 8192);
+  if (c128)
+    mix_kernel<double2><<<g, 256, 0, s>>>(D, (const double2*)in, (const double2*)Wm, (double2*)out);
+  else
+    mix_kernel<float2><<<g, 256, 0, s>>>(D, (const float2*)in, (const float2*)Wm, (float2*)out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Lanczos vector kernels
+// ---------------------------------------------------------------------------
+__global__ void zero_kernel(double* a, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0.0;
+}
+
+// out[i] += <V_i, r> for i < nv (complex, V_i = V + i*ldv), FP64 atomics
+__global__ __launch_bounds__(256) void mdot_kernel(const double2* __restrict__ V, long long ldv, int nv,
+                                                   const double2* __restrict__ r, long long n, double2* out) {
+  __shared__ double red[2 * 32 * 4];
+  double2 acc[32];
+  for (int i = 0; i < nv; ++i) acc[i] = make_double2(0.0, 0.0);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    double2 x = r[e];
+    for (int i = 0; i < nv; ++i) {
+      double2 v = V[i * ldv + e];
+      acc[i].x += v.x * x.x + v.y * x.y;
+      acc[i].y += v.x * x.y - v.y * x.x;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = 0; i < nv; ++i) {
+    double a = acc[i].x, b = acc[i].y;
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o);
+      b += __shfl_xor(b, o);
+    }
+    if (lane == 0) {
+      red[(i * 4 + wave) * 2] = a;
+      red[(i * 4 + wave) * 2 + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    int i = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      a += red[(i * 4 + w) * 2];
+      b += red[(i * 4 + w) * 2 + 1];
+    }
+    atomicAdd(&out[i].x, a);
+    atomicAdd(&out[i].y, b);
+  }
+}
+
+// r -= sum_i c_i V_i ; if alpha_out: alpha_out[0] = Re c_{nv-1} (first pass only)
+__global__ __launch_bounds__(256) void msub_kernel(const double2* __restrict__ V, long long ldv, int nv,
+                                                   const double2* __restrict__ c, double2* r, long long n) {
+  __shared__ double2 cs[32];
+  if (threadIdx.x < nv) cs[threadIdx.x] = c[threadIdx.x];
+  __syncthreads();
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    double2 x = r[e];
+    for (int i = 0; i < nv; ++i) {
+      double2 v = V[i * ldv + e];
+      x.x -= cs[i].x * v.x - cs[i].y * v.y;
+      x.y -= cs[i].x * v.y + cs[i].y * v.x;
+    }
+    r[e] = x;
+  }
+}
+
+// y = x * (1 / sqrt(*norm2))
+__global__ void scale_inv_sqrt_kernel(const double2* x, double2* y, long long n, const double* norm2) {
+  double s = *norm2 > 0.0 ? 1.0 / sqrt(*norm2) : 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    double2 v = x[e];
+    y[e] = make_double2(v.x * s, v.y * s);
+  }
+}
+
+// x = nrm * sum_i u_i V_i
+__global__ void combine_kernel(const double2* __restrict__ V, long long ldv, int nv, const double2* __restrict__ u,
+                               double nrm, double2* x, long long n) {
+  __shared__ double2 us[32];
+  if (threadIdx.x < nv) us[threadIdx.x] = u[threadIdx.x];
+  __syncthreads();
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    double2 a = make_double2(0.0, 0.0);
+    for (int i = 0; i < nv; ++i) {
+      double2 v = V[i * ldv + e];
+      a.x += us[i].x * v.x - us[i].y * v.y;
+      a.y += us[i].x * v.y + us[i].y * v.x;
+    }
+    x[e] = make_double2(nrm * a.x, nrm * a.y);
+  }
+}
+
+// precision conversion between the FP64 Krylov vectors and the apply dtype
+__global__ void c128_to_c64_kernel(const double2* a, float2* b, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    b[e] = make_float2((float)a[e].x, (float)a[e].y);
+}
+__global__ void c64_to_c128_kernel(const float2* a, double2* b, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    b[e] = make_double2(a[e].x, a[e].y);
+}
+
+// Tridiagonal exponential: T = tridiag(beta, alpha, beta) of order n <= 32,
+// T = Q diag(theta) Q^T, u = Q (exp(-i tau theta) * Q^T e_1),
+// err = nrm * beta_{n-1} * |u_{n-1}| (a-posteriori estimate).  One workgroup.
+__global__ __launch_bounds__(256) void tridiag_expm_kernel(const double* alpha, const double* beta, int n,
+                                                           double tau_re, double tau_im, double nrm,
+                                                           double2* u, double* err) {
+  __shared__ double2 G[JS_N * JS_LD];
+  __shared__ double2 Q[JS_N * JS_LD];
+  __shared__ double4 rot[16];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = fmax(scale, fabs(alpha[i]) + (i > 0 ? fabs(beta[i - 1]) : 0.0) +
+                                                      (i + 1 < n ? fabs(beta[i]) : 0.0));
+  for (int e = tid; e < JS_N * JS_N; e += blockDim.x) {
+    int r = e / JS_N, c = e % JS_N;
+    double v = 0.0;
+    if (r < n && c < n) {
+      if (r == c) v = alpha[r];
+      else if (c == r + 1) v = beta[r];
+      else if (r == c + 1) v = beta[c];
+    }
+    G[r * JS_LD + c] = make_double2(v, 0.0);
+  }
+  __syncthreads();
+  herm_jacobi32(G, Q, n, 1e-16 * scale + 1e-300, 0.0, 60, rot, &flag);
+  if (tid < n) {
+    int i = tid;
+    double2 a = make_double2(0.0, 0.0);
+    for (int k = 0; k < n; ++k) {
+      double th = G[k * JS_LD + k].x;
+      // exp(-i tau th) = exp(tau_im th) (cos(tau_re th) - i sin(tau_re th))
+      double mag = exp(tau_im * th), sn, cs;
+      sincos(tau_re * th, &sn, &cs);
+      double q0 = Q[0 * JS_LD + k].x;  // real orthogonal eigenvectors
+      double qi = Q[i * JS_LD + k].x;
+      a.x += qi * mag * cs * q0;
+      a.y -= qi * mag * sn * q0;
+    }
+    u[i] = a;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double2 un = u[n - 1];
+    *err = nrm * fabs(beta[n - 1]) * sqrt(un.x * un.x + un.y * un.y);
+  }
+}
+
+static int vgrid(long long n) { return (int)std::min<long long>((n + 255) / 256, 4096); }
+
+hipError_t launch_zero(hipStream_t s, double* a, int n) {
+  zero_kernel<<<std::max(1, std::min(64, (n + 255) / 256)), 256, 0, s>>>(a, n);
+  return hipGetLastError();
+}
+hipError_t launch_mdot(hipStream_t s, const double2* V, long long ldv, int nv, const double2* r, long long n,
+                       double2* out) {
+  mdot_kernel<<<std::min(vgrid(n), 1024), 256, 0, s>>>(V, ldv, nv, r, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_msub(hipStream_t s, const double2* V, long long ldv, int nv, const double2* c, double2* r,
+                       long long n) {
+  msub_kernel<<<vgrid(n), 256, 0, s>>>(V, ldv, nv, c, r, n);
+  return hipGetLastError();
+}
+hipError_t launch_scale_inv_sqrt(hipStream_t s, const double2* x, double2* y, long long n, const double* norm2) {
+  scale_inv_sqrt_kernel<<<vgrid(n), 256, 0, s>>>(x, y, n, norm2);
+  return hipGetLastError();
+}
+hipError_t launch_combine(hipStream_t s, const double2* V, long long ldv, int nv, const double2* u, double nrm,
+                          double2* x, long long n) {
+  combine_kernel<<<vgrid(n), 256, 0, s>>>(V, ldv, nv, u, nrm, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_convert(hipStream_t s, const void* a, void* b, long long n, bool to_c64) {
+  if (to_c64)
+    c128_to_c64_kernel<<<vgrid(n), 256, 0, s>>>((const double2*)a, (float2*)b, n);
+  else
+    c64_to_c128_kernel<<<vgrid(n), 256, 0, s>>>((const float2*)a, (double2*)b, n);
+  return hipGetLastError();
+}
+hipError_t launch_tridiag_expm(hipStream_t s, const double* alpha, const double* beta, int n, double tau_re,
+                               double tau_im, double nrm, double2* u, double* err) {
+  tridiag_expm_kernel<<<1, 256, 0, s>>>(alpha, beta, n, tau_re, tau_im, nrm, u, err);
+  return hipGetLastError();
+}
+
+// b[j][i] = a[i][j], a: m x n complex128
+__global__ void transpose_c128_kernel(const double2* a, double2* b, int m, int n) {
+  __shared__ double2 t[32][33];
+  int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    int i = by + k, j = bx + threadIdx.x;
+    if (i < m && j < n) t[k][threadIdx.x] = a[(size_t)i * n + j];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    int j = bx + k, i = by + threadIdx.x;
+    if (i < m && j < n) b[(size_t)j * m + i] = t[threadIdx.x][k];
+  }
+}
+
+hipError_t launch_transpose_c128(hipStream_t s, const double2* a, double2* b, int m, int n) {
+  dim3 grid((n + 31) / 32, (m + 31) / 32), block(32, 8);
+  transpose_c128_kernel<<<grid, block, 0, s>>>(a, b, m, n);
+  return hipGetLastError();
+}
+
+// normalised kept rows of a converged Jacobi matrix: row j (sorted) divided
+// by s_j, written as dst[j*len + e] (row-major) or dst[e*k + j] (column-major)
+template <class T>
+__global__ void write_rows_kernel(const JacMat* mat, const int32_t* perm, const double* s2, const SelOut* sel, T* dst,
+                                  int len, int col_major) {
+  const int k = sel->k;
+  const JacMat M = *mat;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < (long long)k * len;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int j = (int)(idx / len), e = (int)(idx % len);
+    int pj = perm[j];
+    pj = (pj >= 0 && pj < M.m) ? pj : 0;
+    double s = sqrt(s2[j]);
+    double inv = s > 0.0 ? 1.0 / s : 0.0;
+    double2 x = M.X[(size_t)pj * M.ld + e];
+    T v;
+    v.x = x.x * inv;
+    v.y = x.y * inv;
+    if (col_major)
+      dst[(size_t)e * k + j] = v;
+    else
+      dst[(size_t)j * len + e] = v;
+  }
+}
+
+hipError_t launch_write_rows(hipStream_t s, const JacMat* mat, const int32_t* perm, const double* s2, const SelOut* sel,
+                             void* dst, int len, int col_major, bool c128) {
+  int g = std::max(1, std::min(4096, (len * 64 + 255) / 256));
+  if (c128)
+    write_rows_kernel<double2><<<g, 256, 0, s>>>(mat, perm, s2, sel, (double2*)dst, len, col_major);
+  else
+    write_rows_kernel<float2><<<g, 256, 0, s>>>(mat, perm, s2, sel, (float2*)dst, len, col_major);
+  return hipGetLastError();
+}

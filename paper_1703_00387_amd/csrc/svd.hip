@@ -307,6 +307,41 @@ __global__ __launch_bounds__(256) void jac_sort_kernel(JacMat* __restrict__ mats
   }
 }
 
+// Largest left and right bond dimensions over the items of a layer.
+__global__ void layer_dims_kernel(const BondItem* __restrict__ items, int n_items, int32_t* out) {
+  __shared__ int ml, mr;
+  if (threadIdx.x == 0) {
+    ml = 1;
+    mr = 1;
+  }
+  __syncthreads();
+  int a = 1, c = 1;
+  for (int i = threadIdx.x; i < n_items; i += blockDim.x) {
+    a = max(a, items[i].chi[items[i].b]);
+    c = max(c, items[i].chi[items[i].b + 2]);
+  }
+  atomicMax(&ml, a);
+  atomicMax(&mr, c);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = ml;
+    out[1] = mr;
+  }
+}
+
+// Largest block count over the batch (bounds the useful rounds of a sweep).
+__global__ void jac_max_nb_kernel(const JacMat* __restrict__ mats, int n_mats, int32_t* out) {
+  __shared__ int mx;
+  if (threadIdx.x == 0) mx = 2;
+  __syncthreads();
+  int local = 2;
+  for (int i = threadIdx.x; i < n_mats; i += blockDim.x)
+    if (!mats[i].conv) local = max(local, mats[i].nb);
+  atomicMax(&mx, local);
+  __syncthreads();
+  if (threadIdx.x == 0) *out = mx;
+}
+
 __global__ void jac_flag_noconv_kernel(const int32_t* unconverged, uint32_t* status) {
   if (*unconverged > 0) atomicOr(status, MPS_DEV_NOCONV_SVD);
 }
@@ -534,6 +569,16 @@ hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t
 hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap) {
   if (n_mats <= 0) return hipSuccess;
   jac_sort_kernel<<<n_mats, 256, (size_t)m_cap * sizeof(double), s>>>(mats, m_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_layer_dims(hipStream_t s, const BondItem* items, int n_items, int32_t* out) {
+  layer_dims_kernel<<<1, 256, 0, s>>>(items, n_items, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_jac_max_nb(hipStream_t s, const JacMat* mats, int n_mats, int32_t* out) {
+  jac_max_nb_kernel<<<1, 256, 0, s>>>(mats, n_mats, out);
   return hipGetLastError();
 }
 

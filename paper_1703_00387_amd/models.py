@@ -66,3 +66,58 @@ def sz_operator() -> np.ndarray:
 
 def number_operator(d: int) -> np.ndarray:
     return np.diag(np.arange(d)).astype(np.complex128)
+
+
+def mpo(spec) -> np.ndarray:
+    """MPO matrices W[k] as an (L, w, w, d, d) complex128 array, [b_l][b_r][s_out][s_in].
+
+    Lower-triangular MPO-matrix form (Eq. MPOdef): identity at the top-left
+    (terms finished) and bottom-right (terms not started); the last row opens a
+    term, the first column closes it.  The left boundary selects row w-1 and
+    the right boundary column 0.
+    """
+    L, d = spec.L, spec.d
+    if spec.model == "tfim":
+        x, _, z = _pauli()
+        one = np.eye(2)
+        J, g = spec.params["J"], spec.params["g"]
+        W = np.zeros((L, 3, 3, 2, 2), dtype=np.complex128)
+        W[:, 0, 0] = one
+        W[:, 1, 0] = z
+        W[:, 2, 0] = -J * g * x
+        W[:, 2, 1] = -J * z
+        W[:, 2, 2] = one
+        return W
+    if spec.model == "xxz":
+        sp = np.array([[0.0, 1.0], [0.0, 0.0]], dtype=np.complex128)
+        sm = sp.T.copy()
+        sz = np.diag([0.5, -0.5]).astype(np.complex128)
+        one = np.eye(2)
+        Jxy = spec.params["Jxy"]
+        W = np.zeros((L, 5, 5, 2, 2), dtype=np.complex128)
+        W[:, 0, 0] = one
+        W[:, 1, 0] = sp
+        W[:, 2, 0] = sm
+        W[:, 3, 0] = sz
+        W[:, 4, 4] = one
+        for k in range(L - 1):
+            W[k, 4, 1] = 0.5 * spec.J_b[k] * Jxy * sm
+            W[k, 4, 2] = 0.5 * spec.J_b[k] * Jxy * sp
+            W[k, 4, 3] = spec.J_b[k] * spec.Jz_b[k] * sz
+        return W
+    if spec.model == "bh":
+        n = np.arange(d, dtype=np.float64)
+        a = np.diag(np.sqrt(n[1:]), 1).astype(np.complex128)
+        ad = a.conj().T
+        one = np.eye(d)
+        t, U = spec.params["t"], spec.params["U"]
+        W = np.zeros((L, 4, 4, d, d), dtype=np.complex128)
+        W[:, 0, 0] = one
+        W[:, 1, 0] = ad
+        W[:, 2, 0] = a
+        W[:, 3, 0] = np.diag(0.5 * U * n * (n - 1))
+        W[:, 3, 1] = -t * a
+        W[:, 3, 2] = -t * ad
+        W[:, 3, 3] = one
+        return W
+    raise ValueError(spec.model)

@@ -237,3 +237,37 @@ def test_nonfinite_flag(H):
     code, word = H.device_status()
     from paper_1703_00387_amd import _lib
     assert code == _lib.MPS_ERR_NONFINITE and word & _lib.MPS_DEV_NONFINITE
+
+
+def test_batch_of_chains_matches_oracle(H):
+    """Several chains of different L and chi_max in one call: each matches the
+    oracle run of that chain alone (the batched workload at reduced size)."""
+    from oracle import mps as omps, models as om
+    from paper_1703_00387_amd import api, models
+    wl = W.xxz_batch256(n_chains=6)
+    specs = []
+    for i, c in enumerate(wl.chains):
+        L = 12 + 2 * i
+        specs.append(W.xxz_chain(L, [16, 32][i % 2], 1.0, 0.5, None, c.Jz_b[:L - 1], "random_product",
+                                 c.local_states[:L]))
+    chains = [_gpu_chain(sp) for sp in specs]
+    api.tebd_step(H, chains, 2, 0.05, 12, 1e-12)
+    for sp, ch in zip(specs, chains):
+        ref = omps.tebd_run(sp, "tebd2", 0.05, 12, 1e-12)
+        site, _, _ = api.observe(H, ch, models.sz_operator())
+        d = np.abs(site.cpu().numpy() - omps.local_expect(ref, 0.5 * om.SZ)).max()
+        assert d <= 1e-6 or sum(ref.disc) >= 1e-8, (sp.L, d)
+
+
+def test_plain_form_equals_batched(H):
+    from paper_1703_00387_amd import api, _lib
+    wl = W.xxz_batch256(n_chains=4)
+    specs = [W.xxz_chain(14, 32, 1.0, 0.5, None, c.Jz_b[:13], "random_product", c.local_states[:14])
+             for c in wl.chains]
+    a = [_gpu_chain(sp) for sp in specs]
+    b = [_gpu_chain(sp) for sp in specs]
+    api.tebd_step(H, a, 2, 0.05, 5, 1e-12)
+    api.tebd_step(H, b, 2, 0.05, 5, 1e-12, flags=_lib.MPS_FLAG_PLAIN)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x.chi, y.chi) and torch.equal(x.B, y.B) and torch.equal(x.lam, y.lam)
