@@ -314,6 +314,15 @@ mps_status mps_observe(mps_handle h, mps_stream stream, const mps_chain_desc* ch
 
 mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
                          int32_t order, double dt, int32_t n_steps, double eps_local, uint32_t flags) {
+  return tebd_impl(h, stream, chains, n_chains, order, dt, n_steps, eps_local, flags, 0, 1 << 30);
+}
+
+}  // extern "C"
+
+// Runs n_steps steps; only layers lo <= index < hi of each step are applied
+// (all of them for the public entry point).
+mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
+                     double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi) {
   if (!h) return MPS_ERR_INVALID;
   if (!chains || n_chains < 1) return mps_fail(h, MPS_ERR_INVALID, "need at least one chain");
   if (order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 2 or 4");
@@ -478,7 +487,9 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
   const int nb_cap = jac_nb(m_cap);
 
   auto run_step = [&]() -> mps_status {
-    for (auto& ly : layers) {
+    for (int li = 0; li < (int)layers.size(); ++li) {
+      if (li < lo || li >= hi) continue;
+      const auto& ly = layers[li];
       const int idx = ly.first * n_cls + ly.second;
       const int n_layer = (int)count[idx];
       if (n_layer == 0) continue;
@@ -562,4 +573,4 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
   return MPS_OK;
 }
 
-}  // extern "C"
+

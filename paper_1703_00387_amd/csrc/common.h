@@ -52,6 +52,10 @@ int jac_nb(int m);
 mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
                       bool fixed);
 
+// TEBD driver with a layer window (api.hip)
+mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
+                     double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi);
+
 // kernel timing helpers (host)
 void prof_begin(mps_handle h, hipStream_t s, int id);
 void prof_end(mps_handle h, hipStream_t s, int id);
