@@ -89,7 +89,7 @@ mps_status mps_kernel_stats(mps_handle h, mps_stream stream, int32_t kernel, dou
                             int64_t* launches, uint64_t* work, int32_t reset);
 
 /*
- * a1. Bond propagators G_n = exp(-i tau_n h_n)   (the local two-site
+ * Bond propagators G_n = exp(-i tau_n h_n)   (the local two-site
  * propagator, step 2 of the plain TEBD update in App. "Details of the Krylov
  * method"; built by a Hermitian
  * Jacobi eigendecomposition h = V diag(e) V^dag in FP64, G = V e^{-i tau e} V^dag).
@@ -102,7 +102,7 @@ mps_status mps_gates(mps_handle h, mps_stream stream, int32_t n, int32_t dd,
                      const void* hmat, const double* tau, void* G64, void* G128);
 
 /*
- * a7. Truncated SVD of one two-site tensor (Sec. "Basic concepts",
+ * Truncated SVD of one two-site tensor (Sec. "Basic concepts",
  * Splitting, SVD case; truncation and discarded weight per Eqs. overlap and
  * elocal; renormalisation of the kept values per App. "Auxiliary calculations").  The SVD runs in FP64 (one-sided block Jacobi).
  *   theta   : complex128 [m][n] input (not modified), m = chi_l*d_l, n = d_r*chi_r
@@ -153,7 +153,7 @@ typedef struct {
 #define MPS_FLAG_PLAIN 0x4u     /* one bond per launch sequence (no batching; comparison form) */
 
 /*
- * a2-a8, a12. n_steps time steps of even/odd Trotter evolution on every chain
+ * n_steps time steps of even/odd Trotter evolution on every chain
  * (Sec. "Sornborger-Stewart decomposition": the even/odd Suzuki-Trotter
  * alternative the paper names; order 2 =
  * Strang splitting: odd bonds tau/2, even bonds tau, odd bonds tau/2; order 4
@@ -171,7 +171,7 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
                          double eps_local, uint32_t flags);
 
 /*
- * a11. Observables of a Hastings-form chain (Sec. "Observables",
+ * Observables of a Hastings-form chain (Sec. "Observables",
  * reduced density matrices of Eq. reducedrho):
  *   site_out[i] = Re sum lam_i[a]^2 conj(B_i[a,s',c]) op1[s',s] B_i[a,s,c]
  *   bond_out[b] = Re <theta_b| op2_b |theta_b>, theta_b = lam_b B_b B_{b+1}
@@ -185,7 +185,7 @@ mps_status mps_observe(mps_handle h, mps_stream stream, const mps_chain_desc* ch
                        double* bond_out, double* entropy_out);
 
 /*
- * a4. Structured effective Hamiltonian y = H_eff x (Sec. "Fundamentals of the
+ * Structured effective Hamiltonian y = H_eff x (Sec. "Fundamentals of the
  * library", Fig. LanczosMPS: the environments and the MPO matrices of the
  * active sites are contracted into x one at a time, O(chi^3), never forming the
  * chi^2 d^2 square matrix).  All operands in `dtype` (MPS_C64 on FP32 MFMA,
@@ -203,7 +203,7 @@ mps_status mps_heff_apply(mps_handle h, mps_stream stream, int32_t dtype, const 
                           int32_t d2, int64_t chi_r, int32_t w_l, int32_t w_m, int32_t w_r);
 
 /*
- * a5. Lanczos exponential x <- exp(-i tau H_eff) x, tau = tau_re + i tau_im
+ * Lanczos exponential x <- exp(-i tau H_eff) x, tau = tau_re + i tau_im
  * (Sec. "Krylov time evolution", Eq. krylov:approx; App. "Details of the Krylov
  * method": with the orthogonality centre in the active sites every Krylov
  * vector and their weighted sum stay local).  Krylov vectors, the three-pass
@@ -221,7 +221,7 @@ mps_status mps_krylov_expm(mps_handle h, mps_stream stream, int32_t dtype, const
                            int32_t n_max, double tol, int32_t* n_used, double* err_est);
 
 /*
- * a9. Environment update (Sec. "Fundamentals of the library": the fixed sites
+ * Environment update (Sec. "Fundamentals of the library": the fixed sites
  * are contracted with their MPO matrices into one left and one right tensor).
  *   side 0 (left):  out[a'][b'][c'] = sum conj(A[a][s'][a']) in[a][b][c] W[b][b'][s'][s] A[c][s][c']
  *                   in [chi_in][w_in][chi_in], A [chi_in][d][chi_out], W [w_in][w_out][d][d]
@@ -251,7 +251,7 @@ typedef struct {
 } mps_oc_chain;
 
 /*
- * a9, a10 and the two-site TDVP sweep (Sec. "Time-dependent variational
+ * The two-site TDVP sweep (Sec. "Time-dependent variational
  * principle"): n_steps symmetric steps; each half-sweep uses tau = dt/2, a
  * forward two-site Lanczos exponential per bond, the FP64 truncated SVD
  * (count rule with eps_local, chi_max), the environment update, and a backward
@@ -262,6 +262,39 @@ typedef struct {
  */
 mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* chain, double dt, int32_t n_steps,
                           double eps_local, int32_t n_max, double tol, double* disc_dev, int32_t* krylov_max_dev);
+
+/*
+ * Reverse-mode gradient of a truncated TEBD2 run (second-order Trotter-Suzuki
+ * splitting of Sec. "Time evolution methods", with the truncated SVD of Sec.
+ * "Basic concepts in tensor network techniques") with respect to per-bond
+ * couplings J_b, where the chain's bond Hamiltonians are h_b = J_b * h0_b.
+ * The paper does not differentiate its runs; this entry point is the exact
+ * adjoint of the update that mps_tebd_step performs.
+ *
+ * Loss = <op1 on `site`> + sum_b <op2 on bond b> of the state after n_steps
+ * (expectation values of Sec. "Observables", in the Hastings form).
+ * The run advances `chain` from its current state exactly as mps_tebd_step
+ * with order 2 and eager scheduling would, keeping one snapshot of the chain
+ * per step in `arena`; the reverse pass re-runs each step layer by layer and
+ * applies the adjoint of every two-site update.  The singular-value backward
+ * keeps the coupling between kept and discarded singular triplets and uses a
+ * Lorentzian broadening `eta` of 1/(s_j^2 - s_i^2) and of 1/s (eta >= 0; 1e-12
+ * is the usual choice).  Only complex128 chains.
+ *   h0      : device complex128 [L-1][d^2][d^2], the unit bond terms
+ *   op1     : device complex128 [d][d];  op2 : device complex128 [d^2][d^2]
+ *   arena   : device memory of at least mps_tebd_grad_arena_bytes(L, d,
+ *             chi_max, n_steps) bytes, owned by the caller (contents scratch)
+ *   loss_dev: FP64 [1];  dJ_dev : FP64 [L-1], overwritten
+ * On return the chain holds the final state; synchronises `stream`.
+ * Errors: MPS_ERR_UNSUPPORTED for complex64 chains, MPS_ERR_CAPACITY for a
+ * short arena or d*chi_max > 2560, MPS_ERR_NONFINITE if a kept weight vanishes.
+ * The device status word carries MPS_DEV_NOCONV_SVD if a reverse-pass SVD did
+ * not converge.
+ */
+size_t mps_tebd_grad_arena_bytes(int32_t L, int32_t d, int32_t chi_max, int32_t n_steps);
+mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0, double dt,
+                         int32_t n_steps, double eps_local, double eta, const void* op1, int32_t site,
+                         const void* op2, void* arena, size_t arena_bytes, double* loss_dev, double* dJ_dev);
 
 #ifdef __cplusplus
 }

@@ -166,6 +166,28 @@ def observe(h: Handle, chain: Chain, op1=None, op2=None, per_bond=False, entropy
     return site, bond, ent
 
 
+def tebd_grad(h: Handle, chain: Chain, h0, dt: float, n_steps: int, eps: float, op1, site: int, op2,
+              eta: float = 1e-12):
+    """Loss <op1 at site> + sum_b <op2 on bond b> after n_steps TEBD2 steps, and
+    its gradient with respect to the per-bond couplings J_b, where the chain's
+    bond Hamiltonians are h_b = J_b * h0[b].  The chain is advanced to the final
+    state.  Returns (loss, dJ) as device tensors (float64, [] and [L-1])."""
+    dev = chain.B.device
+    nbytes = lib().mps_tebd_grad_arena_bytes(chain.L, chain.d, chain.chi_max, n_steps)
+    if nbytes == 0:
+        raise _lib.MPSError(_lib.MPS_ERR_INVALID, "bad shape for the gradient arena")
+    arena = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    h0t = torch.as_tensor(h0, dtype=torch.complex128).to(dev).contiguous()
+    o1 = torch.as_tensor(op1, dtype=torch.complex128).to(dev).contiguous()
+    o2 = torch.as_tensor(op2, dtype=torch.complex128).to(dev).contiguous()
+    loss = torch.zeros((), dtype=torch.float64, device=dev)
+    dJ = torch.zeros(chain.L - 1, dtype=torch.float64, device=dev)
+    d = chain.desc()
+    h.check(lib().mps_tebd_grad(h.h, _stream(), C.byref(d), _ptr(h0t), float(dt), n_steps, float(eps), float(eta),
+                                _ptr(o1), site, _ptr(o2), _ptr(arena), nbytes, _ptr(loss), _ptr(dJ)))
+    return loss, dJ
+
+
 def _code(t):
     return _lib.MPS_C128 if t.dtype == torch.complex128 else _lib.MPS_C64
 

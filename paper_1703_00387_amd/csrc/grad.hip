@@ -1,0 +1,589 @@
+// Reverse-mode gradient of a TEBD2 run with respect to per-bond couplings.
+//
+// Loss: <O1 at one site> + sum_b <O2 on bond b> of the final state (the
+// observables of Sec. "Observables").  The forward run stores the chain at
+// the start of every step (checkpoints); the backward pass restores each step,
+// re-runs its three layers keeping a snapshot before every layer, and walks
+// the updates in reverse.  Per update (Hastings write-back of the forward):
+//   B_b' = theta~' V_k / n_k,  B_{b+1}' = V_k^dag,  lam' = s_k / n_k
+//   theta' = lam_b theta~',  theta~' = G theta~,  theta~ = B_b B_{b+1}.
+// The truncated-SVD backward is the full reduced-SVD backward with the
+// cotangents of the discarded triplets set to zero and U never used (U_bar = 0):
+//   theta'_bar = (theta' V) S^-1 [ X V^dag + diag(s/(s^2+eta)) (V_bar^dag - Jv^dag V^dag) ]
+//   X_ij = F_ij s_i (Jv - Jv^dag)_ij (i != j),  X_ii = s_bar_i - i Im(Jv_ii) s_i/(2 (s_i^2+eta)),
+//   Jv = V^dag V_bar,  F_ij = (s_j^2 - s_i^2) / ((s_j^2 - s_i^2)^2 + eta)
+// (Lorentzian broadening eta; theta' V = U S replaces U).  Singular values
+// below 1e-7 |theta'| that are not kept are treated as exact zeros and enter
+// through the projector (1 - V V^dag).  The coupling gradient of the update is
+// J_bar_b += Re <theta~'_bar, dG/dJ_b theta~> with dG/dJ_b = -i tau h0_b G_b.
+// Everything runs in complex128.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// out[p][i][r] (+)= sum_j op[i][j] in[p][j][r]   (op D x D; dagger: op^dag)
+__global__ void apply_local_kernel(const double2* __restrict__ op, int D, const double2* __restrict__ in,
+                                   double2* __restrict__ out, int P, int R, int dagger, int accumulate) {
+  const long long total = (long long)P * R;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int p = (int)(idx / R), r = (int)(idx % R);
+    const double2* ip = in + (long long)p * D * R + r;
+    double2* opp = out + (long long)p * D * R + r;
+    for (int i = 0; i < D; ++i) {
+      double2 a = make_double2(0.0, 0.0);
+      for (int j = 0; j < D; ++j) {
+        double2 o = dagger ? make_double2(op[j * D + i].x, -op[j * D + i].y) : op[i * D + j];
+        a = cadd(a, cmul(o, ip[(long long)j * R]));
+      }
+      if (accumulate) a = cadd(a, opp[(long long)i * R]);
+      opp[(long long)i * R] = a;
+    }
+  }
+}
+
+// out[r][c] (+)= factor * lam[r / row_div]^power * in[r][c]
+__global__ void row_scale_kernel(const double2* __restrict__ in, double2* out, int rows, int cols,
+                                 const double* __restrict__ lam, int row_div, int power, double factor,
+                                 int accumulate) {
+  const long long total = (long long)rows * cols;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int r = (int)(idx / cols);
+    double l = lam[r / row_div];
+    double f = factor * (power == 2 ? l * l : (power == 1 ? l : 1.0));
+    double2 v = in[idx];
+    v = make_double2(f * v.x, f * v.y);
+    if (accumulate) v = cadd(v, out[idx]);
+    out[idx] = v;
+  }
+}
+
+// lam_bar[a] += mult(a) * Re sum_{rows r: r/row_div = a, c} conj(A[r][c]) B[r][c]
+// mult(a) = factor * (mlam ? mlam[a] : 1).  One workgroup per a.
+__global__ __launch_bounds__(256) void lam_dot_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
+                                                      int row_div, int cols, double* lam_bar,
+                                                      const double* __restrict__ mlam, double factor) {
+  __shared__ double red[4];
+  const int a = blockIdx.x;
+  const long long base = (long long)a * row_div * cols;
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < (long long)row_div * cols; e += blockDim.x) {
+    double2 x = A[base + e], y = B[base + e];
+    acc += x.x * y.x + x.y * y.y;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0] + red[1] + red[2] + red[3];
+    lam_bar[a] += factor * (mlam ? mlam[a] : 1.0) * t;
+  }
+}
+
+// Xt (r x r): the SVD-backward matrix with the left factor written as theta' V,
+// so that theta'_bar = (theta' V) [Xt V^dag + diag(w) (Vbar^dag - Jv^dag V^dag)]:
+//   Xt_ij = F_ij (Jv_ij - conj(Jv_ji))                          (i != j)
+//   Xt_ii = sbar_i / s_i - i Im(Jv_ii) / (2 (s_i^2 + eta))       (i < k, else 0)
+__global__ void svd_x_kernel(const double2* __restrict__ Jv, const double* __restrict__ s,
+                             const double* __restrict__ sbar, int r, int k, double eta, double2* X) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < r * r; e += gridDim.x * blockDim.x) {
+    int i = e / r, j = e % r;
+    double2 v = make_double2(0.0, 0.0);
+    if (i == j) {
+      if (i < k) v = make_double2(sbar[i] / s[i], -0.5 * Jv[e].y / (s[i] * s[i] + eta));
+    } else {
+      double D = s[j] * s[j] - s[i] * s[i];
+      double F = D / (D * D + eta);
+      double2 a = Jv[i * r + j], b = Jv[j * r + i];
+      v = make_double2(F * (a.x - b.x), F * (a.y + b.y));
+    }
+    X[e] = v;
+  }
+}
+
+// Y[i][c] = Y1[i][c] + w_i (conj(Vbar[c][i]) - Z[i][c]),  w_i = 1/(s_i^2+eta) for i < k, else 0
+__global__ void svd_y_kernel(const double2* __restrict__ Y1, const double2* __restrict__ Z,
+                             const double2* __restrict__ Vbar, const double* __restrict__ s, int r, int k, int n,
+                             double eta, double2* Y) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)r * n;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(e / n), c = (int)(e % n);
+    double2 y = Y1[e];
+    if (i < k) {
+      double w = 1.0 / (s[i] * s[i] + eta);
+      double2 vb = Vbar[(long long)c * r + i];
+      y = make_double2(y.x + w * (vb.x - Z[e].x), y.y + w * (-vb.y - Z[e].y));
+    }
+    Y[e] = y;
+  }
+}
+
+// out[j] = sum_i |P[i][j]|^2   (P rows x cols, row-major)
+__global__ void colnorm2_kernel(const double2* __restrict__ P, int rows, int cols, double* out) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < cols; j += gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int i = 0; i < rows; ++i) {
+      double2 v = P[(long long)i * cols + j];
+      a += v.x * v.x + v.y * v.y;
+    }
+    out[j] = a;
+  }
+}
+
+// Vbar[i][j] += conj(Bn_bar[j][i]) for j < k   (Vbar n x r, Bn_bar k x n)
+__global__ void add_conj_t_kernel(double2* Vbar, const double2* __restrict__ Bnb, int n, int r, int k) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)n * k;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i = (int)(e / k), j = (int)(e % k);
+    double2 b = Bnb[(long long)j * n + i];
+    double2& v = Vbar[(long long)i * r + j];
+    v = make_double2(v.x + b.x, v.y - b.y);
+  }
+}
+
+// site tensor between the chain's capacity layout and a compact [chl][d][chr] block
+__global__ void site_copy_kernel(const double2* __restrict__ src, double2* __restrict__ dst, int chl, int d, int chr,
+                                 int chi_max, int to_compact) {
+  const long long total = (long long)chl * d * chr;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    int c = (int)(e % chr);
+    long long as = e / chr;
+    long long cap = as * chi_max + c;
+    if (to_compact)
+      dst[e] = src[cap];
+    else
+      dst[cap] = src[e];
+  }
+}
+
+__global__ void fill_zero_kernel(double2* a, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    a[e] = make_double2(0.0, 0.0);
+}
+
+__global__ void axpy_kernel(const double2* __restrict__ x, double2* y, long long n, double a) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    y[e] = make_double2(y[e].x + a * x[e].x, y[e].y + a * x[e].y);
+}
+
+// J_bar[b] += Re dot
+__global__ void jbar_add_kernel(const double2* dot, double* jbar, int b) { jbar[b] += dot[0].x; }
+
+// dG = -i tau h0 G   (d2 x d2)
+__global__ void dgate_kernel(const double2* h0, const double2* G, double tau, int D, double2* dG) {
+  for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+    int i = e / D, j = e % D;
+    double2 a = make_double2(0.0, 0.0);
+    for (int k = 0; k < D; ++k) a = cadd(a, cmul(h0[i * D + k], G[k * D + j]));
+    dG[e] = make_double2(tau * a.y, -tau * a.x);  // -i tau a
+  }
+}
+
+namespace {
+
+int g1d(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096)); }
+
+struct Ctx {
+  mps_handle h;
+  hipStream_t s;
+};
+
+#define K1(call)                                       \
+  do {                                                 \
+    call;                                              \
+    MPS_TRY_HIP(c.h, hipGetLastError());               \
+  } while (0)
+
+mps_status gemm128(Ctx& c, const void* A, long long rsA, long long csA, int conjA, const void* B, long long rsB,
+                   long long csB, int conjB, void* C, long long rsC, int M, int N, int K, double alpha) {
+  SGemm g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A; g.rsA = rsA; g.csA = csA; g.conjA = conjA;
+  g.B = B; g.rsB = rsB; g.csB = csB; g.conjB = conjB;
+  g.C = C; g.rsC = rsC; g.csC = 1;
+  g.M = M; g.N = N; g.K = K; g.alpha = alpha;
+  if (K <= 0) {
+    K1((fill_zero_kernel<<<g1d((long long)M * N), 256, 0, c.s>>>((double2*)C, (long long)M * N)));
+    return MPS_OK;
+  }
+  MPS_TRY_HIP(c.h, launch_sgemm(c.s, g, true));
+  return MPS_OK;
+}
+
+// Layout of the caller's arena: (n_steps + 1) step checkpoints, three layer
+// snapshots, the site and bond cotangents, the gates and their derivatives.
+struct GradArena {
+  size_t snapB, snapL, snapC, snap;
+  size_t oCk, oLay, oBb, oLb, oG, oDG, oGJ, total;
+  GradArena(int L, int d, int cm, int n_steps) {
+    const size_t site_el = (size_t)cm * d * cm, dd = (size_t)d * d;
+    snapB = (size_t)L * site_el * sizeof(double2);
+    snapL = (size_t)(L + 1) * cm * sizeof(double);
+    snapC = (size_t)(L + 1) * sizeof(int32_t);
+    snap = al(snapB) + al(snapL) + al(snapC);
+    WsPlan p;
+    oCk = p.take<char>((size_t)(n_steps + 1) * snap);
+    oLay = p.take<char>(3 * snap);
+    oBb = p.take<double2>((size_t)L * site_el);
+    oLb = p.take<double>((size_t)(L + 1) * cm);
+    oG = p.take<double2>((size_t)2 * (L - 1) * dd * dd);
+    oDG = p.take<double2>((size_t)2 * (L - 1) * dd * dd);
+    oGJ = p.take<GateJob>((size_t)2 * (L - 1));
+    total = p.off;
+  }
+  static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+  void ptrs(char* base, double2*& B, double*& lam, int32_t*& chi) const {
+    B = (double2*)base;
+    lam = (double*)(base + al(snapB));
+    chi = (int32_t*)(base + al(snapB) + al(snapL));
+  }
+};
+
+// per-update scratch in the handle workspace (re-carved after every TEBD call,
+// which may regrow the workspace)
+struct GradScratch {
+  double2 *T0, *T1, *P0, *Xj, *Vh, *Vb, *Y1, *Z, *Y, *Pm, *Pb, *T1b, *T0b, *Bnew, *Bbl, *Bnl, *Bbs, *Bns, *Jv, *Xm;
+  double2* dot;
+  double *sv, *sbar, *s2, *cn2, *obs;
+  JacMat* mat;
+  SelOut *sel, *seld;
+  int32_t *rowmap, *perm, *unc;
+};
+
+mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
+  const size_t r = (size_t)d * cm, mn = r * r, site_el = (size_t)cm * d * cm;
+  WsPlan p;
+  size_t o[20];
+  for (int i = 0; i < 16; ++i) o[i] = p.take<double2>(mn);
+  for (int i = 16; i < 20; ++i) o[i] = p.take<double2>(site_el);
+  size_t oDot = p.take<double2>(32);
+  size_t oS = p.take<double>(r), oSb = p.take<double>(r), oS2 = p.take<double>(r), oCn = p.take<double>(r),
+         oObs = p.take<double>(2 * (size_t)L);
+  size_t oMat = p.take<JacMat>(1), oSel = p.take<SelOut>(1), oSeld = p.take<SelOut>(1);
+  size_t oRm = p.take<int32_t>(2 * r), oPm = p.take<int32_t>(r), oUnc = p.take<int32_t>(8);
+  mps_status st = mps_ensure_ws(h, p.off);
+  if (st != MPS_OK) return st;
+  char* ws = h->ws;
+  double2** mats[20] = {&g.T0, &g.T1, &g.P0, &g.Xj, &g.Vh, &g.Vb, &g.Y1, &g.Z, &g.Y, &g.Pm,
+                        &g.Pb, &g.T1b, &g.T0b, &g.Bnew, &g.Jv, &g.Xm, &g.Bbl, &g.Bnl, &g.Bbs, &g.Bns};
+  for (int i = 0; i < 20; ++i) *mats[i] = (double2*)(ws + o[i]);
+  g.dot = (double2*)(ws + oDot);
+  g.sv = (double*)(ws + oS);
+  g.sbar = (double*)(ws + oSb);
+  g.s2 = (double*)(ws + oS2);
+  g.cn2 = (double*)(ws + oCn);
+  g.obs = (double*)(ws + oObs);
+  g.mat = (JacMat*)(ws + oMat);
+  g.sel = (SelOut*)(ws + oSel);
+  g.seld = (SelOut*)(ws + oSeld);
+  g.rowmap = (int32_t*)(ws + oRm);
+  g.perm = (int32_t*)(ws + oPm);
+  g.unc = (int32_t*)(ws + oUnc);
+  return MPS_OK;
+}
+
+}  // namespace
+
+extern "C" size_t mps_tebd_grad_arena_bytes(int32_t L, int32_t d, int32_t chi_max, int32_t n_steps) {
+  if (L < 2 || d < 1 || chi_max < 1 || n_steps < 1) return 0;
+  return GradArena(L, d, chi_max, n_steps).total;
+}
+
+extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0,
+                                    double dt, int32_t n_steps, double eps_local, double eta, const void* op1,
+                                    int32_t site, const void* op2, void* arena_ptr, size_t arena_bytes,
+                                    double* loss_dev, double* dJ_dev) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!chain || !h0 || !op1 || !op2 || !loss_dev || !dJ_dev || !arena_ptr)
+    return mps_fail(h, MPS_ERR_INVALID, "null pointer");
+  const mps_chain_desc ch = *chain;
+  if (ch.dtype != MPS_C128) return mps_fail(h, MPS_ERR_UNSUPPORTED, "the gradient needs a complex128 chain");
+  if (ch.L < 2 || ch.d < 1 || ch.d > 5 || ch.chi_max < 1) return mps_fail(h, MPS_ERR_SHAPE, "bad chain shape");
+  if ((int64_t)ch.d * ch.chi_max > 2560) return mps_fail(h, MPS_ERR_CAPACITY, "d*chi_max is limited to 2560");
+  if (site < 0 || site >= ch.L) return mps_fail(h, MPS_ERR_INVALID, "site out of range");
+  if (n_steps < 1) return mps_fail(h, MPS_ERR_INVALID, "n_steps must be >= 1");
+  if (!(eta >= 0.0) || !(dt > 0.0) || !(eps_local >= 0.0)) return mps_fail(h, MPS_ERR_INVALID, "bad dt, eps or eta");
+  const int L = ch.L, d = ch.d, cm = ch.chi_max, dd = d * d;
+  const GradArena A(L, d, cm, n_steps);
+  if (arena_bytes < A.total)
+    return mps_fail(h, MPS_ERR_CAPACITY, "arena smaller than mps_tebd_grad_arena_bytes()");
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c{h, s};
+  const size_t site_el = (size_t)cm * d * cm;
+  char* arena = (char*)arena_ptr;
+  char* lay = arena + A.oLay;
+  double2* Bbar = (double2*)(arena + A.oBb);
+  double* lbar = (double*)(arena + A.oLb);
+  double2* Gt = (double2*)(arena + A.oG);
+  double2* dG = (double2*)(arena + A.oDG);
+  auto bbar = [&](int i) { return Bbar + (size_t)i * site_el; };
+  auto Gp = [&](int k, int b) { return Gt + ((size_t)k * (L - 1) + b) * dd * dd; };
+  auto dGp = [&](int k, int b) { return dG + ((size_t)k * (L - 1) + b) * dd * dd; };
+  auto save = [&](char* dst) -> mps_status {
+    double2* B;
+    double* lam;
+    int32_t* chi;
+    A.ptrs(dst, B, lam, chi);
+    MPS_TRY_HIP(h, hipMemcpyAsync(B, ch.B, A.snapB, hipMemcpyDeviceToDevice, s));
+    MPS_TRY_HIP(h, hipMemcpyAsync(lam, ch.lam, A.snapL, hipMemcpyDeviceToDevice, s));
+    MPS_TRY_HIP(h, hipMemcpyAsync(chi, ch.chi, A.snapC, hipMemcpyDeviceToDevice, s));
+    return MPS_OK;
+  };
+  auto restore = [&](char* src) -> mps_status {
+    double2* B;
+    double* lam;
+    int32_t* chi;
+    A.ptrs(src, B, lam, chi);
+    MPS_TRY_HIP(h, hipMemcpyAsync(ch.B, B, A.snapB, hipMemcpyDeviceToDevice, s));
+    MPS_TRY_HIP(h, hipMemcpyAsync(ch.lam, lam, A.snapL, hipMemcpyDeviceToDevice, s));
+    MPS_TRY_HIP(h, hipMemcpyAsync(ch.chi, chi, A.snapC, hipMemcpyDeviceToDevice, s));
+    return MPS_OK;
+  };
+  mps_status r;
+
+  // ---- forward with a checkpoint per step --------------------------------
+  for (int st = 0; st < n_steps; ++st) {
+    if ((r = save(arena + A.oCk + (size_t)st * A.snap)) != MPS_OK) return r;
+    if ((r = tebd_impl(h, stream, &ch, 1, 2, dt, 1, eps_local, 0, 0, 3)) != MPS_OK) return r;
+  }
+  if ((r = save(arena + A.oCk + (size_t)n_steps * A.snap)) != MPS_OK) return r;
+
+  // ---- gates of the two classes (tau = dt/2 on odd layers, dt on the even one) and dG/dJ
+  const double taus[2] = {0.5 * dt, dt};
+  {
+    std::vector<GateJob> jobs;
+    for (int k = 0; k < 2; ++k)
+      for (int b = 0; b < L - 1; ++b) {
+        GateJob j;
+        std::memset(&j, 0, sizeof(j));
+        j.h = (const double2*)ch.hbond + (size_t)b * dd * dd;
+        j.G64 = nullptr;
+        j.G128 = Gp(k, b);
+        j.tau = taus[k];
+        jobs.push_back(j);
+      }
+    MPS_TRY_HIP(h, hipMemcpyAsync(arena + A.oGJ, jobs.data(), jobs.size() * sizeof(GateJob), hipMemcpyHostToDevice, s));
+    MPS_TRY_HIP(h, hipStreamSynchronize(s));
+    MPS_TRY_HIP(h, launch_gates(s, (const GateJob*)(arena + A.oGJ), (int)jobs.size(), dd));
+    for (int k = 0; k < 2; ++k)
+      for (int b = 0; b < L - 1; ++b)
+        K1((dgate_kernel<<<1, 256, 0, s>>>((const double2*)h0 + (size_t)b * dd * dd, Gp(k, b), taus[k], dd,
+                                            dGp(k, b))));
+  }
+  MPS_TRY_HIP(h, hipMemsetAsync(dJ_dev, 0, (L - 1) * sizeof(double), s));
+
+  // ---- loss and its cotangents at the final state -------------------------
+  GradScratch g;
+  if ((r = grad_scratch(h, L, d, cm, g)) != MPS_OK) return r;
+  std::vector<int32_t> chi(L + 1);
+  MPS_TRY_HIP(h, hipMemcpyAsync(chi.data(), ch.chi, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  {
+    MPS_TRY_HIP(h, launch_observe(s, ch, (const double2*)op1, g.obs, (const double2*)op2, 0, g.obs + L, nullptr));
+    std::vector<double> o(2 * L);
+    MPS_TRY_HIP(h, hipMemcpyAsync(o.data(), g.obs, (2 * L - 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    MPS_TRY_HIP(h, hipStreamSynchronize(s));
+    double loss = o[site];
+    for (int b = 0; b < L - 1; ++b) loss += o[L + b];
+    MPS_TRY_HIP(h, hipMemcpyAsync(loss_dev, &loss, sizeof(double), hipMemcpyHostToDevice, s));
+    MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  }
+  K1((fill_zero_kernel<<<g1d((long long)L * site_el), 256, 0, s>>>(Bbar, (long long)L * site_el)));
+  MPS_TRY_HIP(h, hipMemsetAsync(lbar, 0, (L + 1) * cm * sizeof(double), s));
+  {
+    // site term <O1>_i = sum_a lam_a^2 <B_a|O1|B_a>: B_bar += 2 lam^2 O1 B, lam_bar += 2 lam Re<B, O1 B>
+    const int i = site, a = chi[i], b2 = chi[i + 1];
+    K1((site_copy_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>((const double2*)ch.B + i * site_el, g.Bbs, a, d,
+                                                                     b2, cm, 1)));
+    K1((apply_local_kernel<<<g1d((long long)a * b2), 256, 0, s>>>((const double2*)op1, d, g.Bbs, g.T0, a, b2, 0, 0)));
+    K1((row_scale_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>(g.T0, bbar(i), a * d, b2, ch.lam + (size_t)i * cm,
+                                                                     d, 2, 2.0, 1)));
+    K1((lam_dot_kernel<<<a, 256, 0, s>>>(g.Bbs, g.T0, d, b2, lbar + (size_t)i * cm, ch.lam + (size_t)i * cm, 2.0)));
+    // bond terms <theta|O2|theta>, theta = lam_b B_b B_{b+1}
+    for (int b = 0; b < L - 1; ++b) {
+      const int chl = chi[b], chm = chi[b + 1], chr = chi[b + 2], m = chl * d, n = d * chr;
+      K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>((const double2*)ch.B + b * site_el, g.Bbs, chl, d,
+                                                                    chm, cm, 1)));
+      K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>((const double2*)ch.B + (b + 1) * site_el, g.Bns,
+                                                                    chm, d, chr, cm, 1)));
+      if ((r = gemm128(c, g.Bbs, chm, 1, 0, g.Bns, n, 1, 0, g.T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
+      K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.T0, g.T1, m, n, ch.lam + (size_t)b * cm, d, 1, 1.0,
+                                                                  0)));
+      K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>((const double2*)op2, dd, g.T1, g.P0, chl, chr,
+                                                                        0, 0)));
+      // theta_bar = 2 O2 theta; lam_bar_b += Re<theta_bar, X>; X_bar = lam_b theta_bar
+      K1((lam_dot_kernel<<<chl, 256, 0, s>>>(g.P0, g.T0, d, n, lbar + (size_t)b * cm, nullptr, 2.0)));
+      K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.P0, g.Pb, m, n, ch.lam + (size_t)b * cm, d, 1, 2.0,
+                                                                  0)));
+      if ((r = gemm128(c, g.Pb, n, 1, 0, g.Bns, 1, n, 1, g.Y1, chm, m, chm, n, 1.0)) != MPS_OK) return r;
+      if ((r = gemm128(c, g.Bbs, 1, chm, 1, g.Pb, n, 1, 0, g.Z, n, chm, n, m, 1.0)) != MPS_OK) return r;
+      K1((axpy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>(g.Y1, bbar(b), (long long)m * chm, 1.0)));
+      K1((axpy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>(g.Z, bbar(b + 1), (long long)chm * n, 1.0)));
+    }
+  }
+
+  // ---- backward over steps and layers -------------------------------------
+  const double abs_saved = h->jac_abs;
+  for (int stp = n_steps - 1; stp >= 0; --stp) {
+    if ((r = restore(arena + A.oCk + (size_t)stp * A.snap)) != MPS_OK) return r;
+    for (int li = 0; li < 3; ++li) {
+      if ((r = save(lay + (size_t)li * A.snap)) != MPS_OK) return r;
+      if ((r = tebd_impl(h, stream, &ch, 1, 2, dt, 1, eps_local, 0, li, li + 1)) != MPS_OK) return r;
+    }
+    if ((r = grad_scratch(h, L, d, cm, g)) != MPS_OK) return r;
+    for (int li = 2; li >= 0; --li) {
+      double2 *SB, *NB;
+      double *SL, *NL;
+      int32_t *SC, *NC;
+      A.ptrs(lay + (size_t)li * A.snap, SB, SL, SC);
+      if (li < 2) {
+        A.ptrs(lay + (size_t)(li + 1) * A.snap, NB, NL, NC);
+      } else {
+        NB = (double2*)ch.B;
+        NL = ch.lam;
+        NC = ch.chi;
+      }
+      std::vector<int32_t> co(L + 1), cn(L + 1);
+      MPS_TRY_HIP(h, hipMemcpyAsync(co.data(), SC, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      MPS_TRY_HIP(h, hipMemcpyAsync(cn.data(), NC, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      MPS_TRY_HIP(h, hipStreamSynchronize(s));
+      const int par = (li == 1) ? 1 : 0, cls = (li == 1) ? 1 : 0;
+      for (int b = par; b < L - 1; b += 2) {
+        const int chl = co[b], chm = co[b + 1], chr = co[b + 2], m = chl * d, n = d * chr, k = cn[b + 1];
+        const int rmax = std::min(m, n);
+        const double* lam_b = SL + (size_t)b * cm;
+        // cotangents of the updated tensors, compact: B_b' [m][k], B_{b+1}' [k][n], lam' [k]
+        MPS_TRY_HIP(h, hipMemcpyAsync(g.Bbl, bbar(b), (size_t)m * k * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        MPS_TRY_HIP(h, hipMemcpyAsync(g.Bnl, bbar(b + 1), (size_t)k * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        std::vector<double> lbm(k);
+        MPS_TRY_HIP(h, hipMemcpyAsync(lbm.data(), lbar + (size_t)(b + 1) * cm, k * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+        // recompute theta~ = B_b B_{b+1}, theta~' = G theta~, theta' = lam_b theta~'
+        K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>(SB + b * site_el, g.Bbs, chl, d, chm, cm, 1)));
+        K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>(SB + (b + 1) * site_el, g.Bns, chm, d, chr, cm,
+                                                                      1)));
+        if ((r = gemm128(c, g.Bbs, chm, 1, 0, g.Bns, n, 1, 0, g.T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
+        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>(Gp(cls, b), dd, g.T0, g.T1, chl, chr, 0, 0)));
+        K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.T1, g.P0, m, n, lam_b, d, 1, 1.0, 0)));
+        // the forward's own factors: V_k^dag = B_{b+1}', B_b' = theta~' V_k / n_k
+        K1((site_copy_kernel<<<g1d((long long)k * n), 256, 0, s>>>(NB + (b + 1) * site_el, g.Vh, k, d, chr, cm, 1)));
+        K1((site_copy_kernel<<<g1d((long long)m * k), 256, 0, s>>>(NB + b * site_el, g.Bnew, chl, d, k, cm, 1)));
+        // discarded directions: rows of the residual theta' (1 - V_k V_k^dag), orthogonalised
+        // by the Jacobi sweep with a purely relative tolerance and projected once more
+        if ((r = gemm128(c, g.P0, n, 1, 0, g.Vh, 1, n, 1, g.Pm, k, m, k, n, 1.0)) != MPS_OK) return r;
+        if ((r = gemm128(c, g.Pm, k, 1, 0, g.Vh, n, 1, 0, g.Z, n, m, n, k, 1.0)) != MPS_OK) return r;
+        MPS_TRY_HIP(h, hipMemcpyAsync(g.Xj, g.P0, (size_t)m * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        K1((axpy_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.Z, g.Xj, (long long)m * n, -1.0)));
+        K1((colnorm2_kernel<<<g1d(k), 256, 0, s>>>(g.Pm, m, k, g.cn2)));
+        int rd = 0;
+        std::vector<double> s2h(m, 0.0), kept2(k);
+        if (rmax > k) {
+          JacMat hm;
+          std::memset(&hm, 0, sizeof(hm));
+          hm.X = g.Xj;
+          hm.rowmap = g.rowmap;
+          hm.m = m;
+          hm.n = n;
+          hm.ld = n;
+          hm.nb = jac_nb(m);
+          hm.kmax = rmax - k;
+          MPS_TRY_HIP(h, hipMemcpyAsync(g.mat, &hm, sizeof(hm), hipMemcpyHostToDevice, s));
+          MPS_TRY_HIP(h, launch_jac_prep_plain(s, g.mat, 1, h->status_dev));
+          h->jac_abs = 0.0;
+          r = run_jacobi(h, s, g.mat, 1, hm.nb, m, g.unc, false);
+          h->jac_abs = abs_saved;
+          if (r != MPS_OK) return r;
+          MPS_TRY_HIP(h, launch_select(s, g.mat, 1, g.perm, g.s2, m, hm.kmax, 0.0, g.sel));
+          MPS_TRY_HIP(h, hipMemcpyAsync(s2h.data(), g.s2, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        MPS_TRY_HIP(h, hipMemcpyAsync(kept2.data(), g.cn2, k * sizeof(double), hipMemcpyDeviceToHost, s));
+        MPS_TRY_HIP(h, hipStreamSynchronize(s));
+        double tot = 0.0;
+        for (int j = 0; j < k; ++j) tot += kept2[j];
+        for (int j = 0; j < m; ++j) tot += std::max(s2h[j], 0.0);
+        while (k + rd < rmax && s2h[rd] > 1e-26 * tot) ++rd;
+        const int ru = k + rd;
+        if (rd > 0) {
+          SelOut so;
+          std::memset(&so, 0, sizeof(so));
+          so.k = rd;
+          MPS_TRY_HIP(h, hipMemcpyAsync(g.seld, &so, sizeof(so), hipMemcpyHostToDevice, s));
+          double2* Vd = g.Vh + (size_t)k * n;
+          MPS_TRY_HIP(h, launch_write_rows(s, g.mat, g.perm, g.s2, g.seld, Vd, n, 0, true));
+          if ((r = gemm128(c, Vd, n, 1, 0, g.Vh, 1, n, 1, g.Jv, k, rd, k, n, 1.0)) != MPS_OK) return r;
+          if ((r = gemm128(c, g.Jv, k, 1, 0, g.Vh, n, 1, 0, g.Z, n, rd, n, k, 1.0)) != MPS_OK) return r;
+          K1((axpy_kernel<<<g1d((long long)rd * n), 256, 0, s>>>(g.Z, Vd, (long long)rd * n, -1.0)));
+        }
+        // P = theta' V (m x ru), s_i = |P e_i|
+        if ((r = gemm128(c, g.P0, n, 1, 0, g.Vh, 1, n, 1, g.Pm, ru, m, ru, n, 1.0)) != MPS_OK) return r;
+        K1((colnorm2_kernel<<<g1d(ru), 256, 0, s>>>(g.Pm, m, ru, g.cn2)));
+        // n_bar = -(Re<B_bar_b', B_b'> + sum lam_bar' lam') / n_k,  s_bar = lam_bar'/n_k + n_bar s/n_k
+        MPS_TRY_HIP(h, launch_zero(s, (double*)g.dot, 64));
+        MPS_TRY_HIP(h, launch_mdot(s, g.Bbl, 0, 1, g.Bnew, (long long)m * k, g.dot));
+        double2 dh;
+        std::vector<double> sh2(ru);
+        MPS_TRY_HIP(h, hipMemcpyAsync(&dh, g.dot, sizeof(dh), hipMemcpyDeviceToHost, s));
+        MPS_TRY_HIP(h, hipMemcpyAsync(sh2.data(), g.cn2, ru * sizeof(double), hipMemcpyDeviceToHost, s));
+        MPS_TRY_HIP(h, hipStreamSynchronize(s));
+        std::vector<double> sh(ru), sb(ru, 0.0);
+        double nk2 = 0.0;
+        for (int j = 0; j < ru; ++j) sh[j] = std::sqrt(std::max(sh2[j], 0.0));
+        for (int j = 0; j < k; ++j) nk2 += sh2[j];
+        const double nk = std::sqrt(nk2);
+        if (!(nk > 0.0)) return mps_fail(h, MPS_ERR_NONFINITE, "vanishing kept weight in the reverse pass");
+        double ll = 0.0;
+        for (int j = 0; j < k; ++j) ll += lbm[j] * sh[j] / nk;
+        const double nbar = -(dh.x + ll) / nk;
+        for (int j = 0; j < k; ++j) sb[j] = lbm[j] / nk + nbar * sh[j] / nk;
+        MPS_TRY_HIP(h, hipMemcpyAsync(g.sv, sh.data(), ru * sizeof(double), hipMemcpyHostToDevice, s));
+        MPS_TRY_HIP(h, hipMemcpyAsync(g.sbar, sb.data(), ru * sizeof(double), hipMemcpyHostToDevice, s));
+        // V_bar (n x ru): kept columns theta~'^dag B_bar_b' / n_k + conj(B_bar_{b+1}')^T
+        K1((fill_zero_kernel<<<g1d((long long)n * ru), 256, 0, s>>>(g.Vb, (long long)n * ru)));
+        {
+          SGemm G;
+          std::memset(&G, 0, sizeof(G));
+          G.A = g.T1; G.rsA = 1; G.csA = n; G.conjA = 1;
+          G.B = g.Bbl; G.rsB = k; G.csB = 1;
+          G.C = g.Vb; G.rsC = ru; G.csC = 1;
+          G.M = n; G.N = k; G.K = m; G.alpha = 1.0 / nk;
+          MPS_TRY_HIP(h, launch_sgemm(s, G, true));
+        }
+        K1((add_conj_t_kernel<<<g1d((long long)n * k), 256, 0, s>>>(g.Vb, g.Bnl, n, ru, k)));
+        // Jv = V^dag V_bar; Xt; Y = Xt V^dag + diag(w)(V_bar^dag - Jv^dag V^dag); theta'_bar = P Y
+        if ((r = gemm128(c, g.Vh, n, 1, 0, g.Vb, ru, 1, 0, g.Jv, ru, ru, ru, n, 1.0)) != MPS_OK) return r;
+        K1((svd_x_kernel<<<g1d((long long)ru * ru), 256, 0, s>>>(g.Jv, g.sv, g.sbar, ru, k, eta, g.Xm)));
+        if ((r = gemm128(c, g.Xm, ru, 1, 0, g.Vh, n, 1, 0, g.Y1, n, ru, n, ru, 1.0)) != MPS_OK) return r;
+        if ((r = gemm128(c, g.Jv, 1, ru, 1, g.Vh, n, 1, 0, g.Z, n, ru, n, ru, 1.0)) != MPS_OK) return r;
+        K1((svd_y_kernel<<<g1d((long long)ru * n), 256, 0, s>>>(g.Y1, g.Z, g.Vb, g.sv, ru, k, n, eta, g.Y)));
+        if ((r = gemm128(c, g.Pm, ru, 1, 0, g.Y, n, 1, 0, g.Pb, n, m, n, ru, 1.0)) != MPS_OK) return r;
+        // theta~'_bar = B_bar_b' V_k^dag / n_k + lam_b theta'_bar;  lam_bar_b += Re<theta'_bar, theta~'>
+        if ((r = gemm128(c, g.Bbl, k, 1, 0, g.Vh, n, 1, 0, g.T1b, n, m, n, k, 1.0 / nk)) != MPS_OK) return r;
+        K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.Pb, g.T1b, m, n, lam_b, d, 1, 1.0, 1)));
+        K1((lam_dot_kernel<<<chl, 256, 0, s>>>(g.Pb, g.T1, d, n, lbar + (size_t)b * cm, nullptr, 1.0)));
+        // coupling: J_bar_b += Re<theta~'_bar, dG/dJ_b theta~>
+        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>(dGp(cls, b), dd, g.T0, g.Z, chl, chr, 0, 0)));
+        MPS_TRY_HIP(h, launch_zero(s, (double*)g.dot, 64));
+        MPS_TRY_HIP(h, launch_mdot(s, g.T1b, 0, 1, g.Z, (long long)m * n, g.dot));
+        K1((jbar_add_kernel<<<1, 1, 0, s>>>(g.dot, dJ_dev, b)));
+        // theta~_bar = G^dag theta~'_bar;  B_bar_b = theta~_bar B_{b+1}^dag;  B_bar_{b+1} = B_b^dag theta~_bar
+        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>(Gp(cls, b), dd, g.T1b, g.T0b, chl, chr, 1,
+                                                                          0)));
+        if ((r = gemm128(c, g.T0b, n, 1, 0, g.Bns, 1, n, 1, bbar(b), chm, m, chm, n, 1.0)) != MPS_OK) return r;
+        if ((r = gemm128(c, g.Bbs, 1, chm, 1, g.T0b, n, 1, 0, bbar(b + 1), n, chm, n, m, 1.0)) != MPS_OK) return r;
+        MPS_TRY_HIP(h, hipMemsetAsync(lbar + (size_t)(b + 1) * cm, 0, cm * sizeof(double), s));
+      }
+    }
+  }
+  // the chain is left in the final state of the forward run
+  if ((r = restore(arena + A.oCk + (size_t)n_steps * A.snap)) != MPS_OK) return r;
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  return MPS_OK;
+}
