@@ -24,6 +24,27 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of jac_round_kernel on this workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) over one TEBD4 step from the step-140
+# state, each scaled by the same counter's reading for a plain streaming kernel
+# of known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid only for the
+# kernel source it was measured on (hash of its files); otherwise null.
+JAC_ROUND_TRAFFIC = {
+    "sources_sha256": "bbd39274c81e8cf603993b05bbd19bda41f2976c4dcd69ce297355cb95307e15",
+    "bytes_per_launch": 2.0719e8,
+}
+JAC_ROUND_SOURCES = ("svd.hip", "jacobi_small.h", "mfma_tile.h")
+
+
+def _jac_round_traffic():
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in JAC_ROUND_SOURCES:
+        with open(os.path.join(ROOT, "paper_1703_00387_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    ok = hsh.hexdigest() == JAC_ROUND_TRAFFIC["sources_sha256"]
+    return JAC_ROUND_TRAFFIC["bytes_per_launch"] if ok else None
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -128,7 +149,7 @@ def main():
                                 "n_at_cap": int((chi >= spec.chi_max).sum())}},
         "roofline": {"kernel": "jac_round_kernel (FP64 block-Jacobi round: Gram + rotation)",
                      "bound": "mfma", "achieved": round(jr_ach, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(jr_ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(jr_ach / FP64_PEAK_TFLOPS, 4), "traffic": _jac_round_traffic(),
                      "avg_launch_us": round(jr_avg_s * 1e6, 2), "launches": jr_n},
         "mfma": {"kernel": "theta_gate_kernel", "achieved": round(th_ach, 3), "peak": mfma_peak,
                  "unit": "TFLOP/s", "frac": round(th_ach / mfma_peak, 4)},
