@@ -48,7 +48,7 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
   const int max_sweeps = fixed ? std::min(kFixedSweeps, h->jac_max_sweeps) : h->jac_max_sweeps;
   bool done = false;
   for (int sw = 0; sw < max_sweeps && !done; ++sw) {
-    MPS_TRY_HIP(h, launch_jac_sort(s, mats, n, m_cap));
+    if (sw > 0) MPS_TRY_HIP(h, launch_jac_sort(s, mats, n, m_cap));
     for (int r = 0; r < nb - 1; ++r)
       PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs, h->jac_inner_sweeps,
                                                               h->profile ? h->stats_dev : nullptr));
@@ -269,6 +269,7 @@ mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int6
   size_t oSel = p.take<SelOut>(1);
   size_t oU = p.take<int32_t>(4);
   size_t oR = p.take<int32_t>(m);
+  size_t oNr = p.take<double>(m);
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
   double2* X = (double2*)(h->ws + oX);
@@ -278,6 +279,7 @@ mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int6
   std::memset(&hm, 0, sizeof(hm));
   hm.X = X;
   hm.rowmap = (int32_t*)(h->ws + oR);
+  hm.nrm2 = (double*)(h->ws + oNr);
   hm.m = (int)m;
   hm.n = (int)n;
   hm.ld = (int)n;
@@ -411,6 +413,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   size_t oS2 = p.take<double>(max_items * m_cap);
   size_t oUnc = p.take<int32_t>(8);
   size_t oRow = p.take<int32_t>(max_items * m_cap);
+  size_t oNrm = p.take<double>(max_items * m_cap);
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
   char* ws = h->ws;
@@ -514,7 +517,8 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_eff, c128, stats));
       if (prof) prof_end(h, s, MPS_K_THETA);
       if (prof) prof_begin(h, s, MPS_K_PREP);
-      MPS_TRY_HIP(h, launch_jac_prep_bonds(s, it, mats, n, kJacBlock, (int32_t*)(ws + oRow), m_cap, h->status_dev));
+      MPS_TRY_HIP(h, launch_jac_prep_bonds(s, it, mats, n, kJacBlock, (int32_t*)(ws + oRow), (double*)(ws + oNrm), m_cap,
+                                           h->status_dev));
       if (prof) prof_end(h, s, MPS_K_PREP);
       mps_status r = run_jacobi(h, s, mats, n, nb_cap, m_cap, unconv, fixed);
       if (r != MPS_OK) return r;

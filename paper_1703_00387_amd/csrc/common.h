@@ -137,6 +137,7 @@ struct JacMat {
   int32_t conv, rot;     // converged flag, rotations applied in the running sweep
   int32_t kmax, pad;     // cap on the kept count (0 = use the launch constant)
   double fro2;           // |X|_F^2 at the start
+  double* nrm2;          // [m] squared row norms by physical row, rewritten by every round
 };
 
 // Output of the selection step (sorted singular values, count rule).
@@ -170,7 +171,7 @@ hipError_t launch_gates(hipStream_t s, const GateJob* jobs, int n, int dd);
 hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, bool c128,
                         unsigned long long* stats);
 hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
-                                 int32_t* rowmap_ws, int m_cap, uint32_t* status);
+                                 int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status);
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status);
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round,
                             double tol, double abs_tol, int inner_sweeps, unsigned long long* stats);

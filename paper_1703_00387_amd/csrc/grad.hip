@@ -253,7 +253,7 @@ struct GradArena {
 struct GradScratch {
   double2 *T0, *T1, *P0, *Xj, *Vh, *Vb, *Y1, *Z, *Y, *Pm, *Pb, *T1b, *T0b, *Bnew, *Bbl, *Bnl, *Bbs, *Bns, *Jv, *Xm;
   double2* dot;
-  double *sv, *sbar, *s2, *cn2, *obs;
+  double *sv, *sbar, *s2, *cn2, *obs, *nrm2;
   JacMat* mat;
   SelOut *sel, *seld;
   int32_t *rowmap, *perm, *unc;
@@ -267,7 +267,7 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
   for (int i = 16; i < 20; ++i) o[i] = p.take<double2>(site_el);
   size_t oDot = p.take<double2>(32);
   size_t oS = p.take<double>(r), oSb = p.take<double>(r), oS2 = p.take<double>(r), oCn = p.take<double>(r),
-         oObs = p.take<double>(2 * (size_t)L);
+         oObs = p.take<double>(2 * (size_t)L), oNr = p.take<double>(r);
   size_t oMat = p.take<JacMat>(1), oSel = p.take<SelOut>(1), oSeld = p.take<SelOut>(1);
   size_t oRm = p.take<int32_t>(2 * r), oPm = p.take<int32_t>(r), oUnc = p.take<int32_t>(8);
   mps_status st = mps_ensure_ws(h, p.off);
@@ -282,6 +282,7 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
   g.s2 = (double*)(ws + oS2);
   g.cn2 = (double*)(ws + oCn);
   g.obs = (double*)(ws + oObs);
+  g.nrm2 = (double*)(ws + oNr);
   g.mat = (JacMat*)(ws + oMat);
   g.sel = (SelOut*)(ws + oSel);
   g.seld = (SelOut*)(ws + oSeld);
@@ -490,6 +491,7 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
           std::memset(&hm, 0, sizeof(hm));
           hm.X = g.Xj;
           hm.rowmap = g.rowmap;
+          hm.nrm2 = g.nrm2;
           hm.m = m;
           hm.n = n;
           hm.ld = n;

@@ -4,8 +4,8 @@
 // G  : [N][N+1] complex128 in LDS, overwritten with Q^dag G Q (diagonal)
 // Q  : [N][N+1] complex128 in LDS, overwritten with the accumulated unitary
 //      (initialised here to the identity); G_in = Q diag(G_out) Q^dag.
-// Each step rotates N/2 disjoint index pairs chosen by the circle method, so
-// a sweep of N-1 steps visits every pair once.  The 2x2 rotation for the
+// Each step rotates up to N/2 disjoint index pairs of the odd-even ordering
+// below, so a sweep of N steps visits every pair once.  The 2x2 rotation for the
 // pair (p, q) with a = G_pp, b = G_qq, c = G_pq = |c| e^{i phi} is
 //   J = [[cs, sn], [-sn e^{-i phi}, cs e^{-i phi}]],
 //   t = sign(tau) / (|tau| + sqrt(1 + tau^2)),  tau = (b - a) / (2|c|),
@@ -17,21 +17,48 @@
 #define JS_N 32
 #define JS_LD 33
 
+// Odd-even transposition ordering with exchange: N slots hold the N indices;
+// step t rotates the index pairs in slots (2k, 2k+1) (t even) or (2k+1, 2k+2)
+// (t odd) and then swaps the two indices between their slots, so every index
+// moves one slot per step and all N(N-1)/2 pairs meet once in N steps.  The
+// pairs of every step are tabulated at compile time (p < q; 255 = no pair).
 template <int N>
-__device__ __forceinline__ void js_pair(int step, int k, int& p, int& q) {
-  // circle method over N players, N-1 rounds
-  if (k == 0) {
-    p = N - 1;
-    q = step;
-  } else {
-    p = (step + k) % (N - 1);
-    q = (step - k + N - 1) % (N - 1);
+struct OddEvenTable {
+  unsigned char p[N][N / 2];
+  unsigned char q[N][N / 2];
+};
+
+template <int N>
+constexpr OddEvenTable<N> make_odd_even() {
+  OddEvenTable<N> t{};
+  int idx[N] = {};
+  for (int i = 0; i < N; ++i) idx[i] = i;
+  for (int st = 0; st < N; ++st) {
+    for (int k = 0; k < N / 2; ++k) {
+      t.p[st][k] = 255;
+      t.q[st][k] = 255;
+    }
+    int k = 0;
+    for (int s0 = st % 2; s0 + 1 < N; s0 += 2, ++k) {
+      int a = idx[s0], b = idx[s0 + 1];
+      t.p[st][k] = (unsigned char)(a < b ? a : b);
+      t.q[st][k] = (unsigned char)(a < b ? b : a);
+      idx[s0] = b;
+      idx[s0 + 1] = a;
+    }
   }
-  if (p > q) {
-    int t = p;
-    p = q;
-    q = t;
-  }
+  return t;
+}
+
+__constant__ static const OddEvenTable<32> kOddEven32 = make_odd_even<32>();
+__constant__ static const OddEvenTable<64> kOddEven64 = make_odd_even<64>();
+
+template <int N>
+__device__ __forceinline__ bool js_pair(int step, int k, int& p, int& q) {
+  const OddEvenTable<N>& t = (N == 32) ? (const OddEvenTable<N>&)kOddEven32 : (const OddEvenTable<N>&)kOddEven64;
+  p = t.p[step][k];
+  q = t.q[step][k];
+  return p != 255;
 }
 
 // Returns the number of sweeps used (<= max_sweeps).  Exactly 256 threads call it.
@@ -49,45 +76,56 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();
-    for (int step = 0; step < N - 1; ++step) {
+    for (int step = 0; step < N; ++step) {
       if (tid < NP) {
         int p, q;
-        js_pair<N>(step, tid, p, q);
+        const bool valid = js_pair<N>(step, tid, p, q);
         double4 r = make_double4(1.0, 0.0, 1.0, 0.0);  // cs, sn, ph.re, ph.im ; identity
-        if (q < n) {
+        if (valid && q < n) {
           double a = G[p * LD + p].x, b = G[q * LD + q].x;
           double2 c = G[p * LD + q];
-          double ac = sqrt(c.x * c.x + c.y * c.y);
-          double thr = fmax(abs_thr, rel_thr * sqrt(fabs(a * b)));
-          if (ac > thr && ac > 0.0) {
-            double tau = (b - a) / (2.0 * ac);
+          double ac2 = c.x * c.x + c.y * c.y;
+          // |c| > max(abs_thr, rel_thr sqrt|ab|), compared in squares
+          double thr2 = fmax(abs_thr * abs_thr, rel_thr * rel_thr * fabs(a * b));
+          if (ac2 > thr2 && ac2 > 0.0) {
+            double iac = 1.0 / sqrt(ac2);
+            double tau = 0.5 * (b - a) * iac;
             double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             double cs = 1.0 / sqrt(1.0 + t * t);
-            r = make_double4(cs, t * cs, c.x / ac, c.y / ac);
+            r = make_double4(cs, t * cs, c.x * iac, c.y * iac);
             *flag = 1;
           }
         }
         rot[tid] = r;
       }
       __syncthreads();
-      // columns: G <- G J, Q <- Q J.  Every thread owns IT items; all their
-      // LDS loads are issued before any arithmetic so the latencies overlap.
+      // G <- J^dag G J on 2x2 pair blocks.  With pairs A = (pA, qA) and
+      // B = (pB, qB) of this step, block (A, B) becomes J_A^dag G_AB J_B
+      // (columns first, then rows).  Only blocks with A <= B are computed; the
+      // block (B, A) is written as the conjugate transpose, which keeps G
+      // exactly Hermitian.  Q <- Q J in the same pass (no dependency).
+      // Columns: G <- G J and Q <- Q J.  Item (k, row) updates entries
+      // (row, p_k), (row, q_k); the lanes of a wave take consecutive rows of
+      // one pair, so their LDS accesses fall in distinct banks.  All loads of
+      // a thread are issued before its arithmetic.
+      constexpr int IT = (N * NP + 255) / 256;
       {
-        constexpr int IT = (N * NP + 255) / 256;
         double4 rr[IT];
         int pp[IT], qq_[IT], row_[IT];
         double2 gp[IT], gq[IT], qp[IT], qv[IT];
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
-          int it = tid + 256 * u;
-          int row = it / NP, k = it % NP;
+          const int it = tid + 256 * u;
+          const int k = it / N, row = it % N;
           row_[u] = row;
-          js_pair<N>(step, k, pp[u], qq_[u]);
           rr[u] = rot[k];
-          gp[u] = G[row * LD + pp[u]];
-          gq[u] = G[row * LD + qq_[u]];
-          qp[u] = Q[row * LD + pp[u]];
-          qv[u] = Q[row * LD + qq_[u]];
+          if (!js_pair<N>(step, k, pp[u], qq_[u])) rr[u].y = 0.0;
+          if (rr[u].y != 0.0) {
+            gp[u] = G[row * LD + pp[u]];
+            gq[u] = G[row * LD + qq_[u]];
+            qp[u] = Q[row * LD + pp[u]];
+            qv[u] = Q[row * LD + qq_[u]];
+          }
         }
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
@@ -103,21 +141,23 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
         }
       }
       __syncthreads();
-      // rows: G <- J^dag G
+      // Rows: G <- J^dag G, item (k, col); the rotated pair's own entries are
+      // set exactly (zero coupling, real diagonal) so rounding does not build up.
       {
-        constexpr int IT = (N * NP + 255) / 256;
         double4 rr[IT];
         int pp[IT], qq_[IT], col_[IT];
         double2 gp[IT], gq[IT];
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
-          int it = tid + 256 * u;
-          int col = it / NP, k = it % NP;
+          const int it = tid + 256 * u;
+          const int k = it / N, col = it % N;
           col_[u] = col;
-          js_pair<N>(step, k, pp[u], qq_[u]);
           rr[u] = rot[k];
-          gp[u] = G[pp[u] * LD + col];
-          gq[u] = G[qq_[u] * LD + col];
+          if (!js_pair<N>(step, k, pp[u], qq_[u])) rr[u].y = 0.0;
+          if (rr[u].y != 0.0) {
+            gp[u] = G[pp[u] * LD + col];
+            gq[u] = G[qq_[u] * LD + col];
+          }
         }
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
@@ -126,21 +166,17 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
           const double2 ep = make_double2(r.z, r.w);  // e^{+i phi}
           const int col = col_[u];
           double2 gqe = cmul(gq[u], ep);
-          G[pp[u] * LD + col] = make_double2(r.x * gp[u].x - r.y * gqe.x, r.x * gp[u].y - r.y * gqe.y);
-          G[qq_[u] * LD + col] = make_double2(r.y * gp[u].x + r.x * gqe.x, r.y * gp[u].y + r.x * gqe.y);
-        }
-      }
-      __syncthreads();
-      // exact zeros on the rotated pairs keep rounding from accumulating
-      if (tid < NP) {
-        double4 r = rot[tid];
-        if (r.y != 0.0) {
-          int p, q;
-          js_pair<N>(step, tid, p, q);
-          G[p * LD + q] = make_double2(0.0, 0.0);
-          G[q * LD + p] = make_double2(0.0, 0.0);
-          G[p * LD + p].y = 0.0;
-          G[q * LD + q].y = 0.0;
+          double2 np_ = make_double2(r.x * gp[u].x - r.y * gqe.x, r.x * gp[u].y - r.y * gqe.y);
+          double2 nq_ = make_double2(r.y * gp[u].x + r.x * gqe.x, r.y * gp[u].y + r.x * gqe.y);
+          if (col == pp[u]) {
+            np_.y = 0.0;
+            nq_ = make_double2(0.0, 0.0);
+          } else if (col == qq_[u]) {
+            np_ = make_double2(0.0, 0.0);
+            nq_.y = 0.0;
+          }
+          G[pp[u] * LD + col] = np_;
+          G[qq_[u] * LD + col] = nq_;
         }
       }
       __syncthreads();

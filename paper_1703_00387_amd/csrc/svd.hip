@@ -62,17 +62,21 @@ __device__ double mat_fro2(const double2* X, int m, int n, int ld, double* red) 
 
 __global__ __launch_bounds__(256) void jac_prep_bonds_kernel(const BondItem* __restrict__ items,
                                                              JacMat* __restrict__ mats, int bs,
-                                                             int32_t* rowmap_ws, int m_cap, uint32_t* status) {
+                                                             int32_t* rowmap_ws, double* nrm_ws, int m_cap,
+                                                             uint32_t* status) {
   __shared__ double red[256];
   const BondItem it = items[blockIdx.x];
   const int d = it.d;
   const int m = it.chi[it.b] * d, n = d * it.chi[it.b + 2];
   double2* X = it.X;
   double f2 = mat_fro2(X, m, n, n, red);
+  int32_t* rowmap = rowmap_ws + (size_t)blockIdx.x * m_cap;
+  for (int g = threadIdx.x; g < m; g += blockDim.x) rowmap[g] = g;  // the first sweep keeps the natural order
   if (threadIdx.x == 0) {
     JacMat M;
     M.X = X;
-    M.rowmap = rowmap_ws + (size_t)blockIdx.x * m_cap;
+    M.rowmap = rowmap;
+    M.nrm2 = nrm_ws + (size_t)blockIdx.x * m_cap;
     M.m = m;
     M.n = n;
     M.ld = n;
@@ -94,6 +98,7 @@ __global__ __launch_bounds__(256) void jac_prep_plain_kernel(JacMat* __restrict_
   __shared__ double red[256];
   JacMat* M = mats + blockIdx.x;
   double f2 = mat_fro2(M->X, M->m, M->n, M->ld, red);
+  for (int g = threadIdx.x; g < M->m; g += blockDim.x) M->rowmap[g] = g;
   if (threadIdx.x == 0) {
     M->fro2 = f2;
     M->rot = 0;
@@ -191,9 +196,15 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   __syncthreads();
   // work counters: Gram 64x64 complex MACs per column, rotation the same
   if (tid == 0 && stats) atomicAdd(&stats[1], 32768ull * n * (need ? 2ull : 1ull));
-  if (!need) return;
+  if (!need) {
+    if (tid < JP && rows_s[tid] >= 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
+    return;
+  }
 
   herm_jacobi<JP>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
+  // the rotated rows have squared norms diag(Q^dag G Q), left on G's diagonal
+  if (tid < JP && rows_s[tid] >= 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
+  __syncthreads();
 
   // ---- rotate the rows: y_j = sum_p Q[p][j] x_p, 64 columns at a time -------
   // As[k][j] = Q[p0+k][j] comes from LDS; Bs[k][c] = X[row_{p0+k}][c0+c] is
@@ -276,24 +287,21 @@ __global__ void jac_sweep_end_kernel(JacMat* __restrict__ mats, int n_mats, int3
   if (threadIdx.x == 0) *unconverged = cnt;
 }
 
-// Order the rows by decreasing norm before a sweep, so that blocks hold rows
-// of similar magnitude (the Gram-based inner solve resolves small rows
-// accurately only in blocks without much larger ones; de Rijk's sorting idea
-// for one-sided Jacobi).  One workgroup per matrix.
+// Order the rows by decreasing norm before every sweep after the first, so that
+// blocks hold rows of similar magnitude (the Gram-based inner solve resolves
+// small rows accurately only in blocks without much larger ones; de Rijk's
+// sorting idea for one-sided Jacobi).  The norms are those the last round
+// wrote; the first sweep keeps the natural order, which the descending Schmidt
+// values of the left bond already make nearly sorted.  One workgroup per matrix.
 __global__ __launch_bounds__(256) void jac_sort_kernel(JacMat* __restrict__ mats, int m_cap) {
   extern __shared__ double dyn2[];
   double* s2 = dyn2;
   JacMat* M = mats + blockIdx.x;
   if (M->conv) return;
-  const int m = M->m, n = M->n, ld = M->ld, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int r = wave; r < m; r += 4) {
-    double a = 0.0;
-    for (int c = lane; c < n; c += 64) {
-      double2 v = M->X[(size_t)r * ld + c];
-      a += v.x * v.x + v.y * v.y;
-    }
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-    if (lane == 0) s2[r] = (a >= 0.0 && a <= 1.0e300) ? a : -1.0;
+  const int m = M->m, tid = threadIdx.x;
+  for (int r = tid; r < m; r += 256) {
+    double a = M->nrm2[r];
+    s2[r] = (a >= 0.0 && a <= 1.0e300) ? a : -1.0;
   }
   __syncthreads();
   for (int j = tid; j < m; j += 256) {
@@ -541,9 +549,9 @@ __global__ __launch_bounds__(256) void trunc_u_kernel(const double2* theta, cons
 
 // ---------------------------------------------------------------------------
 hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
-                                 int32_t* rowmap_ws, int m_cap, uint32_t* status) {
+                                 int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status) {
   if (n_items <= 0) return hipSuccess;
-  jac_prep_bonds_kernel<<<n_items, 256, 0, s>>>(items, mats, bs, rowmap_ws, m_cap, status);
+  jac_prep_bonds_kernel<<<n_items, 256, 0, s>>>(items, mats, bs, rowmap_ws, nrm_ws, m_cap, status);
   return hipGetLastError();
 }
 

@@ -252,6 +252,7 @@ struct TdvpWs {
   double2* Xj;
   JacMat* mat;
   int32_t* rowmap;
+  double* nrm2;
   int32_t* perm;
   double* s2;
   SelOut* sel;
@@ -275,7 +276,8 @@ mps_status tdvp_workspace(mps_handle h, bool c128, int chi_max, int d, int w, in
   size_t o_dots = p.take<double2>(32), o_al = p.take<double>(32), o_be = p.take<double>(32);
   size_t o_u = p.take<double2>(32), o_err = p.take<double>(4);
   size_t o_th = p.take<double2>(Nmax), o_thd = p.take<char>(Nmax * es), o_Xj = p.take<double2>(Nmax);
-  size_t o_mat = p.take<JacMat>(1), o_rm = p.take<int32_t>(m_cap), o_pm = p.take<int32_t>(m_cap);
+  size_t o_mat = p.take<JacMat>(1), o_rm = p.take<int32_t>(m_cap), o_pm = p.take<int32_t>(m_cap),
+         o_nr = p.take<double>(m_cap);
   size_t o_s2 = p.take<double>(m_cap), o_sel = p.take<SelOut>(1), o_unc = p.take<int32_t>(8);
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
@@ -300,6 +302,7 @@ mps_status tdvp_workspace(mps_handle h, bool c128, int chi_max, int d, int w, in
   t.Xj = (double2*)(ws + o_Xj);
   t.mat = (JacMat*)(ws + o_mat);
   t.rowmap = (int32_t*)(ws + o_rm);
+  t.nrm2 = (double*)(ws + o_nr);
   t.perm = (int32_t*)(ws + o_pm);
   t.s2 = (double*)(ws + o_s2);
   t.sel = (SelOut*)(ws + o_sel);
@@ -315,6 +318,7 @@ mps_status svd_select(mps_handle h, hipStream_t s, TdvpWs& t, int m, int n, int 
   std::memset(&hm, 0, sizeof(hm));
   hm.X = t.Xj;
   hm.rowmap = t.rowmap;
+  hm.nrm2 = t.nrm2;
   hm.m = m;
   hm.n = n;
   hm.ld = n;
