@@ -17,48 +17,33 @@
 #define JS_N 32
 #define JS_LD 33
 
-// Odd-even transposition ordering with exchange: N slots hold the N indices;
-// step t rotates the index pairs in slots (2k, 2k+1) (t even) or (2k+1, 2k+2)
-// (t odd) and then swaps the two indices between their slots, so every index
-// moves one slot per step and all N(N-1)/2 pairs meet once in N steps.  The
-// pairs of every step are tabulated at compile time (p < q; 255 = no pair).
-template <int N>
-struct OddEvenTable {
-  unsigned char p[N][N / 2];
-  unsigned char q[N][N / 2];
-};
-
-template <int N>
-constexpr OddEvenTable<N> make_odd_even() {
-  OddEvenTable<N> t{};
-  int idx[N] = {};
-  for (int i = 0; i < N; ++i) idx[i] = i;
-  for (int st = 0; st < N; ++st) {
-    for (int k = 0; k < N / 2; ++k) {
-      t.p[st][k] = 255;
-      t.q[st][k] = 255;
-    }
-    int k = 0;
-    for (int s0 = st % 2; s0 + 1 < N; s0 += 2, ++k) {
-      int a = idx[s0], b = idx[s0 + 1];
-      t.p[st][k] = (unsigned char)(a < b ? a : b);
-      t.q[st][k] = (unsigned char)(a < b ? b : a);
-      idx[s0] = b;
-      idx[s0 + 1] = a;
-    }
-  }
-  return t;
+// Odd-even transposition ordering with exchange: N slots (N even) hold the N
+// indices; step t rotates the index pairs in slots (2k, 2k+1) (t even) or
+// (2k+1, 2k+2) (t odd) and then swaps the two indices between their slots,
+// so all N(N-1)/2 pairs meet once in N steps.  Unfolding the line of slots
+// onto a circle of 2N points (slot x <-> points x and 2N-1-x), every index
+// advances one point per step: index e starts at point e (e even) or
+// 2N-1-e (e odd).  That gives the index in slot x at step t in closed form.
+__device__ __forceinline__ int oe_index(int N, int t, int x) {
+  const int y = ((x ^ t) & 1) ? 2 * N - 1 - x : x;   // the occupied point of slot x
+  int y0 = (y - t) % (2 * N);
+  if (y0 < 0) y0 += 2 * N;
+  return y0 < N ? y0 : 2 * N - 1 - y0;
 }
 
-__constant__ static const OddEvenTable<32> kOddEven32 = make_odd_even<32>();
-__constant__ static const OddEvenTable<64> kOddEven64 = make_odd_even<64>();
+// Pair k of step t (p < q); false when slot 2k+1+(t&1) is past the end.
+__device__ __forceinline__ bool oe_pair(int N, int t, int k, int& p, int& q) {
+  const int x = 2 * k + (t & 1);
+  if (x + 1 >= N) return false;
+  const int a = oe_index(N, t, x), b = oe_index(N, t, x + 1);
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+  return true;
+}
 
 template <int N>
 __device__ __forceinline__ bool js_pair(int step, int k, int& p, int& q) {
-  const OddEvenTable<N>& t = (N == 32) ? (const OddEvenTable<N>&)kOddEven32 : (const OddEvenTable<N>&)kOddEven64;
-  p = t.p[step][k];
-  q = t.q[step][k];
-  return p != 255;
+  return oe_pair(N, step, k, p, q);
 }
 
 // Returns the number of sweeps used (<= max_sweeps).  Exactly 256 threads call it.

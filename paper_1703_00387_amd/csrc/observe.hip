@@ -1,4 +1,4 @@
-// K9: observables of a Hastings-form chain with FP64 accumulation.
+// observables of a Hastings-form chain with FP64 accumulation.
 //
 // Local expectation values from the one-site reduced density matrix
 // rho_i = sum lam_i^2 B_i B_i^dag, two-site expectation values from

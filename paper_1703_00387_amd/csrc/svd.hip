@@ -1,4 +1,4 @@
-// K3: batched truncated SVD in FP64 by one-sided block Jacobi.
+// batched truncated SVD in FP64 by one-sided block Jacobi.
 //
 // The SVD split with truncation of Sec. "Basic concepts" (Splitting; Eqs.
 // overlap and elocal).  For theta' (m x n) the rows are orthogonalised by
@@ -27,6 +27,9 @@
 #define JB 32   // rows per block
 #define JP 64   // rows per block pair (panel)
 
+// Block pairs of round r by the circle method over nb blocks (nb even):
+// nb - 1 rounds pair every block with every other once.  Every round keeps
+// all nb/2 pairs busy, which sets the round time (one workgroup per pair).
 __device__ __forceinline__ void jac_pair(int nb, int r, int p, int& I, int& J) {
   if (p == 0) {
     I = nb - 1;

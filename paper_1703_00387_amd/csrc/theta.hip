@@ -1,4 +1,4 @@
-// K1: fused two-site tensor build, gate and left Schmidt scaling.
+// fused two-site tensor build, gate and left Schmidt scaling.
 //
 // For bond b of a Hastings-form chain (Sec. "Basic concepts": contraction of
 // two neighbouring tensors into Theta; App. "Details of the Krylov method":
