@@ -85,6 +85,30 @@ __device__ __forceinline__ void mma_chunk(const T* __restrict__ As, const T* __r
   }
 }
 
+// Same with the A operand read in place from a tile of pitch lda: A(k, m) = Al[k * lda + m].
+template <class T>
+__device__ __forceinline__ void mma_chunk_lda(const T* __restrict__ Al, int lda, const T* __restrict__ Bs,
+                                              AccTile<T>& acc, int wm, int wn, int lane) {
+#pragma unroll
+  for (int kk = 0; kk < TBK / 4; ++kk) {
+    const int kr = kk * 4 + (lane >> 4);
+    T a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = Al[kr * lda + wm + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = Bs[kr * TLD + wn + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc.re[i][j] = Cx<T>::mfma(a[i].x, b[j].x, acc.re[i][j]);
+        acc.re[i][j] = Cx<T>::mfma(-a[i].y, b[j].y, acc.re[i][j]);
+        acc.im[i][j] = Cx<T>::mfma(a[i].x, b[j].y, acc.im[i][j]);
+        acc.im[i][j] = Cx<T>::mfma(a[i].y, b[j].x, acc.im[i][j]);
+      }
+  }
+}
+
 // Write the accumulators into an LDS tile Cs[TBM][ldc].
 template <class T>
 __device__ __forceinline__ void acc_to_lds(const AccTile<T>& acc, T* Cs, int ldc, int wm, int wn, int lane) {

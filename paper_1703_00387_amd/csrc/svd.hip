@@ -26,6 +26,7 @@
 
 #define JB 32   // rows per block
 #define JP 64   // rows per block pair (panel)
+constexpr int kPf = 3;  // staged chunks in flight per thread in the Gram and rotation loops
 
 // Block pairs of round r by the circle method over nb blocks (nb even):
 // nb - 1 rounds pair every block with every other once.  Every round keeps
@@ -110,6 +111,71 @@ __global__ __launch_bounds__(256) void jac_prep_plain_kernel(JacMat* __restrict_
   }
 }
 
+// Hermitian 64x64 Gram on FP64 MFMA: the 10 upper 16x16 tiles (ti <= tj)
+// shared out 3, 3, 2, 2 over the four waves.
+struct HermAcc {
+  doublex4 re[3], im[3];
+};
+
+__device__ __forceinline__ void gram_tiles(int wave, int* ti, int* tj, int& nt) {
+  // wave 0: (0,0) (0,1) (0,2); wave 1: (0,3) (1,1) (1,2); wave 2: (1,3) (2,2); wave 3: (2,3) (3,3)
+  const int TI[4][3] = {{0, 0, 0}, {0, 1, 1}, {1, 2, 0}, {2, 3, 0}};
+  const int TJ[4][3] = {{0, 1, 2}, {3, 1, 2}, {3, 2, 0}, {3, 3, 0}};
+  nt = wave < 2 ? 3 : 2;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    ti[u] = TI[wave][u];
+    tj[u] = TJ[wave][u];
+  }
+}
+
+__device__ __forceinline__ void herm_acc_zero(HermAcc& a) {
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a.re[u][r] = 0.0;
+      a.im[u][r] = 0.0;
+    }
+}
+
+// One staged K-chunk Bs[TBK][TLD] of the 64 rows: G_ij += sum_k conj(x_ik) x_jk,
+// i.e. re += a.x b.x + a.y b.y and im += a.x b.y - a.y b.x.
+__device__ __forceinline__ void herm_mma_chunk(const double2* __restrict__ Bs, HermAcc& acc, const int* ti,
+                                               const int* tj, int nt, int lane) {
+#pragma unroll
+  for (int kk = 0; kk < TBK / 4; ++kk) {
+    const int kr = kk * 4 + (lane >> 4);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      if (u < nt) {
+        const double2 a = Bs[kr * TLD + ti[u] * 16 + (lane & 15)];
+        const double2 b = Bs[kr * TLD + tj[u] * 16 + (lane & 15)];
+        acc.re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc.re[u], 0, 0, 0);
+        acc.im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acc.im[u], 0, 0, 0);
+        acc.re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc.re[u], 0, 0, 0);
+        acc.im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, acc.im[u], 0, 0, 0);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void herm_acc_to_lds(const HermAcc& acc, double2* Gs, int ldg, const int* ti,
+                                                const int* tj, int nt, int lane) {
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    if (u >= nt) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ti[u] * 16 + Cx<double2>::acc_row(lane, r);
+      const int col = tj[u] * 16 + (lane & 15);
+      const double re = acc.re[u][r], im = acc.im[u][r];
+      Gs[row * ldg + col] = make_double2(re, im);
+      if (ti[u] != tj[u]) Gs[col * ldg + row] = make_double2(re, -im);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
                                                         double abs_tol, int inner_sweeps, unsigned long long* stats) {
   // Both arrays hold a [JP][JP+1] matrix (4160 elements) or four staging
@@ -139,46 +205,52 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   __syncthreads();
 
   // ---- Gram matrix of the 64 rows on FP64 MFMA: G[i][j] = <x_i, x_j> --------
-  // The next 16-column chunk is loaded into registers while the current one is
-  // multiplied (two LDS buffers).
+  // 16-column chunks are staged in LDS (two buffers); the next kPf chunks are
+  // already in flight in registers, so the loads of one panel overlap its
+  // multiplies.
   {
-    double2* As0 = Q;
-    double2* Bs0 = Q + TBK * TLD;
-    double2* As1 = Q + 2 * TBK * TLD;
-    double2* Bs1 = Q + 3 * TBK * TLD;
-    AccTile<double2> acc;
-    acc_zero<double2>(acc);
+    double2* Bs0 = Q;
+    double2* Bs1 = Q + TBK * TLD;
     const int i = tid >> 2, kq = (tid & 3) * 4;
     const int gi = rows_s[i];
     const double2* xr = X + (size_t)(gi >= 0 ? gi : 0) * ld;
-    double2 v[4];
-    auto load = [&](int c0) {
+    const int nch = (n + TBK - 1) / TBK;
+    double2 v[kPf][4];
+    auto load = [&](int ci, double2* dst) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        int c = c0 + kq + e;
-        v[e] = (gi >= 0 && c < n) ? xr[c] : make_double2(0.0, 0.0);
+        int c = ci * TBK + kq + e;
+        dst[e] = (gi >= 0 && c < n) ? xr[c] : make_double2(0.0, 0.0);
       }
     };
-    auto store = [&](double2* As, double2* Bs) {
+    auto store = [&](double2* Bs, const double2* src) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        As[(kq + e) * TLD + i] = make_double2(v[e].x, -v[e].y);
-        Bs[(kq + e) * TLD + i] = v[e];
-      }
+      for (int e = 0; e < 4; ++e) Bs[(kq + e) * TLD + i] = src[e];
     };
-    load(0);
-    store(As0, Bs0);
+#pragma unroll
+    for (int u = 0; u < kPf; ++u)
+      if (u < nch) load(u, v[u]);
+    store(Bs0, v[0]);
     __syncthreads();
-    int buf = 0;
-    for (int c0 = 0; c0 < n; c0 += TBK) {
-      const bool more = c0 + TBK < n;
-      if (more) load(c0 + TBK);
-      mma_chunk<double2>(buf ? As1 : As0, buf ? Bs1 : Bs0, acc, wm, wn, lane);
-      if (more) store(buf ? As0 : As1, buf ? Bs0 : Bs1);
-      __syncthreads();
-      buf ^= 1;
+    // G is Hermitian: only its 10 upper 16x16 tiles are formed (3, 3, 2 and 2
+    // per wave) and the lower ones are written as their conjugate transposes.
+    int ti[3], tj[3], nt;
+    gram_tiles(wave, ti, tj, nt);
+    HermAcc hacc;
+    herm_acc_zero(hacc);
+    for (int base = 0; base < nch; base += kPf) {
+#pragma unroll
+      for (int u = 0; u < kPf; ++u) {
+        const int ci = base + u;
+        if (ci < nch) {
+          if (ci + kPf < nch) load(ci + kPf, v[u]);  // chunk ci's registers were staged already
+          herm_mma_chunk((ci & 1) ? Bs1 : Bs0, hacc, ti, tj, nt, lane);
+          if (ci + 1 < nch) store((ci & 1) ? Bs0 : Bs1, v[(u + 1) % kPf]);
+          __syncthreads();
+        }
+      }
     }
-    acc_to_lds<double2>(acc, G, JP + 1, wm, wn, lane);
+    herm_acc_to_lds(hacc, G, JP + 1, ti, tj, nt, lane);
   }
   __syncthreads();
 
@@ -210,63 +282,65 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   __syncthreads();
 
   // ---- rotate the rows: y_j = sum_p Q[p][j] x_p, 64 columns at a time -------
-  // As[k][j] = Q[p0+k][j] comes from LDS; Bs[k][c] = X[row_{p0+k}][c0+c] is
-  // prefetched into registers one chunk ahead.
+  // The A operand Q[p0+k][j] is read in place from LDS; the B operand
+  // X[row_{p0+k}][c0+c] is staged (two LDS buffers) with kPf steps in flight.
   {
-    double2* As0 = G;
-    double2* Bs0 = G + TBK * TLD;
-    double2* As1 = G + 2 * TBK * TLD;
-    double2* Bs1 = G + 3 * TBK * TLD;
+    double2* Bs0 = G;
+    double2* Bs1 = G + TBK * TLD;
     const int k = tid >> 4, q4 = (tid & 15) * 4;
-    double2 v[4];
-    auto load = [&](int c0, int p0) {
-      int g = rows_s[p0 + k];
+    constexpr int PCH = JP / TBK;  // p-chunks per column block
+    const int nsteps = ((n + TBN - 1) / TBN) * PCH;
+    double2 v[kPf][4];
+    auto load = [&](int st, double2* dst) {
+      const int c0 = (st / PCH) * TBN, p0 = (st % PCH) * TBK;
+      const int g = rows_s[p0 + k];
       const double2* xr = X + (size_t)(g >= 0 ? g : 0) * ld;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         int c = c0 + q4 + e;
-        v[e] = (g >= 0 && c < n) ? xr[c] : make_double2(0.0, 0.0);
+        dst[e] = (g >= 0 && c < n) ? xr[c] : make_double2(0.0, 0.0);
       }
     };
-    auto store = [&](double2* As, double2* Bs, int p0) {
+    auto store = [&](double2* Bs, const double2* src) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        As[k * TLD + q4 + e] = Q[(p0 + k) * (JP + 1) + q4 + e];
-        Bs[k * TLD + q4 + e] = v[e];
-      }
+      for (int e = 0; e < 4; ++e) Bs[k * TLD + q4 + e] = src[e];
     };
-    const int nsteps = ((n + TBN - 1) / TBN) * (JP / TBK);  // (column block, p-chunk) pairs
-    load(0, 0);
-    store(As0, Bs0, 0);
+#pragma unroll
+    for (int u = 0; u < kPf; ++u)
+      if (u < nsteps) load(u, v[u]);
+    store(Bs0, v[0]);
     __syncthreads();
     AccTile<double2> acc;
     acc_zero<double2>(acc);
-    int buf = 0;
-    for (int st = 0; st < nsteps; ++st) {
-      const int c0 = (st / (JP / TBK)) * TBN, p0 = (st % (JP / TBK)) * TBK;
-      const bool more = st + 1 < nsteps;
-      const int c1 = ((st + 1) / (JP / TBK)) * TBN, p1 = ((st + 1) % (JP / TBK)) * TBK;
-      if (more) load(c1, p1);
-      mma_chunk<double2>(buf ? As1 : As0, buf ? Bs1 : Bs0, acc, wm, wn, lane);
-      if (p0 + TBK == JP) {
-        // the column block is complete: write its 64 rows (no later chunk reads
-        // these columns), then start the next block from zero
+    for (int base = 0; base < nsteps; base += kPf) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+      for (int u = 0; u < kPf; ++u) {
+        const int st = base + u;
+        if (st < nsteps) {
+          const int c0 = (st / PCH) * TBN, p0 = (st % PCH) * TBK;
+          if (st + kPf < nsteps) load(st + kPf, v[u]);
+          mma_chunk_lda<double2>(Q + p0 * (JP + 1), JP + 1, (st & 1) ? Bs1 : Bs0, acc, wm, wn, lane);
+          if (p0 + TBK == JP) {
+            // the column block is complete: write its 64 rows (every load of
+            // these columns was issued earlier), then start the next block
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              int row = wm + i * 16 + Cx<double2>::acc_row(lane, r);
-              int col = c0 + wn + j * 16 + (lane & 15);
-              int g = rows_s[row];
-              if (g >= 0 && col < n) X[(size_t)g * ld + col] = make_double2(acc.re[i][j][r], acc.im[i][j][r]);
-            }
-        acc_zero<double2>(acc);
+              for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  int row = wm + i * 16 + Cx<double2>::acc_row(lane, r);
+                  int col = c0 + wn + j * 16 + (lane & 15);
+                  int g = rows_s[row];
+                  if (g >= 0 && col < n)
+                    X[(size_t)g * ld + col] = make_double2(acc.re[i][j][r], acc.im[i][j][r]);
+                }
+            acc_zero<double2>(acc);
+          }
+          if (st + 1 < nsteps) store((st & 1) ? Bs0 : Bs1, v[(u + 1) % kPf]);
+          __syncthreads();
+        }
       }
-      if (more) store(buf ? As0 : As1, buf ? Bs0 : Bs1, p1);
-      __syncthreads();
-      buf ^= 1;
     }
   }
   if (tid == 0) atomicAdd(&M->rot, 1);
