@@ -18,10 +18,9 @@
 template <class T>
 __global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restrict__ items, int d, int TA,
                                                          int TC, int ntc_cap, unsigned long long* stats) {
-  __shared__ T smem[TBM * (TBN + 1) > 2 * TBK * TLD ? TBM * (TBN + 1) : 2 * TBK * TLD];
-  __shared__ T Gs[32 * 32];
-  T* As = smem;
-  T* Bs = smem + TBK * TLD;
+  // two staging buffers (A and B tiles each), reused for the output tile
+  __shared__ T smem[TBM * (TBN + 1) > 4 * TBK * TLD ? TBM * (TBN + 1) : 4 * TBK * TLD];
+  __shared__ T Gs[25 * 25];  // the gate, d <= 5 (the chain limit)
   T* Cs = smem;  // reused after the K loop
   typedef typename Cx<T>::R R;
 
@@ -42,33 +41,57 @@ __global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restr
   const int K = chm;
   const T* Abase = (const T*)it.Bl + (size_t)a0 * d * chi_max;
   const T* Br = (const T*)it.Br;
-  for (int k0 = 0; k0 < K; k0 += TBK) {
-    // A tile: rows i (a = a0 + i/d, s = i%d), k = k0..k0+15; As[k][i]
-    {
-      int i = tid >> 2, kq = (tid & 3) * 4;
+  // A tile: rows i (a = a0 + i/d, s = i%d), k = k0..k0+15, staged as As[k][i];
+  // B tile: k, columns j (t = j/TC, c = c0 + j%TC), staged as Bs[k][j].
+  // kPf chunks are in flight in registers ahead of the one being multiplied.
+  constexpr int kPf = 3;
+  const int ia = tid >> 2, kqa = (tid & 3) * 4;
+  const int kb = tid >> 4, jqb = (tid & 15) * 4;
+  T va[kPf][4], vb[kPf][4];
+  auto load = [&](int ci, T* da, T* db) {
+    const int k0 = ci * TBK;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int k = k0 + kq + e;
-        T v = Cx<T>::make(0.0, 0.0);
-        if (i < rows_valid && k < K) v = Abase[(size_t)i * chi_max + k];
-        As[(kq + e) * TLD + i] = v;
+    for (int e = 0; e < 4; ++e) {
+      int k = k0 + kqa + e;
+      T v = Cx<T>::make(0.0, 0.0);
+      if (ia < rows_valid && k < K) v = Abase[(size_t)ia * chi_max + k];
+      da[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int j = jqb + e;
+      int t = j / TC, c = c0 + j % TC;
+      T v = Cx<T>::make(0.0, 0.0);
+      if (t < d && c < chr && k0 + kb < K) v = Br[((size_t)(k0 + kb) * d + t) * chi_max + c];
+      db[e] = v;
+    }
+  };
+  auto store = [&](int buf, const T* da, const T* db) {
+    T* As = smem + buf * 2 * TBK * TLD;
+    T* Bs = As + TBK * TLD;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) As[(kqa + e) * TLD + ia] = da[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Bs[kb * TLD + jqb + e] = db[e];
+  };
+  const int nch = (K + TBK - 1) / TBK;
+#pragma unroll
+  for (int u = 0; u < kPf; ++u)
+    if (u < nch) load(u, va[u], vb[u]);
+  store(0, va[0], vb[0]);
+  __syncthreads();
+  for (int base = 0; base < nch; base += kPf) {
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+      const int ci = base + u;
+      if (ci < nch) {
+        if (ci + kPf < nch) load(ci + kPf, va[u], vb[u]);  // chunk ci's registers were staged already
+        const T* As = smem + (ci & 1) * 2 * TBK * TLD;
+        mma_chunk<T>(As, As + TBK * TLD, acc, wm, wn, lane);
+        if (ci + 1 < nch) store((ci + 1) & 1, va[(u + 1) % kPf], vb[(u + 1) % kPf]);
+        __syncthreads();
       }
     }
-    // B tile: k, columns j (t = j/TC, c = c0 + j%TC); Bs[k][j]
-    {
-      int k = tid >> 4, jq = (tid & 15) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int j = jq + e;
-        int t = j / TC, c = c0 + j % TC;
-        T v = Cx<T>::make(0.0, 0.0);
-        if (t < d && c < chr && k0 + k < K) v = Br[((size_t)(k0 + k) * d + t) * chi_max + c];
-        Bs[k * TLD + j] = v;
-      }
-    }
-    __syncthreads();
-    mma_chunk<T>(As, Bs, acc, wm, wn, lane);
-    __syncthreads();
   }
   acc_to_lds<T>(acc, Cs, TBN + 1, wm, wn, lane);
   __syncthreads();
