@@ -269,8 +269,9 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
     }
   }
   __syncthreads();
-  // work counters: Gram 64x64 complex MACs per column, rotation the same
-  if (tid == 0 && stats) atomicAdd(&stats[1], 32768ull * n * (need ? 2ull : 1ull));
+  // work counter (real flops): the Hermitian Gram needs 64*65/2 complex MACs
+  // per column (16640 n), the rotation 64*64 (32768 n)
+  if (tid == 0 && stats) atomicAdd(&stats[1], (16640ull + (need ? 32768ull : 0ull)) * (unsigned long long)n);
   if (!need) {
     if (tid < JP && rows_s[tid] >= 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
     return;
