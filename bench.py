@@ -50,10 +50,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=140)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before the timed ones (default 140; 40 for xxz_batch256)")
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="xxz_batch256: skip the one-bond-per-launch comparison")
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
     ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256", "bh_heff_chi512", "xxz_grad_L32"])
@@ -70,6 +72,8 @@ def main():
 
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
+    if args.warmup is None:
+        args.warmup = 40 if args.workload == "xxz_batch256" else 140
 
     import workloads as W
     from paper_1703_00387_amd import api, models
@@ -364,8 +368,9 @@ def bench_batch(args):
         t_graph = timed(_lib.MPS_FLAG_GRAPH, args.steps)
         print(f"[bench] batched graph: {t_graph:.2f}s for {args.steps} steps", file=sys.stderr, flush=True)
         plain_steps = 1
-        t_plain = timed(_lib.MPS_FLAG_PLAIN, plain_steps)
-        print(f"[bench] plain: {t_plain:.2f}s for {plain_steps} step", file=sys.stderr, flush=True)
+        t_plain = None if args.no_plain else timed(_lib.MPS_FLAG_PLAIN, plain_steps)
+        if t_plain is not None:
+            print(f"[bench] plain: {t_plain:.2f}s for {plain_steps} step", file=sys.stderr, flush=True)
         same_chi = True
     code, word = h.device_status()
     t_best = min(t_eager, t_graph)
@@ -379,8 +384,9 @@ def bench_batch(args):
                       "updates_per_step": upd, "chi_max_now": max(int(c.chi.max()) for c in chains)},
            "batched_eager": {"ms_per_step": round(t_eager * 1e3 / args.steps, 3)},
            "batched_graph": {"ms_per_step": round(t_graph * 1e3 / args.steps, 3)},
-           "plain": {"value": round(upd * plain_steps / t_plain, 2), "ms_per_step": round(t_plain * 1e3 / plain_steps, 3)},
-           "speedup_vs_plain": round((t_plain / plain_steps) / (t_best / args.steps), 2),
+           "plain": None if t_plain is None else
+           {"value": round(upd * plain_steps / t_plain, 2), "ms_per_step": round(t_plain * 1e3 / plain_steps, 3)},
+           "speedup_vs_plain": None if t_plain is None else round((t_plain / plain_steps) / (t_best / args.steps), 2),
            "device_status": [code, word]}
     print(json.dumps(out))
     h.close()

@@ -11,6 +11,7 @@ namespace {
 
 constexpr int kJacBlock = 32;   // rows per Jacobi block
 constexpr int kFixedSweeps = 20;  // sweeps queued when the host may not synchronise
+constexpr int kLoopInner = 4;     // inner sweeps per outer sweep for single-panel matrices
 
 }  // namespace
 
@@ -46,11 +47,22 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     nb = std::min(nb_cap, std::max(2, (int)h->host_pinned[1]));
   }
   const int max_sweeps = fixed ? std::min(kFixedSweeps, h->jac_max_sweeps) : h->jac_max_sweeps;
+  if (nb == 2) {
+    // every matrix is one 64-row panel: all its sweeps run in one launch (with
+    // a few inner sweeps per outer sweep).  With larger matrices in the batch
+    // the small ones stay in the rounds, where they run beside the others.
+    PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
+                launch_jac_round(s, mats, n, 2, 0, h->jac_tol, h->jac_abs, std::max(h->jac_inner_sweeps, kLoopInner),
+                                 max_sweeps, h->profile ? h->stats_dev : nullptr));
+    MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
+    MPS_TRY_HIP(h, launch_jac_flag_noconv(s, unconv, h->status_dev));
+    return MPS_OK;
+  }
   bool done = false;
   for (int sw = 0; sw < max_sweeps && !done; ++sw) {
     if (sw > 0) MPS_TRY_HIP(h, launch_jac_sort(s, mats, n, m_cap));
     for (int r = 0; r < nb - 1; ++r)
-      PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs, h->jac_inner_sweeps,
+      PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs, h->jac_inner_sweeps, 0,
                                                               h->profile ? h->stats_dev : nullptr));
     MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
     if (!fixed && sw >= 1) {

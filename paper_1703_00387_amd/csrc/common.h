@@ -174,7 +174,7 @@ hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* m
                                  int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status);
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status);
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round,
-                            double tol, double abs_tol, int inner_sweeps, unsigned long long* stats);
+                            double tol, double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats);
 hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged);
 hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap);
 hipError_t launch_jac_flag_noconv(hipStream_t s, const int32_t* unconverged, uint32_t* status);

@@ -176,8 +176,13 @@ __device__ __forceinline__ void herm_acc_to_lds(const HermAcc& acc, double2* Gs,
   }
 }
 
+// One round of the block Jacobi (loop_sweeps == 0), or, for matrices of one
+// 64-row panel (nb == 2), up to loop_sweeps complete sweeps in one launch
+// (loop_sweeps > 0): the panel's only pair is re-formed, solved and rotated
+// until it is orthogonal, with no launch or host round trip per sweep.
 __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
-                                                        double abs_tol, int inner_sweeps, unsigned long long* stats) {
+                                                        double abs_tol, int inner_sweeps, int loop_sweeps,
+                                                        unsigned long long* stats) {
   // Both arrays hold a [JP][JP+1] matrix (4160 elements) or four staging
   // buffers of [TBK][TLD] (4352 elements); sized for the larger.
   constexpr int kLdsElems = (JP * (JP + 1) > 4 * TBK * TLD) ? JP * (JP + 1) : 4 * TBK * TLD;
@@ -191,6 +196,7 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   if (M->conv) return;
   const int nb = M->nb, p = blockIdx.x;
   if (2 * p >= nb || round >= nb - 1) return;
+  if (loop_sweeps > 0 && nb != 2) return;  // larger matrices take the round-based sweeps
   const int m = M->m, n = M->n, ld = M->ld;
   double2* X = M->X;
   int I, J;
@@ -201,6 +207,9 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
     int g = (tid < JB) ? I * JB + tid : J * JB + (tid - JB);
     rows_s[tid] = g < m ? M->rowmap[g] : -1;
   }
+  const int iters = loop_sweeps > 0 ? loop_sweeps : 1;
+  bool rotated = false;
+  for (int it = 0; it < iters; ++it) {
   if (tid == 0) need = 0;
   __syncthreads();
 
@@ -274,8 +283,10 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   if (tid == 0 && stats) atomicAdd(&stats[1], (16640ull + (need ? 32768ull : 0ull)) * (unsigned long long)n);
   if (!need) {
     if (tid < JP && rows_s[tid] >= 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
-    return;
+    rotated = false;
+    break;
   }
+  rotated = true;
 
   herm_jacobi<JP>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
   // the rotated rows have squared norms diag(Q^dag G Q), left on G's diagonal
@@ -344,7 +355,20 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
       }
     }
   }
-  if (tid == 0) atomicAdd(&M->rot, 1);
+  if (loop_sweeps == 0 && tid == 0) atomicAdd(&M->rot, 1);
+  __syncthreads();
+  }
+  // loop mode: a converged matrix is done; one whose pair still rotated in
+  // the last sweep is left to the round-based sweeps (and counted as not
+  // converged by the next sweep end)
+  if (loop_sweeps > 0 && tid == 0) {
+    if (rotated) {
+      M->rot = 1;
+    } else {
+      M->rot = 0;
+      M->conv = 1;
+    }
+  }
 }
 
 __global__ void jac_sweep_end_kernel(JacMat* __restrict__ mats, int n_mats, int32_t* unconverged) {
@@ -640,10 +664,10 @@ hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32
 }
 
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round, double tol,
-                            double abs_tol, int inner_sweeps, unsigned long long* stats) {
+                            double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats) {
   if (n_mats <= 0) return hipSuccess;
   dim3 grid(nb_cap / 2, n_mats);
-  jac_round_kernel<<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, stats);
+  jac_round_kernel<<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats);
   return hipGetLastError();
 }
 
