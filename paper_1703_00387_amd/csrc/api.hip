@@ -47,16 +47,20 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     nb = std::min(nb_cap, std::max(2, (int)h->host_pinned[1]));
   }
   const int max_sweeps = fixed ? std::min(kFixedSweeps, h->jac_max_sweeps) : h->jac_max_sweeps;
-  if (nb == 2) {
-    // every matrix is one 64-row panel: all its sweeps run in one launch (with
-    // a few inner sweeps per outer sweep).  With larger matrices in the batch
-    // the small ones stay in the rounds, where they run beside the others.
+  if (nb == 2 || fixed) {
+    // Matrices of one 64-row panel run all their sweeps in one launch (with a
+    // few inner sweeps per outer sweep); one that converges there is done.
+    // Eager mode does this only when every matrix is that small: otherwise the
+    // small ones stay in the rounds, where they run beside the others.  A
+    // queued schedule cannot see the sizes, so it always starts with it.
     PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
                 launch_jac_round(s, mats, n, 2, 0, h->jac_tol, h->jac_abs, std::max(h->jac_inner_sweeps, kLoopInner),
                                  max_sweeps, h->profile ? h->stats_dev : nullptr));
-    MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
-    MPS_TRY_HIP(h, launch_jac_flag_noconv(s, unconv, h->status_dev));
-    return MPS_OK;
+    if (nb == 2) {
+      MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
+      MPS_TRY_HIP(h, launch_jac_flag_noconv(s, unconv, h->status_dev));
+      return MPS_OK;
+    }
   }
   bool done = false;
   for (int sw = 0; sw < max_sweeps && !done; ++sw) {
