@@ -25,8 +25,9 @@
 
 template <class T>
 __global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
-  __shared__ T As[TBK * TLD];
-  __shared__ T Bs[TBK * TLD];
+  // two staging buffers, each an A and a B chunk; kPf chunks in flight in registers
+  __shared__ T stage[4 * TBK * TLD];
+  constexpr int kPf = 3;
   const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
   const int m0 = tm * TBM, n0 = tn * TBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -36,36 +37,58 @@ __global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
   T* C = (T*)P.C;
   AccTile<T> acc;
   acc_zero<T>(acc);
-  for (int k0 = 0; k0 < P.K; k0 += TBK) {
-    {
-      int i = tid >> 2, kq = (tid & 3) * 4;
+  const int ia = tid >> 2, kqa = (tid & 3) * 4;
+  const int kb = tid >> 4, jqb = (tid & 15) * 4;
+  T va[kPf][4], vb[kPf][4];
+  auto load = [&](int ci, T* da, T* db) {
+    const int k0 = ci * TBK;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int k = k0 + kq + e;
-        T v = Cx<T>::make(0.0, 0.0);
-        if (m0 + i < P.M && k < P.K) {
-          v = A[(long long)(m0 + i) * P.rsA + (long long)k * P.csA];
-          if (P.conjA) v.y = -v.y;
-        }
-        As[(kq + e) * TLD + i] = v;
+    for (int e = 0; e < 4; ++e) {
+      int k = k0 + kqa + e;
+      T v = Cx<T>::make(0.0, 0.0);
+      if (m0 + ia < P.M && k < P.K) {
+        v = A[(long long)(m0 + ia) * P.rsA + (long long)k * P.csA];
+        if (P.conjA) v.y = -v.y;
+      }
+      da[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int j = jqb + e;
+      T v = Cx<T>::make(0.0, 0.0);
+      if (n0 + j < P.N && k0 + kb < P.K) {
+        v = B[(long long)(k0 + kb) * P.rsB + (long long)(n0 + j) * P.csB];
+        if (P.conjB) v.y = -v.y;
+      }
+      db[e] = v;
+    }
+  };
+  auto store = [&](int buf, const T* da, const T* db) {
+    T* As = stage + buf * 2 * TBK * TLD;
+    T* Bs = As + TBK * TLD;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) As[(kqa + e) * TLD + ia] = da[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Bs[kb * TLD + jqb + e] = db[e];
+  };
+  const int nch = (P.K + TBK - 1) / TBK;
+#pragma unroll
+  for (int u = 0; u < kPf; ++u)
+    if (u < nch) load(u, va[u], vb[u]);
+  if (nch > 0) store(0, va[0], vb[0]);
+  __syncthreads();
+  for (int base = 0; base < nch; base += kPf) {
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+      const int ci = base + u;
+      if (ci < nch) {
+        if (ci + kPf < nch) load(ci + kPf, va[u], vb[u]);  // chunk ci's registers were staged already
+        const T* As = stage + (ci & 1) * 2 * TBK * TLD;
+        mma_chunk<T>(As, As + TBK * TLD, acc, wm, wn, lane);
+        if (ci + 1 < nch) store((ci + 1) & 1, va[(u + 1) % kPf], vb[(u + 1) % kPf]);
+        __syncthreads();
       }
     }
-    {
-      int k = tid >> 4, jq = (tid & 15) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int j = jq + e;
-        T v = Cx<T>::make(0.0, 0.0);
-        if (n0 + j < P.N && k0 + k < P.K) {
-          v = B[(long long)(k0 + k) * P.rsB + (long long)(n0 + j) * P.csB];
-          if (P.conjB) v.y = -v.y;
-        }
-        Bs[k * TLD + j] = v;
-      }
-    }
-    __syncthreads();
-    mma_chunk<T>(As, Bs, acc, wm, wn, lane);
-    __syncthreads();
   }
   typedef typename Cx<T>::R R;
   const R alpha = (R)P.alpha;
@@ -128,23 +151,34 @@ __global__ __launch_bounds__(256) void mix_kernel(MixDesc D, const T* __restrict
     long long rest = idx / D.R;
     int o2 = (int)(rest % D.P2), o1 = (int)(rest / D.P2);
     const T* ip = in + o1 * D.is_o1 + o2 * D.is_o2 + r * D.is_r;
+    // the (up to 32) inputs of this position, fully unrolled so they stay in registers
     T x[32];
-    for (int q1 = 0; q1 < D.Q1; ++q1)
-      for (int q2 = 0; q2 < D.Q2; ++q2) x[q1 * D.Q2 + q2] = ip[q1 * D.is_q1 + q2 * D.is_q2];
-    T* op = out + o1 * D.os_o1 + o2 * D.os_o2 + r * D.os_r;
-    for (int p1 = 0; p1 < D.O1; ++p1)
-      for (int p2 = 0; p2 < D.O2; ++p2) {
-        const T* w = Ws + (p1 * D.O2 + p2) * Qi;
-        R ar = 0, ai = 0;
-        for (int q = 0; q < Qi; ++q) {
-          ar += w[q].x * x[q].x - w[q].y * x[q].y;
-          ai += w[q].x * x[q].y + w[q].y * x[q].x;
-        }
-        T v;
-        v.x = ar;
-        v.y = ai;
-        op[p1 * D.os_q1 + p2 * D.os_q2] = v;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      x[q] = Cx<T>::make(0.0, 0.0);
+      if (q < Qi) {
+        const int q1 = q / D.Q2, q2 = q - q1 * D.Q2;
+        x[q] = ip[q1 * D.is_q1 + q2 * D.is_q2];
       }
+    }
+    T* op = out + o1 * D.os_o1 + o2 * D.os_o2 + r * D.os_r;
+    for (int p = 0; p < Qo; ++p) {
+      const int p1 = p / D.O2, p2 = p - p1 * D.O2;
+      const T* w = Ws + p * Qi;
+      R ar = 0, ai = 0;
+#pragma unroll
+      for (int q = 0; q < 32; ++q) {
+        if (q < Qi) {
+          const T wq = w[q];
+          ar += wq.x * x[q].x - wq.y * x[q].y;
+          ai += wq.x * x[q].y + wq.y * x[q].x;
+        }
+      }
+      T v;
+      v.x = ar;
+      v.y = ai;
+      op[p1 * D.os_q1 + p2 * D.os_q2] = v;
+    }
   }
 }
 
