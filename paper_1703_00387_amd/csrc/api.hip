@@ -36,6 +36,20 @@ mps_status upload(mps_handle h, hipStream_t s, void* dst, const std::vector<T>& 
 }  // namespace
 
 // Run the Jacobi sweeps on mats[0..n) (already prepared on the device).
+mps_status mps_aux_streams(mps_handle h, int n) {
+  while ((int)h->aux.size() < n) {
+    hipStream_t st;
+    MPS_TRY_HIP(h, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    h->aux.push_back(st);
+  }
+  while ((int)h->aux_ev.size() < n + 1) {
+    hipEvent_t e;
+    MPS_TRY_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->aux_ev.push_back(e);
+  }
+  return MPS_OK;
+}
+
 mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
                       bool fixed) {
   int nb = nb_cap;
@@ -164,6 +178,8 @@ mps_status mps_destroy(mps_handle h) {
   hipSetDevice(h->device);
   hipDeviceSynchronize();
   for (auto e : h->ev_pool) hipEventDestroy(e);
+  for (auto e : h->aux_ev) hipEventDestroy(e);
+  for (auto st : h->aux) hipStreamDestroy(st);
   if (h->ws) hipFree(h->ws);
   if (h->status_dev) hipFree(h->status_dev);
   if (h->host_pinned) hipHostFree(h->host_pinned);

@@ -44,7 +44,13 @@ struct mps_context {
   double k_ms[MPS_NKERNELS] = {0};
   long long k_launches[MPS_NKERNELS] = {0};
   unsigned long long* stats_dev = nullptr;  // device work counters [MPS_NSTATS]
+  // extra streams (default priority) for independent per-bond work, and events to fork/join them
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> aux_ev;
 };
+
+// Make `n` auxiliary streams available on the handle (created once, kept).
+mps_status mps_aux_streams(mps_handle h, int n);
 
 // Jacobi helpers shared by the drivers (api.hip)
 struct JacMat;
@@ -207,6 +213,7 @@ struct SGemm {
   long long rsA, csA, rsB, csB, rsC, csC;
   int conjA, conjB;
   double alpha;
+  const double* alpha_dev = nullptr;  // when set, alpha is read from the device
 };
 struct MixDesc {
   int P1, P2, R, Q1, Q2, O1, O2;

@@ -101,7 +101,7 @@ __global__ void svd_x_kernel(const double2* __restrict__ Jv, const double* __res
       if (i < k) v = make_double2(sbar[i] / s[i], -0.5 * Jv[e].y / (s[i] * s[i] + eta));
     } else {
       double D = s[j] * s[j] - s[i] * s[i];
-      double F = D / (D * D + eta);
+      double F = D != 0.0 ? D / (D * D + eta) : 0.0;
       double2 a = Jv[i * r + j], b = Jv[j * r + i];
       v = make_double2(F * (a.x - b.x), F * (a.y + b.y));
     }
@@ -123,6 +123,83 @@ __global__ void svd_y_kernel(const double2* __restrict__ Y1, const double2* __re
       y = make_double2(y.x + w * (vb.x - Z[e].x), y.y + w * (-vb.y - Z[e].y));
     }
     Y[e] = y;
+  }
+}
+
+// Number of resolved discarded directions: rows of the sorted residual norms
+// s2 (descending) with s2 > thr * (kept weight + residual weight), at most cap;
+// written as the row count of a selection (for write_rows) and to rd_out.
+__global__ void grad_rd_kernel(const double* __restrict__ s2, const double* __restrict__ kept2, int m, int k,
+                               int cap, double thr, SelOut* sel, int* rd_out) {
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) a += fmax(s2[j], 0.0);
+  for (int j = threadIdx.x; j < k; j += blockDim.x) a += fmax(kept2[j], 0.0);
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double tot = red[0];
+    int rd = 0;
+    while (rd < cap && s2[rd] > thr * tot) ++rd;
+    SelOut o;
+    o.k = rd;
+    o.m = m;
+    o.disc = 0.0;
+    o.norm2 = tot;
+    o.nk = 1.0;
+    *sel = o;
+    *rd_out = rd;
+  }
+}
+
+// Per-update scalars of the reverse pass, from the column norms c2 of
+// theta' V (kept j < k, then the resolved discarded ones, zeros after):
+//   s_j = |c_j|,  n_k = (sum_{j<k} s_j^2)^(1/2),
+//   n_bar = -(Re<B_bar_b', B_b'> + sum_j lam_bar'_j s_j / n_k) / n_k,
+//   s_bar_j = lam_bar'_j / n_k + n_bar s_j / n_k  (j < k, else 0).
+// scal = {n_k, 1/n_k}; a vanishing n_k sets the non-finite status bit.
+__global__ void grad_scalars_kernel(const double* __restrict__ c2, const double* __restrict__ lbm,
+                                    const double2* __restrict__ dot, int k, int r, double* sv, double* sbar,
+                                    double* scal, uint32_t* status) {
+  __shared__ double red[2][256];
+  __shared__ double nk_s;
+  double a = 0.0, b = 0.0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double sj = sqrt(fmax(c2[j], 0.0));
+    a += sj * sj;
+    b += lbm[j] * sj;
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double nk = sqrt(red[0][0]);
+    if (!(nk > 0.0) || !(nk < 1e300)) {
+      atomicOr(status, MPS_DEV_NONFINITE);
+      nk = 1.0;
+    }
+    nk_s = nk;
+    scal[0] = nk;
+    scal[1] = 1.0 / nk;
+    scal[2] = -(dot[0].x + red[1][0] / nk) / nk;  // n_bar
+  }
+  __syncthreads();
+  const double nk = nk_s, nbar = scal[2];
+  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+    double sj = sqrt(fmax(c2[j], 0.0));
+    sv[j] = sj;
+    sbar[j] = j < k ? lbm[j] / nk + nbar * sj / nk : 0.0;
   }
 }
 
@@ -204,13 +281,14 @@ struct Ctx {
   } while (0)
 
 mps_status gemm128(Ctx& c, const void* A, long long rsA, long long csA, int conjA, const void* B, long long rsB,
-                   long long csB, int conjB, void* C, long long rsC, int M, int N, int K, double alpha) {
+                   long long csB, int conjB, void* C, long long rsC, int M, int N, int K, double alpha,
+                   const double* alpha_dev = nullptr) {
   SGemm g;
   std::memset(&g, 0, sizeof(g));
   g.A = A; g.rsA = rsA; g.csA = csA; g.conjA = conjA;
   g.B = B; g.rsB = rsB; g.csB = csB; g.conjB = conjB;
   g.C = C; g.rsC = rsC; g.csC = 1;
-  g.M = M; g.N = N; g.K = K; g.alpha = alpha;
+  g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.alpha_dev = alpha_dev;
   if (K <= 0) {
     K1((fill_zero_kernel<<<g1d((long long)M * N), 256, 0, c.s>>>((double2*)C, (long long)M * N)));
     return MPS_OK;
@@ -248,47 +326,74 @@ struct GradArena {
   }
 };
 
-// per-update scratch in the handle workspace (re-carved after every TEBD call,
-// which may regrow the workspace)
-struct GradScratch {
+// Per-update scratch in the handle workspace, one slice per bond of a layer
+// (the bonds of a layer are updated concurrently on auxiliary streams).  The
+// workspace is carved again after every TEBD call, which may regrow it.
+struct GradItemBuf {
   double2 *T0, *T1, *P0, *Xj, *Vh, *Vb, *Y1, *Z, *Y, *Pm, *Pb, *T1b, *T0b, *Bnew, *Bbl, *Bnl, *Bbs, *Bns, *Jv, *Xm;
-  double2* dot;
-  double *sv, *sbar, *s2, *cn2, *obs, *nrm2;
-  JacMat* mat;
+  double2* dot;  // [2]: <B_bar_b', B_b'> and the coupling overlap
+  double *sv, *sbar, *c2, *kept2, *scal;
+  int32_t* rd;
+};
+struct GradScratch {
+  std::vector<GradItemBuf> it;
+  double* obs;
+  JacMat* mat;    // [n_items]
   SelOut *sel, *seld;
   int32_t *rowmap, *perm, *unc;
+  double *s2, *nrm2;
+  int m_cap;
 };
 
 mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
+  const int ni = L / 2;  // bonds per layer
   const size_t r = (size_t)d * cm, mn = r * r, site_el = (size_t)cm * d * cm;
   WsPlan p;
-  size_t o[20];
-  for (int i = 0; i < 16; ++i) o[i] = p.take<double2>(mn);
-  for (int i = 16; i < 20; ++i) o[i] = p.take<double2>(site_el);
-  size_t oDot = p.take<double2>(32);
-  size_t oS = p.take<double>(r), oSb = p.take<double>(r), oS2 = p.take<double>(r), oCn = p.take<double>(r),
-         oObs = p.take<double>(2 * (size_t)L), oNr = p.take<double>(r);
-  size_t oMat = p.take<JacMat>(1), oSel = p.take<SelOut>(1), oSeld = p.take<SelOut>(1);
-  size_t oRm = p.take<int32_t>(2 * r), oPm = p.take<int32_t>(r), oUnc = p.take<int32_t>(8);
+  std::vector<size_t> o((size_t)ni * 27);
+  for (int i = 0; i < ni; ++i) {
+    size_t* q = &o[(size_t)i * 27];
+    for (int j = 0; j < 16; ++j) q[j] = p.take<double2>(mn);
+    for (int j = 16; j < 20; ++j) q[j] = p.take<double2>(site_el);
+    q[20] = p.take<double2>(2);
+    q[21] = p.take<double>(r);
+    q[22] = p.take<double>(r);
+    q[23] = p.take<double>(r);
+    q[24] = p.take<double>(r);
+    q[25] = p.take<double>(4);
+    q[26] = p.take<int32_t>(1);
+  }
+  size_t oObs = p.take<double>(2 * (size_t)L);
+  size_t oMat = p.take<JacMat>(ni), oSel = p.take<SelOut>(ni), oSeld = p.take<SelOut>(ni);
+  size_t oRm = p.take<int32_t>((size_t)ni * r), oPm = p.take<int32_t>((size_t)ni * r), oUnc = p.take<int32_t>(8);
+  size_t oS2 = p.take<double>((size_t)ni * r), oNr = p.take<double>((size_t)ni * r);
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
   char* ws = h->ws;
-  double2** mats[20] = {&g.T0, &g.T1, &g.P0, &g.Xj, &g.Vh, &g.Vb, &g.Y1, &g.Z, &g.Y, &g.Pm,
-                        &g.Pb, &g.T1b, &g.T0b, &g.Bnew, &g.Jv, &g.Xm, &g.Bbl, &g.Bnl, &g.Bbs, &g.Bns};
-  for (int i = 0; i < 20; ++i) *mats[i] = (double2*)(ws + o[i]);
-  g.dot = (double2*)(ws + oDot);
-  g.sv = (double*)(ws + oS);
-  g.sbar = (double*)(ws + oSb);
-  g.s2 = (double*)(ws + oS2);
-  g.cn2 = (double*)(ws + oCn);
+  g.it.resize(ni);
+  for (int i = 0; i < ni; ++i) {
+    const size_t* q = &o[(size_t)i * 27];
+    GradItemBuf& b = g.it[i];
+    double2** mats[20] = {&b.T0, &b.T1, &b.P0, &b.Xj, &b.Vh, &b.Vb, &b.Y1, &b.Z, &b.Y, &b.Pm,
+                          &b.Pb, &b.T1b, &b.T0b, &b.Bnew, &b.Jv, &b.Xm, &b.Bbl, &b.Bnl, &b.Bbs, &b.Bns};
+    for (int j = 0; j < 20; ++j) *mats[j] = (double2*)(ws + q[j]);
+    b.dot = (double2*)(ws + q[20]);
+    b.sv = (double*)(ws + q[21]);
+    b.sbar = (double*)(ws + q[22]);
+    b.c2 = (double*)(ws + q[23]);
+    b.kept2 = (double*)(ws + q[24]);
+    b.scal = (double*)(ws + q[25]);
+    b.rd = (int32_t*)(ws + q[26]);
+  }
   g.obs = (double*)(ws + oObs);
-  g.nrm2 = (double*)(ws + oNr);
   g.mat = (JacMat*)(ws + oMat);
   g.sel = (SelOut*)(ws + oSel);
   g.seld = (SelOut*)(ws + oSeld);
   g.rowmap = (int32_t*)(ws + oRm);
   g.perm = (int32_t*)(ws + oPm);
   g.unc = (int32_t*)(ws + oUnc);
+  g.s2 = (double*)(ws + oS2);
+  g.nrm2 = (double*)(ws + oNr);
+  g.m_cap = (int)r;
   return MPS_OK;
 }
 
@@ -385,6 +490,7 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
   // ---- loss and its cotangents at the final state -------------------------
   GradScratch g;
   if ((r = grad_scratch(h, L, d, cm, g)) != MPS_OK) return r;
+  const GradItemBuf& g0 = g.it[0];
   std::vector<int32_t> chi(L + 1);
   MPS_TRY_HIP(h, hipMemcpyAsync(chi.data(), ch.chi, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   {
@@ -402,36 +508,56 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
   {
     // site term <O1>_i = sum_a lam_a^2 <B_a|O1|B_a>: B_bar += 2 lam^2 O1 B, lam_bar += 2 lam Re<B, O1 B>
     const int i = site, a = chi[i], b2 = chi[i + 1];
-    K1((site_copy_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>((const double2*)ch.B + i * site_el, g.Bbs, a, d,
+    K1((site_copy_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>((const double2*)ch.B + i * site_el, g0.Bbs, a, d,
                                                                      b2, cm, 1)));
-    K1((apply_local_kernel<<<g1d((long long)a * b2), 256, 0, s>>>((const double2*)op1, d, g.Bbs, g.T0, a, b2, 0, 0)));
-    K1((row_scale_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>(g.T0, bbar(i), a * d, b2, ch.lam + (size_t)i * cm,
+    K1((apply_local_kernel<<<g1d((long long)a * b2), 256, 0, s>>>((const double2*)op1, d, g0.Bbs, g0.T0, a, b2, 0, 0)));
+    K1((row_scale_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>(g0.T0, bbar(i), a * d, b2, ch.lam + (size_t)i * cm,
                                                                      d, 2, 2.0, 1)));
-    K1((lam_dot_kernel<<<a, 256, 0, s>>>(g.Bbs, g.T0, d, b2, lbar + (size_t)i * cm, ch.lam + (size_t)i * cm, 2.0)));
+    K1((lam_dot_kernel<<<a, 256, 0, s>>>(g0.Bbs, g0.T0, d, b2, lbar + (size_t)i * cm, ch.lam + (size_t)i * cm, 2.0)));
     // bond terms <theta|O2|theta>, theta = lam_b B_b B_{b+1}
     for (int b = 0; b < L - 1; ++b) {
       const int chl = chi[b], chm = chi[b + 1], chr = chi[b + 2], m = chl * d, n = d * chr;
-      K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>((const double2*)ch.B + b * site_el, g.Bbs, chl, d,
+      K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>((const double2*)ch.B + b * site_el, g0.Bbs, chl, d,
                                                                     chm, cm, 1)));
-      K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>((const double2*)ch.B + (b + 1) * site_el, g.Bns,
+      K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>((const double2*)ch.B + (b + 1) * site_el, g0.Bns,
                                                                     chm, d, chr, cm, 1)));
-      if ((r = gemm128(c, g.Bbs, chm, 1, 0, g.Bns, n, 1, 0, g.T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
-      K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.T0, g.T1, m, n, ch.lam + (size_t)b * cm, d, 1, 1.0,
+      if ((r = gemm128(c, g0.Bbs, chm, 1, 0, g0.Bns, n, 1, 0, g0.T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
+      K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g0.T0, g0.T1, m, n, ch.lam + (size_t)b * cm, d, 1, 1.0,
                                                                   0)));
-      K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>((const double2*)op2, dd, g.T1, g.P0, chl, chr,
+      K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>((const double2*)op2, dd, g0.T1, g0.P0, chl, chr,
                                                                         0, 0)));
       // theta_bar = 2 O2 theta; lam_bar_b += Re<theta_bar, X>; X_bar = lam_b theta_bar
-      K1((lam_dot_kernel<<<chl, 256, 0, s>>>(g.P0, g.T0, d, n, lbar + (size_t)b * cm, nullptr, 2.0)));
-      K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.P0, g.Pb, m, n, ch.lam + (size_t)b * cm, d, 1, 2.0,
+      K1((lam_dot_kernel<<<chl, 256, 0, s>>>(g0.P0, g0.T0, d, n, lbar + (size_t)b * cm, nullptr, 2.0)));
+      K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g0.P0, g0.Pb, m, n, ch.lam + (size_t)b * cm, d, 1, 2.0,
                                                                   0)));
-      if ((r = gemm128(c, g.Pb, n, 1, 0, g.Bns, 1, n, 1, g.Y1, chm, m, chm, n, 1.0)) != MPS_OK) return r;
-      if ((r = gemm128(c, g.Bbs, 1, chm, 1, g.Pb, n, 1, 0, g.Z, n, chm, n, m, 1.0)) != MPS_OK) return r;
-      K1((axpy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>(g.Y1, bbar(b), (long long)m * chm, 1.0)));
-      K1((axpy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>(g.Z, bbar(b + 1), (long long)chm * n, 1.0)));
+      if ((r = gemm128(c, g0.Pb, n, 1, 0, g0.Bns, 1, n, 1, g0.Y1, chm, m, chm, n, 1.0)) != MPS_OK) return r;
+      if ((r = gemm128(c, g0.Bbs, 1, chm, 1, g0.Pb, n, 1, 0, g0.Z, n, chm, n, m, 1.0)) != MPS_OK) return r;
+      K1((axpy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>(g0.Y1, bbar(b), (long long)m * chm, 1.0)));
+      K1((axpy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>(g0.Z, bbar(b + 1), (long long)chm * n, 1.0)));
     }
   }
 
   // ---- backward over steps and layers -------------------------------------
+  // Every bond of a layer is an independent update: its reverse pass runs on
+  // an auxiliary stream of its own.  The layer's residual SVDs run as one
+  // batch on the launch stream between the two halves.  No per-update host
+  // round trip: the sizes that depend on the data (how many discarded
+  // directions are resolved, n_k) stay on the device, and the matrices that
+  // depend on them are formed at capacity r_cap = min(m, n) with zero rows.
+  const int n_aux = std::min(8, std::max(1, L / 2));
+  if ((r = mps_aux_streams(h, n_aux)) != MPS_OK) return r;
+  auto fork = [&]() -> mps_status {
+    MPS_TRY_HIP(h, hipEventRecord(h->aux_ev[n_aux], s));
+    for (int i = 0; i < n_aux; ++i) MPS_TRY_HIP(h, hipStreamWaitEvent(h->aux[i], h->aux_ev[n_aux], 0));
+    return MPS_OK;
+  };
+  auto join = [&]() -> mps_status {
+    for (int i = 0; i < n_aux; ++i) {
+      MPS_TRY_HIP(h, hipEventRecord(h->aux_ev[i], h->aux[i]));
+      MPS_TRY_HIP(h, hipStreamWaitEvent(s, h->aux_ev[i], 0));
+    }
+    return MPS_OK;
+  };
   const double abs_saved = h->jac_abs;
   for (int stp = n_steps - 1; stp >= 0; --stp) {
     if ((r = restore(arena + A.oCk + (size_t)stp * A.snap)) != MPS_OK) return r;
@@ -457,131 +583,133 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
       MPS_TRY_HIP(h, hipMemcpyAsync(cn.data(), NC, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       MPS_TRY_HIP(h, hipStreamSynchronize(s));
       const int par = (li == 1) ? 1 : 0, cls = (li == 1) ? 1 : 0;
-      for (int b = par; b < L - 1; b += 2) {
-        const int chl = co[b], chm = co[b + 1], chr = co[b + 2], m = chl * d, n = d * chr, k = cn[b + 1];
-        const int rmax = std::min(m, n);
+      std::vector<int> bonds;
+      for (int b = par; b < L - 1; b += 2) bonds.push_back(b);
+      const int ni = (int)bonds.size();
+      // residual matrices of the layer, described for the batched Jacobi
+      std::vector<JacMat> hm(ni);
+      for (int i = 0; i < ni; ++i) {
+        const int b = bonds[i], m = co[b] * d, n = d * co[b + 2], k = cn[b + 1];
+        std::memset(&hm[i], 0, sizeof(JacMat));
+        hm[i].X = g.it[i].Xj;
+        hm[i].rowmap = g.rowmap + (size_t)i * g.m_cap;
+        hm[i].nrm2 = g.nrm2 + (size_t)i * g.m_cap;
+        hm[i].m = m;
+        hm[i].n = n;
+        hm[i].ld = n;
+        hm[i].nb = jac_nb(m);
+        hm[i].kmax = std::max(0, std::min(m, n) - k);
+      }
+      MPS_TRY_HIP(h, hipMemcpyAsync(g.mat, hm.data(), ni * sizeof(JacMat), hipMemcpyHostToDevice, s));
+      MPS_TRY_HIP(h, hipStreamSynchronize(s));
+      int nb_cap = 2, mmax = 1;
+      for (int i = 0; i < ni; ++i) {
+        nb_cap = std::max(nb_cap, hm[i].nb);
+        mmax = std::max(mmax, hm[i].m);
+      }
+
+      // -- first half: recompute the update, form the residual theta'(1 - V_k V_k^dag)
+      if ((r = fork()) != MPS_OK) return r;
+      for (int i = 0; i < ni; ++i) {
+        Ctx c{h, h->aux[i % n_aux]};
+        hipStream_t si = c.s;
+        const GradItemBuf& q = g.it[i];
+        const int b = bonds[i], chl = co[b], chm = co[b + 1], chr = co[b + 2], m = chl * d, n = d * chr;
+        const int k = cn[b + 1];
         const double* lam_b = SL + (size_t)b * cm;
-        // cotangents of the updated tensors, compact: B_b' [m][k], B_{b+1}' [k][n], lam' [k]
-        MPS_TRY_HIP(h, hipMemcpyAsync(g.Bbl, bbar(b), (size_t)m * k * sizeof(double2), hipMemcpyDeviceToDevice, s));
-        MPS_TRY_HIP(h, hipMemcpyAsync(g.Bnl, bbar(b + 1), (size_t)k * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-        std::vector<double> lbm(k);
-        MPS_TRY_HIP(h, hipMemcpyAsync(lbm.data(), lbar + (size_t)(b + 1) * cm, k * sizeof(double),
-                                      hipMemcpyDeviceToHost, s));
-        // recompute theta~ = B_b B_{b+1}, theta~' = G theta~, theta' = lam_b theta~'
-        K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>(SB + b * site_el, g.Bbs, chl, d, chm, cm, 1)));
-        K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>(SB + (b + 1) * site_el, g.Bns, chm, d, chr, cm,
-                                                                      1)));
-        if ((r = gemm128(c, g.Bbs, chm, 1, 0, g.Bns, n, 1, 0, g.T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
-        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>(Gp(cls, b), dd, g.T0, g.T1, chl, chr, 0, 0)));
-        K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.T1, g.P0, m, n, lam_b, d, 1, 1.0, 0)));
+        MPS_TRY_HIP(h, hipMemcpyAsync(q.Bbl, bbar(b), (size_t)m * k * sizeof(double2), hipMemcpyDeviceToDevice, si));
+        MPS_TRY_HIP(h, hipMemcpyAsync(q.Bnl, bbar(b + 1), (size_t)k * n * sizeof(double2), hipMemcpyDeviceToDevice, si));
+        K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, si>>>(SB + b * site_el, q.Bbs, chl, d, chm, cm, 1)));
+        K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, si>>>(SB + (b + 1) * site_el, q.Bns, chm, d, chr, cm,
+                                                                       1)));
+        if ((r = gemm128(c, q.Bbs, chm, 1, 0, q.Bns, n, 1, 0, q.T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
+        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, si>>>(Gp(cls, b), dd, q.T0, q.T1, chl, chr, 0,
+                                                                           0)));
+        K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, si>>>(q.T1, q.P0, m, n, lam_b, d, 1, 1.0, 0)));
         // the forward's own factors: V_k^dag = B_{b+1}', B_b' = theta~' V_k / n_k
-        K1((site_copy_kernel<<<g1d((long long)k * n), 256, 0, s>>>(NB + (b + 1) * site_el, g.Vh, k, d, chr, cm, 1)));
-        K1((site_copy_kernel<<<g1d((long long)m * k), 256, 0, s>>>(NB + b * site_el, g.Bnew, chl, d, k, cm, 1)));
-        // discarded directions: rows of the residual theta' (1 - V_k V_k^dag), orthogonalised
-        // by the Jacobi sweep with a purely relative tolerance and projected once more
-        if ((r = gemm128(c, g.P0, n, 1, 0, g.Vh, 1, n, 1, g.Pm, k, m, k, n, 1.0)) != MPS_OK) return r;
-        if ((r = gemm128(c, g.Pm, k, 1, 0, g.Vh, n, 1, 0, g.Z, n, m, n, k, 1.0)) != MPS_OK) return r;
-        MPS_TRY_HIP(h, hipMemcpyAsync(g.Xj, g.P0, (size_t)m * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-        K1((axpy_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.Z, g.Xj, (long long)m * n, -1.0)));
-        K1((colnorm2_kernel<<<g1d(k), 256, 0, s>>>(g.Pm, m, k, g.cn2)));
-        int rd = 0;
-        std::vector<double> s2h(m, 0.0), kept2(k);
-        if (rmax > k) {
-          JacMat hm;
-          std::memset(&hm, 0, sizeof(hm));
-          hm.X = g.Xj;
-          hm.rowmap = g.rowmap;
-          hm.nrm2 = g.nrm2;
-          hm.m = m;
-          hm.n = n;
-          hm.ld = n;
-          hm.nb = jac_nb(m);
-          hm.kmax = rmax - k;
-          MPS_TRY_HIP(h, hipMemcpyAsync(g.mat, &hm, sizeof(hm), hipMemcpyHostToDevice, s));
-          MPS_TRY_HIP(h, launch_jac_prep_plain(s, g.mat, 1, h->status_dev));
-          h->jac_abs = 0.0;
-          r = run_jacobi(h, s, g.mat, 1, hm.nb, m, g.unc, false);
-          h->jac_abs = abs_saved;
-          if (r != MPS_OK) return r;
-          MPS_TRY_HIP(h, launch_select(s, g.mat, 1, g.perm, g.s2, m, hm.kmax, 0.0, g.sel));
-          MPS_TRY_HIP(h, hipMemcpyAsync(s2h.data(), g.s2, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        K1((site_copy_kernel<<<g1d((long long)k * n), 256, 0, si>>>(NB + (b + 1) * site_el, q.Vh, k, d, chr, cm, 1)));
+        K1((site_copy_kernel<<<g1d((long long)m * k), 256, 0, si>>>(NB + b * site_el, q.Bnew, chl, d, k, cm, 1)));
+        if ((r = gemm128(c, q.P0, n, 1, 0, q.Vh, 1, n, 1, q.Pm, k, m, k, n, 1.0)) != MPS_OK) return r;
+        if ((r = gemm128(c, q.Pm, k, 1, 0, q.Vh, n, 1, 0, q.Z, n, m, n, k, 1.0)) != MPS_OK) return r;
+        MPS_TRY_HIP(h, hipMemcpyAsync(q.Xj, q.P0, (size_t)m * n * sizeof(double2), hipMemcpyDeviceToDevice, si));
+        K1((axpy_kernel<<<g1d((long long)m * n), 256, 0, si>>>(q.Z, q.Xj, (long long)m * n, -1.0)));
+        K1((colnorm2_kernel<<<g1d(k), 256, 0, si>>>(q.Pm, m, k, q.kept2)));
+      }
+      if ((r = join()) != MPS_OK) return r;
+
+      // -- the layer's residual SVDs, orthogonalised with a purely relative tolerance
+      MPS_TRY_HIP(h, launch_jac_prep_plain(s, g.mat, ni, h->status_dev));
+      h->jac_abs = 0.0;
+      r = run_jacobi(h, s, g.mat, ni, nb_cap, g.m_cap, g.unc, false);
+      h->jac_abs = abs_saved;
+      if (r != MPS_OK) return r;
+      MPS_TRY_HIP(h, launch_select(s, g.mat, ni, g.perm, g.s2, g.m_cap, 0, 0.0, g.sel));
+
+      // -- second half: SVD backward, gate and contraction adjoints
+      if ((r = fork()) != MPS_OK) return r;
+      for (int i = 0; i < ni; ++i) {
+        Ctx c{h, h->aux[i % n_aux]};
+        hipStream_t si = c.s;
+        const GradItemBuf& q = g.it[i];
+        const int b = bonds[i], chl = co[b], chm = co[b + 1], chr = co[b + 2], m = chl * d, n = d * chr;
+        const int k = cn[b + 1], rc = std::min(m, n), cap = rc - k;
+        const double* lam_b = SL + (size_t)b * cm;
+        const double* lbm = lbar + (size_t)(b + 1) * cm;
+        const double* inv_nk = q.scal + 1;
+        // discarded directions: the resolved residual rows, normalised, projected once more
+        K1((grad_rd_kernel<<<1, 256, 0, si>>>(g.s2 + (size_t)i * g.m_cap, q.kept2, m, k, cap, 1e-26, g.seld + i,
+                                              q.rd)));
+        if (cap > 0) {
+          double2* Vd = q.Vh + (size_t)k * n;
+          K1((fill_zero_kernel<<<g1d((long long)cap * n), 256, 0, si>>>(Vd, (long long)cap * n)));
+          MPS_TRY_HIP(h, launch_write_rows(si, g.mat + i, g.perm + (size_t)i * g.m_cap, g.s2 + (size_t)i * g.m_cap,
+                                           g.seld + i, Vd, n, 0, true));
+          if ((r = gemm128(c, Vd, n, 1, 0, q.Vh, 1, n, 1, q.Jv, k, cap, k, n, 1.0)) != MPS_OK) return r;
+          if ((r = gemm128(c, q.Jv, k, 1, 0, q.Vh, n, 1, 0, q.Z, n, cap, n, k, 1.0)) != MPS_OK) return r;
+          K1((axpy_kernel<<<g1d((long long)cap * n), 256, 0, si>>>(q.Z, Vd, (long long)cap * n, -1.0)));
         }
-        MPS_TRY_HIP(h, hipMemcpyAsync(kept2.data(), g.cn2, k * sizeof(double), hipMemcpyDeviceToHost, s));
-        MPS_TRY_HIP(h, hipStreamSynchronize(s));
-        double tot = 0.0;
-        for (int j = 0; j < k; ++j) tot += kept2[j];
-        for (int j = 0; j < m; ++j) tot += std::max(s2h[j], 0.0);
-        while (k + rd < rmax && s2h[rd] > 1e-26 * tot) ++rd;
-        const int ru = k + rd;
-        if (rd > 0) {
-          SelOut so;
-          std::memset(&so, 0, sizeof(so));
-          so.k = rd;
-          MPS_TRY_HIP(h, hipMemcpyAsync(g.seld, &so, sizeof(so), hipMemcpyHostToDevice, s));
-          double2* Vd = g.Vh + (size_t)k * n;
-          MPS_TRY_HIP(h, launch_write_rows(s, g.mat, g.perm, g.s2, g.seld, Vd, n, 0, true));
-          if ((r = gemm128(c, Vd, n, 1, 0, g.Vh, 1, n, 1, g.Jv, k, rd, k, n, 1.0)) != MPS_OK) return r;
-          if ((r = gemm128(c, g.Jv, k, 1, 0, g.Vh, n, 1, 0, g.Z, n, rd, n, k, 1.0)) != MPS_OK) return r;
-          K1((axpy_kernel<<<g1d((long long)rd * n), 256, 0, s>>>(g.Z, Vd, (long long)rd * n, -1.0)));
-        }
-        // P = theta' V (m x ru), s_i = |P e_i|
-        if ((r = gemm128(c, g.P0, n, 1, 0, g.Vh, 1, n, 1, g.Pm, ru, m, ru, n, 1.0)) != MPS_OK) return r;
-        K1((colnorm2_kernel<<<g1d(ru), 256, 0, s>>>(g.Pm, m, ru, g.cn2)));
-        // n_bar = -(Re<B_bar_b', B_b'> + sum lam_bar' lam') / n_k,  s_bar = lam_bar'/n_k + n_bar s/n_k
-        MPS_TRY_HIP(h, launch_zero(s, (double*)g.dot, 64));
-        MPS_TRY_HIP(h, launch_mdot(s, g.Bbl, 0, 1, g.Bnew, (long long)m * k, g.dot));
-        double2 dh;
-        std::vector<double> sh2(ru);
-        MPS_TRY_HIP(h, hipMemcpyAsync(&dh, g.dot, sizeof(dh), hipMemcpyDeviceToHost, s));
-        MPS_TRY_HIP(h, hipMemcpyAsync(sh2.data(), g.cn2, ru * sizeof(double), hipMemcpyDeviceToHost, s));
-        MPS_TRY_HIP(h, hipStreamSynchronize(s));
-        std::vector<double> sh(ru), sb(ru, 0.0);
-        double nk2 = 0.0;
-        for (int j = 0; j < ru; ++j) sh[j] = std::sqrt(std::max(sh2[j], 0.0));
-        for (int j = 0; j < k; ++j) nk2 += sh2[j];
-        const double nk = std::sqrt(nk2);
-        if (!(nk > 0.0)) return mps_fail(h, MPS_ERR_NONFINITE, "vanishing kept weight in the reverse pass");
-        double ll = 0.0;
-        for (int j = 0; j < k; ++j) ll += lbm[j] * sh[j] / nk;
-        const double nbar = -(dh.x + ll) / nk;
-        for (int j = 0; j < k; ++j) sb[j] = lbm[j] / nk + nbar * sh[j] / nk;
-        MPS_TRY_HIP(h, hipMemcpyAsync(g.sv, sh.data(), ru * sizeof(double), hipMemcpyHostToDevice, s));
-        MPS_TRY_HIP(h, hipMemcpyAsync(g.sbar, sb.data(), ru * sizeof(double), hipMemcpyHostToDevice, s));
-        // V_bar (n x ru): kept columns theta~'^dag B_bar_b' / n_k + conj(B_bar_{b+1}')^T
-        K1((fill_zero_kernel<<<g1d((long long)n * ru), 256, 0, s>>>(g.Vb, (long long)n * ru)));
+        // P = theta' V (m x rc), its column norms, and the scalars n_k, n_bar, s_bar
+        if ((r = gemm128(c, q.P0, n, 1, 0, q.Vh, 1, n, 1, q.Pm, rc, m, rc, n, 1.0)) != MPS_OK) return r;
+        K1((colnorm2_kernel<<<g1d(rc), 256, 0, si>>>(q.Pm, m, rc, q.c2)));
+        K1((fill_zero_kernel<<<1, 256, 0, si>>>(q.dot, 2)));
+        MPS_TRY_HIP(h, launch_mdot(si, q.Bbl, 0, 1, q.Bnew, (long long)m * k, q.dot));
+        K1((grad_scalars_kernel<<<1, 256, 0, si>>>(q.c2, lbm, q.dot, k, rc, q.sv, q.sbar, q.scal, h->status_dev)));
+        // V_bar (n x rc): kept columns theta~'^dag B_bar_b' / n_k + conj(B_bar_{b+1}')^T
+        K1((fill_zero_kernel<<<g1d((long long)n * rc), 256, 0, si>>>(q.Vb, (long long)n * rc)));
         {
           SGemm G;
           std::memset(&G, 0, sizeof(G));
-          G.A = g.T1; G.rsA = 1; G.csA = n; G.conjA = 1;
-          G.B = g.Bbl; G.rsB = k; G.csB = 1;
-          G.C = g.Vb; G.rsC = ru; G.csC = 1;
-          G.M = n; G.N = k; G.K = m; G.alpha = 1.0 / nk;
-          MPS_TRY_HIP(h, launch_sgemm(s, G, true));
+          G.A = q.T1; G.rsA = 1; G.csA = n; G.conjA = 1;
+          G.B = q.Bbl; G.rsB = k; G.csB = 1;
+          G.C = q.Vb; G.rsC = rc; G.csC = 1;
+          G.M = n; G.N = k; G.K = m; G.alpha = 1.0; G.alpha_dev = inv_nk;
+          MPS_TRY_HIP(h, launch_sgemm(si, G, true));
         }
-        K1((add_conj_t_kernel<<<g1d((long long)n * k), 256, 0, s>>>(g.Vb, g.Bnl, n, ru, k)));
+        K1((add_conj_t_kernel<<<g1d((long long)n * k), 256, 0, si>>>(q.Vb, q.Bnl, n, rc, k)));
         // Jv = V^dag V_bar; Xt; Y = Xt V^dag + diag(w)(V_bar^dag - Jv^dag V^dag); theta'_bar = P Y
-        if ((r = gemm128(c, g.Vh, n, 1, 0, g.Vb, ru, 1, 0, g.Jv, ru, ru, ru, n, 1.0)) != MPS_OK) return r;
-        K1((svd_x_kernel<<<g1d((long long)ru * ru), 256, 0, s>>>(g.Jv, g.sv, g.sbar, ru, k, eta, g.Xm)));
-        if ((r = gemm128(c, g.Xm, ru, 1, 0, g.Vh, n, 1, 0, g.Y1, n, ru, n, ru, 1.0)) != MPS_OK) return r;
-        if ((r = gemm128(c, g.Jv, 1, ru, 1, g.Vh, n, 1, 0, g.Z, n, ru, n, ru, 1.0)) != MPS_OK) return r;
-        K1((svd_y_kernel<<<g1d((long long)ru * n), 256, 0, s>>>(g.Y1, g.Z, g.Vb, g.sv, ru, k, n, eta, g.Y)));
-        if ((r = gemm128(c, g.Pm, ru, 1, 0, g.Y, n, 1, 0, g.Pb, n, m, n, ru, 1.0)) != MPS_OK) return r;
+        if ((r = gemm128(c, q.Vh, n, 1, 0, q.Vb, rc, 1, 0, q.Jv, rc, rc, rc, n, 1.0)) != MPS_OK) return r;
+        K1((svd_x_kernel<<<g1d((long long)rc * rc), 256, 0, si>>>(q.Jv, q.sv, q.sbar, rc, k, eta, q.Xm)));
+        if ((r = gemm128(c, q.Xm, rc, 1, 0, q.Vh, n, 1, 0, q.Y1, n, rc, n, rc, 1.0)) != MPS_OK) return r;
+        if ((r = gemm128(c, q.Jv, 1, rc, 1, q.Vh, n, 1, 0, q.Z, n, rc, n, rc, 1.0)) != MPS_OK) return r;
+        K1((svd_y_kernel<<<g1d((long long)rc * n), 256, 0, si>>>(q.Y1, q.Z, q.Vb, q.sv, rc, k, n, eta, q.Y)));
+        if ((r = gemm128(c, q.Pm, rc, 1, 0, q.Y, n, 1, 0, q.Pb, n, m, n, rc, 1.0)) != MPS_OK) return r;
         // theta~'_bar = B_bar_b' V_k^dag / n_k + lam_b theta'_bar;  lam_bar_b += Re<theta'_bar, theta~'>
-        if ((r = gemm128(c, g.Bbl, k, 1, 0, g.Vh, n, 1, 0, g.T1b, n, m, n, k, 1.0 / nk)) != MPS_OK) return r;
-        K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g.Pb, g.T1b, m, n, lam_b, d, 1, 1.0, 1)));
-        K1((lam_dot_kernel<<<chl, 256, 0, s>>>(g.Pb, g.T1, d, n, lbar + (size_t)b * cm, nullptr, 1.0)));
+        if ((r = gemm128(c, q.Bbl, k, 1, 0, q.Vh, n, 1, 0, q.T1b, n, m, n, k, 1.0, inv_nk)) != MPS_OK) return r;
+        K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, si>>>(q.Pb, q.T1b, m, n, lam_b, d, 1, 1.0, 1)));
+        K1((lam_dot_kernel<<<chl, 256, 0, si>>>(q.Pb, q.T1, d, n, lbar + (size_t)b * cm, nullptr, 1.0)));
         // coupling: J_bar_b += Re<theta~'_bar, dG/dJ_b theta~>
-        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>(dGp(cls, b), dd, g.T0, g.Z, chl, chr, 0, 0)));
-        MPS_TRY_HIP(h, launch_zero(s, (double*)g.dot, 64));
-        MPS_TRY_HIP(h, launch_mdot(s, g.T1b, 0, 1, g.Z, (long long)m * n, g.dot));
-        K1((jbar_add_kernel<<<1, 1, 0, s>>>(g.dot, dJ_dev, b)));
-        // theta~_bar = G^dag theta~'_bar;  B_bar_b = theta~_bar B_{b+1}^dag;  B_bar_{b+1} = B_b^dag theta~_bar
-        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>(Gp(cls, b), dd, g.T1b, g.T0b, chl, chr, 1,
-                                                                          0)));
-        if ((r = gemm128(c, g.T0b, n, 1, 0, g.Bns, 1, n, 1, bbar(b), chm, m, chm, n, 1.0)) != MPS_OK) return r;
-        if ((r = gemm128(c, g.Bbs, 1, chm, 1, g.T0b, n, 1, 0, bbar(b + 1), n, chm, n, m, 1.0)) != MPS_OK) return r;
-        MPS_TRY_HIP(h, hipMemsetAsync(lbar + (size_t)(b + 1) * cm, 0, cm * sizeof(double), s));
+        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, si>>>(dGp(cls, b), dd, q.T0, q.Z, chl, chr, 0,
+                                                                           0)));
+        MPS_TRY_HIP(h, launch_mdot(si, q.T1b, 0, 1, q.Z, (long long)m * n, q.dot + 1));
+        K1((jbar_add_kernel<<<1, 1, 0, si>>>(q.dot + 1, dJ_dev, b)));
+        // theta~_bar = G^dag theta~'_bar ; B_bar_b = theta~_bar B_{b+1}^dag ; B_bar_{b+1} = B_b^dag theta~_bar
+        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, si>>>(Gp(cls, b), dd, q.T1b, q.T0b, chl, chr, 1,
+                                                                           0)));
+        if ((r = gemm128(c, q.T0b, n, 1, 0, q.Bns, 1, n, 1, bbar(b), chm, m, chm, n, 1.0)) != MPS_OK) return r;
+        if ((r = gemm128(c, q.Bbs, 1, chm, 1, q.T0b, n, 1, 0, bbar(b + 1), n, chm, n, m, 1.0)) != MPS_OK) return r;
+        MPS_TRY_HIP(h, hipMemsetAsync(lbar + (size_t)(b + 1) * cm, 0, cm * sizeof(double), si));
       }
+      if ((r = join()) != MPS_OK) return r;
     }
   }
   // the chain is left in the final state of the forward run

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
     }
   }
   typedef typename Cx<T>::R R;
-  const R alpha = (R)P.alpha;
+  const R alpha = P.alpha_dev ? (R)(*P.alpha_dev) : (R)P.alpha;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
