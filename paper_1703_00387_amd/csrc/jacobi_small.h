@@ -1,8 +1,8 @@
 // Cyclic parallel Jacobi eigensolver for a Hermitian matrix of order <= N
 // (N = 32 or 64) held in LDS, run by one 256-thread workgroup, in FP64.
 //
-// G  : [N][N+1] complex128 in LDS, overwritten with Q^dag G Q (diagonal)
-// Q  : [N][N+1] complex128 in LDS, overwritten with the accumulated unitary
+// G  : [N][LD] complex128 in LDS (LD >= N, default N+1), overwritten with Q^dag G Q
+// Q  : [N][LD] complex128 in LDS, overwritten with the accumulated unitary
 //      (initialised here to the identity); G_in = Q diag(G_out) Q^dag.
 // Each step rotates up to N/2 disjoint index pairs of the odd-even ordering
 // below, so a sweep of N steps visits every pair once.  The 2x2 rotation for the
@@ -47,10 +47,10 @@ __device__ __forceinline__ bool js_pair(int step, int k, int& p, int& q) {
 }
 
 // Returns the number of sweeps used (<= max_sweeps).  Exactly 256 threads call it.
-template <int N>
+template <int N, int LD = N + 1>
 __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double rel_thr, int max_sweeps,
                            double4* rot /* LDS [N/2] */, int* flag /* LDS */) {
-  constexpr int LD = N + 1, NP = N / 2;
+  constexpr int NP = N / 2;
   const int tid = threadIdx.x;
   for (int i = tid; i < N * N; i += blockDim.x) {
     int r = i / N, c = i % N;

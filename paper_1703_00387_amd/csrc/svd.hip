@@ -201,6 +201,10 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   double2* X = M->X;
   int I, J;
   jac_pair(nb, round, p, I, J);
+  if (loop_sweeps > 0) {  // one panel: keep the real rows first
+    I = 0;
+    J = 1;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   if (tid < JP) {
@@ -288,7 +292,18 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   }
   rotated = true;
 
-  herm_jacobi<JP>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
+  if (loop_sweeps > 0 && m <= JB) {
+    // a matrix of at most 32 rows: the 32x32 solve on the leading block (the
+    // other rows are zero), Q the identity elsewhere
+    herm_jacobi<JB, JP + 1>(G, Q, JB, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
+    for (int e = tid; e < JP * JP; e += 256) {
+      const int i = e / JP, j = e % JP;
+      if (i >= JB || j >= JB) Q[i * (JP + 1) + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+  } else {
+    herm_jacobi<JP>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
+  }
   // the rotated rows have squared norms diag(Q^dag G Q), left on G's diagonal
   if (tid < JP && rows_s[tid] >= 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
   __syncthreads();
