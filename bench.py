@@ -58,7 +58,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="xxz_batch256: skip the one-bond-per-launch comparison")
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
-    ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256", "bh_heff_chi512", "xxz_grad_L32"])
+    ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256", "bh_heff_chi512", "xxz_grad_L32",
+                             "xxz_sweep_L64"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -73,7 +74,7 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.warmup is None:
-        args.warmup = 40 if args.workload == "xxz_batch256" else 140
+        args.warmup = {"xxz_batch256": 40}.get(args.workload, 140)
 
     import workloads as W
     from paper_1703_00387_amd import api, models
@@ -84,6 +85,8 @@ def main():
         return bench_heff(args)
     if args.workload == "xxz_grad_L32":
         return bench_grad(args)
+    if args.workload == "xxz_sweep_L64":
+        return bench_sweep(args)
     wl = W.xxz_tebd4_L64()
     spec = wl.chains[0]
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
@@ -316,6 +319,64 @@ def bench_grad(args):
         "gradient_s": round(t_grad, 3), "forward_only_s": round(t_fwd, 3),
         "adjoint_over_forward": round(t_grad / t_fwd, 2), "loss": float(loss),
         "grad_norm": float(torch.linalg.vector_norm(dJ)), "device_status": [code, word],
+    }
+    print(json.dumps(out))
+    h.close()
+
+
+def bench_sweep(args):
+    """The paper's own second-order sweep (every bond left to right with dt/2,
+    then right to left) against even/odd TEBD2 on the same chi=256 state of the
+    XXZ chain: the sweep updates one bond at a time, even/odd a whole layer."""
+    import torch
+
+    import workloads as W
+    from paper_1703_00387_amd import api, models
+
+    wl = W.xxz_tebd4_L64()
+    spec = wl.chains[0]
+    h = api.Handle(0)
+    ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
+    if args.load_state:
+        st = torch.load(args.load_state, weights_only=True)
+        for k in ("B", "lam", "chi", "disc"):
+            getattr(ch, k).copy_(st[k].to(getattr(ch, k).device))
+    else:
+        done = 0
+        t0 = time.time()
+        while done < args.warmup:
+            n = min(10, args.warmup - done)
+            api.tebd_step(h, [ch], 4, wl.dt, n, wl.eps_local)
+            torch.cuda.synchronize()
+            done += n
+            print(f"[bench] warmup {done}/{args.warmup}, {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    start = (ch.B.clone(), ch.lam.clone(), ch.chi.clone(), ch.disc.clone())
+
+    def timed(order):
+        ch.B.copy_(start[0]); ch.lam.copy_(start[1]); ch.chi.copy_(start[2]); ch.disc.copy_(start[3])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        api.tebd_step(h, [ch], order, wl.dt, 1, wl.eps_local)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    t_sweep = timed(0)
+    print(f"[bench] sweep step {t_sweep:.2f}s", file=sys.stderr, flush=True)
+    t_eo = timed(2)
+    print(f"[bench] even/odd step {t_eo:.2f}s", file=sys.stderr, flush=True)
+    code, word = h.device_status()
+    L = spec.L
+    upd_sweep, upd_eo = 2 * (L - 1), sum(len(range(p, L - 1, 2)) for p in (0, 1, 0))
+    out = {
+        "metric": "two-site MPS updates/s, the paper's second-order sweep (XXZ L=64, chi_max=256)",
+        "value": round(upd_sweep / t_sweep, 2), "unit": "updates/s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": round(t_sweep * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "xxz_sweep_L64: one sweep step (126 updates, one bond at a time) from the "
+                               "TEBD4 XXZ L=64 chi_max=256 state", "updates_per_step": upd_sweep},
+        "even_odd_tebd2": {"updates_per_s": round(upd_eo / t_eo, 2), "ms_per_step": round(t_eo * 1e3, 3),
+                           "updates_per_step": upd_eo},
+        "device_status": [code, word],
     }
     print(json.dumps(out))
     h.close()

@@ -153,18 +153,24 @@ typedef struct {
 #define MPS_FLAG_PLAIN 0x4u     /* one bond per launch sequence (no batching; comparison form) */
 
 /*
- * n_steps time steps of even/odd Trotter evolution on every chain
- * (Sec. "Sornborger-Stewart decomposition": the even/odd Suzuki-Trotter
- * alternative the paper names; order 2 =
- * Strang splitting: odd bonds tau/2, even bonds tau, odd bonds tau/2; order 4
- * = five Strang steps with weights p,p,1-4p,p,p, p = 1/(4-4^(1/3)), error
- * O(dt^4)).  Every update: theta~ = B_b B_{b+1} and theta~' = G theta~ on
- * FP32 MFMA (complex64), theta' = lam_b theta~' promoted to FP64, FP64 SVD,
- * truncation by the count rule with eps_local and chi_max, lam_{b+1} =
- * s/|s_k|, B_{b+1} = V^dag_k, B_b = theta~' V_k / |s_k|.  All bonds of one
- * layer of all chains are processed together.
+ * n_steps time steps of Trotter evolution on every chain.
+ *   order 2: even/odd Strang splitting (Sec. "Sornborger-Stewart
+ *            decomposition": the Suzuki-Trotter even/odd alternative the paper
+ *            names): odd bonds tau/2, even bonds tau, odd bonds tau/2;
+ *   order 4: five Strang steps with weights p, p, 1-4p, p, p, p = 1/(4-4^(1/3)),
+ *            error O(dt^4);
+ *   order 0: the paper's own second-order sweep (Eq. sornborger2): every bond
+ *            from left to right with dt/2, then from right to left with dt/2,
+ *            one bond at a time (the bonds of different chains together).
+ * Every update: theta~ = B_b B_{b+1} and theta~' = G theta~ on MFMA (FP32 for
+ * complex64 chains, FP64 for complex128), theta' = lam_b theta~' in FP64,
+ * FP64 SVD, truncation by the count rule with eps_local and chi_max,
+ * lam_{b+1} = s/|s_k|, B_{b+1} = V^dag_k, B_b = theta~' V_k / |s_k|.  All bonds
+ * of one layer of all chains are processed together.
  *   chains : HOST array of n_chains descriptors (device pointers inside)
  *   flags  : MPS_FLAG_* bits
+ * Errors: MPS_ERR_INVALID for an order other than 0, 2, 4, an unknown flag or
+ * a null pointer; MPS_ERR_SHAPE / MPS_ERR_CAPACITY for chain shapes.
  */
 mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
                          int32_t n_chains, int32_t order, double dt, int32_t n_steps,

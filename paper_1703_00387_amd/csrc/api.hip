@@ -359,7 +359,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
                      double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi) {
   if (!h) return MPS_ERR_INVALID;
   if (!chains || n_chains < 1) return mps_fail(h, MPS_ERR_INVALID, "need at least one chain");
-  if (order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 2 or 4");
+  if (order != 0 && order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 0, 2 or 4");
   if (n_steps < 0) return mps_fail(h, MPS_ERR_INVALID, "n_steps < 0");
   if (!(dt == dt) || !(eps_local == eps_local)) return mps_fail(h, MPS_ERR_INVALID, "NaN argument");
   if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS | MPS_FLAG_PLAIN))
@@ -399,7 +399,14 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   // time-step classes and the layer sequence of one step
   std::vector<double> taus;
   std::vector<std::pair<int, int>> layers;  // (parity 0 = odd bonds b=0,2,..., class)
-  if (order == 2) {
+  int l_max = 0;
+  for (int c = 0; c < n_chains; ++c) l_max = std::max(l_max, (int)chains[c].L);
+  if (order == 0) {
+    // the sweep: one bond per layer (in every chain), left to right then back,
+    // all with dt/2; layer j < l_max-1 is bond j, layer l_max-1+j is bond L-2-j
+    taus = {0.5 * dt};
+    for (int j = 0; j < 2 * (l_max - 1); ++j) layers.push_back({j, 0});
+  } else if (order == 2) {
     taus = {0.5 * dt, dt};
     layers = {{0, 0}, {1, 1}, {0, 0}};
   } else {
@@ -436,7 +443,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   }
   const size_t max_items = std::max(n_par[0], n_par[1]);
   size_t oSlots = p.take<char>(std::max(slot_bytes[0], slot_bytes[1]) + 256);
-  size_t oItems = p.take<BondItem>((n_par[0] + n_par[1]) * n_cls);
+  size_t oItems = p.take<BondItem>((n_par[0] + n_par[1]) * (order == 0 ? 2 : n_cls));
   size_t oMats = p.take<JacMat>(max_items);
   size_t oSel = p.take<SelOut>(max_items);
   size_t oProbs = p.take<GemmProb>(max_items);
@@ -472,19 +479,28 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   if (st != MPS_OK) return st;
   PROF_LAUNCH(h, s, MPS_K_GATES, launch_gates(s, (const GateJob*)(ws + oJobs), (int)jobs.size(), dd));
 
-  // bond items: for every (parity, class) a contiguous array
+  // bond items: for every group a contiguous array.  Groups are (parity,
+  // class) for the even/odd orders and single sweep layers for order 0.
+  const int n_groups = order == 0 ? (int)layers.size() : 2 * n_cls;
   std::vector<BondItem> items;
-  std::vector<size_t> start(2 * n_cls), count(2 * n_cls);
-  for (int par = 0; par < 2; ++par) {
-    for (int k = 0; k < n_cls; ++k) {
-      start[par * n_cls + k] = items.size();
+  std::vector<size_t> start(n_groups), count(n_groups);
+  for (int gi = 0; gi < n_groups; ++gi) {
+    {
+      const int par = order == 0 ? 0 : gi / n_cls, k = order == 0 ? 0 : gi % n_cls;
+      start[gi] = items.size();
       char* slot = ws + oSlots;
       for (int c = 0; c < n_chains; ++c) {
         const mps_chain_desc& ch = chains[c];
         const size_t site = (size_t)ch.chi_max * ch.d * ch.chi_max;
         const size_t sq = (size_t)ch.d * ch.chi_max * ch.d * ch.chi_max;
-        // largest chains first: their updates are the most expensive
-        for (int b = par; b < ch.L - 1; b += 2) {
+        std::vector<int> bl;
+        if (order == 0) {
+          const int j = gi < l_max - 1 ? gi : gi - (l_max - 1);
+          if (j < ch.L - 1) bl.push_back(gi < l_max - 1 ? j : ch.L - 2 - j);
+        } else {
+          for (int b = par; b < ch.L - 1; b += 2) bl.push_back(b);
+        }
+        for (int b : bl) {
           BondItem it;
           it.Bl = (char*)ch.B + (size_t)b * site * esz;
           it.Br = (char*)ch.B + (size_t)(b + 1) * site * esz;
@@ -506,7 +522,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
           items.push_back(it);
         }
       }
-      count[par * n_cls + k] = items.size() - start[par * n_cls + k];
+      count[gi] = items.size() - start[gi];
     }
   }
   st = upload(h, s, ws + oItems, items);
@@ -525,7 +541,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
     for (int li = 0; li < (int)layers.size(); ++li) {
       if (li < lo || li >= hi) continue;
       const auto& ly = layers[li];
-      const int idx = ly.first * n_cls + ly.second;
+      const int idx = order == 0 ? ly.first : ly.first * n_cls + ly.second;
       const int n_layer = (int)count[idx];
       if (n_layer == 0) continue;
       // plain form: one bond per launch sequence; else the whole layer at once

@@ -119,7 +119,7 @@ def _gpu_vector(chain):
 def _run_compare(H, spec, method, dt, n_steps, eps, check_every, state_check=False, flags=0, dtype="c128"):
     from oracle import mps as omps, models as om
     from paper_1703_00387_amd import api, models
-    order = 2 if method == "tebd2" else 4
+    order = {"tebd2": 2, "tebd4": 4, "sweep": 0}[method]
     hs = om.bond_hamiltonians(spec)
     ref = {}
     op_o = om.number_op(spec.d) if spec.model == "bh" else 0.5 * om.SZ
@@ -169,6 +169,41 @@ def test_xxz_tebd4_small(H, dtype):
     spec = W.xxz_chain(12, 64, 1.0, 0.5)
     worst, _ = _run_compare(H, spec, "tebd4", 0.05, 20, 1e-12, 5, state_check=True, dtype=dtype)
     print(f"xxz L12 tebd4 {dtype} worst |dSz| {worst:.3e}")
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sweep_tfim_and_xxz(H, dtype):
+    """The paper's own second-order sweep (one bond at a time, left to right
+    then back, dt/2 each) against the oracle's sweep."""
+    spec = W.tfim_chain(12, 32, 1.0, 1.0, "all_up")
+    worst, _ = _run_compare(H, spec, "sweep", 0.02, 30, 1e-12, 10, state_check=True, dtype=dtype)
+    spec = W.xxz_chain(10, 16, 1.0, 0.5)
+    worst2, _ = _run_compare(H, spec, "sweep", 0.05, 20, 1e-12, 5, state_check=True, dtype=dtype)
+    print(f"sweep {dtype} worst |dSz| tfim {worst:.3e} xxz {worst2:.3e}")
+
+
+def test_sweep_batch_of_chains_and_graph(H):
+    """Sweeps of chains of different length in one call (each chain runs its own
+    left-to-right-and-back order) match the oracle per chain; graph replay equals eager."""
+    from oracle import mps as omps, models as om
+    from paper_1703_00387_amd import api, models, _lib
+    wl = W.xxz_batch256(n_chains=3)
+    specs = [W.xxz_chain(L, 16, 1.0, 0.5, None, c.Jz_b[:L - 1], "random_product", c.local_states[:L])
+             for L, c in zip((8, 11, 14), wl.chains)]
+    a = [_gpu_chain(sp) for sp in specs]
+    b = [_gpu_chain(sp) for sp in specs]
+    api.tebd_step(H, a, 0, 0.05, 6, 1e-12)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        api.tebd_step(H, b, 0, 0.05, 6, 1e-12, flags=_lib.MPS_FLAG_GRAPH)
+    s.synchronize()
+    for sp, x, y in zip(specs, a, b):
+        ref = omps.tebd_run(sp, "sweep", 0.05, 6, 1e-12)
+        site, _, _ = api.observe(H, x, models.sz_operator())
+        dd = np.abs(site.cpu().numpy() - omps.local_expect(ref, 0.5 * om.SZ)).max()
+        assert dd <= 1e-6, (sp.L, dd)
+        site_g, _, _ = api.observe(H, y, models.sz_operator())
+        assert np.abs(site_g.cpu().numpy() - site.cpu().numpy()).max() <= 1e-9
 
 
 def test_bh_tebd2_d5(H):
