@@ -21,6 +21,8 @@ ed          state-vector references: exact propagation, exact Trotter circuit,
 freefermion single-particle propagation of the XX chain (exact and Trotterized)
 krylov      Lanczos exponential (Sec. Krylov time evolution, App. Krylov)
 tdvp        environments, structured H_eff apply, two-site TDVP (Sec. TDVP)
+ktebd       Krylov TEBD: the Sornborger-Stewart sweep with the Lanczos
+            exponential of every bond term (App. Details of the Krylov method)
 grad        reverse-mode gradient of TEBD2 with truncated-SVD backward, the
             exact-diagonalisation adjoint gradient, finite differences
 """

@@ -30,8 +30,9 @@ def tridiag_expm_e1(alpha, beta, tau):
     return Q @ (np.exp(-1j * tau * th) * Q[0, :])
 
 
-def lanczos_expm(apply_A, psi: np.ndarray, tau: complex, n_max=20, tol=1e-10):
-    """Returns (result, n_used, err_est, converged)."""
+def lanczos_expm(apply_A, psi: np.ndarray, tau: complex, n_max=20, tol=1e-10, history=None):
+    """Returns (result, n_used, err_est, converged).  If ``history`` is a list,
+    the estimate err_j of every iteration is appended to it."""
     nrm = np.linalg.norm(psi)
     if nrm == 0:
         return psi.copy(), 0, 0.0, True
@@ -54,6 +55,8 @@ def lanczos_expm(apply_A, psi: np.ndarray, tau: complex, n_max=20, tol=1e-10):
         beta.append(bj)
         u = tridiag_expm_e1(np.array(alpha), np.array(beta), tau)
         err = nrm * bj * abs(u[-1])
+        if history is not None:
+            history.append(float(err))
         if err <= tol or bj <= 1e-14 * nrm:
             conv = True
             break
