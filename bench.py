@@ -327,7 +327,10 @@ def bench_grad(args):
 def bench_sweep(args):
     """The paper's own second-order sweep (every bond left to right with dt/2,
     then right to left) against even/odd TEBD2 on the same chi=256 state of the
-    XXZ chain: the sweep updates one bond at a time, even/odd a whole layer."""
+    XXZ chain: the sweep updates one bond at a time, even/odd a whole layer.
+    The same sweep with the local Lanczos exponential of every bond term
+    (Krylov TEBD, 20 vectors at most, tol 1e-10) is timed from the same state:
+    the paper's appendix expects plain TEBD to be the faster of the two."""
     import torch
 
     import workloads as W
@@ -352,11 +355,16 @@ def bench_sweep(args):
             print(f"[bench] warmup {done}/{args.warmup}, {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     start = (ch.B.clone(), ch.lam.clone(), ch.chi.clone(), ch.disc.clone())
 
+    n_used = torch.zeros(2 * (spec.L - 1), dtype=torch.int32, device="cuda")
+
     def timed(order):
         ch.B.copy_(start[0]); ch.lam.copy_(start[1]); ch.chi.copy_(start[2]); ch.disc.copy_(start[3])
         torch.cuda.synchronize()
         t = time.perf_counter()
-        api.tebd_step(h, [ch], order, wl.dt, 1, wl.eps_local)
+        if order == "krylov":
+            api.ktebd_step(h, [ch], wl.dt, 1, wl.eps_local, 20, 1e-10, n_used=n_used)
+        else:
+            api.tebd_step(h, [ch], order, wl.dt, 1, wl.eps_local)
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
@@ -364,6 +372,9 @@ def bench_sweep(args):
     print(f"[bench] sweep step {t_sweep:.2f}s", file=sys.stderr, flush=True)
     t_eo = timed(2)
     print(f"[bench] even/odd step {t_eo:.2f}s", file=sys.stderr, flush=True)
+    t_kry = timed("krylov")
+    print(f"[bench] Krylov sweep step {t_kry:.2f}s", file=sys.stderr, flush=True)
+    nu = n_used.cpu().numpy()
     code, word = h.device_status()
     L = spec.L
     upd_sweep, upd_eo = 2 * (L - 1), sum(len(range(p, L - 1, 2)) for p in (0, 1, 0))
@@ -376,6 +387,9 @@ def bench_sweep(args):
                                "TEBD4 XXZ L=64 chi_max=256 state", "updates_per_step": upd_sweep},
         "even_odd_tebd2": {"updates_per_s": round(upd_eo / t_eo, 2), "ms_per_step": round(t_eo * 1e3, 3),
                            "updates_per_step": upd_eo},
+        "krylov_sweep": {"updates_per_s": round(upd_sweep / t_kry, 2), "ms_per_step": round(t_kry * 1e3, 3),
+                         "n_max": 20, "tol": 1e-10, "krylov_vectors_mean": round(float(nu.mean()), 3),
+                         "krylov_vectors_max": int(nu.max())},
         "device_status": [code, word],
     }
     print(json.dumps(out))

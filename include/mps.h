@@ -82,7 +82,8 @@ mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
  * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,
  * 3 = right write-back, 4 = left write-back GEMM, 5 = Jacobi preparation,
- * 6 = propagators.  total_ms = summed event durations, launches = count,
+ * 6 = propagators, 7 = Krylov-TEBD propagators (identity theta build,
+ * reduced matrix, local Lanczos).  total_ms = summed event durations, launches = count,
  * work = useful flops counted on the device (kernels 0, 1 and 4; else 0).
  * Synchronises `stream`.  reset != 0 clears all classes afterwards. */
 mps_status mps_kernel_stats(mps_handle h, mps_stream stream, int32_t kernel, double* total_ms,
@@ -175,6 +176,41 @@ typedef struct {
 mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
                          int32_t n_chains, int32_t order, double dt, int32_t n_steps,
                          double eps_local, uint32_t flags);
+
+/*
+ * n_steps Krylov-TEBD steps on every chain (Sec. "Sornborger-Stewart
+ * decomposition" with the local Krylov propagation of App. "Details of the
+ * Krylov method"): the sweep of order 0 above, where each update propagates
+ * the two-site tensor theta' = lam_b B_b B_{b+1} (the orthogonality centre is
+ * inside the two sites) with the Lanczos approximation of exp(-i dt/2 h_b),
+ * h_b acting on the two physical indices, instead of the exact propagator:
+ * v_1 = theta'/|theta'|, r = h_b v_j, alpha_j = Re<v_j|r>,
+ * r -= alpha_j v_j + beta_{j-1} v_{j-1}, two passes of full Gram-Schmidt,
+ * beta_j = |r|, u = exp(-i tau T_j) e_1, err_j = |theta'| beta_j |u_j|; stop
+ * when err_j <= tol or beta_j <= 1e-14 |theta'|, else after n_max vectors
+ * (then MPS_DEV_NOCONV_LANCZOS is set in the device status word).  The
+ * iteration runs in FP64 on the d^2 x d^2 reduced matrix of theta' (every
+ * Krylov vector is a polynomial in h_b applied to theta'); the resulting
+ * polynomial propagator then takes the path of a gate (theta~ build on MFMA,
+ * FP64 SVD with eps_local / chi_max, Hastings write-back).
+ *   chains     : HOST array of n_chains descriptors as for mps_tebd_step
+ *   n_max      : 1..32 Krylov vectors per update;  tol >= 0
+ *   flags      : MPS_FLAG_GRAPH, MPS_FLAG_FIXED_SWEEPS, MPS_FLAG_PLAIN as above
+ *   n_used_dev : optional device int32 [n_chains][2 (L_max - 1)]; entry
+ *                [c][j] receives the vectors used by sweep position j of the
+ *                last step (j < L_max - 1: bond j left to right; j >= L_max - 1:
+ *                bond L_c - 2 - (j - L_max + 1) right to left); positions a
+ *                shorter chain does not have are left untouched
+ * Between two calls every B is right-canonical and lam_0 B_0 B_1 ... is the
+ * state.  With an approximate propagator (not converged to an invariant
+ * subspace) lam on a bond updated earlier in the right-to-left half differs
+ * from the final Schmidt spectrum by the size of the Krylov error; the next
+ * step does not read those values.
+ * Errors: as mps_tebd_step; MPS_ERR_INVALID for n_max outside 1..32 or tol < 0.
+ */
+mps_status mps_ktebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                          int32_t n_chains, double dt, int32_t n_steps, double eps_local,
+                          int32_t n_max, double tol, uint32_t flags, int32_t* n_used_dev);
 
 /*
  * Observables of a Hastings-form chain (Sec. "Observables",

@@ -57,7 +57,8 @@ class Handle:
     def reserve(self, nbytes: int):
         self.check(lib().mps_reserve(self.h, C.c_size_t(nbytes)))
 
-    KERNELS = {"theta": 0, "jac_round": 1, "select": 2, "wb_right": 3, "gemm": 4, "prep": 5, "gates": 6}
+    KERNELS = {"theta": 0, "jac_round": 1, "select": 2, "wb_right": 3, "gemm": 4, "prep": 5, "gates": 6,
+               "krylov": 7}
 
     def kernel_stats(self, kernel: str, reset=False):
         """(total_ms, launches, useful_flops) of a kernel class (timing on via set_option(3, 1))."""
@@ -151,6 +152,20 @@ def tebd_step(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_steps
               flags: int = 0):
     arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
     h.check(lib().mps_tebd_step(h.h, _stream(), arr, len(chains), order, float(dt), n_steps, float(eps), flags))
+
+
+def ktebd_step(h: Handle, chains: Sequence[Chain], dt: float, n_steps: int, eps: float, n_max: int = 20,
+               tol: float = 1e-10, flags: int = 0, n_used=None):
+    """Krylov TEBD steps (the sweep with the local Lanczos exponential of every
+    bond term).  n_used: optional int32 device tensor [n_chains][2 (L_max-1)]
+    receiving the Krylov vectors used by each update of the last step."""
+    arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
+    if n_used is not None:
+        l_max = max(c.L for c in chains)
+        if n_used.dtype != torch.int32 or n_used.numel() < len(chains) * 2 * (l_max - 1) or not n_used.is_contiguous():
+            raise ValueError("n_used must be a contiguous int32 tensor of n_chains * 2 (L_max - 1) entries")
+    h.check(lib().mps_ktebd_step(h.h, _stream(), arr, len(chains), float(dt), n_steps, float(eps), int(n_max),
+                                 float(tol), flags, _ptr(n_used)))
 
 
 def observe(h: Handle, chain: Chain, op1=None, op2=None, per_bond=False, entropy=False):

@@ -351,15 +351,31 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
   return tebd_impl(h, stream, chains, n_chains, order, dt, n_steps, eps_local, flags, 0, 1 << 30);
 }
 
+mps_status mps_ktebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
+                          double dt, int32_t n_steps, double eps_local, int32_t n_max, double tol, uint32_t flags,
+                          int32_t* n_used_dev) {
+  KryOpts k;
+  k.n_max = n_max;
+  k.tol = tol;
+  k.n_used_dev = n_used_dev;
+  return tebd_impl(h, stream, chains, n_chains, 0, dt, n_steps, eps_local, flags, 0, 1 << 30, &k);
+}
+
 }  // extern "C"
 
 // Runs n_steps steps; only layers lo <= index < hi of each step are applied
 // (all of them for the public entry point).
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
-                     double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi) {
+                     double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi,
+                     const KryOpts* kry) {
   if (!h) return MPS_ERR_INVALID;
   if (!chains || n_chains < 1) return mps_fail(h, MPS_ERR_INVALID, "need at least one chain");
   if (order != 0 && order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 0, 2 or 4");
+  if (kry) {
+    if (order != 0) return mps_fail(h, MPS_ERR_INVALID, "Krylov propagation runs on the sweep (order 0)");
+    if (kry->n_max < 1 || kry->n_max > 32) return mps_fail(h, MPS_ERR_INVALID, "n_max must be in 1..32");
+    if (!(kry->tol >= 0.0)) return mps_fail(h, MPS_ERR_INVALID, "tol must be >= 0");
+  }
   if (n_steps < 0) return mps_fail(h, MPS_ERR_INVALID, "n_steps < 0");
   if (!(dt == dt) || !(eps_local == eps_local)) return mps_fail(h, MPS_ERR_INVALID, "NaN argument");
   if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS | MPS_FLAG_PLAIN))
@@ -453,6 +469,18 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   size_t oUnc = p.take<int32_t>(8);
   size_t oRow = p.take<int32_t>(max_items * m_cap);
   size_t oNrm = p.take<double>(max_items * m_cap);
+  // Krylov propagation: identity propagator, one propagator per chain, a job
+  // per item, rho partials and Krylov histories per item of a layer
+  const int kt_nblk = 32;
+  const size_t kt_hist = kry ? (size_t)2 * (kry->n_max + 1) * dd * dd : 0;
+  size_t oKId = 0, oKG = 0, oKJobs = 0, oKPart = 0, oKHist = 0;
+  if (kry) {
+    oKId = p.take<double2>((size_t)dd * dd);
+    oKG = p.take<double2>((size_t)n_chains * dd * dd);
+    oKJobs = p.take<KryJob>((n_par[0] + n_par[1]) * 2);
+    oKPart = p.take<double2>((size_t)n_chains * kt_nblk * dd * dd);
+    oKHist = p.take<double2>((size_t)n_chains * kt_hist);
+  }
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
   char* ws = h->ws;
@@ -483,6 +511,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   // class) for the even/odd orders and single sweep layers for order 0.
   const int n_groups = order == 0 ? (int)layers.size() : 2 * n_cls;
   std::vector<BondItem> items;
+  std::vector<KryJob> kjobs;
   std::vector<size_t> start(n_groups), count(n_groups);
   for (int gi = 0; gi < n_groups; ++gi) {
     {
@@ -508,6 +537,18 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
           it.lam_m = ch.lam + (size_t)(b + 1) * ch.chi_max;
           it.chi = ch.chi;
           it.G = (const char*)(ws + oG) + (gate_base[c] + ((size_t)k * (ch.L - 1) + b) * dd * dd) * esz;
+          if (kry) {
+            const size_t li = items.size() - start[gi];   // position inside the layer
+            KryJob kj;
+            std::memset(&kj, 0, sizeof(kj));
+            kj.h = (const double2*)ch.hbond + (size_t)b * dd * dd;
+            kj.part = (double2*)(ws + oKPart) + li * kt_nblk * dd * dd;
+            kj.hist = (double2*)(ws + oKHist) + li * kt_hist;
+            kj.G = ws + oKG + (size_t)c * dd * dd * esz;
+            kj.n_used = kry->n_used_dev ? kry->n_used_dev + (size_t)c * 2 * (l_max - 1) + gi : nullptr;
+            kjobs.push_back(kj);
+            it.G = kj.G;
+          }
           it.disc = ch.disc;
           it.X = (double2*)slot;
           slot += (sq * sizeof(double2) + 255) & ~size_t(255);
@@ -527,6 +568,12 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   }
   st = upload(h, s, ws + oItems, items);
   if (st != MPS_OK) return st;
+  if (kry) {
+    st = upload(h, s, ws + oKJobs, kjobs);
+    if (st != MPS_OK) return st;
+    MPS_TRY_HIP(h, launch_ktebd_identity(s, ws + oKId, dd, c128));
+  }
+  KryJob* dJobs = (KryJob*)(ws + oKJobs);
 
   BondItem* dItems = (BondItem*)(ws + oItems);
   JacMat* mats = (JacMat*)(ws + oMats);
@@ -561,6 +608,16 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
         chi_eff = std::min(chi_cap, std::max(h->host_pinned[2], h->host_pinned[3]));
       }
       const int k_cap = std::min(chi_cap, d * chi_eff);  // kept count <= min(d chi_l, d chi_r)
+      if (kry) {
+        // theta' with the identity, its reduced matrix, the local Lanczos
+        // propagator of the bond term into the item's gate
+        KryJob* kj = dJobs + start[idx] + i0;
+        if (prof) prof_begin(h, s, MPS_K_KRYLOV);
+        MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_eff, c128, nullptr, ws + oKId));
+        MPS_TRY_HIP(h, launch_ktebd_rho(s, it, kj, n, d, kt_nblk));
+        MPS_TRY_HIP(h, launch_ktebd_krylov(s, kj, n, d, kt_nblk, kry->n_max, kry->tol, taus[0], c128, h->status_dev));
+        if (prof) prof_end(h, s, MPS_K_KRYLOV);
+      }
       if (prof) prof_begin(h, s, MPS_K_THETA);
       MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_eff, c128, stats));
       if (prof) prof_end(h, s, MPS_K_THETA);

@@ -19,6 +19,7 @@
 #define MPS_K_GEMM 4
 #define MPS_K_PREP 5
 #define MPS_K_GATES 6
+#define MPS_K_KRYLOV 7
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -58,9 +59,18 @@ int jac_nb(int m);
 mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
                       bool fixed);
 
-// TEBD driver with a layer window (api.hip)
+// Local Krylov propagation of the bond terms (Krylov TEBD)
+struct KryOpts {
+  int n_max;            // Krylov vectors per update, 1..32
+  double tol;           // stop when the a-posteriori estimate is <= tol
+  int32_t* n_used_dev;  // optional [n_chains][2 (L_max - 1)] log of the vectors used
+};
+
+// TEBD driver with a layer window (api.hip); kry != null propagates every
+// bond of the sweep (order 0) with the local Lanczos exponential of h_b
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
-                     double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi);
+                     double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi,
+                     const KryOpts* kry = nullptr);
 
 // kernel timing helpers (host)
 void prof_begin(mps_handle h, hipStream_t s, int id);
@@ -127,6 +137,16 @@ struct BondItem {
   int32_t b, d, chi_max, pad;
 };
 
+// One Krylov-TEBD bond update's propagator job (ktebd.hip).
+struct KryJob {
+  const double2* h;    // bond term [D][D] complex128, D = d*d
+  double2* part;       // [nblk][D][D] partial sums of the reduced matrix rho
+  double2* hist;       // [2][n_max+1][D][D]: Krylov vectors Z_j, then polynomials Q_j(h)
+  void* G;             // output propagator [D][D] in the chain precision
+  int32_t* n_used;     // optional: Krylov vectors used
+  int32_t pad[2];
+};
+
 // One propagator to build: G = exp(-i tau h).
 struct GateJob {
   const double2* h;
@@ -175,7 +195,11 @@ struct GemmProb {
 // ---------------------------------------------------------------------------
 hipError_t launch_gates(hipStream_t s, const GateJob* jobs, int n, int dd);
 hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, bool c128,
-                        unsigned long long* stats);
+                        unsigned long long* stats, const void* G_override = nullptr);
+hipError_t launch_ktebd_identity(hipStream_t s, void* G, int dd, bool c128);
+hipError_t launch_ktebd_rho(hipStream_t s, const BondItem* items, const KryJob* jobs, int n_items, int d, int nblk);
+hipError_t launch_ktebd_krylov(hipStream_t s, const KryJob* jobs, int n_items, int d, int nblk, int n_max, double tol,
+                               double tau, bool c128, uint32_t* status);
 hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
                                  int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status);
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status);

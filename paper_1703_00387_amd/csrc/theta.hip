@@ -17,7 +17,8 @@
 
 template <class T>
 __global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restrict__ items, int d, int TA,
-                                                         int TC, int ntc_cap, unsigned long long* stats) {
+                                                         int TC, int ntc_cap, unsigned long long* stats,
+                                                         const void* __restrict__ G_override) {
   // two staging buffers (A and B tiles each), reused for the output tile
   __shared__ T smem[TBM * (TBN + 1) > 4 * TBK * TLD ? TBM * (TBN + 1) : 4 * TBK * TLD];
   __shared__ T Gs[25 * 25];  // the gate, d <= 5 (the chain limit)
@@ -33,7 +34,8 @@ __global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restr
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int dd = d * d;
-  for (int i = tid; i < dd * dd; i += 256) Gs[i] = ((const T*)it.G)[i];
+  const T* Gsrc = G_override ? (const T*)G_override : (const T*)it.G;
+  for (int i = tid; i < dd * dd; i += 256) Gs[i] = Gsrc[i];
 
   AccTile<T> acc;
   acc_zero<T>(acc);
@@ -129,16 +131,17 @@ __global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restr
   }
 }
 
+// G_override (optional): one propagator used for every item instead of its own.
 hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, bool c128,
-                        unsigned long long* stats) {
+                        unsigned long long* stats, const void* G_override) {
   if (n_items <= 0) return hipSuccess;
   if (d < 1 || d > 5) return hipErrorInvalidValue;
   const int TA = TBM / d, TC = TBN / d;
   const int nta = (chi_cap + TA - 1) / TA, ntc = (chi_cap + TC - 1) / TC;
   dim3 grid(nta * ntc, n_items);
   if (c128)
-    theta_gate_kernel<double2><<<grid, 256, 0, s>>>(items, d, TA, TC, ntc, stats);
+    theta_gate_kernel<double2><<<grid, 256, 0, s>>>(items, d, TA, TC, ntc, stats, G_override);
   else
-    theta_gate_kernel<float2><<<grid, 256, 0, s>>>(items, d, TA, TC, ntc, stats);
+    theta_gate_kernel<float2><<<grid, 256, 0, s>>>(items, d, TA, TC, ntc, stats, G_override);
   return hipGetLastError();
 }
