@@ -54,6 +54,8 @@ def main():
                     help="untimed steps before the timed ones (default 140; 40 for xxz_batch256)")
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--jac-threads", type=int, default=512, choices=[256, 512],
+                    help="threads per Jacobi-round workgroup (two waves per SIMD at 512)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="xxz_batch256: skip the one-bond-per-launch comparison")
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
@@ -91,6 +93,7 @@ def main():
     spec = wl.chains[0]
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
     h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
 
     start_step = 0
@@ -156,6 +159,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "xxz_tebd4_L64: TEBD4 XXZ L=64 Jxy=1 Jz=0.5 Neel dt=0.05 chi_max=256 eps=1e-12",
                    "updates_per_step": updates_per_step, "start_step": start_step,
+                   "jacobi_threads": args.jac_threads,
                    "chi_hist": {"max": int(chi.max()), "mean": round(float(chi.mean()), 1),
                                 "n_at_cap": int((chi >= spec.chi_max).sum())}},
         "roofline": {"kernel": "jac_round_kernel (FP64 block-Jacobi round: Gram + rotation)",
@@ -223,6 +227,7 @@ def bench_heff(args):
     tdt = torch.complex128 if args.dtype == "c128" else torch.complex64
     dev = "cuda"
     h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
     Lenv = _herm_env(chi, w, (31, 1), tdt, dev)
     Renv = _herm_env(chi, w, (31, 2), tdt, dev)
     Wt = torch.from_numpy(np.ascontiguousarray(Wm)).to(tdt).to(dev)
@@ -290,6 +295,7 @@ def bench_grad(args):
     h0 = models.bond_hamiltonians(unit)
     sz = models.sz_operator()
     h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
 
     def fresh():
         return api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec))
@@ -339,6 +345,7 @@ def bench_sweep(args):
     wl = W.xxz_tebd4_L64()
     spec = wl.chains[0]
     h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
     if args.load_state:
         st = torch.load(args.load_state, weights_only=True)
@@ -409,6 +416,7 @@ def bench_batch(args):
 
     wl = W.xxz_batch256()
     h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
     chains = [api.Chain.product(W.initial_vectors(c), c.chi_max, models.bond_hamiltonians(c), dtype=args.dtype)
               for c in wl.chains]
     upd = sum(len(range(0, c.L - 1, 2)) * 2 + len(range(1, c.L - 1, 2)) for c in wl.chains)

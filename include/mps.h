@@ -77,7 +77,9 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * off (0): HIP events around every launch of the timed kernels on the call's
  * stream, plus device counters of the useful work they perform (not inside
  * captured graphs), 4 = sweeps of the 64x64 inner eigensolve per Jacobi block
- * pair (default 1). */
+ * pair (default 1), 5 = threads per Jacobi-round workgroup, 256 (four waves,
+ * one per SIMD) or 512 (default: eight waves, two per SIMD; the Gram and
+ * rotation column work alternates between two groups of four waves). */
 mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
  * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,

@@ -69,7 +69,7 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     // queued schedule cannot see the sizes, so it always starts with it.
     PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
                 launch_jac_round(s, mats, n, 2, 0, h->jac_tol, h->jac_abs, std::max(h->jac_inner_sweeps, kLoopInner),
-                                 max_sweeps, h->profile ? h->stats_dev : nullptr));
+                                 max_sweeps, h->profile ? h->stats_dev : nullptr, h->jac_threads));
     if (nb == 2) {
       MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
       MPS_TRY_HIP(h, launch_jac_flag_noconv(s, unconv, h->status_dev));
@@ -81,7 +81,7 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     if (sw > 0) MPS_TRY_HIP(h, launch_jac_sort(s, mats, n, m_cap));
     for (int r = 0; r < nb - 1; ++r)
       PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs, h->jac_inner_sweeps, 0,
-                                                              h->profile ? h->stats_dev : nullptr));
+                                                              h->profile ? h->stats_dev : nullptr, h->jac_threads));
     MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
     if (!fixed && sw >= 1) {
       if (h->profile) {
@@ -215,6 +215,10 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
     case 4:
       if (!(value >= 1.0 && value <= 64.0)) return mps_fail(h, MPS_ERR_INVALID, "inner sweeps must be in [1,64]");
       h->jac_inner_sweeps = (int)value;
+      return MPS_OK;
+    case 5:
+      if (value != 256.0 && value != 512.0) return mps_fail(h, MPS_ERR_INVALID, "Jacobi threads must be 256 or 512");
+      h->jac_threads = (int)value;
       return MPS_OK;
     default:
       return mps_fail(h, MPS_ERR_INVALID, "unknown option");

@@ -36,6 +36,7 @@ struct mps_context {
   double jac_abs = 1e-15;      // absolute tolerance, relative to |theta|_F^2
   int jac_max_sweeps = 30;
   int jac_inner_sweeps = 1;    // sweeps of the 64x64 inner eigensolve per block pair
+  int jac_threads = 512;       // threads per Jacobi-round workgroup (256 or 512)
   // pinned host scratch for small readbacks
   int32_t* host_pinned = nullptr;
   // optional per-kernel timing with HIP events on the launch stream
@@ -204,7 +205,8 @@ hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* m
                                  int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status);
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status);
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round,
-                            double tol, double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats);
+                            double tol, double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
+                            int threads);
 hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged);
 hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap);
 hipError_t launch_jac_flag_noconv(hipStream_t s, const int32_t* unconverged, uint32_t* status);

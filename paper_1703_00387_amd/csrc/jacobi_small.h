@@ -1,5 +1,5 @@
 // Cyclic parallel Jacobi eigensolver for a Hermitian matrix of order <= N
-// (N = 32 or 64) held in LDS, run by one 256-thread workgroup, in FP64.
+// (N = 32 or 64) held in LDS, run by one workgroup of NT (256 or 512) threads, in FP64.
 //
 // G  : [N][LD] complex128 in LDS (LD >= N, default N+1), overwritten with Q^dag G Q
 // Q  : [N][LD] complex128 in LDS, overwritten with the accumulated unitary
@@ -46,8 +46,8 @@ __device__ __forceinline__ bool js_pair(int step, int k, int& p, int& q) {
   return oe_pair(N, step, k, p, q);
 }
 
-// Returns the number of sweeps used (<= max_sweeps).  Exactly 256 threads call it.
-template <int N, int LD = N + 1>
+// Returns the number of sweeps used (<= max_sweeps).  Exactly NT threads call it.
+template <int N, int LD = N + 1, int NT = 256>
 __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double rel_thr, int max_sweeps,
                            double4* rot /* LDS [N/2] */, int* flag /* LDS */) {
   constexpr int NP = N / 2;
@@ -93,14 +93,14 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
       // (row, p_k), (row, q_k); the lanes of a wave take consecutive rows of
       // one pair, so their LDS accesses fall in distinct banks.  All loads of
       // a thread are issued before its arithmetic.
-      constexpr int IT = (N * NP + 255) / 256;
+      constexpr int IT = (N * NP + NT - 1) / NT;
       {
         double4 rr[IT];
         int pp[IT], qq_[IT], row_[IT];
         double2 gp[IT], gq[IT], qp[IT], qv[IT];
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
-          const int it = tid + 256 * u;
+          const int it = tid + NT * u;
           const int k = it / N, row = it % N;
           row_[u] = row;
           rr[u] = rot[k];
@@ -134,7 +134,7 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
         double2 gp[IT], gq[IT];
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
-          const int it = tid + 256 * u;
+          const int it = tid + NT * u;
           const int k = it / N, col = it % N;
           col_[u] = col;
           rr[u] = rot[k];

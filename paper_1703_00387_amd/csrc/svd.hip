@@ -176,13 +176,45 @@ __device__ __forceinline__ void herm_acc_to_lds(const HermAcc& acc, double2* Gs,
   }
 }
 
+// Add a Hermitian partial Gram (same tile split) into the LDS matrix.
+__device__ __forceinline__ void herm_acc_add_lds(const HermAcc& acc, double2* Gs, int ldg, const int* ti,
+                                                 const int* tj, int nt, int lane) {
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    if (u >= nt) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ti[u] * 16 + Cx<double2>::acc_row(lane, r);
+      const int col = tj[u] * 16 + (lane & 15);
+      const double re = acc.re[u][r], im = acc.im[u][r];
+      double2 g = Gs[row * ldg + col];
+      Gs[row * ldg + col] = make_double2(g.x + re, g.y + im);
+      if (ti[u] != tj[u]) {
+        g = Gs[col * ldg + row];
+        Gs[col * ldg + row] = make_double2(g.x + re, g.y - im);
+      }
+    }
+  }
+}
+
 // One round of the block Jacobi (loop_sweeps == 0), or, for matrices of one
 // 64-row panel (nb == 2), up to loop_sweeps complete sweeps in one launch
 // (loop_sweeps > 0): the panel's only pair is re-formed, solved and rotated
 // until it is orthogonal, with no launch or host round trip per sweep.
-__global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
-                                                        double abs_tol, int inner_sweeps, int loop_sweeps,
-                                                        unsigned long long* stats) {
+// NT = 256 (four waves) or 512 threads.  With 512 the waves form two groups
+// of four: the Gram's 16-column chunks and the rotation's 64-column blocks
+// alternate between the groups (each with its own two staging buffers), the
+// two partial Grams are summed in LDS, and the LDS eigensolve uses all eight
+// waves, so every SIMD holds two waves.
+template <int NT>
+__global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
+                                                       double abs_tol, int inner_sweeps, int loop_sweeps,
+                                                       unsigned long long* stats) {
+  constexpr int NG = NT / 256;  // wave groups
+  // chunks in flight per thread in the Gram and rotation loops: with two
+  // waves per SIMD one is enough (measured: 233 us against 250 us for three
+  // at chi = 256), and it leaves more registers
+  constexpr int kPf = NG > 1 ? 1 : ::kPf;
   // Both arrays hold a [JP][JP+1] matrix (4160 elements) or four staging
   // buffers of [TBK][TLD] (4352 elements); sized for the larger.
   constexpr int kLdsElems = (JP * (JP + 1) > 4 * TBK * TLD) ? JP * (JP + 1) : 4 * TBK * TLD;
@@ -205,7 +237,9 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
     I = 0;
     J = 1;
   }
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // group, thread and wave inside the group (constants for one group)
+  const int grp = NG > 1 ? tid >> 8 : 0, gtid = NG > 1 ? tid & 255 : tid, wave = gtid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   if (tid < JP) {
     int g = (tid < JB) ? I * JB + tid : J * JB + (tid - JB);
@@ -222,14 +256,17 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   // already in flight in registers, so the loads of one panel overlap its
   // multiplies.
   {
-    double2* Bs0 = Q;
-    double2* Bs1 = Q + TBK * TLD;
-    const int i = tid >> 2, kq = (tid & 3) * 4;
+    // group grp takes the chunks ci = lc * NG + grp, lc = 0 .. nloc-1
+    double2* Bs0 = Q + grp * 2 * TBK * TLD;
+    double2* Bs1 = Bs0 + TBK * TLD;
+    const int i = gtid >> 2, kq = (gtid & 3) * 4;
     const int gi = rows_s[i];
     const double2* xr = X + (size_t)(gi >= 0 ? gi : 0) * ld;
     const int nch = (n + TBK - 1) / TBK;
+    const int nloc = (nch - grp + NG - 1) / NG, nloc_max = (nch + NG - 1) / NG;
     double2 v[kPf][4];
-    auto load = [&](int ci, double2* dst) {
+    auto load = [&](int lc, double2* dst) {
+      const int ci = lc * NG + grp;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         int c = ci * TBK + kq + e;
@@ -242,28 +279,36 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
     };
 #pragma unroll
     for (int u = 0; u < kPf; ++u)
-      if (u < nch) load(u, v[u]);
-    store(Bs0, v[0]);
+      if (u < nloc) load(u, v[u]);
+    if (nloc > 0) store(Bs0, v[0]);
     __syncthreads();
     // G is Hermitian: only its 10 upper 16x16 tiles are formed (3, 3, 2 and 2
-    // per wave) and the lower ones are written as their conjugate transposes.
+    // per wave of a group) and the lower ones are written as their conjugate
+    // transposes.
     int ti[3], tj[3], nt;
     gram_tiles(wave, ti, tj, nt);
     HermAcc hacc;
     herm_acc_zero(hacc);
-    for (int base = 0; base < nch; base += kPf) {
+    // every thread passes the same barriers: nloc_max iterations for both groups
+    for (int base = 0; base < nloc_max; base += kPf) {
 #pragma unroll
       for (int u = 0; u < kPf; ++u) {
-        const int ci = base + u;
-        if (ci < nch) {
-          if (ci + kPf < nch) load(ci + kPf, v[u]);  // chunk ci's registers were staged already
-          herm_mma_chunk((ci & 1) ? Bs1 : Bs0, hacc, ti, tj, nt, lane);
-          if (ci + 1 < nch) store((ci & 1) ? Bs0 : Bs1, v[(u + 1) % kPf]);
+        const int lc = base + u;
+        if (lc < nloc_max) {
+          if (lc < nloc) {
+            if (lc + kPf < nloc) load(lc + kPf, v[u]);  // chunk lc's registers were staged already
+            herm_mma_chunk((lc & 1) ? Bs1 : Bs0, hacc, ti, tj, nt, lane);
+            if (lc + 1 < nloc) store((lc & 1) ? Bs0 : Bs1, v[(u + 1) % kPf]);
+          }
           __syncthreads();
         }
       }
     }
-    herm_acc_to_lds(hacc, G, JP + 1, ti, tj, nt, lane);
+    if (grp == 0) herm_acc_to_lds(hacc, G, JP + 1, ti, tj, nt, lane);
+    if (NG > 1) {
+      __syncthreads();
+      if (grp == 1) herm_acc_add_lds(hacc, G, JP + 1, ti, tj, nt, lane);
+    }
   }
   __syncthreads();
 
@@ -272,7 +317,7 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   // abs_tol |X|_F^2): the absolute floor bounds the error of every squared
   // singular value by about abs_tol |X|_F^2 and guarantees termination.
   const double abs_thr = abs_tol * M->fro2;
-  for (int e = tid; e < JP * JP; e += 256) {
+  for (int e = tid; e < JP * JP; e += NT) {
     int r = e / JP, c = e % JP;
     if (r < c) {
       double2 g = G[r * (JP + 1) + c];
@@ -295,14 +340,14 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   if (loop_sweeps > 0 && m <= JB) {
     // a matrix of at most 32 rows: the 32x32 solve on the leading block (the
     // other rows are zero), Q the identity elsewhere
-    herm_jacobi<JB, JP + 1>(G, Q, JB, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
-    for (int e = tid; e < JP * JP; e += 256) {
+    herm_jacobi<JB, JP + 1, NT>(G, Q, JB, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
+    for (int e = tid; e < JP * JP; e += NT) {
       const int i = e / JP, j = e % JP;
       if (i >= JB || j >= JB) Q[i * (JP + 1) + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
   } else {
-    herm_jacobi<JP>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
+    herm_jacobi<JP, JP + 1, NT>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
   }
   // the rotated rows have squared norms diag(Q^dag G Q), left on G's diagonal
   if (tid < JP && rows_s[tid] >= 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
@@ -312,14 +357,16 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
   // The A operand Q[p0+k][j] is read in place from LDS; the B operand
   // X[row_{p0+k}][c0+c] is staged (two LDS buffers) with kPf steps in flight.
   {
-    double2* Bs0 = G;
-    double2* Bs1 = G + TBK * TLD;
-    const int k = tid >> 4, q4 = (tid & 15) * 4;
+    // group grp takes the column blocks cb = lb * NG + grp, lb = 0 .. nlb-1
+    double2* Bs0 = G + grp * 2 * TBK * TLD;
+    double2* Bs1 = Bs0 + TBK * TLD;
+    const int k = gtid >> 4, q4 = (gtid & 15) * 4;
     constexpr int PCH = JP / TBK;  // p-chunks per column block
-    const int nsteps = ((n + TBN - 1) / TBN) * PCH;
+    const int ncb = (n + TBN - 1) / TBN;
+    const int nsteps = ((ncb - grp + NG - 1) / NG) * PCH, nsteps_max = ((ncb + NG - 1) / NG) * PCH;
     double2 v[kPf][4];
     auto load = [&](int st, double2* dst) {
-      const int c0 = (st / PCH) * TBN, p0 = (st % PCH) * TBK;
+      const int c0 = ((st / PCH) * NG + grp) * TBN, p0 = (st % PCH) * TBK;
       const int g = rows_s[p0 + k];
       const double2* xr = X + (size_t)(g >= 0 ? g : 0) * ld;
 #pragma unroll
@@ -335,16 +382,18 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
 #pragma unroll
     for (int u = 0; u < kPf; ++u)
       if (u < nsteps) load(u, v[u]);
-    store(Bs0, v[0]);
+    if (nsteps > 0) store(Bs0, v[0]);
     __syncthreads();
     AccTile<double2> acc;
     acc_zero<double2>(acc);
-    for (int base = 0; base < nsteps; base += kPf) {
+    // every thread passes the same barriers: nsteps_max iterations for both groups
+    for (int base = 0; base < nsteps_max; base += kPf) {
 #pragma unroll
       for (int u = 0; u < kPf; ++u) {
         const int st = base + u;
-        if (st < nsteps) {
-          const int c0 = (st / PCH) * TBN, p0 = (st % PCH) * TBK;
+        if (st < nsteps_max) {
+          if (st < nsteps) {
+          const int c0 = ((st / PCH) * NG + grp) * TBN, p0 = (st % PCH) * TBK;
           if (st + kPf < nsteps) load(st + kPf, v[u]);
           mma_chunk_lda<double2>(Q + p0 * (JP + 1), JP + 1, (st & 1) ? Bs1 : Bs0, acc, wm, wn, lane);
           if (p0 + TBK == JP) {
@@ -365,6 +414,7 @@ __global__ __launch_bounds__(256) void jac_round_kernel(JacMat* __restrict__ mat
             acc_zero<double2>(acc);
           }
           if (st + 1 < nsteps) store((st & 1) ? Bs0 : Bs1, v[(u + 1) % kPf]);
+          }
           __syncthreads();
         }
       }
@@ -679,10 +729,16 @@ hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32
 }
 
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round, double tol,
-                            double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats) {
+                            double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
+                            int threads) {
   if (n_mats <= 0) return hipSuccess;
   dim3 grid(nb_cap / 2, n_mats);
-  jac_round_kernel<<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats);
+  if (threads == 512)
+    jac_round_kernel<512><<<grid, 512, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats);
+  else if (threads == 256)
+    jac_round_kernel<256><<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
