@@ -84,25 +84,27 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
         rot[tid] = r;
       }
       __syncthreads();
-      // G <- J^dag G J on 2x2 pair blocks.  With pairs A = (pA, qA) and
-      // B = (pB, qB) of this step, block (A, B) becomes J_A^dag G_AB J_B
-      // (columns first, then rows).  Only blocks with A <= B are computed; the
-      // block (B, A) is written as the conjugate transpose, which keeps G
-      // exactly Hermitian.  Q <- Q J in the same pass (no dependency).
-      // Columns: G <- G J and Q <- Q J.  Item (k, row) updates entries
-      // (row, p_k), (row, q_k); the lanes of a wave take consecutive rows of
-      // one pair, so their LDS accesses fall in distinct banks.  All loads of
-      // a thread are issued before its arithmetic.
-      constexpr int IT = (N * NP + NT - 1) / NT;
-      {
-        double4 rr[IT];
-        int pp[IT], qq_[IT], row_[IT];
-        double2 gp[IT], gq[IT], qp[IT], qv[IT];
+      // G <- J^dag G J with the rotations of this step (disjoint pairs):
+      // first the columns, G <- G J and Q <- Q J, then the rows, G <- J^dag G.
+      // Item (k, row) of the column pass updates entries (row, p_k) and
+      // (row, q_k); the lanes of a wave take consecutive rows of one pair, so
+      // their LDS accesses fall in distinct banks.  Item u of a thread is pair
+      // k = tid / N + u NT / N at row (or column) tid % N (NT is a multiple of
+      // N).  Items go in batches of UB, every load of a batch issued before
+      // its arithmetic; with two waves per SIMD, batches of two keep the
+      // registers within the halved budget.
+      static_assert(NT % N == 0, "thread count must be a multiple of the order");
+      constexpr int IT = N * NP / NT, KS = NT / N;
+      constexpr int UB = NT >= 512 ? (IT < 2 ? IT : 2) : IT;
+      const int row = tid % N, k0 = tid / N;
 #pragma unroll
-        for (int u = 0; u < IT; ++u) {
-          const int it = tid + NT * u;
-          const int k = it / N, row = it % N;
-          row_[u] = row;
+      for (int u0 = 0; u0 < IT; u0 += UB) {
+        double4 rr[UB];
+        int pp[UB], qq_[UB];
+        double2 gp[UB], gq[UB], qp[UB], qv[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int k = k0 + (u0 + u) * KS;
           rr[u] = rot[k];
           if (!js_pair<N>(step, k, pp[u], qq_[u])) rr[u].y = 0.0;
           if (rr[u].y != 0.0) {
@@ -113,11 +115,10 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
           }
         }
 #pragma unroll
-        for (int u = 0; u < IT; ++u) {
+        for (int u = 0; u < UB; ++u) {
           const double4 r = rr[u];
           if (r.y == 0.0) continue;
           const double2 em = make_double2(r.z, -r.w);  // e^{-i phi}
-          const int row = row_[u];
           double2 gqe = cmul(gq[u], em), qqe = cmul(qv[u], em);
           G[row * LD + pp[u]] = make_double2(r.x * gp[u].x - r.y * gqe.x, r.x * gp[u].y - r.y * gqe.y);
           G[row * LD + qq_[u]] = make_double2(r.y * gp[u].x + r.x * gqe.x, r.y * gp[u].y + r.x * gqe.y);
@@ -128,15 +129,15 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
       __syncthreads();
       // Rows: G <- J^dag G, item (k, col); the rotated pair's own entries are
       // set exactly (zero coupling, real diagonal) so rounding does not build up.
-      {
-        double4 rr[IT];
-        int pp[IT], qq_[IT], col_[IT];
-        double2 gp[IT], gq[IT];
+      const int col = tid % N;
 #pragma unroll
-        for (int u = 0; u < IT; ++u) {
-          const int it = tid + NT * u;
-          const int k = it / N, col = it % N;
-          col_[u] = col;
+      for (int u0 = 0; u0 < IT; u0 += UB) {
+        double4 rr[UB];
+        int pp[UB], qq_[UB];
+        double2 gp[UB], gq[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int k = k0 + (u0 + u) * KS;
           rr[u] = rot[k];
           if (!js_pair<N>(step, k, pp[u], qq_[u])) rr[u].y = 0.0;
           if (rr[u].y != 0.0) {
@@ -145,11 +146,10 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
           }
         }
 #pragma unroll
-        for (int u = 0; u < IT; ++u) {
+        for (int u = 0; u < UB; ++u) {
           const double4 r = rr[u];
           if (r.y == 0.0) continue;
           const double2 ep = make_double2(r.z, r.w);  // e^{+i phi}
-          const int col = col_[u];
           double2 gqe = cmul(gq[u], ep);
           double2 np_ = make_double2(r.x * gp[u].x - r.y * gqe.x, r.x * gp[u].y - r.y * gqe.y);
           double2 nq_ = make_double2(r.y * gp[u].x + r.x * gqe.x, r.y * gp[u].y + r.x * gqe.y);
