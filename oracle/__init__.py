@@ -23,6 +23,8 @@ krylov      Lanczos exponential (Sec. Krylov time evolution, App. Krylov)
 tdvp        environments, structured H_eff apply, two-site TDVP (Sec. TDVP)
 ktebd       Krylov TEBD: the Sornborger-Stewart sweep with the Lanczos
             exponential of every bond term (App. Details of the Krylov method)
+timedep     time-dependent Hamiltonians: commutator-free Magnus expansions
+            (midpoint rule, fourth-order two-exponential scheme) over Trotter steps
 grad        reverse-mode gradient of TEBD2 with truncated-SVD backward, the
             exact-diagonalisation adjoint gradient, finite differences
 """
