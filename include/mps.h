@@ -215,6 +215,36 @@ mps_status mps_ktebd_step(mps_handle h, mps_stream stream, const mps_chain_desc*
                           int32_t n_max, double tol, uint32_t flags, int32_t* n_used_dev);
 
 /*
+ * n_steps steps of a time-dependent Hamiltonian H(t) = sum_k f_k(t) H_k
+ * (Sec. "Time evolution methods": time ordering by commutator-free Magnus
+ * expansions).  Step n covers [t_n, t_n + dt] with t_n = t0 + n dt and is a
+ * product of exponentials of linear combinations of H at the nodes
+ * t_n + c_j dt:
+ *   scheme 2 (the paper's default): one node c = 1/2, U = exp(-i dt H(t_n + dt/2));
+ *   scheme 4: nodes c_{1,2} = 1/2 -+ sqrt(3)/6, weights a_1 = (3 - 2 sqrt 3)/12,
+ *             a_2 = (3 + 2 sqrt 3)/12; first exp(-i dt (a_2 H_1 + a_1 H_2)), then
+ *             exp(-i dt (a_1 H_1 + a_2 H_2)), H_j = H(t_n + c_j dt).
+ * Every exponential exp(-i dt A), A = sum_k w_k H_k, is one Trotter step of
+ * `order` as in mps_tebd_step (2, 4, or 0 for the sweep) with bond
+ * Hamiltonians h_b = sum_k w_k h_b^(k), formed on the device.
+ *   chains  : HOST array of descriptors as for mps_tebd_step, except that
+ *             hbond holds every term: complex128 [n_terms][L-1][d*d][d*d]
+ *   n_terms : 1..16;  scheme : 2 or 4 (mps_cfme_nodes gives the nodes)
+ *   f_nodes : HOST FP64 [n_steps][n_nodes][n_terms], f_k(t_n + c_j dt)
+ *   hwork   : DEVICE complex128 [sum_c (L_c - 1)][d*d][d*d], caller-owned
+ *             scratch for the combined bond Hamiltonians
+ * Errors: MPS_ERR_INVALID for a bad scheme or term count, null or
+ * non-finite f_nodes, null hwork; otherwise as mps_tebd_step.
+ */
+mps_status mps_tebd_td_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                            int32_t n_chains, int32_t order, double dt, int32_t n_steps,
+                            double eps_local, uint32_t flags, int32_t n_terms, int32_t scheme,
+                            const double* f_nodes, void* hwork);
+/* The nodes c_j of a scheme (host only): nodes[0..n_nodes-1]; MPS_ERR_INVALID
+ * for an unknown scheme. */
+mps_status mps_cfme_nodes(int32_t scheme, double* nodes, int32_t* n_nodes);
+
+/*
  * Observables of a Hastings-form chain (Sec. "Observables",
  * reduced density matrices of Eq. reducedrho):
  *   site_out[i] = Re sum lam_i[a]^2 conj(B_i[a,s',c]) op1[s',s] B_i[a,s,c]

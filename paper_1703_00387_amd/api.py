@@ -168,6 +168,35 @@ def ktebd_step(h: Handle, chains: Sequence[Chain], dt: float, n_steps: int, eps:
                                  float(tol), flags, _ptr(n_used)))
 
 
+def cfme_nodes(scheme: int):
+    """Nodes c_j of a commutator-free Magnus scheme (2 or 4)."""
+    nodes = (C.c_double * 2)()
+    n = C.c_int32(0)
+    if lib().mps_cfme_nodes(int(scheme), nodes, C.byref(n)) != _lib.MPS_OK:
+        raise ValueError(f"unknown commutator-free Magnus scheme {scheme}")
+    return np.array(nodes[:n.value])
+
+
+def tebd_td_step(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_steps: int, eps: float,
+                 f_nodes, scheme: int = 2, flags: int = 0):
+    """Time-dependent steps; every chain's hbond holds its term split
+    [n_terms][L-1][d*d][d*d] and f_nodes[n][j][k] = f_k(t_n + c_j dt)."""
+    f = np.ascontiguousarray(f_nodes, dtype=np.float64)
+    if f.ndim != 3 or f.shape[0] != n_steps:
+        raise ValueError("f_nodes must be [n_steps][n_nodes][n_terms]")
+    n_terms = f.shape[2]
+    total = 0
+    for c in chains:
+        dd = c.d * c.d
+        if c.hbond.numel() != n_terms * (c.L - 1) * dd * dd:
+            raise ValueError("chain hbond must hold n_terms bond-term sets")
+        total += (c.L - 1) * dd * dd
+    hwork = torch.empty(total, dtype=torch.complex128, device=chains[0].B.device)
+    arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
+    h.check(lib().mps_tebd_td_step(h.h, _stream(), arr, len(chains), order, float(dt), n_steps, float(eps), flags,
+                                   n_terms, int(scheme), f.ctypes.data_as(C.c_void_p), _ptr(hwork)))
+
+
 def observe(h: Handle, chain: Chain, op1=None, op2=None, per_bond=False, entropy=False):
     dev = chain.B.device
     site = torch.zeros(chain.L, dtype=torch.float64, device=dev) if op1 is not None else None

@@ -1,9 +1,10 @@
 """The C-ABI library loads and exports every symbol include/mps.h declares
-(no compute call: runs without a GPU)."""
+(no device call: runs without a GPU)."""
 import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -42,3 +43,13 @@ def test_product_package_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dp, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", src, re.M), f
+
+
+def test_cfme_nodes_match_the_scheme_definition():
+    """Host-only query of the commutator-free Magnus nodes (no GPU needed)."""
+    from oracle import timedep
+    from paper_1703_00387_amd import api
+    for scheme in (2, 4):
+        np.testing.assert_allclose(api.cfme_nodes(scheme), timedep.SCHEMES[scheme][0], rtol=0, atol=1e-15)
+    with pytest.raises(ValueError):
+        api.cfme_nodes(3)
