@@ -61,7 +61,7 @@ def main():
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
     ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256", "bh_heff_chi512", "xxz_grad_L32",
-                             "xxz_sweep_L64"])
+                             "xxz_sweep_L64", "tfim_quench_L64"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -76,7 +76,7 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.warmup is None:
-        args.warmup = {"xxz_batch256": 40}.get(args.workload, 140)
+        args.warmup = {"xxz_batch256": 40, "tfim_quench_L64": 150}.get(args.workload, 140)
 
     import workloads as W
     from paper_1703_00387_amd import api, models
@@ -89,6 +89,8 @@ def main():
         return bench_grad(args)
     if args.workload == "xxz_sweep_L64":
         return bench_sweep(args)
+    if args.workload == "tfim_quench_L64":
+        return bench_quench(args)
     wl = W.xxz_tebd4_L64()
     spec = wl.chains[0]
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
@@ -325,6 +327,73 @@ def bench_grad(args):
         "gradient_s": round(t_grad, 3), "forward_only_s": round(t_fwd, 3),
         "adjoint_over_forward": round(t_grad / t_fwd, 2), "loss": float(loss),
         "grad_norm": float(torch.linalg.vector_norm(dJ)), "device_status": [code, word],
+    }
+    print(json.dumps(out))
+    h.close()
+
+
+def bench_quench(args):
+    """A transverse-field Ising ramp through the critical point,
+    H(t) = -sum sz sz - g(t) sum sx, g(t) = 1.5 - t/3, on L=64 from all up,
+    chi_max=128: TEBD4 steps with the fourth-order commutator-free Magnus
+    scheme (two exponentials, 30 layers per step).  After the untimed
+    steps, the timed steps are compared with as many TEBD4 steps of the
+    Hamiltonian frozen at the same time, from the same state."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1703_00387_amd import api, models
+
+    L, chi_max, dt = 64, 128, 0.02
+    hz = models.bond_hamiltonians(W.tfim_chain(L, chi_max, 1.0, 0.0))
+    hf = [a - b for a, b in zip(models.bond_hamiltonians(W.tfim_chain(L, chi_max, 1.0, 1.0)), hz)]
+    terms = np.ascontiguousarray(np.array([hz, hf]))
+    g = lambda t: 1.5 - t / 3.0
+    nodes = api.cfme_nodes(4)
+    fn = lambda n0, n: np.array([[[1.0, g((k + c) * dt)] for c in nodes] for k in range(n0, n0 + n)])
+    h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
+    spec = W.tfim_chain(L, chi_max, 1.0, 1.5)
+    ch = api.Chain.product(W.initial_vectors(spec), chi_max, terms, dtype=args.dtype)
+    done, t0 = 0, time.time()
+    while done < args.warmup:
+        n = min(10, args.warmup - done)
+        api.tebd_td_step(h, [ch], 4, dt, n, 1e-12, fn(done, n), 4)
+        torch.cuda.synchronize()
+        done += n
+        print(f"[bench] warmup {done}/{args.warmup}, chi_max now {int(ch.chi.max())}, {time.time() - t0:.1f}s",
+              file=sys.stderr, flush=True)
+    start = (ch.B.clone(), ch.lam.clone(), ch.chi.clone(), ch.disc.clone())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.tebd_td_step(h, [ch], 4, dt, args.steps, 1e-12, fn(done, args.steps), 4)
+    torch.cuda.synchronize()
+    t_td = time.perf_counter() - t1
+    chi_end = ch.chi.cpu().numpy()
+    # the same number of TEBD4 steps of H frozen at the start time
+    frozen = api.Chain(ch.L, ch.d, ch.chi_max, start[0], start[1], start[2],
+                       torch.from_numpy(np.ascontiguousarray(np.array(hz) + g(done * dt) * np.array(hf))).cuda(),
+                       start[3])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.tebd_step(h, [frozen], 4, dt, 2 * args.steps, 1e-12)
+    torch.cuda.synchronize()
+    t_fr = time.perf_counter() - t1
+    code, word = h.device_status()
+    upd = sum(len(range(p, L - 1, 2)) for p in (0, 1, 0)) * 5 * 2 * args.steps
+    out = {
+        "metric": "two-site MPS updates/s, time-dependent TEBD4 with the fourth-order commutator-free Magnus scheme "
+                  "(TFIM quench L=64, chi_max=128)",
+        "value": round(upd / t_td, 2), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_td / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "tfim_quench_L64: H(t) = -sum sz sz - (1.5 - t/3) sum sx, L=64, all up, dt=0.02, "
+                               "chi_max=128, eps=1e-12, TEBD4 per exponential, two exponentials per step",
+                   "updates_per_step": upd // args.steps, "chi_max_now": int(chi_end.max()),
+                   "jacobi_threads": args.jac_threads},
+        "frozen_hamiltonian_tebd4": {"updates_per_s": round(upd / t_fr, 2), "steps": 2 * args.steps},
+        "device_status": [code, word],
     }
     print(json.dumps(out))
     h.close()

@@ -111,7 +111,12 @@ mps_status mps_gates(mps_handle h, mps_stream stream, int32_t n, int32_t dd,
  *   theta   : complex128 [m][n] input (not modified), m = chi_l*d_l, n = d_r*chi_r
  *   chi_max : cap on the kept count k
  *   eps     : local tolerance: k = min(chi_max, min{k>=1 : sum_{j>k} s_j^2
- *             <= eps * sum_j s_j^2}); values sorted descending
+ *             <= eps * sum_j s_j^2}); values sorted descending.  A tolerance
+ *             in [0, a), a the Jacobi absolute tolerance (option 2, default
+ *             1e-15), acts as a: squared values below a |theta|^2 are not
+ *             resolved and their directions not orthogonalised, so they count
+ *             as zero; eps < 0 keeps min(chi_max, m) values.  The same holds
+ *             for eps_local of every stepping entry point.
  *   U       : complex128 [m][chi_max] (first k columns written)
  *   S       : FP64 [chi_max] kept singular values, NOT renormalised
  *   Vh      : complex128 [chi_max][n] (first k rows written)

@@ -328,7 +328,8 @@ mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int6
   st = run_jacobi(h, s, mat, 1, hm.nb, (int)m, (int32_t*)(h->ws + oU), false);
   if (st != MPS_OK) return st;
   SelOut* sel = (SelOut*)(h->ws + oSel);
-  MPS_TRY_HIP(h, launch_select(s, mat, 1, (int32_t*)(h->ws + oP), (double*)(h->ws + oS), (int)m, hm.kmax, eps, sel));
+  MPS_TRY_HIP(h, launch_select(s, mat, 1, (int32_t*)(h->ws + oP), (double*)(h->ws + oS), (int)m, hm.kmax,
+                                count_rule_eps(h, eps), sel));
   MPS_TRY_HIP(h, launch_truncate_out(s, mat, (int32_t*)(h->ws + oP), (double*)(h->ws + oS), sel,
                                      (const double2*)theta, m, n, chi_max, (double2*)U, S, (double2*)Vh, k_dev,
                                      disc_dev, norm2_dev));
@@ -632,7 +633,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       mps_status r = run_jacobi(h, s, mats, n, nb_cap, m_cap, unconv, fixed);
       if (r != MPS_OK) return r;
       if (prof) prof_begin(h, s, MPS_K_SELECT);
-      MPS_TRY_HIP(h, launch_select(s, mats, n, perm, s2, m_cap, chi_cap, eps_local, sel));
+      MPS_TRY_HIP(h, launch_select(s, mats, n, perm, s2, m_cap, chi_cap, count_rule_eps(h, eps_local), sel));
       if (prof) prof_end(h, s, MPS_K_SELECT);
       if (prof) prof_begin(h, s, MPS_K_WB_RIGHT);
       MPS_TRY_HIP(h, launch_wb_right(s, it, n, mats, perm, s2, m_cap, sel, chi_eff, d, c128));

@@ -67,6 +67,12 @@ struct KryOpts {
   int32_t* n_used_dev;  // optional [n_chains][2 (L_max - 1)] log of the vectors used
 };
 
+// The tolerance the count rule applies: squared singular values below the
+// Jacobi's absolute floor (jac_abs |theta|^2) are not resolved, their
+// directions are not orthogonalised, so a tail below the floor counts as zero
+// (eps < 0, keep everything up to chi_max, is passed through)
+inline double count_rule_eps(mps_handle h, double eps) { return eps >= 0.0 && eps < h->jac_abs ? h->jac_abs : eps; }
+
 // TEBD driver with a layer window (api.hip); kry != null propagates every
 // bond of the sweep (order 0) with the local Lanczos exponential of h_b
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,

@@ -328,7 +328,7 @@ mps_status svd_select(mps_handle h, hipStream_t s, TdvpWs& t, int m, int n, int 
   MPS_TRY_HIP(h, launch_jac_prep_plain(s, t.mat, 1, h->status_dev));
   mps_status st = run_jacobi(h, s, t.mat, 1, hm.nb, m, t.unconv, false);
   if (st != MPS_OK) return st;
-  MPS_TRY_HIP(h, launch_select(s, t.mat, 1, t.perm, t.s2, m, hm.kmax, eps, t.sel));
+  MPS_TRY_HIP(h, launch_select(s, t.mat, 1, t.perm, t.s2, m, hm.kmax, count_rule_eps(h, eps), t.sel));
   SelOut so;
   MPS_TRY_HIP(h, hipMemcpyAsync(&so, t.sel, sizeof(so), hipMemcpyDeviceToHost, s));
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
