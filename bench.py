@@ -61,7 +61,7 @@ def main():
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
     ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256", "bh_heff_chi512", "xxz_grad_L32",
-                             "xxz_sweep_L64", "tfim_quench_L64"])
+                             "xxz_sweep_L64", "tfim_quench_L64", "bh_tdvp_L32"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -76,7 +76,7 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.warmup is None:
-        args.warmup = {"xxz_batch256": 40, "tfim_quench_L64": 150}.get(args.workload, 140)
+        args.warmup = {"xxz_batch256": 40, "tfim_quench_L64": 150, "bh_tdvp_L32": 40}.get(args.workload, 140)
 
     import workloads as W
     from paper_1703_00387_amd import api, models
@@ -91,6 +91,8 @@ def main():
         return bench_sweep(args)
     if args.workload == "tfim_quench_L64":
         return bench_quench(args)
+    if args.workload == "bh_tdvp_L32":
+        return bench_tdvp(args)
     wl = W.xxz_tebd4_L64()
     spec = wl.chains[0]
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
@@ -270,6 +272,89 @@ def bench_heff(args):
                      "traffic": None, "flops_per_apply": flops},
         "krylov": {"ms_per_exponential": round(t_kry * 1e3, 3), "vectors": n_used,
                    "h_eff_share": round(min(1.0, n_used * t_apply / t_kry), 4)},
+        "device_status": [code, word],
+    }
+    print(json.dumps(out))
+    h.close()
+
+
+def bench_tdvp(args):
+    """Two-site TDVP on the Bose-Hubbard chain (L=32, d=5, t=1, U=4, unit
+    filling, dt=0.02, 20 Lanczos vectors, tol 1e-10, MPO bond dimension 4).
+    The environment update and the one-site H_eff apply (the backward step's
+    operator) are timed at the full shape chi=512; whole 2TDVP steps run at
+    chi_max=64, since one two-site SVD of the 2560 x 2560 theta' at chi=512
+    leaves the single-matrix Jacobi with too little parallelism to finish a
+    step in a bench run."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1703_00387_amd import api, models
+
+    wl = W.bh_tdvp2_L32()
+    spec = wl.chains[0]
+    chi, d = spec.chi_max, spec.d
+    Wm = models.mpo(spec)[spec.L // 2]
+    w = Wm.shape[0]
+    tdt = torch.complex128 if args.dtype == "c128" else torch.complex64
+    h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
+    Lenv = _herm_env(chi, w, (32, 1), tdt, "cuda")
+    Renv = _herm_env(chi, w, (32, 2), tdt, "cuda")
+    Wt = torch.from_numpy(np.ascontiguousarray(Wm)).to(tdt).cuda()
+    A = torch.from_numpy(W.random_complex((chi, d, chi), (32, 3))).to(tdt).cuda()
+    x1 = torch.from_numpy(W.random_complex((chi, d, chi), (32, 4))).to(tdt).cuda()
+    f_env = 8.0 * (2 * w * d * chi ** 3 + w * w * d * d * chi ** 2)
+    f_one = 8.0 * (2 * w * d * chi ** 3 + w * w * d * d * chi ** 2)
+    reps = max(args.steps, 3)
+
+    def timeit(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_envl = timeit(lambda: api.env_update(h, "left", Lenv, Wt, A))
+    t_envr = timeit(lambda: api.env_update(h, "right", Renv, Wt, A))
+    t_one = timeit(lambda: api.heff_apply(h, Lenv, Wt, None, Renv, x1))
+    print(f"[bench] env left {t_envl * 1e3:.2f} ms, right {t_envr * 1e3:.2f} ms, one-site apply {t_one * 1e3:.2f} ms",
+          file=sys.stderr, flush=True)
+    chi_run = 64
+    ch = api.OCChain.product(W.initial_vectors(spec), chi_run, models.mpo(spec), dtype=args.dtype)
+    t0 = time.time()
+    for i in range(args.warmup):
+        api.tdvp2_step(h, ch, wl.dt, 1, wl.eps_local, wl.n_krylov, wl.krylov_tol)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup}, chi_max now {int(ch.chi.max())}, {time.time() - t0:.1f}s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.tdvp2_step(h, ch, wl.dt, args.steps, wl.eps_local, wl.n_krylov, wl.krylov_tol)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t1) / args.steps
+    code, word = h.device_status()
+    L = spec.L
+    upd = 2 * (L - 1)
+    peak = FP64_PEAK_TFLOPS if args.dtype == "c128" else FP32_MFMA_PEAK_TFLOPS
+    out = {
+        "metric": "two-site TDVP updates/s (Bose-Hubbard L=32, d=5, chi_max=64)",
+        "value": round(upd / t_step, 3), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "bh_tdvp_L32: 2TDVP BH L=32 d=5 t=1 U=4 unit filling dt=0.02 n_max=20 tol=1e-10, "
+                               "chi_max=64 for the steps; environment update and one-site H_eff at chi=512",
+                   "two_site_updates_per_step": upd, "one_site_backward_steps_per_step": 2 * (L - 2),
+                   "chi_max_now": int(ch.chi.max())},
+        "env_update_chi512": {"ms_left": round(t_envl * 1e3, 3), "ms_right": round(t_envr * 1e3, 3),
+                              "flops": f_env, "tflops_left": round(f_env / t_envl / 1e12, 3),
+                              "frac_left": round(f_env / t_envl / 1e12 / peak, 4)},
+        "one_site_heff_chi512": {"ms": round(t_one * 1e3, 3), "flops": f_one,
+                                 "tflops": round(f_one / t_one / 1e12, 3), "frac": round(f_one / t_one / 1e12 / peak, 4)},
         "device_status": [code, word],
     }
     print(json.dumps(out))

@@ -94,11 +94,13 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
       // its arithmetic; with two waves per SIMD, batches of two keep the
       // registers within the halved budget.
       static_assert(NT % N == 0, "thread count must be a multiple of the order");
-      constexpr int IT = N * NP / NT, KS = NT / N;
+      // for a small order (N * NP < NT) the first N * NP threads hold one item each
+      constexpr int IT = (N * NP + NT - 1) / NT, KS = NT / N;
       constexpr int UB = NT >= 512 ? (IT < 2 ? IT : 2) : IT;
       const int row = tid % N, k0 = tid / N;
+      const bool active = k0 < NP;
 #pragma unroll
-      for (int u0 = 0; u0 < IT; u0 += UB) {
+      for (int u0 = 0; u0 < IT && active; u0 += UB) {
         double4 rr[UB];
         int pp[UB], qq_[UB];
         double2 gp[UB], gq[UB], qp[UB], qv[UB];
@@ -131,7 +133,7 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
       // set exactly (zero coupling, real diagonal) so rounding does not build up.
       const int col = tid % N;
 #pragma unroll
-      for (int u0 = 0; u0 < IT; u0 += UB) {
+      for (int u0 = 0; u0 < IT && active; u0 += UB) {
         double4 rr[UB];
         int pp[UB], qq_[UB];
         double2 gp[UB], gq[UB];
@@ -173,7 +175,12 @@ __device__ int herm_jacobi(double2* G, double2* Q, int n, double abs_thr, double
   return sweep;
 }
 
+// Order n <= 32 in the JS_N x JS_LD arrays: the sweep runs over the smallest
+// power of two >= n (4 ... 32), so a small matrix takes fewer steps per sweep.
 __device__ __forceinline__ int herm_jacobi32(double2* G, double2* Q, int n, double abs_thr, double rel_thr,
                                              int max_sweeps, double4* rot, int* flag) {
-  return herm_jacobi<32>(G, Q, n, abs_thr, rel_thr, max_sweeps, rot, flag);
+  if (n <= 4) return herm_jacobi<4, JS_LD>(G, Q, n, abs_thr, rel_thr, max_sweeps, rot, flag);
+  if (n <= 8) return herm_jacobi<8, JS_LD>(G, Q, n, abs_thr, rel_thr, max_sweeps, rot, flag);
+  if (n <= 16) return herm_jacobi<16, JS_LD>(G, Q, n, abs_thr, rel_thr, max_sweeps, rot, flag);
+  return herm_jacobi<32, JS_LD>(G, Q, n, abs_thr, rel_thr, max_sweeps, rot, flag);
 }
