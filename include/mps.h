@@ -79,7 +79,11 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * captured graphs), 4 = sweeps of the 64x64 inner eigensolve per Jacobi block
  * pair (default 1), 5 = threads per Jacobi-round workgroup, 256 (four waves,
  * one per SIMD) or 512 (default: eight waves, two per SIMD; the Gram and
- * rotation column work alternates between two groups of four waves). */
+ * rotation column work alternates between two groups of four waves),
+ * 6 = column split: a round with fewer panel pairs than this (default 32;
+ * 0 = never) gives each pair S workgroups over disjoint column ranges, which
+ * form partial Grams, then each sum them, solve the same rotation and rotate
+ * their own columns (one large matrix, as in the sweep or TDVP). */
 mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
  * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,

@@ -51,7 +51,7 @@ mps_status mps_aux_streams(mps_handle h, int n) {
 }
 
 mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
-                      bool fixed) {
+                      bool fixed, bool allow_split) {
   int nb = nb_cap;
   if (!fixed) {
     // eager mode: the largest actual block count bounds the rounds of a sweep
@@ -76,12 +76,29 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
       return MPS_OK;
     }
   }
+  // Few panel pairs (one large matrix): split every pair over S column
+  // ranges so that more CUs work; the partial Grams live in a buffer of the
+  // handle (eager mode only, never inside a captured graph).
+  int S = 1;
+  const int pairs = n * (nb / 2);
+  if (!fixed && allow_split && h->jac_split_below > 0 && pairs < h->jac_split_below) {
+    S = std::max(1, std::min(std::min(16, 256 / std::max(pairs, 1)), std::max(1, m_cap / 64)));
+    const size_t need = (size_t)n * (nb_cap / 2) * S * 64 * 64 * sizeof(double2);
+    if (S > 1 && need > h->split_bytes) {
+      if (h->split_part) MPS_TRY_HIP(h, hipFree(h->split_part));
+      h->split_part = nullptr;
+      h->split_bytes = 0;
+      MPS_TRY_HIP(h, hipMalloc((void**)&h->split_part, need));
+      h->split_bytes = need;
+    }
+  }
   bool done = false;
   for (int sw = 0; sw < max_sweeps && !done; ++sw) {
     if (sw > 0) MPS_TRY_HIP(h, launch_jac_sort(s, mats, n, m_cap));
     for (int r = 0; r < nb - 1; ++r)
       PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs, h->jac_inner_sweeps, 0,
-                                                              h->profile ? h->stats_dev : nullptr, h->jac_threads));
+                                                              h->profile ? h->stats_dev : nullptr, h->jac_threads, S,
+                                                              h->split_part));
     MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
     if (!fixed && sw >= 1) {
       if (h->profile) {
@@ -181,6 +198,7 @@ mps_status mps_destroy(mps_handle h) {
   for (auto e : h->aux_ev) hipEventDestroy(e);
   for (auto st : h->aux) hipStreamDestroy(st);
   if (h->ws) hipFree(h->ws);
+  if (h->split_part) hipFree(h->split_part);
   if (h->status_dev) hipFree(h->status_dev);
   if (h->host_pinned) hipHostFree(h->host_pinned);
   delete h;
@@ -219,6 +237,10 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
     case 5:
       if (value != 256.0 && value != 512.0) return mps_fail(h, MPS_ERR_INVALID, "Jacobi threads must be 256 or 512");
       h->jac_threads = (int)value;
+      return MPS_OK;
+    case 6:
+      if (!(value >= 0.0 && value <= 1.0e6)) return mps_fail(h, MPS_ERR_INVALID, "split threshold must be in [0,1e6]");
+      h->jac_split_below = (int)value;
       return MPS_OK;
     default:
       return mps_fail(h, MPS_ERR_INVALID, "unknown option");

@@ -37,6 +37,9 @@ struct mps_context {
   int jac_max_sweeps = 30;
   int jac_inner_sweeps = 1;    // sweeps of the 64x64 inner eigensolve per block pair
   int jac_threads = 512;       // threads per Jacobi-round workgroup (256 or 512)
+  int jac_split_below = 32;    // split a round's pairs over columns below this many pairs (0 = never)
+  double2* split_part = nullptr;  // partial Grams of split rounds (grown on demand)
+  size_t split_bytes = 0;
   // pinned host scratch for small readbacks
   int32_t* host_pinned = nullptr;
   // optional per-kernel timing with HIP events on the launch stream
@@ -57,8 +60,9 @@ mps_status mps_aux_streams(mps_handle h, int n);
 // Jacobi helpers shared by the drivers (api.hip)
 struct JacMat;
 int jac_nb(int m);
+// allow_split: rounds with few panel pairs may split each pair over columns
 mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
-                      bool fixed);
+                      bool fixed, bool allow_split = true);
 
 // Local Krylov propagation of the bond terms (Krylov TEBD)
 struct KryOpts {
@@ -210,9 +214,18 @@ hipError_t launch_ktebd_krylov(hipStream_t s, const KryJob* jobs, int n_items, i
 hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
                                  int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status);
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status);
+// Column split of a Jacobi round (see jac_round_kernel): S workgroups per
+// panel pair; part holds n_mats * pairs * S partial Grams of 64 x 64.
+struct JacSplit {
+  int S;          // workgroups per pair (1 = no split)
+  int pairs;      // pair slots per matrix in part (nb_cap / 2)
+  int phase;      // 0 = partial Grams, 1 = sum, solve, rotate; 2 = unsplit
+  int pad;
+  double2* part;
+};
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round,
                             double tol, double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
-                            int threads);
+                            int threads, int split_S = 1, double2* split_part = nullptr);
 hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged);
 hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap);
 hipError_t launch_jac_flag_noconv(hipStream_t s, const int32_t* unconverged, uint32_t* status);

@@ -640,7 +640,8 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
       // -- the layer's residual SVDs, orthogonalised with a purely relative tolerance
       MPS_TRY_HIP(h, launch_jac_prep_plain(s, g.mat, ni, h->status_dev));
       h->jac_abs = 0.0;
-      r = run_jacobi(h, s, g.mat, ni, nb_cap, g.m_cap, g.unc, false);
+      // the residual batches are many small matrices: no column split
+      r = run_jacobi(h, s, g.mat, ni, nb_cap, g.m_cap, g.unc, false, false);
       h->jac_abs = abs_saved;
       if (r != MPS_OK) return r;
       MPS_TRY_HIP(h, launch_select(s, g.mat, ni, g.perm, g.s2, g.m_cap, 0, 0.0, g.sel));

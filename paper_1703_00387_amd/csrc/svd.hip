@@ -206,10 +206,16 @@ __device__ __forceinline__ void herm_acc_add_lds(const HermAcc& acc, double2* Gs
 // alternate between the groups (each with its own two staging buffers), the
 // two partial Grams are summed in LDS, and the LDS eigensolve uses all eight
 // waves, so every SIMD holds two waves.
+// Column split (split.S > 1, round mode only): S workgroups share a panel
+// pair, slice s taking the 64-column blocks [ncb s / S, ncb (s+1) / S).
+// Phase 0 writes each slice's partial Gram to split.part; phase 1 sums the S
+// partials in a fixed order (so every slice holds the same G and computes the
+// same rotation), runs the LDS solve and rotates its own columns.  Matrices
+// whose rounds have few panel pairs (one large matrix) then use more CUs.
 template <int NT>
 __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
                                                        double abs_tol, int inner_sweeps, int loop_sweeps,
-                                                       unsigned long long* stats) {
+                                                       unsigned long long* stats, JacSplit split) {
   constexpr int NG = NT / 256;  // wave groups
   // chunks in flight per thread in the Gram and rotation loops: with two
   // waves per SIMD one is enough (measured: 233 us against 250 us for three
@@ -226,11 +232,18 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
   __shared__ int need;
   JacMat* M = mats + blockIdx.y;
   if (M->conv) return;
-  const int nb = M->nb, p = blockIdx.x;
+  const int S = split.S, slice = blockIdx.x % S;
+  const int nb = M->nb, p = blockIdx.x / S;
   if (2 * p >= nb || round >= nb - 1) return;
   if (loop_sweeps > 0 && nb != 2) return;  // larger matrices take the round-based sweeps
   const int m = M->m, n = M->n, ld = M->ld;
   double2* X = M->X;
+  // this workgroup's 64-column blocks [cb0, cb1) and 16-column chunks [ch0, ch1)
+  const int ncb_all = (n + TBN - 1) / TBN;
+  const int cb0 = (int)((long long)ncb_all * slice / S), cb1 = (int)((long long)ncb_all * (slice + 1) / S);
+  const int ch0 = cb0 * (TBN / TBK), ch1 = min(cb1 * (TBN / TBK), (n + TBK - 1) / TBK);
+  // partial Gram of (matrix, pair, slice): [JP][JP]
+  double2* part = S > 1 ? split.part + (((size_t)blockIdx.y * split.pairs + p) * S + slice) * (JP * JP) : nullptr;
   int I, J;
   jac_pair(nb, round, p, I, J);
   if (loop_sweeps > 0) {  // one panel: keep the real rows first
@@ -254,19 +267,19 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
   // ---- Gram matrix of the 64 rows on FP64 MFMA: G[i][j] = <x_i, x_j> --------
   // 16-column chunks are staged in LDS (two buffers); the next kPf chunks are
   // already in flight in registers, so the loads of one panel overlap its
-  // multiplies.
-  {
+  // multiplies.  (Phase 1 of a split round reads the partials instead.)
+  if (split.phase != 1) {
     // group grp takes the chunks ci = lc * NG + grp, lc = 0 .. nloc-1
     double2* Bs0 = Q + grp * 2 * TBK * TLD;
     double2* Bs1 = Bs0 + TBK * TLD;
     const int i = gtid >> 2, kq = (gtid & 3) * 4;
     const int gi = rows_s[i];
     const double2* xr = X + (size_t)(gi >= 0 ? gi : 0) * ld;
-    const int nch = (n + TBK - 1) / TBK;
+    const int nch = max(ch1 - ch0, 0);
     const int nloc = (nch - grp + NG - 1) / NG, nloc_max = (nch + NG - 1) / NG;
     double2 v[kPf][4];
     auto load = [&](int lc, double2* dst) {
-      const int ci = lc * NG + grp;
+      const int ci = ch0 + lc * NG + grp;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         int c = ci * TBK + kq + e;
@@ -311,6 +324,25 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
     }
   }
   __syncthreads();
+  if (S > 1 && split.phase == 0) {
+    // phase 0: leave this slice's partial Gram and stop
+    for (int e = tid; e < JP * JP; e += NT) part[e] = G[(e / JP) * (JP + 1) + e % JP];
+    return;
+  }
+  if (S > 1) {
+    // phase 1: the pair's Gram is the sum of the S partials, added in slice order
+    const double2* pp0 = split.part + ((size_t)blockIdx.y * split.pairs + p) * S * (JP * JP);
+    for (int e = tid; e < JP * JP; e += NT) {
+      double2 a = make_double2(0.0, 0.0);
+      for (int t = 0; t < S; ++t) {
+        const double2 b = pp0[(size_t)t * (JP * JP) + e];
+        a.x += b.x;
+        a.y += b.y;
+      }
+      G[(e / JP) * (JP + 1) + e % JP] = a;
+    }
+    __syncthreads();
+  }
 
   // ---- is any pair of the 64 rows still not orthogonal? --------------------
   // A pair counts as orthogonal when |G_pq| <= max(tol sqrt(G_pp G_qq),
@@ -329,9 +361,10 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
   __syncthreads();
   // work counter (real flops): the Hermitian Gram needs 64*65/2 complex MACs
   // per column (16640 n), the rotation 64*64 (32768 n)
-  if (tid == 0 && stats) atomicAdd(&stats[1], (16640ull + (need ? 32768ull : 0ull)) * (unsigned long long)n);
+  if (tid == 0 && stats && slice == 0)
+    atomicAdd(&stats[1], (16640ull + (need ? 32768ull : 0ull)) * (unsigned long long)n);
   if (!need) {
-    if (tid < JP && rows_s[tid] >= 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
+    if (tid < JP && rows_s[tid] >= 0 && slice == 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
     rotated = false;
     break;
   }
@@ -350,7 +383,7 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
     herm_jacobi<JP, JP + 1, NT>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
   }
   // the rotated rows have squared norms diag(Q^dag G Q), left on G's diagonal
-  if (tid < JP && rows_s[tid] >= 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
+  if (tid < JP && rows_s[tid] >= 0 && slice == 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
   __syncthreads();
 
   // ---- rotate the rows: y_j = sum_p Q[p][j] x_p, 64 columns at a time -------
@@ -362,11 +395,11 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
     double2* Bs1 = Bs0 + TBK * TLD;
     const int k = gtid >> 4, q4 = (gtid & 15) * 4;
     constexpr int PCH = JP / TBK;  // p-chunks per column block
-    const int ncb = (n + TBN - 1) / TBN;
+    const int ncb = max(cb1 - cb0, 0);
     const int nsteps = ((ncb - grp + NG - 1) / NG) * PCH, nsteps_max = ((ncb + NG - 1) / NG) * PCH;
     double2 v[kPf][4];
     auto load = [&](int st, double2* dst) {
-      const int c0 = ((st / PCH) * NG + grp) * TBN, p0 = (st % PCH) * TBK;
+      const int c0 = (cb0 + (st / PCH) * NG + grp) * TBN, p0 = (st % PCH) * TBK;
       const int g = rows_s[p0 + k];
       const double2* xr = X + (size_t)(g >= 0 ? g : 0) * ld;
 #pragma unroll
@@ -393,7 +426,7 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
         const int st = base + u;
         if (st < nsteps_max) {
           if (st < nsteps) {
-          const int c0 = ((st / PCH) * NG + grp) * TBN, p0 = (st % PCH) * TBK;
+          const int c0 = (cb0 + (st / PCH) * NG + grp) * TBN, p0 = (st % PCH) * TBK;
           if (st + kPf < nsteps) load(st + kPf, v[u]);
           mma_chunk_lda<double2>(Q + p0 * (JP + 1), JP + 1, (st & 1) ? Bs1 : Bs0, acc, wm, wn, lane);
           if (p0 + TBK == JP) {
@@ -420,7 +453,7 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
       }
     }
   }
-  if (loop_sweeps == 0 && tid == 0) atomicAdd(&M->rot, 1);
+  if (loop_sweeps == 0 && tid == 0 && slice == 0) atomicAdd(&M->rot, 1);
   __syncthreads();
   }
   // loop mode: a converged matrix is done; one whose pair still rotated in
@@ -730,16 +763,26 @@ hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32
 
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round, double tol,
                             double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
-                            int threads) {
+                            int threads, int split_S, double2* split_part) {
   if (n_mats <= 0) return hipSuccess;
-  dim3 grid(nb_cap / 2, n_mats);
-  if (threads == 512)
-    jac_round_kernel<512><<<grid, 512, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats);
-  else if (threads == 256)
-    jac_round_kernel<256><<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (split_S < 1 || (split_S > 1 && (!split_part || loop_sweeps > 0))) return hipErrorInvalidValue;
+  JacSplit sp;
+  sp.S = split_S;
+  sp.pairs = nb_cap / 2;
+  sp.part = split_part;
+  dim3 grid((nb_cap / 2) * split_S, n_mats);
+  for (int phase = split_S > 1 ? 0 : 2; phase <= (split_S > 1 ? 1 : 2); ++phase) {
+    sp.phase = phase;
+    if (threads == 512)
+      jac_round_kernel<512><<<grid, 512, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats, sp);
+    else if (threads == 256)
+      jac_round_kernel<256><<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats, sp);
+    else
+      return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged) {
