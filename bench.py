@@ -319,6 +319,24 @@ def bench_tdvp(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
+    # the two-site split at the full shape: theta' of (chi d) x (d chi) = 2560 x 2560
+    # with a graded spectrum, truncated to chi = 512 (once; a few seconds)
+    m2 = chi * d
+    Uq, _ = np.linalg.qr(W.random_complex((m2, m2), (32, 5)))
+    Vq, _ = np.linalg.qr(W.random_complex((m2, m2), (32, 6)))
+    th2 = torch.from_numpy((Uq * np.exp(-0.02 * np.arange(m2))) @ Vq.conj().T).cuda()
+    th2 = th2 / torch.linalg.vector_norm(th2)
+    t_svd = {}
+    for below in (0, 32):   # 0: never split; 32: the default (large matrices split below 128 pairs)
+        h.set_option(6, below)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, k_svd, _, _ = h.truncate(th2, chi, wl.eps_local)
+        torch.cuda.synchronize()
+        t_svd[below] = time.perf_counter() - t0
+        print(f"[bench] 2560 x 2560 truncated SVD (split option {below}) {t_svd[below]:.2f} s, k={k_svd}",
+              file=sys.stderr, flush=True)
+    h.set_option(6, 32)
     t_envl = timeit(lambda: api.env_update(h, "left", Lenv, Wt, A))
     t_envr = timeit(lambda: api.env_update(h, "right", Renv, Wt, A))
     t_one = timeit(lambda: api.heff_apply(h, Lenv, Wt, None, Renv, x1))
@@ -353,6 +371,8 @@ def bench_tdvp(args):
         "env_update_chi512": {"ms_left": round(t_envl * 1e3, 3), "ms_right": round(t_envr * 1e3, 3),
                               "flops": f_env, "tflops_left": round(f_env / t_envl / 1e12, 3),
                               "frac_left": round(f_env / t_envl / 1e12 / peak, 4)},
+        "two_site_svd_chi512": {"shape": [chi * d, chi * d], "s_unsplit": round(t_svd[0], 3),
+                                "s_split": round(t_svd[32], 3)},
         "one_site_heff_chi512": {"ms": round(t_one * 1e3, 3), "flops": f_one,
                                  "tflops": round(f_one / t_one / 1e12, 3), "frac": round(f_one / t_one / 1e12 / peak, 4)},
         "device_status": [code, word],

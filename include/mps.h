@@ -81,7 +81,8 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * one per SIMD) or 512 (default: eight waves, two per SIMD; the Gram and
  * rotation column work alternates between two groups of four waves),
  * 6 = column split: a round with fewer panel pairs than this (default 32;
- * 0 = never) gives each pair S workgroups over disjoint column ranges, which
+ * 0 = never), or with fewer than 128 pairs of matrices of at least 1024 rows,
+ * gives each pair S workgroups over disjoint column ranges, which
  * form partial Grams, then each sum them, solve the same rotation and rotate
  * their own columns (one large matrix, as in the sweep or TDVP). */
 mps_status mps_set_option(mps_handle h, int option, double value);

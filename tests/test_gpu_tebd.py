@@ -69,6 +69,7 @@ def _graded(m, n, key, decay):
     (130, 70, 50, 1e-12, "rand"),
     (256, 256, 128, 1e-12, "graded"),
     (512, 512, 256, 1e-12, "graded"),
+    (1280, 1280, 256, 1e-12, "graded"),    # 20 panel pairs: each split over 12 column ranges
     (100, 100, 100, 1e-20, "rank5"),
     (1, 16, 4, 0.0, "rand"),
 ])
