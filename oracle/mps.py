@@ -108,6 +108,29 @@ def truncate(theta_mat: np.ndarray, chi_max: int, eps: float):
     return U[:, :k], s[:k], Vh[:k], w, nk, s
 
 
+def truncate_eig(theta_mat: np.ndarray, chi_max: int, eps: float):
+    """The eigendecomposition split of Sec. "Basic concepts" (Eq. AAD_ULLUD):
+    the Hermitian A A^dag = U lambda^2 U^dag gives U and the squared singular
+    values; U^dag A = lambda V^dag then gives the right factor, so the kept
+    rows of V^dag are (U^dag A)_j / lambda_j.  Same count rule and outputs as
+    ``truncate`` (eigenvalues sorted descending, negative round-off set to 0;
+    a kept row with lambda_j = 0, possible only with eps < 0, is left zero).
+    The squared values carry an absolute error of order eps_mach lambda_1^2, so
+    a singular value s_j comes out with relative error ~ eps_mach (s_1/s_j)^2."""
+    A = theta_mat
+    ev, U = np.linalg.eigh(A @ A.conj().T)
+    order = np.argsort(ev)[::-1]
+    lam2 = np.maximum(ev[order], 0.0)
+    U = U[:, order]
+    s = np.sqrt(lam2)
+    k = count_rule(s, chi_max, eps)
+    w = float(np.sum(lam2[k:]))
+    nk = float(np.sqrt(np.sum(lam2[:k])))
+    inv = np.divide(1.0, s[:k], out=np.zeros(k), where=s[:k] > 0)
+    Vh = (U[:, :k].conj().T @ A) * inv[:, None]
+    return U[:, :k], s[:k], Vh, w, nk, s
+
+
 def apply_bond(psi: MPS, b: int, G: np.ndarray, chi_max: int, eps: float) -> float:
     """One Hastings-form two-site update of bond b.  Returns discarded weight."""
     d = psi.d
