@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--jac-threads", type=int, default=512, choices=[256, 512],
                     help="threads per Jacobi-round workgroup (two waves per SIMD at 512)")
+    ap.add_argument("--split", default="svd", choices=["svd", "eig"],
+                    help="two-site split of matrices of at most 64 rows: one-sided Jacobi SVD or the "
+                         "eigendecomposition of the Gram")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="xxz_batch256: skip the one-bond-per-launch comparison")
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
@@ -98,6 +101,7 @@ def main():
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
+    h.set_option(7, 1.0 if args.split == "eig" else 0.0)
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
 
     start_step = 0
@@ -232,6 +236,7 @@ def bench_heff(args):
     dev = "cuda"
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
+    h.set_option(7, 1.0 if args.split == "eig" else 0.0)
     Lenv = _herm_env(chi, w, (31, 1), tdt, dev)
     Renv = _herm_env(chi, w, (31, 2), tdt, dev)
     Wt = torch.from_numpy(np.ascontiguousarray(Wm)).to(tdt).to(dev)
@@ -300,6 +305,7 @@ def bench_tdvp(args):
     tdt = torch.complex128 if args.dtype == "c128" else torch.complex64
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
+    h.set_option(7, 1.0 if args.split == "eig" else 0.0)
     Lenv = _herm_env(chi, w, (32, 1), tdt, "cuda")
     Renv = _herm_env(chi, w, (32, 2), tdt, "cuda")
     Wt = torch.from_numpy(np.ascontiguousarray(Wm)).to(tdt).cuda()
@@ -403,6 +409,7 @@ def bench_grad(args):
     sz = models.sz_operator()
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
+    h.set_option(7, 1.0 if args.split == "eig" else 0.0)
 
     def fresh():
         return api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec))
@@ -459,6 +466,7 @@ def bench_quench(args):
     fn = lambda n0, n: np.array([[[1.0, g((k + c) * dt)] for c in nodes] for k in range(n0, n0 + n)])
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
+    h.set_option(7, 1.0 if args.split == "eig" else 0.0)
     spec = W.tfim_chain(L, chi_max, 1.0, 1.5)
     ch = api.Chain.product(W.initial_vectors(spec), chi_max, terms, dtype=args.dtype)
     done, t0 = 0, time.time()
@@ -520,6 +528,7 @@ def bench_sweep(args):
     spec = wl.chains[0]
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
+    h.set_option(7, 1.0 if args.split == "eig" else 0.0)
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
     if args.load_state:
         st = torch.load(args.load_state, weights_only=True)
@@ -591,6 +600,7 @@ def bench_batch(args):
     wl = W.xxz_batch256()
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
+    h.set_option(7, 1.0 if args.split == "eig" else 0.0)
     chains = [api.Chain.product(W.initial_vectors(c), c.chi_max, models.bond_hamiltonians(c), dtype=args.dtype)
               for c in wl.chains]
     upd = sum(len(range(0, c.L - 1, 2)) * 2 + len(range(1, c.L - 1, 2)) for c in wl.chains)
@@ -638,7 +648,8 @@ def bench_batch(args):
            "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
            "config": {"workload": "xxz_batch256: 256 XXZ chains, L~U{16..64}, chi_max~{32,64,128,256}, "
                                   "Jz_b~U(0.5,1.5), random product states, TEBD2 dt=0.05",
-                      "updates_per_step": upd, "chi_max_now": max(int(c.chi.max()) for c in chains)},
+                      "updates_per_step": upd, "chi_max_now": max(int(c.chi.max()) for c in chains),
+                      "split": args.split},
            "batched_eager": {"ms_per_step": round(t_eager * 1e3 / args.steps, 3)},
            "batched_graph": {"ms_per_step": round(t_graph * 1e3 / args.steps, 3)},
            "plain": None if t_plain is None else

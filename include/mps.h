@@ -84,7 +84,12 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * 0 = never), or with fewer than 128 pairs of matrices of at least 1024 rows,
  * gives each pair S workgroups over disjoint column ranges, which
  * form partial Grams, then each sum them, solve the same rotation and rotate
- * their own columns (one large matrix, as in the sweep or TDVP). */
+ * their own columns (one large matrix, as in the sweep or TDVP),
+ * 7 = split of matrices of at most 64 rows: 0 = one-sided Jacobi SVD
+ * (default), 1 = the eigendecomposition split (Sec. "Basic concepts", Eq.
+ * AAD_ULLUD): the Gram theta' theta'^dag is diagonalised to convergence in LDS
+ * and the rows are rotated once by its eigenvectors; a singular value s_j then
+ * carries a relative error of order 1e-15 (s_1/s_j)^2. */
 mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
  * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,

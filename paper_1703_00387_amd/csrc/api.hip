@@ -12,6 +12,7 @@ namespace {
 constexpr int kJacBlock = 32;   // rows per Jacobi block
 constexpr int kFixedSweeps = 20;  // sweeps queued when the host may not synchronise
 constexpr int kLoopInner = 4;     // inner sweeps per outer sweep for single-panel matrices
+constexpr int kEigSweeps = 40;    // eigen split: sweeps of the 64x64 Hermitian Jacobi (it stops when converged)
 
 }  // namespace
 
@@ -67,9 +68,14 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     // Eager mode does this only when every matrix is that small: otherwise the
     // small ones stay in the rounds, where they run beside the others.  A
     // queued schedule cannot see the sizes, so it always starts with it.
+    // The eigen split (Sec. "Basic concepts": the Hermitian A A^dag = U lambda^2
+    // U^dag, then U^dag A = lambda V^dag) of a single-panel matrix is one Gram,
+    // its Hermitian Jacobi run to convergence and one rotation of the rows.
+    const bool eig = h->split_method == 1;
     PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
-                launch_jac_round(s, mats, n, 2, 0, h->jac_tol, h->jac_abs, std::max(h->jac_inner_sweeps, kLoopInner),
-                                 max_sweeps, h->profile ? h->stats_dev : nullptr, h->jac_threads));
+                launch_jac_round(s, mats, n, 2, 0, h->jac_tol, h->jac_abs,
+                                 eig ? kEigSweeps : std::max(h->jac_inner_sweeps, kLoopInner), eig ? 1 : max_sweeps,
+                                 h->profile ? h->stats_dev : nullptr, h->jac_threads, 1, nullptr, eig ? 1 : 0));
     if (nb == 2) {
       MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
       MPS_TRY_HIP(h, launch_jac_flag_noconv(s, unconv, h->status_dev));
@@ -244,6 +250,10 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
     case 6:
       if (!(value >= 0.0 && value <= 1.0e6)) return mps_fail(h, MPS_ERR_INVALID, "split threshold must be in [0,1e6]");
       h->jac_split_below = (int)value;
+      return MPS_OK;
+    case 7:
+      if (value != 0.0 && value != 1.0) return mps_fail(h, MPS_ERR_INVALID, "split method must be 0 or 1");
+      h->split_method = (int)value;
       return MPS_OK;
     default:
       return mps_fail(h, MPS_ERR_INVALID, "unknown option");

@@ -38,6 +38,7 @@ struct mps_context {
   int jac_inner_sweeps = 1;    // sweeps of the 64x64 inner eigensolve per block pair
   int jac_threads = 512;       // threads per Jacobi-round workgroup (256 or 512)
   int jac_split_below = 32;    // split a round's pairs over columns below this many pairs (0 = never)
+  int split_method = 0;        // single-panel matrices: 0 = one-sided Jacobi SVD, 1 = eigensolve of the Gram
   double2* split_part = nullptr;  // partial Grams of split rounds (grown on demand)
   size_t split_bytes = 0;
   // pinned host scratch for small readbacks
@@ -220,12 +221,12 @@ struct JacSplit {
   int S;          // workgroups per pair (1 = no split)
   int pairs;      // pair slots per matrix in part (nb_cap / 2)
   int phase;      // 0 = partial Grams, 1 = sum, solve, rotate; 2 = unsplit
-  int pad;
+  int eig;        // loop mode: one Gram, its eigensolve to convergence, one rotation
   double2* part;
 };
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round,
                             double tol, double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
-                            int threads, int split_S = 1, double2* split_part = nullptr);
+                            int threads, int split_S = 1, double2* split_part = nullptr, int eig = 0);
 hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged);
 hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap);
 hipError_t launch_jac_flag_noconv(hipStream_t s, const int32_t* unconverged, uint32_t* status);

@@ -460,9 +460,11 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
   // the last sweep is left to the round-based sweeps (and counted as not
   // converged by the next sweep end)
   if (loop_sweeps > 0 && tid == 0) {
-    if (rotated) {
+    if (rotated && !split.eig) {
       M->rot = 1;
     } else {
+      // converged, or the eigen split: its one rotation by the eigenvectors of
+      // the Gram is the split (the rows' norms are the eigenvalues s^2)
       M->rot = 0;
       M->conv = 1;
     }
@@ -763,13 +765,14 @@ hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32
 
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round, double tol,
                             double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
-                            int threads, int split_S, double2* split_part) {
+                            int threads, int split_S, double2* split_part, int eig) {
   if (n_mats <= 0) return hipSuccess;
   if (split_S < 1 || (split_S > 1 && (!split_part || loop_sweeps > 0))) return hipErrorInvalidValue;
   JacSplit sp;
   sp.S = split_S;
   sp.pairs = nb_cap / 2;
   sp.part = split_part;
+  sp.eig = eig;
   dim3 grid((nb_cap / 2) * split_S, n_mats);
   for (int phase = split_S > 1 ? 0 : 2; phase <= (split_S > 1 ? 1 : 2); ++phase) {
     sp.phase = phase;

@@ -1,0 +1,92 @@
+"""GPU eigendecomposition split (handle option 7 = 1) for matrices of at most
+64 rows: one Gram, its Hermitian Jacobi to convergence in LDS, one rotation.
+
+Bars: the accuracy law of the split (its squared values carry an absolute
+error of order the Jacobi floor 1e-15 |theta|^2), so |Delta s_j| / s_j <=
+1e-13 + 1e-13 (s_1/s_j)^2; kept count identical, discarded weight within
+1e-12 + 1e-6 w; TEBD runs in this mode are held to the usual bar against the
+oracle (|Delta <S^z_i>| <= 1e-6, state overlap 1 - 1e-9).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1703_00387_amd import api
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    h = api.Handle(0)
+    h.set_option(7, 1.0)
+    yield h
+    h.close()
+
+
+def _graded(m, n, s, key):
+    Uq, _ = np.linalg.qr(W.random_complex((m, m), key + (1,)))
+    Vq, _ = np.linalg.qr(W.random_complex((n, n), key + (2,)))
+    r = len(s)
+    return (Uq[:, :r] * s) @ Vq[:, :r].conj().T
+
+
+@pytest.mark.parametrize("m,n,chi,eps,decay", [
+    (64, 64, 64, 1e-12, 0.45),
+    (48, 80, 40, 1e-10, 0.3),
+    (20, 7, 10, 0.0, 0.5),
+    (64, 200, 32, 1e-12, 0.2),
+    (1, 16, 4, 0.0, 0.1),
+])
+def test_eig_split_truncate(H, m, n, chi, eps, decay):
+    from oracle import mps as omps
+    r = min(m, n)
+    s = np.exp(-decay * np.arange(r))
+    A = _graded(m, n, s, (64, m, n))
+    A /= np.linalg.norm(A)
+    U, S, Vh, k, disc, norm2 = H.truncate(torch.from_numpy(A).cuda(), chi, eps)
+    S = S.cpu().numpy()
+    Uo, so, Vho, wo, nko, sfull = omps.truncate(A, chi, eps)
+    assert k == len(so), (k, len(so))
+    rel = np.abs(S - so) / so
+    bound = 1e-13 + 1e-13 * (sfull[0] / so) ** 2
+    print(f"m={m} n={n} k={k} worst rel/bound {np.max(rel / bound):.2e}, s_k/s_1 {so[-1] / sfull[0]:.1e}")
+    assert np.all(rel <= bound)
+    assert abs(disc - wo) <= 1e-12 + 1e-6 * wo
+    R = (U.cpu().numpy() * S) @ Vh.cpu().numpy()
+    assert abs(np.linalg.norm(A - R) ** 2 - wo) < 1e-12
+
+
+def test_eig_split_tebd_batch_and_graph(H):
+    from oracle import mps as omps, models as om
+    from paper_1703_00387_amd import api, models, _lib
+    wl = W.xxz_batch256(n_chains=3)
+    specs = [W.xxz_chain(L, 16, 1.0, 0.5, None, c.Jz_b[:L - 1], "random_product", c.local_states[:L])
+             for L, c in zip((10, 13, 16), wl.chains)]
+    mk = lambda sp: api.Chain.product(W.initial_vectors(sp), sp.chi_max, models.bond_hamiltonians(sp))
+    a = [mk(sp) for sp in specs]
+    b = [mk(sp) for sp in specs]
+    api.tebd_step(H, a, 2, 0.05, 12, 1e-12)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        api.tebd_step(H, b, 2, 0.05, 12, 1e-12, flags=_lib.MPS_FLAG_GRAPH)
+    st.synchronize()
+    code, word = H.device_status()
+    assert code == 0 and word == 0, (code, word)
+    for sp, x, y in zip(specs, a, b):
+        ref = omps.tebd_run(sp, "tebd2", 0.05, 12, 1e-12)
+        site, _, _ = api.observe(H, x, models.sz_operator())
+        dd = np.abs(site.cpu().numpy() - omps.local_expect(ref, 0.5 * om.SZ)).max()
+        assert dd <= 1e-6, (sp.L, dd)
+        site_g, _, _ = api.observe(H, y, models.sz_operator())
+        assert np.abs(site_g.cpu().numpy() - site.cpu().numpy()).max() <= 1e-9
+        B, lam, chi = x.to_host()
+        v = lam[0][:, None] * B[0].reshape(B[0].shape[0], -1)
+        v = v.reshape(-1, B[0].shape[2])
+        for T in B[1:]:
+            v = (v @ T.reshape(T.shape[0], -1)).reshape(-1, T.shape[2])
+        vo = omps.to_vector(ref)
+        ov = abs(np.vdot(v.reshape(-1), vo)) / (np.linalg.norm(v) * np.linalg.norm(vo))
+        assert 1 - ov <= 1e-9, 1 - ov
