@@ -381,6 +381,18 @@ mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* c
  * not converge.
  */
 size_t mps_tebd_grad_arena_bytes(int32_t L, int32_t d, int32_t chi_max, int32_t n_steps);
+/*
+ * The vector-Jacobian product of the same run: for the final observables
+ * obs = (<op1 at site i>, i < L; <op2 on bond b>, b < L-1) and host weights
+ * w_site [L], w_bond [L-1] (the cotangent of obs), dJ_dev receives
+ * sum_i w_site[i] d<op1>_i/dJ + sum_b w_bond[b] d<op2>_b/dJ.  obs_dev (device
+ * FP64 [2L-1], may be NULL) receives obs.  Other arguments, the chain's final
+ * state and the errors as for mps_tebd_grad; non-finite weights are refused.
+ */
+mps_status mps_tebd_vjp(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0, double dt,
+                        int32_t n_steps, double eps_local, double eta, const void* op1, const double* w_site,
+                        const void* op2, const double* w_bond, void* arena, size_t arena_bytes, double* obs_dev,
+                        double* dJ_dev);
 mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0, double dt,
                          int32_t n_steps, double eps_local, double eta, const void* op1, int32_t site,
                          const void* op2, void* arena, size_t arena_bytes, double* loss_dev, double* dJ_dev);

@@ -232,6 +232,65 @@ def tebd_grad(h: Handle, chain: Chain, h0, dt: float, n_steps: int, eps: float, 
     return loss, dJ
 
 
+def tebd_vjp(h: Handle, chain: Chain, h0, dt: float, n_steps: int, eps: float, op1, op2, w_site, w_bond,
+             eta: float = 1e-12):
+    """Final observables (<op1 at i>, i < L; <op2 on b>, b < L-1) of n_steps TEBD2
+    steps from the chain's state, and their vector-Jacobian product with the
+    cotangent (w_site, w_bond) with respect to J_b (h_b = J_b h0[b]).  Returns
+    (obs [2L-1], dJ [L-1]) as device float64 tensors."""
+    dev = chain.B.device
+    L = chain.L
+    nbytes = lib().mps_tebd_grad_arena_bytes(L, chain.d, chain.chi_max, n_steps)
+    if nbytes == 0:
+        raise _lib.MPSError(_lib.MPS_ERR_INVALID, "bad shape for the gradient arena")
+    arena = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    h0t = torch.as_tensor(h0, dtype=torch.complex128).to(dev).contiguous()
+    o1 = torch.as_tensor(op1, dtype=torch.complex128).to(dev).contiguous()
+    o2 = torch.as_tensor(op2, dtype=torch.complex128).to(dev).contiguous()
+    ws = np.ascontiguousarray(np.asarray(w_site, dtype=np.float64).reshape(L))
+    wb = np.ascontiguousarray(np.asarray(w_bond, dtype=np.float64).reshape(L - 1))
+    obs = torch.zeros(2 * L - 1, dtype=torch.float64, device=dev)
+    dJ = torch.zeros(L - 1, dtype=torch.float64, device=dev)
+    d = chain.desc()
+    h.check(lib().mps_tebd_vjp(h.h, _stream(), C.byref(d), _ptr(h0t), float(dt), n_steps, float(eps), float(eta),
+                               _ptr(o1), ws.ctypes.data_as(C.c_void_p), _ptr(o2), wb.ctypes.data_as(C.c_void_p),
+                               _ptr(arena), nbytes, _ptr(obs), _ptr(dJ)))
+    return obs, dJ
+
+
+class TebdObservables(torch.autograd.Function):
+    """Final observables of a TEBD2 run as a differentiable function of the
+    per-bond couplings J (h_b = J_b h0[b]), from a product state:
+
+        obs = TebdObservables.apply(J, h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta)
+
+    obs[:L] = <op1 at site i>, obs[L:] = <op2 on bond b> (float64, on the GPU).
+    The forward runs mps_tebd_step (order 2) and mps_observe; the backward runs
+    mps_tebd_vjp with the incoming gradient as the cotangent (it re-runs the
+    forward with a checkpoint per step).  Complex128 chains only."""
+
+    @staticmethod
+    def forward(ctx, J, h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta=1e-12):
+        hb = J.detach().to(torch.complex128)[:, None, None] * torch.as_tensor(h0, dtype=torch.complex128).to(J.device)
+        chain = Chain.product(vectors, chi_max, hb.cpu().numpy(), device=J.device, dtype="c128")
+        tebd_step(h, [chain], 2, dt, n_steps, eps)
+        site, bond, _ = observe(h, chain, op1, op2)
+        ctx.args = (h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta)
+        ctx.save_for_backward(J.detach())
+        return torch.cat([site, bond])
+
+    @staticmethod
+    def backward(ctx, g):
+        (J,) = ctx.saved_tensors
+        h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta = ctx.args
+        L = J.numel() + 1
+        hb = J.to(torch.complex128)[:, None, None] * torch.as_tensor(h0, dtype=torch.complex128).to(J.device)
+        chain = Chain.product(vectors, chi_max, hb.cpu().numpy(), device=J.device, dtype="c128")
+        w = g.detach().double().cpu().numpy()
+        _, dJ = tebd_vjp(h, chain, h0, dt, n_steps, eps, op1, op2, w[:L], w[L:], eta)
+        return (dJ.to(J.dtype),) + (None,) * 10
+
+
 def _code(t):
     return _lib.MPS_C128 if t.dtype == torch.complex128 else _lib.MPS_C64
 

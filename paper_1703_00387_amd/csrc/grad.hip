@@ -1,7 +1,8 @@
 // Reverse-mode gradient of a TEBD2 run with respect to per-bond couplings.
 //
-// Loss: <O1 at one site> + sum_b <O2 on bond b> of the final state (the
-// observables of Sec. "Observables").  The forward run stores the chain at
+// Loss: sum_i w_i <O1 at site i> + sum_b w_b <O2 on bond b> of the final state
+// (the observables of Sec. "Observables"; one site with weight 1 and every bond
+// with weight 1 for mps_tebd_grad, any weights for mps_tebd_vjp).  The forward run stores the chain at
 // the start of every step (checkpoints); the backward pass restores each step,
 // re-runs its three layers keeping a snapshot before every layer, and walks
 // the updates in reverse.  Per update (Hastings write-back of the forward):
@@ -404,18 +405,24 @@ extern "C" size_t mps_tebd_grad_arena_bytes(int32_t L, int32_t d, int32_t chi_ma
   return GradArena(L, d, chi_max, n_steps).total;
 }
 
-extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0,
-                                    double dt, int32_t n_steps, double eps_local, double eta, const void* op1,
-                                    int32_t site, const void* op2, void* arena_ptr, size_t arena_bytes,
-                                    double* loss_dev, double* dJ_dev) {
+// The adjoint of a TEBD2 run for the weighted loss
+//   sum_i w1[i] <op1 at i> + sum_b w2[b] <op2 on bond b>   (host weights);
+// obs_dev (optional) receives the 2L-1 final observables, loss_dev (optional)
+// the loss, dJ_dev the gradient.
+static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0,
+                                 double dt, int32_t n_steps, double eps_local, double eta, const void* op1,
+                                 const double* w1, const void* op2, const double* w2, void* arena_ptr,
+                                 size_t arena_bytes, double* obs_dev, double* loss_dev, double* dJ_dev) {
   if (!h) return MPS_ERR_INVALID;
-  if (!chain || !h0 || !op1 || !op2 || !loss_dev || !dJ_dev || !arena_ptr)
+  if (!chain || !h0 || !op1 || !op2 || !w1 || !w2 || !dJ_dev || !arena_ptr)
     return mps_fail(h, MPS_ERR_INVALID, "null pointer");
   const mps_chain_desc ch = *chain;
   if (ch.dtype != MPS_C128) return mps_fail(h, MPS_ERR_UNSUPPORTED, "the gradient needs a complex128 chain");
   if (ch.L < 2 || ch.d < 1 || ch.d > 5 || ch.chi_max < 1) return mps_fail(h, MPS_ERR_SHAPE, "bad chain shape");
   if ((int64_t)ch.d * ch.chi_max > 2560) return mps_fail(h, MPS_ERR_CAPACITY, "d*chi_max is limited to 2560");
-  if (site < 0 || site >= ch.L) return mps_fail(h, MPS_ERR_INVALID, "site out of range");
+  for (int i = 0; i < ch.L; ++i)
+    if (!std::isfinite(w1[i]) || (i + 1 < ch.L && !std::isfinite(w2[i])))
+      return mps_fail(h, MPS_ERR_INVALID, "non-finite loss weight");
   if (n_steps < 1) return mps_fail(h, MPS_ERR_INVALID, "n_steps must be >= 1");
   if (!(eta >= 0.0) || !(dt > 0.0) || !(eps_local >= 0.0)) return mps_fail(h, MPS_ERR_INVALID, "bad dt, eps or eta");
   const int L = ch.L, d = ch.d, cm = ch.chi_max, dd = d * d;
@@ -498,24 +505,31 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
     std::vector<double> o(2 * L);
     MPS_TRY_HIP(h, hipMemcpyAsync(o.data(), g.obs, (2 * L - 1) * sizeof(double), hipMemcpyDeviceToHost, s));
     MPS_TRY_HIP(h, hipStreamSynchronize(s));
-    double loss = o[site];
-    for (int b = 0; b < L - 1; ++b) loss += o[L + b];
-    MPS_TRY_HIP(h, hipMemcpyAsync(loss_dev, &loss, sizeof(double), hipMemcpyHostToDevice, s));
+    double loss = 0.0;
+    for (int i = 0; i < L; ++i) loss += w1[i] * o[i];
+    for (int b = 0; b < L - 1; ++b) loss += w2[b] * o[L + b];
+    if (loss_dev) MPS_TRY_HIP(h, hipMemcpyAsync(loss_dev, &loss, sizeof(double), hipMemcpyHostToDevice, s));
+    if (obs_dev) MPS_TRY_HIP(h, hipMemcpyAsync(obs_dev, g.obs, (2 * L - 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
     MPS_TRY_HIP(h, hipStreamSynchronize(s));
   }
   K1((fill_zero_kernel<<<g1d((long long)L * site_el), 256, 0, s>>>(Bbar, (long long)L * site_el)));
   MPS_TRY_HIP(h, hipMemsetAsync(lbar, 0, (L + 1) * cm * sizeof(double), s));
-  {
-    // site term <O1>_i = sum_a lam_a^2 <B_a|O1|B_a>: B_bar += 2 lam^2 O1 B, lam_bar += 2 lam Re<B, O1 B>
-    const int i = site, a = chi[i], b2 = chi[i + 1];
+  for (int i = 0; i < L; ++i) {
+    if (w1[i] == 0.0) continue;
+    // site term w <O1>_i = w sum_a lam_a^2 <B_a|O1|B_a>: B_bar += 2 w lam^2 O1 B, lam_bar += 2 w lam Re<B, O1 B>
+    const int a = chi[i], b2 = chi[i + 1];
     K1((site_copy_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>((const double2*)ch.B + i * site_el, g0.Bbs, a, d,
                                                                      b2, cm, 1)));
     K1((apply_local_kernel<<<g1d((long long)a * b2), 256, 0, s>>>((const double2*)op1, d, g0.Bbs, g0.T0, a, b2, 0, 0)));
     K1((row_scale_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>(g0.T0, bbar(i), a * d, b2, ch.lam + (size_t)i * cm,
-                                                                     d, 2, 2.0, 1)));
-    K1((lam_dot_kernel<<<a, 256, 0, s>>>(g0.Bbs, g0.T0, d, b2, lbar + (size_t)i * cm, ch.lam + (size_t)i * cm, 2.0)));
-    // bond terms <theta|O2|theta>, theta = lam_b B_b B_{b+1}
+                                                                     d, 2, 2.0 * w1[i], 1)));
+    K1((lam_dot_kernel<<<a, 256, 0, s>>>(g0.Bbs, g0.T0, d, b2, lbar + (size_t)i * cm, ch.lam + (size_t)i * cm,
+                                         2.0 * w1[i])));
+  }
+  {
+    // bond terms w <theta|O2|theta>, theta = lam_b B_b B_{b+1}
     for (int b = 0; b < L - 1; ++b) {
+      if (w2[b] == 0.0) continue;
       const int chl = chi[b], chm = chi[b + 1], chr = chi[b + 2], m = chl * d, n = d * chr;
       K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>((const double2*)ch.B + b * site_el, g0.Bbs, chl, d,
                                                                     chm, cm, 1)));
@@ -526,10 +540,10 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
                                                                   0)));
       K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>((const double2*)op2, dd, g0.T1, g0.P0, chl, chr,
                                                                         0, 0)));
-      // theta_bar = 2 O2 theta; lam_bar_b += Re<theta_bar, X>; X_bar = lam_b theta_bar
-      K1((lam_dot_kernel<<<chl, 256, 0, s>>>(g0.P0, g0.T0, d, n, lbar + (size_t)b * cm, nullptr, 2.0)));
-      K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g0.P0, g0.Pb, m, n, ch.lam + (size_t)b * cm, d, 1, 2.0,
-                                                                  0)));
+      // theta_bar = 2 w O2 theta; lam_bar_b += Re<theta_bar, X>; X_bar = lam_b theta_bar
+      K1((lam_dot_kernel<<<chl, 256, 0, s>>>(g0.P0, g0.T0, d, n, lbar + (size_t)b * cm, nullptr, 2.0 * w2[b])));
+      K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g0.P0, g0.Pb, m, n, ch.lam + (size_t)b * cm, d, 1,
+                                                                  2.0 * w2[b], 0)));
       if ((r = gemm128(c, g0.Pb, n, 1, 0, g0.Bns, 1, n, 1, g0.Y1, chm, m, chm, n, 1.0)) != MPS_OK) return r;
       if ((r = gemm128(c, g0.Bbs, 1, chm, 1, g0.Pb, n, 1, 0, g0.Z, n, chm, n, m, 1.0)) != MPS_OK) return r;
       K1((axpy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>(g0.Y1, bbar(b), (long long)m * chm, 1.0)));
@@ -717,4 +731,27 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
   if ((r = restore(arena + A.oCk + (size_t)n_steps * A.snap)) != MPS_OK) return r;
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
   return MPS_OK;
+}
+
+extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0,
+                                    double dt, int32_t n_steps, double eps_local, double eta, const void* op1,
+                                    int32_t site, const void* op2, void* arena_ptr, size_t arena_bytes,
+                                    double* loss_dev, double* dJ_dev) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!chain || !loss_dev) return mps_fail(h, MPS_ERR_INVALID, "null pointer");
+  if (site < 0 || site >= chain->L) return mps_fail(h, MPS_ERR_INVALID, "site out of range");
+  std::vector<double> w1(chain->L, 0.0), w2(chain->L - 1, 1.0);
+  w1[site] = 1.0;
+  return tebd_grad_impl(h, stream, chain, h0, dt, n_steps, eps_local, eta, op1, w1.data(), op2, w2.data(), arena_ptr,
+                        arena_bytes, nullptr, loss_dev, dJ_dev);
+}
+
+extern "C" mps_status mps_tebd_vjp(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0,
+                                   double dt, int32_t n_steps, double eps_local, double eta, const void* op1,
+                                   const double* w_site, const void* op2, const double* w_bond, void* arena_ptr,
+                                   size_t arena_bytes, double* obs_dev, double* dJ_dev) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!chain || chain->L < 2) return mps_fail(h, MPS_ERR_INVALID, "null or short chain");
+  return tebd_grad_impl(h, stream, chain, h0, dt, n_steps, eps_local, eta, op1, w_site, op2, w_bond, arena_ptr,
+                        arena_bytes, obs_dev, nullptr, dJ_dev);
 }
