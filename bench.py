@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--jac-threads", type=int, default=512, choices=[256, 512],
                     help="threads per Jacobi-round workgroup (two waves per SIMD at 512)")
+    ap.add_argument("--autotune", default=None, metavar="CACHE_JSON",
+                    help="xxz_tebd4_L64: autotune the Jacobi for the chi=256 layer (32 x 512 x 512) first, with "
+                         "this JSON cache")
     ap.add_argument("--split", default="svd", choices=["svd", "eig"],
                     help="two-site split of matrices of at most 64 rows: one-sided Jacobi SVD or the "
                          "eigendecomposition of the Gram")
@@ -102,6 +105,7 @@ def main():
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
     h.set_option(7, 1.0 if args.split == "eig" else 0.0)
+    tuned = api.autotune(h, 32, 512, 512, apply=True, cache=args.autotune) if args.autotune else None
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
 
     start_step = 0
@@ -167,7 +171,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "xxz_tebd4_L64: TEBD4 XXZ L=64 Jxy=1 Jz=0.5 Neel dt=0.05 chi_max=256 eps=1e-12",
                    "updates_per_step": updates_per_step, "start_step": start_step,
-                   "jacobi_threads": args.jac_threads,
+                   "jacobi_threads": args.jac_threads, "autotune": tuned,
                    "chi_hist": {"max": int(chi.max()), "mean": round(float(chi.mean()), 1),
                                 "n_at_cap": int((chi >= spec.chi_max).sum())}},
         "roofline": {"kernel": "jac_round_kernel (FP64 block-Jacobi round: Gram + rotation)",

@@ -102,6 +102,26 @@ mps_status mps_kernel_stats(mps_handle h, mps_stream stream, int32_t kernel, dou
                             int64_t* launches, uint64_t* work, int32_t reset);
 
 /*
+ * Autotuner of the Jacobi launch configuration for one shape bucket: n_mats
+ * matrices of m x n (the split of one batched layer).  Each candidate runs the
+ * whole split (preparation, sweeps, selection) on the same seeded synthetic
+ * matrices with graded rows, timed with HIP events after one untimed run:
+ * 256 or 512 threads per round workgroup (option 5), column split below 0, 32
+ * or 128 panel pairs (option 6) and, for m <= 64, the one-sided Jacobi or the
+ * eigendecomposition split (option 7).  apply != 0 leaves the fastest in the
+ * handle (else the handle's settings are restored).
+ *   times_ms     : HOST [*n_candidates] on entry its capacity (12 suffice);
+ *                  on return the count used and the times in candidate order
+ *   best         : HOST int32, index of the fastest candidate
+ * mps_autotune_candidate(m, index, ...) gives candidate `index`'s settings.
+ * Uses the workspace; synchronises `stream`.
+ */
+mps_status mps_autotune_jacobi(mps_handle h, mps_stream stream, int32_t n_mats, int32_t m, int32_t n,
+                               int32_t apply, double* times_ms, int32_t* n_candidates, int32_t* best);
+mps_status mps_autotune_candidate(int32_t m, int32_t index, int32_t* threads, int32_t* split_below,
+                                  int32_t* method);
+
+/*
  * Bond propagators G_n = exp(-i tau_n h_n)   (the local two-site
  * propagator, step 2 of the plain TEBD update in App. "Details of the Krylov
  * method"; built by a Hermitian

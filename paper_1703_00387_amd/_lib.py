@@ -26,7 +26,8 @@ MPS_C64, MPS_C128 = 0, 1
 EXPORTS = ["mps_create", "mps_destroy", "mps_last_error", "mps_reserve", "mps_device_status",
            "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_tebd_step", "mps_ktebd_step", "mps_tebd_td_step", "mps_cfme_nodes",
            "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step",
-           "mps_tebd_grad_arena_bytes", "mps_tebd_grad", "mps_tebd_vjp"]
+           "mps_tebd_grad_arena_bytes", "mps_tebd_grad", "mps_tebd_vjp", "mps_autotune_jacobi",
+           "mps_autotune_candidate"]
 
 
 class ChainDesc(C.Structure):
@@ -71,6 +72,8 @@ def lib():
         "mps_ktebd_step": [vp, vp, C.POINTER(ChainDesc), i32, dbl, i32, dbl, i32, dbl, u32, vp],
         "mps_tebd_td_step": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32, i32, i32, vp, vp],
         "mps_cfme_nodes": [i32, vp, vp],
+        "mps_autotune_jacobi": [vp, vp, i32, i32, i32, i32, vp, vp, vp],
+        "mps_autotune_candidate": [i32, i32, vp, vp, vp],
         "mps_observe": [vp, vp, C.POINTER(ChainDesc), vp, vp, vp, i32, vp, vp],
         "mps_heff_apply": [vp, vp, i32, vp, vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, i32, i32],
         "mps_krylov_expm": [vp, vp, i32, vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, i32, i32, dbl, dbl, i32, dbl,

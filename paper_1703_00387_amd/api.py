@@ -291,6 +291,44 @@ class TebdObservables(torch.autograd.Function):
         return (dJ.to(J.dtype),) + (None,) * 10
 
 
+def autotune(h: Handle, n_mats: int, m: int, n: int, apply: bool = True, cache: str = None):
+    """Time the Jacobi launch configurations on a seeded synthetic batch of
+    n_mats m x n matrices (mps_autotune_jacobi) and, with apply, leave the
+    fastest in the handle.  With a JSON cache path, a bucket measured before on
+    the same device model is applied from the cache without timing.
+    Returns {"threads", "split_below", "method", "times_ms", "cached"}."""
+    import json
+    import os
+    key = f"{torch.cuda.get_device_name(h.device) if torch.cuda.is_available() else 'cpu'}|{n_mats}|{m}|{n}"
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+    if key in table:
+        r = dict(table[key])
+        if apply:
+            h.set_option(5, r["threads"])
+            h.set_option(6, r["split_below"])
+            h.set_option(7, r["method"])
+        r["cached"] = True
+        return r
+    cap = C.c_int32(12)
+    times = (C.c_double * 12)()
+    best = C.c_int32(-1)
+    h.check(lib().mps_autotune_jacobi(h.h, _stream(), n_mats, m, n, 1 if apply else 0, times, C.byref(cap),
+                                      C.byref(best)))
+    t, sb, me = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    check(h.h, lib().mps_autotune_candidate(m, best.value, C.byref(t), C.byref(sb), C.byref(me)))
+    r = {"threads": t.value, "split_below": sb.value, "method": me.value,
+         "times_ms": [round(times[i], 4) for i in range(cap.value)]}
+    if cache:
+        table[key] = r
+        with open(cache, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    r["cached"] = False
+    return r
+
+
 def _code(t):
     return _lib.MPS_C128 if t.dtype == torch.complex128 else _lib.MPS_C64
 
