@@ -184,3 +184,111 @@ __device__ __forceinline__ int herm_jacobi32(double2* G, double2* Q, int n, doub
   if (n <= 16) return herm_jacobi<16, JS_LD>(G, Q, n, abs_thr, rel_thr, max_sweeps, rot, flag);
   return herm_jacobi<32, JS_LD>(G, Q, n, abs_thr, rel_thr, max_sweeps, rot, flag);
 }
+
+// Order 64: herm_jacobi<64> (same ordering, thresholds, rotations and order
+// of operations, so the same results) arranged for the case that matters in
+// the block Jacobi, where the 64 x 64 Gram is nearly diagonal and only a few
+// of a step's 32 pairs rotate.  The 32 lanes that form the step's rotations
+// also list the rotating pairs; the column and row passes then run over the
+// items (listed pair, row or column) spread evenly over the workgroup, and a
+// step with no rotation costs one barrier.  The step's rotations, pairs and
+// list are double-buffered by the step's parity, so the next step can start
+// forming its own while a slower wave still reads them.
+// scr: LDS scratch of at least kJac64Scratch double2.
+constexpr int kJac64Scratch = 2 * (32 * 2 + 32 / 2 + 32 / 4 + 1);
+template <int NT, int LD = 65>
+__device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_thr, int max_sweeps,
+                             double2* scr, int* flag) {
+  constexpr int N = 64, NP = 32;
+  double4* rot = reinterpret_cast<double4*>(scr);             // [2][32]
+  int2* pq = reinterpret_cast<int2*>(rot + 2 * NP);            // [2][32]
+  int* list = reinterpret_cast<int*>(pq + 2 * NP);             // [2][32]
+  int* nrot = list + 2 * NP;                                   // [2]
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N * N; i += NT) {
+    const int r = i / N, c = i % N;
+    Q[r * LD + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int step = 0; step < N; ++step) {
+      const int bf = step & 1;
+      if (tid < 64) {  // wave 0 forms the step's rotations
+        int p = 0, q = 0;
+        bool rotating = false;
+        double4 r = make_double4(1.0, 0.0, 1.0, 0.0);  // cs, sn, e^{i phi}; identity
+        if (tid < NP && js_pair<N>(step, tid, p, q)) {
+          const double a = G[p * LD + p].x, b = G[q * LD + q].x;
+          const double2 c = G[p * LD + q];
+          const double ac2 = c.x * c.x + c.y * c.y;
+          const double thr2 = fmax(abs_thr * abs_thr, rel_thr * rel_thr * fabs(a * b));
+          if (ac2 > thr2 && ac2 > 0.0) {
+            const double iac = 1.0 / sqrt(ac2);
+            const double tau = 0.5 * (b - a) * iac;
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double cs = 1.0 / sqrt(1.0 + t * t);
+            r = make_double4(cs, t * cs, c.x * iac, c.y * iac);
+            rotating = true;
+          }
+        }
+        const unsigned long long m = __ballot(rotating);
+        if (tid < NP) {
+          rot[bf * NP + tid] = r;
+          pq[bf * NP + tid] = make_int2(p, q);
+        }
+        if (rotating) list[bf * NP + __popcll(m & ((1ull << tid) - 1ull))] = tid;
+        if (tid == 0) {
+          nrot[bf] = __popcll(m);
+          if (m) *flag = 1;
+        }
+      }
+      __syncthreads();
+      const int nr = nrot[bf];
+      if (nr == 0) continue;  // the same for every thread
+      // columns: G <- G J and Q <- Q J, item (listed pair, row)
+      for (int i = tid; i < nr * N; i += NT) {
+        const int k = list[bf * NP + (i >> 6)], rc = i & 63;
+        const double4 r = rot[bf * NP + k];
+        const int2 kk = pq[bf * NP + k];
+        const double2 gp = G[rc * LD + kk.x], gq = G[rc * LD + kk.y];
+        const double2 qp = Q[rc * LD + kk.x], qv = Q[rc * LD + kk.y];
+        const double2 em = make_double2(r.z, -r.w);  // e^{-i phi}
+        const double2 gqe = cmul(gq, em), qqe = cmul(qv, em);
+        G[rc * LD + kk.x] = make_double2(r.x * gp.x - r.y * gqe.x, r.x * gp.y - r.y * gqe.y);
+        G[rc * LD + kk.y] = make_double2(r.y * gp.x + r.x * gqe.x, r.y * gp.y + r.x * gqe.y);
+        Q[rc * LD + kk.x] = make_double2(r.x * qp.x - r.y * qqe.x, r.x * qp.y - r.y * qqe.y);
+        Q[rc * LD + kk.y] = make_double2(r.y * qp.x + r.x * qqe.x, r.y * qp.y + r.x * qqe.y);
+      }
+      __syncthreads();
+      // rows: G <- J^dag G, item (listed pair, column); the pair's own entries exactly
+      for (int i = tid; i < nr * N; i += NT) {
+        const int k = list[bf * NP + (i >> 6)], rc = i & 63;
+        const double4 r = rot[bf * NP + k];
+        const int2 kk = pq[bf * NP + k];
+        const double2 gp = G[kk.x * LD + rc], gq = G[kk.y * LD + rc];
+        const double2 ep = make_double2(r.z, r.w);  // e^{+i phi}
+        const double2 gqe = cmul(gq, ep);
+        double2 np_ = make_double2(r.x * gp.x - r.y * gqe.x, r.x * gp.y - r.y * gqe.y);
+        double2 nq_ = make_double2(r.y * gp.x + r.x * gqe.x, r.y * gp.y + r.x * gqe.y);
+        if (rc == kk.x) {
+          np_.y = 0.0;
+          nq_ = make_double2(0.0, 0.0);
+        } else if (rc == kk.y) {
+          np_ = make_double2(0.0, 0.0);
+          nq_.y = 0.0;
+        }
+        G[kk.x * LD + rc] = np_;
+        G[kk.y * LD + rc] = nq_;
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (*flag == 0) break;
+    __syncthreads();
+  }
+  __syncthreads();
+  return sweep;
+}

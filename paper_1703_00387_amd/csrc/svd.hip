@@ -226,7 +226,7 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
   constexpr int kLdsElems = (JP * (JP + 1) > 4 * TBK * TLD) ? JP * (JP + 1) : 4 * TBK * TLD;
   __shared__ double2 G[kLdsElems];  // Gram matrix; staging of the update afterwards
   __shared__ double2 Q[kLdsElems];  // staging of the Gram; then the panel rotation
-  __shared__ double4 rot[JP / 2];
+  __shared__ double2 rotw[kJac64Scratch];  // rotations, index pairs and lists of the inner solve
   __shared__ int rows_s[JP];
   __shared__ int flag;
   __shared__ int need;
@@ -373,14 +373,14 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
   if (loop_sweeps > 0 && m <= JB) {
     // a matrix of at most 32 rows: the 32x32 solve on the leading block (the
     // other rows are zero), Q the identity elsewhere
-    herm_jacobi<JB, JP + 1, NT>(G, Q, JB, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
+    herm_jacobi<JB, JP + 1, NT>(G, Q, JB, 0.25 * abs_thr, tol, inner_sweeps, reinterpret_cast<double4*>(rotw), &flag);
     for (int e = tid; e < JP * JP; e += NT) {
       const int i = e / JP, j = e % JP;
       if (i >= JB || j >= JB) Q[i * (JP + 1) + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
   } else {
-    herm_jacobi<JP, JP + 1, NT>(G, Q, JP, 0.25 * abs_thr, tol, inner_sweeps, rot, &flag);
+    herm_jacobi64<NT, JP + 1>(G, Q, 0.25 * abs_thr, tol, inner_sweeps, rotw, &flag);
   }
   // the rotated rows have squared norms diag(Q^dag G Q), left on G's diagonal
   if (tid < JP && rows_s[tid] >= 0 && slice == 0) M->nrm2[rows_s[tid]] = G[tid * (JP + 1) + tid].x;
