@@ -188,22 +188,25 @@ __device__ __forceinline__ int herm_jacobi32(double2* G, double2* Q, int n, doub
 // Order 64: herm_jacobi<64> (same ordering, thresholds, rotations and order
 // of operations, so the same results) arranged for the case that matters in
 // the block Jacobi, where the 64 x 64 Gram is nearly diagonal and only a few
-// of a step's 32 pairs rotate.  The 32 lanes that form the step's rotations
-// also list the rotating pairs; the column and row passes then run over the
-// items (listed pair, row or column) spread evenly over the workgroup, and a
-// step with no rotation costs one barrier.  The step's rotations, pairs and
-// list are double-buffered by the step's parity, so the next step can start
-// forming its own while a slower wave still reads them.
+// of a step's 32 pairs rotate (about 4 on average in TEBD).  A step is then
+// bound by its chain of dependent LDS round trips, not by arithmetic:
+//  * the 32 lanes that form the step's rotations also list the rotating
+//    pairs, with their rotation and indices (p, q), in LDS;
+//  * the column and row passes run over the items (listed pair, row or
+//    column) spread evenly over the workgroup; a thread reads its items'
+//    records once, together with the count, and keeps them for both passes;
+//  * a step with no rotation costs one barrier.
+// The list is double-buffered by the step's parity, so the next step can
+// start forming its own while a slower wave still reads it.
 // scr: LDS scratch of at least kJac64Scratch double2.
-constexpr int kJac64Scratch = 2 * (32 * 2 + 32 / 2 + 32 / 4 + 1);
+constexpr int kJac64Scratch = 2 * (32 * 2 + 32 / 2) + 1;
 template <int NT, int LD = 65>
 __device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_thr, int max_sweeps,
                              double2* scr, int* flag) {
-  constexpr int N = 64, NP = 32;
-  double4* rot = reinterpret_cast<double4*>(scr);             // [2][32]
-  int2* pq = reinterpret_cast<int2*>(rot + 2 * NP);            // [2][32]
-  int* list = reinterpret_cast<int*>(pq + 2 * NP);             // [2][32]
-  int* nrot = list + 2 * NP;                                   // [2]
+  constexpr int N = 64, NP = 32, MI = N * NP / NT;  // MI: items per thread at most
+  double4* lrot = reinterpret_cast<double4*>(scr);  // [2][32] rotation of listed pair j: cs, sn, e^{i phi}
+  int2* lpq = reinterpret_cast<int2*>(lrot + 2 * NP);  // [2][32] its (p, q)
+  int* nrot = reinterpret_cast<int*>(lpq + 2 * NP);    // [2]
   const int tid = threadIdx.x;
   for (int i = tid; i < N * N; i += NT) {
     const int r = i / N, c = i % N;
@@ -216,10 +219,10 @@ __device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_
     __syncthreads();
     for (int step = 0; step < N; ++step) {
       const int bf = step & 1;
-      if (tid < 64) {  // wave 0 forms the step's rotations
+      if (tid < 64) {  // wave 0 forms and lists the step's rotations
         int p = 0, q = 0;
         bool rotating = false;
-        double4 r = make_double4(1.0, 0.0, 1.0, 0.0);  // cs, sn, e^{i phi}; identity
+        double4 r = make_double4(1.0, 0.0, 1.0, 0.0);
         if (tid < NP && js_pair<N>(step, tid, p, q)) {
           const double a = G[p * LD + p].x, b = G[q * LD + q].x;
           const double2 c = G[p * LD + q];
@@ -235,24 +238,36 @@ __device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_
           }
         }
         const unsigned long long m = __ballot(rotating);
-        if (tid < NP) {
-          rot[bf * NP + tid] = r;
-          pq[bf * NP + tid] = make_int2(p, q);
+        if (rotating) {
+          const int j = __popcll(m & ((1ull << tid) - 1ull));
+          lrot[bf * NP + j] = r;
+          lpq[bf * NP + j] = make_int2(p, q);
         }
-        if (rotating) list[bf * NP + __popcll(m & ((1ull << tid) - 1ull))] = tid;
         if (tid == 0) {
           nrot[bf] = __popcll(m);
           if (m) *flag = 1;
         }
       }
       __syncthreads();
+      // this thread's items i = tid + u NT: listed pair i / 64 at row (column) i % 64;
+      // the records are read with the count (entries past it are not used)
       const int nr = nrot[bf];
+      double4 ir[MI];
+      int2 ik[MI];
+#pragma unroll
+      for (int u = 0; u < MI; ++u) {
+        const int j = (tid + u * NT) >> 6;
+        ir[u] = lrot[bf * NP + j];
+        ik[u] = lpq[bf * NP + j];
+      }
       if (nr == 0) continue;  // the same for every thread
-      // columns: G <- G J and Q <- Q J, item (listed pair, row)
-      for (int i = tid; i < nr * N; i += NT) {
-        const int k = list[bf * NP + (i >> 6)], rc = i & 63;
-        const double4 r = rot[bf * NP + k];
-        const int2 kk = pq[bf * NP + k];
+      const int rc = tid & 63;
+      // columns: G <- G J and Q <- Q J
+#pragma unroll
+      for (int u = 0; u < MI; ++u) {
+        if (((tid + u * NT) >> 6) >= nr) break;
+        const double4 r = ir[u];
+        const int2 kk = ik[u];
         const double2 gp = G[rc * LD + kk.x], gq = G[rc * LD + kk.y];
         const double2 qp = Q[rc * LD + kk.x], qv = Q[rc * LD + kk.y];
         const double2 em = make_double2(r.z, -r.w);  // e^{-i phi}
@@ -263,11 +278,12 @@ __device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_
         Q[rc * LD + kk.y] = make_double2(r.y * qp.x + r.x * qqe.x, r.y * qp.y + r.x * qqe.y);
       }
       __syncthreads();
-      // rows: G <- J^dag G, item (listed pair, column); the pair's own entries exactly
-      for (int i = tid; i < nr * N; i += NT) {
-        const int k = list[bf * NP + (i >> 6)], rc = i & 63;
-        const double4 r = rot[bf * NP + k];
-        const int2 kk = pq[bf * NP + k];
+      // rows: G <- J^dag G; the pair's own entries exactly
+#pragma unroll
+      for (int u = 0; u < MI; ++u) {
+        if (((tid + u * NT) >> 6) >= nr) break;
+        const double4 r = ir[u];
+        const int2 kk = ik[u];
         const double2 gp = G[kk.x * LD + rc], gq = G[kk.y * LD + rc];
         const double2 ep = make_double2(r.z, r.w);  // e^{+i phi}
         const double2 gqe = cmul(gq, ep);
