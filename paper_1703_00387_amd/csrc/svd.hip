@@ -298,8 +298,11 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
     // G is Hermitian: only its 10 upper 16x16 tiles are formed (3, 3, 2 and 2
     // per wave of a group) and the lower ones are written as their conjugate
     // transposes.
+    // The second group takes the tile sets in the order 2, 3, 0, 1, so that
+    // the two waves sharing a SIMD (waves w and w + 4) hold 3 + 2 tiles
+    // between them and every SIMD issues the same number of MFMAs.
     int ti[3], tj[3], nt;
-    gram_tiles(wave, ti, tj, nt);
+    gram_tiles(grp ? (wave + 2) & 3 : wave, ti, tj, nt);
     HermAcc hacc;
     herm_acc_zero(hacc);
     // every thread passes the same barriers: nloc_max iterations for both groups
