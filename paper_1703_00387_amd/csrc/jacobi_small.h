@@ -213,6 +213,10 @@ __device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_
     Q[r * LD + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
+  // wave 0: the pair of lane tid in the coming step, formed while the
+  // previous step's writes drain
+  int p = 0, q = 0;
+  bool valid = tid < NP && js_pair<N>(0, tid, p, q);
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) *flag = 0;
@@ -220,10 +224,9 @@ __device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_
     for (int step = 0; step < N; ++step) {
       const int bf = step & 1;
       if (tid < 64) {  // wave 0 forms and lists the step's rotations
-        int p = 0, q = 0;
         bool rotating = false;
         double4 r = make_double4(1.0, 0.0, 1.0, 0.0);
-        if (tid < NP && js_pair<N>(step, tid, p, q)) {
+        if (valid) {
           const double a = G[p * LD + p].x, b = G[q * LD + q].x;
           const double2 c = G[p * LD + q];
           const double ac2 = c.x * c.x + c.y * c.y;
@@ -247,6 +250,9 @@ __device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_
           nrot[bf] = __popcll(m);
           if (m) *flag = 1;
         }
+        p = 0;
+        q = 0;
+        valid = tid < NP && js_pair<N>(step + 1 < N ? step + 1 : 0, tid, p, q);
       }
       __syncthreads();
       // this thread's items i = tid + u NT: listed pair i / 64 at row (column) i % 64;

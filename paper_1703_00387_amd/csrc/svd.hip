@@ -197,6 +197,56 @@ __device__ __forceinline__ void herm_acc_add_lds(const HermAcc& acc, double2* Gs
   }
 }
 
+// The rotation's complex products with three real MFMAs instead of four
+// (Gauss): for a = ar + i ai and b = br + i bi, t1 = ar br, t2 = ai bi,
+// t3 = (ar + ai)(br + bi), then Re ab = t1 - t2 and Im ab = t3 - t1 - t2.
+struct RotAcc {
+  doublex4 t1[2][2], t2[2][2], t3[2][2];
+};
+
+__device__ __forceinline__ void rot_acc_zero(RotAcc& a) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a.t1[i][j][r] = 0.0;
+        a.t2[i][j][r] = 0.0;
+        a.t3[i][j][r] = 0.0;
+      }
+}
+
+// One staged K-chunk: C(m, n) += sum_k A(k, m) B(k, n), A(k, m) = Al[k * lda + m].
+__device__ __forceinline__ void rot_mma_chunk(const double2* __restrict__ Al, int lda,
+                                              const double2* __restrict__ Bs, RotAcc& acc, int wm, int wn,
+                                              int lane) {
+#pragma unroll
+  for (int kk = 0; kk < TBK / 4; ++kk) {
+    const int kr = kk * 4 + (lane >> 4);
+    double2 a[2], b[2];
+    double as[2], bs[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = Al[kr * lda + wm + i * 16 + (lane & 15)];
+      as[i] = a[i].x + a[i].y;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      b[j] = Bs[kr * TLD + wn + j * 16 + (lane & 15)];
+      bs[j] = b[j].x + b[j].y;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc.t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc.t1[i][j], 0, 0, 0);
+        acc.t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc.t2[i][j], 0, 0, 0);
+        acc.t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], bs[j], acc.t3[i][j], 0, 0, 0);
+      }
+  }
+}
+
 // One round of the block Jacobi (loop_sweeps == 0), or, for matrices of one
 // 64-row panel (nb == 2), up to loop_sweeps complete sweeps in one launch
 // (loop_sweeps > 0): the panel's only pair is re-formed, solved and rotated
@@ -420,8 +470,8 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
       if (u < nsteps) load(u, v[u]);
     if (nsteps > 0) store(Bs0, v[0]);
     __syncthreads();
-    AccTile<double2> acc;
-    acc_zero<double2>(acc);
+    RotAcc acc;
+    rot_acc_zero(acc);
     // every thread passes the same barriers: nsteps_max iterations for both groups
     for (int base = 0; base < nsteps_max; base += kPf) {
 #pragma unroll
@@ -431,7 +481,7 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
           if (st < nsteps) {
           const int c0 = (cb0 + (st / PCH) * NG + grp) * TBN, p0 = (st % PCH) * TBK;
           if (st + kPf < nsteps) load(st + kPf, v[u]);
-          mma_chunk_lda<double2>(Q + p0 * (JP + 1), JP + 1, (st & 1) ? Bs1 : Bs0, acc, wm, wn, lane);
+          rot_mma_chunk(Q + p0 * (JP + 1), JP + 1, (st & 1) ? Bs1 : Bs0, acc, wm, wn, lane);
           if (p0 + TBK == JP) {
             // the column block is complete: write its 64 rows (every load of
             // these columns was issued earlier), then start the next block
@@ -444,10 +494,12 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
                   int row = wm + i * 16 + Cx<double2>::acc_row(lane, r);
                   int col = c0 + wn + j * 16 + (lane & 15);
                   int g = rows_s[row];
-                  if (g >= 0 && col < n)
-                    X[(size_t)g * ld + col] = make_double2(acc.re[i][j][r], acc.im[i][j][r]);
+                  if (g >= 0 && col < n) {
+                    const double t1 = acc.t1[i][j][r], t2 = acc.t2[i][j][r];
+                    X[(size_t)g * ld + col] = make_double2(t1 - t2, acc.t3[i][j][r] - t1 - t2);
+                  }
                 }
-            acc_zero<double2>(acc);
+            rot_acc_zero(acc);
           }
           if (st + 1 < nsteps) store((st & 1) ? Bs0 : Bs1, v[(u + 1) % kPf]);
           }
