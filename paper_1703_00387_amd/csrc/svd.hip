@@ -113,8 +113,11 @@ __global__ __launch_bounds__(256) void jac_prep_plain_kernel(JacMat* __restrict_
 
 // Hermitian 64x64 Gram on FP64 MFMA: the 10 upper 16x16 tiles (ti <= tj)
 // shared out 3, 3, 2, 2 over the four waves.
+// Gram accumulators of a wave's (up to) three tiles, three real products per
+// complex one: for conj(a) b, t1 = ar br, t2 = ai bi, t3 = (ar - ai)(br + bi),
+// Re = t1 + t2, Im = t3 - t1 + t2.
 struct HermAcc {
-  doublex4 re[3], im[3];
+  doublex4 t1[3], t2[3], t3[3];
 };
 
 __device__ __forceinline__ void gram_tiles(int wave, int* ti, int* tj, int& nt) {
@@ -134,13 +137,13 @@ __device__ __forceinline__ void herm_acc_zero(HermAcc& a) {
   for (int u = 0; u < 3; ++u)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      a.re[u][r] = 0.0;
-      a.im[u][r] = 0.0;
+      a.t1[u][r] = 0.0;
+      a.t2[u][r] = 0.0;
+      a.t3[u][r] = 0.0;
     }
 }
 
-// One staged K-chunk Bs[TBK][TLD] of the 64 rows: G_ij += sum_k conj(x_ik) x_jk,
-// i.e. re += a.x b.x + a.y b.y and im += a.x b.y - a.y b.x.
+// One staged K-chunk Bs[TBK][TLD] of the 64 rows: G_ij += sum_k conj(x_ik) x_jk.
 __device__ __forceinline__ void herm_mma_chunk(const double2* __restrict__ Bs, HermAcc& acc, const int* ti,
                                                const int* tj, int nt, int lane) {
 #pragma unroll
@@ -151,10 +154,9 @@ __device__ __forceinline__ void herm_mma_chunk(const double2* __restrict__ Bs, H
       if (u < nt) {
         const double2 a = Bs[kr * TLD + ti[u] * 16 + (lane & 15)];
         const double2 b = Bs[kr * TLD + tj[u] * 16 + (lane & 15)];
-        acc.re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc.re[u], 0, 0, 0);
-        acc.im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acc.im[u], 0, 0, 0);
-        acc.re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc.re[u], 0, 0, 0);
-        acc.im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, acc.im[u], 0, 0, 0);
+        acc.t1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc.t1[u], 0, 0, 0);
+        acc.t2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc.t2[u], 0, 0, 0);
+        acc.t3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x - a.y, b.x + b.y, acc.t3[u], 0, 0, 0);
       }
     }
   }
@@ -169,7 +171,8 @@ __device__ __forceinline__ void herm_acc_to_lds(const HermAcc& acc, double2* Gs,
     for (int r = 0; r < 4; ++r) {
       const int row = ti[u] * 16 + Cx<double2>::acc_row(lane, r);
       const int col = tj[u] * 16 + (lane & 15);
-      const double re = acc.re[u][r], im = acc.im[u][r];
+      const double t1 = acc.t1[u][r], t2 = acc.t2[u][r];
+      const double re = t1 + t2, im = acc.t3[u][r] - t1 + t2;
       Gs[row * ldg + col] = make_double2(re, im);
       if (ti[u] != tj[u]) Gs[col * ldg + row] = make_double2(re, -im);
     }
@@ -186,7 +189,8 @@ __device__ __forceinline__ void herm_acc_add_lds(const HermAcc& acc, double2* Gs
     for (int r = 0; r < 4; ++r) {
       const int row = ti[u] * 16 + Cx<double2>::acc_row(lane, r);
       const int col = tj[u] * 16 + (lane & 15);
-      const double re = acc.re[u][r], im = acc.im[u][r];
+      const double t1 = acc.t1[u][r], t2 = acc.t2[u][r];
+      const double re = t1 + t2, im = acc.t3[u][r] - t1 + t2;
       double2 g = Gs[row * ldg + col];
       Gs[row * ldg + col] = make_double2(g.x + re, g.y + im);
       if (ti[u] != tj[u]) {
