@@ -185,6 +185,30 @@ __device__ __forceinline__ int herm_jacobi32(double2* G, double2* Q, int n, doub
   return herm_jacobi<32, JS_LD>(G, Q, n, abs_thr, rel_thr, max_sweeps, rot, flag);
 }
 
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by
+// two Newton steps (quadratic convergence from the estimate; the last step
+// leaves about one ulp).  Four dependent FMAs each instead of the rounded
+// library square root and division.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double r = fma(-h * y, y, 0.5);
+    y = fma(y, r, y);
+  }
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+  }
+  return y;
+}
+
 // Order 64: herm_jacobi<64> (same ordering, thresholds, rotations and order
 // of operations, so the same results) arranged for the case that matters in
 // the block Jacobi, where the 64 x 64 Gram is nearly diagonal and only a few
@@ -232,10 +256,17 @@ __device__ int herm_jacobi64(double2* G, double2* Q, double abs_thr, double rel_
           const double ac2 = c.x * c.x + c.y * c.y;
           const double thr2 = fmax(abs_thr * abs_thr, rel_thr * rel_thr * fabs(a * b));
           if (ac2 > thr2 && ac2 > 0.0) {
-            const double iac = 1.0 / sqrt(ac2);
+            // the angle is on the step's critical path: t and the unit phase
+            // from refined reciprocal estimates (t needs no last-bit accuracy;
+            // cs = (1 + t^2)^(-1/2) and e^{i phi} = c / |c| keep the rotation
+            // unitary to about an ulp)
+            // (a coupling near the bottom of the normal range takes the
+            // library square root, which handles subnormal |c|^2)
+            const double iac = ac2 > 1e-280 ? rsqrt_nr(ac2) : 1.0 / sqrt(ac2);
             const double tau = 0.5 * (b - a) * iac;
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            const double cs = 1.0 / sqrt(1.0 + t * t);
+            const double w = fma(tau, tau, 1.0);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + w * rsqrt_nr(w));
+            const double cs = rsqrt_nr(fma(t, t, 1.0));
             r = make_double4(cs, t * cs, c.x * iac, c.y * iac);
             rotating = true;
           }
