@@ -54,55 +54,65 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
-__device__ double mat_fro2(const double2* X, int m, int n, int ld, double* red) {
-  double acc = 0.0;
-  for (size_t i = threadIdx.x; i < (size_t)m * n; i += blockDim.x) {
-    size_t r = i / n, c = i % n;
-    double2 v = X[r * ld + c];
-    acc += v.x * v.x + v.y * v.y;
-  }
-  return block_sum(acc, red);
-}
+// Preparation of the Jacobi, in three short launches so that reading X is
+// spread over many workgroups: the descriptors (batched TEBD: from the bond
+// items), the squared row norms (kRowSlices workgroups per matrix, one wave
+// per row), then |X|_F^2 as the sum of the row norms in a fixed order, the
+// natural row order, and the converged/non-finite flags.  The row norms also
+// stand in nrm2 until the first round rewrites them (a matrix that never
+// reaches a round, with non-finite input, keeps them for the selection).
+constexpr int kRowSlices = 16;
 
-__global__ __launch_bounds__(256) void jac_prep_bonds_kernel(const BondItem* __restrict__ items,
-                                                             JacMat* __restrict__ mats, int bs,
-                                                             int32_t* rowmap_ws, double* nrm_ws, int m_cap,
-                                                             uint32_t* status) {
-  __shared__ double red[256];
-  const BondItem it = items[blockIdx.x];
+__global__ void jac_desc_bonds_kernel(const BondItem* __restrict__ items, JacMat* __restrict__ mats, int n_items,
+                                      int bs, int32_t* rowmap_ws, double* nrm_ws, int m_cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  const BondItem it = items[i];
   const int d = it.d;
-  const int m = it.chi[it.b] * d, n = d * it.chi[it.b + 2];
-  double2* X = it.X;
-  double f2 = mat_fro2(X, m, n, n, red);
-  int32_t* rowmap = rowmap_ws + (size_t)blockIdx.x * m_cap;
-  for (int g = threadIdx.x; g < m; g += blockDim.x) rowmap[g] = g;  // the first sweep keeps the natural order
-  if (threadIdx.x == 0) {
-    JacMat M;
-    M.X = X;
-    M.rowmap = rowmap;
-    M.nrm2 = nrm_ws + (size_t)blockIdx.x * m_cap;
-    M.m = m;
-    M.n = n;
-    M.ld = n;
-    int nb = (m + bs - 1) / bs;
-    if (nb < 2) nb = 2;
-    if (nb & 1) nb++;
-    M.nb = nb;
-    M.rot = 0;
-    M.kmax = it.chi_max;
-    M.pad = 0;
-    M.fro2 = f2;
-    M.conv = (f2 == f2 && f2 < 1e300) ? 0 : 1;
-    if (M.conv) atomicOr(status, MPS_DEV_NONFINITE);
-    mats[blockIdx.x] = M;
+  JacMat M;
+  M.X = it.X;
+  M.rowmap = rowmap_ws + (size_t)i * m_cap;
+  M.nrm2 = nrm_ws + (size_t)i * m_cap;
+  M.m = it.chi[it.b] * d;
+  M.n = d * it.chi[it.b + 2];
+  M.ld = M.n;
+  int nb = (M.m + bs - 1) / bs;
+  if (nb < 2) nb = 2;
+  if (nb & 1) nb++;
+  M.nb = nb;
+  M.rot = 0;
+  M.kmax = it.chi_max;
+  M.pad = 0;
+  M.fro2 = 0.0;
+  M.conv = 0;
+  mats[i] = M;
+}
+
+// grid (n_mats, kRowSlices), 256 threads: wave w of slice s takes the rows
+// r = 4 s + w (mod 4 kRowSlices)
+__global__ __launch_bounds__(256) void jac_row_norms_kernel(const JacMat* __restrict__ mats) {
+  const JacMat& M = mats[blockIdx.x];
+  const int m = M.m, n = M.n, ld = M.ld, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = blockIdx.y * 4 + wave; r < m; r += 4 * kRowSlices) {
+    const double2* xr = M.X + (size_t)r * ld;
+    double a = 0.0;
+    for (int c = lane; c < n; c += 64) {
+      const double2 v = xr[c];
+      a += v.x * v.x + v.y * v.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (lane == 0) M.nrm2[r] = a;
   }
 }
 
-__global__ __launch_bounds__(256) void jac_prep_plain_kernel(JacMat* __restrict__ mats, uint32_t* status) {
+__global__ __launch_bounds__(256) void jac_fro_kernel(JacMat* __restrict__ mats, uint32_t* status) {
   __shared__ double red[256];
   JacMat* M = mats + blockIdx.x;
-  double f2 = mat_fro2(M->X, M->m, M->n, M->ld, red);
-  for (int g = threadIdx.x; g < M->m; g += blockDim.x) M->rowmap[g] = g;
+  const int m = M->m;
+  double a = 0.0;
+  for (int r = threadIdx.x; r < m; r += blockDim.x) a += M->nrm2[r];
+  const double f2 = block_sum(a, red);
+  for (int g = threadIdx.x; g < m; g += blockDim.x) M->rowmap[g] = g;  // the first sweep keeps the natural order
   if (threadIdx.x == 0) {
     M->fro2 = f2;
     M->rot = 0;
@@ -625,16 +635,11 @@ __global__ __launch_bounds__(256) void select_kernel(const JacMat* __restrict__ 
   double* s2 = dyn;                       // [m_cap]
   int* perm = (int*)(dyn + m_cap);        // [m_cap]
   const JacMat M = mats[blockIdx.x];
-  const int m = M.m, n = M.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int r = wave; r < m; r += 4) {
-    double a = 0.0;
-    for (int c = lane; c < n; c += 64) {
-      double2 v = M.X[(size_t)r * M.ld + c];
-      a += v.x * v.x + v.y * v.y;
-    }
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-    if (lane == 0) s2[r] = a;
-  }
+  const int m = M.m, tid = threadIdx.x;
+  // the squared row norms of the orthogonalised rows: the diagonal of the
+  // Gram that the last round formed from them (the converging sweep rotates
+  // nothing, so every row's entry comes from a Gram of its final values)
+  for (int r = tid; r < m; r += 256) s2[r] = M.nrm2[r];
   __syncthreads();
   // NaN or negative entries (only possible from non-finite input, already
   // flagged by the preparation) sort last as -1, so the ranks below form a
@@ -812,13 +817,16 @@ __global__ __launch_bounds__(256) void trunc_u_kernel(const double2* theta, cons
 hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
                                  int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status) {
   if (n_items <= 0) return hipSuccess;
-  jac_prep_bonds_kernel<<<n_items, 256, 0, s>>>(items, mats, bs, rowmap_ws, nrm_ws, m_cap, status);
+  jac_desc_bonds_kernel<<<(n_items + 63) / 64, 64, 0, s>>>(items, mats, n_items, bs, rowmap_ws, nrm_ws, m_cap);
+  jac_row_norms_kernel<<<dim3(n_items, kRowSlices), 256, 0, s>>>(mats);
+  jac_fro_kernel<<<n_items, 256, 0, s>>>(mats, status);
   return hipGetLastError();
 }
 
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status) {
   if (n_mats <= 0) return hipSuccess;
-  jac_prep_plain_kernel<<<n_mats, 256, 0, s>>>(mats, status);
+  jac_row_norms_kernel<<<dim3(n_mats, kRowSlices), 256, 0, s>>>(mats);
+  jac_fro_kernel<<<n_mats, 256, 0, s>>>(mats, status);
   return hipGetLastError();
 }
 
