@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # of known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid only for the
 # kernel source it was measured on (hash of its files); otherwise null.
 JAC_ROUND_TRAFFIC = {
-    "sources_sha256": "846784e98535dbc65786d303a17fd22b56c2650c9bfe94fc61e15a4a1a19c01f",
+    "sources_sha256": "7335f49e540948cfb70cc18536a447bc331a1ab283f969b6b3351a33883e9fa3",
     "bytes_per_launch": 2.2524e8,
 }
 JAC_ROUND_SOURCES = ("svd.hip", "jacobi_small.h", "mfma_tile.h")

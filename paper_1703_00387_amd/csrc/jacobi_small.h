@@ -209,11 +209,12 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y;
 }
 
-// Order 64: herm_jacobi<64> (same ordering, thresholds, rotations and order
-// of operations, so the same results) arranged for the case that matters in
-// the block Jacobi, where the 64 x 64 Gram is nearly diagonal and only a few
-// of a step's 32 pairs rotate (about 4 on average in TEBD).  A step is then
-// bound by its chain of dependent LDS round trips, not by arithmetic:
+// Order 64: herm_jacobi<64> (same ordering, thresholds, 2x2 rotations and
+// order of operations; the angle comes from refined reciprocal estimates, so
+// results agree to rounding) arranged for the case that matters in the block
+// Jacobi, where the 64 x 64 Gram is nearly diagonal and only a few of a
+// step's 32 pairs rotate (about 4 on average in TEBD).  A step is then bound
+// by its chain of dependent LDS round trips, not by arithmetic:
 //  * the 32 lanes that form the step's rotations also list the rotating
 //    pairs, with their rotation and indices (p, q), in LDS;
 //  * the column and row passes run over the items (listed pair, row or
