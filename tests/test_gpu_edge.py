@@ -168,3 +168,23 @@ def test_truncate_at_the_size_limit_with_known_spectrum(H):
     R = (U * S.to(torch.complex128)) @ Vh
     err2 = float(torch.linalg.vector_norm(A - R) ** 2)
     assert abs(err2 - s2[k:].sum()) <= 1e-12
+
+
+def test_nonfinite_bond_in_a_batched_layer_is_flagged(H):
+    """A NaN in one chain's tensor reaches the Jacobi preparation of its bond:
+    the layer finishes (every kernel exits) and the device status says
+    non-finite, while a second, finite chain in the same call still matches
+    the oracle."""
+    from oracle import mps as omps, models as om
+    from paper_1703_00387_amd import api, models, _lib
+    good = W.xxz_chain(10, 16, 1.0, 0.5, init="random_product", local_states=W.random_complex((10, 2), (96,)))
+    ref = omps.tebd_run(good, "tebd2", 0.05, 4, 1e-12)
+    bad = W.xxz_chain(10, 16, 1.0, 0.5)
+    cg, cb = _chain(good), _chain(bad)
+    cb.B[3].view(torch.float64)[0] = float("nan")
+    H.device_status()
+    api.tebd_step(H, [cb, cg], 2, 0.05, 4, 1e-12)
+    code, word = H.device_status()
+    assert code == _lib.MPS_ERR_NONFINITE and word & _lib.MPS_DEV_NONFINITE, (code, word)
+    site, _, _ = api.observe(H, cg, models.sz_operator())
+    assert np.abs(site.cpu().numpy() - omps.local_expect(ref, 0.5 * om.SZ)).max() <= 1e-9
