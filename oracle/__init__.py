@@ -25,6 +25,8 @@ ktebd       Krylov TEBD: the Sornborger-Stewart sweep with the Lanczos
             exponential of every bond term (App. Details of the Krylov method)
 timedep     time-dependent Hamiltonians: commutator-free Magnus expansions
             (midpoint rule, fourth-order two-exponential scheme) over Trotter steps
+u1          U(1)-symmetric truncated SVD: blockwise SVDs, global count rule
+            (App. Convenient features)
 grad        reverse-mode gradient of TEBD2 with truncated-SVD backward, the
             exact-diagonalisation adjoint gradient, finite differences
 """
