@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
     ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256", "bh_heff_chi512", "xxz_grad_L32",
-                             "xxz_sweep_L64", "tfim_quench_L64", "bh_tdvp_L32"])
+                             "xxz_sweep_L64", "tfim_quench_L64", "bh_tdvp_L32", "bh_u1_svd_chi320"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -82,7 +82,8 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.warmup is None:
-        args.warmup = {"xxz_batch256": 40, "tfim_quench_L64": 150, "bh_tdvp_L32": 40}.get(args.workload, 140)
+        args.warmup = {"xxz_batch256": 40, "tfim_quench_L64": 150, "bh_tdvp_L32": 40,
+                       "bh_u1_svd_chi320": 1}.get(args.workload, 140)
 
     import workloads as W
     from paper_1703_00387_amd import api, models
@@ -99,6 +100,8 @@ def main():
         return bench_quench(args)
     if args.workload == "bh_tdvp_L32":
         return bench_tdvp(args)
+    if args.workload == "bh_u1_svd_chi320":
+        return bench_u1(args)
     wl = W.xxz_tebd4_L64()
     spec = wl.chains[0]
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
@@ -281,6 +284,76 @@ def bench_heff(args):
                      "traffic": None, "flops_per_apply": flops},
         "krylov": {"ms_per_exponential": round(t_kry * 1e3, 3), "vectors": n_used,
                    "h_eff_share": round(min(1.0, n_used * t_apply / t_kry), 4)},
+        "device_status": [code, word],
+    }
+    print(json.dumps(out))
+    h.close()
+
+
+def bench_u1(args):
+    """The truncated SVD of a number-conserving two-site tensor, dense against
+    U(1) blocks.  Synthetic Bose-Hubbard middle bond at the shape of the
+    paper's symmetry table (L = 32, d = 6, chi = 320): left bond charges (the
+    particle number to the left) drawn around 16, right ones around 18, row
+    (alpha, s1) charge q_alpha + s1, column (s2, gamma) charge q_gamma - s2;
+    theta random on its charge blocks with singular values decaying
+    exponentially.  Times the dense mps_truncate and mps_truncate_u1 on the
+    same matrix (both FP64 Jacobi) and checks they keep the same spectrum."""
+    import numpy as np
+    import torch
+    from paper_1703_00387_amd import api
+
+    d, chi, chi_max, eps = 6, 320, 320, 1e-12
+    rng = np.random.default_rng(170300387 + 32)
+    qa = np.rint(rng.normal(16.0, 2.0, size=chi)).astype(np.int64)
+    qg = np.rint(rng.normal(18.0, 2.0, size=chi)).astype(np.int64)
+    row_q = (qa[:, None] + np.arange(d)[None, :]).reshape(-1)
+    col_q = (qg[None, :] - np.arange(d)[:, None]).reshape(-1)
+    m, n = d * chi, d * chi
+    T = rng.normal(size=(m, n)) + 1j * rng.normal(size=(m, n))
+    T[row_q[:, None] != col_q[None, :]] = 0.0
+    T *= np.exp(-np.arange(m) / 60.0)[rng.permutation(m)][:, None]
+    T /= np.linalg.norm(T)
+    h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
+    th = torch.from_numpy(T).cuda()
+    sectors = len(set(row_q.tolist()) & set(col_q.tolist()))
+
+    def run(fn):
+        times = []
+        for rep in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        return out, float(np.median(times))
+
+    dense, t_dense = run(lambda: h.truncate(th, chi_max, eps))
+    blk, t_u1 = run(lambda: h.truncate_u1(th, row_q, col_q, chi_max, eps))
+    s_d = dense[1].cpu().numpy()
+    s_b = blk[1].cpu().numpy()
+    code, word = h.device_status()
+    out = {
+        "metric": "U(1)-blocked truncated SVD speedup over the dense SVD (Bose-Hubbard two-site tensor, d=6, chi=320)",
+        "value": round(t_dense / t_u1, 2),
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_u1 * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "bh_u1_svd_chi320: theta 1920 x 1920, number-conserving charge blocks",
+                   "sectors": sectors, "chi_max": chi_max, "eps": eps},
+        "dense_ms": round(t_dense * 1e3, 3),
+        "u1_ms": round(t_u1 * 1e3, 3),
+        "kept": [int(dense[3]), int(blk[4])],
+        "max_abs_ds2": float(np.abs(s_d ** 2 - s_b ** 2).max()) if len(s_d) == len(s_b) else None,
         "device_status": [code, word],
     }
     print(json.dumps(out))

@@ -159,6 +159,30 @@ mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int6
                         int32_t* k_dev, double* disc_dev, double* norm2_dev);
 
 /*
+ * U(1)-symmetric truncated SVD (App. "Convenient features", symmetry
+ * conservation: with a diagonal symmetry generator the tensor cut at a bond is
+ * block diagonal in the bond's charge and the decomposition runs on every
+ * block).  Row r of theta carries the charge row_q[r], column c the charge
+ * col_q[c]; theta[r][c] must vanish unless they agree (entries that do not
+ * are ignored).  Every charge present on both sides is one block; the blocks
+ * go through the batched FP64 Jacobi together, and the count rule of
+ * mps_truncate is applied to the union of their singular values (ties
+ * ordered by ascending charge, then by row).  Rows or columns whose charge
+ * has no partner are structural zeros and not part of the spectrum.
+ *   theta   : complex128 [m][n] device input (not modified)
+ *   row_q, col_q : int32 [m], [n] charges, HOST memory
+ *   U, S, Vh, k_dev, disc_dev, norm2_dev : as for mps_truncate; U[r][j] and
+ *             Vh[j][c] vanish unless the row's (column's) charge is q_out[j]
+ *   q_out   : int32 [chi_max] device output: the charge of kept vector j
+ * Errors: MPS_ERR_SHAPE when no charge is shared by rows and columns.
+ * Limits: m, n <= 4096.
+ */
+mps_status mps_truncate_u1(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n,
+                           const int32_t* row_q, const int32_t* col_q, int64_t chi_max, double eps, void* U,
+                           double* S, void* Vh, int32_t* q_out, int32_t* k_dev, double* disc_dev,
+                           double* norm2_dev);
+
+/*
  * A chain in Vidal/Hastings form (B_i = Gamma_i Lambda_{i+1}, right-canonical):
  * |psi> = lam_0 B_0 B_1 ... B_{L-1} (Eq. mps with the Schmidt values of
  * Eq. schmidt on the bonds).  Sites 0..L-1; virtual bond j sits left of site j.

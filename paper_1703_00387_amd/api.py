@@ -98,6 +98,30 @@ class Handle:
         kk = int(k.item())
         return U[:, :kk], S[:kk], Vh[:kk], kk, float(disc.item()), float(nrm.item())
 
+    def truncate_u1(self, theta: torch.Tensor, row_q, col_q, chi_max: int, eps: float):
+        """U(1)-symmetric truncated SVD: theta block diagonal in the row and
+        column charges (int sequences, host).  U, S, Vh, q (first k valid), k,
+        disc, norm2."""
+        theta = theta.contiguous()
+        m, n = theta.shape
+        rq = np.ascontiguousarray(np.asarray(row_q, dtype=np.int32))
+        cq = np.ascontiguousarray(np.asarray(col_q, dtype=np.int32))
+        if rq.shape != (m,) or cq.shape != (n,):
+            raise ValueError("row_q and col_q must have m and n entries")
+        dev = theta.device
+        U = torch.zeros((m, chi_max), dtype=torch.complex128, device=dev)
+        S = torch.zeros(chi_max, dtype=torch.float64, device=dev)
+        Vh = torch.zeros((chi_max, n), dtype=torch.complex128, device=dev)
+        q = torch.zeros(chi_max, dtype=torch.int32, device=dev)
+        k = torch.zeros(1, dtype=torch.int32, device=dev)
+        disc = torch.zeros(1, dtype=torch.float64, device=dev)
+        nrm = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.check(lib().mps_truncate_u1(self.h, _stream(), _ptr(theta), m, n, rq.ctypes.data, cq.ctypes.data,
+                                         chi_max, float(eps), _ptr(U), _ptr(S), _ptr(Vh), _ptr(q), _ptr(k),
+                                         _ptr(disc), _ptr(nrm)))
+        kk = int(k.item())
+        return U[:, :kk], S[:kk], Vh[:kk], q[:kk], kk, float(disc.item()), float(nrm.item())
+
 
 @dataclass
 class Chain:
