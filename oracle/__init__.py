@@ -26,7 +26,7 @@ ktebd       Krylov TEBD: the Sornborger-Stewart sweep with the Lanczos
 timedep     time-dependent Hamiltonians: commutator-free Magnus expansions
             (midpoint rule, fourth-order two-exponential scheme) over Trotter steps
 u1          U(1)-symmetric truncated SVD: blockwise SVDs, global count rule
-            (App. Convenient features)
+            (App. Convenient features); TEBD of charge-carrying chains
 grad        reverse-mode gradient of TEBD2 with truncated-SVD backward, the
             exact-diagonalisation adjoint gradient, finite differences
 """

@@ -64,3 +64,81 @@ def truncate_u1(theta: np.ndarray, row_q, col_q, chi_max: int, eps: float):
     w = float(np.sum(s_all[k:] ** 2))
     nk = float(np.sqrt(np.sum(s_all[:k] ** 2)))
     return Uk, s_all[:k], Vk, qk, w, nk, s_all
+
+
+# ---------------------------------------------------------------------------
+# Charge-carrying chains: TEBD with the blockwise truncation
+# ---------------------------------------------------------------------------
+
+def product_charges(vectors: np.ndarray, qsite) -> list:
+    """Bond charges of a product of basis states: q[b] holds, for the single
+    Schmidt state of bond b, the total charge of sites 0..b-1.  ``vectors``
+    (L, d) must be basis vectors up to a phase."""
+    qsite = np.asarray(qsite)
+    q = [np.zeros(1, dtype=np.int64)]
+    for v in vectors:
+        s = int(np.argmax(np.abs(v)))
+        if np.count_nonzero(v) != 1:
+            raise ValueError("a charge-carrying product state needs basis states on every site")
+        q.append(np.array([q[-1][0] + qsite[s]], dtype=np.int64))
+    return q
+
+
+def bond_charges(q_left, q_right, qsite):
+    """Row and column charges of theta at the bond between two sites: row
+    (alpha, s1) carries q_left[alpha] + qsite[s1] (the charge left of the new
+    bond), column (s2, gamma) carries q_right[gamma] - qsite[s2] (the charge
+    left of the right bond minus that of the second site)."""
+    qsite = np.asarray(qsite)
+    row_q = (np.asarray(q_left)[:, None] + qsite[None, :]).reshape(-1)
+    col_q = (np.asarray(q_right)[None, :] - qsite[:, None]).reshape(-1)
+    return row_q, col_q
+
+
+def apply_bond_u1(psi, q: list, qsite, b: int, G: np.ndarray, chi_max: int, eps: float) -> float:
+    """The Hastings-form update of ``mps.apply_bond`` with the blockwise
+    truncation: theta' is cut at bond b+1 by ``truncate_u1`` with the charges
+    of ``bond_charges``, and q[b+1] becomes the charges of the kept vectors.
+    Returns the discarded weight."""
+    d = psi.d
+    Bl, Br = psi.B[b], psi.B[b + 1]
+    chl, chr_ = Bl.shape[0], Br.shape[2]
+    theta_t = np.einsum("asb,btc->astc", Bl, Br)
+    theta_tp = np.einsum("uvst,astc->auvc", G.reshape(d, d, d, d), theta_t)
+    mat = (psi.lam[b][:, None, None, None] * theta_tp).reshape(chl * d, d * chr_)
+    row_q, col_q = bond_charges(q[b], q[b + 2], qsite)
+    _, s, Vh, qk, w, nk, _ = truncate_u1(mat, row_q, col_q, chi_max, eps)
+    k = len(s)
+    psi.lam[b + 1] = s / nk
+    psi.B[b + 1] = Vh.reshape(k, d, chr_)
+    psi.B[b] = (theta_tp.reshape(chl * d, d * chr_) @ Vh.conj().T / nk).reshape(chl, d, k)
+    q[b + 1] = qk
+    psi.disc.append(w)
+    return w
+
+
+def tebd_run_u1(spec, method: str, dt: float, n_steps: int, eps: float, qsite, chi_max=None):
+    """``mps.tebd_run`` on a charge-carrying chain: the product state of
+    ``spec`` (basis states), every update by ``apply_bond_u1``.  Returns the
+    state and its bond charges."""
+    from workloads import initial_vectors
+    from . import models
+    from .mps import GateCache, product_mps, step_layers
+    chi_max = spec.chi_max if chi_max is None else chi_max
+    vecs = initial_vectors(spec)
+    psi = product_mps(vecs)
+    q = product_charges(vecs, qsite)
+    gates = GateCache(models.bond_hamiltonians(spec))
+    for _ in range(n_steps):
+        for bonds, tau in step_layers(method, spec.L, dt):
+            for b in bonds:
+                apply_bond_u1(psi, q, qsite, b, gates(b, tau), chi_max, eps)
+    return psi, q
+
+
+def sector_spectra(lam, q) -> dict:
+    """{charge: Schmidt values of that charge, descending} of one bond."""
+    out = {}
+    for c in sorted(set(np.asarray(q).tolist())):
+        out[int(c)] = np.sort(np.asarray(lam)[np.asarray(q) == c])[::-1]
+    return out

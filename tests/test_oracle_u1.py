@@ -1,5 +1,6 @@
-"""Pins of the U(1)-symmetric truncated SVD oracle (oracle/u1.py) against the
-dense SVD and against the charge structure of a number-conserving state.
+"""Pins of the U(1)-symmetric truncated SVD and TEBD oracle (oracle/u1.py)
+against the dense SVD, the exact Trotter circuit and the charge structure of
+number-conserving states.
 
 * A random theta that is block diagonal in charge: the blockwise spectrum is
   the dense spectrum without its structural zeros; k, the discarded weight,
@@ -9,6 +10,11 @@ dense SVD and against the charge structure of a number-conserving state.
   S^z): cut into left and right halves, its coefficient matrix vanishes
   outside the blocks where the left charge plus the right charge is the
   total, and the blockwise and dense decompositions agree.
+* TEBD of charge-carrying chains (XXZ from a Neel state with charges n_up or
+  2 S^z, Bose-Hubbard at unit filling with the particle number): untruncated,
+  the state is the Trotter circuit's and every bond's Schmidt values split by
+  charge as the exact vector's do; truncated, the run equals the dense TEBD
+  (same bond dimensions, discarded weight and state).
 """
 import numpy as np
 import pytest
@@ -70,3 +76,71 @@ def test_neel_state_splits_by_charge():
     Ud, sd, Vd, wd, nkd, sd_all = omps.truncate(theta, 64, 0.0)
     assert np.allclose(np.sort(s_all)[::-1][:len(sd)], sd, atol=1e-13)
     assert np.abs((Uk * sk) @ Vk - theta).max() <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# TEBD of charge-carrying chains (apply_bond_u1 / tebd_run_u1)
+# ---------------------------------------------------------------------------
+
+def _left_charges(nsites, d, qsite):
+    """Charge of every configuration of nsites sites (first site most significant)."""
+    q = np.zeros(1, dtype=np.int64)
+    for _ in range(nsites):
+        q = (q[:, None] + np.asarray(qsite)[None, :]).reshape(-1)
+    return q
+
+
+@pytest.mark.parametrize("spec,qsite,method", [
+    (W.xxz_chain(10, 32, 1.0, 0.5), [1, 0], "tebd2"),
+    (W.xxz_chain(9, 16, 1.0, 0.7), [1, -1], "sweep"),
+    (W.bh_chain(6, 2, 27, 1.0, 3.0), [0, 1, 2], "tebd4"),
+])
+def test_untruncated_u1_tebd_equals_trotter_circuit(spec, qsite, method):
+    """At full bond dimension the blockwise update loses nothing: the state is
+    the exact Trotter circuit's, and every bond's Schmidt values split by
+    charge as the exact vector's coefficient matrix does (the charge labels
+    come out right: a wrong label moves a value to another sector)."""
+    L, d = spec.L, spec.d
+    psi, q = u1.tebd_run_u1(spec, method, 0.1, 5, -1.0, qsite)   # keep everything
+    v = ed.trotter_circuit(spec, method, 0.1, 5)
+    got = omps.to_vector(psi)
+    assert 1.0 - abs(np.vdot(got, v)) <= 1e-12
+    for b in range(1, L):
+        M = v.reshape(d ** b, d ** (L - b))
+        qL = _left_charges(b, d, qsite)
+        exact = {}
+        for c in sorted(set(qL.tolist())):
+            s = np.linalg.svd(M[qL == c], compute_uv=False)
+            s = s[s > 1e-6]
+            if len(s):
+                exact[int(c)] = s
+        ours = {c: s[s > 1e-6] for c, s in u1.sector_spectra(psi.lam[b], q[b]).items()}
+        ours = {c: s for c, s in ours.items() if len(s)}
+        assert sorted(exact) == sorted(ours), b
+        for c in exact:
+            assert len(exact[c]) == len(ours[c]) and np.abs(exact[c] - ours[c]).max() <= 1e-10, (b, c)
+
+
+def test_truncated_u1_tebd_equals_dense_tebd():
+    """With truncation the blockwise and the dense update keep the same
+    values (the spectrum is the same set; no two sectors tie at the cut), so
+    the two runs give the same state, bond dimensions and discarded weight."""
+    spec = W.xxz_chain(12, 6, 1.0, 0.5)
+    psi, q = u1.tebd_run_u1(spec, "tebd2", 0.05, 30, 1e-10, [1, 0])
+    ref = omps.tebd_run(spec, "tebd2", 0.05, 30, 1e-10)
+    assert psi.chis() == ref.chis()
+    assert abs(sum(psi.disc) - sum(ref.disc)) <= 1e-12 + 1e-8 * sum(ref.disc)
+    assert sum(ref.disc) > 1e-6                       # the cut is inside the spectrum
+    a, r = omps.to_vector(psi), omps.to_vector(ref)
+    assert 1.0 - abs(np.vdot(a, r)) / (np.linalg.norm(a) * np.linalg.norm(r)) <= 1e-10
+    # total charge: every configuration in the support has L/2 up spins
+    qs = _left_charges(12, 2, [1, 0])
+    assert np.abs(a[qs != 6]).max() == 0.0
+
+
+def test_product_charges_need_basis_states():
+    spec = W.xxz_chain(4, 4, 1.0, 0.5, init="random_product", local_states=W.random_complex((4, 2), (5,)))
+    with pytest.raises(ValueError):
+        u1.product_charges(W.initial_vectors(spec), [1, 0])
+    q = u1.product_charges(W.product_state_vectors("neel", 5, 2), [1, 0])
+    assert [int(x[0]) for x in q] == [0, 1, 1, 2, 2, 3]
