@@ -239,6 +239,42 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
                          double eps_local, uint32_t flags);
 
 /*
+ * Charges of a U(1)-symmetric chain (App. "Convenient features", symmetry
+ * conservation: a diagonal generator such as the particle number or 2 S^z).
+ *   qbond : int32 DEVICE [L+1][chi_max]: qbond[b][a] is the total charge of
+ *           sites 0..b-1 in Schmidt state a of bond b (a < chi[b]); bond b+1
+ *           is rewritten by every update of the bond between sites b, b+1
+ *   qsite : charge of local basis state s (s < d), host values
+ * For a product of basis states q_0 = 0 and q_{b+1} = q_b + qsite[s_b].
+ */
+typedef struct {
+  int32_t* qbond;
+  int32_t qsite[5];
+  int32_t reserved[3];
+} mps_u1_chain;
+
+/*
+ * mps_tebd_step on charge-conserving chains (App. "Convenient features",
+ * symmetry conservation).  Every update cuts theta' at the new bond into its
+ * charge blocks: row (a, s1) carries qbond[b][a] + qsite[s1], column
+ * (s2, g) carries qbond[b+2][g] - qsite[s2]; entries between different
+ * charges are not read.  The blocks of all bonds of a layer go through the
+ * batched FP64 Jacobi together; the count rule (eps_local, chi_max) is applied
+ * per bond to the union of its blocks' values, ties ordered by ascending
+ * charge; B_{b+1} = V^dag_k (zero off its block's columns), lam_{b+1} and
+ * qbond[b+1] follow, B_b = theta~' V_k / |s_k| as in mps_tebd_step.  The bond
+ * Hamiltonians must commute with the charge.  The host reads the bond charges
+ * once per layer (the block shapes set the launches), so MPS_FLAG_GRAPH is
+ * refused.
+ *   charges : HOST array of n_chains descriptors, one per chain
+ * Errors: as mps_tebd_step; MPS_ERR_INVALID for MPS_FLAG_GRAPH or a null
+ * qbond; MPS_ERR_SHAPE when no charge is shared across a bond.
+ */
+mps_status mps_tebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                            const mps_u1_chain* charges, int32_t n_chains, int32_t order, double dt,
+                            int32_t n_steps, double eps_local, uint32_t flags);
+
+/*
  * n_steps Krylov-TEBD steps on every chain (Sec. "Sornborger-Stewart
  * decomposition" with the local Krylov propagation of App. "Details of the
  * Krylov method"): the sweep of order 0 above, where each update propagates

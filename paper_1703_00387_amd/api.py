@@ -178,6 +178,50 @@ def tebd_step(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_steps
     h.check(lib().mps_tebd_step(h.h, _stream(), arr, len(chains), order, float(dt), n_steps, float(eps), flags))
 
 
+@dataclass
+class Charges:
+    """Bond charges of a U(1)-symmetric chain (layout of mps_u1_chain):
+    qbond[b][a] is the charge of sites 0..b-1 in Schmidt state a of bond b,
+    qsite[s] the charge of local basis state s."""
+    qbond: torch.Tensor    # int32 [L+1][chi_max]
+    qsite: tuple
+
+    @staticmethod
+    def product(vectors: np.ndarray, qsite, chi_max: int, device="cuda") -> "Charges":
+        """Charges of a product of basis states (q_0 = 0, q_{b+1} = q_b + qsite[s_b])."""
+        L, d = vectors.shape
+        if len(qsite) != d:
+            raise ValueError("qsite needs one charge per local basis state")
+        q = torch.zeros((L + 1, chi_max), dtype=torch.int32)
+        acc = 0
+        for i in range(L):
+            nz = np.flatnonzero(np.abs(vectors[i]) > 0)
+            if len(nz) != 1:
+                raise ValueError("a charge-carrying product state needs a basis state on every site")
+            acc += int(qsite[nz[0]])
+            q[i + 1, 0] = acc
+        return Charges(q.to(device), tuple(int(x) for x in qsite))
+
+    def desc(self) -> _lib.U1ChainDesc:
+        qs = list(self.qsite) + [0] * (5 - len(self.qsite))
+        return _lib.U1ChainDesc(self.qbond.data_ptr(), (C.c_int32 * 5)(*qs), (C.c_int32 * 3)())
+
+
+def tebd_step_u1(h: Handle, chains: Sequence[Chain], charges: Sequence[Charges], order: int, dt: float,
+                 n_steps: int, eps: float, flags: int = 0):
+    """tebd_step on charge-carrying chains: every update truncated on the
+    charge blocks of its bond; charges[i].qbond follows the chain."""
+    if len(charges) != len(chains):
+        raise ValueError("one Charges per chain")
+    for c, q in zip(chains, charges):
+        if q.qbond.shape != (c.L + 1, c.chi_max) or q.qbond.dtype != torch.int32 or not q.qbond.is_contiguous():
+            raise ValueError("qbond must be a contiguous int32 tensor [L+1][chi_max]")
+    arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
+    qa = (_lib.U1ChainDesc * len(chains))(*[q.desc() for q in charges])
+    h.check(lib().mps_tebd_step_u1(h.h, _stream(), arr, qa, len(chains), order, float(dt), n_steps, float(eps),
+                                   flags))
+
+
 def ktebd_step(h: Handle, chains: Sequence[Chain], dt: float, n_steps: int, eps: float, n_max: int = 20,
                tol: float = 1e-10, flags: int = 0, n_used=None):
     """Krylov TEBD steps (the sweep with the local Lanczos exponential of every

@@ -401,13 +401,21 @@ mps_status mps_ktebd_step(mps_handle h, mps_stream stream, const mps_chain_desc*
   return tebd_impl(h, stream, chains, n_chains, 0, dt, n_steps, eps_local, flags, 0, 1 << 30, &k);
 }
 
+mps_status mps_tebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                            const mps_u1_chain* charges, int32_t n_chains, int32_t order, double dt,
+                            int32_t n_steps, double eps_local, uint32_t flags) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!charges) return mps_fail(h, MPS_ERR_INVALID, "null charges");
+  return tebd_impl(h, stream, chains, n_chains, order, dt, n_steps, eps_local, flags, 0, 1 << 30, nullptr, charges);
+}
+
 }  // extern "C"
 
 // Runs n_steps steps; only layers lo <= index < hi of each step are applied
 // (all of them for the public entry point).
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
                      double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi,
-                     const KryOpts* kry) {
+                     const KryOpts* kry, const mps_u1_chain* u1) {
   if (!h) return MPS_ERR_INVALID;
   if (!chains || n_chains < 1) return mps_fail(h, MPS_ERR_INVALID, "need at least one chain");
   if (order != 0 && order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 0, 2 or 4");
@@ -421,6 +429,12 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS | MPS_FLAG_PLAIN))
     return mps_fail(h, MPS_ERR_INVALID, "unknown flag");
   const bool plain = flags & MPS_FLAG_PLAIN;
+  if (u1) {
+    if (flags & MPS_FLAG_GRAPH) return mps_fail(h, MPS_ERR_INVALID, "charge-carrying chains cannot be captured");
+    if (kry) return mps_fail(h, MPS_ERR_INVALID, "charge-carrying chains take the exact gates");
+    for (int c = 0; c < n_chains; ++c)
+      if (!u1[c].qbond) return mps_fail(h, MPS_ERR_INVALID, "null qbond");
+  }
   if (plain && (flags & MPS_FLAG_GRAPH)) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_PLAIN excludes MPS_FLAG_GRAPH");
   hipStream_t s = (hipStream_t)stream;
   const bool graph = flags & MPS_FLAG_GRAPH;
@@ -521,6 +535,8 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
     oKPart = p.take<double2>((size_t)n_chains * kt_nblk * dd * dd);
     oKHist = p.take<double2>((size_t)n_chains * kt_hist);
   }
+  size_t oU1 = 0;
+  if (u1) oU1 = p.take<char>(u1_layer_bytes((int)max_items, d * chi_cap, chi_cap));
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
   char* ws = h->ws;
@@ -551,6 +567,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   // class) for the even/odd orders and single sweep layers for order 0.
   const int n_groups = order == 0 ? (int)layers.size() : 2 * n_cls;
   std::vector<BondItem> items;
+  std::vector<int> item_chain;
   std::vector<KryJob> kjobs;
   std::vector<size_t> start(n_groups), count(n_groups);
   for (int gi = 0; gi < n_groups; ++gi) {
@@ -601,6 +618,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
           it.chi_max = ch.chi_max;
           it.pad = 0;
           items.push_back(it);
+          item_chain.push_back(c);
         }
       }
       count[gi] = items.size() - start[gi];
@@ -661,6 +679,12 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       if (prof) prof_begin(h, s, MPS_K_THETA);
       MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_eff, c128, stats));
       if (prof) prof_end(h, s, MPS_K_THETA);
+      if (u1) {
+        const size_t first = start[idx] + i0;
+        mps_status r = u1_layer(h, s, items.data() + first, it, item_chain.data() + first, n, u1, (int)max_items,
+                                m_cap, chi_cap, eps_local, c128, ws + oU1, sel, unconv, fixed);
+        if (r != MPS_OK) return r;
+      } else {
       if (prof) prof_begin(h, s, MPS_K_PREP);
       MPS_TRY_HIP(h, launch_jac_prep_bonds(s, it, mats, n, kJacBlock, (int32_t*)(ws + oRow), (double*)(ws + oNrm), m_cap,
                                            h->status_dev));
@@ -673,6 +697,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       if (prof) prof_begin(h, s, MPS_K_WB_RIGHT);
       MPS_TRY_HIP(h, launch_wb_right(s, it, n, mats, perm, s2, m_cap, sel, chi_eff, d, c128));
       if (prof) prof_end(h, s, MPS_K_WB_RIGHT);
+      }
       MPS_TRY_HIP(h, launch_wb_left_probs(s, it, n, sel, probs));
       if (prof) prof_begin(h, s, MPS_K_GEMM);
       MPS_TRY_HIP(h, launch_gemm_bt_conj(s, probs, n, d * chl_eff, k_cap, c128, stats));

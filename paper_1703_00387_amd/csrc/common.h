@@ -80,9 +80,21 @@ inline double count_rule_eps(mps_handle h, double eps) { return eps >= 0.0 && ep
 
 // TEBD driver with a layer window (api.hip); kry != null propagates every
 // bond of the sweep (order 0) with the local Lanczos exponential of h_b
+// u1 != null: charge-carrying chains, every update truncated on its charge blocks
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
                      double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi,
-                     const KryOpts* kry = nullptr);
+                     const KryOpts* kry = nullptr, const mps_u1_chain* u1 = nullptr);
+
+// Charge-carrying chains (u1.hip): the truncation of one layer of n bond
+// items (theta' in their X slots) on the charge blocks of every bond, in place
+// of preparation, Jacobi, selection and right write-back.  chain_of[i] is the
+// chain of item i; region holds u1_layer_bytes(n_cap, m_cap, chi_cap) bytes.
+struct BondItem;
+struct SelOut;
+size_t u1_layer_bytes(int n_cap, int m_cap, int chi_cap);
+mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const BondItem* it_dev, const int* chain_of,
+                    int n, const mps_u1_chain* u1c, int n_cap, int m_cap, int chi_cap, double eps, bool c128,
+                    char* region, SelOut* sel, int32_t* unconv, bool fixed);
 
 // kernel timing helpers (host)
 void prof_begin(mps_handle h, hipStream_t s, int id);

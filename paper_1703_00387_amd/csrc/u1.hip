@@ -15,21 +15,38 @@
 
 namespace {
 
+// One charge block of one matrix.  Row and column lists of all matrices of a
+// call are concatenated; row_off and col_off index them, the rows of matrix i
+// occupy [row0_i, row0_i + R_i) of the row list.
 struct U1Block {
-  int32_t q, m, n, row_off, col_off, pad;  // charge, shape, offsets into the row and column lists
-  int64_t x_off;                           // offset of the gathered block (complex128 elements)
+  const double2* src;                       // the matrix the block is cut from, row-major with leading dim ld
+  int64_t ld;
+  int64_t x_off;                            // offset of the gathered block (complex128 elements)
+  int32_t q, m, n, row_off, col_off, item;  // charge, shape, list offsets, owning matrix
 };
 
-// X_b[i][j] = theta[rows[i]][cols[j]], grid (chunks, blocks)
-__global__ __launch_bounds__(256) void u1_gather_kernel(const double2* __restrict__ theta, int64_t ldt,
-                                                        const U1Block* __restrict__ blk,
+// The blocks and rows of one matrix.
+struct U1Range {
+  int32_t blk0, nblk;  // its blocks: [blk0, blk0 + nblk), ascending charge
+  int32_t row0, R;     // its entries of the row list
+  int32_t kmax, ncols; // cap on the kept count, columns of the matrix
+};
+
+// Per bond item of a charge-carrying chain.
+struct U1Item {
+  int32_t* qb;         // the chain's bond charges [L+1][chi_max]
+  int32_t b, chi_max, d, pad;
+};
+
+// X_b[i][j] = src[rows[i]][cols[j]], grid (chunks, blocks)
+__global__ __launch_bounds__(256) void u1_gather_kernel(const U1Block* __restrict__ blk,
                                                         const int32_t* __restrict__ rows,
                                                         const int32_t* __restrict__ cols, double2* __restrict__ Xw) {
   const U1Block b = blk[blockIdx.y];
   const int64_t tot = (int64_t)b.m * b.n;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
     const int i = (int)(e / b.n), j = (int)(e % b.n);
-    Xw[b.x_off + e] = theta[(size_t)rows[b.row_off + i] * ldt + cols[b.col_off + j]];
+    Xw[b.x_off + e] = b.src[(size_t)rows[b.row_off + i] * b.ld + cols[b.col_off + j]];
   }
 }
 
@@ -44,22 +61,26 @@ __device__ __forceinline__ int u1_block_of(const U1Block* blk, int nblk, int e) 
   return lo;
 }
 
-// One workgroup.  Entry e of the concatenated row list (blocks by ascending
-// charge, rows in order) holds a squared singular value: the converged row
-// norm of its block.  They are ranked descending (ties by e, that is by
-// charge, then by row), the count rule is applied to the sorted list, and the
-// sorted entries, their values and the selection summary are written.
+// One workgroup per matrix.  Entry e of the matrix's row list (blocks by
+// ascending charge, rows in order) holds a squared singular value: the
+// converged row norm of its block.  They are ranked descending (ties by e,
+// that is by charge, then by row), the count rule is applied to the sorted
+// list, and the sorted entries (as positions in the whole row list), their
+// values and the selection summary are written.
 __global__ __launch_bounds__(256) void u1_select_kernel(const JacMat* __restrict__ mats,
-                                                        const U1Block* __restrict__ blk, int nblk, int R,
-                                                        int kmax, double eps, int32_t* pe, double* s2o,
-                                                        SelOut* out) {
+                                                        const U1Block* __restrict__ blk,
+                                                        const U1Range* __restrict__ ranges, double eps,
+                                                        int32_t* pe, double* s2o, SelOut* out) {
   extern __shared__ double dyn[];
+  const U1Range rg = ranges[blockIdx.x];
+  const int R = rg.R, kmax = rg.kmax;
   double* v = dyn;                // [R]
   int* perm = (int*)(v + R);      // [R]
   const int tid = threadIdx.x;
+  const U1Block* bl = blk + rg.blk0;
   for (int e = tid; e < R; e += 256) {
-    const int b = u1_block_of(blk, nblk, e);
-    const double a = mats[b].nrm2[e - blk[b].row_off];
+    const int b = u1_block_of(bl, rg.nblk, rg.row0 + e);
+    const double a = mats[rg.blk0 + b].nrm2[rg.row0 + e - bl[b].row_off];
     v[e] = (a >= 0.0 && a <= 1.0e300) ? a : -1.0;  // non-finite entries sort last (flagged by the preparation)
   }
   __syncthreads();
@@ -74,8 +95,8 @@ __global__ __launch_bounds__(256) void u1_select_kernel(const JacMat* __restrict
   }
   __syncthreads();
   for (int r = tid; r < R; r += 256) {
-    pe[r] = perm[r];
-    s2o[r] = fmax(v[perm[r]], 0.0);
+    pe[rg.row0 + r] = rg.row0 + perm[r];
+    s2o[rg.row0 + r] = fmax(v[perm[r]], 0.0);
   }
   __syncthreads();
   if (tid == 0) {
@@ -105,7 +126,7 @@ __global__ __launch_bounds__(256) void u1_select_kernel(const JacMat* __restrict
     o.disc = disc;
     o.norm2 = total;
     o.nk = kept > 0.0 ? sqrt(kept) : 1.0;
-    *out = o;
+    out[blockIdx.x] = o;
   }
 }
 
@@ -176,7 +197,223 @@ __global__ __launch_bounds__(256) void u1_u_kernel(const double2* __restrict__ t
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// charge-carrying chains: one layer of bond items
+// ---------------------------------------------------------------------------
+
+// Row i of out: chi_b, chi_{b+2}, the charges of bond b (chi_max entries),
+// those of bond b+2 (chi_max entries).
+__global__ __launch_bounds__(256) void u1_read_kernel(const BondItem* __restrict__ items,
+                                                      const U1Item* __restrict__ ui, int stride,
+                                                      int32_t* __restrict__ out) {
+  const BondItem it = items[blockIdx.x];
+  const int cm = it.chi_max;
+  const int chl = it.chi[it.b], chr = it.chi[it.b + 2];
+  int32_t* o = out + (size_t)blockIdx.x * stride;
+  if (threadIdx.x == 0) {
+    o[0] = chl;
+    o[1] = chr;
+  }
+  const int32_t* qb = ui[blockIdx.x].qb;
+  for (int a = threadIdx.x; a < min(max(chl, 0), cm); a += 256) o[2 + a] = qb[(size_t)it.b * cm + a];
+  for (int g = threadIdx.x; g < min(max(chr, 0), cm); g += 256) o[2 + cm + g] = qb[(size_t)(it.b + 2) * cm + g];
+}
+
+// grid (kept-count cap, items): kept vector j of item i.  Its block row over
+// s_j is the new right site's row j (V^dag_k, zero off the block's columns),
+// stored in the chain's tensor and in the item's V^dag workspace; lam_{b+1},
+// the bond charge, chi_{b+1} and the discarded weight are written alongside.
+template <class T>
+__global__ __launch_bounds__(256) void u1_wb_kernel(const BondItem* __restrict__ items,
+                                                    const U1Item* __restrict__ ui, const JacMat* __restrict__ mats,
+                                                    const U1Block* __restrict__ blk,
+                                                    const U1Range* __restrict__ ranges,
+                                                    const int32_t* __restrict__ cols, const int32_t* __restrict__ pe,
+                                                    const double* __restrict__ s2o, const SelOut* __restrict__ sel) {
+  const int i = blockIdx.y, j = blockIdx.x;
+  const BondItem it = items[i];
+  const U1Range rg = ranges[i];
+  const SelOut so = sel[i];
+  const int d = it.d, cm = it.chi_max, ncols = rg.ncols, chr = ncols / d;
+  if (j == 0 && threadIdx.x == 0) {
+    it.chi[it.b + 1] = so.k;
+    it.disc[it.b] += so.disc;
+  }
+  if (j >= so.k) return;
+  const int e = pe[rg.row0 + j];
+  const U1Block* bl = blk + rg.blk0;
+  const int b = u1_block_of(bl, rg.nblk, e);
+  const U1Block B = bl[b];
+  const JacMat M = mats[rg.blk0 + b];
+  const int r = e - B.row_off;
+  const double sv = sqrt(s2o[rg.row0 + j]);
+  const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
+  T* vrow = (T*)it.Vh + (size_t)j * ncols;
+  T* Br = (T*)it.Br;
+  T z;
+  z.x = 0;
+  z.y = 0;
+  for (int c = threadIdx.x; c < ncols; c += 256) {
+    vrow[c] = z;
+    Br[((size_t)j * d + c / chr) * cm + c % chr] = z;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < B.n; c += 256) {
+    const double2 x = M.X[(size_t)r * M.ld + c];
+    T v;
+    v.x = x.x * inv;
+    v.y = x.y * inv;
+    const int col = cols[B.col_off + c];
+    vrow[col] = v;
+    Br[((size_t)j * d + col / chr) * cm + col % chr] = v;
+  }
+  if (threadIdx.x == 0) {
+    it.lam_m[j] = sv / so.nk;
+    ui[i].qb[(size_t)(it.b + 1) * cm + j] = B.q;
+  }
+}
+
+// Workspace of u1_layer for up to n_cap items of at most m_cap rows and columns.
+struct U1Plan {
+  size_t oItems, oRb, oX, oMats, oBlk, oRg, oRows, oCols, oRm, oNrm, oPe, oS2, off;
+  U1Plan(int n_cap, int m_cap, int chi_cap) {
+    WsPlan p;
+    const size_t nm = (size_t)n_cap * m_cap;
+    oItems = p.take<U1Item>(n_cap);
+    oRb = p.take<int32_t>((size_t)n_cap * (2 + 2 * chi_cap));
+    oX = p.take<double2>(nm * m_cap);
+    oMats = p.take<JacMat>(nm);
+    oBlk = p.take<U1Block>(nm);
+    oRg = p.take<U1Range>(n_cap);
+    oRows = p.take<int32_t>(nm);
+    oCols = p.take<int32_t>(nm);
+    oRm = p.take<int32_t>(nm);
+    oNrm = p.take<double>(nm);
+    oPe = p.take<int32_t>(nm);
+    oS2 = p.take<double>(nm);
+    off = p.off + 256;
+  }
+};
+
 }  // namespace
+
+size_t u1_layer_bytes(int n_cap, int m_cap, int chi_cap) { return U1Plan(n_cap, m_cap, chi_cap).off; }
+
+mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const BondItem* it_dev, const int* chain_of,
+                    int n, const mps_u1_chain* u1c, int n_cap, int m_cap, int chi_cap, double eps, bool c128,
+                    char* region, SelOut* sel, int32_t* unconv, bool fixed) {
+  if (n <= 0) return MPS_OK;
+  const U1Plan P(n_cap, m_cap, chi_cap);
+  region = (char*)(((uintptr_t)region + 255) & ~(uintptr_t)255);
+  const int stride = 2 + 2 * chi_cap;
+  std::vector<U1Item> ui(n);
+  for (int i = 0; i < n; ++i) ui[i].qb = u1c[chain_of[i]].qbond;
+  MPS_TRY_HIP(h, hipMemcpyAsync(region + P.oItems, ui.data(), n * sizeof(U1Item), hipMemcpyHostToDevice, s));
+  U1Item* dUi = (U1Item*)(region + P.oItems);
+  u1_read_kernel<<<n, 256, 0, s>>>(it_dev, dUi, stride, (int32_t*)(region + P.oRb));
+  MPS_TRY_HIP(h, hipGetLastError());
+  std::vector<int32_t> rb((size_t)n * stride);
+  MPS_TRY_HIP(h, hipMemcpyAsync(rb.data(), region + P.oRb, rb.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  // the charge blocks of every item, ascending charge, rows and columns in order
+  std::vector<U1Block> blocks;
+  std::vector<U1Range> ranges(n);
+  std::vector<int32_t> rows, cols;
+  int64_t xw = 0, max_mn = 1;
+  int max_m = 1, max_R = 1, k_cap = 1;
+  for (int i = 0; i < n; ++i) {
+    const BondItem& it = it_host[i];
+    const int d = it.d, cm = it.chi_max;
+    const int32_t* o = rb.data() + (size_t)i * stride;
+    const int chl = o[0], chr = o[1];
+    if (chl < 1 || chl > cm || chr < 1 || chr > cm)
+      return mps_fail(h, MPS_ERR_SHAPE, "bond dimension out of range in a charge-carrying chain");
+    const int32_t* qs = u1c[chain_of[i]].qsite;
+    std::map<int32_t, std::pair<std::vector<int32_t>, std::vector<int32_t>>> sec;
+    for (int a = 0; a < chl; ++a)
+      for (int s1 = 0; s1 < d; ++s1) sec[o[2 + a] + qs[s1]].first.push_back(a * d + s1);
+    for (int s2 = 0; s2 < d; ++s2)
+      for (int g = 0; g < chr; ++g) sec[o[2 + cm + g] - qs[s2]].second.push_back(s2 * chr + g);
+    U1Range& rg = ranges[i];
+    rg.blk0 = (int32_t)blocks.size();
+    rg.row0 = (int32_t)rows.size();
+    rg.ncols = d * chr;
+    for (auto& kv : sec) {
+      const auto& rr = kv.second.first;
+      const auto& cc = kv.second.second;
+      if (rr.empty() || cc.empty()) continue;
+      U1Block b;
+      b.src = it.X;
+      b.ld = (int64_t)d * chr;
+      b.q = kv.first;
+      b.m = (int32_t)rr.size();
+      b.n = (int32_t)cc.size();
+      b.row_off = (int32_t)rows.size();
+      b.col_off = (int32_t)cols.size();
+      b.item = i;
+      b.x_off = xw;
+      xw += (int64_t)b.m * b.n;
+      max_m = std::max(max_m, b.m);
+      max_mn = std::max<int64_t>(max_mn, (int64_t)b.m * b.n);
+      rows.insert(rows.end(), rr.begin(), rr.end());
+      cols.insert(cols.end(), cc.begin(), cc.end());
+      blocks.push_back(b);
+    }
+    rg.nblk = (int32_t)blocks.size() - rg.blk0;
+    rg.R = (int32_t)rows.size() - rg.row0;
+    if (rg.nblk == 0)
+      return mps_fail(h, MPS_ERR_SHAPE, "no charge is shared across a bond of a charge-carrying chain");
+    rg.kmax = std::min(cm, rg.R);
+    max_R = std::max(max_R, rg.R);
+    k_cap = std::max(k_cap, rg.kmax);
+  }
+  const int nblk = (int)blocks.size();
+  if ((int64_t)xw > (int64_t)n_cap * m_cap * m_cap || (int64_t)nblk > (int64_t)n_cap * m_cap ||
+      (int64_t)rows.size() > (int64_t)n_cap * m_cap || (int64_t)cols.size() > (int64_t)n_cap * m_cap)
+    return mps_fail(h, MPS_ERR_CAPACITY, "charge blocks exceed the layer workspace");
+  char* const ws = region;
+  std::vector<JacMat> hm(nblk);
+  for (int i = 0; i < nblk; ++i) {
+    std::memset(&hm[i], 0, sizeof(JacMat));
+    hm[i].X = (double2*)(ws + P.oX) + blocks[i].x_off;
+    hm[i].rowmap = (int32_t*)(ws + P.oRm) + blocks[i].row_off;
+    hm[i].nrm2 = (double*)(ws + P.oNrm) + blocks[i].row_off;
+    hm[i].m = blocks[i].m;
+    hm[i].n = blocks[i].n;
+    hm[i].ld = blocks[i].n;
+    hm[i].nb = jac_nb(blocks[i].m);
+    hm[i].kmax = blocks[i].m;
+  }
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oMats, hm.data(), nblk * sizeof(JacMat), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oBlk, blocks.data(), nblk * sizeof(U1Block), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oRg, ranges.data(), n * sizeof(U1Range), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oRows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oCols, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  JacMat* mats = (JacMat*)(ws + P.oMats);
+  const U1Block* blk = (const U1Block*)(ws + P.oBlk);
+  const U1Range* rgd = (const U1Range*)(ws + P.oRg);
+  const int gx = (int)std::min<int64_t>((max_mn + 255) / 256, 1024);
+  u1_gather_kernel<<<dim3(gx, nblk), 256, 0, s>>>(blk, (const int32_t*)(ws + P.oRows), (const int32_t*)(ws + P.oCols),
+                                                 (double2*)(ws + P.oX));
+  MPS_TRY_HIP(h, hipGetLastError());
+  MPS_TRY_HIP(h, launch_jac_prep_plain(s, mats, nblk, h->status_dev));
+  mps_status st = run_jacobi(h, s, mats, nblk, jac_nb(max_m), max_m, unconv, fixed);
+  if (st != MPS_OK) return st;
+  int32_t* pe = (int32_t*)(ws + P.oPe);
+  double* s2o = (double*)(ws + P.oS2);
+  u1_select_kernel<<<n, 256, (size_t)max_R * (sizeof(double) + sizeof(int)), s>>>(mats, blk, rgd,
+                                                                                   count_rule_eps(h, eps), pe, s2o, sel);
+  MPS_TRY_HIP(h, hipGetLastError());
+  const int32_t* dcols = (const int32_t*)(ws + P.oCols);
+  if (c128)
+    u1_wb_kernel<double2><<<dim3(k_cap, n), 256, 0, s>>>(it_dev, dUi, mats, blk, rgd, dcols, pe, s2o, sel);
+  else
+    u1_wb_kernel<float2><<<dim3(k_cap, n), 256, 0, s>>>(it_dev, dUi, mats, blk, rgd, dcols, pe, s2o, sel);
+  MPS_TRY_HIP(h, hipGetLastError());
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));  // the host vectors go out of scope at return
+  return MPS_OK;
+}
 
 extern "C" mps_status mps_truncate_u1(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n,
                                       const int32_t* row_q, const int32_t* col_q, int64_t chi_max, double eps,
@@ -201,12 +438,14 @@ extern "C" mps_status mps_truncate_u1(mps_handle h, mps_stream stream, const voi
     const auto& cc = kv.second.second;
     if (rr.empty() || cc.empty()) continue;
     U1Block b;
+    b.src = (const double2*)theta;
+    b.ld = n;
     b.q = kv.first;
     b.m = (int32_t)rr.size();
     b.n = (int32_t)cc.size();
     b.row_off = (int32_t)rows.size();
     b.col_off = (int32_t)cols.size();
-    b.pad = 0;
+    b.item = 0;
     b.x_off = xw;
     xw += (int64_t)b.m * b.n;
     max_m = std::max(max_m, b.m);
@@ -229,6 +468,7 @@ extern "C" mps_status mps_truncate_u1(mps_handle h, mps_stream stream, const voi
   const size_t oPe = p.take<int32_t>(R);
   const size_t oS2 = p.take<double>(R);
   const size_t oSel = p.take<SelOut>(1);
+  const size_t oRg = p.take<U1Range>(1);
   const size_t oU = p.take<int32_t>(4);
   const size_t oRq = p.take<int32_t>(m);
   mps_status st = mps_ensure_ws(h, p.off);
@@ -251,6 +491,9 @@ extern "C" mps_status mps_truncate_u1(mps_handle h, mps_stream stream, const voi
   MPS_TRY_HIP(h, hipMemcpyAsync(ws + oRows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   MPS_TRY_HIP(h, hipMemcpyAsync(ws + oCols, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   MPS_TRY_HIP(h, hipMemcpyAsync(ws + oRq, row_q, (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  const int kmax = (int)std::min<int64_t>(chi_max, R);
+  const U1Range rg{0, nblk, 0, R, kmax, (int32_t)n};
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + oRg, &rg, sizeof(U1Range), hipMemcpyHostToDevice, s));
   MPS_TRY_HIP(h, hipStreamSynchronize(s));  // the host vectors go out of scope at return
   const JacMat* mats = (const JacMat*)(ws + oM);
   const U1Block* blk = (const U1Block*)(ws + oB);
@@ -258,17 +501,16 @@ extern "C" mps_status mps_truncate_u1(mps_handle h, mps_stream stream, const voi
     int64_t max_mn = 1;
     for (const auto& b : blocks) max_mn = std::max<int64_t>(max_mn, (int64_t)b.m * b.n);
     const int gx = (int)std::min<int64_t>((max_mn + 255) / 256, 1024);
-    u1_gather_kernel<<<dim3(gx, nblk), 256, 0, s>>>((const double2*)theta, n, blk, (const int32_t*)(ws + oRows),
-                                                   (const int32_t*)(ws + oCols), (double2*)(ws + oX));
+    u1_gather_kernel<<<dim3(gx, nblk), 256, 0, s>>>(blk, (const int32_t*)(ws + oRows), (const int32_t*)(ws + oCols),
+                                                   (double2*)(ws + oX));
     MPS_TRY_HIP(h, hipGetLastError());
   }
   MPS_TRY_HIP(h, launch_jac_prep_plain(s, (JacMat*)(ws + oM), nblk, h->status_dev));
   st = run_jacobi(h, s, (JacMat*)(ws + oM), nblk, jac_nb(max_m), max_m, (int32_t*)(ws + oU), false);
   if (st != MPS_OK) return st;
-  const int kmax = (int)std::min<int64_t>(chi_max, R);
   SelOut* sel = (SelOut*)(ws + oSel);
   u1_select_kernel<<<1, 256, (size_t)R * (sizeof(double) + sizeof(int)), s>>>(
-      mats, blk, nblk, R, kmax, count_rule_eps(h, eps), (int32_t*)(ws + oPe), (double*)(ws + oS2), sel);
+      mats, blk, (const U1Range*)(ws + oRg), count_rule_eps(h, eps), (int32_t*)(ws + oPe), (double*)(ws + oS2), sel);
   MPS_TRY_HIP(h, hipGetLastError());
   u1_vh_kernel<<<kmax, 256, 0, s>>>(mats, blk, nblk, (const int32_t*)(ws + oCols), (const int32_t*)(ws + oPe),
                                     (const double*)(ws + oS2), sel, n, (double2*)Vh, S, q_out, k_dev, disc_dev,

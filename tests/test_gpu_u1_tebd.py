@@ -1,0 +1,142 @@
+"""TEBD of charge-carrying chains on the GPU (mps_tebd_step_u1) against the
+oracle's blockwise TEBD (oracle/u1.py: tebd_run_u1), at the bars of the dense
+TEBD tests: |Delta <O_i>| <= 1e-9 for local observables and 1 - overlap <=
+1e-9 for complex128 chains (2e-6 for the local observables of complex64
+chains), the bond dimensions identical, and at every bond the Schmidt values
+of each charge within 1e-9 of the oracle's (the charges the update assigns
+decide which sector a value lands in).  XXZ chains from a Neel state carry
+n_up or 2 S^z, Bose-Hubbard chains at unit filling the particle number.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1703_00387_amd import api
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    h = api.Handle(0)
+    yield h
+    h.close()
+
+
+def _chain(spec, qsite, dtype="c128"):
+    from paper_1703_00387_amd import api, models
+    v = W.initial_vectors(spec)
+    ch = api.Chain.product(v, spec.chi_max, models.bond_hamiltonians(spec), dtype=dtype)
+    return ch, api.Charges.product(v, qsite, spec.chi_max)
+
+
+def _vector(chain):
+    B, lam, chi = chain.to_host()
+    v = lam[0][:, None] * B[0].reshape(B[0].shape[0], -1)
+    v = v.reshape(-1, B[0].shape[2])
+    for T in B[1:]:
+        v = (v @ T.reshape(T.shape[0], -1)).reshape(-1, T.shape[2])
+    return v.reshape(-1)
+
+
+def _check(H, ch, q, ref, qref, spec, dtype="c128"):
+    from oracle import mps as omps, models as om, u1
+    from paper_1703_00387_amd import api, models
+    chi = ch.chi.cpu().numpy()
+    assert list(chi) == ref.chis()
+    if spec.d == 2:
+        op, oop = models.sz_operator(), 0.5 * om.SZ
+    else:
+        op, oop = models.number_operator(spec.d), om.number_op(spec.d)
+    site, _, _ = api.observe(H, ch, op)
+    dev = np.abs(site.cpu().numpy() - omps.local_expect(ref, oop)).max()
+    lam = ch.lam.cpu().numpy()
+    qb = q.qbond.cpu().numpy()
+    worst = 0.0
+    for b in range(1, spec.L):
+        ours = u1.sector_spectra(lam[b, :chi[b]], qb[b, :chi[b]])
+        theirs = u1.sector_spectra(ref.lam[b], qref[b])
+        assert sorted(ours) == sorted(theirs), b
+        for c in ours:
+            assert len(ours[c]) == len(theirs[c]), (b, c)
+            worst = max(worst, np.abs(ours[c] - theirs[c]).max())
+    print(f"L={spec.L} chi={chi.max()} max|d<O>|={dev:.2e} max|d lam|={worst:.2e} disc={sum(ref.disc):.2e}")
+    if dtype == "c128":
+        assert dev <= 1e-9 and worst <= 1e-9
+        a, r = _vector(ch), omps.to_vector(ref)
+        assert 1.0 - abs(np.vdot(a, r)) / (np.linalg.norm(a) * np.linalg.norm(r)) <= 1e-9
+        assert abs(float(ch.disc.sum().item()) - sum(ref.disc)) <= 1e-12 + 1e-6 * sum(ref.disc)
+    else:
+        assert dev <= 2e-6 and worst <= 2e-6
+
+
+CASES = [
+    ("xxz_tebd2", W.xxz_chain(16, 8, 1.0, 0.5), [1, 0], 2, "tebd2", 0.05, 40, 1e-10),
+    ("xxz_tebd4_2sz", W.xxz_chain(12, 6, 1.0, 0.7), [1, -1], 4, "tebd4", 0.1, 12, 1e-10),
+    ("xxz_sweep", W.xxz_chain(10, 6, 1.0, 0.5), [1, 0], 0, "sweep", 0.05, 30, 1e-12),
+    ("bh_tebd2", W.bh_chain(8, 2, 16, 1.0, 3.0), [0, 1, 2], 2, "tebd2", 0.05, 10, 1e-10),
+    ("bh_sweep_d5", W.bh_chain(6, 4, 24, 1.0, 2.0), [0, 1, 2, 3, 4], 0, "sweep", 0.05, 6, 1e-12),
+]
+
+
+@pytest.mark.parametrize("name,spec,qsite,order,method,dt,n,eps", CASES, ids=[c[0] for c in CASES])
+def test_u1_tebd_matches_oracle(H, name, spec, qsite, order, method, dt, n, eps):
+    from oracle import u1
+    from paper_1703_00387_amd import api
+    print(f"case {name}", flush=True)
+    ref, qref = u1.tebd_run_u1(spec, method, dt, n, eps, qsite)
+    ch, q = _chain(spec, qsite)
+    api.tebd_step_u1(H, [ch], [q], order, dt, n, eps)
+    code, word = H.device_status()
+    assert code == 0, word
+    _check(H, ch, q, ref, qref, spec)
+
+
+def test_u1_tebd_batched_chains_and_complex64(H):
+    """Two complex128 chains of different lengths in one call, then a
+    complex64 chain (FP32 MFMA contractions, FP64 SVD)."""
+    from oracle import u1
+    from paper_1703_00387_amd import api
+    specs = [W.xxz_chain(10, 8, 1.0, 0.5), W.xxz_chain(14, 10, 1.0, 0.3)]
+    refs = [u1.tebd_run_u1(s, "tebd2", 0.05, 30, 1e-10, [1, 0]) for s in specs]
+    chs = [_chain(s, [1, 0]) for s in specs]
+    api.tebd_step_u1(H, [c for c, _ in chs], [q for _, q in chs], 2, 0.05, 30, 1e-10)
+    for (c, q), (r, qr), s in zip(chs, refs, specs):
+        _check(H, c, q, r, qr, s)
+    s = W.xxz_chain(12, 8, 1.0, 0.5)
+    r, qr = u1.tebd_run_u1(s, "tebd2", 0.05, 10, 1e-10, [1, 0])
+    c, q = _chain(s, [1, 0], "c64")
+    api.tebd_step_u1(H, [c], [q], 2, 0.05, 10, 1e-10)
+    _check(H, c, q, r, qr, s, "c64")
+
+
+def test_u1_tebd_equals_dense_gpu_tebd(H):
+    """The blockwise and the dense GPU update give the same chain when no two
+    sectors tie at the cut (the plain one-bond-per-launch form for the U(1)
+    run)."""
+    from paper_1703_00387_amd import api, _lib
+    spec = W.xxz_chain(16, 12, 1.0, 0.5)
+    cu, q = _chain(spec, [1, 0])
+    cd, _ = _chain(spec, [1, 0])
+    api.tebd_step_u1(H, [cu], [q], 2, 0.05, 40, 1e-10, _lib.MPS_FLAG_PLAIN)
+    api.tebd_step(H, [cd], 2, 0.05, 40, 1e-10)
+    assert torch.equal(cu.chi, cd.chi)
+    a, b = _vector(cu), _vector(cd)
+    assert 1.0 - abs(np.vdot(a, b)) / (np.linalg.norm(a) * np.linalg.norm(b)) <= 1e-9
+
+
+def test_u1_tebd_errors(H):
+    from paper_1703_00387_amd import api, _lib
+    spec = W.xxz_chain(6, 4, 1.0, 0.5)
+    ch, q = _chain(spec, [1, 0])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with pytest.raises(_lib.MPSError) as e:
+            api.tebd_step_u1(H, [ch], [q], 2, 0.05, 1, 1e-10, _lib.MPS_FLAG_GRAPH)
+    assert e.value.code == _lib.MPS_ERR_INVALID
+    q.qbond[2, 0] = 100                  # bond 0's columns carry charges no row has
+    with pytest.raises(_lib.MPSError) as e:
+        api.tebd_step_u1(H, [ch], [q], 2, 0.05, 1, 1e-10)
+    assert e.value.code == _lib.MPS_ERR_SHAPE
