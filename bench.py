@@ -67,7 +67,8 @@ def main():
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
     ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256", "bh_heff_chi512", "xxz_grad_L32",
-                             "xxz_sweep_L64", "tfim_quench_L64", "bh_tdvp_L32", "bh_u1_svd_chi320"])
+                             "xxz_sweep_L64", "tfim_quench_L64", "bh_tdvp_L32", "bh_u1_svd_chi320",
+                             "xxz_tebd4_L64_u1"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -102,6 +103,8 @@ def main():
         return bench_tdvp(args)
     if args.workload == "bh_u1_svd_chi320":
         return bench_u1(args)
+    if args.workload == "xxz_tebd4_L64_u1":
+        return bench_u1_tebd(args)
     wl = W.xxz_tebd4_L64()
     spec = wl.chains[0]
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
@@ -354,6 +357,76 @@ def bench_u1(args):
         "u1_ms": round(t_u1 * 1e3, 3),
         "kept": [int(dense[3]), int(blk[4])],
         "max_abs_ds2": float(np.abs(s_d ** 2 - s_b ** 2).max()) if len(s_d) == len(s_b) else None,
+        "device_status": [code, word],
+    }
+    print(json.dumps(out))
+    h.close()
+
+
+def bench_u1_tebd(args):
+    """The headline TEBD4 workload (XXZ L = 64, chi = 256, Neel start) on a
+    charge-carrying chain: the charge is the number of up spins, every update
+    truncated on the charge blocks of its bond.  After the warmup (U(1)
+    steps), the same state is stepped once more on a copy with the dense
+    update, so both rates are measured on one state."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1703_00387_amd import api, models
+
+    wl = W.xxz_tebd4_L64()
+    spec = wl.chains[0]
+    updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
+    h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
+    v = W.initial_vectors(spec)
+    ch = api.Chain.product(v, spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
+    q = api.Charges.product(v, [1, 0], spec.chi_max)
+    t0 = time.time()
+    done = 0
+    while done < args.warmup:
+        n = min(10, args.warmup - done)
+        api.tebd_step_u1(h, [ch], [q], 4, wl.dt, n, wl.eps_local)
+        torch.cuda.synchronize()
+        done += n
+        print(f"[bench] warmup {done}/{args.warmup} U(1) steps, chi_max now {int(ch.chi.max())}, "
+              f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    cd = api.Chain(ch.L, ch.d, ch.chi_max, ch.B.clone(), ch.lam.clone(), ch.chi.clone(), ch.hbond, ch.disc.clone())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.tebd_step_u1(h, [ch], [q], 4, wl.dt, args.steps, wl.eps_local)
+    torch.cuda.synchronize()
+    t_u1 = time.perf_counter() - t1
+    print(f"[bench] {args.steps} U(1) steps {t_u1:.3f}s", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    api.tebd_step(h, [cd], 4, wl.dt, args.steps, wl.eps_local)
+    torch.cuda.synchronize()
+    t_dense = time.perf_counter() - t1
+    print(f"[bench] {args.steps} dense steps {t_dense:.3f}s", file=sys.stderr, flush=True)
+    code, word = h.device_status()
+    chi = ch.chi.cpu().numpy()
+    mid = spec.L // 2
+    qmid = q.qbond[mid, :int(chi[mid])].cpu().numpy()
+    n_upd = updates_per_step * args.steps
+    out = {
+        "metric": "two-site updates per second (TEBD4, U(1) charge blocks)",
+        "value": round(n_upd / t_u1, 3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_u1 / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "xxz_tebd4_L64_u1: XXZ L=64 chi_max=256 TEBD4 from the Neel state, charge n_up",
+                   "L": spec.L, "chi_max": spec.chi_max, "dt": wl.dt, "eps_local": wl.eps_local},
+        "dense_updates_per_s": round(n_upd / t_dense, 3),
+        "speedup_over_dense": round(t_dense / t_u1, 2),
+        "chi_max_reached": int(chi.max()),
+        "sectors_mid_bond": int(len(set(qmid.tolist()))),
         "device_status": [code, word],
     }
     print(json.dumps(out))
