@@ -81,6 +81,23 @@ CASES = [
 ]
 
 
+def _fock_bh(occ, n_max, chi_max):
+    """Bose-Hubbard chain from a product of Fock states (occupations occ): an
+    uneven start breaks the reflection symmetry that would give sectors n and
+    N - n of the middle bond equal spectra (ties at the cut)."""
+    import dataclasses
+    ls = np.zeros((len(occ), n_max + 1), dtype=np.complex128)
+    ls[np.arange(len(occ)), occ] = 1.0
+    return dataclasses.replace(W.bh_chain(len(occ), n_max, chi_max, 1.0, 2.0), init="random_product", local_states=ls)
+
+
+CASES.append(
+    # chi_max = 160 binds at the middle bonds; charge blocks up to 109 rows run
+    # the multi-panel rounds of the Jacobi (the cases above fit one panel)
+    ("bh_tebd2_multipanel", _fock_bh([1, 2, 0, 1, 3, 1, 0, 2, 1, 1], 3, 160), [0, 1, 2, 3], 2, "tebd2", 0.05, 30,
+     1e-10))
+
+
 @pytest.mark.parametrize("name,spec,qsite,order,method,dt,n,eps", CASES, ids=[c[0] for c in CASES])
 def test_u1_tebd_matches_oracle(H, name, spec, qsite, order, method, dt, n, eps):
     from oracle import u1
@@ -140,3 +157,34 @@ def test_u1_tebd_errors(H):
     with pytest.raises(_lib.MPSError) as e:
         api.tebd_step_u1(H, [ch], [q], 2, 0.05, 1, 1e-10)
     assert e.value.code == _lib.MPS_ERR_SHAPE
+
+
+def test_u1_tebd_at_the_bench_shape_equals_dense(H):
+    """XXZ L = 64, chi_max = 256, TEBD4 from the Neel state: after the U(1)
+    warmup to chi = 256 (charge blocks above 64 rows), one more U(1) step and
+    one dense step from copies of the same state keep the same bond
+    dimensions and give the same local S^z and entanglement entropies."""
+    from paper_1703_00387_amd import api, models
+    wl = W.xxz_tebd4_L64()
+    spec = wl.chains[0]
+    ch, q = _chain(spec, [1, 0])
+    for _ in range(14):
+        api.tebd_step_u1(H, [ch], [q], 4, wl.dt, 10, wl.eps_local)
+        print(f"warmup chi {int(ch.chi.max())}", flush=True)
+    chi = ch.chi.cpu().numpy()
+    qb = q.qbond.cpu().numpy()
+    mid = spec.L // 2
+    counts = np.bincount(qb[mid, :chi[mid]] - qb[mid, :chi[mid]].min())
+    assert int(chi.max()) == 256 and (counts[1:] + counts[:-1]).max() > 64   # row blocks n_c + n_{c-1}
+    cd = api.Chain(ch.L, ch.d, ch.chi_max, ch.B.clone(), ch.lam.clone(), ch.chi.clone(), ch.hbond, ch.disc.clone())
+    api.tebd_step_u1(H, [ch], [q], 4, wl.dt, 1, wl.eps_local)
+    api.tebd_step(H, [cd], 4, wl.dt, 1, wl.eps_local)
+    code, word = H.device_status()
+    assert code == 0, word
+    assert torch.equal(ch.chi, cd.chi)
+    su, _, eu = api.observe(H, ch, models.sz_operator(), entropy=True)
+    sd, _, ed = api.observe(H, cd, models.sz_operator(), entropy=True)
+    dz = (su - sd).abs().max().item()
+    de = (eu - ed).abs().max().item()
+    print(f"max|d Sz|={dz:.2e} max|d S|={de:.2e}")
+    assert dz <= 1e-9 and de <= 1e-9
