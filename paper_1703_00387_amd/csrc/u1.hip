@@ -7,6 +7,7 @@
 // their union); the kept right vectors are scattered back to the full column
 // space with the charge of their block, and U = theta V / s.
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -320,6 +321,8 @@ mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const 
   std::vector<U1Block> blocks;
   std::vector<U1Range> ranges(n);
   std::vector<int32_t> rows, cols;
+  std::vector<int32_t> rq, cq, keys;     // per item: row and column charges, distinct row charges
+  std::vector<int> nr, nc, pr, pc;       // per charge slot: counts, then fill positions
   int64_t xw = 0, max_mn = 1;
   int max_m = 1, max_R = 1, k_cap = 1;
   for (int i = 0; i < n; ++i) {
@@ -330,35 +333,79 @@ mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const 
     if (chl < 1 || chl > cm || chr < 1 || chr > cm)
       return mps_fail(h, MPS_ERR_SHAPE, "bond dimension out of range in a charge-carrying chain");
     const int32_t* qs = u1c[chain_of[i]].qsite;
-    std::map<int32_t, std::pair<std::vector<int32_t>, std::vector<int32_t>>> sec;
+    const int M = chl * d, N = d * chr;
+    rq.resize(M);
+    cq.resize(N);
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
     for (int a = 0; a < chl; ++a)
-      for (int s1 = 0; s1 < d; ++s1) sec[o[2 + a] + qs[s1]].first.push_back(a * d + s1);
+      for (int s1 = 0; s1 < d; ++s1) {
+        const int32_t v = o[2 + a] + qs[s1];
+        rq[a * d + s1] = v;
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+      }
     for (int s2 = 0; s2 < d; ++s2)
-      for (int g = 0; g < chr; ++g) sec[o[2 + cm + g] - qs[s2]].second.push_back(s2 * chr + g);
+      for (int g = 0; g < chr; ++g) cq[s2 * chr + g] = o[2 + cm + g] - qs[s2];
+    // charge slots in ascending order: offsets from the smallest row charge
+    // when the rows' charges are dense, else positions among their sorted
+    // distinct values; a column whose charge no row has gets no slot
+    const bool direct = (int64_t)hi - lo < 4LL * (M + N);
+    keys.clear();
+    if (!direct) {
+      keys.assign(rq.begin(), rq.end());
+      std::sort(keys.begin(), keys.end());
+      keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    }
+    auto slot = [&](int32_t v) -> int {
+      if (direct) return (v < lo || v > hi) ? -1 : (int)(v - lo);
+      auto f = std::lower_bound(keys.begin(), keys.end(), v);
+      return (f != keys.end() && *f == v) ? (int)(f - keys.begin()) : -1;
+    };
+    const int K = direct ? (int)(hi - lo + 1) : (int)keys.size();
+    nr.assign(K, 0);
+    nc.assign(K, 0);
+    for (int r = 0; r < M; ++r) nr[slot(rq[r])]++;
+    for (int c = 0; c < N; ++c) {
+      const int k = slot(cq[c]);
+      if (k >= 0) nc[k]++;
+    }
     U1Range& rg = ranges[i];
     rg.blk0 = (int32_t)blocks.size();
     rg.row0 = (int32_t)rows.size();
-    rg.ncols = d * chr;
-    for (auto& kv : sec) {
-      const auto& rr = kv.second.first;
-      const auto& cc = kv.second.second;
-      if (rr.empty() || cc.empty()) continue;
+    rg.ncols = N;
+    pr.assign(K, -1);
+    pc.assign(K, -1);
+    size_t rtot = rows.size(), ctot = cols.size();
+    for (int k = 0; k < K; ++k) {
+      if (nr[k] == 0 || nc[k] == 0) continue;
       U1Block b;
       b.src = it.X;
-      b.ld = (int64_t)d * chr;
-      b.q = kv.first;
-      b.m = (int32_t)rr.size();
-      b.n = (int32_t)cc.size();
-      b.row_off = (int32_t)rows.size();
-      b.col_off = (int32_t)cols.size();
+      b.ld = N;
+      b.q = direct ? lo + k : keys[k];
+      b.m = nr[k];
+      b.n = nc[k];
+      b.row_off = (int32_t)rtot;
+      b.col_off = (int32_t)ctot;
       b.item = i;
       b.x_off = xw;
+      pr[k] = (int)rtot;
+      pc[k] = (int)ctot;
+      rtot += b.m;
+      ctot += b.n;
       xw += (int64_t)b.m * b.n;
       max_m = std::max(max_m, b.m);
       max_mn = std::max<int64_t>(max_mn, (int64_t)b.m * b.n);
-      rows.insert(rows.end(), rr.begin(), rr.end());
-      cols.insert(cols.end(), cc.begin(), cc.end());
       blocks.push_back(b);
+    }
+    rows.resize(rtot);
+    cols.resize(ctot);
+    for (int r = 0; r < M; ++r) {
+      const int k = slot(rq[r]);
+      if (pr[k] >= 0) rows[pr[k]++] = r;
+    }
+    for (int c = 0; c < N; ++c) {
+      const int k = slot(cq[c]);
+      if (k >= 0 && pc[k] >= 0) cols[pc[k]++] = c;
     }
     rg.nblk = (int32_t)blocks.size() - rg.blk0;
     rg.R = (int32_t)rows.size() - rg.row0;

@@ -188,3 +188,28 @@ def test_u1_tebd_at_the_bench_shape_equals_dense(H):
     de = (eu - ed).abs().max().item()
     print(f"max|d Sz|={dz:.2e} max|d S|={de:.2e}")
     assert dz <= 1e-9 and de <= 1e-9
+
+
+def test_u1_tebd_edge_cases(H):
+    """chi_max = 1 (one value kept per update, in one sector), zero steps
+    (nothing changes, charges included) and the fixed-sweep form (no host
+    read-back inside the Jacobi) against the oracle."""
+    from oracle import u1
+    from paper_1703_00387_amd import api, _lib
+    spec = W.xxz_chain(8, 1, 1.0, 0.5)
+    ref, qref = u1.tebd_run_u1(spec, "tebd2", 0.05, 10, 1e-12, [1, 0])
+    ch, q = _chain(spec, [1, 0])
+    api.tebd_step_u1(H, [ch], [q], 2, 0.05, 10, 1e-12)
+    assert int(ch.chi.max().item()) == 1
+    _check(H, ch, q, ref, qref, spec)
+
+    spec = W.xxz_chain(12, 8, 1.0, 0.5)
+    ch, q = _chain(spec, [1, 0])
+    api.tebd_step_u1(H, [ch], [q], 2, 0.05, 20, 1e-10)
+    before = (ch.B.clone(), ch.lam.clone(), ch.chi.clone(), ch.disc.clone(), q.qbond.clone())
+    api.tebd_step_u1(H, [ch], [q], 2, 0.05, 0, 1e-10)
+    for a, b in zip(before, (ch.B, ch.lam, ch.chi, ch.disc, q.qbond)):
+        assert torch.equal(a, b)
+    api.tebd_step_u1(H, [ch], [q], 2, 0.05, 10, 1e-10, _lib.MPS_FLAG_FIXED_SWEEPS)
+    ref, qref = u1.tebd_run_u1(spec, "tebd2", 0.05, 30, 1e-10, [1, 0])
+    _check(H, ch, q, ref, qref, spec)
