@@ -67,35 +67,45 @@ def truncate_u1(theta: np.ndarray, row_q, col_q, chi_max: int, eps: float):
 
 
 # ---------------------------------------------------------------------------
-# Charge-carrying chains: TEBD with the blockwise truncation
+# Charge-carrying chains: TEBD with the blockwise truncation.  The charge is
+# additive: U(1) (modulus 0) or Z_n (modulus n, charges taken modulo n, as
+# for the parity of a particle number with n = 2).
 # ---------------------------------------------------------------------------
 
-def product_charges(vectors: np.ndarray, qsite) -> list:
+def _reduce(q, modulus: int):
+    """Charges of U(1) (modulus 0) as they are; of Z_n (modulus n) in 0..n-1."""
+    q = np.asarray(q, dtype=np.int64)
+    return q if modulus == 0 else np.mod(q, modulus)
+
+
+def product_charges(vectors: np.ndarray, qsite, modulus: int = 0) -> list:
     """Bond charges of a product of basis states: q[b] holds, for the single
-    Schmidt state of bond b, the total charge of sites 0..b-1.  ``vectors``
-    (L, d) must be basis vectors up to a phase."""
+    Schmidt state of bond b, the total charge of sites 0..b-1 (modulo n for a
+    Z_n symmetry, modulus n).  ``vectors`` (L, d) must be basis vectors up to
+    a phase."""
     qsite = np.asarray(qsite)
     q = [np.zeros(1, dtype=np.int64)]
     for v in vectors:
         s = int(np.argmax(np.abs(v)))
         if np.count_nonzero(v) != 1:
             raise ValueError("a charge-carrying product state needs basis states on every site")
-        q.append(np.array([q[-1][0] + qsite[s]], dtype=np.int64))
+        q.append(_reduce([q[-1][0] + qsite[s]], modulus))
     return q
 
 
-def bond_charges(q_left, q_right, qsite):
+def bond_charges(q_left, q_right, qsite, modulus: int = 0):
     """Row and column charges of theta at the bond between two sites: row
     (alpha, s1) carries q_left[alpha] + qsite[s1] (the charge left of the new
     bond), column (s2, gamma) carries q_right[gamma] - qsite[s2] (the charge
-    left of the right bond minus that of the second site)."""
+    left of the right bond minus that of the second site); modulo n for Z_n."""
     qsite = np.asarray(qsite)
     row_q = (np.asarray(q_left)[:, None] + qsite[None, :]).reshape(-1)
     col_q = (np.asarray(q_right)[None, :] - qsite[:, None]).reshape(-1)
-    return row_q, col_q
+    return _reduce(row_q, modulus), _reduce(col_q, modulus)
 
 
-def apply_bond_u1(psi, q: list, qsite, b: int, G: np.ndarray, chi_max: int, eps: float) -> float:
+def apply_bond_u1(psi, q: list, qsite, b: int, G: np.ndarray, chi_max: int, eps: float,
+                  modulus: int = 0) -> float:
     """The Hastings-form update of ``mps.apply_bond`` with the blockwise
     truncation: theta' is cut at bond b+1 by ``truncate_u1`` with the charges
     of ``bond_charges``, and q[b+1] becomes the charges of the kept vectors.
@@ -106,7 +116,7 @@ def apply_bond_u1(psi, q: list, qsite, b: int, G: np.ndarray, chi_max: int, eps:
     theta_t = np.einsum("asb,btc->astc", Bl, Br)
     theta_tp = np.einsum("uvst,astc->auvc", G.reshape(d, d, d, d), theta_t)
     mat = (psi.lam[b][:, None, None, None] * theta_tp).reshape(chl * d, d * chr_)
-    row_q, col_q = bond_charges(q[b], q[b + 2], qsite)
+    row_q, col_q = bond_charges(q[b], q[b + 2], qsite, modulus)
     _, s, Vh, qk, w, nk, _ = truncate_u1(mat, row_q, col_q, chi_max, eps)
     k = len(s)
     psi.lam[b + 1] = s / nk
@@ -117,22 +127,24 @@ def apply_bond_u1(psi, q: list, qsite, b: int, G: np.ndarray, chi_max: int, eps:
     return w
 
 
-def tebd_run_u1(spec, method: str, dt: float, n_steps: int, eps: float, qsite, chi_max=None):
+def tebd_run_u1(spec, method: str, dt: float, n_steps: int, eps: float, qsite, chi_max=None, modulus: int = 0,
+                hs=None):
     """``mps.tebd_run`` on a charge-carrying chain: the product state of
-    ``spec`` (basis states), every update by ``apply_bond_u1``.  Returns the
-    state and its bond charges."""
+    ``spec`` (basis states), every update by ``apply_bond_u1``; bond terms
+    ``hs`` (default: those of ``spec``).  Returns the state and its bond
+    charges."""
     from workloads import initial_vectors
     from . import models
     from .mps import GateCache, product_mps, step_layers
     chi_max = spec.chi_max if chi_max is None else chi_max
     vecs = initial_vectors(spec)
     psi = product_mps(vecs)
-    q = product_charges(vecs, qsite)
-    gates = GateCache(models.bond_hamiltonians(spec))
+    q = product_charges(vecs, qsite, modulus)
+    gates = GateCache(models.bond_hamiltonians(spec) if hs is None else hs)
     for _ in range(n_steps):
         for bonds, tau in step_layers(method, spec.L, dt):
             for b in bonds:
-                apply_bond_u1(psi, q, qsite, b, gates(b, tau), chi_max, eps)
+                apply_bond_u1(psi, q, qsite, b, gates(b, tau), chi_max, eps, modulus)
     return psi, q
 
 

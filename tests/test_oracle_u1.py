@@ -15,6 +15,9 @@ number-conserving states.
   the state is the Trotter circuit's and every bond's Schmidt values split by
   charge as the exact vector's do; truncated, the run equals the dense TEBD
   (same bond dimensions, discarded weight and state).
+* Z_2 charges (the parity of n_up) on an XYZ chain, where n_up itself is not
+  conserved: untruncated, the Trotter circuit and its parity-resolved
+  spectra; the U(1) run misses the circuit; truncated, the dense TEBD.
 """
 import numpy as np
 import pytest
@@ -144,3 +147,63 @@ def test_product_charges_need_basis_states():
         u1.product_charges(W.initial_vectors(spec), [1, 0])
     q = u1.product_charges(W.product_state_vectors("neel", 5, 2), [1, 0])
     assert [int(x[0]) for x in q] == [0, 1, 1, 2, 2, 3]
+
+
+# ---------------------------------------------------------------------------
+# Z_n charges (modulus n): the parity of n_up on an XYZ chain
+# ---------------------------------------------------------------------------
+
+def _xyz_terms(L, jx=1.0, jy=0.6, jz=0.4):
+    """XYZ bond terms: with jx != jy the pair terms s+s+ and s-s- change n_up
+    by 2, so only its parity (Z_2) is conserved."""
+    X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+    Z = np.diag([1.0, -1.0]).astype(np.complex128)
+    h = 0.25 * (jx * np.kron(X, X) + jy * np.kron(Y, Y) + jz * np.kron(Z, Z))
+    return [h.copy() for _ in range(L - 1)]
+
+
+def _circuit(spec, hs, method, dt, n_steps):
+    v = ed.product_vector(W.initial_vectors(spec))
+    for _ in range(n_steps):
+        for bonds, tau in omps.step_layers(method, spec.L, dt):
+            for b in bonds:
+                v = ed.apply_two_site(v, omps.gate(hs[b], tau), b, spec.L, spec.d)
+    return v
+
+
+def test_z2_tebd_of_an_xyz_chain():
+    """Untruncated, the Z_2 run is the Trotter circuit and each bond's Schmidt
+    values split by the parity of the left n_up as the exact vector's do; a
+    U(1) run on the same chain projects out the n_up-changing terms and
+    misses the circuit (the modulus matters); truncated, Z_2 equals the dense
+    TEBD."""
+    L, d = 10, 2
+    spec = W.xxz_chain(L, 32, 1.0, 0.5)
+    hs = _xyz_terms(L)
+    psi, q = u1.tebd_run_u1(spec, "tebd2", 0.1, 5, -1.0, [1, 0], modulus=2, hs=hs)
+    v = _circuit(spec, hs, "tebd2", 0.1, 5)
+    assert 1.0 - abs(np.vdot(omps.to_vector(psi), v)) <= 1e-12
+    for b in range(1, L):
+        M = v.reshape(d ** b, d ** (L - b))
+        par = _left_charges(b, d, [1, 0]) % 2
+        for c in (0, 1):
+            s = np.linalg.svd(M[par == c], compute_uv=False)
+            s = s[s > 1e-6]
+            ours = u1.sector_spectra(psi.lam[b], q[b]).get(c, np.zeros(0))
+            ours = ours[ours > 1e-6]
+            assert len(s) == len(ours) and (len(s) == 0 or np.abs(s - ours).max() <= 1e-10), (b, c)
+        assert set(np.asarray(q[b]).tolist()) <= {0, 1}
+    pu, _ = u1.tebd_run_u1(spec, "tebd2", 0.1, 5, -1.0, [1, 0], modulus=0, hs=hs)
+    assert 1.0 - abs(np.vdot(omps.to_vector(pu), v)) / np.linalg.norm(omps.to_vector(pu)) > 1e-4
+    spec = W.xxz_chain(12, 6, 1.0, 0.5)
+    hs = _xyz_terms(12)
+    pz, _ = u1.tebd_run_u1(spec, "tebd2", 0.05, 30, 1e-10, [1, 0], modulus=2, hs=hs)
+    ref = omps.product_mps(W.initial_vectors(spec))
+    for _ in range(30):
+        for bonds, tau in omps.strang_layers(12, 0.05):
+            for b in bonds:
+                omps.apply_bond(ref, b, omps.gate(hs[b], tau), 6, 1e-10)
+    assert pz.chis() == ref.chis() and sum(ref.disc) > 1e-7
+    a, r = omps.to_vector(pz), omps.to_vector(ref)
+    assert 1.0 - abs(np.vdot(a, r)) / (np.linalg.norm(a) * np.linalg.norm(r)) <= 1e-10
