@@ -239,18 +239,25 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
                          double eps_local, uint32_t flags);
 
 /*
- * Charges of a U(1)-symmetric chain (App. "Convenient features", symmetry
+ * Charges of a symmetric chain (App. "Convenient features", symmetry
  * conservation: a diagonal generator such as the particle number or 2 S^z).
- *   qbond : int32 DEVICE [L+1][chi_max]: qbond[b][a] is the total charge of
- *           sites 0..b-1 in Schmidt state a of bond b (a < chi[b]); bond b+1
- *           is rewritten by every update of the bond between sites b, b+1
- *   qsite : charge of local basis state s (s < d), host values
+ *   qbond   : int32 DEVICE [L+1][chi_max]: qbond[b][a] is the total charge of
+ *             sites 0..b-1 in Schmidt state a of bond b (a < chi[b]); bond
+ *             b+1 is rewritten by every update of the bond between sites b,
+ *             b+1
+ *   qsite   : charge of local basis state s (s < d), host values
+ *   modulus : 0 for U(1) (charges compared as integers); n >= 2 for Z_n
+ *             (charges compared modulo n, written in 0..n-1), e.g. n = 2 for
+ *             the parity of a particle number
  * For a product of basis states q_0 = 0 and q_{b+1} = q_b + qsite[s_b].
+ * Several U(1) generators pack into one charge as q_1 K + q_2 with K larger
+ * than twice the range of q_2, as long as the packed values fit int32.
  */
 typedef struct {
   int32_t* qbond;
   int32_t qsite[5];
-  int32_t reserved[3];
+  int32_t modulus;
+  int32_t reserved[2];
 } mps_u1_chain;
 
 /*
@@ -267,8 +274,9 @@ typedef struct {
  * once per layer (the block shapes set the launches), so MPS_FLAG_GRAPH is
  * refused.
  *   charges : HOST array of n_chains descriptors, one per chain
- * Errors: as mps_tebd_step; MPS_ERR_INVALID for MPS_FLAG_GRAPH or a null
- * qbond; MPS_ERR_SHAPE when no charge is shared across a bond.
+ * Errors: as mps_tebd_step; MPS_ERR_INVALID for MPS_FLAG_GRAPH, a null
+ * qbond or a modulus < 0 or == 1; MPS_ERR_SHAPE when no charge is shared
+ * across a bond.
  */
 mps_status mps_tebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
                             const mps_u1_chain* charges, int32_t n_chains, int32_t order, double dt,

@@ -37,7 +37,7 @@ class ChainDesc(C.Structure):
 
 
 class U1ChainDesc(C.Structure):
-    _fields_ = [("qbond", C.c_void_p), ("qsite", C.c_int32 * 5), ("reserved", C.c_int32 * 3)]
+    _fields_ = [("qbond", C.c_void_p), ("qsite", C.c_int32 * 5), ("modulus", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class OCChainDesc(C.Structure):

@@ -180,15 +180,17 @@ def tebd_step(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_steps
 
 @dataclass
 class Charges:
-    """Bond charges of a U(1)-symmetric chain (layout of mps_u1_chain):
+    """Bond charges of a symmetric chain (layout of mps_u1_chain):
     qbond[b][a] is the charge of sites 0..b-1 in Schmidt state a of bond b,
-    qsite[s] the charge of local basis state s."""
+    qsite[s] the charge of local basis state s; modulus 0 for U(1), n >= 2
+    for Z_n (charges modulo n)."""
     qbond: torch.Tensor    # int32 [L+1][chi_max]
     qsite: tuple
+    modulus: int = 0
 
     @staticmethod
-    def product(vectors: np.ndarray, qsite, chi_max: int, device="cuda") -> "Charges":
-        """Charges of a product of basis states (q_0 = 0, q_{b+1} = q_b + qsite[s_b])."""
+    def product(vectors: np.ndarray, qsite, chi_max: int, device="cuda", modulus: int = 0) -> "Charges":
+        """Charges of a product of basis states (q_0 = 0, q_{b+1} = q_b + qsite[s_b], modulo n for Z_n)."""
         L, d = vectors.shape
         if len(qsite) != d:
             raise ValueError("qsite needs one charge per local basis state")
@@ -199,12 +201,14 @@ class Charges:
             if len(nz) != 1:
                 raise ValueError("a charge-carrying product state needs a basis state on every site")
             acc += int(qsite[nz[0]])
+            if modulus:
+                acc %= modulus
             q[i + 1, 0] = acc
-        return Charges(q.to(device), tuple(int(x) for x in qsite))
+        return Charges(q.to(device), tuple(int(x) for x in qsite), int(modulus))
 
     def desc(self) -> _lib.U1ChainDesc:
         qs = list(self.qsite) + [0] * (5 - len(self.qsite))
-        return _lib.U1ChainDesc(self.qbond.data_ptr(), (C.c_int32 * 5)(*qs), (C.c_int32 * 3)())
+        return _lib.U1ChainDesc(self.qbond.data_ptr(), (C.c_int32 * 5)(*qs), self.modulus, (C.c_int32 * 2)())
 
 
 def tebd_step_u1(h: Handle, chains: Sequence[Chain], charges: Sequence[Charges], order: int, dt: float,

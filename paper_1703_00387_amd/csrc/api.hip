@@ -434,6 +434,8 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
     if (kry) return mps_fail(h, MPS_ERR_INVALID, "charge-carrying chains take the exact gates");
     for (int c = 0; c < n_chains; ++c)
       if (!u1[c].qbond) return mps_fail(h, MPS_ERR_INVALID, "null qbond");
+      else if (u1[c].modulus < 0 || u1[c].modulus == 1)
+        return mps_fail(h, MPS_ERR_INVALID, "modulus must be 0 (U(1)) or at least 2 (Z_n)");
   }
   if (plain && (flags & MPS_FLAG_GRAPH)) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_PLAIN excludes MPS_FLAG_GRAPH");
   hipStream_t s = (hipStream_t)stream;

@@ -333,19 +333,21 @@ mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const 
     if (chl < 1 || chl > cm || chr < 1 || chr > cm)
       return mps_fail(h, MPS_ERR_SHAPE, "bond dimension out of range in a charge-carrying chain");
     const int32_t* qs = u1c[chain_of[i]].qsite;
+    const int32_t md = u1c[chain_of[i]].modulus;  // 0: U(1); n >= 2: Z_n
+    auto red = [md](int64_t v) -> int32_t { return md == 0 ? (int32_t)v : (int32_t)(((v % md) + md) % md); };
     const int M = chl * d, N = d * chr;
     rq.resize(M);
     cq.resize(N);
     int32_t lo = INT32_MAX, hi = INT32_MIN;
     for (int a = 0; a < chl; ++a)
       for (int s1 = 0; s1 < d; ++s1) {
-        const int32_t v = o[2 + a] + qs[s1];
+        const int32_t v = red((int64_t)o[2 + a] + qs[s1]);
         rq[a * d + s1] = v;
         lo = std::min(lo, v);
         hi = std::max(hi, v);
       }
     for (int s2 = 0; s2 < d; ++s2)
-      for (int g = 0; g < chr; ++g) cq[s2 * chr + g] = o[2 + cm + g] - qs[s2];
+      for (int g = 0; g < chr; ++g) cq[s2 * chr + g] = red((int64_t)o[2 + cm + g] - qs[s2]);
     // charge slots in ascending order: offsets from the smallest row charge
     // when the rows' charges are dense, else positions among their sorted
     // distinct values; a column whose charge no row has gets no slot

@@ -213,3 +213,40 @@ def test_u1_tebd_edge_cases(H):
     api.tebd_step_u1(H, [ch], [q], 2, 0.05, 10, 1e-10, _lib.MPS_FLAG_FIXED_SWEEPS)
     ref, qref = u1.tebd_run_u1(spec, "tebd2", 0.05, 30, 1e-10, [1, 0])
     _check(H, ch, q, ref, qref, spec)
+
+
+def _xyz_terms(L, jx=1.0, jy=0.6, jz=0.4):
+    X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    Y = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+    Z = np.diag([1.0, -1.0]).astype(np.complex128)
+    h = 0.25 * (jx * np.kron(X, X) + jy * np.kron(Y, Y) + jz * np.kron(Z, Z))
+    return np.array([h.copy() for _ in range(L - 1)])
+
+
+@pytest.mark.parametrize("order,method,chi", [(2, "tebd2", 8), (0, "sweep", 10)])
+def test_z2_tebd_of_an_xyz_chain(H, order, method, chi):
+    """Z_2 charges (parity of n_up, modulus 2) on an XYZ chain, where n_up
+    itself is not conserved, against the oracle's Z_2 run."""
+    from oracle import u1
+    from paper_1703_00387_amd import api
+    spec = W.xxz_chain(14, chi, 1.0, 0.5)
+    hs = _xyz_terms(spec.L)
+    ref, qref = u1.tebd_run_u1(spec, method, 0.05, 30, 1e-10, [1, 0], modulus=2, hs=list(hs))
+    v = W.initial_vectors(spec)
+    ch = api.Chain.product(v, spec.chi_max, hs)
+    q = api.Charges.product(v, [1, 0], spec.chi_max, modulus=2)
+    api.tebd_step_u1(H, [ch], [q], order, 0.05, 30, 1e-10)
+    code, word = H.device_status()
+    assert code == 0, word
+    assert set(q.qbond.cpu().numpy()[1:-1, 0].tolist()) <= {0, 1}
+    _check(H, ch, q, ref, qref, spec)
+
+
+def test_z2_modulus_one_is_refused(H):
+    from paper_1703_00387_amd import api, _lib
+    spec = W.xxz_chain(6, 4, 1.0, 0.5)
+    ch, q = _chain(spec, [1, 0])
+    q.modulus = 1
+    with pytest.raises(_lib.MPSError) as e:
+        api.tebd_step_u1(H, [ch], [q], 2, 0.05, 1, 1e-10)
+    assert e.value.code == _lib.MPS_ERR_INVALID
