@@ -45,9 +45,11 @@ from .mps import MPS, product_mps, truncate
 
 
 def bond_krylov_update(psi: MPS, b: int, h: np.ndarray, tau: float, chi_max: int, eps: float, n_max: int,
-                       tol: float, moving_right: bool, log=None) -> float:
+                       tol: float, moving_right: bool, log=None, charges=None) -> float:
     """One KTEBD update of bond b with the centre inside the two sites.
-    Returns the discarded weight; appends (b, n_used, err, history, conv) to log."""
+    Returns the discarded weight; appends (b, n_used, err, history, conv) to log.
+    ``charges`` = (q, qsite, modulus) of a charge-carrying chain: the cut
+    runs on the charge blocks (``u1.truncate_u1``) and q[b+1] is updated."""
     Ml, Mr = psi.B[b], psi.B[b + 1]
     chl, d, _ = Ml.shape
     chr_ = Mr.shape[2]
@@ -60,7 +62,14 @@ def bond_krylov_update(psi: MPS, b: int, h: np.ndarray, tau: float, chi_max: int
 
     hist = []
     out, n, err, conv = lanczos_expm(apply_h, theta.reshape(-1), tau, n_max, tol, history=hist)
-    U, s, Vh, w, nk, _ = truncate(out.reshape(chl * d, d * chr_), chi_max, eps)
+    if charges is None:
+        U, s, Vh, w, nk, _ = truncate(out.reshape(chl * d, d * chr_), chi_max, eps)
+    else:
+        from .u1 import bond_charges, truncate_u1
+        q, qsite, modulus = charges
+        rq, cq = bond_charges(q[b], q[b + 2], qsite, modulus)
+        U, s, Vh, qk, w, nk, _ = truncate_u1(out.reshape(chl * d, d * chr_), rq, cq, chi_max, eps)
+        q[b + 1] = qk
     k = len(s)
     lam = s / nk
     psi.lam[b + 1] = lam
@@ -76,14 +85,15 @@ def bond_krylov_update(psi: MPS, b: int, h: np.ndarray, tau: float, chi_max: int
     return w
 
 
-def ktebd_step(psi: MPS, hs, dt: float, chi_max: int, eps: float, n_max: int, tol: float, log=None) -> MPS:
+def ktebd_step(psi: MPS, hs, dt: float, chi_max: int, eps: float, n_max: int, tol: float, log=None,
+               charges=None) -> MPS:
     """One Sornborger-Stewart step with local Krylov propagation (module docstring)."""
     L = psi.L
     tau = 0.5 * dt
     for b in range(L - 1):
-        bond_krylov_update(psi, b, hs[b], tau, chi_max, eps, n_max, tol, True, log)
+        bond_krylov_update(psi, b, hs[b], tau, chi_max, eps, n_max, tol, True, log, charges)
     for b in range(L - 2, -1, -1):
-        bond_krylov_update(psi, b, hs[b], tau, chi_max, eps, n_max, tol, False, log)
+        bond_krylov_update(psi, b, hs[b], tau, chi_max, eps, n_max, tol, False, log, charges)
     return psi
 
 

@@ -148,6 +148,23 @@ def tebd_run_u1(spec, method: str, dt: float, n_steps: int, eps: float, qsite, c
     return psi, q
 
 
+def ktebd_run_u1(spec, dt: float, n_steps: int, eps: float, qsite, n_max: int = 20, tol: float = 1e-10,
+                 modulus: int = 0):
+    """``ktebd.ktebd_run`` on a charge-carrying chain (every cut on the
+    charge blocks of its bond).  Returns the state and its bond charges."""
+    from workloads import initial_vectors
+    from . import models
+    from .ktebd import ktebd_step
+    from .mps import product_mps
+    vecs = initial_vectors(spec)
+    psi = product_mps(vecs)
+    q = product_charges(vecs, qsite, modulus)
+    hs = models.bond_hamiltonians(spec)
+    for _ in range(n_steps):
+        ktebd_step(psi, hs, dt, spec.chi_max, eps, n_max, tol, charges=(q, qsite, modulus))
+    return psi, q
+
+
 def sector_spectra(lam, q) -> dict:
     """{charge: Schmidt values of that charge, descending} of one bond."""
     out = {}

@@ -207,3 +207,17 @@ def test_z2_tebd_of_an_xyz_chain():
     assert pz.chis() == ref.chis() and sum(ref.disc) > 1e-7
     a, r = omps.to_vector(pz), omps.to_vector(ref)
     assert 1.0 - abs(np.vdot(a, r)) / (np.linalg.norm(a) * np.linalg.norm(r)) <= 1e-10
+
+
+def test_krylov_tebd_on_charge_blocks_equals_dense_krylov_tebd():
+    """The Krylov sweep with the blockwise cut equals the dense Krylov sweep
+    under truncation (same bond dimensions and state), and its bond charges
+    split the Schmidt values as at the start of the next update."""
+    from oracle import ktebd
+    spec = W.xxz_chain(10, 6, 1.0, 0.5)
+    psi, q = u1.ktebd_run_u1(spec, 0.05, 20, 1e-10, [1, 0], n_max=20, tol=1e-12)
+    ref = ktebd.ktebd_run(spec, 0.05, 20, 1e-10, n_max=20, tol=1e-12)
+    assert psi.chis() == ref.chis() and sum(ref.disc) > 1e-8
+    a, r = omps.to_vector(psi), omps.to_vector(ref)
+    assert 1.0 - abs(np.vdot(a, r)) / (np.linalg.norm(a) * np.linalg.norm(r)) <= 1e-10
+    assert all(len(q[b]) == len(psi.lam[b]) for b in range(spec.L + 1))
