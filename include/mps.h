@@ -318,6 +318,18 @@ mps_status mps_ktebd_step(mps_handle h, mps_stream stream, const mps_chain_desc*
                           int32_t n_max, double tol, uint32_t flags, int32_t* n_used_dev);
 
 /*
+ * mps_ktebd_step on charge-carrying chains: the Krylov sweep with every cut
+ * on the charge blocks of its bond, as in mps_tebd_step_u1 (App. "Convenient
+ * features", symmetry conservation; App. "Details of the Krylov method").
+ * The bond Hamiltonians must commute with the charge, so the Lanczos
+ * propagator does.  Arguments, errors and limits as mps_ktebd_step and
+ * mps_tebd_step_u1.
+ */
+mps_status mps_ktebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                             const mps_u1_chain* charges, int32_t n_chains, double dt, int32_t n_steps,
+                             double eps_local, int32_t n_max, double tol, uint32_t flags, int32_t* n_used_dev);
+
+/*
  * n_steps steps of a time-dependent Hamiltonian H(t) = sum_k f_k(t) H_k
  * (Sec. "Time evolution methods": time ordering by commutator-free Magnus
  * expansions).  Step n covers [t_n, t_n + dt] with t_n = t0 + n dt and is a

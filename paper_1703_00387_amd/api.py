@@ -240,6 +240,17 @@ def ktebd_step(h: Handle, chains: Sequence[Chain], dt: float, n_steps: int, eps:
                                  float(tol), flags, _ptr(n_used)))
 
 
+def ktebd_step_u1(h: Handle, chains: Sequence[Chain], charges: Sequence[Charges], dt: float, n_steps: int,
+                  eps: float, n_max: int = 20, tol: float = 1e-10, flags: int = 0):
+    """ktebd_step on charge-carrying chains (every cut on the charge blocks of its bond)."""
+    if len(charges) != len(chains):
+        raise ValueError("one Charges per chain")
+    arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
+    qa = (_lib.U1ChainDesc * len(chains))(*[q.desc() for q in charges])
+    h.check(lib().mps_ktebd_step_u1(h.h, _stream(), arr, qa, len(chains), float(dt), n_steps, float(eps),
+                                    int(n_max), float(tol), flags, None))
+
+
 def cfme_nodes(scheme: int):
     """Nodes c_j of a commutator-free Magnus scheme (2 or 4)."""
     nodes = (C.c_double * 2)()

@@ -401,6 +401,18 @@ mps_status mps_ktebd_step(mps_handle h, mps_stream stream, const mps_chain_desc*
   return tebd_impl(h, stream, chains, n_chains, 0, dt, n_steps, eps_local, flags, 0, 1 << 30, &k);
 }
 
+mps_status mps_ktebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                             const mps_u1_chain* charges, int32_t n_chains, double dt, int32_t n_steps,
+                             double eps_local, int32_t n_max, double tol, uint32_t flags, int32_t* n_used_dev) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!charges) return mps_fail(h, MPS_ERR_INVALID, "null charges");
+  KryOpts k;
+  k.n_max = n_max;
+  k.tol = tol;
+  k.n_used_dev = n_used_dev;
+  return tebd_impl(h, stream, chains, n_chains, 0, dt, n_steps, eps_local, flags, 0, 1 << 30, &k, charges);
+}
+
 mps_status mps_tebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
                             const mps_u1_chain* charges, int32_t n_chains, int32_t order, double dt,
                             int32_t n_steps, double eps_local, uint32_t flags) {
@@ -431,7 +443,6 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   const bool plain = flags & MPS_FLAG_PLAIN;
   if (u1) {
     if (flags & MPS_FLAG_GRAPH) return mps_fail(h, MPS_ERR_INVALID, "charge-carrying chains cannot be captured");
-    if (kry) return mps_fail(h, MPS_ERR_INVALID, "charge-carrying chains take the exact gates");
     for (int c = 0; c < n_chains; ++c)
       if (!u1[c].qbond) return mps_fail(h, MPS_ERR_INVALID, "null qbond");
       else if (u1[c].modulus < 0 || u1[c].modulus == 1)

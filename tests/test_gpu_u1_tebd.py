@@ -250,3 +250,18 @@ def test_z2_modulus_one_is_refused(H):
     with pytest.raises(_lib.MPSError) as e:
         api.tebd_step_u1(H, [ch], [q], 2, 0.05, 1, 1e-10)
     assert e.value.code == _lib.MPS_ERR_INVALID
+
+
+@pytest.mark.parametrize("spec,qsite", [(W.xxz_chain(12, 8, 1.0, 0.5), [1, 0]),
+                                        (W.bh_chain(8, 2, 16, 1.0, 3.0), [0, 1, 2])], ids=["xxz", "bh"])
+def test_krylov_tebd_on_charge_blocks(H, spec, qsite):
+    """mps_ktebd_step_u1 (the Krylov sweep, every cut on the charge blocks)
+    against the oracle's Krylov sweep with the blockwise cut."""
+    from oracle import u1
+    from paper_1703_00387_amd import api
+    ref, qref = u1.ktebd_run_u1(spec, 0.05, 20, 1e-10, qsite, n_max=20, tol=1e-12)
+    ch, q = _chain(spec, qsite)
+    api.ktebd_step_u1(H, [ch], [q], 0.05, 20, 1e-10, 20, 1e-12)
+    code, word = H.device_status()
+    assert code == 0, word
+    _check(H, ch, q, ref, qref, spec)
