@@ -53,9 +53,11 @@ def combine(term_hs, coef) -> list:
 
 
 def td_tebd_run(psi: mps.MPS, term_hs, f, method: str, dt: float, n_steps: int, eps: float, chi_max: int,
-                scheme: int = 2, t0: float = 0.0, observe=None) -> mps.MPS:
+                scheme: int = 2, t0: float = 0.0, observe=None, charges=None) -> mps.MPS:
     """n_steps steps from time t0: every exponential of the scheme is one
-    Trotter step of ``method`` with its combined bond Hamiltonians."""
+    Trotter step of ``method`` with its combined bond Hamiltonians.
+    ``charges`` = (q, qsite, modulus) of a charge-carrying chain: every
+    update by ``u1.apply_bond_u1`` (q is updated in place)."""
     L = psi.L
     layers = mps.step_layers(method, L, dt)
     if observe:
@@ -65,7 +67,12 @@ def td_tebd_run(psi: mps.MPS, term_hs, f, method: str, dt: float, n_steps: int, 
             hs = combine(term_hs, coef)
             for bonds, tau in layers:
                 for b in bonds:
-                    mps.apply_bond(psi, b, mps.gate(hs[b], tau), chi_max, eps)
+                    if charges is None:
+                        mps.apply_bond(psi, b, mps.gate(hs[b], tau), chi_max, eps)
+                    else:
+                        from .u1 import apply_bond_u1
+                        q, qsite, modulus = charges
+                        apply_bond_u1(psi, q, qsite, b, mps.gate(hs[b], tau), chi_max, eps, modulus)
         if observe:
             observe(psi, n + 1)
     return psi

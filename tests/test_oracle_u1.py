@@ -221,3 +221,22 @@ def test_krylov_tebd_on_charge_blocks_equals_dense_krylov_tebd():
     a, r = omps.to_vector(psi), omps.to_vector(ref)
     assert 1.0 - abs(np.vdot(a, r)) / (np.linalg.norm(a) * np.linalg.norm(r)) <= 1e-10
     assert all(len(q[b]) == len(psi.lam[b]) for b in range(spec.L + 1))
+
+
+def test_time_dependent_run_on_charge_blocks_equals_dense():
+    """The Magnus-scheme run with the blockwise cut (H(t) = H_xy + f(t) H_zz,
+    both conserving n_up) equals the dense run under truncation."""
+    from oracle import models as om, timedep
+    L, chi = 10, 8
+    spec = W.xxz_chain(L, chi, 1.0, 0.5)
+    hxy = om.bond_hamiltonians(W.xxz_chain(L, chi, 1.0, 0.0))
+    hzz = [om.bond_hamiltonians(W.xxz_chain(L, chi, 1.0, 1.0))[b] - hxy[b] for b in range(L - 1)]
+    f = lambda t: np.array([1.0, 0.5 + 0.5 * np.sin(2.0 * t)])
+    v = W.initial_vectors(spec)
+    q = u1.product_charges(v, [1, 0])
+    a = timedep.td_tebd_run(omps.product_mps(v), [hxy, hzz], f, "tebd4", 0.05, 16, 1e-10, chi, 4,
+                            charges=(q, [1, 0], 0))
+    r = timedep.td_tebd_run(omps.product_mps(v), [hxy, hzz], f, "tebd4", 0.05, 16, 1e-10, chi, 4)
+    assert a.chis() == r.chis() and sum(r.disc) > 1e-9
+    va, vr = omps.to_vector(a), omps.to_vector(r)
+    assert 1.0 - abs(np.vdot(va, vr)) / (np.linalg.norm(va) * np.linalg.norm(vr)) <= 1e-10
