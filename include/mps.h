@@ -355,6 +355,18 @@ mps_status mps_tebd_td_step(mps_handle h, mps_stream stream, const mps_chain_des
                             int32_t n_chains, int32_t order, double dt, int32_t n_steps,
                             double eps_local, uint32_t flags, int32_t n_terms, int32_t scheme,
                             const double* f_nodes, void* hwork);
+
+/*
+ * mps_tebd_td_step on charge-carrying chains: every exponential's Trotter
+ * step is a mps_tebd_step_u1 step (App. "Convenient features", symmetry
+ * conservation; Sec. "Time evolution methods", time ordering).  Every term
+ * set must commute with the charge.  Arguments, errors and limits as
+ * mps_tebd_td_step and mps_tebd_step_u1.
+ */
+mps_status mps_tebd_td_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                               const mps_u1_chain* charges, int32_t n_chains, int32_t order, double dt,
+                               int32_t n_steps, double eps_local, uint32_t flags, int32_t n_terms, int32_t scheme,
+                               const double* f_nodes, void* hwork);
 /* The nodes c_j of a scheme (host only): nodes[0..n_nodes-1]; MPS_ERR_INVALID
  * for an unknown scheme. */
 mps_status mps_cfme_nodes(int32_t scheme, double* nodes, int32_t* n_nodes);

@@ -24,7 +24,7 @@ MPS_C64, MPS_C128 = 0, 1
 
 # every exported symbol that include/mps.h declares
 EXPORTS = ["mps_create", "mps_destroy", "mps_last_error", "mps_reserve", "mps_device_status",
-           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_cfme_nodes",
+           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
            "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step",
            "mps_tebd_grad_arena_bytes", "mps_tebd_grad", "mps_tebd_vjp", "mps_autotune_jacobi",
            "mps_autotune_candidate"]
@@ -78,6 +78,8 @@ def lib():
         "mps_ktebd_step_u1": [vp, vp, C.POINTER(ChainDesc), C.POINTER(U1ChainDesc), i32, dbl, i32, dbl, i32, dbl, u32,
                               vp],
         "mps_ktebd_step": [vp, vp, C.POINTER(ChainDesc), i32, dbl, i32, dbl, i32, dbl, u32, vp],
+        "mps_tebd_td_step_u1": [vp, vp, C.POINTER(ChainDesc), C.POINTER(U1ChainDesc), i32, i32, dbl, i32, dbl, u32,
+                                i32, i32, vp, vp],
         "mps_tebd_td_step": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32, i32, i32, vp, vp],
         "mps_cfme_nodes": [i32, vp, vp],
         "mps_autotune_jacobi": [vp, vp, i32, i32, i32, i32, vp, vp, vp],

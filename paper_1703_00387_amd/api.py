@@ -7,7 +7,7 @@ from __future__ import annotations
 
 import ctypes as C
 from dataclasses import dataclass
-from typing import List, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -261,9 +261,10 @@ def cfme_nodes(scheme: int):
 
 
 def tebd_td_step(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_steps: int, eps: float,
-                 f_nodes, scheme: int = 2, flags: int = 0):
+                 f_nodes, scheme: int = 2, flags: int = 0, charges: Optional[Sequence["Charges"]] = None):
     """Time-dependent steps; every chain's hbond holds its term split
-    [n_terms][L-1][d*d][d*d] and f_nodes[n][j][k] = f_k(t_n + c_j dt)."""
+    [n_terms][L-1][d*d][d*d] and f_nodes[n][j][k] = f_k(t_n + c_j dt).
+    charges: one Charges per chain for charge-carrying chains."""
     f = np.ascontiguousarray(f_nodes, dtype=np.float64)
     if f.ndim != 3 or f.shape[0] != n_steps:
         raise ValueError("f_nodes must be [n_steps][n_nodes][n_terms]")
@@ -276,6 +277,14 @@ def tebd_td_step(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_st
         total += (c.L - 1) * dd * dd
     hwork = torch.empty(total, dtype=torch.complex128, device=chains[0].B.device)
     arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
+    if charges is not None:
+        if len(charges) != len(chains):
+            raise ValueError("one Charges per chain")
+        qa = (_lib.U1ChainDesc * len(chains))(*[q.desc() for q in charges])
+        h.check(lib().mps_tebd_td_step_u1(h.h, _stream(), arr, qa, len(chains), order, float(dt), n_steps,
+                                          float(eps), flags, n_terms, int(scheme), f.ctypes.data_as(C.c_void_p),
+                                          _ptr(hwork)))
+        return
     h.check(lib().mps_tebd_td_step(h.h, _stream(), arr, len(chains), order, float(dt), n_steps, float(eps), flags,
                                    n_terms, int(scheme), f.ctypes.data_as(C.c_void_p), _ptr(hwork)))
 

@@ -64,6 +64,10 @@ int scheme_table(int scheme, double* nodes, double W[2][2], int* n_exp) {
 
 }  // namespace
 
+mps_status td_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
+                   double dt, int32_t n_steps, double eps_local, uint32_t flags, int32_t n_terms, int32_t scheme,
+                   const double* f_nodes, void* hwork, const mps_u1_chain* u1);
+
 extern "C" {
 
 mps_status mps_cfme_nodes(int32_t scheme, double* nodes, int32_t* n_nodes) {
@@ -79,6 +83,25 @@ mps_status mps_cfme_nodes(int32_t scheme, double* nodes, int32_t* n_nodes) {
 mps_status mps_tebd_td_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
                             int32_t order, double dt, int32_t n_steps, double eps_local, uint32_t flags,
                             int32_t n_terms, int32_t scheme, const double* f_nodes, void* hwork) {
+  return td_impl(h, stream, chains, n_chains, order, dt, n_steps, eps_local, flags, n_terms, scheme, f_nodes, hwork,
+                 nullptr);
+}
+
+mps_status mps_tebd_td_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                               const mps_u1_chain* charges, int32_t n_chains, int32_t order, double dt,
+                               int32_t n_steps, double eps_local, uint32_t flags, int32_t n_terms, int32_t scheme,
+                               const double* f_nodes, void* hwork) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!charges) return mps_fail(h, MPS_ERR_INVALID, "null charges");
+  return td_impl(h, stream, chains, n_chains, order, dt, n_steps, eps_local, flags, n_terms, scheme, f_nodes, hwork,
+                 charges);
+}
+
+}  // extern "C"
+
+mps_status td_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
+                   double dt, int32_t n_steps, double eps_local, uint32_t flags, int32_t n_terms, int32_t scheme,
+                   const double* f_nodes, void* hwork, const mps_u1_chain* u1) {
   if (!h) return MPS_ERR_INVALID;
   if (!chains || n_chains < 1) return mps_fail(h, MPS_ERR_INVALID, "need at least one chain");
   if (n_terms < 1 || n_terms > kMaxTerms) return mps_fail(h, MPS_ERR_INVALID, "n_terms must be in 1..16");
@@ -116,11 +139,10 @@ mps_status mps_tebd_td_step(mps_handle h, mps_stream stream, const mps_chain_des
                                                   n_terms, tw);
         MPS_TRY_HIP(h, hipGetLastError());
       }
-      mps_status st = tebd_impl(h, stream, tmp.data(), n_chains, order, dt, 1, eps_local, flags, 0, 1 << 30);
+      mps_status st = tebd_impl(h, stream, tmp.data(), n_chains, order, dt, 1, eps_local, flags, 0, 1 << 30, nullptr,
+                                u1);
       if (st != MPS_OK) return st;
     }
   }
   return MPS_OK;
 }
-
-}  // extern "C"

@@ -265,3 +265,30 @@ def test_krylov_tebd_on_charge_blocks(H, spec, qsite):
     code, word = H.device_status()
     assert code == 0, word
     _check(H, ch, q, ref, qref, spec)
+
+
+def test_time_dependent_steps_on_charge_blocks(H):
+    """mps_tebd_td_step_u1: an XXZ chain with a time-dependent anisotropy
+    (H(t) = H_xy + f(t) H_zz, both terms conserve n_up), the fourth-order
+    Magnus scheme over TEBD4, against the oracle's scheme with the blockwise
+    cut."""
+    from oracle import models as om, timedep, u1, mps as omps
+    from paper_1703_00387_amd import api
+    L, chi, dt, n = 10, 8, 0.05, 16
+    spec = W.xxz_chain(L, chi, 1.0, 0.5)
+    hxy = om.bond_hamiltonians(W.xxz_chain(L, chi, 1.0, 0.0))
+    hzz = [om.bond_hamiltonians(W.xxz_chain(L, chi, 1.0, 1.0))[b] - hxy[b] for b in range(L - 1)]
+    terms = [hxy, hzz]
+    f = lambda t: np.array([1.0, 0.5 + 0.5 * np.sin(2.0 * t)])
+    v = W.initial_vectors(spec)
+    qref = u1.product_charges(v, [1, 0])
+    ref = timedep.td_tebd_run(omps.product_mps(v), terms, f, "tebd4", dt, n, 1e-10, chi, 4,
+                              charges=(qref, [1, 0], 0))
+    ch = api.Chain.product(v, chi, np.array(terms))
+    q = api.Charges.product(v, [1, 0], chi)
+    nodes = api.cfme_nodes(4)
+    fn = np.array([[f(k * dt + c * dt) for c in nodes] for k in range(n)])
+    api.tebd_td_step(H, [ch], 4, dt, n, 1e-10, fn, 4, charges=[q])
+    code, word = H.device_status()
+    assert code == 0, word
+    _check(H, ch, q, ref, qref, spec)
