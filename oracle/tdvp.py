@@ -121,10 +121,26 @@ def _right_envs(psi: OCMPS, Ws):
     return R
 
 
+def _split(th2, b, chi_max, eps, charges):
+    """Truncated SVD of the two-site matrix of bond b: dense, or on the charge
+    blocks of a charge-carrying chain (charges = (q, qsite, modulus); q[b+1]
+    becomes the charges of the kept vectors)."""
+    if charges is None:
+        return truncate(th2, chi_max, eps)
+    from .u1 import bond_charges, truncate_u1
+    q, qsite, modulus = charges
+    rq, cq = bond_charges(q[b], q[b + 2], qsite, modulus)
+    U, s, Vh, qk, w, nk, s_all = truncate_u1(th2, rq, cq, chi_max, eps)
+    q[b + 1] = qk
+    return U, s, Vh, w, nk, s_all
+
+
 def tdvp2_step(psi: OCMPS, Ws, dt: float, chi_max: int, eps: float, n_max=20, tol=1e-10,
-               log=None):
+               log=None, charges=None):
     """One symmetric 2TDVP step.  psi must have its orthogonality centre on
-    site 0 with all other sites right-canonical; on return the same holds."""
+    site 0 with all other sites right-canonical; on return the same holds.
+    ``charges`` = (q, qsite, modulus): every split on the charge blocks of
+    its bond (App. "Convenient features"), q updated in place."""
     L = psi.L
     w = Ws[0].shape[0]
     tau = 0.5 * dt
@@ -141,7 +157,7 @@ def tdvp2_step(psi: OCMPS, Ws, dt: float, chi_max: int, eps: float, n_max=20, to
         th, n, err, conv = lanczos_expm(f, th.reshape(-1), tau, n_max, tol)
         if log is not None:
             log.append(("2f", b, n, err, conv))
-        U, s, Vh, wdisc, nk, _ = truncate(th.reshape(sh[0] * sh[1], sh[2] * sh[3]), chi_max, eps)
+        U, s, Vh, wdisc, nk, _ = _split(th.reshape(sh[0] * sh[1], sh[2] * sh[3]), b, chi_max, eps, charges)
         k = len(s)
         psi.M[b] = U.reshape(sh[0], sh[1], k)
         C = (s[:, None] * Vh).reshape(k, sh[2], sh[3])
@@ -162,7 +178,7 @@ def tdvp2_step(psi: OCMPS, Ws, dt: float, chi_max: int, eps: float, n_max=20, to
         th, n, err, conv = lanczos_expm(f, th.reshape(-1), tau, n_max, tol)
         if log is not None:
             log.append(("2f", b, n, err, conv))
-        U, s, Vh, wdisc, nk, _ = truncate(th.reshape(sh[0] * sh[1], sh[2] * sh[3]), chi_max, eps)
+        U, s, Vh, wdisc, nk, _ = _split(th.reshape(sh[0] * sh[1], sh[2] * sh[3]), b, chi_max, eps, charges)
         k = len(s)
         psi.M[b + 1] = Vh.reshape(k, sh[2], sh[3])
         C = (U * s[None, :]).reshape(sh[0], sh[1], k)

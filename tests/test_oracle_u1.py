@@ -240,3 +240,25 @@ def test_time_dependent_run_on_charge_blocks_equals_dense():
     assert a.chis() == r.chis() and sum(r.disc) > 1e-9
     va, vr = omps.to_vector(a), omps.to_vector(r)
     assert 1.0 - abs(np.vdot(va, vr)) / (np.linalg.norm(va) * np.linalg.norm(vr)) <= 1e-10
+
+
+@pytest.mark.parametrize("spec,qsite", [(W.xxz_chain(8, 6, 1.0, 0.5), [1, 0]),
+                                        (W.bh_chain(6, 2, 9, 1.0, 3.0), [0, 1, 2])], ids=["xxz", "bh"])
+def test_tdvp_on_charge_blocks_equals_dense_tdvp(spec, qsite):
+    """Two-site TDVP with every split on the charge blocks equals the dense
+    TDVP under truncation, and the bond charges follow the bond dimensions."""
+    from oracle import models as om, tdvp as ot
+    Ws = om.mpo(spec)
+    v = W.initial_vectors(spec)
+    a = ot.product_oc(v)
+    r = ot.product_oc(v)
+    q = u1.product_charges(v, qsite)
+    for _ in range(10):
+        ot.tdvp2_step(a, Ws, 0.05, spec.chi_max, 1e-10, 20, 1e-12, charges=(q, qsite, 0))
+        ot.tdvp2_step(r, Ws, 0.05, spec.chi_max, 1e-10, 20, 1e-12)
+    chis = [T.shape[0] for T in a.M] + [1]
+    assert chis == [T.shape[0] for T in r.M] + [1]
+    assert max(chis) > 2
+    assert all(len(q[b]) == chis[b] for b in range(spec.L + 1))
+    va, vr = a.to_vector(), r.to_vector()
+    assert 1.0 - abs(np.vdot(va, vr)) / (np.linalg.norm(va) * np.linalg.norm(vr)) <= 1e-10
