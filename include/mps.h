@@ -465,6 +465,22 @@ mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* c
                           double eps_local, int32_t n_max, double tol, double* disc_dev, int32_t* krylov_max_dev);
 
 /*
+ * mps_tdvp2_step on a charge-carrying chain: every two-site split runs on the
+ * charge blocks of its bond (App. "Convenient features", symmetry
+ * conservation), row (a, s1) of theta carrying qbond[b][a] + qsite[s1] and
+ * column (s2, g) qbond[b+2][g] - qsite[s2]; A_b = U_k (left to right) or
+ * B_{b+1} = V^dag_k (right to left) vanish off each kept vector's block, and
+ * qbond[b+1] takes the kept charges.  The MPO must commute with the charge.
+ *   charges : one HOST descriptor (mps_u1_chain, qbond on the device)
+ * Errors: as mps_tdvp2_step; MPS_ERR_INVALID for null charges or a modulus
+ * < 0 or == 1; MPS_ERR_SHAPE for d > 5 or when no charge is shared across a
+ * bond.
+ */
+mps_status mps_tdvp2_step_u1(mps_handle h, mps_stream stream, const mps_oc_chain* chain,
+                             const mps_u1_chain* charges, double dt, int32_t n_steps, double eps_local,
+                             int32_t n_max, double tol, double* disc_dev, int32_t* krylov_max_dev);
+
+/*
  * Reverse-mode gradient of a truncated TEBD2 run (second-order Trotter-Suzuki
  * splitting of Sec. "Time evolution methods", with the truncated SVD of Sec.
  * "Basic concepts in tensor network techniques") with respect to per-bond

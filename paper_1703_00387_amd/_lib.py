@@ -25,7 +25,7 @@ MPS_C64, MPS_C128 = 0, 1
 # every exported symbol that include/mps.h declares
 EXPORTS = ["mps_create", "mps_destroy", "mps_last_error", "mps_reserve", "mps_device_status",
            "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
-           "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step",
+           "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step", "mps_tdvp2_step_u1",
            "mps_tebd_grad_arena_bytes", "mps_tebd_grad", "mps_tebd_vjp", "mps_autotune_jacobi",
            "mps_autotune_candidate"]
 
@@ -89,6 +89,7 @@ def lib():
         "mps_krylov_expm": [vp, vp, i32, vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, i32, i32, dbl, dbl, i32, dbl,
                             vp, vp],
         "mps_env_update": [vp, vp, i32, i32, vp, vp, vp, vp, i64, i32, i64, i32, i32],
+        "mps_tdvp2_step_u1": [vp, vp, C.POINTER(OCChainDesc), C.POINTER(U1ChainDesc), dbl, i32, dbl, i32, dbl, vp, vp],
         "mps_tdvp2_step": [vp, vp, C.POINTER(OCChainDesc), dbl, i32, dbl, i32, dbl, vp, vp],
         "mps_tebd_grad": [vp, vp, C.POINTER(ChainDesc), vp, dbl, i32, dbl, dbl, vp, i32, vp, vp, C.c_size_t, vp, vp],
         "mps_tebd_vjp": [vp, vp, C.POINTER(ChainDesc), vp, dbl, i32, dbl, dbl, vp, vp, vp, vp, vp, C.c_size_t, vp, vp],

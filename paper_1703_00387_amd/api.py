@@ -512,9 +512,19 @@ class OCChain:
         return v.reshape(-1)
 
 
-def tdvp2_step(h: Handle, chain: OCChain, dt: float, n_steps: int, eps: float, n_max=20, tol=1e-10):
+def tdvp2_step(h: Handle, chain: OCChain, dt: float, n_steps: int, eps: float, n_max=20, tol=1e-10,
+               charges: Optional["Charges"] = None):
+    """Two-site TDVP steps; charges: the chain's Charges for a charge-carrying
+    chain (every split on the charge blocks of its bond)."""
     kmax = torch.zeros(1, dtype=torch.int32, device=chain.M.device)
     d = chain.desc()
-    h.check(lib().mps_tdvp2_step(h.h, _stream(), C.byref(d), float(dt), n_steps, float(eps), n_max, float(tol),
-                                 _ptr(chain.disc), _ptr(kmax)))
+    if charges is not None:
+        if charges.qbond.shape != (chain.L + 1, chain.chi_max) or charges.qbond.dtype != torch.int32:
+            raise ValueError("qbond must be an int32 tensor [L+1][chi_max]")
+        q = charges.desc()
+        h.check(lib().mps_tdvp2_step_u1(h.h, _stream(), C.byref(d), C.byref(q), float(dt), n_steps, float(eps),
+                                        n_max, float(tol), _ptr(chain.disc), _ptr(kmax)))
+    else:
+        h.check(lib().mps_tdvp2_step(h.h, _stream(), C.byref(d), float(dt), n_steps, float(eps), n_max, float(tol),
+                                     _ptr(chain.disc), _ptr(kmax)))
     return int(kmax.item())

@@ -96,6 +96,16 @@ mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const 
                     int n, const mps_u1_chain* u1c, int n_cap, int m_cap, int chi_cap, double eps, bool c128,
                     char* region, SelOut* sel, int32_t* unconv, bool fixed);
 
+// One matrix X (complex128 [m][n], m, n <= m_cap) truncated on its charge
+// blocks (row_q, col_q on the host); the kept rows, normalised, go to dst in
+// the chain precision as rows [k][n] or, col_major, as columns [n][k]; k, the
+// discarded weight and the kept charges (q_out, host) are returned.  region
+// holds u1_layer_bytes(1, m_cap, chi_cap) bytes, sel one device SelOut.
+mps_status u1_split_one(mps_handle h, hipStream_t s, const double2* X, int m, int n, const int32_t* row_q,
+                        const int32_t* col_q, int kmax, double eps, char* region, int m_cap, int chi_cap,
+                        SelOut* sel, void* dst, int col_major, bool c128, int* k_out, double* disc_out,
+                        int32_t* q_out);
+
 // kernel timing helpers (host)
 void prof_begin(mps_handle h, hipStream_t s, int id);
 void prof_end(mps_handle h, hipStream_t s, int id);

@@ -257,10 +257,12 @@ struct TdvpWs {
   double* s2;
   SelOut* sel;
   int32_t* unconv;
+  char* u1r;  // charge-carrying chains: workspace of the blockwise split
 };
 
 // plan and carve the workspace for a chain with the given capacities
-mps_status tdvp_workspace(mps_handle h, bool c128, int chi_max, int d, int w, int L, int n_max, TdvpWs& t) {
+mps_status tdvp_workspace(mps_handle h, bool c128, int chi_max, int d, int w, int L, int n_max, TdvpWs& t,
+                          bool u1 = false) {
   const size_t es = esize(c128);
   const long long Nmax = (long long)chi_max * d * d * chi_max;
   const long long Xmax = (long long)chi_max * w * d * d * chi_max;
@@ -279,6 +281,7 @@ mps_status tdvp_workspace(mps_handle h, bool c128, int chi_max, int d, int w, in
   size_t o_mat = p.take<JacMat>(1), o_rm = p.take<int32_t>(m_cap), o_pm = p.take<int32_t>(m_cap),
          o_nr = p.take<double>(m_cap);
   size_t o_s2 = p.take<double>(m_cap), o_sel = p.take<SelOut>(1), o_unc = p.take<int32_t>(8);
+  size_t o_u1 = u1 ? p.take<char>(u1_layer_bytes(1, m_cap, chi_max)) : 0;
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
   char* ws = h->ws;
@@ -307,6 +310,7 @@ mps_status tdvp_workspace(mps_handle h, bool c128, int chi_max, int d, int w, in
   t.s2 = (double*)(ws + o_s2);
   t.sel = (SelOut*)(ws + o_sel);
   t.unconv = (int32_t*)(ws + o_unc);
+  t.u1r = u1 ? ws + o_u1 : nullptr;
   return MPS_OK;
 }
 
@@ -338,6 +342,10 @@ mps_status svd_select(mps_handle h, hipStream_t s, TdvpWs& t, int m, int n, int 
 }
 
 }  // namespace
+
+mps_status tdvp_impl(mps_handle h, mps_stream stream, const mps_oc_chain* chain, double dt, int32_t n_steps,
+                     double eps_local, int32_t n_max, double tol, double* disc_dev, int32_t* krylov_max_dev,
+                     const mps_u1_chain* u1);
 
 extern "C" {
 
@@ -457,6 +465,24 @@ mps_status mps_krylov_expm(mps_handle h, mps_stream stream, int32_t dtype, const
 
 mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* chain, double dt, int32_t n_steps,
                           double eps_local, int32_t n_max, double tol, double* disc_dev, int32_t* krylov_max_dev) {
+  return tdvp_impl(h, stream, chain, dt, n_steps, eps_local, n_max, tol, disc_dev, krylov_max_dev, nullptr);
+}
+
+mps_status mps_tdvp2_step_u1(mps_handle h, mps_stream stream, const mps_oc_chain* chain,
+                             const mps_u1_chain* charges, double dt, int32_t n_steps, double eps_local,
+                             int32_t n_max, double tol, double* disc_dev, int32_t* krylov_max_dev) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!charges || !charges->qbond) return mps_fail(h, MPS_ERR_INVALID, "null charges");
+  if (charges->modulus < 0 || charges->modulus == 1)
+    return mps_fail(h, MPS_ERR_INVALID, "modulus must be 0 (U(1)) or at least 2 (Z_n)");
+  return tdvp_impl(h, stream, chain, dt, n_steps, eps_local, n_max, tol, disc_dev, krylov_max_dev, charges);
+}
+
+}  // extern "C"
+
+mps_status tdvp_impl(mps_handle h, mps_stream stream, const mps_oc_chain* chain, double dt, int32_t n_steps,
+                     double eps_local, int32_t n_max, double tol, double* disc_dev, int32_t* krylov_max_dev,
+                     const mps_u1_chain* u1) {
   if (!h) return MPS_ERR_INVALID;
   if (!chain) return mps_fail(h, MPS_ERR_INVALID, "null chain");
   const mps_oc_chain& c = *chain;
@@ -472,11 +498,26 @@ mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* c
   const size_t es = esize(c128);
   const int L = c.L, d = c.d, w = c.w, cm = c.chi_max;
   TdvpWs t;
-  mps_status st = tdvp_workspace(h, c128, cm, d, w, L, n_max, t);
+  if (u1 && d > 5) return mps_fail(h, MPS_ERR_SHAPE, "charge-carrying chains need d <= 5");
+  mps_status st = tdvp_workspace(h, c128, cm, d, w, L, n_max, t, u1 != nullptr);
   if (st != MPS_OK) return st;
   std::vector<int32_t> chi(L + 1);
   MPS_TRY_HIP(h, hipMemcpyAsync(chi.data(), c.chi, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  // charge-carrying chains: the bond charges on the host for the sweep
+  std::vector<int32_t> qb(u1 ? (size_t)(L + 1) * cm : 0), rq, cq, qk(cm);
+  if (u1) MPS_TRY_HIP(h, hipMemcpyAsync(qb.data(), u1->qbond, qb.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  const int32_t md = u1 ? u1->modulus : 0;
+  auto red = [md](int64_t v) -> int32_t { return md == 0 ? (int32_t)v : (int32_t)(((v % md) + md) % md); };
+  // row (a, s1) and column (s2, g) charges of theta at bond b (chl x d, d x chr)
+  auto charges_of = [&](int b, int chl, int chr) {
+    rq.resize((size_t)chl * d);
+    cq.resize((size_t)d * chr);
+    for (int a = 0; a < chl; ++a)
+      for (int s1 = 0; s1 < d; ++s1) rq[a * d + s1] = red((int64_t)qb[(size_t)b * cm + a] + u1->qsite[s1]);
+    for (int s2 = 0; s2 < d; ++s2)
+      for (int g = 0; g < chr; ++g) cq[s2 * chr + g] = red((int64_t)qb[(size_t)(b + 2) * cm + g] - u1->qsite[s2]);
+  };
   for (int i = 0; i <= L; ++i)
     if (chi[i] < 1 || chi[i] > cm) return mps_fail(h, MPS_ERR_SHAPE, "chi entries must be in [1, chi_max]");
   const size_t site = (size_t)cm * d * cm * es;
@@ -543,10 +584,19 @@ mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* c
       MPS_TRY_HIP(h, launch_transpose_c128(s, t.th128, t.Xj, m, n));
       int k;
       double w_disc;
-      if ((st = svd_select(h, s, t, n, m, cm, eps_local, &k, &w_disc)) != MPS_OK) return st;
+      if (u1) {
+        // the rows of theta^T carry the column charges; A_b = U_k as [chl*d][k]
+        charges_of(b, chl, chr);
+        if ((st = u1_split_one(h, s, t.Xj, n, m, cq.data(), rq.data(), cm, eps_local, t.u1r, d * cm, cm, t.sel, Mp(b),
+                               1, c128, &k, &w_disc, qk.data())) != MPS_OK)
+          return st;
+        std::copy(qk.begin(), qk.begin() + k, qb.begin() + (size_t)(b + 1) * cm);
+      } else {
+        if ((st = svd_select(h, s, t, n, m, cm, eps_local, &k, &w_disc)) != MPS_OK) return st;
+        // A_b = U_k, column-major rows -> [chl*d][k]
+        MPS_TRY_HIP(h, launch_write_rows(s, t.mat, t.perm, t.s2, t.sel, Mp(b), m, 1, c128));
+      }
       disc[b] += w_disc;
-      // A_b = U_k, column-major rows -> [chl*d][k]
-      MPS_TRY_HIP(h, launch_write_rows(s, t.mat, t.perm, t.s2, t.sel, Mp(b), m, 1, c128));
       // C = U_k^dag theta -> M_{b+1} [k][d*chr]
       if (!c128) MPS_TRY_HIP(h, launch_convert(s, t.th128, t.thdt, (long long)m * n, true));
       SGemm g;
@@ -570,10 +620,19 @@ mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* c
       MPS_TRY_HIP(h, hipMemcpyAsync(t.Xj, t.th128, (size_t)m * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
       int k;
       double w_disc;
-      if ((st = svd_select(h, s, t, m, n, cm, eps_local, &k, &w_disc)) != MPS_OK) return st;
+      if (u1) {
+        // B_{b+1} = V_k^dag, row-major [k][d*chr], zero off each vector's block
+        charges_of(b, chl, chr);
+        if ((st = u1_split_one(h, s, t.Xj, m, n, rq.data(), cq.data(), cm, eps_local, t.u1r, d * cm, cm, t.sel,
+                               Mp(b + 1), 0, c128, &k, &w_disc, qk.data())) != MPS_OK)
+          return st;
+        std::copy(qk.begin(), qk.begin() + k, qb.begin() + (size_t)(b + 1) * cm);
+      } else {
+        if ((st = svd_select(h, s, t, m, n, cm, eps_local, &k, &w_disc)) != MPS_OK) return st;
+        // B_{b+1} = V_k^dag, row-major [k][d*chr]
+        MPS_TRY_HIP(h, launch_write_rows(s, t.mat, t.perm, t.s2, t.sel, Mp(b + 1), n, 0, c128));
+      }
       disc[b] += w_disc;
-      // B_{b+1} = V_k^dag, row-major [k][d*chr]
-      MPS_TRY_HIP(h, launch_write_rows(s, t.mat, t.perm, t.s2, t.sel, Mp(b + 1), n, 0, c128));
       // C = theta V_k -> M_b [chl*d][k]
       if (!c128) MPS_TRY_HIP(h, launch_convert(s, t.th128, t.thdt, (long long)m * n, true));
       SGemm g;
@@ -591,6 +650,7 @@ mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* c
     }
   }
   MPS_TRY_HIP(h, hipMemcpyAsync(c.chi, chi.data(), (L + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (u1) MPS_TRY_HIP(h, hipMemcpyAsync(u1->qbond, qb.data(), qb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   if (disc_dev) {
     std::vector<double> old(L - 1);
     MPS_TRY_HIP(h, hipMemcpyAsync(old.data(), disc_dev, (L - 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -602,5 +662,3 @@ mps_status mps_tdvp2_step(mps_handle h, mps_stream stream, const mps_oc_chain* c
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
   return MPS_OK;
 }
-
-}  // extern "C"

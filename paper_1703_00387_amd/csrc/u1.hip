@@ -275,6 +275,41 @@ __global__ __launch_bounds__(256) void u1_wb_kernel(const BondItem* __restrict__
   }
 }
 
+// One matrix, grid (kept-count cap): kept vector j of the matrix's blocks,
+// divided by s_j, zero off its block's columns, written as row j of dst
+// ([k][len]) or as column j ([len][k], col_major); its charge to q_out[j].
+template <class T>
+__global__ __launch_bounds__(256) void u1_rows_kernel(const JacMat* __restrict__ mats,
+                                                      const U1Block* __restrict__ blk, int nblk,
+                                                      const int32_t* __restrict__ cols,
+                                                      const int32_t* __restrict__ pe, const double* __restrict__ s2o,
+                                                      const SelOut* __restrict__ sel, T* dst, int len, int col_major,
+                                                      int32_t* q_out) {
+  const int k = sel->k, j = blockIdx.x;
+  if (j >= k) return;
+  const int e = pe[j];
+  const int b = u1_block_of(blk, nblk, e);
+  const U1Block B = blk[b];
+  const JacMat M = mats[b];
+  const int r = e - B.row_off;
+  const double sv = sqrt(s2o[j]);
+  const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
+  T z;
+  z.x = 0;
+  z.y = 0;
+  for (int c = threadIdx.x; c < len; c += 256) dst[col_major ? (size_t)c * k + j : (size_t)j * len + c] = z;
+  __syncthreads();
+  for (int c = threadIdx.x; c < B.n; c += 256) {
+    const double2 x = M.X[(size_t)r * M.ld + c];
+    T v;
+    v.x = x.x * inv;
+    v.y = x.y * inv;
+    const int col = cols[B.col_off + c];
+    dst[col_major ? (size_t)col * k + j : (size_t)j * len + col] = v;
+  }
+  if (threadIdx.x == 0) q_out[j] = B.q;
+}
+
 // Workspace of u1_layer for up to n_cap items of at most m_cap rows and columns.
 struct U1Plan {
   size_t oItems, oRb, oX, oMats, oBlk, oRg, oRows, oCols, oRm, oNrm, oPe, oS2, off;
@@ -282,7 +317,7 @@ struct U1Plan {
     WsPlan p;
     const size_t nm = (size_t)n_cap * m_cap;
     oItems = p.take<U1Item>(n_cap);
-    oRb = p.take<int32_t>((size_t)n_cap * (2 + 2 * chi_cap));
+    oRb = p.take<int32_t>((size_t)n_cap * (2 + 2 * chi_cap) + 16);
     oX = p.take<double2>(nm * m_cap);
     oMats = p.take<JacMat>(nm);
     oBlk = p.take<U1Block>(nm);
@@ -461,6 +496,95 @@ mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const 
     u1_wb_kernel<float2><<<dim3(k_cap, n), 256, 0, s>>>(it_dev, dUi, mats, blk, rgd, dcols, pe, s2o, sel);
   MPS_TRY_HIP(h, hipGetLastError());
   MPS_TRY_HIP(h, hipStreamSynchronize(s));  // the host vectors go out of scope at return
+  return MPS_OK;
+}
+
+mps_status u1_split_one(mps_handle h, hipStream_t s, const double2* X, int m, int n, const int32_t* row_q,
+                        const int32_t* col_q, int kmax, double eps, char* region, int m_cap, int chi_cap,
+                        SelOut* sel, void* dst, int col_major, bool c128, int* k_out, double* disc_out,
+                        int32_t* q_out) {
+  if (m < 1 || n < 1 || m > m_cap || n > m_cap) return mps_fail(h, MPS_ERR_CAPACITY, "split larger than its workspace");
+  const U1Plan P(1, m_cap, chi_cap);
+  region = (char*)(((uintptr_t)region + 255) & ~(uintptr_t)255);
+  char* const ws = region;
+  std::map<int32_t, std::pair<std::vector<int32_t>, std::vector<int32_t>>> sec;
+  for (int r = 0; r < m; ++r) sec[row_q[r]].first.push_back(r);
+  for (int c = 0; c < n; ++c) sec[col_q[c]].second.push_back(c);
+  std::vector<U1Block> blocks;
+  std::vector<int32_t> rows, cols;
+  int64_t xw = 0, max_mn = 1;
+  int max_m = 1;
+  for (auto& kv : sec) {
+    const auto& rr = kv.second.first;
+    const auto& cc = kv.second.second;
+    if (rr.empty() || cc.empty()) continue;
+    U1Block b;
+    b.src = X;
+    b.ld = n;
+    b.q = kv.first;
+    b.m = (int32_t)rr.size();
+    b.n = (int32_t)cc.size();
+    b.row_off = (int32_t)rows.size();
+    b.col_off = (int32_t)cols.size();
+    b.item = 0;
+    b.x_off = xw;
+    xw += (int64_t)b.m * b.n;
+    max_m = std::max(max_m, b.m);
+    max_mn = std::max<int64_t>(max_mn, (int64_t)b.m * b.n);
+    rows.insert(rows.end(), rr.begin(), rr.end());
+    cols.insert(cols.end(), cc.begin(), cc.end());
+    blocks.push_back(b);
+  }
+  const int nblk = (int)blocks.size();
+  if (nblk == 0) return mps_fail(h, MPS_ERR_SHAPE, "no charge is shared across a bond of a charge-carrying chain");
+  const int R = (int)rows.size();
+  const U1Range rg{0, nblk, 0, R, std::min(kmax, R), n};
+  std::vector<JacMat> hm(nblk);
+  for (int i = 0; i < nblk; ++i) {
+    std::memset(&hm[i], 0, sizeof(JacMat));
+    hm[i].X = (double2*)(ws + P.oX) + blocks[i].x_off;
+    hm[i].rowmap = (int32_t*)(ws + P.oRm) + blocks[i].row_off;
+    hm[i].nrm2 = (double*)(ws + P.oNrm) + blocks[i].row_off;
+    hm[i].m = blocks[i].m;
+    hm[i].n = blocks[i].n;
+    hm[i].ld = blocks[i].n;
+    hm[i].nb = jac_nb(blocks[i].m);
+    hm[i].kmax = blocks[i].m;
+  }
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oMats, hm.data(), nblk * sizeof(JacMat), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oBlk, blocks.data(), nblk * sizeof(U1Block), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oRg, &rg, sizeof(U1Range), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oRows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oCols, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  JacMat* mats = (JacMat*)(ws + P.oMats);
+  const U1Block* blk = (const U1Block*)(ws + P.oBlk);
+  const int gx = (int)std::min<int64_t>((max_mn + 255) / 256, 1024);
+  u1_gather_kernel<<<dim3(gx, nblk), 256, 0, s>>>(blk, (const int32_t*)(ws + P.oRows), (const int32_t*)(ws + P.oCols),
+                                                 (double2*)(ws + P.oX));
+  MPS_TRY_HIP(h, hipGetLastError());
+  MPS_TRY_HIP(h, launch_jac_prep_plain(s, mats, nblk, h->status_dev));
+  mps_status st = run_jacobi(h, s, mats, nblk, jac_nb(max_m), max_m, (int32_t*)(ws + P.oRb), false);
+  if (st != MPS_OK) return st;
+  int32_t* pe = (int32_t*)(ws + P.oPe);
+  double* s2o = (double*)(ws + P.oS2);
+  u1_select_kernel<<<1, 256, (size_t)R * (sizeof(double) + sizeof(int)), s>>>(
+      mats, blk, (const U1Range*)(ws + P.oRg), count_rule_eps(h, eps), pe, s2o, sel);
+  MPS_TRY_HIP(h, hipGetLastError());
+  int32_t* qd = (int32_t*)(ws + P.oRb) + 8;   // after the Jacobi's counters
+  const int32_t* dcols = (const int32_t*)(ws + P.oCols);
+  if (c128)
+    u1_rows_kernel<double2><<<rg.kmax, 256, 0, s>>>(mats, blk, nblk, dcols, pe, s2o, sel, (double2*)dst, n,
+                                                    col_major, qd);
+  else
+    u1_rows_kernel<float2><<<rg.kmax, 256, 0, s>>>(mats, blk, nblk, dcols, pe, s2o, sel, (float2*)dst, n,
+                                                   col_major, qd);
+  MPS_TRY_HIP(h, hipGetLastError());
+  SelOut so;
+  MPS_TRY_HIP(h, hipMemcpyAsync(&so, sel, sizeof(so), hipMemcpyDeviceToHost, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(q_out, qd, rg.kmax * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));  // the host vectors go out of scope at return
+  *k_out = so.k;
+  *disc_out = so.disc;
   return MPS_OK;
 }
 

@@ -292,3 +292,34 @@ def test_time_dependent_steps_on_charge_blocks(H):
     code, word = H.device_status()
     assert code == 0, word
     _check(H, ch, q, ref, qref, spec)
+
+
+@pytest.mark.parametrize("spec,qsite,steps", [(W.xxz_chain(8, 6, 1.0, 0.5), [1, 0], 10),
+                                              (W.bh_chain(6, 2, 9, 1.0, 3.0), [0, 1, 2], 10)], ids=["xxz", "bh"])
+def test_tdvp_on_charge_blocks(H, spec, qsite, steps):
+    """mps_tdvp2_step_u1 (every two-site split on the charge blocks) against
+    the oracle's TDVP with the blockwise split: the state, the bond
+    dimensions and the multiset of charges at every bond."""
+    from oracle import models as om, tdvp as ot, u1
+    from paper_1703_00387_amd import api, models as pm
+    v = W.initial_vectors(spec)
+    psi = ot.product_oc(v)
+    qref = u1.product_charges(v, qsite)
+    Ws = om.mpo(spec)
+    for _ in range(steps):
+        ot.tdvp2_step(psi, Ws, 0.05, spec.chi_max, 1e-10, 20, 1e-12, charges=(qref, qsite, 0))
+    ch = api.OCChain.product(v, spec.chi_max, pm.mpo(spec))
+    q = api.Charges.product(v, qsite, spec.chi_max)
+    api.tdvp2_step(H, ch, 0.05, steps, 1e-10, 20, 1e-12, charges=q)
+    code, word = H.device_status()
+    assert code == 0, word
+    chi = ch.chi.cpu().numpy()
+    assert list(chi) == [T.shape[0] for T in psi.M] + [1]
+    qb = q.qbond.cpu().numpy()
+    for b in range(spec.L + 1):
+        assert sorted(qb[b, :chi[b]].tolist()) == sorted(np.asarray(qref[b]).tolist()), b
+    vg, vo = ch.to_vector(), psi.to_vector()
+    ov = abs(np.vdot(vg, vo)) / (np.linalg.norm(vg) * np.linalg.norm(vo))
+    print(f"L={spec.L} chi={chi.max()} 1-overlap={1 - ov:.1e}")
+    assert 1 - ov <= 1e-9
+    assert abs(np.linalg.norm(vg) - np.linalg.norm(vo)) <= 1e-9
