@@ -511,6 +511,23 @@ def bench_tdvp(args):
     api.tdvp2_step(h, ch, wl.dt, args.steps, wl.eps_local, wl.n_krylov, wl.krylov_tol)
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t1) / args.steps
+    # the same run on a charge-carrying chain (particle number, every split on
+    # the charge blocks of its bond)
+    v0 = W.initial_vectors(spec)
+    cu = api.OCChain.product(v0, chi_run, models.mpo(spec), dtype=args.dtype)
+    qu = api.Charges.product(v0, list(range(d)), chi_run)
+    t0 = time.time()
+    for i in range(args.warmup):
+        api.tdvp2_step(h, cu, wl.dt, 1, wl.eps_local, wl.n_krylov, wl.krylov_tol, charges=qu)
+        torch.cuda.synchronize()
+        if (i + 1) % 10 == 0 or i + 1 == args.warmup:
+            print(f"[bench] U(1) warmup {i + 1}/{args.warmup}, chi_max now {int(cu.chi.max())}, "
+                  f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.tdvp2_step(h, cu, wl.dt, args.steps, wl.eps_local, wl.n_krylov, wl.krylov_tol, charges=qu)
+    torch.cuda.synchronize()
+    t_step_u1 = (time.perf_counter() - t1) / args.steps
     code, word = h.device_status()
     L = spec.L
     upd = 2 * (L - 1)
@@ -524,6 +541,8 @@ def bench_tdvp(args):
                                "chi_max=64 for the steps; environment update and one-site H_eff at chi=512",
                    "two_site_updates_per_step": upd, "one_site_backward_steps_per_step": 2 * (L - 2),
                    "chi_max_now": int(ch.chi.max())},
+        "u1_updates_per_s": round(upd / t_step_u1, 3),
+        "u1_chi_max_now": int(cu.chi.max()),
         "env_update_chi512": {"ms_left": round(t_envl * 1e3, 3), "ms_right": round(t_envr * 1e3, 3),
                               "flops": f_env, "tflops_left": round(f_env / t_envl / 1e12, 3),
                               "frac_left": round(f_env / t_envl / 1e12 / peak, 4)},
