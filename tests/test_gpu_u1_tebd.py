@@ -323,3 +323,32 @@ def test_tdvp_on_charge_blocks(H, spec, qsite, steps):
     print(f"L={spec.L} chi={chi.max()} 1-overlap={1 - ov:.1e}")
     assert 1 - ov <= 1e-9
     assert abs(np.linalg.norm(vg) - np.linalg.norm(vo)) <= 1e-9
+
+
+def test_tdvp_on_charge_blocks_complex64(H):
+    """A complex64 chain through mps_tdvp2_step_u1 (the blockwise split writes
+    U_k and V^dag_k in single precision): the state within single-precision
+    accuracy of the oracle's, the bond charges identical."""
+    from oracle import models as om, tdvp as ot, u1
+    from paper_1703_00387_amd import api, models as pm
+    spec = W.xxz_chain(8, 6, 1.0, 0.5)
+    v = W.initial_vectors(spec)
+    psi = ot.product_oc(v)
+    qref = u1.product_charges(v, [1, 0])
+    Ws = om.mpo(spec)
+    for _ in range(6):
+        ot.tdvp2_step(psi, Ws, 0.05, spec.chi_max, 1e-8, 20, 1e-10, charges=(qref, [1, 0], 0))
+    ch = api.OCChain.product(v, spec.chi_max, pm.mpo(spec), dtype="c64")
+    q = api.Charges.product(v, [1, 0], spec.chi_max)
+    api.tdvp2_step(H, ch, 0.05, 6, 1e-8, 20, 1e-10, charges=q)
+    code, word = H.device_status()
+    assert code == 0, word
+    chi = ch.chi.cpu().numpy()
+    assert list(chi) == [T.shape[0] for T in psi.M] + [1]
+    qb = q.qbond.cpu().numpy()
+    for b in range(spec.L + 1):
+        assert sorted(qb[b, :chi[b]].tolist()) == sorted(np.asarray(qref[b]).tolist()), b
+    vg, vo = ch.to_vector().astype(np.complex128), psi.to_vector()
+    ov = abs(np.vdot(vg, vo)) / (np.linalg.norm(vg) * np.linalg.norm(vo))
+    print(f"c64 1-overlap={1 - ov:.1e}")
+    assert 1 - ov <= 1e-6
