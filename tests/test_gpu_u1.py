@@ -91,3 +91,57 @@ def test_no_shared_charge_is_an_error(H):
     with pytest.raises(_lib.MPSError) as e:
         H.truncate_u1(T, [0, 0, 1, 1], [2, 2, 3, 3], 4, 1e-12)
     assert e.value.code == _lib.MPS_ERR_SHAPE
+
+
+def test_u1_truncate_at_the_size_limit_with_known_spectrum(H):
+    """4096 x 4096 (the boundary's limit) with four charges interleaved over
+    rows and columns (row r and column c carry r mod 4 and c mod 4): block q is
+    R_q diag(s_q) R'_q with Householder reflectors, so the singular values are
+    exactly the union of the s_q.  Kept values, their charges, the discarded
+    weight, the block structure of U and Vh and the reconstruction error
+    against the exact spectrum."""
+    n, nq = 4096, 4
+    nb = n // nq
+    dev = "cuda"
+    gen = np.random.default_rng(170300387 + 97)
+    rates = [0.004, 0.005, 0.006, 0.007]
+    s_blocks = [torch.exp(-rates[q] * torch.arange(nb, dtype=torch.float64, device=dev)) * (1.0 + 0.1 * q)
+                for q in range(nq)]
+    tot = torch.sqrt(sum((sq ** 2).sum() for sq in s_blocks))
+    s_blocks = [sq / tot for sq in s_blocks]
+
+    def refl(M, left):
+        v = torch.from_numpy(gen.normal(size=nb) + 1j * gen.normal(size=nb)).to(dev)
+        v = v / torch.linalg.vector_norm(v)
+        if left:
+            return M - 2.0 * torch.outer(v, v.conj() @ M)
+        return M - 2.0 * torch.outer(M @ v, v.conj())
+
+    A = torch.zeros((n, n), dtype=torch.complex128, device=dev)
+    for q in range(nq):
+        Bq = refl(refl(torch.diag(s_blocks[q]).to(torch.complex128), True), False)
+        A[q::nq, q::nq] = Bq
+    row_q = np.arange(n) % nq
+    col_q = np.arange(n) % nq
+    H.device_status()
+    chi, eps = 256, 1e-12
+    U, S, Vh, qo, k, disc, norm2 = H.truncate_u1(A, row_q, col_q, chi, eps)
+    code, word = H.device_status()
+    assert code == 0, word
+    allv = np.concatenate([sq.cpu().numpy() for sq in s_blocks])
+    owner = np.repeat(np.arange(nq), nb)
+    order = np.argsort(-allv, kind="stable")
+    s2 = allv[order] ** 2
+    tail = np.cumsum(s2[::-1])[::-1]
+    k_ref = min(chi, next(kk for kk in range(1, n + 1) if kk == n or tail[kk] <= eps * s2.sum()))
+    print(f"4096 x 4096 U(1): k={k} (ref {k_ref}) disc={disc:.3e}")
+    assert k == k_ref
+    assert np.abs(S.cpu().numpy() ** 2 - s2[:k]).max() <= 1e-13
+    assert np.array_equal(qo.cpu().numpy(), owner[order][:k])
+    assert abs(disc - s2[k:].sum()) <= 1e-12 + 1e-6 * s2[k:].sum()
+    Uc, Vc, qn = U.cpu().numpy(), Vh.cpu().numpy(), qo.cpu().numpy()
+    assert np.all(Uc[row_q[:, None] != qn[None, :]] == 0)
+    assert np.all(Vc[qn[:, None] != col_q[None, :]] == 0)
+    R = (U * S.to(torch.complex128)) @ Vh
+    err2 = float(torch.linalg.vector_norm(A - R) ** 2)
+    assert abs(err2 - s2[k:].sum()) <= 1e-12
