@@ -453,6 +453,7 @@ mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const 
     k_cap = std::max(k_cap, rg.kmax);
   }
   const int nblk = (int)blocks.size();
+  if (nblk > 65535) return mps_fail(h, MPS_ERR_CAPACITY, "more than 65535 charge blocks in one layer");
   if ((int64_t)xw > (int64_t)n_cap * m_cap * m_cap || (int64_t)nblk > (int64_t)n_cap * m_cap ||
       (int64_t)rows.size() > (int64_t)n_cap * m_cap || (int64_t)cols.size() > (int64_t)n_cap * m_cap)
     return mps_fail(h, MPS_ERR_CAPACITY, "charge blocks exceed the layer workspace");
