@@ -276,7 +276,8 @@ typedef struct {
  *   charges : HOST array of n_chains descriptors, one per chain
  * Errors: as mps_tebd_step; MPS_ERR_INVALID for MPS_FLAG_GRAPH, a null
  * qbond or a modulus < 0 or == 1; MPS_ERR_SHAPE when no charge is shared
- * across a bond.
+ * across a bond; MPS_ERR_CAPACITY when the bonds of one layer have more than
+ * 65535 charge blocks together.
  */
 mps_status mps_tebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
                             const mps_u1_chain* charges, int32_t n_chains, int32_t order, double dt,
