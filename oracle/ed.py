@@ -14,10 +14,10 @@ circuit, reduced density matrices and the paper's error measures.
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 import scipy.sparse.linalg
 
 from . import models
-from .mps import GateCache, step_layers
 
 
 def product_vector(vectors: np.ndarray) -> np.ndarray:
@@ -33,19 +33,59 @@ def apply_two_site(psi: np.ndarray, G: np.ndarray, b: int, L: int, d: int) -> np
     return t.reshape(-1)
 
 
+def _suzuki_p() -> float:
+    """Weight p of the five-stage fourth-order fractal U2(p)U2(p)U2(1-4p)U2(p)U2(p):
+    the third-order error cancels when 4 p^3 + (1 - 4p)^3 = 0.  Taken here as
+    the real root of that cubic, so the circuit does not share the closed
+    form the MPS schedule uses."""
+    roots = np.roots([4.0 - 64.0, 48.0, -12.0, 1.0])   # 4p^3 + (1-4p)^3 expanded
+    real = roots[np.abs(roots.imag) < 1e-12].real
+    return float(real[0])
+
+
+def circuit_schedule(method: str, L: int, dt: float):
+    """The ordered list of (bond, tau) exponentials of one time step, written
+    from the definitions independently of the MPS code: Strang splitting with
+    the bonds b = 0, 2, 4, ... (the paper's odd bonds, 1-based) applied first
+    and last with tau/2 and the others with tau in between; the fourth-order
+    fractal of five Strang steps; the Sornborger-Stewart sweep (every bond
+    left to right, then right to left, each with dt/2; Eq. sornborger2)."""
+    def strang(tau):
+        first = [(b, 0.5 * tau) for b in range(L - 1) if b % 2 == 0]
+        middle = [(b, tau) for b in range(L - 1) if b % 2 == 1]
+        return first + middle + list(first)
+    if method == "tebd2":
+        return strang(dt)
+    if method == "tebd4":
+        p = _suzuki_p()
+        out = []
+        for w in (p, p, 1.0 - 4.0 * p, p, p):
+            out += strang(w * dt)
+        return out
+    if method == "sweep":
+        right = [(b, 0.5 * dt) for b in range(L - 1)]
+        return right + right[::-1]
+    raise ValueError(method)
+
+
 def trotter_circuit(spec, method: str, dt: float, n_steps: int, psi0=None, observe=None):
-    """Apply the TEBD gate sequence of ``method`` to the state vector."""
+    """Apply the TEBD gate sequence of ``method`` to the state vector.  The
+    two-site propagators are matrix exponentials (scipy's Pade expm), not the
+    eigendecomposition the MPS code uses, and the schedule is
+    ``circuit_schedule``: nothing of the MPS update is shared."""
     from workloads import initial_vectors
     L, d = spec.L, spec.d
     psi = product_vector(initial_vectors(spec)) if psi0 is None else psi0.copy()
-    gates = GateCache(models.bond_hamiltonians(spec))
-    layers = step_layers(method, L, dt)
+    hs = models.bond_hamiltonians(spec)
+    cache = {}
     if observe:
         observe(psi, 0)
     for n in range(1, n_steps + 1):
-        for bonds, tau in layers:
-            for b in bonds:
-                psi = apply_two_site(psi, gates(b, tau), b, L, d)
+        for b, tau in circuit_schedule(method, L, dt):
+            key = (b, tau)
+            if key not in cache:
+                cache[key] = scipy.linalg.expm(-1j * tau * hs[b])
+            psi = apply_two_site(psi, cache[key], b, L, d)
         if observe:
             observe(psi, n)
     return psi

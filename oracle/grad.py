@@ -25,6 +25,7 @@ G_b(tau) = exp(-i tau J_b h0_b) and dG/dJ_b = -i tau h0_b G_b.
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 import torch
 
 from . import models, mps as omps, ed
@@ -161,17 +162,14 @@ def ed_gradient(spec, dt, n_steps, method="tebd2"):
     from workloads import initial_vectors
     L, d = spec.L, spec.d
     psi = ed.product_vector(initial_vectors(spec))
-    layers = omps.step_layers(method, L, dt)
-    seq = []
-    for _ in range(n_steps):
-        for bonds, tau in layers:
-            for b in bonds:
-                seq.append((b, tau))
+    # the circuit's own schedule and Pade exponentials: nothing shared with
+    # the MPS run whose gradient this checks
+    seq = ed.circuit_schedule(method, L, dt) * n_steps
     h0 = [models.xxz_unit_bond(spec, b) for b in range(L - 1)]
     G = {}
     for b, tau in seq:
         if (b, tau) not in G:
-            G[(b, tau)] = omps.gate(spec.J_b[b] * h0[b], tau)
+            G[(b, tau)] = scipy.linalg.expm(-1j * tau * spec.J_b[b] * h0[b])
     for b, tau in seq:
         psi = ed.apply_two_site(psi, G[(b, tau)], b, L, d)
     site = L // 2 - 1

@@ -102,7 +102,8 @@ def test_xx_free_fermions_L64(method):
     psi = mps.tebd_run(spec, method, dt, n, 1e-14,
                        observe=lambda p, k: out.append((mps.local_expect(p, 0.5 * models.SZ),
                                                         float(np.sum(np.sqrt(p.disc))))))
-    Cs = ff.evolve_trotter(ff.neel_correlation(L), spec.J_b, 1.0, mps.step_layers(method, L, dt), n)
+    sched = [([b], tau) for b, tau in ed.circuit_schedule(method, L, dt)]
+    Cs = ff.evolve_trotter(ff.neel_correlation(L), spec.J_b, 1.0, sched, n)
     for k, (sz, bound) in enumerate(out):
         err = np.abs(sz - ff.sz_from_C(Cs[k])).max()
         assert err <= max(1e-12, bound), (k, err, bound)
