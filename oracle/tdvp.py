@@ -53,17 +53,20 @@ def update_right(Renv, B, W):
     return np.einsum("xpa,bypq,ayc,zqc->xbz", B.conj(), W, Renv, B)
 
 
+# Each stage below contracts two tensors over the indices its subscripts name;
+# optimize=True only lets NumPy evaluate that pairwise sum through BLAS
+# (tensordot) instead of its element loop, the same contraction.
 def heff2_apply(Lenv, W1, W2, Renv, x):
-    X1 = np.einsum("xba,astc->xbstc", Lenv, x)
-    X2 = np.einsum("bgus,xbstc->xgutc", W1, X1)
-    X3 = np.einsum("gevt,xgutc->xuevc", W2, X2)
-    return np.einsum("xuevc,yec->xuvy", X3, Renv)
+    X1 = np.einsum("xba,astc->xbstc", Lenv, x, optimize=True)
+    X2 = np.einsum("bgus,xbstc->xgutc", W1, X1, optimize=True)
+    X3 = np.einsum("gevt,xgutc->xuevc", W2, X2, optimize=True)
+    return np.einsum("xuevc,yec->xuvy", X3, Renv, optimize=True)
 
 
 def heff1_apply(Lenv, W, Renv, x):
-    X1 = np.einsum("xba,asc->xbsc", Lenv, x)
-    X2 = np.einsum("bgus,xbsc->xguc", W, X1)
-    return np.einsum("xguc,ygc->xuy", X2, Renv)
+    X1 = np.einsum("xba,asc->xbsc", Lenv, x, optimize=True)
+    X2 = np.einsum("bgus,xbsc->xguc", W, X1, optimize=True)
+    return np.einsum("xguc,ygc->xuy", X2, Renv, optimize=True)
 
 
 def heff2_dense(Lenv, W1, W2, Renv) -> np.ndarray:
