@@ -96,7 +96,11 @@ mps_status mps_set_option(mps_handle h, int option, double value);
  * 3 = right write-back, 4 = left write-back GEMM, 5 = Jacobi preparation,
  * 6 = propagators, 7 = Krylov-TEBD propagators (identity theta build,
  * reduced matrix, local Lanczos).  total_ms = summed event durations, launches = count,
- * work = useful flops counted on the device (kernels 0, 1 and 4; else 0).
+ * work = flops counted on the device: for kernels 0 and 4 the products'
+ * useful flops, for kernel 1 the Jacobi's own Gram and rotation flops, for
+ * kernel 5 the algorithmic work of the batched TEBD splits prepared
+ * (88 m n min(m, n) per m x n complex SVD, a bidiagonalisation SVD's count);
+ * else 0.
  * Synchronises `stream`.  reset != 0 clears all classes afterwards. */
 mps_status mps_kernel_stats(mps_handle h, mps_stream stream, int32_t kernel, double* total_ms,
                             int64_t* launches, uint64_t* work, int32_t reset);

@@ -283,7 +283,7 @@ mps_status mps_kernel_stats(mps_handle h, mps_stream stream, int32_t kernel, dou
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
   unsigned long long w[MPS_NSTATS];
   MPS_TRY_HIP(h, hipMemcpy(w, h->stats_dev, sizeof(w), hipMemcpyDeviceToHost));
-  static const int work_slot[MPS_NKERNELS] = {0, 1, -1, -1, 3, -1, -1, -1};
+  static const int work_slot[MPS_NKERNELS] = {0, 1, -1, -1, 3, 5, -1, -1};
   if (total_ms) *total_ms = h->k_ms[kernel];
   if (launches) *launches = h->k_launches[kernel];
   if (work) *work = work_slot[kernel] >= 0 ? w[work_slot[kernel]] : 0;
@@ -700,7 +700,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       } else {
       if (prof) prof_begin(h, s, MPS_K_PREP);
       MPS_TRY_HIP(h, launch_jac_prep_bonds(s, it, mats, n, kJacBlock, (int32_t*)(ws + oRow), (double*)(ws + oNrm), m_cap,
-                                           h->status_dev));
+                                           h->status_dev, stats));
       if (prof) prof_end(h, s, MPS_K_PREP);
       mps_status r = run_jacobi(h, s, mats, n, nb_cap, m_cap, unconv, fixed);
       if (r != MPS_OK) return r;

@@ -235,7 +235,8 @@ hipError_t launch_ktebd_rho(hipStream_t s, const BondItem* items, const KryJob* 
 hipError_t launch_ktebd_krylov(hipStream_t s, const KryJob* jobs, int n_items, int d, int nblk, int n_max, double tol,
                                double tau, bool c128, uint32_t* status);
 hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
-                                 int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status);
+                                 int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status,
+                                 unsigned long long* stats = nullptr);
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status);
 // Column split of a Jacobi round (see jac_round_kernel): S workgroups per
 // panel pair; part holds n_mats * pairs * S partial Grams of 64 x 64.

@@ -63,8 +63,12 @@ __device__ double block_sum(double v, double* red) {
 // reaches a round, with non-finite input, keeps them for the selection).
 constexpr int kRowSlices = 16;
 
+// stats (optional) slot 5 accumulates the algorithmic work of the splits:
+// 88 m n min(m, n) real flops per m x n complex SVD, the count of a
+// bidiagonalisation SVD that the Jacobi's own Gram and rotation flops exceed.
 __global__ void jac_desc_bonds_kernel(const BondItem* __restrict__ items, JacMat* __restrict__ mats, int n_items,
-                                      int bs, int32_t* rowmap_ws, double* nrm_ws, int m_cap) {
+                                      int bs, int32_t* rowmap_ws, double* nrm_ws, int m_cap,
+                                      unsigned long long* stats) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_items) return;
   const BondItem it = items[i];
@@ -86,6 +90,10 @@ __global__ void jac_desc_bonds_kernel(const BondItem* __restrict__ items, JacMat
   M.fro2 = 0.0;
   M.conv = 0;
   mats[i] = M;
+  if (stats) {
+    const unsigned long long mm = M.m, nn = M.n;
+    atomicAdd(&stats[5], 88ull * mm * nn * (mm < nn ? mm : nn));
+  }
 }
 
 // grid (n_mats, kRowSlices), 256 threads: wave w of slice s takes the rows
@@ -815,9 +823,11 @@ __global__ __launch_bounds__(256) void trunc_u_kernel(const double2* theta, cons
 
 // ---------------------------------------------------------------------------
 hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, int bs,
-                                 int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status) {
+                                 int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status,
+                                 unsigned long long* stats) {
   if (n_items <= 0) return hipSuccess;
-  jac_desc_bonds_kernel<<<(n_items + 63) / 64, 64, 0, s>>>(items, mats, n_items, bs, rowmap_ws, nrm_ws, m_cap);
+  jac_desc_bonds_kernel<<<(n_items + 63) / 64, 64, 0, s>>>(items, mats, n_items, bs, rowmap_ws, nrm_ws, m_cap,
+                                                           stats);
   jac_row_norms_kernel<<<dim3(n_items, kRowSlices), 256, 0, s>>>(mats);
   jac_fro_kernel<<<n_items, 256, 0, s>>>(mats, status);
   return hipGetLastError();
