@@ -24,6 +24,14 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _check_device_matrix(theta):
+    """The truncation kernels read theta as complex128 [m][n] in device memory."""
+    if not isinstance(theta, torch.Tensor) or theta.dtype != torch.complex128 or theta.dim() != 2:
+        raise ValueError("theta must be a complex128 matrix [m][n]")
+    if theta.device.type != "cuda":
+        raise ValueError(f"theta must be in device memory, not on {theta.device}")
+
+
 class Handle:
     """An mps_handle on one device (owns the library workspace)."""
 
@@ -84,6 +92,7 @@ class Handle:
 
     def truncate(self, theta: torch.Tensor, chi_max: int, eps: float):
         """Truncated SVD of a complex128 matrix: U, S, Vh (first k valid), k, disc, norm2."""
+        _check_device_matrix(theta)
         theta = theta.contiguous()
         m, n = theta.shape
         dev = theta.device
@@ -102,6 +111,7 @@ class Handle:
         """U(1)-symmetric truncated SVD: theta block diagonal in the row and
         column charges (int sequences, host).  U, S, Vh, q (first k valid), k,
         disc, norm2."""
+        _check_device_matrix(theta)
         theta = theta.contiguous()
         m, n = theta.shape
         rq = np.ascontiguousarray(np.asarray(row_q, dtype=np.int32))
@@ -211,15 +221,36 @@ class Charges:
         return _lib.U1ChainDesc(self.qbond.data_ptr(), (C.c_int32 * 5)(*qs), self.modulus, (C.c_int32 * 2)())
 
 
+def _check_charges(chain, q: "Charges"):
+    """The bond charges a kernel reads and writes with the chain's chi_max
+    stride: a contiguous int32 [L+1][chi_max] tensor on the chain's device,
+    at most five site charges."""
+    if not isinstance(q, Charges):
+        raise ValueError("charges must be Charges")
+    t = q.qbond
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or tuple(t.shape) != (chain.L + 1, chain.chi_max):
+        raise ValueError(f"qbond must be an int32 tensor [L+1][chi_max] = [{chain.L + 1}][{chain.chi_max}]")
+    if not t.is_contiguous():
+        raise ValueError("qbond must be contiguous")
+    dev = chain.B.device if hasattr(chain, "B") else chain.M.device
+    if t.device != dev:
+        raise ValueError(f"qbond is on {t.device}, the chain on {dev}")
+    if len(q.qsite) > 5 or len(q.qsite) != chain.d:
+        raise ValueError("qsite needs one charge per local basis state (d <= 5)")
+
+
+def _check_charge_list(chains, charges):
+    if len(charges) != len(chains):
+        raise ValueError("one Charges per chain")
+    for c, q in zip(chains, charges):
+        _check_charges(c, q)
+
+
 def tebd_step_u1(h: Handle, chains: Sequence[Chain], charges: Sequence[Charges], order: int, dt: float,
                  n_steps: int, eps: float, flags: int = 0):
     """tebd_step on charge-carrying chains: every update truncated on the
     charge blocks of its bond; charges[i].qbond follows the chain."""
-    if len(charges) != len(chains):
-        raise ValueError("one Charges per chain")
-    for c, q in zip(chains, charges):
-        if q.qbond.shape != (c.L + 1, c.chi_max) or q.qbond.dtype != torch.int32 or not q.qbond.is_contiguous():
-            raise ValueError("qbond must be a contiguous int32 tensor [L+1][chi_max]")
+    _check_charge_list(chains, charges)
     arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
     qa = (_lib.U1ChainDesc * len(chains))(*[q.desc() for q in charges])
     h.check(lib().mps_tebd_step_u1(h.h, _stream(), arr, qa, len(chains), order, float(dt), n_steps, float(eps),
@@ -243,8 +274,7 @@ def ktebd_step(h: Handle, chains: Sequence[Chain], dt: float, n_steps: int, eps:
 def ktebd_step_u1(h: Handle, chains: Sequence[Chain], charges: Sequence[Charges], dt: float, n_steps: int,
                   eps: float, n_max: int = 20, tol: float = 1e-10, flags: int = 0):
     """ktebd_step on charge-carrying chains (every cut on the charge blocks of its bond)."""
-    if len(charges) != len(chains):
-        raise ValueError("one Charges per chain")
+    _check_charge_list(chains, charges)
     arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
     qa = (_lib.U1ChainDesc * len(chains))(*[q.desc() for q in charges])
     h.check(lib().mps_ktebd_step_u1(h.h, _stream(), arr, qa, len(chains), float(dt), n_steps, float(eps),
@@ -278,8 +308,7 @@ def tebd_td_step(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_st
     hwork = torch.empty(total, dtype=torch.complex128, device=chains[0].B.device)
     arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
     if charges is not None:
-        if len(charges) != len(chains):
-            raise ValueError("one Charges per chain")
+        _check_charge_list(chains, charges)
         qa = (_lib.U1ChainDesc * len(chains))(*[q.desc() for q in charges])
         h.check(lib().mps_tebd_td_step_u1(h.h, _stream(), arr, qa, len(chains), order, float(dt), n_steps,
                                           float(eps), flags, n_terms, int(scheme), f.ctypes.data_as(C.c_void_p),
@@ -519,8 +548,7 @@ def tdvp2_step(h: Handle, chain: OCChain, dt: float, n_steps: int, eps: float, n
     kmax = torch.zeros(1, dtype=torch.int32, device=chain.M.device)
     d = chain.desc()
     if charges is not None:
-        if charges.qbond.shape != (chain.L + 1, chain.chi_max) or charges.qbond.dtype != torch.int32:
-            raise ValueError("qbond must be an int32 tensor [L+1][chi_max]")
+        _check_charges(chain, charges)
         q = charges.desc()
         h.check(lib().mps_tdvp2_step_u1(h.h, _stream(), C.byref(d), C.byref(q), float(dt), n_steps, float(eps),
                                         n_max, float(tol), _ptr(chain.disc), _ptr(kmax)))
