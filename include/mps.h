@@ -163,6 +163,23 @@ mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int6
                         int32_t* k_dev, double* disc_dev, double* norm2_dev);
 
 /*
+ * mps_truncate without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * mps_truncate (same kernels and launch shapes), but every intermediate lives
+ * in a fixed device array of 9 MiB inside the library (one copy per GPU, held
+ * until the process ends), so the call makes no hipMalloc, hipFree or other
+ * allocating call.
+ * Limits: m, n <= 512 (MPS_ERR_CAPACITY beyond).
+ * Every call on one GPU shares that GPU's array and overwrites it: calls that
+ * overlap on one GPU (two streams, two threads, two handles) race; serialise
+ * them.  Nothing needs to be cleared between calls.
+ */
+mps_status mps_truncate_noalloc(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n,
+                                int64_t chi_max, double eps, void* U, double* S, void* Vh,
+                                int32_t* k_dev, double* disc_dev, double* norm2_dev);
+
+/*
  * U(1)-symmetric truncated SVD (App. "Convenient features", symmetry
  * conservation: with a diagonal symmetry generator the tensor cut at a bond is
  * block diagonal in the bond's charge and the decomposition runs on every

@@ -24,7 +24,7 @@ MPS_C64, MPS_C128 = 0, 1
 
 # every exported symbol that include/mps.h declares
 EXPORTS = ["mps_create", "mps_destroy", "mps_last_error", "mps_reserve", "mps_device_status",
-           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
+           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_noalloc", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
            "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step", "mps_tdvp2_step_u1",
            "mps_tebd_grad_arena_bytes", "mps_tebd_grad", "mps_tebd_vjp", "mps_autotune_jacobi",
            "mps_autotune_candidate"]
@@ -72,6 +72,7 @@ def lib():
         "mps_kernel_stats": [vp, vp, i32, C.POINTER(dbl), C.POINTER(i64), C.POINTER(C.c_uint64), i32],
         "mps_gates": [vp, vp, i32, i32, vp, vp, vp, vp],
         "mps_truncate": [vp, vp, vp, i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp],
+        "mps_truncate_noalloc": [vp, vp, vp, i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp],
         "mps_truncate_u1": [vp, vp, vp, i64, i64, vp, vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp],
         "mps_tebd_step": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32],
         "mps_tebd_step_u1": [vp, vp, C.POINTER(ChainDesc), C.POINTER(U1ChainDesc), i32, i32, dbl, i32, dbl, u32],

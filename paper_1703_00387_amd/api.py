@@ -90,8 +90,9 @@ class Handle:
                                    _ptr(G64), _ptr(G128)))
         return G64, G128
 
-    def truncate(self, theta: torch.Tensor, chi_max: int, eps: float):
-        """Truncated SVD of a complex128 matrix: U, S, Vh (first k valid), k, disc, norm2."""
+    def truncate(self, theta: torch.Tensor, chi_max: int, eps: float, noalloc: bool = False):
+        """Truncated SVD of a complex128 matrix: U, S, Vh (first k valid), k, disc, norm2.
+        noalloc: through mps_truncate_noalloc (m, n <= 512, no allocation in the library)."""
         _check_device_matrix(theta)
         theta = theta.contiguous()
         m, n = theta.shape
@@ -102,8 +103,9 @@ class Handle:
         k = torch.zeros(1, dtype=torch.int32, device=dev)
         disc = torch.zeros(1, dtype=torch.float64, device=dev)
         nrm = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.check(lib().mps_truncate(self.h, _stream(), _ptr(theta), m, n, chi_max, float(eps), _ptr(U), _ptr(S),
-                                      _ptr(Vh), _ptr(k), _ptr(disc), _ptr(nrm)))
+        fn = lib().mps_truncate_noalloc if noalloc else lib().mps_truncate
+        self.check(fn(self.h, _stream(), _ptr(theta), m, n, chi_max, float(eps), _ptr(U), _ptr(S),
+                      _ptr(Vh), _ptr(k), _ptr(disc), _ptr(nrm)))
         kk = int(k.item())
         return U[:, :kk], S[:kk], Vh[:kk], kk, float(disc.item()), float(nrm.item())
 

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -52,7 +53,7 @@ mps_status mps_aux_streams(mps_handle h, int n) {
 }
 
 mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
-                      bool fixed, bool allow_split) {
+                      bool fixed, bool allow_split, double2* split_buf, size_t split_buf_bytes) {
   int nb = nb_cap;
   if (!fixed) {
     // eager mode: the largest actual block count bounds the rounds of a sweep
@@ -90,15 +91,23 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
   // Large matrices (m >= 1024) split up to half a chip's worth of pairs: a
   // 2560 x 2560 SVD (40 pairs) took 1.19 s unsplit and 0.47 s with S = 6.
   const bool few = pairs < h->jac_split_below || (pairs < 128 && m_cap >= 1024);
+  double2* split_part = h->split_part;
   if (!fixed && allow_split && h->jac_split_below > 0 && few) {
     S = std::max(1, std::min(std::min(16, 256 / std::max(pairs, 1)), std::max(1, m_cap / 64)));
-    const size_t need = (size_t)n * (nb_cap / 2) * S * 64 * 64 * sizeof(double2);
-    if (S > 1 && need > h->split_bytes) {
+    const size_t per_slice = (size_t)n * (nb_cap / 2) * 64 * 64 * sizeof(double2);
+    if (split_buf) {
+      // a caller-provided buffer: as many slices as it holds, no allocation
+      S = std::max(1, std::min<int>(S, (int)(split_buf_bytes / per_slice)));
+      split_part = split_buf;
+    }
+    const size_t need = per_slice * S;
+    if (!split_buf && S > 1 && need > h->split_bytes) {
       if (h->split_part) MPS_TRY_HIP(h, hipFree(h->split_part));
       h->split_part = nullptr;
       h->split_bytes = 0;
       MPS_TRY_HIP(h, hipMalloc((void**)&h->split_part, need));
       h->split_bytes = need;
+      split_part = h->split_part;
     }
   }
   bool done = false;
@@ -107,7 +116,7 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     for (int r = 0; r < nb - 1; ++r)
       PROF_LAUNCH(h, s, MPS_K_JAC_ROUND, launch_jac_round(s, mats, n, nb_cap, r, h->jac_tol, h->jac_abs, h->jac_inner_sweeps, 0,
                                                               h->profile ? h->stats_dev : nullptr, h->jac_threads, S,
-                                                              h->split_part));
+                                                              split_part));
     MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n, unconv));
     if (!fixed && sw >= 1) {
       if (h->profile) {
@@ -177,6 +186,101 @@ mps_status mps_ensure_ws(mps_handle h, size_t bytes) {
   return MPS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// truncated SVD of one matrix: shared by mps_truncate (handle workspace) and
+// mps_truncate_noalloc (the fixed device scratch below)
+// ---------------------------------------------------------------------------
+static mps_status truncate_check(mps_handle h, const void* theta, int64_t m, int64_t n, int64_t chi_max, double eps,
+                          void* U, double* S, void* Vh, int32_t* k_dev, double* disc_dev, double* norm2_dev) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!theta || !U || !S || !Vh || !k_dev || !disc_dev || !norm2_dev)
+    return mps_fail(h, MPS_ERR_INVALID, "null pointer");
+  if (m < 1 || n < 1 || chi_max < 1) return mps_fail(h, MPS_ERR_SHAPE, "m, n, chi_max must be >= 1");
+  if (!(eps == eps)) return mps_fail(h, MPS_ERR_INVALID, "eps is NaN");
+  return MPS_OK;
+}
+
+struct TruncPlan {
+  size_t oX, oM, oP, oS, oSel, oU, oR, oNr, off;
+};
+
+static TruncPlan truncate_plan(int64_t m, int64_t n) {
+  WsPlan p;
+  TruncPlan t;
+  t.oX = p.take<double2>((size_t)m * n);
+  t.oM = p.take<JacMat>(1);
+  t.oP = p.take<int32_t>(m);
+  t.oS = p.take<double>(m);
+  t.oSel = p.take<SelOut>(1);
+  t.oU = p.take<int32_t>(4);
+  t.oR = p.take<int32_t>(m);
+  t.oNr = p.take<double>(m);
+  t.off = p.off;
+  return t;
+}
+
+// ws holds truncate_plan(m, n).off bytes; split_buf (optional) the partial
+// Grams of column-split rounds (else the handle's buffer, grown on demand).
+static mps_status truncate_run(mps_handle h, hipStream_t s, const void* theta, int64_t m, int64_t n, int64_t chi_max,
+                        double eps, void* U, double* S, void* Vh, int32_t* k_dev, double* disc_dev,
+                        double* norm2_dev, char* ws, double2* split_buf, size_t split_bytes) {
+  const TruncPlan t = truncate_plan(m, n);
+  double2* X = (double2*)(ws + t.oX);
+  JacMat* mat = (JacMat*)(ws + t.oM);
+  MPS_TRY_HIP(h, hipMemcpyAsync(X, theta, (size_t)m * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  JacMat hm;
+  std::memset(&hm, 0, sizeof(hm));
+  hm.X = X;
+  hm.rowmap = (int32_t*)(ws + t.oR);
+  hm.nrm2 = (double*)(ws + t.oNr);
+  hm.m = (int)m;
+  hm.n = (int)n;
+  hm.ld = (int)n;
+  hm.nb = jac_nb((int)m);
+  hm.kmax = (int)std::min<int64_t>(chi_max, m);
+  std::vector<JacMat> hv(1, hm);
+  mps_status st = upload(h, s, mat, hv);
+  if (st != MPS_OK) return st;
+  MPS_TRY_HIP(h, launch_jac_prep_plain(s, mat, 1, h->status_dev));
+  st = run_jacobi(h, s, mat, 1, hm.nb, (int)m, (int32_t*)(ws + t.oU), false, true, split_buf, split_bytes);
+  if (st != MPS_OK) return st;
+  SelOut* sel = (SelOut*)(ws + t.oSel);
+  MPS_TRY_HIP(h, launch_select(s, mat, 1, (int32_t*)(ws + t.oP), (double*)(ws + t.oS), (int)m, hm.kmax,
+                                count_rule_eps(h, eps), sel));
+  MPS_TRY_HIP(h, launch_truncate_out(s, mat, (int32_t*)(ws + t.oP), (double*)(ws + t.oS), sel,
+                                     (const double2*)theta, m, n, chi_max, (double2*)U, S, (double2*)Vh, k_dev,
+                                     disc_dev, norm2_dev));
+  return MPS_OK;
+}
+
+// The scratch of mps_truncate_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes its name to
+// a kernel (on the host the name is only a stand-in); mps_create takes this
+// device's address of it once with hipGetSymbolAddress, and the kernels get
+// that address.  Layout: the truncation's workspace (X copy of at most
+// 512 x 512, descriptors, row maps), then the partial Grams of the column
+// split in the rest.
+constexpr int64_t kNoAllocMaxDim = 512;
+constexpr size_t kNoAllocScratchBytes = size_t(9) << 20;   // 9 MiB
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's scratch (device current), once per device.
+static mps_status scratch_setup(int device, char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return MPS_ERR_CAPACITY;
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MPS_ERR_HIP;
+    g_scratch_ptr[device] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return MPS_OK;
+}
+
 extern "C" {
 
 mps_status mps_create(mps_handle* out, int device) {
@@ -195,6 +299,12 @@ mps_status mps_create(mps_handle* out, int device) {
     return MPS_ERR_HIP;
   }
   h->stats_dev = (unsigned long long*)((char*)h->status_dev + 64);
+  if (scratch_setup(device, &h->scratch) != MPS_OK) {
+    hipFree(h->status_dev);
+    hipHostFree(h->host_pinned);
+    delete h;
+    return MPS_ERR_HIP;
+  }
   *out = h;
   return MPS_OK;
 }
@@ -325,50 +435,35 @@ mps_status mps_gates(mps_handle h, mps_stream stream, int32_t n, int32_t dd, con
 mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n, int64_t chi_max,
                         double eps, void* U, double* S, void* Vh, int32_t* k_dev, double* disc_dev,
                         double* norm2_dev) {
-  if (!h) return MPS_ERR_INVALID;
-  if (!theta || !U || !S || !Vh || !k_dev || !disc_dev || !norm2_dev)
-    return mps_fail(h, MPS_ERR_INVALID, "null pointer");
-  if (m < 1 || n < 1 || chi_max < 1) return mps_fail(h, MPS_ERR_SHAPE, "m, n, chi_max must be >= 1");
+  mps_status st = truncate_check(h, theta, m, n, chi_max, eps, U, S, Vh, k_dev, disc_dev, norm2_dev);
+  if (st != MPS_OK) return st;
   if (m > 4096 || n > 4096) return mps_fail(h, MPS_ERR_CAPACITY, "m and n are limited to 4096");
-  if (!(eps == eps)) return mps_fail(h, MPS_ERR_INVALID, "eps is NaN");
-  hipStream_t s = (hipStream_t)stream;
-  WsPlan p;
-  size_t oX = p.take<double2>((size_t)m * n);
-  size_t oM = p.take<JacMat>(1);
-  size_t oP = p.take<int32_t>(m);
-  size_t oS = p.take<double>(m);
-  size_t oSel = p.take<SelOut>(1);
-  size_t oU = p.take<int32_t>(4);
-  size_t oR = p.take<int32_t>(m);
-  size_t oNr = p.take<double>(m);
-  mps_status st = mps_ensure_ws(h, p.off);
+  st = mps_ensure_ws(h, truncate_plan(m, n).off);
   if (st != MPS_OK) return st;
-  double2* X = (double2*)(h->ws + oX);
-  JacMat* mat = (JacMat*)(h->ws + oM);
-  MPS_TRY_HIP(h, hipMemcpyAsync(X, theta, (size_t)m * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  JacMat hm;
-  std::memset(&hm, 0, sizeof(hm));
-  hm.X = X;
-  hm.rowmap = (int32_t*)(h->ws + oR);
-  hm.nrm2 = (double*)(h->ws + oNr);
-  hm.m = (int)m;
-  hm.n = (int)n;
-  hm.ld = (int)n;
-  hm.nb = jac_nb((int)m);
-  hm.kmax = (int)std::min<int64_t>(chi_max, m);
-  std::vector<JacMat> hv(1, hm);
-  st = upload(h, s, mat, hv);
+  return truncate_run(h, (hipStream_t)stream, theta, m, n, chi_max, eps, U, S, Vh, k_dev, disc_dev, norm2_dev, h->ws,
+                      nullptr, 0);
+}
+
+mps_status mps_truncate_noalloc(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n,
+                                int64_t chi_max, double eps, void* U, double* S, void* Vh, int32_t* k_dev,
+                                double* disc_dev, double* norm2_dev) {
+  mps_status st = truncate_check(h, theta, m, n, chi_max, eps, U, S, Vh, k_dev, disc_dev, norm2_dev);
   if (st != MPS_OK) return st;
-  MPS_TRY_HIP(h, launch_jac_prep_plain(s, mat, 1, h->status_dev));
-  st = run_jacobi(h, s, mat, 1, hm.nb, (int)m, (int32_t*)(h->ws + oU), false);
-  if (st != MPS_OK) return st;
-  SelOut* sel = (SelOut*)(h->ws + oSel);
-  MPS_TRY_HIP(h, launch_select(s, mat, 1, (int32_t*)(h->ws + oP), (double*)(h->ws + oS), (int)m, hm.kmax,
-                                count_rule_eps(h, eps), sel));
-  MPS_TRY_HIP(h, launch_truncate_out(s, mat, (int32_t*)(h->ws + oP), (double*)(h->ws + oS), sel,
-                                     (const double2*)theta, m, n, chi_max, (double2*)U, S, (double2*)Vh, k_dev,
-                                     disc_dev, norm2_dev));
-  return MPS_OK;
+  if (m > kNoAllocMaxDim || n > kNoAllocMaxDim)
+    return mps_fail(h, MPS_ERR_CAPACITY, "mps_truncate_noalloc: m and n are limited to 512 (its fixed scratch)");
+  char* base = h->scratch;   // device address of this device's copy of the scratch array
+  if (!base) return mps_fail(h, MPS_ERR_HIP, "mps_truncate_noalloc: scratch address unavailable on this device");
+  const size_t off = (truncate_plan(m, n).off + 255) & ~size_t(255);
+  if (off > kNoAllocScratchBytes) return mps_fail(h, MPS_ERR_CAPACITY, "mps_truncate_noalloc: scratch too small");
+  // no event timing here: creating events is not allowed on this path
+  struct ProfGuard {
+    mps_handle h;
+    bool saved;
+    ~ProfGuard() { h->profile = saved; }
+  } guard{h, h->profile};
+  h->profile = false;
+  return truncate_run(h, (hipStream_t)stream, theta, m, n, chi_max, eps, U, S, Vh, k_dev, disc_dev, norm2_dev, base,
+                      (double2*)(base + off), kNoAllocScratchBytes - off);
 }
 
 mps_status mps_observe(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* op1,

@@ -41,6 +41,7 @@ struct mps_context {
   int split_method = 0;        // single-panel matrices: 0 = one-sided Jacobi SVD, 1 = eigensolve of the Gram
   double2* split_part = nullptr;  // partial Grams of split rounds (grown on demand)
   size_t split_bytes = 0;
+  char* scratch = nullptr;        // this device's address of the no-allocation entry's scratch array
   // pinned host scratch for small readbacks
   int32_t* host_pinned = nullptr;
   // optional per-kernel timing with HIP events on the launch stream
@@ -62,8 +63,11 @@ mps_status mps_aux_streams(mps_handle h, int n);
 struct JacMat;
 int jac_nb(int m);
 // allow_split: rounds with few panel pairs may split each pair over columns
+// split_buf (optional, split_buf_bytes long): the partial Grams of column-split
+// rounds go there instead of the handle's buffer (grown on demand); the split
+// then uses as many slices as it holds
 mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_cap, int m_cap, int32_t* unconv,
-                      bool fixed, bool allow_split = true);
+                      bool fixed, bool allow_split = true, double2* split_buf = nullptr, size_t split_buf_bytes = 0);
 
 // Local Krylov propagation of the bond terms (Krylov TEBD)
 struct KryOpts {
