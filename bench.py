@@ -70,6 +70,9 @@ def main():
                     help="two-site split of matrices of at most 64 rows: one-sided Jacobi SVD or the "
                          "eigendecomposition of the Gram")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rounds", action="store_true",
+                    help="one launch per Jacobi round with a convergence read-back per sweep, instead of the "
+                         "persistent Jacobi launch")
     ap.add_argument("--no-plain", action="store_true", help="xxz_batch256: skip the one-bond-per-launch comparison")
     ap.add_argument("--save-state", default=None, help="save the chain after the warmup (torch.save)")
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
@@ -118,6 +121,7 @@ def main():
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
     h.set_option(7, 1.0 if args.split == "eig" else 0.0)
+    h.set_option(8, 0.0 if args.rounds else 1.0)
     tuned = api.autotune(h, 32, 512, 512, apply=True, cache=args.autotune) if args.autotune else None
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
 
@@ -211,12 +215,14 @@ def main():
         "config": {"workload": "xxz_tebd4_L64: TEBD4 XXZ L=64 Jxy=1 Jz=0.5 Neel dt=0.05 chi_max=256 eps=1e-12",
                    "updates_per_step": updates_per_step, "prelude_steps": prelude, "start_step": start_step,
                    "jacobi_threads": args.jac_threads, "autotune": tuned,
+                   "jacobi_schedule": "round launches" if args.rounds else "persistent",
                    "chi_hist": {"max": int(chi.max()), "mean": round(float(chi.mean()), 1),
                                 "n_at_cap": int((chi >= spec.chi_max).sum()), "n_at_cap_start": n_at_cap0}},
         "windows": {"steps": sizes, "updates_per_s": [round(r, 2) for r in rates],
                     "mean_updates_per_s": round(updates_per_step * args.steps / elapsed, 2),
                     "timed_s": round(elapsed, 4)},
-        "roofline": {"kernel": "jac_round_kernel (FP64 block-Jacobi round: Gram + rotation)",
+        "roofline": {"kernel": ("jac_round_kernel (FP64 block-Jacobi round: Gram + rotation)" if args.rounds else
+                                "jac_persist_kernel (FP64 block Jacobi, all sweeps of a layer: Gram + rotation)"),
                      "bound": "mfma", "achieved": round(jr_ach, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(jr_ach / FP64_PEAK_TFLOPS, 4),
                      "traffic": _jac_round_traffic() if same_state else None,

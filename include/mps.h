@@ -57,6 +57,7 @@ typedef enum {
 #define MPS_DEV_NOCONV_SVD     0x1u
 #define MPS_DEV_NOCONV_LANCZOS 0x2u
 #define MPS_DEV_NONFINITE      0x4u
+#define MPS_DEV_SCHED_TIMEOUT  0x8u  /* a persistent kernel's bounded wait ran out */
 
 typedef struct mps_context* mps_handle;
 typedef void* mps_stream; /* hipStream_t */
@@ -89,7 +90,14 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * (default), 1 = the eigendecomposition split (Sec. "Basic concepts", Eq.
  * AAD_ULLUD): the Gram theta' theta'^dag is diagonalised to convergence in LDS
  * and the rows are rotated once by its eigenvectors; a singular value s_j then
- * carries a relative error of order 1e-15 (s_1/s_j)^2. */
+ * carries a relative error of order 1e-15 (s_1/s_j)^2,
+ * 8 = persistent Jacobi (default 1): a batch whose rounds need no column
+ * split runs all its sweeps in one launch of resident workgroups that take
+ * (sweep, round, matrix, pair) items from a device queue, each waiting only
+ * for the previous round of its own matrix, with convergence decided on the
+ * device; 0 = one launch per round and a convergence read-back per sweep.
+ * A wait of the persistent launch is bounded (seconds); one that runs out
+ * sets MPS_DEV_SCHED_TIMEOUT and the launch ends. */
 mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
  * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,

@@ -14,6 +14,7 @@ constexpr int kJacBlock = 32;   // rows per Jacobi block
 constexpr int kFixedSweeps = 20;  // sweeps queued when the host may not synchronise
 constexpr int kLoopInner = 4;     // inner sweeps per outer sweep for single-panel matrices
 constexpr int kEigSweeps = 40;    // eigen split: sweeps of the 64x64 Hermitian Jacobi (it stops when converged)
+constexpr int kSpinLimit = 1000000;  // polls of a persistent Jacobi wait before it gives up (a few seconds)
 
 }  // namespace
 
@@ -109,6 +110,25 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
       h->split_bytes = need;
       split_part = h->split_part;
     }
+  }
+  if (S == 1 && h->jac_persistent && n <= kSchedCap) {
+    // every remaining sweep in one persistent launch: pairs from a device
+    // queue, convergence decided on the device, no host round trip
+    JacSched sc;
+    sc.head = (unsigned long long*)h->sched;
+    sc.n_conv = (int32_t*)(h->sched + 8);
+    sc.abort = (int32_t*)(h->sched + 12);
+    sc.done = (int32_t*)(h->sched + 16);
+    sc.ready = sc.done + kSchedCap;
+    sc.n = n;
+    sc.nb_cap = nb;
+    sc.max_sweeps = h->jac_max_sweeps;
+    sc.spin_limit = kSpinLimit;
+    const int grid = std::max(1, std::min(h->n_cu, n * (nb / 2)));
+    PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
+                launch_jac_persist(s, mats, sc, h->jac_tol, h->jac_abs, h->jac_inner_sweeps,
+                                   h->profile ? h->stats_dev : nullptr, h->jac_threads, grid, h->status_dev));
+    return MPS_OK;
   }
   bool done = false;
   for (int sw = 0; sw < max_sweeps && !done; ++sw) {
@@ -292,15 +312,25 @@ mps_status mps_create(mps_handle* out, int device) {
   mps_context* h = new (std::nothrow) mps_context();
   if (!h) return MPS_ERR_CAPACITY;
   h->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete h;
+    return MPS_ERR_HIP;
+  }
+  h->n_cu = std::max(1, prop.multiProcessorCount);
   if (hipMalloc((void**)&h->status_dev, 256) != hipSuccess ||
       hipMemset(h->status_dev, 0, 256) != hipSuccess ||
+      hipMalloc((void**)&h->sched, kSchedBytes) != hipSuccess ||
       hipHostMalloc((void**)&h->host_pinned, 256, hipHostMallocDefault) != hipSuccess) {
+    if (h->status_dev) hipFree(h->status_dev);
+    if (h->sched) hipFree(h->sched);
     delete h;
     return MPS_ERR_HIP;
   }
   h->stats_dev = (unsigned long long*)((char*)h->status_dev + 64);
   if (scratch_setup(device, &h->scratch) != MPS_OK) {
     hipFree(h->status_dev);
+    hipFree(h->sched);
     hipHostFree(h->host_pinned);
     delete h;
     return MPS_ERR_HIP;
@@ -319,6 +349,7 @@ mps_status mps_destroy(mps_handle h) {
   if (h->ws) hipFree(h->ws);
   if (h->split_part) hipFree(h->split_part);
   if (h->status_dev) hipFree(h->status_dev);
+  if (h->sched) hipFree(h->sched);
   if (h->host_pinned) hipHostFree(h->host_pinned);
   delete h;
   return MPS_OK;
@@ -365,6 +396,10 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
       if (value != 0.0 && value != 1.0) return mps_fail(h, MPS_ERR_INVALID, "split method must be 0 or 1");
       h->split_method = (int)value;
       return MPS_OK;
+    case 8:
+      if (value != 0.0 && value != 1.0) return mps_fail(h, MPS_ERR_INVALID, "persistent Jacobi must be 0 or 1");
+      h->jac_persistent = (int)value;
+      return MPS_OK;
     default:
       return mps_fail(h, MPS_ERR_INVALID, "unknown option");
   }
@@ -381,6 +416,8 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word) {
   if (w & MPS_DEV_NONFINITE) return mps_fail(h, MPS_ERR_NONFINITE, "non-finite values met on the device");
   if (w & (MPS_DEV_NOCONV_SVD | MPS_DEV_NOCONV_LANCZOS))
     return mps_fail(h, MPS_ERR_NOCONV, "an iteration did not converge");
+  if (w & MPS_DEV_SCHED_TIMEOUT)
+    return mps_fail(h, MPS_ERR_NOCONV, "a persistent Jacobi wait ran out (results incomplete)");
   return MPS_OK;
 }
 

@@ -42,6 +42,9 @@ struct mps_context {
   double2* split_part = nullptr;  // partial Grams of split rounds (grown on demand)
   size_t split_bytes = 0;
   char* scratch = nullptr;        // this device's address of the no-allocation entry's scratch array
+  int jac_persistent = 1;         // batches without a column split: all sweeps in one persistent launch
+  int n_cu = 256;                 // compute units of the device (persistent grid size)
+  char* sched = nullptr;          // counters of the persistent Jacobi (kSchedBytes)
   // pinned host scratch for small readbacks
   int32_t* host_pinned = nullptr;
   // optional per-kernel timing with HIP events on the launch stream
@@ -254,6 +257,23 @@ struct JacSplit {
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round,
                             double tol, double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
                             int threads, int split_S = 1, double2* split_part = nullptr, int eig = 0);
+// Capacity of the handle's persistent-Jacobi counters: matrices per launch.
+constexpr int kSchedCap = 65536;
+constexpr size_t kSchedBytes = 16 + 2 * sizeof(int32_t) * (size_t)kSchedCap;
+// Counters of a persistent Jacobi launch (device memory, cleared by the launch).
+struct JacSched {
+  unsigned long long* head;  // next work item
+  int32_t* n_conv;           // matrices converged
+  int32_t* abort;            // set when a wait ran out: every workgroup leaves
+  int32_t* done;             // [n] finished pair items per matrix
+  int32_t* ready;            // [n] last sweep whose row order is set
+  int32_t n, nb_cap, max_sweeps, spin_limit;
+};
+// All sweeps of n matrices (at most max_sweeps) in one launch of `grid`
+// resident workgroups (see jac_persist_kernel), then the convergence flags.
+hipError_t launch_jac_persist(hipStream_t s, JacMat* mats, const JacSched& sc, double tol, double abs_tol,
+                              int inner_sweeps, unsigned long long* stats, int threads, int grid,
+                              uint32_t* status);
 hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged);
 hipError_t launch_jac_sort(hipStream_t s, JacMat* mats, int n_mats, int m_cap);
 hipError_t launch_jac_flag_noconv(hipStream_t s, const int32_t* unconverged, uint32_t* status);

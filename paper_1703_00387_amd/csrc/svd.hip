@@ -284,30 +284,62 @@ __device__ __forceinline__ void rot_mma_chunk(const double2* __restrict__ Al, in
 // partials in a fixed order (so every slice holds the same G and computes the
 // same rotation), runs the LDS solve and rotates its own columns.  Matrices
 // whose rounds have few panel pairs (one large matrix) then use more CUs.
+// Both LDS arrays of a round hold a [JP][JP+1] matrix (4160 elements) or four
+// staging buffers of [TBK][TLD] (4352 elements); sized for the larger.
+constexpr int kLdsElems = (JP * (JP + 1) > 4 * TBK * TLD) ? JP * (JP + 1) : 4 * TBK * TLD;
+
+// The LDS a workgroup works in while it handles one panel pair, at module
+// scope so that every kernel using the pair body addresses it directly.
+__shared__ double2 jl_G[kLdsElems];         // Gram matrix; staging of the update afterwards
+__shared__ double2 jl_Q[kLdsElems];         // staging of the Gram; then the panel rotation
+__shared__ double2 jl_rotw[kJac64Scratch];  // rotations, index pairs and lists of the inner solve
+__shared__ int jl_rows[JP];                 // physical rows of the pair
+__shared__ int jl_flag;
+__shared__ int jl_need;
+
+// One panel pair (blocks I and J of matrix M, pair slot p of matrix index mat)
+// handled by one workgroup: Gram, orthogonality test, LDS solve, rotation of
+// the rows (or, column split, this slice's share; loop mode, several sweeps).
+template <int NT>
+__device__ __forceinline__ void jac_pair_body(JacMat* __restrict__ M, int I, int J, int mat, int p, int slice,
+                                              double tol, double abs_tol, int inner_sweeps, int loop_sweeps,
+                                              unsigned long long* stats, const JacSplit& split);
+
 template <int NT>
 __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
                                                        double abs_tol, int inner_sweeps, int loop_sweeps,
                                                        unsigned long long* stats, JacSplit split) {
-  constexpr int NG = NT / 256;  // wave groups
-  // chunks in flight per thread in the Gram and rotation loops: with two
-  // waves per SIMD one is enough (measured: 233 us against 250 us for three
-  // at chi = 256), and it leaves more registers
-  constexpr int kPf = NG > 1 ? 1 : ::kPf;
-  // Both arrays hold a [JP][JP+1] matrix (4160 elements) or four staging
-  // buffers of [TBK][TLD] (4352 elements); sized for the larger.
-  constexpr int kLdsElems = (JP * (JP + 1) > 4 * TBK * TLD) ? JP * (JP + 1) : 4 * TBK * TLD;
-  __shared__ double2 G[kLdsElems];  // Gram matrix; staging of the update afterwards
-  __shared__ double2 Q[kLdsElems];  // staging of the Gram; then the panel rotation
-  __shared__ double2 rotw[kJac64Scratch];  // rotations, index pairs and lists of the inner solve
-  __shared__ int rows_s[JP];
-  __shared__ int flag;
-  __shared__ int need;
   JacMat* M = mats + blockIdx.y;
   if (M->conv) return;
   const int S = split.S, slice = blockIdx.x % S;
   const int nb = M->nb, p = blockIdx.x / S;
   if (2 * p >= nb || round >= nb - 1) return;
   if (loop_sweeps > 0 && nb != 2) return;  // larger matrices take the round-based sweeps
+  int I, J;
+  jac_pair(nb, round, p, I, J);
+  if (loop_sweeps > 0) {  // one panel: keep the real rows first
+    I = 0;
+    J = 1;
+  }
+  jac_pair_body<NT>(M, I, J, blockIdx.y, p, slice, tol, abs_tol, inner_sweeps, loop_sweeps, stats, split);
+}
+
+template <int NT>
+__device__ __forceinline__ void jac_pair_body(JacMat* __restrict__ M, int I, int J, int mat, int p, int slice,
+                                              double tol, double abs_tol, int inner_sweeps, int loop_sweeps,
+                                              unsigned long long* stats, const JacSplit& split) {
+  constexpr int NG = NT / 256;  // wave groups
+  // chunks in flight per thread in the Gram and rotation loops: with two
+  // waves per SIMD one is enough (measured: 233 us against 250 us for three
+  // at chi = 256), and it leaves more registers
+  constexpr int kPf = NG > 1 ? 1 : ::kPf;
+  double2* const G = jl_G;
+  double2* const Q = jl_Q;
+  double2* const rotw = jl_rotw;
+  int* const rows_s = jl_rows;
+  int& flag = jl_flag;
+  int& need = jl_need;
+  const int S = split.S;
   const int m = M->m, n = M->n, ld = M->ld;
   double2* X = M->X;
   // this workgroup's 64-column blocks [cb0, cb1) and 16-column chunks [ch0, ch1)
@@ -315,13 +347,7 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
   const int cb0 = (int)((long long)ncb_all * slice / S), cb1 = (int)((long long)ncb_all * (slice + 1) / S);
   const int ch0 = cb0 * (TBN / TBK), ch1 = min(cb1 * (TBN / TBK), (n + TBK - 1) / TBK);
   // partial Gram of (matrix, pair, slice): [JP][JP]
-  double2* part = S > 1 ? split.part + (((size_t)blockIdx.y * split.pairs + p) * S + slice) * (JP * JP) : nullptr;
-  int I, J;
-  jac_pair(nb, round, p, I, J);
-  if (loop_sweeps > 0) {  // one panel: keep the real rows first
-    I = 0;
-    J = 1;
-  }
+  double2* part = S > 1 ? split.part + (((size_t)mat * split.pairs + p) * S + slice) * (JP * JP) : nullptr;
   const int tid = threadIdx.x, lane = tid & 63;
   // group, thread and wave inside the group (constants for one group)
   const int grp = NG > 1 ? tid >> 8 : 0, gtid = NG > 1 ? tid & 255 : tid, wave = gtid >> 6;
@@ -406,7 +432,7 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
   }
   if (S > 1) {
     // phase 1: the pair's Gram is the sum of the S partials, added in slice order
-    const double2* pp0 = split.part + ((size_t)blockIdx.y * split.pairs + p) * S * (JP * JP);
+    const double2* pp0 = split.part + ((size_t)mat * split.pairs + p) * S * (JP * JP);
     for (int e = tid; e < JP * JP; e += NT) {
       double2 a = make_double2(0.0, 0.0);
       for (int t = 0; t < S; ++t) {
@@ -546,6 +572,216 @@ __global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats
       M->conv = 1;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent sweeps: one launch runs every round of every sweep of a batch.
+// The work items are (sweep s, round r, matrix i, pair slot p), numbered
+//   g = ((s * (nb_cap - 1) + r) * n + i) * (nb_cap / 2) + p
+// and taken in increasing g from a device counter by workgroups that stay
+// resident.  An item needs the previous round of its matrix (round r of
+// matrix i starts when done[i] counts every pair item of its earlier rounds);
+// the first item of a sweep after the first (p = 0, r = 0) waits for the
+// whole previous sweep, decides convergence (no rotation in it) and sorts the
+// rows by norm, and the other items of that round wait for the sort
+// (ready[i] = s).  Every dependency has a smaller g, so the item with the
+// smallest g not yet finished can always run: the queue cannot deadlock.
+// A workgroup that finishes a pair early (an orthogonal pair stops after its
+// Gram) takes the next item at once instead of idling until the slowest pair
+// of a round launch ends, and there is no launch or host round trip between
+// rounds or sweeps.  Waits are bounded: past spin_limit polls the workgroup
+// sets MPS_DEV_SCHED_TIMEOUT and leaves, and so do those waiting on it.
+// Cross-workgroup visibility: the rows, norms and counters are published with
+// agent-scope release fences and read after agent-scope acquires.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ld_acq(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_rlx(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *ctr >= target or the matrix is converged; false on timeout or
+// when another workgroup has aborted the launch.  The polls are relaxed (no
+// cache invalidation per poll); one acquire fence follows the poll that
+// succeeds.
+__device__ bool jac_wait(const int32_t* ctr, int target, const int32_t* conv, const int32_t* abort_flag,
+                         int spin_limit) {
+  for (int it = 0; it < spin_limit; ++it) {
+    if (ld_rlx(ctr) >= target || ld_rlx(conv) != 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return true;
+    }
+    if (ld_rlx(abort_flag) != 0) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+constexpr int kActExit = 0, kActSkip = 1, kActPair = 2, kActSortPair = 3;
+
+template <int NT>
+__global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ mats, JacSched sc, double tol,
+                                                         double abs_tol, int inner_sweeps,
+                                                         unsigned long long* stats, uint32_t* status) {
+  __shared__ int act_s, mat_s, I_s, J_s, p_s, sweep_s;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // Wave 0 decides, with all its lanes active: the leader test is uniform over
+  // a wave (readfirstlane), so the decision is a scalar branch around whole
+  // waves.  A per-thread test (tid == 0) around the waits let the compiler
+  // restructure the item loop so that the other lanes re-entered it without
+  // the decision; every loop inside the decision is free of barriers.
+  const bool leader = __builtin_amdgcn_readfirstlane(tid) == 0;
+  const int R = sc.nb_cap - 1, P = sc.nb_cap / 2, n = sc.n;
+  const unsigned long long total = (unsigned long long)sc.max_sweeps * R * n * P;
+  JacSplit unsplit;
+  unsplit.S = 1;
+  unsplit.pairs = P;
+  unsplit.phase = 2;
+  unsplit.eig = 0;
+  unsplit.part = nullptr;
+  for (;;) {
+    if (leader) {
+      // one atomic for the wave (lane 0 adds 1, the others 0); every lane
+      // takes lane 0's value
+      const unsigned long long inc = lane == 0 ? 1ull : 0ull;
+      const unsigned long long got =
+          __hip_atomic_fetch_add(sc.head, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long g = __shfl(got, 0);
+      int act = kActExit, mi = 0, I = 0, J = 0, p = 0, sw = 0;
+      if (g < total && ld_rlx(sc.n_conv) < n && ld_rlx(sc.abort) == 0) {
+        p = (int)(g % P);
+        unsigned long long q = g / P;
+        mi = (int)(q % n);
+        q /= n;
+        const int r = (int)(q % R);
+        sw = (int)(q / R);
+        JacMat* M = mats + mi;
+        const int nb = M->nb;
+        act = kActSkip;
+        if (r < nb - 1 && 2 * p < nb && ld_rlx(&M->conv) == 0) {
+          const int per_round = nb / 2, rounds = nb - 1;
+          bool ok = true;
+          if (sw > 0 && r == 0 && p == 0) {
+            // the whole previous sweep, then convergence and the row order
+            ok = jac_wait(sc.done + mi, sw * rounds * per_round, &M->conv, sc.abort, sc.spin_limit);
+            if (ok && ld_rlx(&M->conv) == 0) {
+              if (__hip_atomic_load(&M->rot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                // converged: the wave's lanes store the same flag; one count
+                __hip_atomic_store(&M->conv, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(sc.n_conv, lane == 0 ? 1 : 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+              } else {
+                act = kActSortPair;
+              }
+            }
+          } else if (sw > 0 && r == 0) {
+            ok = jac_wait(sc.ready + mi, sw, &M->conv, sc.abort, sc.spin_limit);
+            if (ok && ld_rlx(&M->conv) == 0) act = kActPair;
+          } else if (r > 0) {
+            ok = jac_wait(sc.done + mi, (sw * rounds + r) * per_round, &M->conv, sc.abort, sc.spin_limit);
+            if (ok && ld_rlx(&M->conv) == 0) act = kActPair;
+          } else {
+            act = kActPair;   // round 0 of the first sweep: the rows as prepared
+          }
+          if (!ok) {
+            // out of time (or another workgroup gave up): every workgroup leaves
+            atomicOr(status, MPS_DEV_SCHED_TIMEOUT);
+            __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            act = kActExit;
+          }
+          if (act >= kActPair) jac_pair(nb, r, p, I, J);
+        }
+      }
+      // the lanes agree (same loads of the same words); lane 0's decision is
+      // the workgroup's
+      act = __shfl(act, 0);
+      if (lane == 0) {
+        act_s = act;
+        mat_s = __shfl(mi, 0);
+        I_s = I;
+        J_s = J;
+        p_s = p;
+        sweep_s = sw;
+      }
+    }
+    // the leader's acquire (in jac_wait) came after the waited-for workgroups'
+    // releases; the barrier orders the rest of the workgroup after it
+    __syncthreads();
+    const int act = __builtin_amdgcn_readfirstlane(act_s);
+    const int mi = __builtin_amdgcn_readfirstlane(mat_s);
+    const int I = __builtin_amdgcn_readfirstlane(I_s), J = __builtin_amdgcn_readfirstlane(J_s);
+    const int p = __builtin_amdgcn_readfirstlane(p_s), sw = __builtin_amdgcn_readfirstlane(sweep_s);
+    __syncthreads();
+    if (act == kActExit) break;
+    if (act == kActSkip) continue;
+    JacMat* M = mats + mi;
+    if (act == kActSortPair) {
+      // rows by decreasing norm (the norms the last rounds left), NaN last;
+      // the ranks of all rows are computed from the norms in global memory
+      const int m = M->m;
+      for (int j = tid; j < m; j += NT) {
+        double v = M->nrm2[j];
+        if (!(v >= 0.0 && v <= 1.0e300)) v = -1.0;
+        int rank = 0;
+        for (int i = 0; i < m; ++i) {
+          double w = M->nrm2[i];
+          if (!(w >= 0.0 && w <= 1.0e300)) w = -1.0;
+          rank += (w > v) || (w == v && i < j);
+        }
+        M->rowmap[rank] = j;
+      }
+      if (leader) __hip_atomic_store(&M->rot, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // every wave's stores complete (in L2), then one release by the leader
+      // (its write-back of L2 covers the whole workgroup's rows)
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (leader) __hip_atomic_store(sc.ready + mi, sw, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    jac_pair_body<NT>(M, I, J, mi, p, 0, tol, abs_tol, inner_sweeps, 0, stats, unsplit);
+    // publish the rotated rows and their norms, then count the item: every
+    // wave waits for its stores to complete (they are in L2 then), and the
+    // leader's release (one write-back of L2 to memory) precedes the count
+    // (one add per workgroup: lane 0 of wave 0 adds 1, the other lanes 0)
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (leader) __hip_atomic_fetch_add(sc.done + mi, lane == 0 ? 1 : 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Before a persistent launch: counters cleared, matrices already converged
+// (non-finite input) counted.  One workgroup.
+__global__ void jac_persist_init_kernel(JacMat* __restrict__ mats, JacSched sc) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    *sc.head = 0ull;
+    *sc.abort = 0;
+  }
+  __syncthreads();
+  int local = 0;
+  for (int i = threadIdx.x; i < sc.n; i += blockDim.x) {
+    sc.done[i] = 0;
+    sc.ready[i] = 0;
+    mats[i].rot = 0;
+    local += mats[i].conv != 0;
+  }
+  atomicAdd(&cnt, local);
+  __syncthreads();
+  if (threadIdx.x == 0) *sc.n_conv = cnt;
+}
+
+// After it: a matrix whose last sweep rotated nothing is converged; one that
+// still rotated after max_sweeps is flagged.
+__global__ void jac_persist_finish_kernel(JacMat* __restrict__ mats, int n, uint32_t* status) {
+  int bad = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    JacMat* M = mats + i;
+    if (!M->conv) {
+      if (M->rot == 0) M->conv = 1;
+      else bad = 1;
+    }
+  }
+  if (bad) atomicOr(status, MPS_DEV_NOCONV_SVD);
 }
 
 __global__ void jac_sweep_end_kernel(JacMat* __restrict__ mats, int n_mats, int32_t* unconverged) {
@@ -863,6 +1099,26 @@ hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap,
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_jac_persist(hipStream_t s, JacMat* mats, const JacSched& sc, double tol, double abs_tol,
+                              int inner_sweeps, unsigned long long* stats, int threads, int grid,
+                              uint32_t* status) {
+  if (sc.n <= 0) return hipSuccess;
+  if (sc.nb_cap < 2 || (sc.nb_cap & 1) || grid < 1) return hipErrorInvalidValue;
+  jac_persist_init_kernel<<<1, 256, 0, s>>>(mats, sc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (threads == 512)
+    jac_persist_kernel<512><<<grid, 512, 0, s>>>(mats, sc, tol, abs_tol, inner_sweeps, stats, status);
+  else if (threads == 256)
+    jac_persist_kernel<256><<<grid, 256, 0, s>>>(mats, sc, tol, abs_tol, inner_sweeps, stats, status);
+  else
+    return hipErrorInvalidValue;
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  jac_persist_finish_kernel<<<1, 256, 0, s>>>(mats, sc.n, status);
+  return hipGetLastError();
 }
 
 hipError_t launch_jac_sweep_end(hipStream_t s, JacMat* mats, int n_mats, int32_t* unconverged) {
