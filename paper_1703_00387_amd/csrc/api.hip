@@ -120,6 +120,7 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     sc.abort = (int32_t*)(h->sched + 12);
     sc.done = (int32_t*)(h->sched + 16);
     sc.ready = sc.done + kSchedCap;
+    sc.bdone = (size_t)n * nb <= (size_t)kSchedBlkCap ? sc.ready + kSchedCap : nullptr;
     sc.n = n;
     sc.nb_cap = nb;
     sc.max_sweeps = h->jac_max_sweeps;

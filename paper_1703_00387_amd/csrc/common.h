@@ -259,7 +259,8 @@ hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap,
                             int threads, int split_S = 1, double2* split_part = nullptr, int eig = 0);
 // Capacity of the handle's persistent-Jacobi counters: matrices per launch.
 constexpr int kSchedCap = 65536;
-constexpr size_t kSchedBytes = 16 + 2 * sizeof(int32_t) * (size_t)kSchedCap;
+constexpr int kSchedBlkCap = 1 << 20;   // per-block round counters (matrices x blocks)
+constexpr size_t kSchedBytes = 16 + 2 * sizeof(int32_t) * (size_t)kSchedCap + sizeof(int32_t) * (size_t)kSchedBlkCap;
 // Counters of a persistent Jacobi launch (device memory, cleared by the launch).
 struct JacSched {
   unsigned long long* head;  // next work item
@@ -267,6 +268,7 @@ struct JacSched {
   int32_t* abort;            // set when a wait ran out: every workgroup leaves
   int32_t* done;             // [n] finished pair items per matrix
   int32_t* ready;            // [n] last sweep whose row order is set
+  int32_t* bdone;            // [n][nb_cap] rounds each block has been through (or null)
   int32_t n, nb_cap, max_sweeps, spin_limit;
 };
 // All sweeps of n matrices (at most max_sweeps) in one launch of `grid`

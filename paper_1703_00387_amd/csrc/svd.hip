@@ -579,8 +579,10 @@ __device__ __forceinline__ void jac_pair_body(JacMat* __restrict__ M, int I, int
 // The work items are (sweep s, round r, matrix i, pair slot p), numbered
 //   g = ((s * (nb_cap - 1) + r) * n + i) * (nb_cap / 2) + p
 // and taken in increasing g from a device counter by workgroups that stay
-// resident.  An item needs the previous round of its matrix (round r of
-// matrix i starts when done[i] counts every pair item of its earlier rounds);
+// resident.  Inside a sweep an item needs only the two pairs of the previous
+// round that held its blocks I and J (bdone[i][b] counts the rounds block b
+// of matrix i has been through; without that array, the whole previous round
+// of its matrix: done[i] counts its finished pair items);
 // the first item of a sweep after the first (p = 0, r = 0) waits for the
 // whole previous sweep, decides convergence (no rotation in it) and sorts the
 // rows by norm, and the other items of that round wait for the sort
@@ -624,7 +626,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ mats, JacSched sc, double tol,
                                                          double abs_tol, int inner_sweeps,
                                                          unsigned long long* stats, uint32_t* status) {
-  __shared__ int act_s, mat_s, I_s, J_s, p_s, sweep_s;
+  __shared__ int act_s, mat_s, I_s, J_s, p_s, sweep_s, rg_s;
   const int tid = threadIdx.x, lane = tid & 63;
   // Wave 0 decides, with all its lanes active: the leader test is uniform over
   // a wave (readfirstlane), so the decision is a scalar branch around whole
@@ -648,7 +650,7 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
       const unsigned long long got =
           __hip_atomic_fetch_add(sc.head, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned long long g = __shfl(got, 0);
-      int act = kActExit, mi = 0, I = 0, J = 0, p = 0, sw = 0;
+      int act = kActExit, mi = 0, I = 0, J = 0, p = 0, sw = 0, rg = 0;
       if (g < total && ld_rlx(sc.n_conv) < n && ld_rlx(sc.abort) == 0) {
         p = (int)(g % P);
         unsigned long long q = g / P;
@@ -661,6 +663,8 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
         act = kActSkip;
         if (r < nb - 1 && 2 * p < nb && ld_rlx(&M->conv) == 0) {
           const int per_round = nb / 2, rounds = nb - 1;
+          rg = sw * rounds + r;   // rounds of this matrix before this one
+          jac_pair(nb, r, p, I, J);
           bool ok = true;
           if (sw > 0 && r == 0 && p == 0) {
             // the whole previous sweep, then convergence and the row order
@@ -678,7 +682,14 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
             ok = jac_wait(sc.ready + mi, sw, &M->conv, sc.abort, sc.spin_limit);
             if (ok && ld_rlx(&M->conv) == 0) act = kActPair;
           } else if (r > 0) {
-            ok = jac_wait(sc.done + mi, (sw * rounds + r) * per_round, &M->conv, sc.abort, sc.spin_limit);
+            if (sc.bdone) {
+              // only the two pairs of the previous round that held blocks I and J
+              const int32_t* bd = sc.bdone + (size_t)mi * sc.nb_cap;
+              ok = jac_wait(bd + I, rg, &M->conv, sc.abort, sc.spin_limit) &&
+                   jac_wait(bd + J, rg, &M->conv, sc.abort, sc.spin_limit);
+            } else {
+              ok = jac_wait(sc.done + mi, rg * per_round, &M->conv, sc.abort, sc.spin_limit);
+            }
             if (ok && ld_rlx(&M->conv) == 0) act = kActPair;
           } else {
             act = kActPair;   // round 0 of the first sweep: the rows as prepared
@@ -689,7 +700,6 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
             __hip_atomic_store(sc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             act = kActExit;
           }
-          if (act >= kActPair) jac_pair(nb, r, p, I, J);
         }
       }
       // the lanes agree (same loads of the same words); lane 0's decision is
@@ -702,6 +712,7 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
         J_s = J;
         p_s = p;
         sweep_s = sw;
+        rg_s = rg;
       }
     }
     // the leader's acquire (in jac_wait) came after the waited-for workgroups'
@@ -711,6 +722,7 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
     const int mi = __builtin_amdgcn_readfirstlane(mat_s);
     const int I = __builtin_amdgcn_readfirstlane(I_s), J = __builtin_amdgcn_readfirstlane(J_s);
     const int p = __builtin_amdgcn_readfirstlane(p_s), sw = __builtin_amdgcn_readfirstlane(sweep_s);
+    const int rg = __builtin_amdgcn_readfirstlane(rg_s);
     __syncthreads();
     if (act == kActExit) break;
     if (act == kActSkip) continue;
@@ -744,7 +756,15 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
     // (one add per workgroup: lane 0 of wave 0 adds 1, the other lanes 0)
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (leader) __hip_atomic_fetch_add(sc.done + mi, lane == 0 ? 1 : 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (leader) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (sc.bdone) {
+        int32_t* bd = sc.bdone + (size_t)mi * sc.nb_cap;
+        __hip_atomic_store(bd + I, rg + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(bd + J, rg + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __hip_atomic_fetch_add(sc.done + mi, lane == 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -765,6 +785,8 @@ __global__ void jac_persist_init_kernel(JacMat* __restrict__ mats, JacSched sc) 
     mats[i].rot = 0;
     local += mats[i].conv != 0;
   }
+  if (sc.bdone)
+    for (int i = threadIdx.x; i < sc.n * sc.nb_cap; i += blockDim.x) sc.bdone[i] = 0;
   atomicAdd(&cnt, local);
   __syncthreads();
   if (threadIdx.x == 0) *sc.n_conv = cnt;
