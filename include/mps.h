@@ -24,11 +24,15 @@
  *   Lanczos iteration that did not converge) set bits of a device status word
  *   that mps_device_status() reads; the call still writes a best-effort
  *   result.  No C++ exception and no abort crosses this ABI.
- * - Ownership: the caller owns every input and output buffer.  The handle
- *   owns a device workspace that it grows with hipMalloc when a call needs
- *   more (never while the stream is being captured: reserve first with
- *   mps_reserve); it is freed by mps_destroy.  No pointer passed in is kept
- *   after a call returns.
+ * - Ownership: the caller owns every input and output buffer.  A handle from
+ *   mps_create owns a device workspace that it grows with hipMalloc when a
+ *   call needs more (never while the stream is being captured: reserve first
+ *   with mps_reserve); it is freed by mps_destroy.  A handle from
+ *   mps_create_ws works in the caller's workspace instead and never
+ *   allocates or frees device memory after its creation: a call that needs
+ *   more than the caller gave returns MPS_ERR_CAPACITY (sizes from
+ *   mps_workspace_size or mps_workspace_needed).  No pointer passed in is kept
+ *   after a call returns, except that workspace.
  * - Calls that share one handle must not run concurrently on different
  *   streams: they share the workspace.
  */
@@ -64,11 +68,37 @@ typedef void* mps_stream; /* hipStream_t */
 
 /* Create a handle bound to HIP device `device` (made current).  */
 mps_status mps_create(mps_handle* h, int device);
-/* Free the handle and its workspace (synchronises the device first). */
+/* Create a handle that works in the caller's device workspace
+ * [workspace, workspace + ws_bytes) (256-byte aligned, owned by the caller,
+ * kept until mps_destroy).  The handle's own small buffers (status word,
+ * counters of the persistent Jacobi: about 9 MB) are allocated here; no call
+ * on this handle allocates or frees device memory afterwards.  Column-split
+ * Jacobi rounds keep their partial Grams behind each call's plan, and use
+ * fewer column slices when the workspace leaves less room. */
+mps_status mps_create_ws(mps_handle* h, int device, void* workspace, size_t ws_bytes);
+/* Operations of mps_workspace_size. */
+#define MPS_OP_TRUNCATE 0 /* mps_truncate of a (d chi_max) x (d chi_max) matrix              */
+#define MPS_OP_TEBD     1 /* mps_tebd_step (dense chains, any order) of n_chains chains      */
+#define MPS_OP_HEFF     2 /* mps_heff_apply, two sites, chi_l = chi_r = chi_max, w = w_l,m,r  */
+#define MPS_OP_KRYLOV   3 /* mps_krylov_expm with those operands and n_krylov vectors       */
+#define MPS_OP_TDVP     4 /* mps_tdvp2_step of a chain of L sites, MPO dimension w          */
+/* Device workspace bytes that a call of `op` needs at the given capacities
+ * (host only, no device work): n_chains chains of L sites, local dimension
+ * d, bond capacity chi_max, element type dtype (MPS_C64 or MPS_C128), MPO
+ * dimension w and Krylov vectors n_krylov where they apply.  The figure comes
+ * from the entry point's own planning (run without any work) plus room for
+ * the column split of one large matrix.  0 for arguments the call refuses. */
+size_t mps_workspace_size(int32_t op, int32_t dtype, int32_t n_chains, int32_t L, int32_t d, int32_t chi_max,
+                          int32_t w, int32_t n_krylov);
+/* Largest workspace any call on this handle has planned so far. */
+mps_status mps_workspace_needed(mps_handle h, size_t* bytes);
+/* Free the handle and its workspace (synchronises the device first; a
+ * caller-owned workspace is left to the caller). */
 mps_status mps_destroy(mps_handle h);
 /* Message of the last error returned on this handle ("" if none). */
 const char* mps_last_error(mps_handle h);
-/* Make the workspace at least `bytes` large (hipMalloc happens here). */
+/* Make the workspace at least `bytes` large (hipMalloc happens here; a
+ * caller-owned workspace that is smaller gives MPS_ERR_CAPACITY). */
 mps_status mps_reserve(mps_handle h, size_t bytes);
 /* Synchronise `stream`, return and clear the device status word. */
 mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
@@ -242,6 +272,7 @@ typedef struct {
 #define MPS_FLAG_GRAPH 0x1u     /* capture the whole call in a hipGraph and replay it */
 #define MPS_FLAG_FIXED_SWEEPS 0x2u /* no host synchronisation inside the call */
 #define MPS_FLAG_PLAIN 0x4u     /* one bond per launch sequence (no batching; comparison form) */
+#define MPS_FLAG_CHECKPOINT 0x8u /* mps_tebd_step_ex: keep every step's chains for mps_tebd_step_vjp */
 
 /*
  * n_steps time steps of Trotter evolution on every chain.
@@ -266,6 +297,34 @@ typedef struct {
 mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
                          int32_t n_chains, int32_t order, double dt, int32_t n_steps,
                          double eps_local, uint32_t flags);
+
+/*
+ * mps_tebd_step with the record the adjoint and the error analysis need
+ * (Sec. "Time evolution methods"; the discarded weight of Sec. "Basic
+ * concepts in tensor network techniques", Eq. elocal).
+ *   flags       : as mps_tebd_step, plus MPS_FLAG_CHECKPOINT: before every
+ *                 step and after the last, every chain (B, lam, chi) is
+ *                 copied into ckpt_arena; complex128 chains only, not with
+ *                 MPS_FLAG_GRAPH.  mps_tebd_step_vjp reads the arena.
+ *   ckpt_arena  : device, at least mps_tebd_ckpt_bytes(chains, n_chains,
+ *                 n_steps) bytes, owned by the caller (NULL without the flag)
+ *   disc_log_dev: device FP64 [n_steps][n_layers][n_chains][L_max-1] or NULL,
+ *                 n_layers = 3 (order 2), 15 (order 4), 2 (L_max-1) (order
+ *                 0); entry (step, layer, c, b) receives the discarded weight
+ *                 of the update of bond b of chain c in that layer.  Entries
+ *                 of bonds a layer does not update are not written (clear the
+ *                 log first).  Works with MPS_FLAG_GRAPH (the replayed step
+ *                 reads its index from a device counter).
+ * Errors: as mps_tebd_step; MPS_ERR_INVALID for MPS_FLAG_CHECKPOINT without
+ * an arena or with MPS_FLAG_GRAPH; MPS_ERR_CAPACITY for a short arena;
+ * MPS_ERR_UNSUPPORTED for MPS_FLAG_CHECKPOINT on complex64 chains.
+ */
+mps_status mps_tebd_step_ex(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
+                            int32_t order, double dt, int32_t n_steps, double eps_local, uint32_t flags,
+                            void* ckpt_arena, size_t ckpt_bytes, double* disc_log_dev);
+/* Bytes of the checkpoint arena of mps_tebd_step_ex for these chains and
+ * n_steps (host only; 0 for bad arguments). */
+size_t mps_tebd_ckpt_bytes(const mps_chain_desc* chains, int32_t n_chains, int32_t n_steps);
 
 /*
  * Charges of a symmetric chain (App. "Convenient features", symmetry
@@ -554,6 +613,32 @@ mps_status mps_tebd_vjp(mps_handle h, mps_stream stream, const mps_chain_desc* c
 mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0, double dt,
                          int32_t n_steps, double eps_local, double eta, const void* op1, int32_t site,
                          const void* op2, void* arena, size_t arena_bytes, double* loss_dev, double* dJ_dev);
+/*
+ * The vector-Jacobian product of a batched TEBD2 run recorded by
+ * mps_tebd_step_ex with MPS_FLAG_CHECKPOINT (order 2), for any cotangent of
+ * the final states: with dL = sum_c Re <dB_final[c], dB_c> + <dLam_final[c],
+ * dlam_c> (the cotangent of a complex entry x is dL/dRe x + i dL/dIm x),
+ * dJ_dev[c][b] receives dL/dJ_b of chain c, where that chain's bond terms
+ * are h_b = J_b h0[c][b].  The reverse pass is the one of mps_tebd_grad
+ * (truncated-SVD backward with the kept/discarded coupling and a Lorentzian
+ * broadening eta), run chain by chain on the chain's arena block.
+ *   chains      : the chains of the forward call, holding their final states
+ *                 (left so on return)
+ *   h0          : HOST array of n_chains device pointers, complex128
+ *                 [L-1][d^2][d^2] unit bond terms
+ *   ckpt_arena  : the forward's arena (its scratch parts are overwritten)
+ *   dB_final    : HOST array of device pointers, complex128 in the layout of B
+ *   dLam_final  : HOST array of device pointers, FP64 in the layout of lam
+ *   dJ_dev      : device FP64 [n_chains][L_max-1], overwritten (entries past
+ *                 a chain's L-1 are 0)
+ * Synchronises `stream`.  Errors: MPS_ERR_INVALID for an arena not written by
+ * an order-2 mps_tebd_step_ex for the same chains, null pointers or eta < 0;
+ * MPS_ERR_CAPACITY for a short arena or d*chi_max > 2560.
+ */
+mps_status mps_tebd_step_vjp(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
+                             const void* const* h0, void* ckpt_arena, size_t ckpt_bytes,
+                             const void* const* dB_final, const double* const* dLam_final, double* dJ_dev,
+                             double eta);
 
 #ifdef __cplusplus
 }

@@ -87,13 +87,12 @@ def torch_gate(e, V, Jb, tau):
     return (V * ph[None, :]) @ V.conj().transpose(0, 1)
 
 
-def tebd2_loss_torch(spec, J: torch.Tensor, dt: float, n_steps: int, chi_max: int, eps: float,
-                     eta: float = 1e-12, site=None, method="tebd2"):
-    """Loss <S^z_site>(T) + sum_b <S^z_b S^z_{b+1}>(T) of the truncated TEBD
-    run, as a differentiable function of the per-bond couplings J."""
+def tebd2_state_torch(spec, J: torch.Tensor, dt: float, n_steps: int, chi_max: int, eps: float,
+                      eta: float = 1e-12, method="tebd2"):
+    """The final Hastings-form state (B, lam lists of tensors) of the truncated
+    TEBD run, as a differentiable function of the per-bond couplings J."""
     from workloads import initial_vectors
     L, d = spec.L, spec.d
-    site = L // 2 - 1 if site is None else site
     psi0 = omps.product_mps(initial_vectors(spec))
     B = [torch.tensor(x) for x in psi0.B]
     lam = [torch.tensor(x) for x in psi0.lam]
@@ -115,6 +114,23 @@ def tebd2_loss_torch(spec, J: torch.Tensor, dt: float, n_steps: int, chi_max: in
                 lam[b + 1] = s / nk
                 B[b + 1] = Vh.reshape(k, d, chr_)
                 B[b] = (thp.reshape(chl * d, d * chr_) @ Vh.conj().transpose(0, 1) / nk).reshape(chl, d, k)
+    return B, lam
+
+
+def site_expect_torch(B, lam, op: np.ndarray, i: int):
+    """<op at site i> = sum_a lam_i[a]^2 <B_i[a]| op |B_i[a]> of a Hastings-form state."""
+    Bi = B[i]
+    l2 = (lam[i] ** 2).to(Bi.dtype)
+    return torch.real(torch.einsum("a,asc,st,atc->", l2, Bi.conj(), torch.tensor(op), Bi))
+
+
+def tebd2_loss_torch(spec, J: torch.Tensor, dt: float, n_steps: int, chi_max: int, eps: float,
+                     eta: float = 1e-12, site=None, method="tebd2"):
+    """Loss <S^z_site>(T) + sum_b <S^z_b S^z_{b+1}>(T) of the truncated TEBD
+    run, as a differentiable function of the per-bond couplings J."""
+    L, d = spec.L, spec.d
+    site = L // 2 - 1 if site is None else site
+    B, lam = tebd2_state_torch(spec, J, dt, n_steps, chi_max, eps, eta, method)
     sz = torch.tensor(0.5 * models.SZ)
     Bi = B[site]
     l2 = (lam[site] ** 2).to(Bi.dtype)

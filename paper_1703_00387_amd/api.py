@@ -32,18 +32,40 @@ def _check_device_matrix(theta):
         raise ValueError(f"theta must be in device memory, not on {theta.device}")
 
 
-class Handle:
-    """An mps_handle on one device (owns the library workspace)."""
+def workspace_size(op: int, dtype: str = "c128", n_chains: int = 1, L: int = 2, d: int = 2, chi_max: int = 1,
+                   w: int = 0, n_krylov: int = 0) -> int:
+    """mps_workspace_size: device workspace bytes a call of `op` (MPS_OP_*) needs (host only)."""
+    code = _lib.MPS_C128 if dtype == "c128" else _lib.MPS_C64
+    return int(lib().mps_workspace_size(op, code, n_chains, L, d, chi_max, w, n_krylov))
 
-    def __init__(self, device: int = 0):
+
+class Handle:
+    """An mps_handle on one device.  With `workspace` (a uint8 device tensor,
+    kept alive by the handle) the library works in that memory and never
+    allocates after creation (mps_create_ws); otherwise it owns a growable
+    workspace."""
+
+    def __init__(self, device: int = 0, workspace: Optional[torch.Tensor] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("libmps needs a HIP device")
         self.device = device
+        self.workspace = workspace
         h = C.c_void_p()
-        code = lib().mps_create(C.byref(h), device)
+        if workspace is not None:
+            if workspace.device.type != "cuda" or not workspace.is_contiguous() or workspace.data_ptr() % 256:
+                raise ValueError("workspace must be a contiguous, 256-byte aligned device tensor")
+            code = lib().mps_create_ws(C.byref(h), device, C.c_void_p(workspace.data_ptr()),
+                                       workspace.numel() * workspace.element_size())
+        else:
+            code = lib().mps_create(C.byref(h), device)
         if code != 0:
             raise _lib.MPSError(code, "mps_create failed")
         self.h = h
+
+    def workspace_needed(self) -> int:
+        n = C.c_size_t(0)
+        self.check(lib().mps_workspace_needed(self.h, C.byref(n)))
+        return int(n.value)
 
     def close(self):
         if self.h:
@@ -188,6 +210,57 @@ def tebd_step(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_steps
               flags: int = 0):
     arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
     h.check(lib().mps_tebd_step(h.h, _stream(), arr, len(chains), order, float(dt), n_steps, float(eps), flags))
+
+
+def tebd_ckpt_bytes(chains: Sequence[Chain], n_steps: int) -> int:
+    """mps_tebd_ckpt_bytes: bytes of the checkpoint arena of tebd_step_ex."""
+    arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
+    return int(lib().mps_tebd_ckpt_bytes(arr, len(chains), n_steps))
+
+
+def tebd_step_ex(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_steps: int, eps: float,
+                 flags: int = 0, ckpt: Optional[torch.Tensor] = None, disc_log: Optional[torch.Tensor] = None):
+    """mps_tebd_step_ex: tebd_step with an optional checkpoint arena (uint8 device
+    tensor, with flags | MPS_FLAG_CHECKPOINT) and an optional float64 device log
+    [n_steps][n_layers][n_chains][L_max-1] of every update's discarded weight."""
+    if disc_log is not None:
+        l_max = max(c.L for c in chains)
+        n_layers = {2: 3, 4: 15, 0: 2 * (l_max - 1)}.get(order, 0)
+        if (disc_log.dtype != torch.float64 or not disc_log.is_contiguous() or disc_log.device.type != "cuda"
+                or disc_log.numel() < n_steps * n_layers * len(chains) * (l_max - 1)):
+            raise ValueError("disc_log must be a contiguous float64 device tensor of "
+                             "n_steps * n_layers * n_chains * (L_max - 1) entries")
+    if ckpt is not None and (ckpt.device.type != "cuda" or not ckpt.is_contiguous()):
+        raise ValueError("ckpt must be a contiguous device tensor")
+    arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
+    nbytes = ckpt.numel() * ckpt.element_size() if ckpt is not None else 0
+    h.check(lib().mps_tebd_step_ex(h.h, _stream(), arr, len(chains), order, float(dt), n_steps, float(eps), flags,
+                                   _ptr(ckpt), nbytes, _ptr(disc_log)))
+
+
+def tebd_step_vjp(h: Handle, chains: Sequence[Chain], h0: Sequence[torch.Tensor], ckpt: torch.Tensor,
+                  dB: Sequence[torch.Tensor], dlam: Sequence[torch.Tensor], eta: float = 1e-12) -> torch.Tensor:
+    """mps_tebd_step_vjp: dL/dJ [n_chains, L_max-1] for state cotangents dB
+    (complex128, the layout of each chain's B) and dlam (float64, of lam) of a
+    TEBD2 run recorded by tebd_step_ex with MPS_FLAG_CHECKPOINT."""
+    n = len(chains)
+    if not (len(h0) == len(dB) == len(dlam) == n):
+        raise ValueError("one h0, dB and dlam per chain")
+    for c, hh, b, l in zip(chains, h0, dB, dlam):
+        if b.shape != c.B.shape or b.dtype != torch.complex128 or not b.is_contiguous():
+            raise ValueError("dB must be complex128 in the layout of the chain's B")
+        if l.shape != c.lam.shape or l.dtype != torch.float64 or not l.is_contiguous():
+            raise ValueError("dlam must be float64 in the layout of the chain's lam")
+        if hh.dtype != torch.complex128 or not hh.is_contiguous():
+            raise ValueError("h0 must be contiguous complex128")
+    l_max = max(c.L for c in chains)
+    dJ = torch.zeros((n, l_max - 1), dtype=torch.float64, device=chains[0].B.device)
+    arr = (ChainDesc * n)(*[c.desc() for c in chains])
+    P = C.c_void_p * n
+    h.check(lib().mps_tebd_step_vjp(h.h, _stream(), arr, n, P(*[hh.data_ptr() for hh in h0]), _ptr(ckpt),
+                                    ckpt.numel() * ckpt.element_size(), P(*[b.data_ptr() for b in dB]),
+                                    P(*[l.data_ptr() for l in dlam]), _ptr(dJ), float(eta)))
+    return dJ
 
 
 @dataclass

@@ -93,13 +93,19 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
   // 2560 x 2560 SVD (40 pairs) took 1.19 s unsplit and 0.47 s with S = 6.
   const bool few = pairs < h->jac_split_below || (pairs < 128 && m_cap >= 1024);
   double2* split_part = h->split_part;
+  if (!split_buf && h->ws_external) {
+    // a caller-owned workspace: the partial Grams go behind the call's plan
+    const size_t off = (h->ws_call + 255) & ~size_t(255);
+    split_buf = (double2*)(h->ws + std::min(off, h->ws_bytes));
+    split_buf_bytes = off < h->ws_bytes ? h->ws_bytes - off : 0;
+  }
   if (!fixed && allow_split && h->jac_split_below > 0 && few) {
     S = std::max(1, std::min(std::min(16, 256 / std::max(pairs, 1)), std::max(1, m_cap / 64)));
     const size_t per_slice = (size_t)n * (nb_cap / 2) * 64 * 64 * sizeof(double2);
     if (split_buf) {
       // a caller-provided buffer: as many slices as it holds, no allocation
       S = std::max(1, std::min<int>(S, (int)(split_buf_bytes / per_slice)));
-      split_part = split_buf;
+      split_part = S > 1 ? split_buf : nullptr;
     }
     const size_t need = per_slice * S;
     if (!split_buf && S > 1 && need > h->split_bytes) {
@@ -190,7 +196,14 @@ mps_status mps_fail(mps_handle h, mps_status code, const std::string& msg) {
 }
 
 mps_status mps_ensure_ws(mps_handle h, size_t bytes) {
+  h->ws_needed = std::max(h->ws_needed, bytes);
+  if (h->plan_only) return mps_fail(h, MPS_ERR_UNSUPPORTED, "planning only");
+  h->ws_call = bytes;
   if (bytes <= h->ws_bytes) return MPS_OK;
+  if (h->ws_external)
+    return mps_fail(h, MPS_ERR_CAPACITY, "the caller's workspace holds " + std::to_string(h->ws_bytes) +
+                                             " bytes, this call needs " + std::to_string(bytes) +
+                                             " (mps_workspace_size)");
   size_t want = std::max(bytes, h->ws_bytes + h->ws_bytes / 4);
   if (h->ws) {
     MPS_TRY_HIP(h, hipDeviceSynchronize());
@@ -340,6 +353,90 @@ mps_status mps_create(mps_handle* out, int device) {
   return MPS_OK;
 }
 
+mps_status mps_create_ws(mps_handle* out, int device, void* workspace, size_t ws_bytes) {
+  if (!out) return MPS_ERR_INVALID;
+  *out = nullptr;
+  if (!workspace && ws_bytes > 0) return MPS_ERR_INVALID;
+  mps_status st = mps_create(out, device);
+  if (st != MPS_OK) return st;
+  (*out)->ws = (char*)workspace;
+  (*out)->ws_bytes = ws_bytes;
+  (*out)->ws_external = true;
+  return MPS_OK;
+}
+
+size_t mps_workspace_size(int32_t op, int32_t dtype, int32_t n_chains, int32_t L, int32_t d, int32_t chi_max,
+                          int32_t w, int32_t n_krylov) {
+  // A planning handle: every entry point checks its arguments and plans its
+  // workspace as for a real call, then stops before any work.
+  // The pointers below are never dereferenced.
+  mps_context ctx;
+  ctx.plan_only = true;
+  void* fake = (void*)(uintptr_t)0x1000;
+  double* fd = (double*)fake;
+  int32_t* fi = (int32_t*)fake;
+  if (dtype != MPS_C64 && dtype != MPS_C128) return 0;
+  if (n_chains < 1 || L < 2 || d < 1 || chi_max < 1) return 0;
+  const int64_t m = (int64_t)d * chi_max;
+  switch (op) {
+    case MPS_OP_TRUNCATE:
+      mps_truncate(&ctx, nullptr, fake, m, m, chi_max, 0.0, fake, fd, fake, fi, fd, fd);
+      break;
+    case MPS_OP_TEBD: {
+      std::vector<mps_chain_desc> cs((size_t)n_chains);
+      for (auto& c : cs) {
+        c.L = L;
+        c.d = d;
+        c.chi_max = chi_max;
+        c.dtype = dtype;
+        c.B = fake;
+        c.lam = fd;
+        c.chi = fi;
+        c.hbond = fake;
+        c.disc = fd;
+      }
+      mps_tebd_step(&ctx, nullptr, cs.data(), n_chains, 4, 0.05, 1, 1e-12, 0);
+      break;
+    }
+    case MPS_OP_HEFF:
+      if (w < 1) return 0;
+      mps_heff_apply(&ctx, nullptr, dtype, fake, fake, fake, fake, fake, fake, chi_max, d, d, chi_max, w, w, w);
+      break;
+    case MPS_OP_KRYLOV:
+      if (w < 1 || n_krylov < 1) return 0;
+      mps_krylov_expm(&ctx, nullptr, dtype, fake, fake, fake, fake, fake, chi_max, d, d, chi_max, w, w, w, 0.01, 0.0,
+                      n_krylov, 1e-10, fi, fd);
+      break;
+    case MPS_OP_TDVP: {
+      if (w < 1 || n_krylov < 1) return 0;
+      mps_oc_chain c;
+      std::memset(&c, 0, sizeof(c));
+      c.L = L;
+      c.d = d;
+      c.chi_max = chi_max;
+      c.dtype = dtype;
+      c.w = w;
+      c.M = fake;
+      c.chi = fi;
+      c.W = fake;
+      mps_tdvp2_step(&ctx, nullptr, &c, 0.02, 1, 1e-12, n_krylov, 1e-10, fd, fi);
+      break;
+    }
+    default:
+      return 0;
+  }
+  if (ctx.ws_needed == 0) return 0;   // the arguments were refused
+  // room behind the plan for the partial Grams of column-split Jacobi rounds
+  // (at most 256 pair slices of 64 x 64 complex128)
+  return ((ctx.ws_needed + 255) & ~size_t(255)) + (size_t)256 * 64 * 64 * sizeof(double2);
+}
+
+mps_status mps_workspace_needed(mps_handle h, size_t* bytes) {
+  if (!h || !bytes) return MPS_ERR_INVALID;
+  *bytes = h->ws_needed;
+  return MPS_OK;
+}
+
 mps_status mps_destroy(mps_handle h) {
   if (!h) return MPS_ERR_INVALID;
   hipSetDevice(h->device);
@@ -347,7 +444,7 @@ mps_status mps_destroy(mps_handle h) {
   for (auto e : h->ev_pool) hipEventDestroy(e);
   for (auto e : h->aux_ev) hipEventDestroy(e);
   for (auto st : h->aux) hipStreamDestroy(st);
-  if (h->ws) hipFree(h->ws);
+  if (h->ws && !h->ws_external) hipFree(h->ws);
   if (h->split_part) hipFree(h->split_part);
   if (h->status_dev) hipFree(h->status_dev);
   if (h->sched) hipFree(h->sched);
@@ -524,6 +621,13 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
   return tebd_impl(h, stream, chains, n_chains, order, dt, n_steps, eps_local, flags, 0, 1 << 30);
 }
 
+mps_status mps_tebd_step_ex(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
+                            int32_t order, double dt, int32_t n_steps, double eps_local, uint32_t flags,
+                            void* ckpt_arena, size_t ckpt_bytes, double* disc_log_dev) {
+  return tebd_impl(h, stream, chains, n_chains, order, dt, n_steps, eps_local, flags, 0, 1 << 30, nullptr, nullptr,
+                   ckpt_arena, ckpt_bytes, disc_log_dev);
+}
+
 mps_status mps_ktebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
                           double dt, int32_t n_steps, double eps_local, int32_t n_max, double tol, uint32_t flags,
                           int32_t* n_used_dev) {
@@ -560,7 +664,7 @@ mps_status mps_tebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_des
 // (all of them for the public entry point).
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
                      double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi,
-                     const KryOpts* kry, const mps_u1_chain* u1) {
+                     const KryOpts* kry, const mps_u1_chain* u1, void* ckpt, size_t ckpt_bytes, double* disc_log) {
   if (!h) return MPS_ERR_INVALID;
   if (!chains || n_chains < 1) return mps_fail(h, MPS_ERR_INVALID, "need at least one chain");
   if (order != 0 && order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 0, 2 or 4");
@@ -571,9 +675,20 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   }
   if (n_steps < 0) return mps_fail(h, MPS_ERR_INVALID, "n_steps < 0");
   if (!(dt == dt) || !(eps_local == eps_local)) return mps_fail(h, MPS_ERR_INVALID, "NaN argument");
-  if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS | MPS_FLAG_PLAIN))
+  if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS | MPS_FLAG_PLAIN | MPS_FLAG_CHECKPOINT))
     return mps_fail(h, MPS_ERR_INVALID, "unknown flag");
   const bool plain = flags & MPS_FLAG_PLAIN;
+  const bool checkpoint = flags & MPS_FLAG_CHECKPOINT;
+  if (checkpoint) {
+    if (!ckpt) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_CHECKPOINT needs an arena");
+    if (flags & MPS_FLAG_GRAPH) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_CHECKPOINT excludes MPS_FLAG_GRAPH");
+    if (u1 || kry) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_CHECKPOINT is for dense gate TEBD");
+    for (int c = 0; c < n_chains; ++c)
+      if (chains[c].dtype != MPS_C128) return mps_fail(h, MPS_ERR_UNSUPPORTED, "checkpoints need complex128 chains");
+    if (n_steps > 0 && ckpt_bytes < mps_tebd_ckpt_bytes(chains, n_chains, n_steps))
+      return mps_fail(h, MPS_ERR_CAPACITY, "arena smaller than mps_tebd_ckpt_bytes()");
+  }
+  if (disc_log && (u1 || kry)) return mps_fail(h, MPS_ERR_INVALID, "the discarded-weight log is for dense gate TEBD");
   if (u1) {
     if (flags & MPS_FLAG_GRAPH) return mps_fail(h, MPS_ERR_INVALID, "charge-carrying chains cannot be captured");
     for (int c = 0; c < n_chains; ++c)
@@ -762,7 +877,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
           it.b = b;
           it.d = ch.d;
           it.chi_max = ch.chi_max;
-          it.pad = 0;
+          it.pad = c * (l_max - 1) + b;   // the update's offset in a layer's log slice
           items.push_back(it);
           item_chain.push_back(c);
         }
@@ -787,6 +902,30 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   double* s2 = (double*)(ws + oS2);
   int32_t* unconv = (int32_t*)(ws + oUnc);
   const int nb_cap = jac_nb(m_cap);
+  // device step counter of the discarded-weight log (bytes 192.. of the status block)
+  int32_t* log_step = (int32_t*)((char*)h->status_dev + 192);
+  if (disc_log) MPS_TRY_HIP(h, launch_set_int(s, log_step, 0));
+  if (checkpoint) {
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    hd.magic = kCkptMagic;
+    hd.n_chains = n_chains;
+    hd.n_steps = n_steps;
+    hd.order = order;
+    hd.dt = dt;
+    hd.eps_local = eps_local;
+    hd.shape_sum = ckpt_shape_sum(chains, n_chains);
+    MPS_TRY_HIP(h, hipMemcpyAsync(ckpt, &hd, sizeof(hd), hipMemcpyHostToDevice, s));
+    MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  }
+  auto save_all = [&](int stp) -> mps_status {
+    for (int c = 0; c < n_chains; ++c) {
+      mps_status r = grad_ckpt_save(h, s, chains[c], (char*)ckpt + ckpt_block_offset(chains, c, n_steps), n_steps,
+                                    stp);
+      if (r != MPS_OK) return r;
+    }
+    return MPS_OK;
+  };
 
   auto run_step = [&]() -> mps_status {
     for (int li = 0; li < (int)layers.size(); ++li) {
@@ -841,7 +980,14 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       MPS_TRY_HIP(h, launch_select(s, mats, n, perm, s2, m_cap, chi_cap, count_rule_eps(h, eps_local), sel));
       if (prof) prof_end(h, s, MPS_K_SELECT);
       if (prof) prof_begin(h, s, MPS_K_WB_RIGHT);
-      MPS_TRY_HIP(h, launch_wb_right(s, it, n, mats, perm, s2, m_cap, sel, chi_eff, d, c128));
+      DiscLog lg;
+      if (disc_log) {
+        lg.log = disc_log;
+        lg.step = log_step;
+        lg.step_stride = (long long)layers.size() * n_chains * (l_max - 1);
+        lg.layer_off = (long long)li * n_chains * (l_max - 1);
+      }
+      MPS_TRY_HIP(h, launch_wb_right(s, it, n, mats, perm, s2, m_cap, sel, chi_eff, d, c128, lg));
       if (prof) prof_end(h, s, MPS_K_WB_RIGHT);
       }
       MPS_TRY_HIP(h, launch_wb_left_probs(s, it, n, sel, probs));
@@ -854,14 +1000,17 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       }
       }
     }
+    if (disc_log) MPS_TRY_HIP(h, launch_inc_int(s, log_step));
     return MPS_OK;
   };
 
   if (!graph) {
     for (int stp = 0; stp < n_steps; ++stp) {
+      if (checkpoint && (st = save_all(stp)) != MPS_OK) return st;
       st = run_step();
       if (st != MPS_OK) return st;
     }
+    if (checkpoint && (st = save_all(n_steps)) != MPS_OK) return st;
     return MPS_OK;
   }
   hipGraph_t g = nullptr;

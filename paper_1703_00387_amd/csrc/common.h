@@ -28,8 +28,12 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 struct mps_context {
   int device = 0;
-  char* ws = nullptr;          // device workspace owned by the handle
+  char* ws = nullptr;          // device workspace (the handle's, or the caller's)
   size_t ws_bytes = 0;
+  bool ws_external = false;    // caller-owned workspace: never grown, never freed here
+  size_t ws_call = 0;          // bytes the running call planned (the rest may hold split partials)
+  size_t ws_needed = 0;        // largest plan seen on this handle
+  bool plan_only = false;      // mps_workspace_size: entry points stop after planning
   uint32_t* status_dev = nullptr;  // device status word (MPS_DEV_* bits)
   std::string err;
   double jac_tol = 1e-13;      // relative orthogonality tolerance of the Jacobi SVD
@@ -88,9 +92,27 @@ inline double count_rule_eps(mps_handle h, double eps) { return eps >= 0.0 && ep
 // TEBD driver with a layer window (api.hip); kry != null propagates every
 // bond of the sweep (order 0) with the local Lanczos exponential of h_b
 // u1 != null: charge-carrying chains, every update truncated on its charge blocks
+// ckpt (MPS_FLAG_CHECKPOINT): the checkpoint arena of mps_tebd_step_ex;
+// disc_log: its per-update discarded-weight log (both optional)
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
                      double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi,
-                     const KryOpts* kry = nullptr, const mps_u1_chain* u1 = nullptr);
+                     const KryOpts* kry = nullptr, const mps_u1_chain* u1 = nullptr, void* ckpt = nullptr,
+                     size_t ckpt_bytes = 0, double* disc_log = nullptr);
+
+// Checkpoint arena of mps_tebd_step_ex: a header, then for every chain the
+// block of the adjoint (mps_tebd_grad_arena_bytes of that chain), 256-byte
+// aligned, whose step checkpoints grad_ckpt_save writes.
+struct CkptHeader {
+  uint32_t magic;          // kCkptMagic
+  int32_t n_chains, n_steps, order;
+  double dt, eps_local;
+  int64_t shape_sum;       // sum over chains of (L, d, chi_max) mixed: a check that the chains are the same
+};
+constexpr uint32_t kCkptMagic = 0x4d50534bu;
+constexpr size_t kCkptHeader = 256;
+int64_t ckpt_shape_sum(const mps_chain_desc* chains, int n_chains);
+size_t ckpt_block_offset(const mps_chain_desc* chains, int c, int n_steps);
+mps_status grad_ckpt_save(mps_handle h, hipStream_t s, const mps_chain_desc& ch, char* block, int n_steps, int st);
 
 // Charge-carrying chains (u1.hip): the truncation of one layer of n bond
 // items (theta' in their X slots) on the charge blocks of every bond, in place
@@ -126,6 +148,10 @@ mps_status prof_harvest(mps_handle h, hipStream_t s);
   } while (0)
 
 mps_status mps_fail(mps_handle h, mps_status code, const std::string& msg);
+// Make the workspace hold `bytes` for the running call.  A handle with a
+// caller-owned workspace refuses a larger plan (MPS_ERR_CAPACITY); a
+// planning handle records the size and returns MPS_ERR_UNSUPPORTED, which
+// the entry points pass up before they queue any work.
 mps_status mps_ensure_ws(mps_handle h, size_t bytes);
 
 #define MPS_TRY_HIP(h, call)                                                         \
@@ -175,7 +201,7 @@ struct BondItem {
   double2* X;            // workspace: theta' complex128 [(d chi_max)^2]
   void* T;               // workspace: theta~' [(d chi_max)^2]
   void* Vh;              // workspace: kept V^dag rows [chi_max][d chi_max]
-  int32_t b, d, chi_max, pad;
+  int32_t b, d, chi_max, pad;   // pad: the item's offset in a discarded-weight log slice
 };
 
 // One Krylov-TEBD bond update's propagator job (ktebd.hip).
@@ -283,9 +309,19 @@ hipError_t launch_jac_max_nb(hipStream_t s, const JacMat* mats, int n_mats, int3
 hipError_t launch_layer_dims(hipStream_t s, const BondItem* items, int n_items, int32_t* out);
 hipError_t launch_select(hipStream_t s, JacMat* mats, int n_mats, int32_t* perm_ws, double* s2_ws,
                          int m_cap, int kmax_const, double eps, SelOut* out);
+// Per-update discarded-weight log of mps_tebd_step_ex: the entry of an item
+// is log[step * step_stride + layer_off + item.pad] with the step read from
+// a device counter (so a captured step logs into its replay's slice).
+struct DiscLog {
+  double* log = nullptr;
+  const int32_t* step = nullptr;
+  long long step_stride = 0, layer_off = 0;
+};
 hipError_t launch_wb_right(hipStream_t s, const BondItem* items, int n_items, const JacMat* mats,
                            const int32_t* perm_ws, const double* s2_ws, int m_cap, const SelOut* sel,
-                           int chi_cap, int d, bool c128);
+                           int chi_cap, int d, bool c128, const DiscLog& lg = DiscLog());
+hipError_t launch_set_int(hipStream_t s, int32_t* p, int v);
+hipError_t launch_inc_int(hipStream_t s, int32_t* p);
 hipError_t launch_wb_left_probs(hipStream_t s, const BondItem* items, int n_items, const SelOut* sel,
                                 GemmProb* probs);
 hipError_t launch_gemm_bt_conj(hipStream_t s, const GemmProb* probs, int n_probs, int M_cap, int N_cap, bool c128,

@@ -405,24 +405,68 @@ extern "C" size_t mps_tebd_grad_arena_bytes(int32_t L, int32_t d, int32_t chi_ma
   return GradArena(L, d, chi_max, n_steps).total;
 }
 
+int64_t ckpt_shape_sum(const mps_chain_desc* chains, int n_chains) {
+  int64_t t = 0;
+  for (int c = 0; c < n_chains; ++c)
+    t += (int64_t)(c + 1) * (chains[c].L * 1000003LL + chains[c].d * 1009LL + chains[c].chi_max);
+  return t;
+}
+
+size_t ckpt_block_offset(const mps_chain_desc* chains, int c, int n_steps) {
+  size_t off = kCkptHeader;
+  for (int i = 0; i < c; ++i)
+    off += (GradArena(chains[i].L, chains[i].d, chains[i].chi_max, n_steps).total + 255) & ~size_t(255);
+  return off;
+}
+
+extern "C" size_t mps_tebd_ckpt_bytes(const mps_chain_desc* chains, int32_t n_chains, int32_t n_steps) {
+  if (!chains || n_chains < 1 || n_steps < 1) return 0;
+  for (int c = 0; c < n_chains; ++c)
+    if (chains[c].L < 2 || chains[c].d < 1 || chains[c].chi_max < 1) return 0;
+  return ckpt_block_offset(chains, n_chains, n_steps);
+}
+
+// Checkpoint of step `st` of a chain into its adjoint arena block (the same
+// layout the adjoint's own forward writes): B, lam and chi copied device to
+// device on `s`.
+mps_status grad_ckpt_save(mps_handle h, hipStream_t s, const mps_chain_desc& ch, char* block, int n_steps, int st) {
+  const GradArena A(ch.L, ch.d, ch.chi_max, n_steps);
+  double2* B;
+  double* lam;
+  int32_t* chi;
+  A.ptrs(block + A.oCk + (size_t)st * A.snap, B, lam, chi);
+  MPS_TRY_HIP(h, hipMemcpyAsync(B, ch.B, A.snapB, hipMemcpyDeviceToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(lam, ch.lam, A.snapL, hipMemcpyDeviceToDevice, s));
+  MPS_TRY_HIP(h, hipMemcpyAsync(chi, ch.chi, A.snapC, hipMemcpyDeviceToDevice, s));
+  return MPS_OK;
+}
+
 // The adjoint of a TEBD2 run for the weighted loss
 //   sum_i w1[i] <op1 at i> + sum_b w2[b] <op2 on bond b>   (host weights);
 // obs_dev (optional) receives the 2L-1 final observables, loss_dev (optional)
 // the loss, dJ_dev the gradient.
+// With dB_seed and dLam_seed (device; the chain's B and lam layouts) the
+// forward is not run: the arena already holds its checkpoints (written by
+// mps_tebd_step_ex with MPS_CHECKPOINT), the chain holds the final state, and
+// the reverse pass starts from these state cotangents instead of the loss.
 static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0,
                                  double dt, int32_t n_steps, double eps_local, double eta, const void* op1,
                                  const double* w1, const void* op2, const double* w2, void* arena_ptr,
-                                 size_t arena_bytes, double* obs_dev, double* loss_dev, double* dJ_dev) {
+                                 size_t arena_bytes, double* obs_dev, double* loss_dev, double* dJ_dev,
+                                 const void* dB_seed = nullptr, const double* dLam_seed = nullptr) {
   if (!h) return MPS_ERR_INVALID;
-  if (!chain || !h0 || !op1 || !op2 || !w1 || !w2 || !dJ_dev || !arena_ptr)
+  const bool seeded = dB_seed != nullptr;
+  if (seeded && !dLam_seed) return mps_fail(h, MPS_ERR_INVALID, "null lambda cotangent");
+  if (!chain || !h0 || (!seeded && (!op1 || !op2 || !w1 || !w2)) || !dJ_dev || !arena_ptr)
     return mps_fail(h, MPS_ERR_INVALID, "null pointer");
   const mps_chain_desc ch = *chain;
   if (ch.dtype != MPS_C128) return mps_fail(h, MPS_ERR_UNSUPPORTED, "the gradient needs a complex128 chain");
   if (ch.L < 2 || ch.d < 1 || ch.d > 5 || ch.chi_max < 1) return mps_fail(h, MPS_ERR_SHAPE, "bad chain shape");
   if ((int64_t)ch.d * ch.chi_max > 2560) return mps_fail(h, MPS_ERR_CAPACITY, "d*chi_max is limited to 2560");
-  for (int i = 0; i < ch.L; ++i)
-    if (!std::isfinite(w1[i]) || (i + 1 < ch.L && !std::isfinite(w2[i])))
-      return mps_fail(h, MPS_ERR_INVALID, "non-finite loss weight");
+  if (!seeded)
+    for (int i = 0; i < ch.L; ++i)
+      if (!std::isfinite(w1[i]) || (i + 1 < ch.L && !std::isfinite(w2[i])))
+        return mps_fail(h, MPS_ERR_INVALID, "non-finite loss weight");
   if (n_steps < 1) return mps_fail(h, MPS_ERR_INVALID, "n_steps must be >= 1");
   if (!(eta >= 0.0) || !(dt > 0.0) || !(eps_local >= 0.0)) return mps_fail(h, MPS_ERR_INVALID, "bad dt, eps or eta");
   const int L = ch.L, d = ch.d, cm = ch.chi_max, dd = d * d;
@@ -464,11 +508,13 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
   mps_status r;
 
   // ---- forward with a checkpoint per step --------------------------------
-  for (int st = 0; st < n_steps; ++st) {
-    if ((r = save(arena + A.oCk + (size_t)st * A.snap)) != MPS_OK) return r;
-    if ((r = tebd_impl(h, stream, &ch, 1, 2, dt, 1, eps_local, 0, 0, 3)) != MPS_OK) return r;
+  if (!seeded) {
+    for (int st = 0; st < n_steps; ++st) {
+      if ((r = save(arena + A.oCk + (size_t)st * A.snap)) != MPS_OK) return r;
+      if ((r = tebd_impl(h, stream, &ch, 1, 2, dt, 1, eps_local, 0, 0, 3)) != MPS_OK) return r;
+    }
+    if ((r = save(arena + A.oCk + (size_t)n_steps * A.snap)) != MPS_OK) return r;
   }
-  if ((r = save(arena + A.oCk + (size_t)n_steps * A.snap)) != MPS_OK) return r;
 
   // ---- gates of the two classes (tau = dt/2 on odd layers, dt on the even one) and dG/dJ
   const double taus[2] = {0.5 * dt, dt};
@@ -500,6 +546,17 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
   const GradItemBuf& g0 = g.it[0];
   std::vector<int32_t> chi(L + 1);
   MPS_TRY_HIP(h, hipMemcpyAsync(chi.data(), ch.chi, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  if (seeded) {
+    // the state cotangents as given: site i's block of B (capacity layout
+    // [chi_max][d][chi_max]) into the reverse pass's compact [chi_i][d][chi_i+1]
+    MPS_TRY_HIP(h, hipStreamSynchronize(s));
+    K1((fill_zero_kernel<<<g1d((long long)L * site_el), 256, 0, s>>>(Bbar, (long long)L * site_el)));
+    for (int i = 0; i < L; ++i)
+      K1((site_copy_kernel<<<g1d((long long)chi[i] * d * chi[i + 1]), 256, 0, s>>>(
+          (const double2*)dB_seed + (size_t)i * site_el, bbar(i), chi[i], d, chi[i + 1], cm, 1)));
+    MPS_TRY_HIP(h, hipMemcpyAsync(lbar, dLam_seed, (size_t)(L + 1) * cm * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  if (!seeded) {  // seeding from the loss
   {
     MPS_TRY_HIP(h, launch_observe(s, ch, (const double2*)op1, g.obs, (const double2*)op2, 0, g.obs + L, nullptr));
     std::vector<double> o(2 * L);
@@ -550,6 +607,7 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
       K1((axpy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>(g0.Z, bbar(b + 1), (long long)chm * n, 1.0)));
     }
   }
+  }  // seeding from the loss
 
   // ---- backward over steps and layers -------------------------------------
   // Every bond of a layer is an independent update: its reverse pass runs on
@@ -754,4 +812,36 @@ extern "C" mps_status mps_tebd_vjp(mps_handle h, mps_stream stream, const mps_ch
   if (!chain || chain->L < 2) return mps_fail(h, MPS_ERR_INVALID, "null or short chain");
   return tebd_grad_impl(h, stream, chain, h0, dt, n_steps, eps_local, eta, op1, w_site, op2, w_bond, arena_ptr,
                         arena_bytes, obs_dev, nullptr, dJ_dev);
+}
+
+extern "C" mps_status mps_tebd_step_vjp(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
+                                        int32_t n_chains, const void* const* h0, void* ckpt_arena, size_t ckpt_bytes,
+                                        const void* const* dB_final, const double* const* dLam_final,
+                                        double* dJ_dev, double eta) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!chains || n_chains < 1 || !h0 || !ckpt_arena || !dB_final || !dLam_final || !dJ_dev)
+    return mps_fail(h, MPS_ERR_INVALID, "null pointer");
+  if (!(eta >= 0.0)) return mps_fail(h, MPS_ERR_INVALID, "eta must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  CkptHeader hd;
+  MPS_TRY_HIP(h, hipMemcpyAsync(&hd, ckpt_arena, sizeof(hd), hipMemcpyDeviceToHost, s));
+  MPS_TRY_HIP(h, hipStreamSynchronize(s));
+  if (hd.magic != kCkptMagic || hd.n_chains != n_chains || hd.shape_sum != ckpt_shape_sum(chains, n_chains))
+    return mps_fail(h, MPS_ERR_INVALID, "the arena was not written by mps_tebd_step_ex for these chains");
+  if (hd.order != 2) return mps_fail(h, MPS_ERR_INVALID, "the adjoint covers order-2 (TEBD2) runs");
+  if (ckpt_bytes < mps_tebd_ckpt_bytes(chains, n_chains, hd.n_steps))
+    return mps_fail(h, MPS_ERR_CAPACITY, "arena smaller than mps_tebd_ckpt_bytes()");
+  int l_max = 2;
+  for (int c = 0; c < n_chains; ++c) l_max = std::max(l_max, (int)chains[c].L);
+  MPS_TRY_HIP(h, hipMemsetAsync(dJ_dev, 0, (size_t)n_chains * (l_max - 1) * sizeof(double), s));
+  for (int c = 0; c < n_chains; ++c) {
+    if (!h0[c] || !dB_final[c] || !dLam_final[c]) return mps_fail(h, MPS_ERR_INVALID, "null per-chain pointer");
+    char* block = (char*)ckpt_arena + ckpt_block_offset(chains, c, hd.n_steps);
+    const size_t bytes = GradArena(chains[c].L, chains[c].d, chains[c].chi_max, hd.n_steps).total;
+    mps_status r = tebd_grad_impl(h, stream, chains + c, h0[c], hd.dt, hd.n_steps, hd.eps_local, eta, nullptr,
+                                  nullptr, nullptr, nullptr, block, bytes, nullptr, nullptr,
+                                  dJ_dev + (size_t)c * (l_max - 1), dB_final[c], dLam_final[c]);
+    if (r != MPS_OK) return r;
+  }
+  return MPS_OK;
 }

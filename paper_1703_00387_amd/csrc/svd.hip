@@ -971,7 +971,7 @@ __global__ __launch_bounds__(256) void wb_right_kernel(const BondItem* __restric
                                                        const JacMat* __restrict__ mats,
                                                        const int32_t* __restrict__ perm_ws,
                                                        const double* __restrict__ s2_ws, int m_cap,
-                                                       const SelOut* __restrict__ sel, int d) {
+                                                       const SelOut* __restrict__ sel, int d, DiscLog lg) {
   const BondItem it = items[blockIdx.y];
   const JacMat M = mats[blockIdx.y];
   const SelOut so = sel[blockIdx.y];
@@ -1001,9 +1001,14 @@ __global__ __launch_bounds__(256) void wb_right_kernel(const BondItem* __restric
     if (threadIdx.x == 0) {
       it.chi[it.b + 1] = k;
       it.disc[it.b] += so.disc;
+      // the update's own entry of the discarded-weight log (step from the device counter)
+      if (lg.log) lg.log[(long long)(*lg.step) * lg.step_stride + lg.layer_off + it.pad] = so.disc;
     }
   }
 }
+
+__global__ void set_int_kernel(int32_t* p, int v) { *p = v; }
+__global__ void inc_int_kernel(int32_t* p) { *p += 1; }
 
 // Fill the write-back GEMM problems B_b = theta~' Vh^dag / n_k on the device.
 __global__ void wb_left_probs_kernel(const BondItem* __restrict__ items, int n_items,
@@ -1184,16 +1189,26 @@ hipError_t launch_select(hipStream_t s, JacMat* mats, int n_mats, int32_t* perm_
 
 hipError_t launch_wb_right(hipStream_t s, const BondItem* items, int n_items, const JacMat* mats,
                            const int32_t* perm_ws, const double* s2_ws, int m_cap, const SelOut* sel, int chi_cap,
-                           int d, bool c128) {
+                           int d, bool c128, const DiscLog& lg) {
   if (n_items <= 0) return hipSuccess;
   size_t cap = (size_t)chi_cap * d * chi_cap;
   int gx = (int)((cap + 255) / 256);
   if (gx > 64) gx = 64;
   dim3 grid(gx, n_items);
   if (c128)
-    wb_right_kernel<double2><<<grid, 256, 0, s>>>(items, mats, perm_ws, s2_ws, m_cap, sel, d);
+    wb_right_kernel<double2><<<grid, 256, 0, s>>>(items, mats, perm_ws, s2_ws, m_cap, sel, d, lg);
   else
-    wb_right_kernel<float2><<<grid, 256, 0, s>>>(items, mats, perm_ws, s2_ws, m_cap, sel, d);
+    wb_right_kernel<float2><<<grid, 256, 0, s>>>(items, mats, perm_ws, s2_ws, m_cap, sel, d, lg);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(hipStream_t s, int32_t* p, int v) {
+  set_int_kernel<<<1, 1, 0, s>>>(p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_inc_int(hipStream_t s, int32_t* p) {
+  inc_int_kernel<<<1, 1, 0, s>>>(p);
   return hipGetLastError();
 }
 

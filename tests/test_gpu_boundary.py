@@ -1,0 +1,189 @@
+"""GPU tests of the boundary's workspace, record and adjoint entry points,
+through the C ABI.
+
+* A handle on a caller-owned workspace (mps_create_ws) sized by
+  mps_workspace_size gives bit-identical TEBD results to a handle that owns
+  its workspace, takes no device memory during the calls, and a workspace
+  that is too small is refused with MPS_ERR_CAPACITY.
+* The per-update discarded-weight log of mps_tebd_step_ex equals the oracle's
+  discarded weight of every update in order (R10: |dw| <= 1e-12 + 1e-6 w),
+  adds up to the chains' per-bond accumulators, and a captured step logs the
+  same as the eager one.
+* mps_tebd_step_vjp after a checkpointed batched TEBD2 run: for state
+  cotangents built from a weighted sum of <S^z_i> of each chain's final
+  state, dL/dJ equals the oracle's reverse-mode gradient of that loss
+  (1e-6 relative) and the single-chain adjoint mps_tebd_vjp (1e-10 relative).
+"""
+import copy
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1703_00387_amd import api
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    h = api.Handle(0)
+    yield h
+    h.close()
+
+
+def _chain(spec, dtype="c128"):
+    from paper_1703_00387_amd import api, models
+    return api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=dtype)
+
+
+def _batch_specs(n, L0, chi):
+    wl = W.xxz_batch256(n_chains=n)
+    return [W.xxz_chain(L0 + 2 * i, chi, 1.0, 0.5, None, c.Jz_b[:L0 + 2 * i - 1], "random_product",
+                        c.local_states[:L0 + 2 * i]) for i, c in enumerate(wl.chains)]
+
+
+def test_caller_owned_workspace(H):
+    from paper_1703_00387_amd import api, _lib
+    specs = _batch_specs(3, 12, 32)
+    need = api.workspace_size(_lib.MPS_OP_TEBD, "c128", 3, 16, 2, 32)
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    hw = api.Handle(0, workspace=ws)
+    try:
+        a = [_chain(sp) for sp in specs]
+        b = [_chain(sp) for sp in specs]
+        print(f"[boundary] caller workspace {need} bytes", flush=True)
+        api.tebd_step(hw, a, 4, 0.05, 2, 1e-12)          # loads every module once
+        api.tebd_step(H, b, 4, 0.05, 2, 1e-12)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        api.tebd_step(hw, a, 4, 0.05, 3, 1e-12)
+        torch.cuda.synchronize()
+        free1 = torch.cuda.mem_get_info()[0]
+        api.tebd_step(H, b, 4, 0.05, 3, 1e-12)
+        torch.cuda.synchronize()
+        assert free1 == free0, (free0, free1)
+        for x, y in zip(a, b):
+            assert torch.equal(x.chi, y.chi) and torch.equal(x.B, y.B) and torch.equal(x.lam, y.lam)
+        assert 0 < hw.workspace_needed() <= need
+        # a single large matrix: the column split keeps its partial Grams behind the plan
+        A = torch.from_numpy(W.random_complex((256, 256), (81,))).cuda()
+        r1 = hw.truncate(A, 64, 1e-12)
+        r2 = H.truncate(A, 64, 1e-12)
+        assert r1[3] == r2[3] and (r1[1] - r2[1]).abs().max().item() <= 1e-14
+    finally:
+        hw.close()
+    small = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    hs = api.Handle(0, workspace=small)
+    try:
+        c = [_chain(specs[0])]
+        with pytest.raises(_lib.MPSError) as e:
+            api.tebd_step(hs, c, 2, 0.05, 1, 1e-12)
+        assert e.value.code == _lib.MPS_ERR_CAPACITY
+        assert hs.workspace_needed() > 4096
+    finally:
+        hs.close()
+
+
+@pytest.mark.parametrize("order,method", [(2, "tebd2"), (4, "tebd4")])
+def test_disc_log_matches_oracle(H, order, method):
+    from oracle import mps as omps
+    from paper_1703_00387_amd import api
+    specs = _batch_specs(2, 8, 2)     # chi_max = 2: the cap cuts
+    n_steps, dt, eps = 4, 0.1, 1e-10
+    n_layers = 3 if order == 2 else 15
+    l_max = max(sp.L for sp in specs)
+    chains = [_chain(sp) for sp in specs]
+    log = torch.zeros((n_steps, n_layers, len(chains), l_max - 1), dtype=torch.float64, device="cuda")
+    print(f"[boundary] disc log order {order}", flush=True)
+    api.tebd_step_ex(H, chains, order, dt, n_steps, eps, disc_log=log)
+    torch.cuda.synchronize()
+    code, word = H.device_status()
+    assert code == 0, word
+    lg = log.cpu().numpy()
+    for c, (sp, ch) in enumerate(zip(specs, chains)):
+        ref = omps.tebd_run(sp, method, dt, n_steps, eps)
+        got = []
+        layers = omps.step_layers(method, sp.L, dt)
+        for st in range(n_steps):
+            for li, (bonds, _) in enumerate(layers):
+                got += [lg[st, li, c, b] for b in bonds]
+        got, want = np.array(got), np.array(ref.disc)
+        assert len(got) == len(want)
+        assert (np.abs(got - want) <= 1e-12 + 1e-6 * want).all(), np.abs(got - want).max()
+        assert want.max() > 1e-6                  # the cap cut
+        acc = ch.disc.cpu().numpy()
+        np.testing.assert_allclose(lg[:, :, c, :sp.L - 1].sum(axis=(0, 1)), acc, rtol=1e-12, atol=1e-18)
+    # the captured step logs the same
+    g = [_chain(sp) for sp in specs]
+    log2 = torch.zeros_like(log)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        api.tebd_step_ex(H, g, order, dt, n_steps, eps, flags=0x1, disc_log=log2)
+    s.synchronize()
+    assert torch.equal(log, log2)
+
+
+def test_checkpointed_vjp_matches_oracle_and_single_chain(H):
+    from oracle import grad, models as om
+    from paper_1703_00387_amd import api, _lib, models
+    dt, n_steps, chi, eps = 0.05, 6, 8, 1e-12
+    specs = []
+    for L in (6, 8):
+        sp = W.xxz_chain(L, chi, 1.0, 0.5, J_b=W.xxz_grad_couplings(L))
+        specs.append(sp)
+    h0s = []
+    for sp in specs:
+        unit = copy.copy(sp)
+        unit.J_b = np.ones(sp.L - 1)
+        h0s.append(torch.from_numpy(np.ascontiguousarray(models.bond_hamiltonians(unit))).cuda())
+    chains = [_chain(sp) for sp in specs]
+    ck = torch.zeros(api.tebd_ckpt_bytes(chains, n_steps), dtype=torch.uint8, device="cuda")
+    print("[boundary] checkpointed forward", flush=True)
+    api.tebd_step_ex(H, chains, 2, dt, n_steps, eps, flags=_lib.MPS_FLAG_CHECKPOINT, ckpt=ck)
+    torch.cuda.synchronize()
+    # cotangents of L = sum_i w_i <S^z_i> at the final state (dL = Re<dB, dB'> + <dlam, dlam'>):
+    # dB_i = 2 w_i lam_i^2 (S^z B_i), dlam_i[a] = 2 w_i lam_i[a] Re<B_i[a], S^z B_i[a]>
+    sz = 0.5 * om.SZ
+    weights, dBs, dls = [], [], []
+    for c, (sp, ch) in enumerate(zip(specs, chains)):
+        w = W.random_real((sp.L,), (91, c), -1.0, 1.0)
+        weights.append(w)
+        B = ch.B.cpu().numpy()
+        lam = ch.lam.cpu().numpy()
+        chis = ch.chi.cpu().numpy()
+        dB = np.zeros_like(B)
+        dl = np.zeros_like(lam)
+        for i in range(sp.L):
+            a, r = chis[i], chis[i + 1]
+            Bi = B[i, :a, :, :r]
+            OB = np.einsum("st,atc->asc", sz, Bi)
+            l = lam[i, :a]
+            dB[i, :a, :, :r] = 2 * w[i] * (l ** 2)[:, None, None] * OB
+            dl[i, :a] += 2 * w[i] * l * np.real(np.einsum("asc,asc->a", Bi.conj(), OB))
+        dBs.append(torch.from_numpy(dB).cuda())
+        dls.append(torch.from_numpy(dl).cuda())
+    print("[boundary] tebd_step_vjp", flush=True)
+    dJ = api.tebd_step_vjp(H, chains, h0s, ck, dBs, dls, eta=1e-12).cpu().numpy()
+    code, word = H.device_status()
+    assert code == 0, word
+    for c, sp in enumerate(specs):
+        # oracle: reverse mode through the same truncated run, loss from its own final state
+        J = torch.tensor(np.asarray(sp.J_b, dtype=np.float64), requires_grad=True)
+        Bt, lt = grad.tebd2_state_torch(sp, J, dt, n_steps, chi, eps, 1e-12)
+        loss = sum(weights[c][i] * grad.site_expect_torch(Bt, lt, sz, i) for i in range(sp.L))
+        loss.backward()
+        g_or = J.grad.numpy()
+        rel = np.linalg.norm(dJ[c, :sp.L - 1] - g_or) / np.linalg.norm(g_or)
+        # the single-chain adjoint with the same weights
+        one = _chain(sp)
+        _, dJ1 = api.tebd_vjp(H, one, h0s[c], dt, n_steps, eps, models.sz_operator(),
+                              np.kron(models.sz_operator(), models.sz_operator()), weights[c], np.zeros(sp.L - 1))
+        dJ1 = dJ1.cpu().numpy()
+        rel1 = np.linalg.norm(dJ[c, :sp.L - 1] - dJ1) / np.linalg.norm(dJ1)
+        print(f"[boundary] chain L={sp.L}: rel vs oracle {rel:.2e}, vs single-chain adjoint {rel1:.2e}", flush=True)
+        assert rel <= 1e-6 and rel1 <= 1e-10
+        assert np.all(dJ[c, sp.L - 1:] == 0.0)
