@@ -104,7 +104,9 @@ mps_status mps_reserve(mps_handle h, size_t bytes);
 mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
 /* Tuning knobs: 0 = Jacobi relative tolerance (default 1e-13),
  * 1 = Jacobi maximum sweeps (default 30), 2 = Jacobi absolute tolerance
- * relative to |theta|_F^2 (default 1e-15), 3 = kernel timing on (!= 0) or
+ * relative to |theta|_F^2 (default 1e-15, at least 1e-30: under a purely
+ * relative criterion the rows beyond the rank of a matrix with more rows
+ * than columns never count as orthogonal and end as NaN rows), 3 = kernel timing on (!= 0) or
  * off (0): HIP events around every launch of the timed kernels on the call's
  * stream, plus device counters of the useful work they perform (not inside
  * captured graphs), 4 = sweeps of the 64x64 inner eigensolve per Jacobi block
@@ -639,6 +641,52 @@ mps_status mps_tebd_step_vjp(mps_handle h, mps_stream stream, const mps_chain_de
                              const void* const* h0, void* ckpt_arena, size_t ckpt_bytes,
                              const void* const* dB_final, const double* const* dLam_final, double* dJ_dev,
                              double eta);
+
+/*
+ * The vector-Jacobian products of the two pieces of one TEBD update (the
+ * reverse of its steps: contraction and local propagator of the plain
+ * two-site update in App. "Details of the Krylov method", truncated SVD split
+ * of Sec. "Basic concepts"; the paper gives the forward steps only).
+ * Cotangents follow dL = Re sum conj(Xbar) dX (the cotangent of a complex
+ * entry x is dL/dRe x + i dL/dIm x); every array is complex128 row-major on
+ * the device, every output is overwritten, the call is asynchronous on
+ * `stream`.
+ *
+ * mps_theta_gate_vjp: for theta'[(a,s)][(t,c)] = lam_l[a] sum_{u,v} G[(s,t)][(u,v)]
+ * sum_b Bl[a][u][b] Br[b][v][c] (theta' is [chl*d][d*chr]) and its cotangent
+ * theta_bar of the same shape, writes
+ *   dBl [chl][d][chm], dBr [chm][d][chr], dlam_l FP64 [chl], dG [d*d][d*d].
+ * Bl [chl][d][chm], Br [chm][d][chr], lam_l FP64 [chl], G [d*d][d*d].
+ * Errors: MPS_ERR_INVALID for a null pointer, MPS_ERR_SHAPE for a dimension
+ * < 1 or d > 5, MPS_ERR_CAPACITY for d*chl, d*chr or chm above 4096.
+ */
+mps_status mps_theta_gate_vjp(mps_handle h, mps_stream stream, const void* Bl, const void* Br, const double* lam_l,
+                              const void* G, const void* theta_bar, int32_t chl, int32_t d, int32_t chm, int32_t chr,
+                              void* dBl, void* dBr, double* dlam_l, void* dG);
+/*
+ * mps_truncate_vjp: theta_bar [m][n] = dL/dtheta for the kept factors of
+ * mps_truncate(theta) = (U, S, Vh) with k kept values, given
+ *   S [k], Vh [k][n]      : the forward's kept values and rows of V^dag
+ *   U_bar [m][ld_ubar]    : cotangent of U (first k columns), may be NULL
+ *   S_bar [k], Vh_bar [k][n] : cotangents of S and Vh, each may be NULL
+ *   eta                   : Lorentzian broadening (>= 0) of the inverse gaps
+ *                           1/(s_j^2 - s_i^2) -> D/(D^2 + eta) and of 1/s_j
+ *                           -> s_j/(s_j^2 + eta); eta = 0 is the exact
+ *                           derivative where the gaps are nonzero.
+ * The full reduced SVD backward is used, with the discarded triplets'
+ * cotangents zero but their coupling to the kept ones retained: the
+ * discarded directions are resolved by an FP64 Jacobi SVD of
+ * theta (1 - V_k V_k^dag) with an absolute tolerance of 1e-30 of its weight
+ * (directions of weight below 1e-26 |theta|^2 are dropped).  U_bar enters through
+ * U = theta V_k S^-1.  L must not depend on the phases of the singular
+ * vectors (as no quantity of the Hastings form does).
+ * Errors: MPS_ERR_INVALID for a null theta, S, Vh or theta_bar or eta < 0;
+ * MPS_ERR_SHAPE for k outside [1, min(m, n)] or ld_ubar < k;
+ * MPS_ERR_CAPACITY for m or n above 2560.
+ */
+mps_status mps_truncate_vjp(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n, int32_t k,
+                            const double* S, const void* Vh, const void* U_bar, int64_t ld_ubar, const double* S_bar,
+                            const void* Vh_bar, double eta, void* theta_bar);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,29 @@ class TruncSVD(torch.autograd.Function):
         return gA, None, None
 
 
+def theta_gate_torch(Bl, Br, lam_l, G):
+    """theta' of one two-site update (App. "Details of the Krylov method", the
+    plain two-site update: contract the two sites over their shared bond, apply
+    the two-site propagator to the physical pair; rows scaled by the left
+    Schmidt values, Hastings form).  Bl [chl][d][chm], Br [chm][d][chr],
+    lam_l [chl], G [d*d][d*d] with G[(s,t)][(u,v)] mapping (u,v) to (s,t);
+    returns theta' [chl*d][d*chr]."""
+    chl, d, _ = Bl.shape
+    chr_ = Br.shape[2]
+    th = torch.einsum("aub,bvc->auvc", Bl, Br).reshape(chl, d * d, chr_)
+    thp = torch.einsum("xy,ayc->axc", G, th)
+    return (lam_l.to(thp.dtype)[:, None, None] * thp).reshape(chl * d, d * chr_)
+
+
+def theta_gate_vjp(Bl, Br, lam_l, G, theta_bar):
+    """(dBl, dBr, dlam_l, dG) of theta_gate_torch for the cotangent theta_bar,
+    with dL = Re sum conj(Xbar) dX (reverse mode of the definition above)."""
+    xs = [torch.tensor(np.asarray(x), requires_grad=True) for x in (Bl, Br, lam_l, G)]
+    tp = theta_gate_torch(*xs)
+    torch.real(torch.sum(torch.tensor(np.asarray(theta_bar)).conj() * tp)).backward()
+    return tuple(x.grad.numpy() for x in xs)
+
+
 def _gate_factors(spec, b):
     e, V = np.linalg.eigh(models.xxz_unit_bond(spec, b))
     return torch.tensor(e), torch.tensor(V)

@@ -25,7 +25,7 @@ MPS_OP_TRUNCATE, MPS_OP_TEBD, MPS_OP_HEFF, MPS_OP_KRYLOV, MPS_OP_TDVP = range(5)
 
 # every exported symbol that include/mps.h declares
 EXPORTS = ["mps_create", "mps_create_ws", "mps_workspace_size", "mps_workspace_needed", "mps_destroy", "mps_last_error", "mps_reserve", "mps_device_status",
-           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_noalloc", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_ex", "mps_tebd_ckpt_bytes", "mps_tebd_step_vjp", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
+           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_noalloc", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_ex", "mps_tebd_ckpt_bytes", "mps_tebd_step_vjp", "mps_theta_gate_vjp", "mps_truncate_vjp", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
            "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step", "mps_tdvp2_step_u1",
            "mps_tebd_grad_arena_bytes", "mps_tebd_grad", "mps_tebd_vjp", "mps_autotune_jacobi",
            "mps_autotune_candidate"]
@@ -82,6 +82,8 @@ def lib():
         "mps_tebd_step_ex": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32, vp, C.c_size_t, vp],
         "mps_tebd_step_vjp": [vp, vp, C.POINTER(ChainDesc), i32, C.POINTER(vp), vp, C.c_size_t, C.POINTER(vp),
                               C.POINTER(vp), vp, dbl],
+        "mps_theta_gate_vjp": [vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp],
+        "mps_truncate_vjp": [vp, vp, vp, i64, i64, i32, vp, vp, vp, i64, vp, vp, dbl, vp],
         "mps_tebd_step_u1": [vp, vp, C.POINTER(ChainDesc), C.POINTER(U1ChainDesc), i32, i32, dbl, i32, dbl, u32],
         "mps_ktebd_step_u1": [vp, vp, C.POINTER(ChainDesc), C.POINTER(U1ChainDesc), i32, dbl, i32, dbl, i32, dbl, u32,
                               vp],

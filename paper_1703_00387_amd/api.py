@@ -263,6 +263,62 @@ def tebd_step_vjp(h: Handle, chains: Sequence[Chain], h0: Sequence[torch.Tensor]
     return dJ
 
 
+def _c128(x, name, shape):
+    if (not isinstance(x, torch.Tensor) or x.dtype != torch.complex128 or x.device.type != "cuda"
+            or not x.is_contiguous() or tuple(x.shape) != tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous complex128 device tensor of shape {tuple(shape)}")
+
+
+def _f64(x, name, shape):
+    if (not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or x.device.type != "cuda"
+            or not x.is_contiguous() or tuple(x.shape) != tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {tuple(shape)}")
+
+
+def theta_gate_vjp(h: Handle, Bl: torch.Tensor, Br: torch.Tensor, lam_l: torch.Tensor, G: torch.Tensor,
+                   theta_bar: torch.Tensor):
+    """mps_theta_gate_vjp: (dBl, dBr, dlam_l, dG) for theta' = lam_l G (Bl Br)
+    with cotangent theta_bar [chl*d][d*chr].  Bl [chl][d][chm], Br [chm][d][chr],
+    G [d*d][d*d], all complex128 on the device; lam_l float64 [chl]."""
+    if Bl.dim() != 3 or Br.dim() != 3:
+        raise ValueError("Bl and Br are [chi][d][chi]")
+    chl, d, chm = Bl.shape
+    chr_ = Br.shape[2]
+    _c128(Bl, "Bl", (chl, d, chm))
+    _c128(Br, "Br", (chm, d, chr_))
+    _f64(lam_l, "lam_l", (chl,))
+    _c128(G, "G", (d * d, d * d))
+    _c128(theta_bar, "theta_bar", (chl * d, d * chr_))
+    dBl, dBr, dG = torch.empty_like(Bl), torch.empty_like(Br), torch.empty_like(G)
+    dl = torch.empty_like(lam_l)
+    h.check(lib().mps_theta_gate_vjp(h.h, _stream(), _ptr(Bl), _ptr(Br), _ptr(lam_l), _ptr(G), _ptr(theta_bar),
+                                     chl, d, chm, chr_, _ptr(dBl), _ptr(dBr), _ptr(dl), _ptr(dG)))
+    return dBl, dBr, dl, dG
+
+
+def truncate_vjp(h: Handle, theta: torch.Tensor, S: torch.Tensor, Vh: torch.Tensor, U_bar=None, S_bar=None,
+                 Vh_bar=None, eta: float = 0.0) -> torch.Tensor:
+    """mps_truncate_vjp: dL/dtheta for the kept factors (U, S, Vh) of a
+    truncated SVD of theta [m][n] with k = len(S) kept values; the cotangents
+    U_bar [m][k], S_bar [k], Vh_bar [k][n] may each be None (zero)."""
+    _check_device_matrix(theta)
+    m, n = theta.shape
+    k = int(S.shape[0])
+    _f64(S, "S", (k,))
+    _c128(Vh, "Vh", (k, n))
+    if U_bar is not None:
+        _c128(U_bar, "U_bar", (m, k))
+    if S_bar is not None:
+        _f64(S_bar, "S_bar", (k,))
+    if Vh_bar is not None:
+        _c128(Vh_bar, "Vh_bar", (k, n))
+    theta = theta.contiguous()
+    out = torch.empty_like(theta)
+    h.check(lib().mps_truncate_vjp(h.h, _stream(), _ptr(theta), m, n, k, _ptr(S), _ptr(Vh), _ptr(U_bar), k,
+                                   _ptr(S_bar), _ptr(Vh_bar), float(eta), _ptr(out)))
+    return out
+
+
 @dataclass
 class Charges:
     """Bond charges of a symmetric chain (layout of mps_u1_chain):

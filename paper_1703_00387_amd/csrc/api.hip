@@ -472,7 +472,8 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
       h->jac_max_sweeps = (int)value;
       return MPS_OK;
     case 2:
-      if (!(value >= 0.0 && value < 1.0)) return mps_fail(h, MPS_ERR_INVALID, "absolute tolerance must be in [0,1)");
+      if (!(value >= kJacAbsFloor && value < 1.0))
+        return mps_fail(h, MPS_ERR_INVALID, "absolute tolerance must be in [1e-30,1)");
       h->jac_abs = value;
       return MPS_OK;
     case 3:

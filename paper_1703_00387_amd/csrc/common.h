@@ -87,6 +87,12 @@ struct KryOpts {
 // Jacobi's absolute floor (jac_abs |theta|^2) are not resolved, their
 // directions are not orthogonalised, so a tail below the floor counts as zero
 // (eps < 0, keep everything up to chi_max, is passed through)
+// Smallest Jacobi absolute tolerance (relative to |X|_F^2).  Under a purely
+// relative criterion, rows beyond the rank of a matrix with more rows than
+// columns have no room to become orthogonal: they are rotated toward zero
+// sweep after sweep and end as NaN rows.  The floor lets them count as
+// converged once |G_pq| <= 1e-30 |X|_F^2, far below any resolved value.
+constexpr double kJacAbsFloor = 1e-30;
 inline double count_rule_eps(mps_handle h, double eps) { return eps >= 0.0 && eps < h->jac_abs ? h->jac_abs : eps; }
 
 // TEBD driver with a layer window (api.hip); kry != null propagates every

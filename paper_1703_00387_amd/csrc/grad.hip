@@ -709,9 +709,9 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
       }
       if ((r = join()) != MPS_OK) return r;
 
-      // -- the layer's residual SVDs, orthogonalised with a purely relative tolerance
+      // -- the layer's residual SVDs, orthogonalised with the smallest absolute tolerance
       MPS_TRY_HIP(h, launch_jac_prep_plain(s, g.mat, ni, h->status_dev));
-      h->jac_abs = 0.0;
+      h->jac_abs = kJacAbsFloor;
       // the residual batches are many small matrices: no column split
       r = run_jacobi(h, s, g.mat, ni, nb_cap, g.m_cap, g.unc, false, false);
       h->jac_abs = abs_saved;
@@ -842,6 +842,219 @@ extern "C" mps_status mps_tebd_step_vjp(mps_handle h, mps_stream stream, const m
                                   nullptr, nullptr, nullptr, block, bytes, nullptr, nullptr,
                                   dJ_dev + (size_t)c * (l_max - 1), dB_final[c], dLam_final[c]);
     if (r != MPS_OK) return r;
+  }
+  return MPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Single-update vector-Jacobian products (the pieces of the reverse pass above)
+// ---------------------------------------------------------------------------
+namespace {
+
+// dG[e] = sum_{a,c} Tb[a][uv][c] conj(T[a][st][c]),  e = uv * D + st; one workgroup per entry
+__global__ __launch_bounds__(256) void gate_bar_kernel(const double2* __restrict__ Tb, const double2* __restrict__ T,
+                                                       int P, int D, int R, double2* dG) {
+  __shared__ double2 red[4];
+  const int uv = blockIdx.x / D, st = blockIdx.x % D;
+  double2 acc = make_double2(0.0, 0.0);
+  for (long long e = threadIdx.x; e < (long long)P * R; e += blockDim.x) {
+    const long long a = e / R, c = e % R;
+    const double2 x = Tb[(a * D + uv) * R + c], y = T[(a * D + st) * R + c];
+    acc.x += x.x * y.x + x.y * y.y;     // x conj(y)
+    acc.y += x.y * y.x - x.x * y.y;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.x += __shfl_xor(acc.x, o);
+    acc.y += __shfl_xor(acc.y, o);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    dG[blockIdx.x] = make_double2(red[0].x + red[1].x + red[2].x + red[3].x, red[0].y + red[1].y + red[2].y + red[3].y);
+}
+
+__global__ void sqrt_kernel(const double* __restrict__ a, double* b, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = sqrt(fmax(a[i], 0.0));
+}
+
+// Cotangents of the kept factors with U written as theta V_k S^-1 (U_bar
+// folded into those of V_k and S).  One workgroup per kept j:
+//   w_j = s_j / (s_j^2 + eta),  Wt = U_bar^dag theta (k x n),
+//   Vbar[c][j] = conj(Vh_bar[j][c] + w_j Wt[j][c])           (j < k; other columns 0)
+//   sbar_j = S_bar_j - w_j^2 Re sum_c Wt[j][c] conj(Vh[j][c])
+// Null Vh_bar, S_bar or Wt count as zero.
+__global__ __launch_bounds__(256) void trunc_bar_kernel(const double2* __restrict__ vhb, const double* __restrict__ sb,
+                                                        const double2* __restrict__ Wt, const double2* __restrict__ Vh,
+                                                        const double* __restrict__ s, double eta, int n, int r,
+                                                        double2* Vb, double* sbar) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  const double w = s[j] / (s[j] * s[j] + eta);
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const long long e = (long long)j * n + c;
+    double2 v = vhb ? vhb[e] : make_double2(0.0, 0.0);
+    if (Wt) {
+      const double2 t = Wt[e], q = Vh[e];
+      v = make_double2(v.x + w * t.x, v.y + w * t.y);
+      acc += t.x * q.x + t.y * q.y;
+    }
+    Vb[(long long)c * r + j] = make_double2(v.x, -v.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) sbar[j] = (sb ? sb[j] : 0.0) - w * w * (red[0] + red[1] + red[2] + red[3]);
+}
+
+// out[i][j] = in[i * ld + j] * s_j / (s_j^2 + eta)   (rows x k)
+__global__ void col_inv_scale_kernel(const double2* __restrict__ in, int ld, int rows, int k,
+                                     const double* __restrict__ s, double eta, double2* out) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)rows * k;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long i = e / k;
+    const int j = (int)(e % k);
+    const double w = s[j] / (s[j] * s[j] + eta);
+    const double2 v = in[i * ld + j];
+    out[e] = make_double2(w * v.x, w * v.y);
+  }
+}
+
+}  // namespace
+
+extern "C" mps_status mps_theta_gate_vjp(mps_handle h, mps_stream stream, const void* Bl, const void* Br,
+                                         const double* lam_l, const void* G, const void* theta_bar, int32_t chl,
+                                         int32_t d, int32_t chm, int32_t chr, void* dBl, void* dBr, double* dlam_l,
+                                         void* dG) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!Bl || !Br || !lam_l || !G || !theta_bar || !dBl || !dBr || !dlam_l || !dG)
+    return mps_fail(h, MPS_ERR_INVALID, "null pointer");
+  if (chl < 1 || chm < 1 || chr < 1 || d < 1 || d > 5) return mps_fail(h, MPS_ERR_SHAPE, "bad dimensions");
+  if ((int64_t)d * chl > 4096 || (int64_t)d * chr > 4096 || chm > 4096)
+    return mps_fail(h, MPS_ERR_CAPACITY, "d*chi and chi are limited to 4096");
+  const int dd = d * d, m = chl * d, n = d * chr;
+  const size_t mn = (size_t)m * n;
+  WsPlan p;
+  const size_t o0 = p.take<double2>(mn), o1 = p.take<double2>(mn), o2 = p.take<double2>(mn),
+               o3 = p.take<double2>(mn);
+  mps_status st = mps_ensure_ws(h, p.off);
+  if (st != MPS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c{h, s};
+  double2* T0 = (double2*)(h->ws + o0);  // theta~ = Bl Br
+  double2* T1 = (double2*)(h->ws + o1);  // theta~' = G theta~
+  double2* T2 = (double2*)(h->ws + o2);  // theta~'_bar = lam theta'_bar
+  double2* T3 = (double2*)(h->ws + o3);  // theta~_bar = G^dag theta~'_bar
+  mps_status r;
+  if ((r = gemm128(c, Bl, chm, 1, 0, Br, n, 1, 0, T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
+  K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>((const double2*)G, dd, T0, T1, chl, chr, 0, 0)));
+  MPS_TRY_HIP(h, hipMemsetAsync(dlam_l, 0, (size_t)chl * sizeof(double), s));
+  K1((lam_dot_kernel<<<chl, 256, 0, s>>>((const double2*)theta_bar, T1, d, n, dlam_l, nullptr, 1.0)));
+  K1((row_scale_kernel<<<g1d((long long)mn), 256, 0, s>>>((const double2*)theta_bar, T2, m, n, lam_l, d, 1, 1.0, 0)));
+  K1((gate_bar_kernel<<<dd * dd, 256, 0, s>>>(T2, T0, chl, dd, chr, (double2*)dG)));
+  K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, s>>>((const double2*)G, dd, T2, T3, chl, chr, 1, 0)));
+  if ((r = gemm128(c, T3, n, 1, 0, Br, 1, n, 1, dBl, chm, m, chm, n, 1.0)) != MPS_OK) return r;
+  if ((r = gemm128(c, Bl, 1, chm, 1, T3, n, 1, 0, dBr, n, chm, n, m, 1.0)) != MPS_OK) return r;
+  return MPS_OK;
+}
+
+extern "C" mps_status mps_truncate_vjp(mps_handle h, mps_stream stream, const void* theta, int64_t m64, int64_t n64,
+                                       int32_t k, const double* S, const void* Vh, const void* U_bar, int64_t ld_ubar,
+                                       const double* S_bar, const void* Vh_bar, double eta, void* theta_bar) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!theta || !S || !Vh || !theta_bar) return mps_fail(h, MPS_ERR_INVALID, "null pointer");
+  if (m64 < 1 || n64 < 1 || k < 1 || k > std::min(m64, n64)) return mps_fail(h, MPS_ERR_SHAPE, "bad dimensions");
+  if (U_bar && ld_ubar < k) return mps_fail(h, MPS_ERR_SHAPE, "ld_ubar < k");
+  if (m64 > 2560 || n64 > 2560) return mps_fail(h, MPS_ERR_CAPACITY, "m and n are limited to 2560");
+  if (!(eta >= 0.0)) return mps_fail(h, MPS_ERR_INVALID, "eta must be >= 0");
+  const int m = (int)m64, n = (int)n64, rc = std::min(m, n), cap = rc - k;
+  const size_t mn = (size_t)m * n;
+  WsPlan p;
+  const size_t oP = p.take<double2>((size_t)m * rc), oZ = p.take<double2>(mn), oR = p.take<double2>(mn),
+               oV = p.take<double2>((size_t)rc * n), oVb = p.take<double2>((size_t)n * rc),
+               oJ = p.take<double2>((size_t)rc * rc), oX = p.take<double2>((size_t)rc * rc),
+               oY1 = p.take<double2>((size_t)rc * n), oY = p.take<double2>((size_t)rc * n),
+               oZ2 = p.take<double2>((size_t)rc * n), oJd = p.take<double2>((size_t)rc * rc),
+               oW = p.take<double2>((size_t)k * n), oUs = p.take<double2>((size_t)m * k);
+  const size_t oc2 = p.take<double>(rc), osv = p.take<double>(rc), okept = p.take<double>(rc),
+               osb = p.take<double>(rc);
+  const size_t oMat = p.take<JacMat>(1), oSel = p.take<SelOut>(1), oSeld = p.take<SelOut>(1);
+  const size_t oRm = p.take<int32_t>(m), oPm = p.take<int32_t>(m), oS2 = p.take<double>(m), oNr = p.take<double>(m),
+               oUnc = p.take<int32_t>(8), oRd = p.take<int32_t>(1);
+  mps_status st = mps_ensure_ws(h, p.off);
+  if (st != MPS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c{h, s};
+  char* ws = h->ws;
+  double2 *P = (double2*)(ws + oP), *Z = (double2*)(ws + oZ), *R = (double2*)(ws + oR), *Vf = (double2*)(ws + oV),
+          *Vb = (double2*)(ws + oVb), *Jv = (double2*)(ws + oJ), *Xm = (double2*)(ws + oX),
+          *Y1 = (double2*)(ws + oY1), *Y = (double2*)(ws + oY), *Z2 = (double2*)(ws + oZ2), *Jd = (double2*)(ws + oJd),
+          *Wt = (double2*)(ws + oW), *Us = (double2*)(ws + oUs);
+  double *c2 = (double*)(ws + oc2), *sv = (double*)(ws + osv), *kept2 = (double*)(ws + okept),
+         *sbar = (double*)(ws + osb);
+  JacMat* mat = (JacMat*)(ws + oMat);
+  SelOut *sel = (SelOut*)(ws + oSel), *seld = (SelOut*)(ws + oSeld);
+  mps_status r;
+  // V rows: the kept rows Vh, then the resolved discarded directions, then zeros
+  K1((fill_zero_kernel<<<g1d((long long)rc * n), 256, 0, s>>>(Vf, (long long)rc * n)));
+  MPS_TRY_HIP(h, hipMemcpyAsync(Vf, Vh, (size_t)k * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  if ((r = gemm128(c, theta, n, 1, 0, Vf, 1, n, 1, P, k, m, k, n, 1.0)) != MPS_OK) return r;
+  K1((colnorm2_kernel<<<g1d(k), 256, 0, s>>>(P, m, k, kept2)));
+  if (cap > 0) {
+    // residual theta (1 - V_k V_k^dag), orthogonalised with the smallest
+    // absolute tolerance: its rows that carry weight give the discarded directions
+    if ((r = gemm128(c, P, k, 1, 0, Vf, n, 1, 0, Z, n, m, n, k, 1.0)) != MPS_OK) return r;
+    MPS_TRY_HIP(h, hipMemcpyAsync(R, theta, mn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    K1((axpy_kernel<<<g1d((long long)mn), 256, 0, s>>>(Z, R, (long long)mn, -1.0)));
+    JacMat hm;
+    std::memset(&hm, 0, sizeof(hm));
+    hm.X = R;
+    hm.rowmap = (int32_t*)(ws + oRm);
+    hm.nrm2 = (double*)(ws + oNr);
+    hm.m = m;
+    hm.n = n;
+    hm.ld = n;
+    hm.nb = jac_nb(m);
+    hm.kmax = cap;
+    MPS_TRY_HIP(h, hipMemcpyAsync(mat, &hm, sizeof(hm), hipMemcpyHostToDevice, s));
+    MPS_TRY_HIP(h, hipStreamSynchronize(s));
+    MPS_TRY_HIP(h, launch_jac_prep_plain(s, mat, 1, h->status_dev));
+    const double abs_saved = h->jac_abs;
+    h->jac_abs = kJacAbsFloor;
+    r = run_jacobi(h, s, mat, 1, hm.nb, m, (int32_t*)(ws + oUnc), false, true);
+    h->jac_abs = abs_saved;
+    if (r != MPS_OK) return r;
+    MPS_TRY_HIP(h, launch_select(s, mat, 1, (int32_t*)(ws + oPm), (double*)(ws + oS2), m, 0, 0.0, sel));
+    K1((grad_rd_kernel<<<1, 256, 0, s>>>((double*)(ws + oS2), kept2, m, k, cap, 1e-26, seld, (int32_t*)(ws + oRd))));
+    double2* Vd = Vf + (size_t)k * n;
+    MPS_TRY_HIP(h, launch_write_rows(s, mat, (int32_t*)(ws + oPm), (double*)(ws + oS2), seld, Vd, n, 0, true));
+    // project them once more against V_k
+    if ((r = gemm128(c, Vd, n, 1, 0, Vf, 1, n, 1, Jd, k, cap, k, n, 1.0)) != MPS_OK) return r;
+    if ((r = gemm128(c, Jd, k, 1, 0, Vf, n, 1, 0, Z2, n, cap, n, k, 1.0)) != MPS_OK) return r;
+    K1((axpy_kernel<<<g1d((long long)cap * n), 256, 0, s>>>(Z2, Vd, (long long)cap * n, -1.0)));
+  }
+  // P = theta V (m x rc); s_j = |P_j| for the discarded j, the forward's S for the kept
+  if ((r = gemm128(c, theta, n, 1, 0, Vf, 1, n, 1, P, rc, m, rc, n, 1.0)) != MPS_OK) return r;
+  K1((colnorm2_kernel<<<g1d(rc), 256, 0, s>>>(P, m, rc, c2)));
+  K1((sqrt_kernel<<<g1d(rc), 256, 0, s>>>(c2, sv, rc)));
+  MPS_TRY_HIP(h, hipMemcpyAsync(sv, S, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // cotangents of V and S (U_bar folded in), the backward matrices, theta_bar = P Y
+  if (U_bar && (r = gemm128(c, U_bar, 1, ld_ubar, 1, theta, n, 1, 0, Wt, n, k, n, m, 1.0)) != MPS_OK) return r;
+  K1((fill_zero_kernel<<<g1d((long long)n * rc), 256, 0, s>>>(Vb, (long long)n * rc)));
+  K1((trunc_bar_kernel<<<k, 256, 0, s>>>((const double2*)Vh_bar, S_bar, U_bar ? Wt : nullptr, Vf, sv, eta, n, rc,
+                                          Vb, sbar)));
+  if ((r = gemm128(c, Vf, n, 1, 0, Vb, rc, 1, 0, Jv, rc, rc, rc, n, 1.0)) != MPS_OK) return r;
+  K1((svd_x_kernel<<<g1d((long long)rc * rc), 256, 0, s>>>(Jv, sv, sbar, rc, k, eta, Xm)));
+  if ((r = gemm128(c, Xm, rc, 1, 0, Vf, n, 1, 0, Y1, n, rc, n, rc, 1.0)) != MPS_OK) return r;
+  if ((r = gemm128(c, Jv, 1, rc, 1, Vf, n, 1, 0, Z2, n, rc, n, rc, 1.0)) != MPS_OK) return r;
+  K1((svd_y_kernel<<<g1d((long long)rc * n), 256, 0, s>>>(Y1, Z2, Vb, sv, rc, k, n, eta, Y)));
+  if ((r = gemm128(c, P, rc, 1, 0, Y, n, 1, 0, theta_bar, n, m, n, rc, 1.0)) != MPS_OK) return r;
+  if (U_bar) {
+    // theta_bar += U_bar diag(w) V_k^dag, the direct term of U = theta V_k S^-1
+    K1((col_inv_scale_kernel<<<g1d((long long)m * k), 256, 0, s>>>((const double2*)U_bar, (int)ld_ubar, m, k, sv, eta,
+                                                                     Us)));
+    if ((r = gemm128(c, Us, k, 1, 0, Vf, n, 1, 0, Z, n, m, n, k, 1.0)) != MPS_OK) return r;
+    K1((axpy_kernel<<<g1d((long long)mn), 256, 0, s>>>(Z, (double2*)theta_bar, (long long)mn, 1.0)));
   }
   return MPS_OK;
 }

@@ -9,6 +9,11 @@ through the C ABI.
   discarded weight of every update in order (R10: |dw| <= 1e-12 + 1e-6 w),
   adds up to the chains' per-bond accumulators, and a captured step logs the
   same as the eager one.
+* mps_theta_gate_vjp and mps_truncate_vjp (the two pieces of one update's
+  reverse pass) against the oracle's reverse mode of the theta' definition
+  (1e-13 of the largest entry) and its truncated-SVD backward (1e-10
+  relative), the latter with the cotangents of a gauge-invariant loss of
+  (U, S, Vh) taken by each side in its own gauge.
 * mps_tebd_step_vjp after a checkpointed batched TEBD2 run: for state
   cotangents built from a weighted sum of <S^z_i> of each chain's final
   state, dL/dJ equals the oracle's reverse-mode gradient of that loss
@@ -187,3 +192,106 @@ def test_checkpointed_vjp_matches_oracle_and_single_chain(H):
         print(f"[boundary] chain L={sp.L}: rel vs oracle {rel:.2e}, vs single-chain adjoint {rel1:.2e}", flush=True)
         assert rel <= 1e-6 and rel1 <= 1e-10
         assert np.all(dJ[c, sp.L - 1:] == 0.0)
+
+
+def _unitary(n, seed):
+    q, _ = np.linalg.qr(W.random_complex((n, n), seed))
+    return q
+
+
+@pytest.mark.parametrize("chl,d,chm,chr_", [(37, 2, 50, 29), (8, 3, 21, 13), (64, 2, 128, 64)])
+def test_theta_gate_vjp_matches_oracle(H, chl, d, chm, chr_):
+    from oracle import grad
+    from paper_1703_00387_amd import api
+    seed = (101, chl, d, chm)
+    Bl = W.random_complex((chl, d, chm), seed + (0,))
+    Br = W.random_complex((chm, d, chr_), seed + (1,))
+    G = W.random_complex((d * d, d * d), seed + (2,))
+    tb = W.random_complex((chl * d, d * chr_), seed + (3,))
+    lam = W.random_real((chl,), seed + (4,), 0.1, 1.0)
+    want = grad.theta_gate_vjp(Bl, Br, lam, G, tb)
+    cu = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    print(f"[boundary] theta_gate_vjp {chl}x{d}x{chm}x{chr_}", flush=True)
+    got = api.theta_gate_vjp(H, cu(Bl), cu(Br), cu(lam), cu(G), cu(tb))
+    torch.cuda.synchronize()
+    for name, g, w in zip(("dBl", "dBr", "dlam", "dG"), got, want):
+        g = g.cpu().numpy()
+        err = np.abs(g - w).max() / np.abs(w).max()
+        assert err <= 1e-13, (name, err)
+
+
+def _spectral(m, n, s, seed):
+    r = len(s)
+    return (_unitary(m, seed + (0,))[:, :r] * s[None, :]) @ _unitary(n, seed + (1,))[:r, :]
+
+
+@pytest.mark.parametrize("m,n,k,cots,eta", [(96, 64, 20, "usv", 0.0), (64, 150, 30, "usv", 0.0),
+                                            (130, 130, 130, "usv", 0.0), (200, 120, 1, "usv", 0.0),
+                                            (160, 96, 40, "sv", 1e-12), (80, 200, 24, "v", 0.0)])
+def test_truncate_vjp_matches_oracle(H, m, n, k, cots, eta):
+    """mps_truncate_vjp against the oracle's truncated-SVD backward, each side
+    taking the cotangents of one gauge-invariant loss in its own gauge."""
+    from oracle import grad
+    from paper_1703_00387_amd import api
+    seed = (111, m, n, k)
+    r = min(m, n)
+    s = np.geomspace(1.0, 1e-2, r)          # gaps s_i^2 - s_{i+1}^2 >= 0.07 s_i^2
+    A0 = _spectral(m, n, s, seed)
+    M = W.random_complex((m, m), seed + (2,))
+    N = W.random_complex((n, n), seed + (3,))
+    K = W.random_complex((m, n), seed + (4,))
+    c = W.random_real((k,), seed + (5,), -1.0, 1.0)
+    w = W.random_real((k,), seed + (6,), -1.0, 1.0)
+
+    def loss(U, sv, Vh):
+        t = torch.tensor
+        out = torch.zeros((), dtype=torch.float64)
+        if "u" in cots:
+            out = out + torch.real(torch.einsum("rj,rq,qj->", U.conj(), t(M), U))
+            out = out + torch.real(torch.sum(t(K).conj() * ((U * t(c)[None, :]) @ Vh)))
+        if "s" in cots:
+            out = out + torch.sum(t(w) * sv ** 3)
+        if "v" in cots:
+            out = out + torch.real(torch.einsum("jc,cd,jd->", Vh, t(N), Vh.conj()))
+        return out
+
+    A = torch.tensor(A0, requires_grad=True)
+    loss(*grad.TruncSVD.apply(A, k, eta)).backward()
+    want = A.grad.numpy()
+    Ad = torch.from_numpy(A0).cuda()
+    print(f"[boundary] truncate_vjp {m}x{n} k={k} cotangents {cots} eta {eta}", flush=True)
+    U, S, Vh, kk, _, _ = H.truncate(Ad, k, -1.0)
+    assert kk == k
+    leaves = [x.detach().cpu().clone().requires_grad_(True) for x in (U, S, Vh)]
+    loss(*leaves).backward()
+    bars = [x.grad.cuda().contiguous() if x.grad is not None else None for x in leaves]
+    got = api.truncate_vjp(H, Ad, S.contiguous(), Vh.contiguous(), bars[0] if "u" in cots else None,
+                           bars[1] if "s" in cots else None, bars[2], eta=eta).cpu().numpy()
+    code, word = H.device_status()
+    assert code == 0 and word == 0, (code, word)
+    assert np.isfinite(got).all()
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    # the backward divides by the gaps s_i^2 - s_j^2 >= 0.07 s_i^2 (s >= 1e-2):
+    # SVD errors of 1e-16 |theta| grow to about 1e-16 / (0.07e-4) = 1.4e-11
+    print(f"[boundary]   rel {err:.2e}", flush=True)
+    assert err <= 1e-9
+
+
+def test_jacobi_absolute_tolerance_floor(H):
+    from paper_1703_00387_amd import _lib
+    with pytest.raises(_lib.MPSError) as e:
+        H.set_option(2, 0.0)
+    assert e.value.code == _lib.MPS_ERR_INVALID
+    H.set_option(2, 1e-30)
+    # a residual with more rows than columns: every row comes back finite
+    m, n, k = 96, 64, 20
+    A0 = _spectral(m, n, np.geomspace(1.0, 1e-2, n), (113,))
+    _, _, Vh = np.linalg.svd(A0, full_matrices=False)
+    R = A0 - (A0 @ Vh[:k].conj().T) @ Vh[:k]
+    try:
+        U, S, V, kk, _, _ = H.truncate(torch.from_numpy(R).cuda(), n - k, -1.0)
+        assert kk == n - k and torch.isfinite(torch.view_as_real(V)).all().item()
+        np.testing.assert_allclose(S.cpu().numpy(), np.linalg.svd(R, compute_uv=False)[:n - k], rtol=1e-12,
+                                   atol=1e-15)
+    finally:
+        H.set_option(2, 1e-15)

@@ -79,3 +79,67 @@ def test_broadening_sensitivity_small():
     gs = [grad.reverse_gradient(spec, 0.05, 6, 8, 1e-12, eta=eta)[1] for eta in (1e-10, 1e-12, 1e-14)]
     for g in gs[1:]:
         assert np.linalg.norm(g - gs[0]) / np.linalg.norm(gs[0]) < 1e-6
+
+
+def test_truncsvd_backward_all_cotangents_fd():
+    # truncated (k = 3 of 5), m > n, a loss that uses U, s and Vh each on
+    # their own (gauge invariant): every cotangent of the backward is exercised
+    rng = np.random.default_rng(2)
+    A0 = rng.normal(size=(9, 5)) + 1j * rng.normal(size=(9, 5))
+    M = rng.normal(size=(9, 9)) + 1j * rng.normal(size=(9, 9))
+    N = rng.normal(size=(5, 5)) + 1j * rng.normal(size=(5, 5))
+    K = rng.normal(size=(9, 5)) + 1j * rng.normal(size=(9, 5))
+    c = np.array([0.7, -1.3, 0.4])
+
+    def loss(U, s, Vh):
+        t = torch.tensor
+        return (torch.real(torch.einsum("rj,rq,qj->", U.conj(), t(M), U))
+                + torch.sum(s ** 3)
+                + torch.real(torch.einsum("jc,cd,jd->", Vh, t(N), Vh.conj()))
+                + torch.real(torch.sum(t(K).conj() * ((U * t(c)[None, :]) @ Vh))))
+
+    def f(Anp):
+        return float(loss(*grad.TruncSVD.apply(torch.tensor(Anp), 3, 0.0)))
+
+    A = torch.tensor(A0, requires_grad=True)
+    loss(*grad.TruncSVD.apply(A, 3, 0.0)).backward()
+    g = A.grad.numpy()
+    h = 1e-6
+    for (i, j) in [(0, 0), (4, 2), (8, 4), (6, 1)]:
+        for unit in (1.0, 1j):
+            E = np.zeros_like(A0)
+            E[i, j] = unit * h
+            fd = (f(A0 + E) - f(A0 - E)) / (2 * h)
+            an = np.real(np.conj(g[i, j]) * unit)
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(fd)), (i, j, unit, fd, an)
+
+
+def test_theta_gate_vjp_fd():
+    # the reverse mode of the theta' definition against central differences of
+    # L = Re <W, theta'> in every input (real and imaginary directions)
+    rng = np.random.default_rng(3)
+    chl, d, chm, chr_ = 3, 2, 4, 2
+    cplx = lambda *sh: rng.normal(size=sh) + 1j * rng.normal(size=sh)
+    Bl, Br, G, Wt = cplx(chl, d, chm), cplx(chm, d, chr_), cplx(d * d, d * d), cplx(chl * d, d * chr_)
+    lam = rng.uniform(0.2, 1.0, size=chl)
+    got = grad.theta_gate_vjp(Bl, Br, lam, G, Wt)
+
+    def f(args):
+        tp = grad.theta_gate_torch(*[torch.tensor(a) for a in args]).numpy()
+        return float(np.real(np.sum(np.conj(Wt) * tp)))
+
+    base = [Bl, Br, lam, G]
+    h = 1e-6
+    for which, idx in [(0, (2, 1, 3)), (0, (0, 0, 0)), (1, (3, 1, 1)), (1, (1, 0, 0)), (2, (1,)), (3, (2, 1)),
+                       (3, (0, 3))]:
+        units = (1.0,) if which == 2 else (1.0, 1j)
+        for unit in units:
+            plus = [x.copy() for x in base]
+            minus = [x.copy() for x in base]
+            plus[which] = plus[which].astype(np.complex128 if which != 2 else np.float64)
+            minus[which] = minus[which].astype(plus[which].dtype)
+            plus[which][idx] += unit * h
+            minus[which][idx] -= unit * h
+            fd = (f(plus) - f(minus)) / (2 * h)
+            an = np.real(np.conj(got[which][idx]) * unit)
+            assert abs(fd - an) < 1e-7 * max(1.0, abs(fd)), (which, idx, unit, fd, an)
