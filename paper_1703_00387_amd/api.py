@@ -543,6 +543,54 @@ class TebdObservables(torch.autograd.Function):
         return (dJ.to(J.dtype),) + (None,) * 10
 
 
+class TebdStep(torch.autograd.Function):
+    """Final Hastings-form states of a batched TEBD2 run as a differentiable
+    function of the per-bond couplings J [n_chains, L_max-1] (chain c has
+    h_b = J[c, b] h0[c][b]), from product states:
+
+        outs = TebdStep.apply(J, h, vectors, chi_max, h0, dt, n_steps, eps, eta)
+
+    vectors[c] and h0[c] are chain c's initial site vectors and unit bond
+    terms (complex128 [L_c-1][d^2][d^2]).  outs = (B_0, lam_0, chi_0, B_1,
+    ...) in the capacity layout of Chain; chi_c is not differentiable.  The
+    forward runs mps_tebd_step_ex with MPS_FLAG_CHECKPOINT, the backward
+    mps_tebd_step_vjp on that checkpoint with the incoming cotangents of the
+    B and lam (zero where None).  Complex128 chains only."""
+
+    @staticmethod
+    def forward(ctx, J, h, vectors, chi_max, h0, dt, n_steps, eps, eta=1e-12):
+        n = len(vectors)
+        if J.dim() != 2 or J.shape[0] != n:
+            raise ValueError("J must be [n_chains, L_max-1]")
+        dev = J.device
+        h0d = [torch.as_tensor(np.ascontiguousarray(x), dtype=torch.complex128).to(dev).contiguous() for x in h0]
+        chains = []
+        for c in range(n):
+            L = len(vectors[c])
+            if h0d[c].shape[0] != L - 1 or J.shape[1] < L - 1:
+                raise ValueError("h0[c] needs L_c-1 bond terms and J at least L_c-1 columns")
+            hb = J.detach()[c, :L - 1].to(torch.complex128)[:, None, None] * h0d[c]
+            chains.append(Chain.product(vectors[c], chi_max, hb.cpu().numpy(), device=dev, dtype="c128"))
+        ck = torch.zeros(tebd_ckpt_bytes(chains, n_steps), dtype=torch.uint8, device=dev)
+        tebd_step_ex(h, chains, 2, dt, n_steps, eps, flags=_lib.MPS_FLAG_CHECKPOINT, ckpt=ck)
+        ctx.state = (h, chains, h0d, ck, eta, J.shape[1])
+        outs = []
+        for ch in chains:
+            outs += [ch.B.clone(), ch.lam.clone(), ch.chi.clone()]
+        ctx.mark_non_differentiable(*outs[2::3])
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        h, chains, h0d, ck, eta, width = ctx.state
+        dB = [g.contiguous() if g is not None else torch.zeros_like(ch.B) for g, ch in zip(grads[0::3], chains)]
+        dl = [g.contiguous() if g is not None else torch.zeros_like(ch.lam) for g, ch in zip(grads[1::3], chains)]
+        dJ = tebd_step_vjp(h, chains, h0d, ck, dB, dl, eta)
+        out = torch.zeros((len(chains), width), dtype=torch.float64, device=dJ.device)
+        out[:, :dJ.shape[1]] = dJ
+        return (out,) + (None,) * 8
+
+
 def autotune(h: Handle, n_mats: int, m: int, n: int, apply: bool = True, cache: str = None):
     """Time the Jacobi launch configurations on a seeded synthetic batch of
     n_mats m x n matrices (mps_autotune_jacobi) and, with apply, leave the

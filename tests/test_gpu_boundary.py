@@ -17,7 +17,9 @@ through the C ABI.
 * mps_tebd_step_vjp after a checkpointed batched TEBD2 run: for state
   cotangents built from a weighted sum of <S^z_i> of each chain's final
   state, dL/dJ equals the oracle's reverse-mode gradient of that loss
-  (1e-6 relative) and the single-chain adjoint mps_tebd_vjp (1e-10 relative).
+  (1e-6 relative) and the single-chain adjoint mps_tebd_vjp (1e-10 relative);
+  api.TebdStep gives the same gradient through torch.autograd for a loss
+  that torch computes from the final states.
 """
 import copy
 
@@ -295,3 +297,48 @@ def test_jacobi_absolute_tolerance_floor(H):
                                    atol=1e-15)
     finally:
         H.set_option(2, 1e-15)
+
+
+def test_tebd_step_autograd_function(H):
+    """api.TebdStep (forward: checkpointed batched TEBD2, backward:
+    mps_tebd_step_vjp) under torch.autograd, for a loss computed by torch
+    from the final states, against the oracle's reverse-mode gradient."""
+    from oracle import grad, models as om
+    from paper_1703_00387_amd import api, models
+    dt, n_steps, chi, eps = 0.05, 5, 8, 1e-12
+    specs = [W.xxz_chain(L, chi, 1.0, 0.5, J_b=W.xxz_grad_couplings(L)) for L in (8, 6)]
+    h0s = []
+    for sp in specs:
+        unit = copy.copy(sp)
+        unit.J_b = np.ones(sp.L - 1)
+        h0s.append(np.ascontiguousarray(models.bond_hamiltonians(unit)))
+    Jn = np.zeros((2, 7))
+    for c, sp in enumerate(specs):
+        Jn[c, :sp.L - 1] = sp.J_b
+    J = torch.tensor(Jn, device="cuda", requires_grad=True)
+    sz = 0.5 * om.SZ
+    szt = torch.from_numpy(sz.astype(np.complex128)).cuda()
+    weights = [W.random_real((sp.L,), (93, c), -1.0, 1.0) for c, sp in enumerate(specs)]
+    print("[boundary] TebdStep forward", flush=True)
+    outs = api.TebdStep.apply(J, H, [W.initial_vectors(sp) for sp in specs], chi, h0s, dt, n_steps, eps, 1e-12)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    for c, sp in enumerate(specs):
+        B, lam, chis = outs[3 * c], outs[3 * c + 1], outs[3 * c + 2].cpu().numpy()
+        for i in range(sp.L):
+            a, r = int(chis[i]), int(chis[i + 1])
+            Bi = B[i, :a, :, :r]
+            OB = torch.einsum("st,atc->asc", szt, Bi)
+            loss = loss + weights[c][i] * torch.sum(lam[i, :a] ** 2 * torch.real(torch.einsum("asc,asc->a",
+                                                                                              Bi.conj(), OB)))
+    print("[boundary] TebdStep backward", flush=True)
+    loss.backward()
+    g = J.grad.cpu().numpy()
+    for c, sp in enumerate(specs):
+        Jt = torch.tensor(np.asarray(sp.J_b, dtype=np.float64), requires_grad=True)
+        Bt, lt = grad.tebd2_state_torch(sp, Jt, dt, n_steps, chi, eps, 1e-12)
+        lo = sum(weights[c][i] * grad.site_expect_torch(Bt, lt, sz, i) for i in range(sp.L))
+        lo.backward()
+        rel = np.linalg.norm(g[c, :sp.L - 1] - Jt.grad.numpy()) / np.linalg.norm(Jt.grad.numpy())
+        print(f"[boundary] TebdStep chain L={sp.L}: rel {rel:.2e}", flush=True)
+        assert rel <= 1e-6
+        assert np.all(g[c, sp.L - 1:] == 0.0)
