@@ -847,6 +847,7 @@ def bench_batch(args):
         t_eager = timed(0, args.steps)
         after_eager = [c.chi.clone() for c in chains]
         print(f"[bench] batched eager: {t_eager:.2f}s for {args.steps} steps", file=sys.stderr, flush=True)
+        t_capture = timed(_lib.MPS_FLAG_GRAPH, 1)      # captures the step (kept by the handle)
         t_graph = timed(_lib.MPS_FLAG_GRAPH, args.steps)
         print(f"[bench] batched graph: {t_graph:.2f}s for {args.steps} steps", file=sys.stderr, flush=True)
         plain_steps = 1
@@ -866,7 +867,8 @@ def bench_batch(args):
                       "updates_per_step": upd, "chi_max_now": max(int(c.chi.max()) for c in chains),
                       "split": args.split},
            "batched_eager": {"ms_per_step": round(t_eager * 1e3 / args.steps, 3)},
-           "batched_graph": {"ms_per_step": round(t_graph * 1e3 / args.steps, 3)},
+           "batched_graph": {"ms_per_step": round(t_graph * 1e3 / args.steps, 3),
+                             "first_call_with_capture_ms": round(t_capture * 1e3, 3)},
            "plain": None if t_plain is None else
            {"value": round(upd * plain_steps / t_plain, 2), "ms_per_step": round(t_plain * 1e3 / plain_steps, 3)},
            "speedup_vs_plain": None if t_plain is None else round((t_plain / plain_steps) / (t_best / args.steps), 2),

@@ -271,7 +271,10 @@ typedef struct {
   double* disc;
 } mps_chain_desc;
 
-#define MPS_FLAG_GRAPH 0x1u     /* capture the whole call in a hipGraph and replay it */
+#define MPS_FLAG_GRAPH 0x1u     /* capture one step in a hipGraph and replay it n_steps times; the handle
+                                   keeps the last captured step and replays it, with no new capture, on a
+                                   later call with the same chains (pointers and shapes), order, dt,
+                                   eps_local, log and Jacobi options */
 #define MPS_FLAG_FIXED_SWEEPS 0x2u /* no host synchronisation inside the call */
 #define MPS_FLAG_PLAIN 0x4u     /* one bond per launch sequence (no batching; comparison form) */
 #define MPS_FLAG_CHECKPOINT 0x8u /* mps_tebd_step_ex: keep every step's chains for mps_tebd_step_vjp */

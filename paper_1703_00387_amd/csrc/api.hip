@@ -444,6 +444,8 @@ mps_status mps_destroy(mps_handle h) {
   for (auto e : h->ev_pool) hipEventDestroy(e);
   for (auto e : h->aux_ev) hipEventDestroy(e);
   for (auto st : h->aux) hipStreamDestroy(st);
+  if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) hipGraphDestroy(h->graph);
   if (h->ws && !h->ws_external) hipFree(h->ws);
   if (h->split_part) hipFree(h->split_part);
   if (h->status_dev) hipFree(h->status_dev);
@@ -785,6 +787,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   size_t oUnc = p.take<int32_t>(8);
   size_t oRow = p.take<int32_t>(max_items * m_cap);
   size_t oNrm = p.take<double>(max_items * m_cap);
+  size_t oTiles = p.take<int32_t>(max_items + 1);   // tile lists of the fixed-grid launches
   // Krylov propagation: identity propagator, one propagator per chain, a job
   // per item, rho partials and Krylov histories per item of a layer
   const int kt_nblk = 32;
@@ -963,7 +966,10 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
         if (prof) prof_end(h, s, MPS_K_KRYLOV);
       }
       if (prof) prof_begin(h, s, MPS_K_THETA);
-      MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_eff, c128, stats));
+      // without host synchronisation the bond dimensions are only known on the
+      // device: the theta and write-back GEMM launches walk lists of real tiles
+      int32_t* tiles = fixed ? (int32_t*)(ws + oTiles) : nullptr;
+      MPS_TRY_HIP(h, launch_theta(s, it, n, d, chi_eff, c128, stats, nullptr, tiles));
       if (prof) prof_end(h, s, MPS_K_THETA);
       if (u1) {
         const size_t first = start[idx] + i0;
@@ -993,7 +999,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       }
       MPS_TRY_HIP(h, launch_wb_left_probs(s, it, n, sel, probs));
       if (prof) prof_begin(h, s, MPS_K_GEMM);
-      MPS_TRY_HIP(h, launch_gemm_bt_conj(s, probs, n, d * chl_eff, k_cap, c128, stats));
+      MPS_TRY_HIP(h, launch_gemm_bt_conj(s, probs, n, d * chl_eff, k_cap, c128, stats, tiles));
       if (prof) prof_end(h, s, MPS_K_GEMM);
       if (prof) {
         mps_status ps = prof_harvest(h, s);
@@ -1014,32 +1020,81 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
     if (checkpoint && (st = save_all(n_steps)) != MPS_OK) return st;
     return MPS_OK;
   }
-  hipGraph_t g = nullptr;
-  hipGraphExec_t ge = nullptr;
-  MPS_TRY_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  st = run_step();
-  hipError_t ec = hipStreamEndCapture(s, &g);
-  if (st != MPS_OK) {
-    if (g) hipGraphDestroy(g);
-    return st;
+  // Everything one step's launches depend on: the workspace and its plan, the
+  // chains, the schedule, the count rule and the solver options.  The gates
+  // and the bond items were rewritten into the workspace above, so a step
+  // captured with the same key replays unchanged.
+  std::vector<uint64_t> key;
+  auto put = [&](uint64_t v) { key.push_back(v); };
+  auto bits = [](double x) {
+    uint64_t u;
+    std::memcpy(&u, &x, sizeof(u));
+    return u;
+  };
+  put((uint64_t)(uintptr_t)ws);
+  put(p.off);
+  put((uint64_t)n_chains);
+  put((uint64_t)order);
+  put(flags);
+  put(bits(dt));
+  put(bits(eps_local));
+  put((uint64_t)(uintptr_t)disc_log);
+  put(kry ? (uint64_t)kry->n_max : 0);
+  put(kry ? bits(kry->tol) : 0);
+  put(kry ? (uint64_t)(uintptr_t)kry->n_used_dev : 0);
+  put(bits(h->jac_tol));
+  put(bits(h->jac_abs));
+  put((uint64_t)h->jac_max_sweeps);
+  put((uint64_t)h->jac_inner_sweeps);
+  put((uint64_t)h->jac_threads);
+  put((uint64_t)h->jac_split_below);
+  put((uint64_t)h->split_method);
+  put((uint64_t)h->jac_persistent);
+  for (int c = 0; c < n_chains; ++c) {
+    const mps_chain_desc& ch = chains[c];
+    put(((uint64_t)(uint32_t)ch.L << 32) | (uint32_t)ch.d);
+    put(((uint64_t)(uint32_t)ch.chi_max << 32) | (uint32_t)ch.dtype);
+    put((uint64_t)(uintptr_t)ch.B);
+    put((uint64_t)(uintptr_t)ch.lam);
+    put((uint64_t)(uintptr_t)ch.chi);
+    put((uint64_t)(uintptr_t)ch.hbond);
+    put((uint64_t)(uintptr_t)ch.disc);
   }
-  if (ec != hipSuccess) return mps_fail(h, MPS_ERR_HIP, std::string("capture: ") + hipGetErrorString(ec));
-  hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-  if (ei != hipSuccess) {
-    hipGraphDestroy(g);
-    return mps_fail(h, MPS_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(ei));
+  if (!h->graph_exec || key != h->graph_key) {
+    if (h->graph_exec) {
+      MPS_TRY_HIP(h, hipStreamSynchronize(s));
+      hipGraphExecDestroy(h->graph_exec);
+      h->graph_exec = nullptr;
+    }
+    if (h->graph) {
+      hipGraphDestroy(h->graph);
+      h->graph = nullptr;
+    }
+    h->graph_key.clear();
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    MPS_TRY_HIP(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    st = run_step();
+    hipError_t ec = hipStreamEndCapture(s, &g);
+    if (st != MPS_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess) return mps_fail(h, MPS_ERR_HIP, std::string("capture: ") + hipGetErrorString(ec));
+    hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      hipGraphDestroy(g);
+      return mps_fail(h, MPS_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(ei));
+    }
+    h->graph = g;
+    h->graph_exec = ge;
+    h->graph_key = key;
   }
   for (int stp = 0; stp < n_steps; ++stp) {
-    hipError_t el = hipGraphLaunch(ge, s);
-    if (el != hipSuccess) {
-      hipGraphExecDestroy(ge);
-      hipGraphDestroy(g);
-      return mps_fail(h, MPS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(el));
-    }
+    hipError_t el = hipGraphLaunch(h->graph_exec, s);
+    if (el != hipSuccess) return mps_fail(h, MPS_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(el));
   }
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
-  hipGraphExecDestroy(ge);
-  hipGraphDestroy(g);
   return MPS_OK;
 }
 

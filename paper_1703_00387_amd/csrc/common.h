@@ -61,6 +61,11 @@ struct mps_context {
   // extra streams (default priority) for independent per-bond work, and events to fork/join them
   std::vector<hipStream_t> aux;
   std::vector<hipEvent_t> aux_ev;
+  // the last captured TEBD step (MPS_FLAG_GRAPH) and the launch parameters it
+  // was captured with: a call with the same parameters replays it
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint64_t> graph_key;
 };
 
 // Make `n` auxiliary streams available on the handle (created once, kept).
@@ -267,8 +272,13 @@ struct GemmProb {
 // launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 hipError_t launch_gates(hipStream_t s, const GateJob* jobs, int n, int dd);
+// Workgroups of the list-walking launches (theta and batched GEMM with
+// tile_offs): 8 per CU of the 256-CU device.
+constexpr int kListGrid = 2048;
+// tile_offs (optional, n_items + 1 int32 of device scratch): walk the list of
+// the bonds' real tiles with a fixed grid instead of a grid sized for chi_cap
 hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, bool c128,
-                        unsigned long long* stats, const void* G_override = nullptr);
+                        unsigned long long* stats, const void* G_override = nullptr, int32_t* tile_offs = nullptr);
 hipError_t launch_ktebd_identity(hipStream_t s, void* G, int dd, bool c128);
 hipError_t launch_ktebd_rho(hipStream_t s, const BondItem* items, const KryJob* jobs, int n_items, int d, int nblk);
 hipError_t launch_ktebd_krylov(hipStream_t s, const KryJob* jobs, int n_items, int d, int nblk, int n_max, double tol,
@@ -331,7 +341,7 @@ hipError_t launch_inc_int(hipStream_t s, int32_t* p);
 hipError_t launch_wb_left_probs(hipStream_t s, const BondItem* items, int n_items, const SelOut* sel,
                                 GemmProb* probs);
 hipError_t launch_gemm_bt_conj(hipStream_t s, const GemmProb* probs, int n_probs, int M_cap, int N_cap, bool c128,
-                               unsigned long long* stats);
+                               unsigned long long* stats, int32_t* tile_offs = nullptr);
 hipError_t launch_gemm_nn(hipStream_t s, const GemmProb* probs, int n_probs, int M_cap, int N_cap, bool c128,
                           unsigned long long* stats);
 hipError_t launch_truncate_out(hipStream_t s, const JacMat* mat, const int32_t* perm, const double* s2,

@@ -8,18 +8,20 @@
 // Each problem of the batch reads its own dimensions (possibly written by an
 // earlier kernel on the device); the grid is sized for the capacity and tiles
 // beyond a problem's dimensions return at once.
+#include <algorithm>
+
 #include "mfma_tile.h"
 
+__device__ __forceinline__ int gemm_dim_m(const GemmProb& P) { return P.M_dev ? P.M_mul * *P.M_dev : P.M; }
+__device__ __forceinline__ int gemm_dim_n(const GemmProb& P) { return P.N_dev ? P.N_mul * *P.N_dev : P.N; }
+
+// One output tile (tm, tn) of problem P; a tile past its dimensions returns.
 template <class T, bool BT>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmProb* __restrict__ probs, int ntn_cap,
-                                                   unsigned long long* stats) {
-  __shared__ T As[TBK * TLD];
-  __shared__ T Bs[TBK * TLD];
-  const GemmProb P = probs[blockIdx.y];
-  const int M = P.M_dev ? P.M_mul * *P.M_dev : P.M;
-  const int N = P.N_dev ? P.N_mul * *P.N_dev : P.N;
+__device__ __forceinline__ void gemm_tile(const GemmProb& P, int tm, int tn, unsigned long long* stats, T* As,
+                                          T* Bs) {
+  const int M = gemm_dim_m(P);
+  const int N = gemm_dim_n(P);
   const int K = P.K_dev ? P.K_mul * *P.K_dev : P.K;
-  const int tm = blockIdx.x / ntn_cap, tn = blockIdx.x % ntn_cap;
   const int m0 = tm * TBM, n0 = tn * TBN;
   if (m0 >= M || n0 >= N) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -88,10 +90,81 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmProb* __restrict__ 
       }
 }
 
+// Grid over (capacity tiles, problems).
+template <class T, bool BT>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmProb* __restrict__ probs, int ntn_cap,
+                                                   unsigned long long* stats) {
+  __shared__ T As[TBK * TLD];
+  __shared__ T Bs[TBK * TLD];
+  const GemmProb P = probs[blockIdx.y];
+  gemm_tile<T, BT>(P, blockIdx.x / ntn_cap, blockIdx.x % ntn_cap, stats, As, Bs);
+}
+
+// offs[i] = output tiles of the problems before i (dimensions read on the
+// device), offs[n] = total; one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void gemm_tile_offsets_kernel(const GemmProb* __restrict__ probs, int n,
+                                                                 int32_t* offs) {
+  __shared__ int part[1024];
+  const int per = (n + 1023) / 1024;
+  const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
+  auto count = [&](int i) {
+    const GemmProb& P = probs[i];
+    return ((gemm_dim_m(P) + TBM - 1) / TBM) * ((gemm_dim_n(P) + TBN - 1) / TBN);
+  };
+  int sum = 0;
+  for (int i = i0; i < i1; ++i) sum += count(i);
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+  for (int i = i0; i < i1; ++i) {
+    offs[i] = run;
+    run += count(i);
+  }
+  if (threadIdx.x == 1023) offs[n] = part[1023];
+}
+
+// A fixed grid walking the list of real tiles.
+template <class T, bool BT>
+__global__ __launch_bounds__(256) void gemm_list_kernel(const GemmProb* __restrict__ probs, int n,
+                                                        const int32_t* __restrict__ offs,
+                                                        unsigned long long* stats) {
+  __shared__ T As[TBK * TLD];
+  __shared__ T Bs[TBK * TLD];
+  const int total = offs[n];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = n - 1;   // the last problem whose first tile is <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const GemmProb P = probs[lo];
+    const int ntn = (gemm_dim_n(P) + TBN - 1) / TBN;
+    const int l = t - offs[lo];
+    gemm_tile<T, BT>(P, l / ntn, l % ntn, stats, As, Bs);
+    __syncthreads();
+  }
+}
+
 hipError_t launch_gemm_bt_conj(hipStream_t s, const GemmProb* probs, int n_probs, int M_cap, int N_cap, bool c128,
-                               unsigned long long* stats) {
+                               unsigned long long* stats, int32_t* tile_offs) {
   if (n_probs <= 0) return hipSuccess;
   int ntm = (M_cap + TBM - 1) / TBM, ntn = (N_cap + TBN - 1) / TBN;
+  if (tile_offs) {
+    gemm_tile_offsets_kernel<<<1, 1024, 0, s>>>(probs, n_probs, tile_offs);
+    const int grid = (int)std::min<long long>((long long)ntm * ntn * n_probs, kListGrid);
+    if (c128)
+      gemm_list_kernel<double2, true><<<grid, 256, 0, s>>>(probs, n_probs, tile_offs, stats);
+    else
+      gemm_list_kernel<float2, true><<<grid, 256, 0, s>>>(probs, n_probs, tile_offs, stats);
+    return hipGetLastError();
+  }
   dim3 grid(ntm * ntn, n_probs);
   if (c128)
     gemm_kernel<double2, true><<<grid, 256, 0, s>>>(probs, ntn, stats);

@@ -13,22 +13,28 @@
 //   T : theta~' in the chain's precision (kept for the write-back GEMM)
 //   X : theta'  complex128 (input of the FP64 SVD)
 // The chain precision T is complex64 (FP32 MFMA) or complex128 (FP64 MFMA).
+#include <algorithm>
+
 #include "mfma_tile.h"
 
+// two staging buffers (A and B tiles each), reused for the output tile
 template <class T>
-__global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restrict__ items, int d, int TA,
-                                                         int TC, int ntc_cap, unsigned long long* stats,
-                                                         const void* __restrict__ G_override) {
-  // two staging buffers (A and B tiles each), reused for the output tile
-  __shared__ T smem[TBM * (TBN + 1) > 4 * TBK * TLD ? TBM * (TBN + 1) : 4 * TBK * TLD];
-  __shared__ T Gs[25 * 25];  // the gate, d <= 5 (the chain limit)
+struct ThetaLds {
+  static constexpr int kElems = TBM * (TBN + 1) > 4 * TBK * TLD ? TBM * (TBN + 1) : 4 * TBK * TLD;
+};
+
+// One output tile (left block ta, right block tc) of item `it`; a tile past
+// the bond's dimensions returns at once.  smem holds ThetaLds<T>::kElems
+// elements, Gs 25 * 25 (the gate, d <= 5).
+template <class T>
+__device__ __forceinline__ void theta_tile(const BondItem& it, int d, int TA, int TC, int ta, int tc,
+                                           unsigned long long* stats, const void* __restrict__ G_override,
+                                           T* smem, T* Gs) {
   T* Cs = smem;  // reused after the K loop
   typedef typename Cx<T>::R R;
 
-  const BondItem it = items[blockIdx.y];
   const int chi_max = it.chi_max;
   const int chl = it.chi[it.b], chm = it.chi[it.b + 1], chr = it.chi[it.b + 2];
-  const int ta = blockIdx.x / ntc_cap, tc = blockIdx.x % ntc_cap;
   const int a0 = ta * TA, c0 = tc * TC;
   if (a0 >= chl || c0 >= chr) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -131,13 +137,90 @@ __global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restr
   }
 }
 
+// Grid over (capacity tiles, items): tiles past an item's dimensions return.
+template <class T>
+__global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restrict__ items, int d, int TA,
+                                                         int TC, int ntc_cap, unsigned long long* stats,
+                                                         const void* __restrict__ G_override) {
+  __shared__ T smem[ThetaLds<T>::kElems];
+  __shared__ T Gs[25 * 25];
+  const BondItem it = items[blockIdx.y];
+  theta_tile<T>(it, d, TA, TC, blockIdx.x / ntc_cap, blockIdx.x % ntc_cap, stats, G_override, smem, Gs);
+}
+
+// Number of output tiles of item i: ceil(chi_l / TA) * ceil(chi_r / TC) from
+// the bond dimensions on the device; offs[i] = sum of the counts before i,
+// offs[n] = total (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void theta_tile_offsets_kernel(const BondItem* __restrict__ items, int n, int TA,
+                                                                  int TC, int32_t* offs) {
+  __shared__ int part[1024];
+  const int per = (n + 1023) / 1024;
+  const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
+  auto count = [&](int i) {
+    const BondItem& it = items[i];
+    return ((it.chi[it.b] + TA - 1) / TA) * ((it.chi[it.b + 2] + TC - 1) / TC);
+  };
+  int sum = 0;
+  for (int i = i0; i < i1; ++i) sum += count(i);
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+  for (int i = i0; i < i1; ++i) {
+    offs[i] = run;
+    run += count(i);
+  }
+  if (threadIdx.x == 1023) offs[n] = part[1023];
+}
+
+// A fixed grid walking the list of real tiles (offs from the kernel above):
+// no workgroup is spent on capacity that the bonds do not use, so the grid
+// can be sized without knowing the bond dimensions on the host.
+template <class T>
+__global__ __launch_bounds__(256) void theta_gate_list_kernel(const BondItem* __restrict__ items, int n_items,
+                                                              const int32_t* __restrict__ offs, int d, int TA,
+                                                              int TC, unsigned long long* stats,
+                                                              const void* __restrict__ G_override) {
+  __shared__ T smem[ThetaLds<T>::kElems];
+  __shared__ T Gs[25 * 25];
+  const int total = offs[n_items];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = n_items - 1;   // the last item whose first tile is <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (offs[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BondItem it = items[lo];
+    const int ntc = (it.chi[it.b + 2] + TC - 1) / TC;
+    const int l = t - offs[lo];
+    theta_tile<T>(it, d, TA, TC, l / ntc, l % ntc, stats, G_override, smem, Gs);
+    __syncthreads();   // the next tile restages the gate and the staging buffers
+  }
+}
+
 // G_override (optional): one propagator used for every item instead of its own.
 hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, bool c128,
-                        unsigned long long* stats, const void* G_override) {
+                        unsigned long long* stats, const void* G_override, int32_t* tile_offs) {
   if (n_items <= 0) return hipSuccess;
   if (d < 1 || d > 5) return hipErrorInvalidValue;
   const int TA = TBM / d, TC = TBN / d;
   const int nta = (chi_cap + TA - 1) / TA, ntc = (chi_cap + TC - 1) / TC;
+  if (tile_offs) {
+    theta_tile_offsets_kernel<<<1, 1024, 0, s>>>(items, n_items, TA, TC, tile_offs);
+    const long long cap_tiles = (long long)nta * ntc * n_items;
+    const int grid = (int)std::min<long long>(cap_tiles, kListGrid);
+    if (c128)
+      theta_gate_list_kernel<double2><<<grid, 256, 0, s>>>(items, n_items, tile_offs, d, TA, TC, stats, G_override);
+    else
+      theta_gate_list_kernel<float2><<<grid, 256, 0, s>>>(items, n_items, tile_offs, d, TA, TC, stats, G_override);
+    return hipGetLastError();
+  }
   dim3 grid(nta * ntc, n_items);
   if (c128)
     theta_gate_kernel<double2><<<grid, 256, 0, s>>>(items, d, TA, TC, ntc, stats, G_override);

@@ -253,6 +253,27 @@ def test_graph_replay_equals_eager(H):
     assert torch.equal(eager.chi, g.chi)
     assert torch.equal(eager.B, g.B)
     assert torch.equal(eager.lam, g.lam)
+    # the handle keeps the captured step: a second call with the same chain,
+    # schedule and options replays it without a new capture; a changed option
+    # (or another chain) captures anew
+    with torch.cuda.stream(s):
+        api.tebd_step(H, [eager], 2, 0.05, 3, 1e-12, flags=0x2)
+        api.tebd_step(H, [g], 2, 0.05, 3, 1e-12, flags=0x1)
+        H.set_option(4, 2)
+        try:
+            api.tebd_step(H, [eager], 2, 0.05, 2, 1e-12, flags=0x2)
+            api.tebd_step(H, [g], 2, 0.05, 2, 1e-12, flags=0x1)
+        finally:
+            H.set_option(4, 1)
+        other = _gpu_chain(spec)
+        ref = _gpu_chain(spec)
+        api.tebd_step(H, [ref], 2, 0.05, 4, 1e-12, flags=0x2)
+        api.tebd_step(H, [other], 2, 0.05, 4, 1e-12, flags=0x1)
+    s.synchronize()
+    for a, b in ((eager, g), (ref, other)):
+        assert torch.equal(a.chi, b.chi)
+        assert torch.equal(a.B, b.B)
+        assert torch.equal(a.lam, b.lam)
 
 
 def test_argument_errors(H):
