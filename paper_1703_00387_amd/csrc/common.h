@@ -372,8 +372,11 @@ hipError_t launch_wmix_build(hipStream_t s, const void* W, void* Wm, int O1, int
                              int ws_o2, int ws_i1, int ws_i2, bool c128);
 hipError_t launch_mix(hipStream_t s, const MixDesc& D, const void* in, const void* Wm, void* out, bool c128);
 hipError_t launch_zero(hipStream_t s, double* a, int n);
+// Workgroups of the first stage of launch_mdot; part holds kMdotBlocks * nv
+// shares, which a second launch adds to out in a fixed order.
+constexpr int kMdotBlocks = 256;
 hipError_t launch_mdot(hipStream_t s, const double2* V, long long ldv, int nv, const double2* r, long long n,
-                       double2* out);
+                       double2* out, double2* part);
 hipError_t launch_msub(hipStream_t s, const double2* V, long long ldv, int nv, const double2* c, double2* r,
                        long long n);
 hipError_t launch_scale_inv_sqrt(hipStream_t s, const double2* x, double2* y, long long n, const double* norm2);

@@ -333,6 +333,7 @@ struct GradArena {
 struct GradItemBuf {
   double2 *T0, *T1, *P0, *Xj, *Vh, *Vb, *Y1, *Z, *Y, *Pm, *Pb, *T1b, *T0b, *Bnew, *Bbl, *Bnl, *Bbs, *Bns, *Jv, *Xm;
   double2* dot;  // [2]: <B_bar_b', B_b'> and the coupling overlap
+  double2* part; // kMdotBlocks shares of one overlap
   double *sv, *sbar, *c2, *kept2, *scal;
   int32_t* rd;
 };
@@ -350,9 +351,9 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
   const int ni = L / 2;  // bonds per layer
   const size_t r = (size_t)d * cm, mn = r * r, site_el = (size_t)cm * d * cm;
   WsPlan p;
-  std::vector<size_t> o((size_t)ni * 27);
+  std::vector<size_t> o((size_t)ni * 28);
   for (int i = 0; i < ni; ++i) {
-    size_t* q = &o[(size_t)i * 27];
+    size_t* q = &o[(size_t)i * 28];
     for (int j = 0; j < 16; ++j) q[j] = p.take<double2>(mn);
     for (int j = 16; j < 20; ++j) q[j] = p.take<double2>(site_el);
     q[20] = p.take<double2>(2);
@@ -362,6 +363,7 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
     q[24] = p.take<double>(r);
     q[25] = p.take<double>(4);
     q[26] = p.take<int32_t>(1);
+    q[27] = p.take<double2>(kMdotBlocks);
   }
   size_t oObs = p.take<double>(2 * (size_t)L);
   size_t oMat = p.take<JacMat>(ni), oSel = p.take<SelOut>(ni), oSeld = p.take<SelOut>(ni);
@@ -372,7 +374,7 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
   char* ws = h->ws;
   g.it.resize(ni);
   for (int i = 0; i < ni; ++i) {
-    const size_t* q = &o[(size_t)i * 27];
+    const size_t* q = &o[(size_t)i * 28];
     GradItemBuf& b = g.it[i];
     double2** mats[20] = {&b.T0, &b.T1, &b.P0, &b.Xj, &b.Vh, &b.Vb, &b.Y1, &b.Z, &b.Y, &b.Pm,
                           &b.Pb, &b.T1b, &b.T0b, &b.Bnew, &b.Jv, &b.Xm, &b.Bbl, &b.Bnl, &b.Bbs, &b.Bns};
@@ -384,6 +386,7 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
     b.kept2 = (double*)(ws + q[24]);
     b.scal = (double*)(ws + q[25]);
     b.rd = (int32_t*)(ws + q[26]);
+    b.part = (double2*)(ws + q[27]);
   }
   g.obs = (double*)(ws + oObs);
   g.mat = (JacMat*)(ws + oMat);
@@ -745,7 +748,7 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
         if ((r = gemm128(c, q.P0, n, 1, 0, q.Vh, 1, n, 1, q.Pm, rc, m, rc, n, 1.0)) != MPS_OK) return r;
         K1((colnorm2_kernel<<<g1d(rc), 256, 0, si>>>(q.Pm, m, rc, q.c2)));
         K1((fill_zero_kernel<<<1, 256, 0, si>>>(q.dot, 2)));
-        MPS_TRY_HIP(h, launch_mdot(si, q.Bbl, 0, 1, q.Bnew, (long long)m * k, q.dot));
+        MPS_TRY_HIP(h, launch_mdot(si, q.Bbl, 0, 1, q.Bnew, (long long)m * k, q.dot, q.part));
         K1((grad_scalars_kernel<<<1, 256, 0, si>>>(q.c2, lbm, q.dot, k, rc, q.sv, q.sbar, q.scal, h->status_dev)));
         // V_bar (n x rc): kept columns theta~'^dag B_bar_b' / n_k + conj(B_bar_{b+1}')^T
         K1((fill_zero_kernel<<<g1d((long long)n * rc), 256, 0, si>>>(q.Vb, (long long)n * rc)));
@@ -773,7 +776,7 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
         // coupling: J_bar_b += Re<theta~'_bar, dG/dJ_b theta~>
         K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, si>>>(dGp(cls, b), dd, q.T0, q.Z, chl, chr, 0,
                                                                            0)));
-        MPS_TRY_HIP(h, launch_mdot(si, q.T1b, 0, 1, q.Z, (long long)m * n, q.dot + 1));
+        MPS_TRY_HIP(h, launch_mdot(si, q.T1b, 0, 1, q.Z, (long long)m * n, q.dot + 1, q.part));
         K1((jbar_add_kernel<<<1, 1, 0, si>>>(q.dot + 1, dJ_dev, b)));
         // theta~_bar = G^dag theta~'_bar ; B_bar_b = theta~_bar B_{b+1}^dag ; B_bar_{b+1} = B_b^dag theta~_bar
         K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, si>>>(Gp(cls, b), dd, q.T1b, q.T0b, chl, chr, 1,

@@ -212,9 +212,11 @@ __global__ void zero_kernel(double* a, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0.0;
 }
 
-// out[i] += <V_i, r> for i < nv (complex, V_i = V + i*ldv), FP64 atomics
+// part[block][i] = this block's share of <V_i, r> for i < nv (complex,
+// V_i = V + i*ldv); a fixed grid-stride order, wave shuffles and a fixed
+// order over the waves, so the shares do not depend on scheduling
 __global__ __launch_bounds__(256) void mdot_kernel(const double2* __restrict__ V, long long ldv, int nv,
-                                                   const double2* __restrict__ r, long long n, double2* out) {
+                                                   const double2* __restrict__ r, long long n, double2* part) {
   __shared__ double red[2 * 32 * 4];
   double2 acc[32];
   for (int i = 0; i < nv; ++i) acc[i] = make_double2(0.0, 0.0);
@@ -246,9 +248,21 @@ __global__ __launch_bounds__(256) void mdot_kernel(const double2* __restrict__ V
       a += red[(i * 4 + w) * 2];
       b += red[(i * 4 + w) * 2 + 1];
     }
-    atomicAdd(&out[i].x, a);
-    atomicAdd(&out[i].y, b);
+    part[(long long)blockIdx.x * nv + i] = make_double2(a, b);
   }
+}
+
+// out[i] += sum over the blocks' shares, in block order (deterministic)
+__global__ void mdot_sum_kernel(const double2* __restrict__ part, int n_blocks, int nv, double2* out) {
+  const int i = threadIdx.x;
+  if (i >= nv) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < n_blocks; ++k) {
+    const double2 v = part[(long long)k * nv + i];
+    a += v.x;
+    b += v.y;
+  }
+  out[i] = make_double2(out[i].x + a, out[i].y + b);
 }
 
 // r -= sum_i c_i V_i ; if alpha_out: alpha_out[0] = Re c_{nv-1} (first pass only)
@@ -322,8 +336,11 @@ hipError_t launch_zero(hipStream_t s, double* a, int n) {
   return hipGetLastError();
 }
 hipError_t launch_mdot(hipStream_t s, const double2* V, long long ldv, int nv, const double2* r, long long n,
-                       double2* out) {
-  mdot_kernel<<<std::min(vgrid(n), 1024), 256, 0, s>>>(V, ldv, nv, r, n, out);
+                       double2* out, double2* part) {
+  if (nv < 1 || nv > 32) return hipErrorInvalidValue;
+  const int g = std::min(vgrid(n), kMdotBlocks);
+  mdot_kernel<<<g, 256, 0, s>>>(V, ldv, nv, r, n, part);
+  mdot_sum_kernel<<<1, 64, 0, s>>>(part, g, nv, out);
   return hipGetLastError();
 }
 hipError_t launch_msub(hipStream_t s, const double2* V, long long ldv, int nv, const double2* c, double2* r,

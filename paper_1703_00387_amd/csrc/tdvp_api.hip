@@ -33,6 +33,7 @@ struct KryBufs {
   void* xin;       // dtype copies for the complex64 apply
   void* yout;
   double2* dots;   // 32
+  double2* part;   // kMdotBlocks * 32 shares of the overlaps
   double* alpha;   // 32
   double* beta;    // 32
   double2* u;      // 32
@@ -162,7 +163,7 @@ mps_status krylov_int(mps_handle h, hipStream_t s, bool c128, const void* L, con
   const long long N = (long long)chl * d1 * (W2 ? d2 : 1) * chr;
   double2 hd[32];
   MPS_TRY_HIP(h, launch_zero(s, (double*)k.dots, 64));
-  MPS_TRY_HIP(h, launch_mdot(s, x, N, 1, x, N, k.dots));
+  MPS_TRY_HIP(h, launch_mdot(s, x, N, 1, x, N, k.dots, k.part));
   MPS_TRY_HIP(h, hipMemcpyAsync(hd, k.dots, sizeof(double2), hipMemcpyDeviceToHost, s));
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
   const double nrm = std::sqrt(std::max(hd[0].x, 0.0));
@@ -190,7 +191,7 @@ mps_status krylov_int(mps_handle h, hipStream_t s, bool c128, const void* L, con
     // full Gram-Schmidt against every Krylov vector
     for (int pass = 0; pass < 3; ++pass) {
       MPS_TRY_HIP(h, launch_zero(s, (double*)k.dots, 64));
-      MPS_TRY_HIP(h, launch_mdot(s, k.V, k.ldv, j + 1, k.r, N, k.dots));
+      MPS_TRY_HIP(h, launch_mdot(s, k.V, k.ldv, j + 1, k.r, N, k.dots, k.part));
       if (pass == 0) {
         MPS_TRY_HIP(h, hipMemcpyAsync(hd, k.dots, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, s));
         MPS_TRY_HIP(h, hipStreamSynchronize(s));
@@ -199,7 +200,7 @@ mps_status krylov_int(mps_handle h, hipStream_t s, bool c128, const void* L, con
       MPS_TRY_HIP(h, launch_msub(s, k.V, k.ldv, j + 1, k.dots, k.r, N));
     }
     MPS_TRY_HIP(h, launch_zero(s, (double*)k.dots, 64));
-    MPS_TRY_HIP(h, launch_mdot(s, k.r, N, 1, k.r, N, k.dots));
+    MPS_TRY_HIP(h, launch_mdot(s, k.r, N, 1, k.r, N, k.dots, k.part));
     MPS_TRY_HIP(h, hipMemcpyAsync(hd, k.dots, sizeof(double2), hipMemcpyDeviceToHost, s));
     MPS_TRY_HIP(h, hipStreamSynchronize(s));
     const double bj = std::sqrt(std::max(hd[0].x, 0.0));
@@ -275,7 +276,7 @@ mps_status tdvp_workspace(mps_handle h, bool c128, int chi_max, int d, int w, in
   size_t o_V = p.take<double2>((size_t)(n_max + 1) * Nmax);
   size_t o_r = p.take<double2>(Nmax);
   size_t o_xin = p.take<char>(Nmax * es), o_yout = p.take<char>(Nmax * es);
-  size_t o_dots = p.take<double2>(32), o_al = p.take<double>(32), o_be = p.take<double>(32);
+  size_t o_dots = p.take<double2>(32), o_part = p.take<double2>((size_t)kMdotBlocks * 32), o_al = p.take<double>(32), o_be = p.take<double>(32);
   size_t o_u = p.take<double2>(32), o_err = p.take<double>(4);
   size_t o_th = p.take<double2>(Nmax), o_thd = p.take<char>(Nmax * es), o_Xj = p.take<double2>(Nmax);
   size_t o_mat = p.take<JacMat>(1), o_rm = p.take<int32_t>(m_cap), o_pm = p.take<int32_t>(m_cap),
@@ -295,6 +296,7 @@ mps_status tdvp_workspace(mps_handle h, bool c128, int chi_max, int d, int w, in
   t.kb.xin = ws + o_xin;
   t.kb.yout = ws + o_yout;
   t.kb.dots = (double2*)(ws + o_dots);
+  t.kb.part = (double2*)(ws + o_part);
   t.kb.alpha = (double*)(ws + o_al);
   t.kb.beta = (double*)(ws + o_be);
   t.kb.u = (double2*)(ws + o_u);
@@ -423,7 +425,7 @@ mps_status mps_krylov_expm(mps_handle h, mps_stream stream, int32_t dtype, const
   size_t o4 = p.take<char>(1024 * es), o5 = p.take<char>(1024 * es);
   size_t oV = p.take<double2>((size_t)(n_max + 1) * N), oR = p.take<double2>(N);
   size_t oi = p.take<char>(N * es), oo = p.take<char>(N * es);
-  size_t od = p.take<double2>(32), oa = p.take<double>(32), ob = p.take<double>(32), ou = p.take<double2>(32),
+  size_t od = p.take<double2>(32), opart = p.take<double2>((size_t)kMdotBlocks * 32), oa = p.take<double>(32), ob = p.take<double>(32), ou = p.take<double2>(32),
          oe = p.take<double>(4), ox = p.take<double2>(N);
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
@@ -435,6 +437,7 @@ mps_status mps_krylov_expm(mps_handle h, mps_stream stream, int32_t dtype, const
   k.xin = ws + oi;
   k.yout = ws + oo;
   k.dots = (double2*)(ws + od);
+  k.part = (double2*)(ws + opart);
   k.alpha = (double*)(ws + oa);
   k.beta = (double*)(ws + ob);
   k.u = (double2*)(ws + ou);

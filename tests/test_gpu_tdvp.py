@@ -118,3 +118,23 @@ def test_tdvp2_step_matches_oracle(H, spec, dt, steps, chi):
     ov = abs(np.vdot(vg, vo)) / (np.linalg.norm(vg) * np.linalg.norm(vo))
     assert 1 - ov <= 1e-9, 1 - ov
     assert abs(np.linalg.norm(vg) - np.linalg.norm(vo)) <= 1e-9
+
+
+def test_krylov_expm_is_deterministic(H):
+    """The Lanczos overlaps are reduced in a fixed order (per-block shares,
+    then one ordered sum): repeated runs on the same input agree bit for bit."""
+    from paper_1703_00387_amd import api
+    chi, d, w = 64, 3, 4
+    Lenv = W.random_complex((chi, w, chi), (61,))
+    Wm = W.random_complex((w, w, d, d), (62,))
+    Renv = W.random_complex((chi, w, chi), (63,))
+    x0 = W.random_complex((chi, d, d, chi), (64,))
+    outs = []
+    for _ in range(3):
+        x = _t(x0)
+        n, err = api.krylov_expm(H, _t(Lenv), _t(Wm), _t(Wm), _t(Renv), x, 0.01, 12, 0.0)
+        torch.cuda.synchronize()
+        outs.append((x.cpu(), n, err))
+    H.device_status()    # a tolerance of 0 leaves the non-converged bit
+    for x, n, err in outs[1:]:
+        assert torch.equal(x, outs[0][0]) and n == outs[0][1] and err == outs[0][2]
