@@ -164,6 +164,36 @@ mps_status mps_autotune_jacobi(mps_handle h, mps_stream stream, int32_t n_mats, 
                                int32_t apply, double* times_ms, int32_t* n_candidates, int32_t* best);
 mps_status mps_autotune_candidate(int32_t m, int32_t index, int32_t* threads, int32_t* split_below,
                                   int32_t* method);
+/*
+ * Autotuner for the MFMA tile shape of the GEMMs (the contractions of the
+ * effective-Hamiltonian apply, App. "Details of the Krylov method", and of
+ * the Hastings write-back, Sec. "Basic concepts").  Every candidate tile,
+ * (32 MI) x (32 NJ) per 256-thread workgroup of 2 x 2 waves, with
+ * (MI, NJ) in {(2,2), (4,2), (2,4), (1,2), (2,1), (1,1)}, runs the product
+ * on synthetic operands in `dtype` (one untimed run, then the mean of five
+ * timed with HIP events on `stream`); with `apply` the fastest becomes the
+ * tile of its bucket.  A bucket is (kind, precision, shape class of M x N):
+ * at most 64 tiles of 64 x 64, tall (M >= 2N), wide (N >= 2M), or square.
+ * The choice is process-wide (all handles and devices of the process).
+ *   kind  : 0 = the strided GEMM (C = A B, A [M][K], B [K][N], batch 1);
+ *           1 = the batched write-back GEMM (C_i = A_i B_i^dag, B_i [N][K],
+ *               `batch` problems)
+ *   times_ms, n_candidates, best : as for mps_autotune_jacobi (6 candidates)
+ * Every tile shape sums each output element over K in the same order, so
+ * the results do not depend on the choice.  Uses the workspace; synchronises
+ * `stream`.  Errors: MPS_ERR_INVALID for a bad kind or dtype, MPS_ERR_SHAPE
+ * for sizes < 1 or batch != 1 with kind 0, MPS_ERR_CAPACITY for operands
+ * above 2^26 elements, batch above 4096 or a short times_ms.
+ */
+mps_status mps_autotune_gemm(mps_handle h, mps_stream stream, int32_t kind, int32_t dtype, int32_t batch, int32_t M,
+                             int32_t N, int32_t K, int32_t apply, double* times_ms, int32_t* n_candidates,
+                             int32_t* best);
+/* Tile of candidate `index`: tile_m x tile_n. */
+mps_status mps_gemm_candidate(int32_t index, int32_t* tile_m, int32_t* tile_n);
+/* The candidate the bucket of (kind, dtype, M, N) uses now. */
+mps_status mps_gemm_tile_choice(int32_t kind, int32_t dtype, int32_t M, int32_t N, int32_t* index);
+/* Set the candidate of the bucket of (kind, dtype, M, N) (e.g. from a cache of earlier tuning). */
+mps_status mps_set_gemm_tile(int32_t kind, int32_t dtype, int32_t M, int32_t N, int32_t index);
 
 /*
  * Bond propagators G_n = exp(-i tau_n h_n)   (the local two-site

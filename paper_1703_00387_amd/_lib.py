@@ -28,7 +28,8 @@ EXPORTS = ["mps_create", "mps_create_ws", "mps_workspace_size", "mps_workspace_n
            "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_noalloc", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_ex", "mps_tebd_ckpt_bytes", "mps_tebd_step_vjp", "mps_theta_gate_vjp", "mps_truncate_vjp", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
            "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step", "mps_tdvp2_step_u1",
            "mps_tebd_grad_arena_bytes", "mps_tebd_grad", "mps_tebd_vjp", "mps_autotune_jacobi",
-           "mps_autotune_candidate"]
+           "mps_autotune_candidate", "mps_autotune_gemm", "mps_gemm_candidate", "mps_gemm_tile_choice",
+           "mps_set_gemm_tile"]
 
 
 class ChainDesc(C.Structure):
@@ -94,6 +95,10 @@ def lib():
         "mps_cfme_nodes": [i32, vp, vp],
         "mps_autotune_jacobi": [vp, vp, i32, i32, i32, i32, vp, vp, vp],
         "mps_autotune_candidate": [i32, i32, vp, vp, vp],
+        "mps_autotune_gemm": [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp],
+        "mps_gemm_candidate": [i32, vp, vp],
+        "mps_gemm_tile_choice": [i32, i32, i32, i32, vp],
+        "mps_set_gemm_tile": [i32, i32, i32, i32, i32],
         "mps_observe": [vp, vp, C.POINTER(ChainDesc), vp, vp, vp, i32, vp, vp],
         "mps_heff_apply": [vp, vp, i32, vp, vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, i32, i32],
         "mps_krylov_expm": [vp, vp, i32, vp, vp, vp, vp, vp, i64, i32, i32, i64, i32, i32, i32, dbl, dbl, i32, dbl,

@@ -591,6 +591,35 @@ class TebdStep(torch.autograd.Function):
         return (out,) + (None,) * 8
 
 
+def autotune_gemm(h: Handle, kind: int, dtype: str, M: int, N: int, K: int, batch: int = 1, apply: bool = True):
+    """mps_autotune_gemm: time the six MFMA tile shapes of the strided (kind 0)
+    or batched write-back (kind 1) GEMM at M x N x K and, with apply, make the
+    fastest the tile of that shape bucket.  Returns {"times_ms", "best",
+    "tiles"} with tiles[i] = (tile_m, tile_n) of candidate i."""
+    cap = C.c_int32(8)
+    times = (C.c_double * 8)()
+    best = C.c_int32(-1)
+    code = _lib.MPS_C128 if dtype == "c128" else _lib.MPS_C64
+    h.check(lib().mps_autotune_gemm(h.h, _stream(), kind, code, batch, M, N, K, 1 if apply else 0, times,
+                                    C.byref(cap), C.byref(best)))
+    tiles = []
+    for i in range(cap.value):
+        tm, tn = C.c_int32(0), C.c_int32(0)
+        check(h.h, lib().mps_gemm_candidate(i, C.byref(tm), C.byref(tn)))
+        tiles.append((tm.value, tn.value))
+    return {"times_ms": [times[i] for i in range(cap.value)], "best": best.value, "tiles": tiles}
+
+
+def gemm_tile(kind: int, dtype: str, M: int, N: int, index: Optional[int] = None) -> int:
+    """The tile candidate of the (kind, dtype, M x N) bucket; with index, set it first."""
+    code = _lib.MPS_C128 if dtype == "c128" else _lib.MPS_C64
+    if index is not None:
+        check(None, lib().mps_set_gemm_tile(kind, code, M, N, index))
+    out = C.c_int32(-1)
+    check(None, lib().mps_gemm_tile_choice(kind, code, M, N, C.byref(out)))
+    return out.value
+
+
 def autotune(h: Handle, n_mats: int, m: int, n: int, apply: bool = True, cache: str = None):
     """Time the Jacobi launch configurations on a seeded synthetic batch of
     n_mats m x n matrices (mps_autotune_jacobi) and, with apply, leave the

@@ -362,6 +362,18 @@ struct SGemm {
   double alpha;
   const double* alpha_dev = nullptr;  // when set, alpha is read from the device
 };
+// GEMM tile shapes: shape classes of an M x N product, the candidate a class
+// uses (process-wide table per precision, set by the autotuner) and a launch
+// with an explicit candidate.
+constexpr int kGemmShapeClasses = 4;
+int gemm_shape_class(long long M, long long N);
+void set_sgemm_choice(bool c128, int shape_class, int cand);
+int get_sgemm_choice(bool c128, int shape_class);
+hipError_t launch_sgemm_cand(hipStream_t s, const SGemm& P, bool c128, int cand);
+void set_bgemm_choice(bool c128, int shape_class, int cand);
+int get_bgemm_choice(bool c128, int shape_class);
+hipError_t launch_gemm_bt_conj_cand(hipStream_t s, const GemmProb* probs, int n_probs, int M_cap, int N_cap,
+                                    bool c128, unsigned long long* stats, int32_t* tile_offs, int cand);
 struct MixDesc {
   int P1, P2, R, Q1, Q2, O1, O2;
   long long is_o1, is_o2, is_q1, is_q2, is_r;

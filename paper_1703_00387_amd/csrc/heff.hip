@@ -24,53 +24,76 @@
 // strided complex GEMM: C = alpha op(A) op(B), element strides, optional conj
 // ---------------------------------------------------------------------------
 
-template <class T>
+// Tile (32 MI) x (32 NJ) per 256-thread workgroup (2 x 2 waves); the shape is
+// chosen per (precision, shape class) from the table the autotuner fills.
+template <class T, int MI, int NJ>
 __global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
-  // two staging buffers, each an A and a B chunk; kPf chunks in flight in registers
-  __shared__ T stage[4 * TBK * TLD];
-  constexpr int kPf = 3;
+  constexpr int BM = 32 * MI, BN = 32 * NJ, LDA = BM + 4, LDB = BN + 4;
+  constexpr int PA = BM >= 64 ? BM / 64 : 1, PB = BN >= 64 ? BN / 64 : 1;
+  constexpr int kPf = MI * NJ > 4 ? 2 : 3;   // chunks in flight in registers
+  // two staging buffers, each an A and a B chunk
+  __shared__ T stage[2 * TBK * (LDA + LDB)];
   const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
-  const int m0 = tm * TBM, n0 = tn * TBN;
+  const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * MI * 16, wn = (wave & 1) * NJ * 16;
   const T* A = (const T*)P.A;
   const T* B = (const T*)P.B;
   T* C = (T*)P.C;
-  AccTile<T> acc;
-  acc_zero<T>(acc);
+  AccTileT<T, MI, NJ> acc;
+  acc_zero_t<T, MI, NJ>(acc);
   const int ia = tid >> 2, kqa = (tid & 3) * 4;
   const int kb = tid >> 4, jqb = (tid & 15) * 4;
-  T va[kPf][4], vb[kPf][4];
-  auto load = [&](int ci, T* da, T* db) {
+  T va[kPf][PA][4], vb[kPf][PB][4];
+  auto load = [&](int ci, T (*da)[4], T (*db)[4]) {
     const int k0 = ci * TBK;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int k = k0 + kqa + e;
-      T v = Cx<T>::make(0.0, 0.0);
-      if (m0 + ia < P.M && k < P.K) {
-        v = A[(long long)(m0 + ia) * P.rsA + (long long)k * P.csA];
-        if (P.conjA) v.y = -v.y;
+    for (int q = 0; q < PA; ++q) {
+      const int row = ia + 64 * q;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int k = k0 + kqa + e;
+        T v = Cx<T>::make(0.0, 0.0);
+        if (row < BM && m0 + row < P.M && k < P.K) {
+          v = A[(long long)(m0 + row) * P.rsA + (long long)k * P.csA];
+          if (P.conjA) v.y = -v.y;
+        }
+        da[q][e] = v;
       }
-      da[e] = v;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int j = jqb + e;
-      T v = Cx<T>::make(0.0, 0.0);
-      if (n0 + j < P.N && k0 + kb < P.K) {
-        v = B[(long long)(k0 + kb) * P.rsB + (long long)(n0 + j) * P.csB];
-        if (P.conjB) v.y = -v.y;
+    for (int q = 0; q < PB; ++q) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int j = jqb + 64 * q + e;
+        T v = Cx<T>::make(0.0, 0.0);
+        if (j < BN && n0 + j < P.N && k0 + kb < P.K) {
+          v = B[(long long)(k0 + kb) * P.rsB + (long long)(n0 + j) * P.csB];
+          if (P.conjB) v.y = -v.y;
+        }
+        db[q][e] = v;
       }
-      db[e] = v;
     }
   };
-  auto store = [&](int buf, const T* da, const T* db) {
-    T* As = stage + buf * 2 * TBK * TLD;
-    T* Bs = As + TBK * TLD;
+  auto store = [&](int buf, T (*da)[4], T (*db)[4]) {
+    T* As = stage + buf * TBK * (LDA + LDB);
+    T* Bs = As + TBK * LDA;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) As[(kqa + e) * TLD + ia] = da[e];
+    for (int q = 0; q < PA; ++q) {
+      const int row = ia + 64 * q;
+      if (row < BM) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) Bs[kb * TLD + jqb + e] = db[e];
+        for (int e = 0; e < 4; ++e) As[(kqa + e) * LDA + row] = da[q][e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = jqb + 64 * q + e;
+        if (j < BN) Bs[kb * LDB + j] = db[q][e];
+      }
+    }
   };
   const int nch = (P.K + TBK - 1) / TBK;
 #pragma unroll
@@ -84,8 +107,8 @@ __global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
       const int ci = base + u;
       if (ci < nch) {
         if (ci + kPf < nch) load(ci + kPf, va[u], vb[u]);  // chunk ci's registers were staged already
-        const T* As = stage + (ci & 1) * 2 * TBK * TLD;
-        mma_chunk<T>(As, As + TBK * TLD, acc, wm, wn, lane);
+        const T* As = stage + (ci & 1) * TBK * (LDA + LDB);
+        mma_chunk_t<T, MI, NJ>(As, LDA, As + TBK * LDA, LDB, acc, wm, wn, lane);
         if (ci + 1 < nch) store((ci + 1) & 1, va[(u + 1) % kPf], vb[(u + 1) % kPf]);
         __syncthreads();
       }
@@ -94,9 +117,9 @@ __global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
   typedef typename Cx<T>::R R;
   const R alpha = P.alpha_dev ? (R)(*P.alpha_dev) : (R)P.alpha;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int row = m0 + wm + i * 16 + Cx<T>::acc_row(lane, r);
@@ -110,14 +133,46 @@ __global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
       }
 }
 
-hipError_t launch_sgemm(hipStream_t s, const SGemm& P, bool c128) {
-  if (P.M <= 0 || P.N <= 0) return hipSuccess;
-  int ntm = (P.M + TBM - 1) / TBM, ntn = (P.N + TBN - 1) / TBN;
-  if (c128)
-    sgemm_kernel<double2><<<ntm * ntn, 256, 0, s>>>(P, ntn);
-  else
-    sgemm_kernel<float2><<<ntm * ntn, 256, 0, s>>>(P, ntn);
+// Tile shape per (precision, shape class), candidate indices of
+// gemm_cand_mi / gemm_cand_nj; 0 (64 x 64) until the autotuner sets one.
+static int g_sgemm_choice[2][kGemmShapeClasses] = {};
+
+int gemm_shape_class(long long M, long long N) {
+  if (M * N <= 64LL * 64 * 64) return 0;   // at most 64 default tiles: few workgroups
+  if (M >= 2 * N) return 1;                // tall
+  if (N >= 2 * M) return 2;                // wide
+  return 3;
+}
+
+void set_sgemm_choice(bool c128, int shape_class, int cand) { g_sgemm_choice[c128 ? 1 : 0][shape_class] = cand; }
+int get_sgemm_choice(bool c128, int shape_class) { return g_sgemm_choice[c128 ? 1 : 0][shape_class]; }
+
+template <class T, int MI, int NJ>
+static hipError_t sgemm_go(hipStream_t s, const SGemm& P) {
+  const int ntm = (P.M + 32 * MI - 1) / (32 * MI), ntn = (P.N + 32 * NJ - 1) / (32 * NJ);
+  sgemm_kernel<T, MI, NJ><<<ntm * ntn, 256, 0, s>>>(P, ntn);
   return hipGetLastError();
+}
+
+template <class T>
+static hipError_t sgemm_cand(hipStream_t s, const SGemm& P, int cand) {
+  switch (cand) {
+    case 1: return sgemm_go<T, 4, 2>(s, P);
+    case 2: return sgemm_go<T, 2, 4>(s, P);
+    case 3: return sgemm_go<T, 1, 2>(s, P);
+    case 4: return sgemm_go<T, 2, 1>(s, P);
+    case 5: return sgemm_go<T, 1, 1>(s, P);
+    default: return sgemm_go<T, 2, 2>(s, P);
+  }
+}
+
+hipError_t launch_sgemm_cand(hipStream_t s, const SGemm& P, bool c128, int cand) {
+  if (P.M <= 0 || P.N <= 0) return hipSuccess;
+  return c128 ? sgemm_cand<double2>(s, P, cand) : sgemm_cand<float2>(s, P, cand);
+}
+
+hipError_t launch_sgemm(hipStream_t s, const SGemm& P, bool c128) {
+  return launch_sgemm_cand(s, P, c128, get_sgemm_choice(c128, gemm_shape_class(P.M, P.N)));
 }
 
 // ---------------------------------------------------------------------------

@@ -126,3 +126,56 @@ __device__ __forceinline__ void acc_to_lds(const AccTile<T>& acc, T* Cs, int ldc
         Cs[row * ldc + col] = v;
       }
 }
+
+// ---------------------------------------------------------------------------
+// Tile shapes for the tuned GEMMs: 2 x 2 waves, each wave MI x NJ MFMA tiles
+// of 16 x 16, so a workgroup tile is (32 MI) x (32 NJ); MI = NJ = 2 is the
+// 64 x 64 tile above.  The staged chunks have pitches BM + 4 and BN + 4.
+// ---------------------------------------------------------------------------
+template <class T, int MI, int NJ>
+struct AccTileT {
+  typename Cx<T>::V4 re[MI][NJ];
+  typename Cx<T>::V4 im[MI][NJ];
+};
+
+template <class T, int MI, int NJ>
+__device__ __forceinline__ void acc_zero_t(AccTileT<T, MI, NJ>& a) {
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a.re[i][j][r] = 0;
+        a.im[i][j][r] = 0;
+      }
+}
+
+// One staged K-chunk: As[TBK][lda] (rows of the tile), Bs[TBK][ldb] (columns).
+template <class T, int MI, int NJ>
+__device__ __forceinline__ void mma_chunk_t(const T* __restrict__ As, int lda, const T* __restrict__ Bs, int ldb,
+                                            AccTileT<T, MI, NJ>& acc, int wm, int wn, int lane) {
+#pragma unroll
+  for (int kk = 0; kk < TBK / 4; ++kk) {
+    const int kr = kk * 4 + (lane >> 4);
+    T a[MI], b[NJ];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) a[i] = As[kr * lda + wm + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) b[j] = Bs[kr * ldb + wn + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        acc.re[i][j] = Cx<T>::mfma(a[i].x, b[j].x, acc.re[i][j]);
+        acc.re[i][j] = Cx<T>::mfma(-a[i].y, b[j].y, acc.re[i][j]);
+        acc.im[i][j] = Cx<T>::mfma(a[i].x, b[j].y, acc.im[i][j]);
+        acc.im[i][j] = Cx<T>::mfma(a[i].y, b[j].x, acc.im[i][j]);
+      }
+  }
+}
+
+// The tile shapes the GEMM autotuner chooses from: (MI, NJ) of candidate c.
+constexpr int kGemmCands = 6;
+__host__ __device__ constexpr int gemm_cand_mi(int c) { return c == 1 ? 4 : (c == 3 || c == 5) ? 1 : 2; }
+__host__ __device__ constexpr int gemm_cand_nj(int c) { return c == 2 ? 4 : (c == 4 || c == 5) ? 1 : 2; }

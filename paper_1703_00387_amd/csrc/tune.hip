@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "common.h"
+#include "mfma_tile.h"
 
 namespace {
 
@@ -151,4 +152,138 @@ extern "C" mps_status mps_autotune_candidate(int32_t m, int32_t index, int32_t* 
           return MPS_OK;
         }
   return MPS_ERR_INVALID;
+}
+
+// ---------------------------------------------------------------------------
+// Tile shapes of the MFMA GEMMs
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class T>
+__global__ void tune_fill_c_kernel(T* X, long long n, unsigned long long seed) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    T v;
+    v.x = tune_hash(seed + 2 * (unsigned long long)e);
+    v.y = tune_hash(seed + 2 * (unsigned long long)e + 1);
+    X[e] = v;
+  }
+}
+
+}  // namespace
+
+extern "C" mps_status mps_autotune_gemm(mps_handle h, mps_stream stream, int32_t kind, int32_t dtype, int32_t batch,
+                                        int32_t M, int32_t N, int32_t K, int32_t apply, double* times_ms,
+                                        int32_t* n_candidates, int32_t* best) {
+  if (!h) return MPS_ERR_INVALID;
+  if (!times_ms || !n_candidates || !best) return mps_fail(h, MPS_ERR_INVALID, "null output");
+  if (kind != 0 && kind != 1) return mps_fail(h, MPS_ERR_INVALID, "kind must be 0 (strided) or 1 (batched)");
+  if (dtype != MPS_C64 && dtype != MPS_C128) return mps_fail(h, MPS_ERR_INVALID, "dtype must be MPS_C64 or MPS_C128");
+  if (M < 1 || N < 1 || K < 1 || batch < 1 || (kind == 0 && batch != 1))
+    return mps_fail(h, MPS_ERR_SHAPE, "bad shape (the strided kind takes batch = 1)");
+  if ((long long)M * K > (1LL << 26) || (long long)N * K > (1LL << 26) || (long long)M * N > (1LL << 26) ||
+      batch > 4096)
+    return mps_fail(h, MPS_ERR_CAPACITY, "operands are limited to 2^26 elements, batch to 4096");
+  if (*n_candidates < kGemmCands) return mps_fail(h, MPS_ERR_CAPACITY, "times_ms too short");
+  const bool c128 = dtype == MPS_C128;
+  const size_t es = c128 ? sizeof(double2) : sizeof(float2);
+  hipStream_t s = (hipStream_t)stream;
+  WsPlan p;
+  const size_t oA = p.take<char>((size_t)batch * M * K * es), oB = p.take<char>((size_t)batch * N * K * es),
+               oC = p.take<char>((size_t)batch * M * N * es), oP = p.take<GemmProb>(batch);
+  mps_status st = mps_ensure_ws(h, p.off);
+  if (st != MPS_OK) return st;
+  char* ws = h->ws;
+  const int g = 1024;
+  if (c128) {
+    tune_fill_c_kernel<double2><<<g, 256, 0, s>>>((double2*)(ws + oA), (long long)batch * M * K, 11);
+    tune_fill_c_kernel<double2><<<g, 256, 0, s>>>((double2*)(ws + oB), (long long)batch * N * K, 1u << 30);
+  } else {
+    tune_fill_c_kernel<float2><<<g, 256, 0, s>>>((float2*)(ws + oA), (long long)batch * M * K, 11);
+    tune_fill_c_kernel<float2><<<g, 256, 0, s>>>((float2*)(ws + oB), (long long)batch * N * K, 1u << 30);
+  }
+  MPS_TRY_HIP(h, hipGetLastError());
+  SGemm sg;
+  std::memset(&sg, 0, sizeof(sg));
+  if (kind == 0) {
+    // C = A B with A [M][K], B [K][N] row-major (the H_eff stage form)
+    sg.A = ws + oA; sg.rsA = K; sg.csA = 1;
+    sg.B = ws + oB; sg.rsB = N; sg.csB = 1;
+    sg.C = ws + oC; sg.rsC = N; sg.csC = 1;
+    sg.M = M; sg.N = N; sg.K = K; sg.alpha = 1.0;
+  } else {
+    // C_i = A_i B_i^dag, the write-back form, batch problems
+    std::vector<GemmProb> pr(batch);
+    for (int i = 0; i < batch; ++i) {
+      GemmProb& q = pr[i];
+      std::memset(&q, 0, sizeof(q));
+      q.A = ws + oA + (size_t)i * M * K * es;
+      q.B = ws + oB + (size_t)i * N * K * es;
+      q.C = ws + oC + (size_t)i * M * N * es;
+      q.M = M; q.N = N; q.K = K;
+      q.lda = K; q.ldb = K; q.ldc = N;
+      q.alpha = 1.0;
+    }
+    MPS_TRY_HIP(h, hipMemcpyAsync(ws + oP, pr.data(), batch * sizeof(GemmProb), hipMemcpyHostToDevice, s));
+  }
+  hipEvent_t e0, e1;
+  MPS_TRY_HIP(h, hipEventCreate(&e0));
+  MPS_TRY_HIP(h, hipEventCreate(&e1));
+  auto run = [&](int c) -> hipError_t {
+    return kind == 0 ? launch_sgemm_cand(s, sg, c128, c)
+                     : launch_gemm_bt_conj_cand(s, (const GemmProb*)(ws + oP), batch, M, N, c128, nullptr, nullptr, c);
+  };
+  int best_i = -1;
+  double best_ms = 1e300;
+  hipError_t he = hipSuccess;
+  for (int c = 0; c < kGemmCands && he == hipSuccess; ++c) {
+    he = run(c);   // untimed
+    const int reps = 5;
+    if (he == hipSuccess) he = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) he = run(c);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    times_ms[c] = ms / reps;
+    if (he == hipSuccess && times_ms[c] < best_ms) {
+      best_ms = times_ms[c];
+      best_i = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (he != hipSuccess) return mps_fail(h, MPS_ERR_HIP, std::string("gemm tuning: ") + hipGetErrorString(he));
+  if (apply) {
+    const int cls = gemm_shape_class(M, N);
+    if (kind == 0) set_sgemm_choice(c128, cls, best_i);
+    else set_bgemm_choice(c128, cls, best_i);
+  }
+  *n_candidates = kGemmCands;
+  *best = best_i;
+  return MPS_OK;
+}
+
+extern "C" mps_status mps_gemm_candidate(int32_t index, int32_t* tile_m, int32_t* tile_n) {
+  if (!tile_m || !tile_n || index < 0 || index >= kGemmCands) return MPS_ERR_INVALID;
+  *tile_m = 32 * gemm_cand_mi(index);
+  *tile_n = 32 * gemm_cand_nj(index);
+  return MPS_OK;
+}
+
+extern "C" mps_status mps_gemm_tile_choice(int32_t kind, int32_t dtype, int32_t M, int32_t N, int32_t* index) {
+  if (!index || (kind != 0 && kind != 1) || (dtype != MPS_C64 && dtype != MPS_C128) || M < 1 || N < 1)
+    return MPS_ERR_INVALID;
+  const int cls = gemm_shape_class(M, N);
+  *index = kind == 0 ? get_sgemm_choice(dtype == MPS_C128, cls) : get_bgemm_choice(dtype == MPS_C128, cls);
+  return MPS_OK;
+}
+
+extern "C" mps_status mps_set_gemm_tile(int32_t kind, int32_t dtype, int32_t M, int32_t N, int32_t index) {
+  if ((kind != 0 && kind != 1) || (dtype != MPS_C64 && dtype != MPS_C128) || M < 1 || N < 1 || index < 0 ||
+      index >= kGemmCands)
+    return MPS_ERR_INVALID;
+  const int cls = gemm_shape_class(M, N);
+  if (kind == 0) set_sgemm_choice(dtype == MPS_C128, cls, index);
+  else set_bgemm_choice(dtype == MPS_C128, cls, index);
+  return MPS_OK;
 }
