@@ -763,6 +763,9 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   size_t n_jobs = 0;
   for (int c = 0; c < n_chains; ++c) n_jobs += (size_t)n_cls * (chains[c].L - 1);
   size_t oJobs = p.take<GateJob>(n_jobs);
+  // multi-panel matrices under the eigendecomposition split take two more
+  // slots per item (the Gram and the rows U^dag theta')
+  const bool eig_slots = h->split_method == 1 && !u1 && d * chi_cap > 64;
   // per parity: items and their workspace slots
   size_t n_par[2] = {0, 0}, slot_bytes[2] = {0, 0};
   for (int c = 0; c < n_chains; ++c) {
@@ -772,7 +775,8 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       int par = b & 1;
       n_par[par]++;
       slot_bytes[par] += ((sq * sizeof(double2) + 255) & ~size_t(255)) + ((sq * esz + 255) & ~size_t(255)) +
-                         (((size_t)ch.chi_max * ch.d * ch.chi_max * esz + 255) & ~size_t(255));
+                         (((size_t)ch.chi_max * ch.d * ch.chi_max * esz + 255) & ~size_t(255)) +
+                         (eig_slots ? 2 * ((sq * sizeof(double2) + 255) & ~size_t(255)) : 0);
     }
   }
   const size_t max_items = std::max(n_par[0], n_par[1]);
@@ -878,6 +882,14 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
           slot += (sq * esz + 255) & ~size_t(255);
           it.Vh = slot;
           slot += ((size_t)ch.chi_max * ch.d * ch.chi_max * esz + 255) & ~size_t(255);
+          it.gram = nullptr;
+          it.urows = nullptr;
+          if (eig_slots) {
+            it.gram = (double2*)slot;
+            slot += (sq * sizeof(double2) + 255) & ~size_t(255);
+            it.urows = (double2*)slot;
+            slot += (sq * sizeof(double2) + 255) & ~size_t(255);
+          }
           it.b = b;
           it.d = ch.d;
           it.chi_max = ch.chi_max;
@@ -981,8 +993,25 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       MPS_TRY_HIP(h, launch_jac_prep_bonds(s, it, mats, n, kJacBlock, (int32_t*)(ws + oRow), (double*)(ws + oNrm), m_cap,
                                            h->status_dev, stats));
       if (prof) prof_end(h, s, MPS_K_PREP);
-      mps_status r = run_jacobi(h, s, mats, n, nb_cap, m_cap, unconv, fixed);
-      if (r != MPS_OK) return r;
+      mps_status r = MPS_OK;
+      if (eig_slots && nb_cap > 2) {
+        // the eigendecomposition split at any size: Gram on MFMA, the
+        // one-sided Jacobi on its rows with the smallest absolute tolerance,
+        // rows normalised, W = U^dag theta' on MFMA
+        MPS_TRY_HIP(h, launch_eig_gram(s, it, mats, n, probs, m_cap, tiles, h->status_dev));
+        const double abs_saved = h->jac_abs;
+        const int meth_saved = h->split_method;
+        h->jac_abs = kJacAbsFloor;
+        h->split_method = 0;
+        r = run_jacobi(h, s, mats, n, nb_cap, m_cap, unconv, fixed);
+        h->jac_abs = abs_saved;
+        h->split_method = meth_saved;
+        if (r != MPS_OK) return r;
+        MPS_TRY_HIP(h, launch_eig_rows(s, it, mats, n, probs, m_cap, m_cap, kJacAbsFloor));
+      } else {
+        r = run_jacobi(h, s, mats, n, nb_cap, m_cap, unconv, fixed);
+        if (r != MPS_OK) return r;
+      }
       if (prof) prof_begin(h, s, MPS_K_SELECT);
       MPS_TRY_HIP(h, launch_select(s, mats, n, perm, s2, m_cap, chi_cap, count_rule_eps(h, eps_local), sel));
       if (prof) prof_end(h, s, MPS_K_SELECT);

@@ -212,6 +212,8 @@ struct BondItem {
   double2* X;            // workspace: theta' complex128 [(d chi_max)^2]
   void* T;               // workspace: theta~' [(d chi_max)^2]
   void* Vh;              // workspace: kept V^dag rows [chi_max][d chi_max]
+  double2* gram;         // workspace of the eigendecomposition split of multi-panel matrices:
+  double2* urows;        //   the Gram theta' theta'^dag and the rows U^dag theta' [(d chi_max)^2] (else null)
   int32_t b, d, chi_max, pad;   // pad: the item's offset in a discarded-weight log slice
 };
 
@@ -287,6 +289,13 @@ hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* m
                                  int32_t* rowmap_ws, double* nrm_ws, int m_cap, uint32_t* status,
                                  unsigned long long* stats = nullptr);
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status);
+// Eigendecomposition split of a layer (Sec. "Basic concepts": theta' theta'^dag
+// = U lambda^2 U^dag, then U^dag theta' = lambda V^dag) for matrices of any
+// size: the steps around the Jacobi of the Grams (probs: one GemmProb per item)
+hipError_t launch_eig_gram(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, GemmProb* probs,
+                           int m_cap, int32_t* tile_offs, uint32_t* status);
+hipError_t launch_eig_rows(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, GemmProb* probs,
+                           int m_cap, int n_cap, double floor);
 // Column split of a Jacobi round (see jac_round_kernel): S workgroups per
 // panel pair; part holds n_mats * pairs * S partial Grams of 64 x 64.
 struct JacSplit {

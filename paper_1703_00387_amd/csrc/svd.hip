@@ -1096,6 +1096,109 @@ hipError_t launch_jac_prep_bonds(hipStream_t s, const BondItem* items, JacMat* m
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Eigendecomposition split of multi-panel matrices: the Gram G = theta' theta'^dag
+// on FP64 MFMA, the one-sided Jacobi on the rows of G (rows -> lambda_j u_j^dag),
+// the rows normalised (their norms lambda_j = s_j^2 become the squared values
+// the selection reads), W = U^dag theta' on MFMA (rows s_j v_j^dag, the form
+// the write-back reads).
+// ---------------------------------------------------------------------------
+__global__ void eig_gram_probs_kernel(const BondItem* __restrict__ items, JacMat* mats, int n, GemmProb* probs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  JacMat& M = mats[i];
+  GemmProb P;
+  P.A = M.X;
+  P.B = M.X;
+  P.C = items[i].gram;
+  P.M = M.m;
+  P.N = M.m;
+  P.K = M.n;
+  P.lda = M.ld;
+  P.ldb = M.ld;
+  P.ldc = M.m;
+  P.M_dev = P.N_dev = P.K_dev = nullptr;
+  P.M_mul = P.N_mul = P.K_mul = 1;
+  P.inv_alpha_dev = nullptr;
+  P.alpha = 1.0;
+  probs[i] = P;
+  // the Jacobi now runs on the rows of G (m x m)
+  M.X = items[i].gram;
+  M.n = M.m;
+  M.ld = M.m;
+  M.conv = 0;
+  M.rot = 0;
+  M.fro2 = 0.0;
+}
+
+// grid (n_items, kRowSlices): rows of the rotated Gram normalised to u_j^dag,
+// nrm2[r] = lambda_j; rows at or below the floor (floor |G|_F^2 in squared
+// norm) are not resolved and become zero rows
+__global__ __launch_bounds__(256) void eig_rows_kernel(const JacMat* __restrict__ mats, double floor) {
+  const JacMat& M = mats[blockIdx.x];
+  const int m = M.m, ld = M.ld, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = blockIdx.y * 4 + wave; r < m; r += 4 * kRowSlices) {
+    const double n2 = M.nrm2[r];
+    const bool keep = n2 > floor * M.fro2 && n2 > 0.0;
+    const double inv = keep ? 1.0 / sqrt(n2) : 0.0;
+    double2* xr = M.X + (size_t)r * ld;
+    for (int c = lane; c < m; c += 64) {
+      const double2 v = xr[c];
+      xr[c] = make_double2(v.x * inv, v.y * inv);
+    }
+    if (lane == 0) M.nrm2[r] = keep ? sqrt(n2) : 0.0;
+  }
+}
+
+__global__ void eig_w_probs_kernel(const BondItem* __restrict__ items, JacMat* mats, int n, GemmProb* probs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BondItem it = items[i];
+  JacMat& M = mats[i];
+  const int m = M.m, nn = it.d * it.chi[it.b + 2];
+  GemmProb P;
+  P.A = it.gram;  // normalised rows u_j^dag, [m][m]
+  P.B = it.X;     // theta', [m][nn]
+  P.C = it.urows;
+  P.M = m;
+  P.N = nn;
+  P.K = m;
+  P.lda = m;
+  P.ldb = nn;
+  P.ldc = nn;
+  P.M_dev = P.N_dev = P.K_dev = nullptr;
+  P.M_mul = P.N_mul = P.K_mul = 1;
+  P.inv_alpha_dev = nullptr;
+  P.alpha = 1.0;
+  probs[i] = P;
+  // selection and write-back read the rows of W with the squared values lambda_j
+  M.X = it.urows;
+  M.n = nn;
+  M.ld = nn;
+}
+
+hipError_t launch_eig_gram(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, GemmProb* probs,
+                           int m_cap, int32_t* tile_offs, uint32_t* status) {
+  if (n_items <= 0) return hipSuccess;
+  eig_gram_probs_kernel<<<(n_items + 63) / 64, 64, 0, s>>>(items, mats, n_items, probs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // G = theta' theta'^dag: the batched write-back GEMM form A B^dag with B = A
+  e = launch_gemm_bt_conj(s, probs, n_items, m_cap, m_cap, true, nullptr, tile_offs);
+  if (e != hipSuccess) return e;
+  return launch_jac_prep_plain(s, mats, n_items, status);
+}
+
+hipError_t launch_eig_rows(hipStream_t s, const BondItem* items, JacMat* mats, int n_items, GemmProb* probs,
+                           int m_cap, int n_cap, double floor) {
+  if (n_items <= 0) return hipSuccess;
+  eig_rows_kernel<<<dim3(n_items, kRowSlices), 256, 0, s>>>(mats, floor);
+  eig_w_probs_kernel<<<(n_items + 63) / 64, 64, 0, s>>>(items, mats, n_items, probs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_gemm_nn(s, probs, n_items, m_cap, n_cap, true, nullptr);
+}
+
 hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32_t* status) {
   if (n_mats <= 0) return hipSuccess;
   jac_row_norms_kernel<<<dim3(n_mats, kRowSlices), 256, 0, s>>>(mats);
