@@ -27,15 +27,17 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of jac_round_kernel on this workload, from two rocprofv3
-# --pmc runs (FETCH_SIZE, WRITE_SIZE) over one TEBD4 step from the step-140
-# state, each scaled by the same counter's reading for a plain streaming kernel
-# of known size (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid only for the
-# kernel source it was measured on (hash of its files); otherwise null.
+# HBM bytes per launch of the Jacobi kernel (jac_persist_kernel, one launch per
+# layer) on this workload, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# WRITE_SIZE) over the first timed TEBD4 step of the default command (state
+# after 140 prelude and 5 warmup steps from the Neel state), each scaled by the
+# same counter's reading for a plain streaming kernel of known size
+# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid only for the kernel source
+# it was measured on (hash of its files); otherwise null.
 JAC_ROUND_TRAFFIC = {
-    "sources_sha256": "7335f49e540948cfb70cc18536a447bc331a1ab283f969b6b3351a33883e9fa3",
-    "bytes_per_launch": 2.2524e8,
-    "warmup": 2,   # state: 140 prelude steps + this many warmup steps from the Neel state
+    "sources_sha256": "ad340838f2482566951f889fa490521e77fda120f6924618f43a29b73699ea1e",
+    "bytes_per_launch": 3.8767e10,
+    "warmup": 5,   # state: 140 prelude steps + this many warmup steps from the Neel state
 }
 JAC_ROUND_SOURCES = ("svd.hip", "jacobi_small.h", "mfma_tile.h")
 
@@ -195,7 +197,8 @@ def main():
     kernel_share = {k: round(v[0] / (elapsed * 1e3), 4) for k, v in stats.items()}
     # the stored HBM traffic figure describes the profiled state: the default
     # prelude and warmup from the Neel state, at the kernel source it was taken on
-    same_state = (not args.load_state and prelude == 140 and args.warmup == JAC_ROUND_TRAFFIC["warmup"]
+    same_state = (not args.load_state and not args.rounds and prelude == 140
+                  and args.warmup == JAC_ROUND_TRAFFIC["warmup"]
                   and args.dtype == "c128")
 
     out = {

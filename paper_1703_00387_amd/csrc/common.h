@@ -379,6 +379,9 @@ int gemm_shape_class(long long M, long long N);
 void set_sgemm_choice(bool c128, int shape_class, int cand);
 int get_sgemm_choice(bool c128, int shape_class);
 hipError_t launch_sgemm_cand(hipStream_t s, const SGemm& P, bool c128, int cand);
+// complex128 products probs[0..n) (device array) in one launch; M_max, N_max
+// bound every problem's M and N
+hipError_t launch_sgemm_batched(hipStream_t s, const SGemm* probs, int n_probs, int M_max, int N_max);
 void set_bgemm_choice(bool c128, int shape_class, int cand);
 int get_bgemm_choice(bool c128, int shape_class);
 hipError_t launch_gemm_bt_conj_cand(hipStream_t s, const GemmProb* probs, int n_probs, int M_cap, int N_cap,

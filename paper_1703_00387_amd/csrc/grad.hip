@@ -337,8 +337,31 @@ struct GradItemBuf {
   double *sv, *sbar, *c2, *kept2, *scal;
   int32_t* rd;
 };
+// One bond update of a layer in the batched reverse pass: its dimensions and
+// the buffers its stages read and write (device array, one entry per bond).
+struct GDesc {
+  int32_t b, chl, chm, chr, m, n, k, rc, cap, d, cm, pad;
+  double2 *T0, *T1, *P0, *Xj, *Vh, *Vb, *Y1, *Z, *Y, *Pm, *Pb, *T1b, *T0b, *Bnew, *Bbl, *Bnl, *Bbs, *Bns, *Jv, *Xm;
+  double2* dot;
+  double *sv, *sbar, *c2, *kept2, *scal;
+  int32_t* rd;
+  const double2 *SBb, *SBb1, *NBb, *NBb1;  // capacity-layout sites before / after the update
+  double2 *bbar_b, *bbar_b1;                // compact site cotangents
+  const double* lam_b;
+  double *lbar_b, *lbar_b1;
+  const double2 *G, *dG;
+  const JacMat* mat;
+  const int32_t* perm;
+  const double* s2;
+  SelOut* seld;
+  double* dJ;   // &dJ[b]
+};
+constexpr int kGradGemmStages = 14;
+
 struct GradScratch {
   std::vector<GradItemBuf> it;
+  GDesc* gd;      // [n_items]
+  SGemm* sg;      // [kGradGemmStages][n_items]
   double* obs;
   JacMat* mat;    // [n_items]
   SelOut *sel, *seld;
@@ -366,6 +389,7 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
     q[27] = p.take<double2>(kMdotBlocks);
   }
   size_t oObs = p.take<double>(2 * (size_t)L);
+  size_t oGD = p.take<GDesc>(ni), oSG = p.take<SGemm>((size_t)kGradGemmStages * ni);
   size_t oMat = p.take<JacMat>(ni), oSel = p.take<SelOut>(ni), oSeld = p.take<SelOut>(ni);
   size_t oRm = p.take<int32_t>((size_t)ni * r), oPm = p.take<int32_t>((size_t)ni * r), oUnc = p.take<int32_t>(8);
   size_t oS2 = p.take<double>((size_t)ni * r), oNr = p.take<double>((size_t)ni * r);
@@ -389,6 +413,8 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
     b.part = (double2*)(ws + q[27]);
   }
   g.obs = (double*)(ws + oObs);
+  g.gd = (GDesc*)(ws + oGD);
+  g.sg = (SGemm*)(ws + oSG);
   g.mat = (JacMat*)(ws + oMat);
   g.sel = (SelOut*)(ws + oSel);
   g.seld = (SelOut*)(ws + oSeld);
@@ -399,6 +425,319 @@ mps_status grad_scratch(mps_handle h, int L, int d, int cm, GradScratch& g) {
   g.nrm2 = (double*)(ws + oNr);
   g.m_cap = (int)r;
   return MPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched reverse pass of one layer: every stage covers all bonds of the
+// layer in one launch (grid.y = bond), with the same arithmetic per bond as
+// the single-update adjoint (mps_truncate_vjp, mps_theta_gate_vjp).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long bg_tid() { return (long long)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ long long bg_stride() { return (long long)gridDim.x * blockDim.x; }
+
+// compact [rows / d][d][cols] block of a capacity-layout site [cm][d][cm]
+__device__ __forceinline__ void bg_site_compact(const double2* __restrict__ src, double2* dst, int a_n, int d,
+                                                int c_n, int cm) {
+  const long long total = (long long)a_n * d * c_n;
+  for (long long e = bg_tid(); e < total; e += bg_stride()) {
+    const int c = (int)(e % c_n);
+    const long long as = e / c_n;
+    dst[e] = src[as * cm + c];
+  }
+}
+
+// cotangents in, the update's tensors compacted
+__global__ __launch_bounds__(256) void bg_prep_kernel(const GDesc* __restrict__ D) {
+  const GDesc& q = D[blockIdx.y];
+  for (long long e = bg_tid(); e < (long long)q.m * q.k; e += bg_stride()) q.Bbl[e] = q.bbar_b[e];
+  for (long long e = bg_tid(); e < (long long)q.k * q.n; e += bg_stride()) q.Bnl[e] = q.bbar_b1[e];
+  bg_site_compact(q.SBb, q.Bbs, q.chl, q.d, q.chm, q.cm);
+  bg_site_compact(q.SBb1, q.Bns, q.chm, q.d, q.chr, q.cm);
+  bg_site_compact(q.NBb1, q.Vh, q.k, q.d, q.chr, q.cm);
+  bg_site_compact(q.NBb, q.Bnew, q.chl, q.d, q.k, q.cm);
+}
+
+// theta~' = G theta~ (T1) and theta' = lam_b theta~' (P0)
+__global__ __launch_bounds__(256) void bg_gate_kernel(const GDesc* __restrict__ D) {
+  const GDesc& q = D[blockIdx.y];
+  const int dd = q.d * q.d, R = q.chr;
+  for (long long idx = bg_tid(); idx < (long long)q.chl * R; idx += bg_stride()) {
+    const int pp = (int)(idx / R), rr = (int)(idx % R);
+    const long long base = (long long)pp * dd * R + rr;
+    const double la = q.lam_b[pp];
+    for (int i = 0; i < dd; ++i) {
+      double2 a = make_double2(0.0, 0.0);
+      for (int j = 0; j < dd; ++j) a = cadd(a, cmul(q.G[i * dd + j], q.T0[base + (long long)j * R]));
+      q.T1[base + (long long)i * R] = a;
+      q.P0[base + (long long)i * R] = make_double2(la * a.x, la * a.y);
+    }
+  }
+}
+
+// residual theta' (1 - V_k V_k^dag) and the kept column weights |theta' V_k|^2
+__global__ __launch_bounds__(256) void bg_resid_kernel(const GDesc* __restrict__ D) {
+  const GDesc& q = D[blockIdx.y];
+  for (long long e = bg_tid(); e < (long long)q.m * q.n; e += bg_stride()) {
+    const double2 x = q.P0[e], z = q.Z[e];
+    q.Xj[e] = make_double2(x.x + (-1.0) * z.x, x.y + (-1.0) * z.y);
+  }
+  for (long long j = bg_tid(); j < q.k; j += bg_stride()) {
+    double a = 0.0;
+    for (int i = 0; i < q.m; ++i) {
+      const double2 v = q.Pm[(long long)i * q.k + j];
+      a += v.x * v.x + v.y * v.y;
+    }
+    q.kept2[j] = a;
+  }
+}
+
+// resolved discarded directions (count), the rows they go to cleared; one workgroup per bond
+__global__ __launch_bounds__(256) void bg_rd_kernel(const GDesc* __restrict__ D) {
+  __shared__ double red[256];
+  const GDesc& q = D[blockIdx.x];
+  double a = 0.0;
+  for (int j = threadIdx.x; j < q.m; j += blockDim.x) a += fmax(q.s2[j], 0.0);
+  for (int j = threadIdx.x; j < q.k; j += blockDim.x) a += fmax(q.kept2[j], 0.0);
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double tot = red[0];
+    int rd = 0;
+    while (rd < q.cap && q.s2[rd] > 1e-26 * tot) ++rd;
+    SelOut o;
+    o.k = rd;
+    o.m = q.m;
+    o.disc = 0.0;
+    o.norm2 = tot;
+    o.nk = 1.0;
+    *q.seld = o;
+    *q.rd = rd;
+  }
+  if (q.cap > 0) {
+    double2* Vd = q.Vh + (size_t)q.k * q.n;
+    for (long long e = threadIdx.x; e < (long long)q.cap * q.n; e += blockDim.x) Vd[e] = make_double2(0.0, 0.0);
+  }
+}
+
+// the resolved residual rows, normalised, as the discarded rows of V^dag
+__global__ __launch_bounds__(256) void bg_rows_kernel(const GDesc* __restrict__ D) {
+  const GDesc& q = D[blockIdx.y];
+  if (q.cap <= 0) return;
+  const int kk = q.seld->k, len = q.n;
+  const JacMat M = *q.mat;
+  double2* Vd = q.Vh + (size_t)q.k * q.n;
+  for (long long idx = bg_tid(); idx < (long long)kk * len; idx += bg_stride()) {
+    const int j = (int)(idx / len), e = (int)(idx % len);
+    int pj = q.perm[j];
+    pj = (pj >= 0 && pj < M.m) ? pj : 0;
+    const double sj = sqrt(q.s2[j]);
+    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    const double2 x = M.X[(size_t)pj * M.ld + e];
+    Vd[(size_t)j * len + e] = make_double2(x.x * inv, x.y * inv);
+  }
+}
+
+// V_d -= (V_d V_k^dag) V_k (the projection formed in Z)
+__global__ __launch_bounds__(256) void bg_reproj_kernel(const GDesc* __restrict__ D) {
+  const GDesc& q = D[blockIdx.y];
+  if (q.cap <= 0) return;
+  double2* Vd = q.Vh + (size_t)q.k * q.n;
+  for (long long e = bg_tid(); e < (long long)q.cap * q.n; e += bg_stride()) {
+    const double2 z = q.Z[e], y = Vd[e];
+    Vd[e] = make_double2(y.x + (-1.0) * z.x, y.y + (-1.0) * z.y);
+  }
+}
+
+// per bond (one workgroup): column weights c2 of P = theta' V, <B_bar_b', B_b'>,
+// the scalars n_k, 1/n_k, n_bar, s and s_bar (as in the single-update pass),
+// and V_bar cleared
+__global__ __launch_bounds__(256) void bg_scal_kernel(const GDesc* __restrict__ D, uint32_t* status) {
+  __shared__ double red[2][256];
+  __shared__ double nk_s, nbar_s;
+  const GDesc& q = D[blockIdx.x];
+  const int rc = q.rc, k = q.k;
+  for (int j = threadIdx.x; j < rc; j += blockDim.x) {
+    double a = 0.0;
+    for (int i = 0; i < q.m; ++i) {
+      const double2 v = q.Pm[(long long)i * rc + j];
+      a += v.x * v.x + v.y * v.y;
+    }
+    q.c2[j] = a;
+  }
+  double dr = 0.0;
+  for (long long e = threadIdx.x; e < (long long)q.m * k; e += blockDim.x) {
+    const double2 v = q.Bbl[e], x = q.Bnew[e];
+    dr += v.x * x.x + v.y * x.y;
+  }
+  for (long long e = threadIdx.x; e < (long long)q.n * rc; e += blockDim.x) q.Vb[e] = make_double2(0.0, 0.0);
+  red[0][threadIdx.x] = dr;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[0][threadIdx.x] += red[0][threadIdx.x + o];
+    __syncthreads();
+  }
+  const double dot = red[0][0];
+  __syncthreads();
+  const double* lbm = q.lbar_b1;
+  double a = 0.0, b = 0.0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const double sj = sqrt(fmax(q.c2[j], 0.0));
+    a += sj * sj;
+    b += lbm[j] * sj;
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double nk = sqrt(red[0][0]);
+    if (!(nk > 0.0) || !(nk < 1e300)) {
+      atomicOr(status, MPS_DEV_NONFINITE);
+      nk = 1.0;
+    }
+    nk_s = nk;
+    nbar_s = -(dot + red[1][0] / nk) / nk;
+    q.scal[0] = nk;
+    q.scal[1] = 1.0 / nk;
+    q.scal[2] = nbar_s;
+    q.dot[0] = make_double2(dot, 0.0);
+  }
+  __syncthreads();
+  const double nk = nk_s, nbar = nbar_s;
+  for (int j = threadIdx.x; j < rc; j += blockDim.x) {
+    const double sj = sqrt(fmax(q.c2[j], 0.0));
+    q.sv[j] = sj;
+    q.sbar[j] = j < k ? lbm[j] / nk + nbar * sj / nk : 0.0;
+  }
+}
+
+// V_bar[i][j] += conj(B_bar_{b+1}'[j][i]) for j < k
+__global__ __launch_bounds__(256) void bg_addconj_kernel(const GDesc* __restrict__ D) {
+  const GDesc& q = D[blockIdx.y];
+  for (long long e = bg_tid(); e < (long long)q.n * q.k; e += bg_stride()) {
+    const int i = (int)(e / q.k), j = (int)(e % q.k);
+    const double2 b = q.Bnl[(long long)j * q.n + i];
+    double2& v = q.Vb[(long long)i * q.rc + j];
+    v = make_double2(v.x + b.x, v.y - b.y);
+  }
+}
+
+// the SVD-backward matrix Xt (as svd_x_kernel) for every bond
+__global__ __launch_bounds__(256) void bg_svdx_kernel(const GDesc* __restrict__ D, double eta) {
+  const GDesc& q = D[blockIdx.y];
+  const int r = q.rc, k = q.k;
+  for (long long e = bg_tid(); e < (long long)r * r; e += bg_stride()) {
+    const int i = (int)(e / r), j = (int)(e % r);
+    double2 v = make_double2(0.0, 0.0);
+    if (i == j) {
+      if (i < k) v = make_double2(q.sbar[i] / q.sv[i], -0.5 * q.Jv[e].y / (q.sv[i] * q.sv[i] + eta));
+    } else {
+      const double Dd = q.sv[j] * q.sv[j] - q.sv[i] * q.sv[i];
+      const double F = Dd != 0.0 ? Dd / (Dd * Dd + eta) : 0.0;
+      const double2 a = q.Jv[(long long)i * r + j], b = q.Jv[(long long)j * r + i];
+      v = make_double2(F * (a.x - b.x), F * (a.y + b.y));
+    }
+    q.Xm[e] = v;
+  }
+}
+
+// Y = Y1 + diag(w) (V_bar^dag - Jv^dag V^dag) (as svd_y_kernel)
+__global__ __launch_bounds__(256) void bg_svdy_kernel(const GDesc* __restrict__ D, double eta) {
+  const GDesc& q = D[blockIdx.y];
+  const int r = q.rc, k = q.k, n = q.n;
+  for (long long e = bg_tid(); e < (long long)r * n; e += bg_stride()) {
+    const int i = (int)(e / n), c = (int)(e % n);
+    double2 y = q.Y1[e];
+    if (i < k) {
+      const double w = 1.0 / (q.sv[i] * q.sv[i] + eta);
+      const double2 vb = q.Vb[(long long)c * r + i];
+      y = make_double2(y.x + w * (vb.x - q.Z[e].x), y.y + w * (-vb.y - q.Z[e].y));
+    }
+    q.Y[e] = y;
+  }
+}
+
+// theta~'_bar += lam_b theta'_bar and lam_bar_b += Re<theta'_bar, theta~'>;
+// workgroup (a, bond) takes the d rows of left index a
+__global__ __launch_bounds__(256) void bg_thetabar_kernel(const GDesc* __restrict__ D) {
+  __shared__ double red[4];
+  const GDesc& q = D[blockIdx.y];
+  const int a = blockIdx.x;
+  if (a >= q.chl) return;
+  const long long base = (long long)a * q.d * q.n, len = (long long)q.d * q.n;
+  const double la = q.lam_b[a];
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < len; e += blockDim.x) {
+    const double2 x = q.Pb[base + e], y = q.T1[base + e];
+    acc += x.x * y.x + x.y * y.y;
+    const double2 t = q.T1b[base + e];
+    q.T1b[base + e] = make_double2(la * x.x + t.x, la * x.y + t.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) q.lbar_b[a] += 1.0 * (red[0] + red[1] + red[2] + red[3]);
+}
+
+// dG/dJ theta~ (Z) and theta~_bar = G^dag theta~'_bar (T0b)
+__global__ __launch_bounds__(256) void bg_gatebar_kernel(const GDesc* __restrict__ D) {
+  const GDesc& q = D[blockIdx.y];
+  const int dd = q.d * q.d, R = q.chr;
+  for (long long idx = bg_tid(); idx < (long long)q.chl * R; idx += bg_stride()) {
+    const int pp = (int)(idx / R), rr = (int)(idx % R);
+    const long long base = (long long)pp * dd * R + rr;
+    for (int i = 0; i < dd; ++i) {
+      double2 a = make_double2(0.0, 0.0), g = make_double2(0.0, 0.0);
+      for (int j = 0; j < dd; ++j) {
+        a = cadd(a, cmul(q.dG[i * dd + j], q.T0[base + (long long)j * R]));
+        const double2 o = make_double2(q.G[j * dd + i].x, -q.G[j * dd + i].y);
+        g = cadd(g, cmul(o, q.T1b[base + (long long)j * R]));
+      }
+      q.Z[base + (long long)i * R] = a;
+      q.T0b[base + (long long)i * R] = g;
+    }
+  }
+}
+
+// J_bar_b += Re<theta~'_bar, dG/dJ_b theta~> (one workgroup per bond), lam_bar_{b+1} cleared
+__global__ __launch_bounds__(256) void bg_jbar_kernel(const GDesc* __restrict__ D) {
+  __shared__ double red[4];
+  const GDesc& q = D[blockIdx.x];
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < (long long)q.m * q.n; e += blockDim.x) {
+    const double2 v = q.T1b[e], x = q.Z[e];
+    acc += v.x * x.x + v.y * x.y;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *q.dJ += red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void bg_zero_lbar_kernel(const GDesc* __restrict__ D) {
+  const GDesc& q = D[blockIdx.x];
+  for (int j = threadIdx.x; j < q.cm; j += blockDim.x) q.lbar_b1[j] = 0.0;
+}
+
+SGemm sg_make(const void* A, long long rsA, long long csA, int conjA, const void* B, long long rsB, long long csB,
+              int conjB, void* C, long long rsC, int M, int N, int K, const double* alpha_dev = nullptr) {
+  SGemm g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A; g.rsA = rsA; g.csA = csA; g.conjA = conjA;
+  g.B = B; g.rsB = rsB; g.csB = csB; g.conjB = conjB;
+  g.C = C; g.rsC = rsC; g.csC = 1;
+  g.M = M; g.N = N; g.K = K; g.alpha = 1.0; g.alpha_dev = alpha_dev;
+  return g;
 }
 
 }  // namespace
@@ -613,26 +952,14 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
   }  // seeding from the loss
 
   // ---- backward over steps and layers -------------------------------------
-  // Every bond of a layer is an independent update: its reverse pass runs on
-  // an auxiliary stream of its own.  The layer's residual SVDs run as one
-  // batch on the launch stream between the two halves.  No per-update host
-  // round trip: the sizes that depend on the data (how many discarded
+  // Every bond of a layer is an independent update: each stage of the reverse
+  // pass runs for all bonds of the layer in one launch (bond = grid.y), the
+  // layer's residual SVDs as one batch between the two halves.  No per-update
+  // host round trip: the sizes that depend on the data (how many discarded
   // directions are resolved, n_k) stay on the device, and the matrices that
   // depend on them are formed at capacity r_cap = min(m, n) with zero rows.
-  const int n_aux = std::min(8, std::max(1, L / 2));
-  if ((r = mps_aux_streams(h, n_aux)) != MPS_OK) return r;
-  auto fork = [&]() -> mps_status {
-    MPS_TRY_HIP(h, hipEventRecord(h->aux_ev[n_aux], s));
-    for (int i = 0; i < n_aux; ++i) MPS_TRY_HIP(h, hipStreamWaitEvent(h->aux[i], h->aux_ev[n_aux], 0));
-    return MPS_OK;
-  };
-  auto join = [&]() -> mps_status {
-    for (int i = 0; i < n_aux; ++i) {
-      MPS_TRY_HIP(h, hipEventRecord(h->aux_ev[i], h->aux[i]));
-      MPS_TRY_HIP(h, hipStreamWaitEvent(s, h->aux_ev[i], 0));
-    }
-    return MPS_OK;
-  };
+  std::vector<GDesc> gdh;
+  std::vector<SGemm> sgh;
   const double abs_saved = h->jac_abs;
   for (int stp = n_steps - 1; stp >= 0; --stp) {
     if ((r = restore(arena + A.oCk + (size_t)stp * A.snap)) != MPS_OK) return r;
@@ -683,34 +1010,97 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
         mmax = std::max(mmax, hm[i].m);
       }
 
-      // -- first half: recompute the update, form the residual theta'(1 - V_k V_k^dag)
-      if ((r = fork()) != MPS_OK) return r;
+      // -- the layer's bond updates, described once for the batched stages
+      gdh.assign(ni, GDesc());
       for (int i = 0; i < ni; ++i) {
-        Ctx c{h, h->aux[i % n_aux]};
-        hipStream_t si = c.s;
         const GradItemBuf& q = g.it[i];
-        const int b = bonds[i], chl = co[b], chm = co[b + 1], chr = co[b + 2], m = chl * d, n = d * chr;
-        const int k = cn[b + 1];
-        const double* lam_b = SL + (size_t)b * cm;
-        MPS_TRY_HIP(h, hipMemcpyAsync(q.Bbl, bbar(b), (size_t)m * k * sizeof(double2), hipMemcpyDeviceToDevice, si));
-        MPS_TRY_HIP(h, hipMemcpyAsync(q.Bnl, bbar(b + 1), (size_t)k * n * sizeof(double2), hipMemcpyDeviceToDevice, si));
-        K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, si>>>(SB + b * site_el, q.Bbs, chl, d, chm, cm, 1)));
-        K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, si>>>(SB + (b + 1) * site_el, q.Bns, chm, d, chr, cm,
-                                                                       1)));
-        if ((r = gemm128(c, q.Bbs, chm, 1, 0, q.Bns, n, 1, 0, q.T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
-        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, si>>>(Gp(cls, b), dd, q.T0, q.T1, chl, chr, 0,
-                                                                           0)));
-        K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, si>>>(q.T1, q.P0, m, n, lam_b, d, 1, 1.0, 0)));
-        // the forward's own factors: V_k^dag = B_{b+1}', B_b' = theta~' V_k / n_k
-        K1((site_copy_kernel<<<g1d((long long)k * n), 256, 0, si>>>(NB + (b + 1) * site_el, q.Vh, k, d, chr, cm, 1)));
-        K1((site_copy_kernel<<<g1d((long long)m * k), 256, 0, si>>>(NB + b * site_el, q.Bnew, chl, d, k, cm, 1)));
-        if ((r = gemm128(c, q.P0, n, 1, 0, q.Vh, 1, n, 1, q.Pm, k, m, k, n, 1.0)) != MPS_OK) return r;
-        if ((r = gemm128(c, q.Pm, k, 1, 0, q.Vh, n, 1, 0, q.Z, n, m, n, k, 1.0)) != MPS_OK) return r;
-        MPS_TRY_HIP(h, hipMemcpyAsync(q.Xj, q.P0, (size_t)m * n * sizeof(double2), hipMemcpyDeviceToDevice, si));
-        K1((axpy_kernel<<<g1d((long long)m * n), 256, 0, si>>>(q.Z, q.Xj, (long long)m * n, -1.0)));
-        K1((colnorm2_kernel<<<g1d(k), 256, 0, si>>>(q.Pm, m, k, q.kept2)));
+        GDesc& x = gdh[i];
+        std::memset(&x, 0, sizeof(x));
+        const int b = bonds[i];
+        x.b = b;
+        x.chl = co[b];
+        x.chm = co[b + 1];
+        x.chr = co[b + 2];
+        x.m = x.chl * d;
+        x.n = d * x.chr;
+        x.k = cn[b + 1];
+        x.rc = std::min(x.m, x.n);
+        x.cap = x.rc - x.k;
+        x.d = d;
+        x.cm = cm;
+        x.T0 = q.T0; x.T1 = q.T1; x.P0 = q.P0; x.Xj = q.Xj; x.Vh = q.Vh; x.Vb = q.Vb; x.Y1 = q.Y1; x.Z = q.Z;
+        x.Y = q.Y; x.Pm = q.Pm; x.Pb = q.Pb; x.T1b = q.T1b; x.T0b = q.T0b; x.Bnew = q.Bnew; x.Bbl = q.Bbl;
+        x.Bnl = q.Bnl; x.Bbs = q.Bbs; x.Bns = q.Bns; x.Jv = q.Jv; x.Xm = q.Xm;
+        x.dot = q.dot;
+        x.sv = q.sv; x.sbar = q.sbar; x.c2 = q.c2; x.kept2 = q.kept2; x.scal = q.scal;
+        x.rd = q.rd;
+        x.SBb = SB + b * site_el;
+        x.SBb1 = SB + (b + 1) * site_el;
+        x.NBb = NB + b * site_el;
+        x.NBb1 = NB + (b + 1) * site_el;
+        x.bbar_b = bbar(b);
+        x.bbar_b1 = bbar(b + 1);
+        x.lam_b = SL + (size_t)b * cm;
+        x.lbar_b = lbar + (size_t)b * cm;
+        x.lbar_b1 = lbar + (size_t)(b + 1) * cm;
+        x.G = Gp(cls, b);
+        x.dG = dGp(cls, b);
+        x.mat = g.mat + i;
+        x.perm = g.perm + (size_t)i * g.m_cap;
+        x.s2 = g.s2 + (size_t)i * g.m_cap;
+        x.seld = g.seld + i;
+        x.dJ = dJ_dev + b;
       }
-      if ((r = join()) != MPS_OK) return r;
+      // the products of every stage, one problem per bond (gemm128 argument order)
+      sgh.assign((size_t)kGradGemmStages * ni, SGemm());
+      int mx[kGradGemmStages] = {0}, nx[kGradGemmStages] = {0};
+      for (int i = 0; i < ni; ++i) {
+        const GDesc& q = gdh[i];
+        const int m = q.m, n = q.n, k = q.k, rc = q.rc, cap = q.cap, chm = q.chm;
+        double2* Vd = q.Vh + (size_t)k * n;
+        const double* inv_nk = q.scal + 1;
+        SGemm st[kGradGemmStages] = {
+            sg_make(q.Bbs, chm, 1, 0, q.Bns, n, 1, 0, q.T0, n, m, n, chm),           // 0: theta~
+            sg_make(q.P0, n, 1, 0, q.Vh, 1, n, 1, q.Pm, k, m, k, n),                 // 1: theta' V_k
+            sg_make(q.Pm, k, 1, 0, q.Vh, n, 1, 0, q.Z, n, m, n, k),                  // 2: projection
+            sg_make(Vd, n, 1, 0, q.Vh, 1, n, 1, q.Jv, k, cap, k, n),                 // 3: V_d V_k^dag
+            sg_make(q.Jv, k, 1, 0, q.Vh, n, 1, 0, q.Z, n, cap, n, k),                // 4: its projection
+            sg_make(q.P0, n, 1, 0, q.Vh, 1, n, 1, q.Pm, rc, m, rc, n),               // 5: P = theta' V
+            sg_make(q.T1, 1, n, 1, q.Bbl, k, 1, 0, q.Vb, rc, n, k, m, inv_nk),       // 6: V_bar kept part
+            sg_make(q.Vh, n, 1, 0, q.Vb, rc, 1, 0, q.Jv, rc, rc, rc, n),             // 7: Jv = V^dag V_bar
+            sg_make(q.Xm, rc, 1, 0, q.Vh, n, 1, 0, q.Y1, n, rc, n, rc),              // 8: Xt V^dag
+            sg_make(q.Jv, 1, rc, 1, q.Vh, n, 1, 0, q.Z, n, rc, n, rc),               // 9: Jv^dag V^dag
+            sg_make(q.Pm, rc, 1, 0, q.Y, n, 1, 0, q.Pb, n, m, n, rc),                // 10: theta'_bar
+            sg_make(q.Bbl, k, 1, 0, q.Vh, n, 1, 0, q.T1b, n, m, n, k, inv_nk),       // 11: B_bar_b' V_k^dag / n_k
+            sg_make(q.T0b, n, 1, 0, q.Bns, 1, n, 1, q.bbar_b, chm, m, chm, n),       // 12: B_bar_b
+            sg_make(q.Bbs, 1, chm, 1, q.T0b, n, 1, 0, q.bbar_b1, n, chm, n, m)};     // 13: B_bar_{b+1}
+        for (int j = 0; j < kGradGemmStages; ++j) {
+          sgh[(size_t)j * ni + i] = st[j];
+          mx[j] = std::max(mx[j], st[j].M);
+          nx[j] = std::max(nx[j], st[j].N);
+        }
+      }
+      // the previous layer's uploads finished at the synchronisation above
+      MPS_TRY_HIP(h, hipMemcpyAsync(g.gd, gdh.data(), ni * sizeof(GDesc), hipMemcpyHostToDevice, s));
+      MPS_TRY_HIP(h, hipMemcpyAsync(g.sg, sgh.data(), sgh.size() * sizeof(SGemm), hipMemcpyHostToDevice, s));
+      int emax = 1, chl_max = 1;
+      for (int i = 0; i < ni; ++i) {
+        emax = std::max(emax, std::max(gdh[i].m, gdh[i].rc) * std::max(gdh[i].n, gdh[i].rc));
+        chl_max = std::max(chl_max, gdh[i].chl);
+      }
+      const dim3 eg(std::max(1, std::min(1024, (emax + 255) / 256)), ni);
+      auto stage = [&](int j) -> hipError_t {
+        return launch_sgemm_batched(s, g.sg + (size_t)j * ni, ni, mx[j], nx[j]);
+      };
+      const GDesc* D = g.gd;
+
+      // -- first half: recompute the update, form the residual theta'(1 - V_k V_k^dag)
+      K1((bg_prep_kernel<<<eg, 256, 0, s>>>(D)));
+      MPS_TRY_HIP(h, stage(0));
+      K1((bg_gate_kernel<<<eg, 256, 0, s>>>(D)));
+      MPS_TRY_HIP(h, stage(1));
+      MPS_TRY_HIP(h, stage(2));
+      K1((bg_resid_kernel<<<eg, 256, 0, s>>>(D)));
 
       // -- the layer's residual SVDs, orthogonalised with the smallest absolute tolerance
       MPS_TRY_HIP(h, launch_jac_prep_plain(s, g.mat, ni, h->status_dev));
@@ -721,71 +1111,29 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
       if (r != MPS_OK) return r;
       MPS_TRY_HIP(h, launch_select(s, g.mat, ni, g.perm, g.s2, g.m_cap, 0, 0.0, g.sel));
 
-      // -- second half: SVD backward, gate and contraction adjoints
-      if ((r = fork()) != MPS_OK) return r;
-      for (int i = 0; i < ni; ++i) {
-        Ctx c{h, h->aux[i % n_aux]};
-        hipStream_t si = c.s;
-        const GradItemBuf& q = g.it[i];
-        const int b = bonds[i], chl = co[b], chm = co[b + 1], chr = co[b + 2], m = chl * d, n = d * chr;
-        const int k = cn[b + 1], rc = std::min(m, n), cap = rc - k;
-        const double* lam_b = SL + (size_t)b * cm;
-        const double* lbm = lbar + (size_t)(b + 1) * cm;
-        const double* inv_nk = q.scal + 1;
-        // discarded directions: the resolved residual rows, normalised, projected once more
-        K1((grad_rd_kernel<<<1, 256, 0, si>>>(g.s2 + (size_t)i * g.m_cap, q.kept2, m, k, cap, 1e-26, g.seld + i,
-                                              q.rd)));
-        if (cap > 0) {
-          double2* Vd = q.Vh + (size_t)k * n;
-          K1((fill_zero_kernel<<<g1d((long long)cap * n), 256, 0, si>>>(Vd, (long long)cap * n)));
-          MPS_TRY_HIP(h, launch_write_rows(si, g.mat + i, g.perm + (size_t)i * g.m_cap, g.s2 + (size_t)i * g.m_cap,
-                                           g.seld + i, Vd, n, 0, true));
-          if ((r = gemm128(c, Vd, n, 1, 0, q.Vh, 1, n, 1, q.Jv, k, cap, k, n, 1.0)) != MPS_OK) return r;
-          if ((r = gemm128(c, q.Jv, k, 1, 0, q.Vh, n, 1, 0, q.Z, n, cap, n, k, 1.0)) != MPS_OK) return r;
-          K1((axpy_kernel<<<g1d((long long)cap * n), 256, 0, si>>>(q.Z, Vd, (long long)cap * n, -1.0)));
-        }
-        // P = theta' V (m x rc), its column norms, and the scalars n_k, n_bar, s_bar
-        if ((r = gemm128(c, q.P0, n, 1, 0, q.Vh, 1, n, 1, q.Pm, rc, m, rc, n, 1.0)) != MPS_OK) return r;
-        K1((colnorm2_kernel<<<g1d(rc), 256, 0, si>>>(q.Pm, m, rc, q.c2)));
-        K1((fill_zero_kernel<<<1, 256, 0, si>>>(q.dot, 2)));
-        MPS_TRY_HIP(h, launch_mdot(si, q.Bbl, 0, 1, q.Bnew, (long long)m * k, q.dot, q.part));
-        K1((grad_scalars_kernel<<<1, 256, 0, si>>>(q.c2, lbm, q.dot, k, rc, q.sv, q.sbar, q.scal, h->status_dev)));
-        // V_bar (n x rc): kept columns theta~'^dag B_bar_b' / n_k + conj(B_bar_{b+1}')^T
-        K1((fill_zero_kernel<<<g1d((long long)n * rc), 256, 0, si>>>(q.Vb, (long long)n * rc)));
-        {
-          SGemm G;
-          std::memset(&G, 0, sizeof(G));
-          G.A = q.T1; G.rsA = 1; G.csA = n; G.conjA = 1;
-          G.B = q.Bbl; G.rsB = k; G.csB = 1;
-          G.C = q.Vb; G.rsC = rc; G.csC = 1;
-          G.M = n; G.N = k; G.K = m; G.alpha = 1.0; G.alpha_dev = inv_nk;
-          MPS_TRY_HIP(h, launch_sgemm(si, G, true));
-        }
-        K1((add_conj_t_kernel<<<g1d((long long)n * k), 256, 0, si>>>(q.Vb, q.Bnl, n, rc, k)));
-        // Jv = V^dag V_bar; Xt; Y = Xt V^dag + diag(w)(V_bar^dag - Jv^dag V^dag); theta'_bar = P Y
-        if ((r = gemm128(c, q.Vh, n, 1, 0, q.Vb, rc, 1, 0, q.Jv, rc, rc, rc, n, 1.0)) != MPS_OK) return r;
-        K1((svd_x_kernel<<<g1d((long long)rc * rc), 256, 0, si>>>(q.Jv, q.sv, q.sbar, rc, k, eta, q.Xm)));
-        if ((r = gemm128(c, q.Xm, rc, 1, 0, q.Vh, n, 1, 0, q.Y1, n, rc, n, rc, 1.0)) != MPS_OK) return r;
-        if ((r = gemm128(c, q.Jv, 1, rc, 1, q.Vh, n, 1, 0, q.Z, n, rc, n, rc, 1.0)) != MPS_OK) return r;
-        K1((svd_y_kernel<<<g1d((long long)rc * n), 256, 0, si>>>(q.Y1, q.Z, q.Vb, q.sv, rc, k, n, eta, q.Y)));
-        if ((r = gemm128(c, q.Pm, rc, 1, 0, q.Y, n, 1, 0, q.Pb, n, m, n, rc, 1.0)) != MPS_OK) return r;
-        // theta~'_bar = B_bar_b' V_k^dag / n_k + lam_b theta'_bar;  lam_bar_b += Re<theta'_bar, theta~'>
-        if ((r = gemm128(c, q.Bbl, k, 1, 0, q.Vh, n, 1, 0, q.T1b, n, m, n, k, 1.0, inv_nk)) != MPS_OK) return r;
-        K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, si>>>(q.Pb, q.T1b, m, n, lam_b, d, 1, 1.0, 1)));
-        K1((lam_dot_kernel<<<chl, 256, 0, si>>>(q.Pb, q.T1, d, n, lbar + (size_t)b * cm, nullptr, 1.0)));
-        // coupling: J_bar_b += Re<theta~'_bar, dG/dJ_b theta~>
-        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, si>>>(dGp(cls, b), dd, q.T0, q.Z, chl, chr, 0,
-                                                                           0)));
-        MPS_TRY_HIP(h, launch_mdot(si, q.T1b, 0, 1, q.Z, (long long)m * n, q.dot + 1, q.part));
-        K1((jbar_add_kernel<<<1, 1, 0, si>>>(q.dot + 1, dJ_dev, b)));
-        // theta~_bar = G^dag theta~'_bar ; B_bar_b = theta~_bar B_{b+1}^dag ; B_bar_{b+1} = B_b^dag theta~_bar
-        K1((apply_local_kernel<<<g1d((long long)chl * chr), 256, 0, si>>>(Gp(cls, b), dd, q.T1b, q.T0b, chl, chr, 1,
-                                                                           0)));
-        if ((r = gemm128(c, q.T0b, n, 1, 0, q.Bns, 1, n, 1, bbar(b), chm, m, chm, n, 1.0)) != MPS_OK) return r;
-        if ((r = gemm128(c, q.Bbs, 1, chm, 1, q.T0b, n, 1, 0, bbar(b + 1), n, chm, n, m, 1.0)) != MPS_OK) return r;
-        MPS_TRY_HIP(h, hipMemsetAsync(lbar + (size_t)(b + 1) * cm, 0, cm * sizeof(double), si));
-      }
-      if ((r = join()) != MPS_OK) return r;
+      // -- second half: discarded directions, SVD backward, gate and contraction adjoints
+      K1((bg_rd_kernel<<<ni, 256, 0, s>>>(D)));
+      K1((bg_rows_kernel<<<eg, 256, 0, s>>>(D)));
+      MPS_TRY_HIP(h, stage(3));
+      MPS_TRY_HIP(h, stage(4));
+      K1((bg_reproj_kernel<<<eg, 256, 0, s>>>(D)));
+      MPS_TRY_HIP(h, stage(5));
+      K1((bg_scal_kernel<<<ni, 256, 0, s>>>(D, h->status_dev)));
+      MPS_TRY_HIP(h, stage(6));
+      K1((bg_addconj_kernel<<<eg, 256, 0, s>>>(D)));
+      MPS_TRY_HIP(h, stage(7));
+      K1((bg_svdx_kernel<<<eg, 256, 0, s>>>(D, eta)));
+      MPS_TRY_HIP(h, stage(8));
+      MPS_TRY_HIP(h, stage(9));
+      K1((bg_svdy_kernel<<<eg, 256, 0, s>>>(D, eta)));
+      MPS_TRY_HIP(h, stage(10));
+      MPS_TRY_HIP(h, stage(11));
+      K1((bg_thetabar_kernel<<<dim3(chl_max, ni), 256, 0, s>>>(D)));
+      K1((bg_gatebar_kernel<<<eg, 256, 0, s>>>(D)));
+      K1((bg_jbar_kernel<<<ni, 256, 0, s>>>(D)));
+      MPS_TRY_HIP(h, stage(12));
+      MPS_TRY_HIP(h, stage(13));
+      K1((bg_zero_lbar_kernel<<<ni, 256, 0, s>>>(D)));
     }
   }
   // the chain is left in the final state of the forward run

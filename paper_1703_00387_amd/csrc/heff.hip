@@ -27,13 +27,17 @@
 // Tile (32 MI) x (32 NJ) per 256-thread workgroup (2 x 2 waves); the shape is
 // chosen per (precision, shape class) from the table the autotuner fills.
 template <class T, int MI, int NJ>
-__global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
+struct SGemmLds {
+  static constexpr int kElems = 2 * TBK * (32 * MI + 4 + 32 * NJ + 4);
+};
+
+// Output tile (tm, tn) of P; stage holds SGemmLds<T, MI, NJ>::kElems elements
+// (two staging buffers, each an A and a B chunk).
+template <class T, int MI, int NJ>
+__device__ __forceinline__ void sgemm_tile(const SGemm& P, int tm, int tn, T* stage) {
   constexpr int BM = 32 * MI, BN = 32 * NJ, LDA = BM + 4, LDB = BN + 4;
   constexpr int PA = BM >= 64 ? BM / 64 : 1, PB = BN >= 64 ? BN / 64 : 1;
   constexpr int kPf = MI * NJ > 4 ? 2 : 3;   // chunks in flight in registers
-  // two staging buffers, each an A and a B chunk
-  __shared__ T stage[2 * TBK * (LDA + LDB)];
-  const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * MI * 16, wn = (wave & 1) * NJ * 16;
@@ -131,6 +135,31 @@ __global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
           C[(long long)row * P.rsC + (long long)col * P.csC] = v;
         }
       }
+}
+
+template <class T, int MI, int NJ>
+__global__ __launch_bounds__(256) void sgemm_kernel(SGemm P, int ntn) {
+  __shared__ T stage[SGemmLds<T, MI, NJ>::kElems];
+  sgemm_tile<T, MI, NJ>(P, blockIdx.x / ntn, blockIdx.x % ntn, stage);
+}
+
+// A batch of independent products, problem blockIdx.y; the grid covers the
+// largest, tiles past a problem's dimensions return at once.
+template <class T, int MI, int NJ>
+__global__ __launch_bounds__(256) void sgemm_batched_kernel(const SGemm* __restrict__ probs, int ntn) {
+  __shared__ T stage[SGemmLds<T, MI, NJ>::kElems];
+  const SGemm P = probs[blockIdx.y];
+  const int tm = blockIdx.x / ntn, tn = blockIdx.x % ntn;
+  if (tm * 32 * MI >= P.M || tn * 32 * NJ >= P.N) return;
+  sgemm_tile<T, MI, NJ>(P, tm, tn, stage);
+}
+
+hipError_t launch_sgemm_batched(hipStream_t s, const SGemm* probs, int n_probs, int M_max, int N_max) {
+  if (n_probs <= 0 || M_max <= 0 || N_max <= 0) return hipSuccess;
+  if (n_probs > 65535) return hipErrorInvalidValue;
+  const int ntm = (M_max + 63) / 64, ntn = (N_max + 63) / 64;
+  sgemm_batched_kernel<double2, 2, 2><<<dim3(ntm * ntn, n_probs), 256, 0, s>>>(probs, ntn);
+  return hipGetLastError();
 }
 
 // Tile shape per (precision, shape class), candidate indices of
