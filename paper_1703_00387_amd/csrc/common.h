@@ -398,7 +398,7 @@ hipError_t launch_mix(hipStream_t s, const MixDesc& D, const void* in, const voi
 hipError_t launch_zero(hipStream_t s, double* a, int n);
 // Workgroups of the first stage of launch_mdot; part holds kMdotBlocks * nv
 // shares, which a second launch adds to out in a fixed order.
-constexpr int kMdotBlocks = 256;
+constexpr int kMdotBlocks = 1024;
 hipError_t launch_mdot(hipStream_t s, const double2* V, long long ldv, int nv, const double2* r, long long n,
                        double2* out, double2* part);
 hipError_t launch_msub(hipStream_t s, const double2* V, long long ldv, int nv, const double2* c, double2* r,
