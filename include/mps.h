@@ -233,6 +233,22 @@ mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int6
                         int32_t* k_dev, double* disc_dev, double* norm2_dev);
 
 /*
+ * mps_truncate in either precision, with the kept values renormalised on
+ * request (the renormalisation of App. "Auxiliary calculations").
+ *   dtype       : MPS_C128 (theta, U, Vh complex128, as mps_truncate) or
+ *                 MPS_C64 (theta, U, Vh complex64; the SVD still runs in FP64
+ *                 on an up-converted copy; U and Vh are written whole, zero
+ *                 past the kept count)
+ *   renormalize : 1: S_j <- S_j / (sum_{i<k} S_i^2)^(1/2) (the Schmidt values
+ *                 of the normalised truncated state); 0: S as mps_truncate
+ * Other arguments, limits and errors as mps_truncate; MPS_ERR_INVALID for
+ * another dtype or renormalize flag.
+ */
+mps_status mps_truncate_ex(mps_handle h, mps_stream stream, int32_t dtype, const void* theta, int64_t m, int64_t n,
+                           int64_t chi_max, double eps, int32_t renormalize, void* U, double* S, void* Vh,
+                           int32_t* k_dev, double* disc_dev, double* norm2_dev);
+
+/*
  * mps_truncate without any allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same arguments, results and errors as
@@ -308,6 +324,7 @@ typedef struct {
 #define MPS_FLAG_FIXED_SWEEPS 0x2u /* no host synchronisation inside the call */
 #define MPS_FLAG_PLAIN 0x4u     /* one bond per launch sequence (no batching; comparison form) */
 #define MPS_FLAG_CHECKPOINT 0x8u /* mps_tebd_step_ex: keep every step's chains for mps_tebd_step_vjp */
+#define MPS_FLAG_OBSERVE 0x10u   /* mps_tebd_step_ex: <op at every site> of every chain after every step */
 
 /*
  * n_steps time steps of Trotter evolution on every chain.
@@ -350,13 +367,21 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
  *                 of bonds a layer does not update are not written (clear the
  *                 log first).  Works with MPS_FLAG_GRAPH (the replayed step
  *                 reads its index from a device counter).
+ *   obs_op      : with MPS_FLAG_OBSERVE, a single-site operator, device
+ *                 complex128 [d][d] (Sec. "Observables"), else NULL
+ *   obs_log_dev : with MPS_FLAG_OBSERVE, device FP64 [n_steps][n_chains][L_max]:
+ *                 entry (step, c, i) receives <obs_op at site i> of chain c
+ *                 after that step (sum_a lam_i[a]^2 <B_i[a]| op |B_i[a]>);
+ *                 sites past a chain's L are not written.  Works with
+ *                 MPS_FLAG_GRAPH (the same device step counter).
  * Errors: as mps_tebd_step; MPS_ERR_INVALID for MPS_FLAG_CHECKPOINT without
  * an arena or with MPS_FLAG_GRAPH; MPS_ERR_CAPACITY for a short arena;
  * MPS_ERR_UNSUPPORTED for MPS_FLAG_CHECKPOINT on complex64 chains.
  */
 mps_status mps_tebd_step_ex(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
                             int32_t order, double dt, int32_t n_steps, double eps_local, uint32_t flags,
-                            void* ckpt_arena, size_t ckpt_bytes, double* disc_log_dev);
+                            void* ckpt_arena, size_t ckpt_bytes, double* disc_log_dev, const void* obs_op,
+                            double* obs_log_dev);
 /* Bytes of the checkpoint arena of mps_tebd_step_ex for these chains and
  * n_steps (host only; 0 for bad arguments). */
 size_t mps_tebd_ckpt_bytes(const mps_chain_desc* chains, int32_t n_chains, int32_t n_steps);

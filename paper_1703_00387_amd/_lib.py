@@ -19,13 +19,13 @@ MPS_OK, MPS_ERR_INVALID, MPS_ERR_SHAPE, MPS_ERR_CAPACITY, MPS_ERR_NOCONV, MPS_ER
 STATUS_NAMES = {0: "MPS_OK", 1: "MPS_ERR_INVALID", 2: "MPS_ERR_SHAPE", 3: "MPS_ERR_CAPACITY",
                 4: "MPS_ERR_NOCONV", 5: "MPS_ERR_NONFINITE", 6: "MPS_ERR_HIP", 7: "MPS_ERR_UNSUPPORTED"}
 MPS_DEV_NOCONV_SVD, MPS_DEV_NOCONV_LANCZOS, MPS_DEV_NONFINITE, MPS_DEV_SCHED_TIMEOUT = 0x1, 0x2, 0x4, 0x8
-MPS_FLAG_GRAPH, MPS_FLAG_FIXED_SWEEPS, MPS_FLAG_PLAIN, MPS_FLAG_CHECKPOINT = 0x1, 0x2, 0x4, 0x8
+MPS_FLAG_GRAPH, MPS_FLAG_FIXED_SWEEPS, MPS_FLAG_PLAIN, MPS_FLAG_CHECKPOINT, MPS_FLAG_OBSERVE = 0x1, 0x2, 0x4, 0x8, 0x10
 MPS_C64, MPS_C128 = 0, 1
 MPS_OP_TRUNCATE, MPS_OP_TEBD, MPS_OP_HEFF, MPS_OP_KRYLOV, MPS_OP_TDVP = range(5)
 
 # every exported symbol that include/mps.h declares
 EXPORTS = ["mps_create", "mps_create_ws", "mps_workspace_size", "mps_workspace_needed", "mps_destroy", "mps_last_error", "mps_reserve", "mps_device_status",
-           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_noalloc", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_ex", "mps_tebd_ckpt_bytes", "mps_tebd_step_vjp", "mps_theta_gate_vjp", "mps_truncate_vjp", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
+           "mps_set_option", "mps_kernel_stats", "mps_gates", "mps_truncate", "mps_truncate_ex", "mps_truncate_noalloc", "mps_truncate_u1", "mps_tebd_step", "mps_tebd_step_ex", "mps_tebd_ckpt_bytes", "mps_tebd_step_vjp", "mps_theta_gate_vjp", "mps_truncate_vjp", "mps_tebd_step_u1", "mps_ktebd_step", "mps_ktebd_step_u1", "mps_tebd_td_step", "mps_tebd_td_step_u1", "mps_cfme_nodes",
            "mps_observe", "mps_heff_apply", "mps_krylov_expm", "mps_env_update", "mps_tdvp2_step", "mps_tdvp2_step_u1",
            "mps_tebd_grad_arena_bytes", "mps_tebd_grad", "mps_tebd_vjp", "mps_autotune_jacobi",
            "mps_autotune_candidate", "mps_autotune_gemm", "mps_gemm_candidate", "mps_gemm_tile_choice",
@@ -80,7 +80,8 @@ def lib():
         "mps_truncate_noalloc": [vp, vp, vp, i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp],
         "mps_truncate_u1": [vp, vp, vp, i64, i64, vp, vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp],
         "mps_tebd_step": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32],
-        "mps_tebd_step_ex": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32, vp, C.c_size_t, vp],
+        "mps_tebd_step_ex": [vp, vp, C.POINTER(ChainDesc), i32, i32, dbl, i32, dbl, u32, vp, C.c_size_t, vp, vp, vp],
+        "mps_truncate_ex": [vp, vp, i32, vp, i64, i64, i64, dbl, i32, vp, vp, vp, vp, vp, vp],
         "mps_tebd_step_vjp": [vp, vp, C.POINTER(ChainDesc), i32, C.POINTER(vp), vp, C.c_size_t, C.POINTER(vp),
                               C.POINTER(vp), vp, dbl],
         "mps_theta_gate_vjp": [vp, vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp],

@@ -131,6 +131,29 @@ class Handle:
         kk = int(k.item())
         return U[:, :kk], S[:kk], Vh[:kk], kk, float(disc.item()), float(nrm.item())
 
+    def truncate_ex(self, theta: torch.Tensor, chi_max: int, eps: float, renormalize: bool = False):
+        """mps_truncate_ex: truncated SVD of a complex64 or complex128 matrix (the
+        SVD in FP64 either way); U, S, Vh (first k valid), k, disc, norm2, with S
+        renormalised on request."""
+        if (not isinstance(theta, torch.Tensor) or theta.dim() != 2
+                or theta.dtype not in (torch.complex64, torch.complex128) or theta.device.type != "cuda"):
+            raise ValueError("theta must be a complex64 or complex128 device matrix [m][n]")
+        theta = theta.contiguous()
+        m, n = theta.shape
+        dev, dt = theta.device, theta.dtype
+        U = torch.zeros((m, chi_max), dtype=dt, device=dev)
+        S = torch.zeros(chi_max, dtype=torch.float64, device=dev)
+        Vh = torch.zeros((chi_max, n), dtype=dt, device=dev)
+        k = torch.zeros(1, dtype=torch.int32, device=dev)
+        disc = torch.zeros(1, dtype=torch.float64, device=dev)
+        nrm = torch.zeros(1, dtype=torch.float64, device=dev)
+        code = _lib.MPS_C128 if dt == torch.complex128 else _lib.MPS_C64
+        self.check(lib().mps_truncate_ex(self.h, _stream(), code, _ptr(theta), m, n, chi_max, float(eps),
+                                         1 if renormalize else 0, _ptr(U), _ptr(S), _ptr(Vh), _ptr(k), _ptr(disc),
+                                         _ptr(nrm)))
+        kk = int(k.item())
+        return U[:, :kk], S[:kk], Vh[:kk], kk, float(disc.item()), float(nrm.item())
+
     def truncate_u1(self, theta: torch.Tensor, row_q, col_q, chi_max: int, eps: float):
         """U(1)-symmetric truncated SVD: theta block diagonal in the row and
         column charges (int sequences, host).  U, S, Vh, q (first k valid), k,
@@ -219,10 +242,22 @@ def tebd_ckpt_bytes(chains: Sequence[Chain], n_steps: int) -> int:
 
 
 def tebd_step_ex(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_steps: int, eps: float,
-                 flags: int = 0, ckpt: Optional[torch.Tensor] = None, disc_log: Optional[torch.Tensor] = None):
+                 flags: int = 0, ckpt: Optional[torch.Tensor] = None, disc_log: Optional[torch.Tensor] = None,
+                 obs_op: Optional[torch.Tensor] = None, obs_log: Optional[torch.Tensor] = None):
     """mps_tebd_step_ex: tebd_step with an optional checkpoint arena (uint8 device
-    tensor, with flags | MPS_FLAG_CHECKPOINT) and an optional float64 device log
-    [n_steps][n_layers][n_chains][L_max-1] of every update's discarded weight."""
+    tensor, with flags | MPS_FLAG_CHECKPOINT), an optional float64 device log
+    [n_steps][n_layers][n_chains][L_max-1] of every update's discarded weight,
+    and, with obs_op (complex128 [d][d] on the device) and obs_log (float64
+    [n_steps][n_chains][L_max] on the device), <obs_op at every site> after
+    every step (MPS_FLAG_OBSERVE is set for them)."""
+    if (obs_op is None) != (obs_log is None):
+        raise ValueError("obs_op and obs_log go together")
+    if obs_op is not None:
+        d = chains[0].d
+        l_max = max(c.L for c in chains)
+        _c128(obs_op, "obs_op", (d, d))
+        _f64(obs_log, "obs_log", (n_steps, len(chains), l_max))
+        flags |= _lib.MPS_FLAG_OBSERVE
     if disc_log is not None:
         l_max = max(c.L for c in chains)
         n_layers = {2: 3, 4: 15, 0: 2 * (l_max - 1)}.get(order, 0)
@@ -235,7 +270,7 @@ def tebd_step_ex(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_st
     arr = (ChainDesc * len(chains))(*[c.desc() for c in chains])
     nbytes = ckpt.numel() * ckpt.element_size() if ckpt is not None else 0
     h.check(lib().mps_tebd_step_ex(h.h, _stream(), arr, len(chains), order, float(dt), n_steps, float(eps), flags,
-                                   _ptr(ckpt), nbytes, _ptr(disc_log)))
+                                   _ptr(ckpt), nbytes, _ptr(disc_log), _ptr(obs_op), _ptr(obs_log)))
 
 
 def tebd_step_vjp(h: Handle, chains: Sequence[Chain], h0: Sequence[torch.Tensor], ckpt: torch.Tensor,

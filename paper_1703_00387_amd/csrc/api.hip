@@ -582,6 +582,70 @@ mps_status mps_truncate(mps_handle h, mps_stream stream, const void* theta, int6
                       nullptr, 0);
 }
 
+// S <- S / (sum_{j<k} S_j^2)^(1/2) for the kept values (one workgroup)
+__global__ __launch_bounds__(256) void renorm_kept_kernel(double* S, const int32_t* k_dev) {
+  __shared__ double red[256];
+  const int k = *k_dev;
+  double a = 0.0;
+  for (int j = threadIdx.x; j < k; j += 256) a += S[j] * S[j];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double nk = sqrt(red[0]);
+  const double inv = nk > 0.0 ? 1.0 / nk : 0.0;
+  for (int j = threadIdx.x; j < k; j += 256) S[j] *= inv;
+}
+
+mps_status mps_truncate_ex(mps_handle h, mps_stream stream, int32_t dtype, const void* theta, int64_t m, int64_t n,
+                           int64_t chi_max, double eps, int32_t renormalize, void* U, double* S, void* Vh,
+                           int32_t* k_dev, double* disc_dev, double* norm2_dev) {
+  mps_status st = truncate_check(h, theta, m, n, chi_max, eps, U, S, Vh, k_dev, disc_dev, norm2_dev);
+  if (st != MPS_OK) return st;
+  if (dtype != MPS_C64 && dtype != MPS_C128) return mps_fail(h, MPS_ERR_INVALID, "dtype must be MPS_C64 or MPS_C128");
+  if (renormalize != 0 && renormalize != 1) return mps_fail(h, MPS_ERR_INVALID, "renormalize must be 0 or 1");
+  if (m > 4096 || n > 4096) return mps_fail(h, MPS_ERR_CAPACITY, "m and n are limited to 4096");
+  const bool c64 = dtype == MPS_C64;
+  WsPlan p;
+  const size_t oT = p.take<char>(truncate_plan(m, n).off);
+  size_t oX = 0, oU = 0, oV = 0;
+  if (c64) {
+    oX = p.take<double2>((size_t)m * n);
+    oU = p.take<double2>((size_t)m * chi_max);
+    oV = p.take<double2>((size_t)chi_max * n);
+  }
+  st = mps_ensure_ws(h, p.off);
+  if (st != MPS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = h->ws;
+  const void* th = theta;
+  void* Uo = U;
+  void* Vo = Vh;
+  if (c64) {
+    // the SVD runs in FP64: theta up-converted, the factors converted back
+    MPS_TRY_HIP(h, launch_convert(s, theta, ws + oX, m * n, false));
+    th = ws + oX;
+    Uo = ws + oU;
+    Vo = ws + oV;
+    // cleared by kernels (no memset nodes if the caller captures the call)
+    MPS_TRY_HIP(h, launch_zero(s, (double*)Uo, (int)(2 * m * chi_max)));
+    MPS_TRY_HIP(h, launch_zero(s, (double*)Vo, (int)(2 * chi_max * n)));
+  }
+  st = truncate_run(h, s, th, m, n, chi_max, eps, Uo, S, Vo, k_dev, disc_dev, norm2_dev, ws + oT, nullptr, 0);
+  if (st != MPS_OK) return st;
+  if (c64) {
+    MPS_TRY_HIP(h, launch_convert(s, Uo, U, m * chi_max, true));
+    MPS_TRY_HIP(h, launch_convert(s, Vo, Vh, chi_max * n, true));
+  }
+  if (renormalize) {
+    renorm_kept_kernel<<<1, 256, 0, s>>>(S, k_dev);
+    MPS_TRY_HIP(h, hipGetLastError());
+  }
+  return MPS_OK;
+}
+
 mps_status mps_truncate_noalloc(mps_handle h, mps_stream stream, const void* theta, int64_t m, int64_t n,
                                 int64_t chi_max, double eps, void* U, double* S, void* Vh, int32_t* k_dev,
                                 double* disc_dev, double* norm2_dev) {
@@ -626,9 +690,10 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
 
 mps_status mps_tebd_step_ex(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
                             int32_t order, double dt, int32_t n_steps, double eps_local, uint32_t flags,
-                            void* ckpt_arena, size_t ckpt_bytes, double* disc_log_dev) {
+                            void* ckpt_arena, size_t ckpt_bytes, double* disc_log_dev, const void* obs_op,
+                            double* obs_log_dev) {
   return tebd_impl(h, stream, chains, n_chains, order, dt, n_steps, eps_local, flags, 0, 1 << 30, nullptr, nullptr,
-                   ckpt_arena, ckpt_bytes, disc_log_dev);
+                   ckpt_arena, ckpt_bytes, disc_log_dev, obs_op, obs_log_dev);
 }
 
 mps_status mps_ktebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,
@@ -667,7 +732,8 @@ mps_status mps_tebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_des
 // (all of them for the public entry point).
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
                      double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi,
-                     const KryOpts* kry, const mps_u1_chain* u1, void* ckpt, size_t ckpt_bytes, double* disc_log) {
+                     const KryOpts* kry, const mps_u1_chain* u1, void* ckpt, size_t ckpt_bytes, double* disc_log,
+                     const void* obs_op, double* obs_log) {
   if (!h) return MPS_ERR_INVALID;
   if (!chains || n_chains < 1) return mps_fail(h, MPS_ERR_INVALID, "need at least one chain");
   if (order != 0 && order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "order must be 0, 2 or 4");
@@ -678,8 +744,14 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   }
   if (n_steps < 0) return mps_fail(h, MPS_ERR_INVALID, "n_steps < 0");
   if (!(dt == dt) || !(eps_local == eps_local)) return mps_fail(h, MPS_ERR_INVALID, "NaN argument");
-  if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS | MPS_FLAG_PLAIN | MPS_FLAG_CHECKPOINT))
+  if (flags & ~(MPS_FLAG_GRAPH | MPS_FLAG_FIXED_SWEEPS | MPS_FLAG_PLAIN | MPS_FLAG_CHECKPOINT | MPS_FLAG_OBSERVE))
     return mps_fail(h, MPS_ERR_INVALID, "unknown flag");
+  if ((flags & MPS_FLAG_OBSERVE) && (!obs_op || !obs_log))
+    return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_OBSERVE needs an operator and a log");
+  if (!(flags & MPS_FLAG_OBSERVE)) {
+    obs_op = nullptr;
+    obs_log = nullptr;
+  }
   const bool plain = flags & MPS_FLAG_PLAIN;
   const bool checkpoint = flags & MPS_FLAG_CHECKPOINT;
   if (checkpoint) {
@@ -920,7 +992,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   const int nb_cap = jac_nb(m_cap);
   // device step counter of the discarded-weight log (bytes 192.. of the status block)
   int32_t* log_step = (int32_t*)((char*)h->status_dev + 192);
-  if (disc_log) MPS_TRY_HIP(h, launch_set_int(s, log_step, 0));
+  if (disc_log || obs_log) MPS_TRY_HIP(h, launch_set_int(s, log_step, 0));
   if (checkpoint) {
     CkptHeader hd;
     std::memset(&hd, 0, sizeof(hd));
@@ -1036,7 +1108,11 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       }
       }
     }
-    if (disc_log) MPS_TRY_HIP(h, launch_inc_int(s, log_step));
+    if (obs_log)
+      for (int c = 0; c < n_chains; ++c)
+        MPS_TRY_HIP(h, launch_observe_log(s, chains[c], (const double2*)obs_op, obs_log + (size_t)c * l_max, log_step,
+                                          (long long)n_chains * l_max));
+    if (disc_log || obs_log) MPS_TRY_HIP(h, launch_inc_int(s, log_step));
     return MPS_OK;
   };
 
@@ -1068,6 +1144,8 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   put(bits(dt));
   put(bits(eps_local));
   put((uint64_t)(uintptr_t)disc_log);
+  put((uint64_t)(uintptr_t)obs_op);
+  put((uint64_t)(uintptr_t)obs_log);
   put(kry ? (uint64_t)kry->n_max : 0);
   put(kry ? bits(kry->tol) : 0);
   put(kry ? (uint64_t)(uintptr_t)kry->n_used_dev : 0);

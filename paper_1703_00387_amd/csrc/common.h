@@ -104,11 +104,13 @@ inline double count_rule_eps(mps_handle h, double eps) { return eps >= 0.0 && ep
 // bond of the sweep (order 0) with the local Lanczos exponential of h_b
 // u1 != null: charge-carrying chains, every update truncated on its charge blocks
 // ckpt (MPS_FLAG_CHECKPOINT): the checkpoint arena of mps_tebd_step_ex;
-// disc_log: its per-update discarded-weight log (both optional)
+// disc_log: its per-update discarded-weight log; obs_op, obs_log
+// (MPS_FLAG_OBSERVE): <op at every site> of every chain after every step (all optional)
 mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains, int32_t order,
                      double dt, int32_t n_steps, double eps_local, uint32_t flags, int lo, int hi,
                      const KryOpts* kry = nullptr, const mps_u1_chain* u1 = nullptr, void* ckpt = nullptr,
-                     size_t ckpt_bytes = 0, double* disc_log = nullptr);
+                     size_t ckpt_bytes = 0, double* disc_log = nullptr, const void* obs_op = nullptr,
+                     double* obs_log = nullptr);
 
 // Checkpoint arena of mps_tebd_step_ex: a header, then for every chain the
 // block of the adjoint (mps_tebd_grad_arena_bytes of that chain), 256-byte
@@ -357,6 +359,9 @@ hipError_t launch_truncate_out(hipStream_t s, const JacMat* mat, const int32_t* 
                                const SelOut* sel, const double2* theta, int64_t m, int64_t n,
                                int64_t chi_max, double2* U, double* S, double2* Vh, int32_t* k_dev,
                                double* disc_dev, double* norm2_dev);
+// site expectation values of op1 into row *step of a log (row stride step_stride)
+hipError_t launch_observe_log(hipStream_t s, const mps_chain_desc& c, const double2* op1, double* log,
+                              const int32_t* step, long long step_stride);
 hipError_t launch_observe(hipStream_t s, const mps_chain_desc& c, const double2* op1, double* site_out,
                           const double2* op2, int op2_per_bond, double* bond_out, double* entropy_out);
 

@@ -29,9 +29,12 @@ __device__ __forceinline__ double2 ld2(const void* p, size_t i) {
 }
 
 // one workgroup per site
+// site_out[i], or with step: site_out[(*step) * step_stride + i] (a log whose
+// row the device counter selects, so a replayed graph writes the right row)
 template <class T>
 __global__ __launch_bounds__(256) void obs_site_kernel(mps_chain_desc c, const double2* __restrict__ op1,
-                                                       double* site_out) {
+                                                       double* site_out, const int32_t* step = nullptr,
+                                                       long long step_stride = 0) {
   __shared__ double red[4];
   const int i = blockIdx.x, d = c.d, cm = c.chi_max;
   const int chl = c.chi[i], chr = c.chi[i + 1];
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(256) void obs_site_kernel(mps_chain_desc c, const d
     acc += lam[a] * lam[a] * part;
   }
   double r = obs_block_sum(acc, red);
-  if (threadIdx.x == 0) site_out[i] = r;
+  if (threadIdx.x == 0) site_out[(step ? (long long)(*step) * step_stride : 0) + i] = r;
 }
 
 // grid (chi_max, L-1): workgroup (a, b) adds row a of <theta_b|op2|theta_b>
@@ -133,4 +136,13 @@ hipError_t launch_observe(hipStream_t s, const mps_chain_desc& c, const double2*
     return hipGetLastError();
   }
   return hipSuccess;
+}
+
+hipError_t launch_observe_log(hipStream_t s, const mps_chain_desc& c, const double2* op1, double* log,
+                              const int32_t* step, long long step_stride) {
+  if (c.dtype == 1)
+    obs_site_kernel<double2><<<c.L, 256, 0, s>>>(c, op1, log, step, step_stride);
+  else
+    obs_site_kernel<float2><<<c.L, 256, 0, s>>>(c, op1, log, step, step_stride);
+  return hipGetLastError();
 }

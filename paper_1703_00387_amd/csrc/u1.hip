@@ -177,17 +177,30 @@ __global__ __launch_bounds__(256) void u1_vh_kernel(const JacMat* __restrict__ m
 __global__ __launch_bounds__(256) void u1_u_kernel(const double2* __restrict__ theta, const double2* __restrict__ Vh,
                                                    const double* __restrict__ S, const SelOut* __restrict__ sel,
                                                    const int32_t* __restrict__ rowq, const int32_t* __restrict__ q_out,
-                                                   int64_t m, int64_t n, int64_t chi_max, double2* U) {
+                                                   const U1Block* __restrict__ blk, int nblk,
+                                                   const int32_t* __restrict__ cols, int64_t m, int64_t n,
+                                                   int64_t chi_max, double2* U) {
   const int k = sel->k;
   const size_t total = (size_t)m * k;
   for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
     const int i = (int)(idx / k), j = (int)(idx % k);
     double2 acc = make_double2(0.0, 0.0);
-    if (rowq[i] != q_out[j]) {
+    const int32_t q = q_out[j];
+    int b = -1;
+    if (rowq[i] == q)
+      for (int t = 0; t < nblk; ++t)
+        if (blk[t].q == q) {
+          b = t;
+          break;
+        }
+    if (b < 0) {
       U[(size_t)i * chi_max + j] = acc;
       continue;
     }
-    for (int64_t c = 0; c < n; ++c) {
+    // only the block's columns: Vh_j vanishes on the others
+    const int32_t* cb = cols + blk[b].col_off;
+    for (int t = 0; t < blk[b].n; ++t) {
+      const int64_t c = cb[t];
       const double2 a = theta[(size_t)i * n + c], v = Vh[(size_t)j * n + c];
       acc.x += a.x * v.x + a.y * v.y;
       acc.y += a.y * v.x - a.x * v.y;
@@ -693,7 +706,7 @@ extern "C" mps_status mps_truncate_u1(mps_handle h, mps_stream stream, const voi
   {
     const int g = (int)std::max<int64_t>(1, std::min<int64_t>((m * kmax + 255) / 256, 4096));
     u1_u_kernel<<<g, 256, 0, s>>>((const double2*)theta, (const double2*)Vh, S, sel, (const int32_t*)(ws + oRq),
-                                  q_out, m, n, chi_max, (double2*)U);
+                                  q_out, blk, nblk, (const int32_t*)(ws + oCols), m, n, chi_max, (double2*)U);
     MPS_TRY_HIP(h, hipGetLastError());
   }
   return MPS_OK;

@@ -342,3 +342,62 @@ def test_tebd_step_autograd_function(H):
         print(f"[boundary] TebdStep chain L={sp.L}: rel {rel:.2e}", flush=True)
         assert rel <= 1e-6
         assert np.all(g[c, sp.L - 1:] == 0.0)
+
+
+def test_truncate_ex_dtypes_and_renormalize(H):
+    """mps_truncate_ex: complex128 equals mps_truncate bit for bit (renormalised
+    S = S / |S|); complex64 input is split in FP64 on the exactly up-converted
+    matrix (values against the oracle's SVD of it, 1e-13), factors in complex64."""
+    from oracle import mps as omps
+    m, n, chi = 200, 160, 64
+    s = np.geomspace(1.0, 1e-5, min(m, n))
+    A0 = _spectral(m, n, s, (121,))
+    A0 /= np.linalg.norm(A0)
+    A = torch.from_numpy(A0).cuda()
+    U1, S1, V1, k1, w1, n1 = H.truncate(A, chi, 1e-12)
+    U2, S2, V2, k2, w2, n2 = H.truncate_ex(A, chi, 1e-12, renormalize=True)
+    assert k1 == k2 and torch.equal(U1, U2) and torch.equal(V1, V2) and w1 == w2 and n1 == n2
+    np.testing.assert_allclose(S2.cpu().numpy(), (S1 / torch.linalg.vector_norm(S1)).cpu().numpy(), rtol=1e-14)
+    A64 = A.to(torch.complex64)
+    Ar = A64.to(torch.complex128).cpu().numpy()
+    U, S, V, k, w, nrm = H.truncate_ex(A64, chi, 1e-12)
+    assert U.dtype == torch.complex64 and V.dtype == torch.complex64
+    Uo, so, Vho, wo, nko, sfull = omps.truncate(Ar, chi, 1e-12)
+    assert k == len(so)
+    assert np.abs(S.cpu().numpy() ** 2 - so ** 2).max() <= 1e-13
+    R = (U.cpu().numpy().astype(np.complex128) * S.cpu().numpy()) @ V.cpu().numpy().astype(np.complex128)
+    Ro = (Uo * so) @ Vho
+    assert np.abs(R - Ro).max() <= 2e-6
+    with pytest.raises(Exception):
+        H.truncate_ex(A.real.contiguous(), chi, 1e-12)
+
+
+def test_observation_log_matches_oracle(H):
+    """MPS_FLAG_OBSERVE: <S^z_i> of every chain after every step, eager and
+    under graph replay, against the oracle's runs of 1..n steps."""
+    from oracle import mps as omps, models as om
+    from paper_1703_00387_amd import api, models, _lib
+    specs = _batch_specs(2, 8, 16)
+    n_steps, dt, eps = 4, 0.05, 1e-12
+    l_max = max(sp.L for sp in specs)
+    sz = torch.from_numpy((0.5 * om.SZ).astype(np.complex128)).cuda()
+    a = [_chain(sp) for sp in specs]
+    log = torch.full((n_steps, len(a), l_max), -7.0, dtype=torch.float64, device="cuda")
+    print("[boundary] observation log", flush=True)
+    api.tebd_step_ex(H, a, 2, dt, n_steps, eps, obs_op=sz, obs_log=log)
+    b = [_chain(sp) for sp in specs]
+    log2 = torch.full_like(log, -7.0)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        api.tebd_step_ex(H, b, 2, dt, n_steps, eps, flags=_lib.MPS_FLAG_GRAPH, obs_op=sz, obs_log=log2)
+    st.synchronize()
+    code, word = H.device_status()
+    assert code == 0 and word == 0, (code, word)
+    lg, lg2 = log.cpu().numpy(), log2.cpu().numpy()
+    for c, sp in enumerate(specs):
+        for stp in range(n_steps):
+            ref = omps.tebd_run(sp, "tebd2", dt, stp + 1, eps)
+            want = omps.local_expect(ref, 0.5 * om.SZ)
+            assert np.abs(lg[stp, c, :sp.L] - want).max() <= 1e-10
+            assert np.abs(lg2[stp, c, :sp.L] - want).max() <= 1e-10
+        assert np.all(lg[:, c, sp.L:] == -7.0)
