@@ -441,12 +441,28 @@ def bench_u1_tebd(args):
         print(f"[bench] warmup {done}/{args.warmup} U(1) steps, chi_max now {int(ch.chi.max())}, "
               f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     cd = api.Chain(ch.L, ch.d, ch.chi_max, ch.B.clone(), ch.lam.clone(), ch.chi.clone(), ch.hbond, ch.disc.clone())
+    cg = api.Chain(ch.L, ch.d, ch.chi_max, ch.B.clone(), ch.lam.clone(), ch.chi.clone(), ch.hbond, ch.disc.clone())
+    qg = api.Charges(q.qbond.clone(), q.qsite, q.modulus)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     api.tebd_step_u1(h, [ch], [q], 4, wl.dt, args.steps, wl.eps_local)
     torch.cuda.synchronize()
     t_u1 = time.perf_counter() - t1
     print(f"[bench] {args.steps} U(1) steps {t_u1:.3f}s", file=sys.stderr, flush=True)
+    # the same steps captured once in a graph (the charge blocks are built on
+    # the device) and replayed, from a copy of the same state
+    from paper_1703_00387_amd import _lib
+    sg = torch.cuda.Stream()
+    with torch.cuda.stream(sg):
+        t1 = time.perf_counter()
+        api.tebd_step_u1(h, [cg], [qg], 4, wl.dt, 1, wl.eps_local, _lib.MPS_FLAG_GRAPH)
+        sg.synchronize()
+        t_cap = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        api.tebd_step_u1(h, [cg], [qg], 4, wl.dt, args.steps, wl.eps_local, _lib.MPS_FLAG_GRAPH)
+        sg.synchronize()
+        t_graph = time.perf_counter() - t1
+    print(f"[bench] {args.steps} U(1) steps replayed {t_graph:.3f}s", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
     api.tebd_step(h, [cd], 4, wl.dt, args.steps, wl.eps_local)
     torch.cuda.synchronize()
@@ -474,6 +490,8 @@ def bench_u1_tebd(args):
                    "L": spec.L, "chi_max": spec.chi_max, "dt": wl.dt, "eps_local": wl.eps_local},
         "dense_updates_per_s": round(n_upd / t_dense, 3),
         "speedup_over_dense": round(t_dense / t_u1, 2),
+        "graph_replay_updates_per_s": round(n_upd / t_graph, 3),
+        "graph_first_call_with_capture_ms": round(t_cap * 1e3, 3),
         "chi_max_reached": int(chi.max()),
         "sectors_mid_bond": int(len(set(qmid.tolist()))),
         "device_status": [code, word],

@@ -62,6 +62,9 @@ typedef enum {
 #define MPS_DEV_NOCONV_LANCZOS 0x2u
 #define MPS_DEV_NONFINITE      0x4u
 #define MPS_DEV_SCHED_TIMEOUT  0x8u  /* a persistent kernel's bounded wait ran out */
+#define MPS_DEV_CHARGE         0x10u /* a bond of a charge-carrying chain whose rows and columns share
+                                        no charge (or whose bond dimension is out of range): that
+                                        update was skipped, the bond keeps its tensors */
 
 typedef struct mps_context* mps_handle;
 typedef void* mps_stream; /* hipStream_t */
@@ -100,7 +103,9 @@ const char* mps_last_error(mps_handle h);
 /* Make the workspace at least `bytes` large (hipMalloc happens here; a
  * caller-owned workspace that is smaller gives MPS_ERR_CAPACITY). */
 mps_status mps_reserve(mps_handle h, size_t bytes);
-/* Synchronise `stream`, return and clear the device status word. */
+/* Synchronise `stream`, return and clear the device status word.  Returns
+ * MPS_ERR_NONFINITE, MPS_ERR_NOCONV (NOCONV or SCHED_TIMEOUT bits) or
+ * MPS_ERR_SHAPE (MPS_DEV_CHARGE) when such a bit was set, in that order. */
 mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
 /* Tuning knobs: 0 = Jacobi relative tolerance (default 1e-13),
  * 1 = Jacobi maximum sweeps (default 30), 2 = Jacobi absolute tolerance
@@ -418,14 +423,15 @@ typedef struct {
  * per bond to the union of its blocks' values, ties ordered by ascending
  * charge; B_{b+1} = V^dag_k (zero off its block's columns), lam_{b+1} and
  * qbond[b+1] follow, B_b = theta~' V_k / |s_k| as in mps_tebd_step.  The bond
- * Hamiltonians must commute with the charge.  The host reads the bond charges
- * once per layer (the block shapes set the launches), so MPS_FLAG_GRAPH is
- * refused.
+ * Hamiltonians must commute with the charge.  The charge blocks are built on
+ * the device from qbond (no host synchronisation inside a layer), so
+ * MPS_FLAG_GRAPH captures and replays the step as for dense chains; an update
+ * whose rows and columns share no charge (or whose bond dimension is out of
+ * range) is skipped, leaving the bond as it was, and sets MPS_DEV_CHARGE.
  *   charges : HOST array of n_chains descriptors, one per chain
- * Errors: as mps_tebd_step; MPS_ERR_INVALID for MPS_FLAG_GRAPH, a null
- * qbond or a modulus < 0 or == 1; MPS_ERR_SHAPE when no charge is shared
- * across a bond; MPS_ERR_CAPACITY when the bonds of one layer have more than
- * 65535 charge blocks together.
+ * Errors: as mps_tebd_step; MPS_ERR_INVALID for a null qbond or a modulus
+ * < 0 or == 1; MPS_ERR_CAPACITY when d*chi_max > 2048 or when (bonds of one
+ * layer) * d * chi_max > 65536.
  */
 mps_status mps_tebd_step_u1(mps_handle h, mps_stream stream, const mps_chain_desc* chains,
                             const mps_u1_chain* charges, int32_t n_chains, int32_t order, double dt,

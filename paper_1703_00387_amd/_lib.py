@@ -19,6 +19,7 @@ MPS_OK, MPS_ERR_INVALID, MPS_ERR_SHAPE, MPS_ERR_CAPACITY, MPS_ERR_NOCONV, MPS_ER
 STATUS_NAMES = {0: "MPS_OK", 1: "MPS_ERR_INVALID", 2: "MPS_ERR_SHAPE", 3: "MPS_ERR_CAPACITY",
                 4: "MPS_ERR_NOCONV", 5: "MPS_ERR_NONFINITE", 6: "MPS_ERR_HIP", 7: "MPS_ERR_UNSUPPORTED"}
 MPS_DEV_NOCONV_SVD, MPS_DEV_NOCONV_LANCZOS, MPS_DEV_NONFINITE, MPS_DEV_SCHED_TIMEOUT = 0x1, 0x2, 0x4, 0x8
+MPS_DEV_CHARGE = 0x10
 MPS_FLAG_GRAPH, MPS_FLAG_FIXED_SWEEPS, MPS_FLAG_PLAIN, MPS_FLAG_CHECKPOINT, MPS_FLAG_OBSERVE = 0x1, 0x2, 0x4, 0x8, 0x10
 MPS_C64, MPS_C128 = 0, 1
 MPS_OP_TRUNCATE, MPS_OP_TEBD, MPS_OP_HEFF, MPS_OP_KRYLOV, MPS_OP_TDVP = range(5)

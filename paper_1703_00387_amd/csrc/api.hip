@@ -15,6 +15,7 @@ constexpr int kFixedSweeps = 20;  // sweeps queued when the host may not synchro
 constexpr int kLoopInner = 4;     // inner sweeps per outer sweep for single-panel matrices
 constexpr int kEigSweeps = 40;    // eigen split: sweeps of the 64x64 Hermitian Jacobi (it stops when converged)
 constexpr int kSpinLimit = 1000000;  // polls of a persistent Jacobi wait before it gives up (a few seconds)
+constexpr int kSlotGrid = 1024;      // workgroup rows of a slot-mode loop launch
 
 }  // namespace
 
@@ -131,6 +132,8 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     sc.nb_cap = nb;
     sc.max_sweeps = h->jac_max_sweeps;
     sc.spin_limit = kSpinLimit;
+    sc.list = nullptr;
+    sc.act = nullptr;
     const int grid = std::max(1, std::min(h->n_cu, n * (nb / 2)));
     PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
                 launch_jac_persist(s, mats, sc, h->jac_tol, h->jac_abs, h->jac_inner_sweeps,
@@ -156,6 +159,46 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     }
   }
   if (!done) MPS_TRY_HIP(h, launch_jac_flag_noconv(s, unconv, h->status_dev));
+  return MPS_OK;
+}
+
+mps_status run_jacobi_slots(mps_handle h, hipStream_t s, JacMat* mats, int n_slots, int nb_cap, int32_t* unconv,
+                            int32_t* list, int32_t* cnt) {
+  if (n_slots <= 0) return MPS_OK;
+  if (n_slots > kSchedCap || (size_t)n_slots * nb_cap > (size_t)kSchedBlkCap)
+    return mps_fail(h, MPS_ERR_CAPACITY, "too many Jacobi slots");
+  const bool eig = h->split_method == 1;
+  unsigned long long* stats = h->profile ? h->stats_dev : nullptr;
+  // the slots to do; when every one has one panel, all their sweeps in one
+  // launch (decided on the device); else the rounds take them all
+  MPS_TRY_HIP(h, launch_jac_list(s, mats, n_slots, list, cnt));
+  PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
+              launch_jac_round(s, mats, n_slots, 2, 0, h->jac_tol, h->jac_abs,
+                               eig ? kEigSweeps : std::max(h->jac_inner_sweeps, kLoopInner),
+                               eig ? 1 : h->jac_max_sweeps, stats, h->jac_threads, 1, nullptr, eig ? 1 : 0, list,
+                               cnt, kSlotGrid));
+  if (nb_cap == 2) {
+    MPS_TRY_HIP(h, launch_jac_sweep_end(s, mats, n_slots, unconv));
+    MPS_TRY_HIP(h, launch_jac_flag_noconv(s, unconv, h->status_dev));
+    return MPS_OK;
+  }
+  // the rest on the persistent kernel, which lists them again
+  JacSched sc;
+  sc.head = (unsigned long long*)h->sched;
+  sc.n_conv = (int32_t*)(h->sched + 8);
+  sc.abort = (int32_t*)(h->sched + 12);
+  sc.done = (int32_t*)(h->sched + 16);
+  sc.ready = sc.done + kSchedCap;
+  sc.bdone = sc.ready + kSchedCap;
+  sc.n = n_slots;
+  sc.nb_cap = nb_cap;
+  sc.max_sweeps = h->jac_max_sweeps;
+  sc.spin_limit = kSpinLimit;
+  sc.list = list;
+  sc.act = cnt;
+  PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
+              launch_jac_persist(s, mats, sc, h->jac_tol, h->jac_abs, h->jac_inner_sweeps, stats, h->jac_threads,
+                                 h->n_cu, h->status_dev));
   return MPS_OK;
 }
 
@@ -519,6 +562,8 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word) {
     return mps_fail(h, MPS_ERR_NOCONV, "an iteration did not converge");
   if (w & MPS_DEV_SCHED_TIMEOUT)
     return mps_fail(h, MPS_ERR_NOCONV, "a persistent Jacobi wait ran out (results incomplete)");
+  if (w & MPS_DEV_CHARGE)
+    return mps_fail(h, MPS_ERR_SHAPE, "a bond of a charge-carrying chain shared no charge across its cut (skipped)");
   return MPS_OK;
 }
 
@@ -765,7 +810,6 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   }
   if (disc_log && (u1 || kry)) return mps_fail(h, MPS_ERR_INVALID, "the discarded-weight log is for dense gate TEBD");
   if (u1) {
-    if (flags & MPS_FLAG_GRAPH) return mps_fail(h, MPS_ERR_INVALID, "charge-carrying chains cannot be captured");
     for (int c = 0; c < n_chains; ++c)
       if (!u1[c].qbond) return mps_fail(h, MPS_ERR_INVALID, "null qbond");
       else if (u1[c].modulus < 0 || u1[c].modulus == 1)
@@ -876,8 +920,17 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
     oKPart = p.take<double2>((size_t)n_chains * kt_nblk * dd * dd);
     oKHist = p.take<double2>((size_t)n_chains * kt_hist);
   }
-  size_t oU1 = 0;
-  if (u1) oU1 = p.take<char>(u1_layer_bytes((int)max_items, d * chi_cap, chi_cap));
+  size_t oU1 = 0, oU1Items = 0;
+  if (u1) {
+    // the device block plan holds a bond's row and column charges in LDS and
+    // lists every charge block of a layer among n_items * d chi_max slots
+    if (d * chi_cap > 2048)
+      return mps_fail(h, MPS_ERR_CAPACITY, "charge-carrying chains need d*chi_max <= 2048");
+    if ((int64_t)max_items * d * chi_cap > kSchedCap)
+      return mps_fail(h, MPS_ERR_CAPACITY, "charge-carrying layers need bonds * d*chi_max <= 65536");
+    oU1 = p.take<char>(u1_layer_bytes((int)max_items, d * chi_cap, chi_cap));
+    oU1Items = p.take<U1Item>((n_par[0] + n_par[1]) * (order == 0 ? 2 : n_cls));
+  }
   mps_status st = mps_ensure_ws(h, p.off);
   if (st != MPS_OK) return st;
   char* ws = h->ws;
@@ -975,6 +1028,18 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   }
   st = upload(h, s, ws + oItems, items);
   if (st != MPS_OK) return st;
+  if (u1) {
+    // the charges of every item, beside the items
+    std::vector<U1Item> uitems(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+      const mps_u1_chain& q = u1[item_chain[i]];
+      uitems[i].qb = q.qbond;
+      uitems[i].modulus = q.modulus;
+      for (int t = 0; t < 5; ++t) uitems[i].qsite[t] = t < d ? q.qsite[t] : 0;
+    }
+    st = upload(h, s, ws + oU1Items, uitems);
+    if (st != MPS_OK) return st;
+  }
   if (kry) {
     st = upload(h, s, ws + oKJobs, kjobs);
     if (st != MPS_OK) return st;
@@ -1057,8 +1122,8 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
       if (prof) prof_end(h, s, MPS_K_THETA);
       if (u1) {
         const size_t first = start[idx] + i0;
-        mps_status r = u1_layer(h, s, items.data() + first, it, item_chain.data() + first, n, u1, (int)max_items,
-                                m_cap, chi_cap, eps_local, c128, ws + oU1, sel, unconv, fixed);
+        mps_status r = u1_layer(h, s, it, (const U1Item*)(ws + oU1Items) + first, n, (int)max_items, m_cap, chi_cap,
+                                eps_local, c128, ws + oU1, sel, unconv);
         if (r != MPS_OK) return r;
       } else {
       if (prof) prof_begin(h, s, MPS_K_PREP);
@@ -1157,6 +1222,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   put((uint64_t)h->jac_split_below);
   put((uint64_t)h->split_method);
   put((uint64_t)h->jac_persistent);
+  put(u1 ? 1 : 0);
   for (int c = 0; c < n_chains; ++c) {
     const mps_chain_desc& ch = chains[c];
     put(((uint64_t)(uint32_t)ch.L << 32) | (uint32_t)ch.d);

@@ -129,14 +129,27 @@ mps_status grad_ckpt_save(mps_handle h, hipStream_t s, const mps_chain_desc& ch,
 
 // Charge-carrying chains (u1.hip): the truncation of one layer of n bond
 // items (theta' in their X slots) on the charge blocks of every bond, in place
-// of preparation, Jacobi, selection and right write-back.  chain_of[i] is the
-// chain of item i; region holds u1_layer_bytes(n_cap, m_cap, chi_cap) bytes.
+// of preparation, Jacobi, selection and right write-back.  ui_dev[i] holds
+// the charges of item i (device); the blocks are built on the device and no
+// step synchronises with the host, so a layer can be captured in a graph.
+// m_cap <= 2048 and n_cap * m_cap <= kSchedCap; region holds
+// u1_layer_bytes(n_cap, m_cap, chi_cap) bytes.
 struct BondItem;
 struct SelOut;
+struct U1Item {
+  int32_t* qb;         // the chain's bond charges [L+1][chi_max]
+  int32_t modulus;     // 0: U(1); n >= 2: Z_n
+  int32_t qsite[5];    // charges of the local states (d <= 5)
+};
 size_t u1_layer_bytes(int n_cap, int m_cap, int chi_cap);
-mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const BondItem* it_dev, const int* chain_of,
-                    int n, const mps_u1_chain* u1c, int n_cap, int m_cap, int chi_cap, double eps, bool c128,
-                    char* region, SelOut* sel, int32_t* unconv, bool fixed);
+mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_dev, const U1Item* ui_dev, int n, int n_cap,
+                    int m_cap, int chi_cap, double eps, bool c128, char* region, SelOut* sel, int32_t* unconv);
+// Jacobi of the slots mats[0, n_slots): empty slots are converged matrices,
+// the others are found on the device (list: n_slots ints, cnt: 2 ints), so no
+// launch depends on their number; when all have one panel they run in loop
+// mode, else all of them on the persistent kernel.
+mps_status run_jacobi_slots(mps_handle h, hipStream_t s, JacMat* mats, int n_slots, int nb_cap, int32_t* unconv,
+                            int32_t* list, int32_t* cnt);
 
 // One matrix X (complex128 [m][n], m, n <= m_cap) truncated on its charge
 // blocks (row_q, col_q on the host); the kept rows, normalised, go to dst in
@@ -307,9 +320,18 @@ struct JacSplit {
   int eig;        // loop mode: one Gram, its eigensolve to convergence, one rotation
   double2* part;
 };
+// list / n_list (slot mode, optional): the round runs on the matrices
+// mats[list[k]], k < n_list[0] (at most n_mats), n_grid workgroup rows taking
+// them in turn (a loop-mode launch only when n_list[1], their largest block
+// count, is 2); otherwise on mats[0, n_mats), one workgroup row each.
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round,
                             double tol, double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
-                            int threads, int split_S = 1, double2* split_part = nullptr, int eig = 0);
+                            int threads, int split_S = 1, double2* split_part = nullptr, int eig = 0,
+                            const int32_t* list = nullptr, const int32_t* n_list = nullptr, int n_grid = 0);
+// Slot mode: the slots of mats[0, n) still to do (conv == 0), in slot order,
+// to list; their count to cnt[0] and their largest block count (at least 2)
+// to cnt[1].
+hipError_t launch_jac_list(hipStream_t s, const JacMat* mats, int n, int32_t* list, int32_t* cnt);
 // Capacity of the handle's persistent-Jacobi counters: matrices per launch.
 constexpr int kSchedCap = 65536;
 constexpr int kSchedBlkCap = 1 << 20;   // per-block round counters (matrices x blocks)
@@ -323,6 +345,11 @@ struct JacSched {
   int32_t* ready;            // [n] last sweep whose row order is set
   int32_t* bdone;            // [n][nb_cap] rounds each block has been through (or null)
   int32_t n, nb_cap, max_sweeps, spin_limit;
+  // slot mode (or null): the launch lists the matrices still to do among
+  // mats[0, n) (conv == 0) in list[], their count and largest block count in
+  // act[0], act[1]; n and nb_cap are then capacities
+  int32_t* list;
+  int32_t* act;
 };
 // All sweeps of n matrices (at most max_sweeps) in one launch of `grid`
 // resident workgroups (see jac_persist_kernel), then the convergence flags.

@@ -305,23 +305,35 @@ __device__ __forceinline__ void jac_pair_body(JacMat* __restrict__ M, int I, int
                                               double tol, double abs_tol, int inner_sweeps, int loop_sweeps,
                                               unsigned long long* stats, const JacSplit& split);
 
+// Matrix k of the launch is mats[list[k]] for k < *n_list (slot mode) or
+// mats[k] for k < n_mats; workgroup row y takes k = y, y + gridDim.y, ...
 template <int NT>
-__global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats, int round, double tol,
+__global__ __launch_bounds__(NT) void jac_round_kernel(JacMat* __restrict__ mats, int n_mats,
+                                                       const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ n_list, int round, double tol,
                                                        double abs_tol, int inner_sweeps, int loop_sweeps,
                                                        unsigned long long* stats, JacSplit split) {
-  JacMat* M = mats + blockIdx.y;
-  if (M->conv) return;
-  const int S = split.S, slice = blockIdx.x % S;
-  const int nb = M->nb, p = blockIdx.x / S;
-  if (2 * p >= nb || round >= nb - 1) return;
-  if (loop_sweeps > 0 && nb != 2) return;  // larger matrices take the round-based sweeps
-  int I, J;
-  jac_pair(nb, round, p, I, J);
-  if (loop_sweeps > 0) {  // one panel: keep the real rows first
-    I = 0;
-    J = 1;
+  // slot mode, loop mode: only when every listed matrix has one panel (as
+  // the eager schedule does: otherwise the small ones run in the rounds
+  // beside the others)
+  if (list && loop_sweeps > 0 && n_list[1] > 2) return;
+  const int nk = list ? min(*n_list, n_mats) : n_mats;
+  for (int k = blockIdx.y; k < nk; k += gridDim.y) {
+    const int mi = list ? list[k] : k;
+    JacMat* M = mats + mi;
+    if (M->conv) continue;
+    const int S = split.S, slice = blockIdx.x % S;
+    const int nb = M->nb, p = blockIdx.x / S;
+    if (2 * p >= nb || round >= nb - 1) continue;
+    if (loop_sweeps > 0 && nb != 2) continue;  // larger matrices take the round-based sweeps
+    int I, J;
+    jac_pair(nb, round, p, I, J);
+    if (loop_sweeps > 0) {  // one panel: keep the real rows first
+      I = 0;
+      J = 1;
+    }
+    jac_pair_body<NT>(M, I, J, mi, p, slice, tol, abs_tol, inner_sweeps, loop_sweeps, stats, split);
   }
-  jac_pair_body<NT>(M, I, J, blockIdx.y, p, slice, tol, abs_tol, inner_sweeps, loop_sweeps, stats, split);
 }
 
 template <int NT>
@@ -634,7 +646,11 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
   // restructure the item loop so that the other lanes re-entered it without
   // the decision; every loop inside the decision is free of barriers.
   const bool leader = __builtin_amdgcn_readfirstlane(tid) == 0;
-  const int R = sc.nb_cap - 1, P = sc.nb_cap / 2, n = sc.n;
+  // slot mode: the listed matrices (count and largest block count from the
+  // list launch before this one); else all of mats[0, n)
+  const int n = sc.list ? sc.act[0] : sc.n;
+  const int nbl = sc.list ? sc.act[1] : sc.nb_cap;
+  const int R = nbl - 1, P = nbl / 2;
   const unsigned long long total = (unsigned long long)sc.max_sweeps * R * n * P;
   JacSplit unsplit;
   unsplit.S = 1;
@@ -658,7 +674,7 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
         q /= n;
         const int r = (int)(q % R);
         sw = (int)(q / R);
-        JacMat* M = mats + mi;
+        JacMat* M = mats + (sc.list ? sc.list[mi] : mi);
         const int nb = M->nb;
         act = kActSkip;
         if (r < nb - 1 && 2 * p < nb && ld_rlx(&M->conv) == 0) {
@@ -726,7 +742,7 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
     __syncthreads();
     if (act == kActExit) break;
     if (act == kActSkip) continue;
-    JacMat* M = mats + mi;
+    JacMat* M = mats + (sc.list ? sc.list[mi] : mi);
     if (act == kActSortPair) {
       // rows by decreasing norm (the norms the last rounds left), NaN last;
       // the ranks of all rows are computed from the norms in global memory
@@ -768,6 +784,40 @@ __global__ __launch_bounds__(NT) void jac_persist_kernel(JacMat* __restrict__ ma
   }
 }
 
+// Slot mode: the slots of mats[0, n) with conv == 0 in slot order, their
+// count and their largest block count.  One workgroup of 256.
+__global__ __launch_bounds__(256) void jac_list_kernel(const JacMat* __restrict__ mats, int n, int32_t* list,
+                                                       int32_t* cnt) {
+  __shared__ int part[256];
+  __shared__ int nbmax;
+  const int tid = threadIdx.x;
+  if (tid == 0) nbmax = 2;
+  const int per = (n + 255) / 256, lo = min(n, tid * per), hi = min(n, lo + per);
+  int c = 0, nbm = 2;
+  for (int i = lo; i < hi; ++i)
+    if (mats[i].conv == 0) {
+      ++c;
+      nbm = max(nbm, mats[i].nb);
+    }
+  part[tid] = c;
+  __syncthreads();
+  atomicMax(&nbmax, nbm);
+  if (tid == 0) {
+    int acc = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int v = part[t];
+      part[t] = acc;
+      acc += v;
+    }
+    cnt[0] = acc;
+  }
+  __syncthreads();
+  int pos = part[tid];
+  for (int i = lo; i < hi; ++i)
+    if (mats[i].conv == 0) list[pos++] = i;
+  if (tid == 0) cnt[1] = nbmax;
+}
+
 // Before a persistent launch: counters cleared, matrices already converged
 // (non-finite input) counted.  One workgroup.
 __global__ void jac_persist_init_kernel(JacMat* __restrict__ mats, JacSched sc) {
@@ -778,15 +828,18 @@ __global__ void jac_persist_init_kernel(JacMat* __restrict__ mats, JacSched sc) 
     *sc.abort = 0;
   }
   __syncthreads();
+  // slot mode: the listed matrices (none of them converged)
+  const int n = sc.list ? sc.act[0] : sc.n;
   int local = 0;
-  for (int i = threadIdx.x; i < sc.n; i += blockDim.x) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    JacMat* M = mats + (sc.list ? sc.list[i] : i);
     sc.done[i] = 0;
     sc.ready[i] = 0;
-    mats[i].rot = 0;
-    local += mats[i].conv != 0;
+    M->rot = 0;
+    local += M->conv != 0;
   }
   if (sc.bdone)
-    for (int i = threadIdx.x; i < sc.n * sc.nb_cap; i += blockDim.x) sc.bdone[i] = 0;
+    for (int i = threadIdx.x; i < n * sc.nb_cap; i += blockDim.x) sc.bdone[i] = 0;
   atomicAdd(&cnt, local);
   __syncthreads();
   if (threadIdx.x == 0) *sc.n_conv = cnt;
@@ -1206,23 +1259,32 @@ hipError_t launch_jac_prep_plain(hipStream_t s, JacMat* mats, int n_mats, uint32
   return hipGetLastError();
 }
 
+hipError_t launch_jac_list(hipStream_t s, const JacMat* mats, int n, int32_t* list, int32_t* cnt) {
+  jac_list_kernel<<<1, 256, 0, s>>>(mats, n, list, cnt);
+  return hipGetLastError();
+}
+
 hipError_t launch_jac_round(hipStream_t s, JacMat* mats, int n_mats, int nb_cap, int round, double tol,
                             double abs_tol, int inner_sweeps, int loop_sweeps, unsigned long long* stats,
-                            int threads, int split_S, double2* split_part, int eig) {
+                            int threads, int split_S, double2* split_part, int eig, const int32_t* list,
+                            const int32_t* n_list, int n_grid) {
   if (n_mats <= 0) return hipSuccess;
   if (split_S < 1 || (split_S > 1 && (!split_part || loop_sweeps > 0))) return hipErrorInvalidValue;
+  if ((list == nullptr) != (n_list == nullptr) || (list && n_grid < 1)) return hipErrorInvalidValue;
   JacSplit sp;
   sp.S = split_S;
   sp.pairs = nb_cap / 2;
   sp.part = split_part;
   sp.eig = eig;
-  dim3 grid((nb_cap / 2) * split_S, n_mats);
+  dim3 grid((nb_cap / 2) * split_S, list ? std::min(n_grid, n_mats) : n_mats);
   for (int phase = split_S > 1 ? 0 : 2; phase <= (split_S > 1 ? 1 : 2); ++phase) {
     sp.phase = phase;
     if (threads == 512)
-      jac_round_kernel<512><<<grid, 512, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats, sp);
+      jac_round_kernel<512><<<grid, 512, 0, s>>>(mats, n_mats, list, n_list, round, tol, abs_tol, inner_sweeps,
+                                                  loop_sweeps, stats, sp);
     else if (threads == 256)
-      jac_round_kernel<256><<<grid, 256, 0, s>>>(mats, round, tol, abs_tol, inner_sweeps, loop_sweeps, stats, sp);
+      jac_round_kernel<256><<<grid, 256, 0, s>>>(mats, n_mats, list, n_list, round, tol, abs_tol, inner_sweeps,
+                                                  loop_sweeps, stats, sp);
     else
       return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
@@ -1235,7 +1297,9 @@ hipError_t launch_jac_persist(hipStream_t s, JacMat* mats, const JacSched& sc, d
                               int inner_sweeps, unsigned long long* stats, int threads, int grid,
                               uint32_t* status) {
   if (sc.n <= 0) return hipSuccess;
-  if (sc.nb_cap < 2 || (sc.nb_cap & 1) || grid < 1) return hipErrorInvalidValue;
+  if (sc.nb_cap < 2 || (sc.nb_cap & 1) || grid < 1 || (sc.list == nullptr) != (sc.act == nullptr))
+    return hipErrorInvalidValue;
+  if (sc.list) jac_list_kernel<<<1, 256, 0, s>>>(mats, sc.n, sc.list, sc.act);
   jac_persist_init_kernel<<<1, 256, 0, s>>>(mats, sc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

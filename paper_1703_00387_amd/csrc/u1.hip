@@ -33,12 +33,6 @@ struct U1Range {
   int32_t kmax, ncols; // cap on the kept count, columns of the matrix
 };
 
-// Per bond item of a charge-carrying chain.
-struct U1Item {
-  int32_t* qb;         // the chain's bond charges [L+1][chi_max]
-  int32_t b, chi_max, d, pad;
-};
-
 // X_b[i][j] = src[rows[i]][cols[j]], grid (chunks, blocks)
 __global__ __launch_bounds__(256) void u1_gather_kernel(const U1Block* __restrict__ blk,
                                                         const int32_t* __restrict__ rows,
@@ -100,7 +94,17 @@ __global__ __launch_bounds__(256) void u1_select_kernel(const JacMat* __restrict
     s2o[rg.row0 + r] = fmax(v[perm[r]], 0.0);
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid == 0 && R == 0) {
+    // no block (a bond without a shared charge): nothing is kept, the update
+    // is skipped
+    SelOut o;
+    o.k = 0;
+    o.m = 0;
+    o.disc = 0.0;
+    o.norm2 = 0.0;
+    o.nk = 1.0;
+    out[blockIdx.x] = o;
+  } else if (tid == 0) {
     double total = 0.0;
     for (int r = R - 1; r >= 0; --r) total += fmax(v[perm[r]], 0.0);
     int k = R;
@@ -216,24 +220,6 @@ __global__ __launch_bounds__(256) void u1_u_kernel(const double2* __restrict__ t
 // charge-carrying chains: one layer of bond items
 // ---------------------------------------------------------------------------
 
-// Row i of out: chi_b, chi_{b+2}, the charges of bond b (chi_max entries),
-// those of bond b+2 (chi_max entries).
-__global__ __launch_bounds__(256) void u1_read_kernel(const BondItem* __restrict__ items,
-                                                      const U1Item* __restrict__ ui, int stride,
-                                                      int32_t* __restrict__ out) {
-  const BondItem it = items[blockIdx.x];
-  const int cm = it.chi_max;
-  const int chl = it.chi[it.b], chr = it.chi[it.b + 2];
-  int32_t* o = out + (size_t)blockIdx.x * stride;
-  if (threadIdx.x == 0) {
-    o[0] = chl;
-    o[1] = chr;
-  }
-  const int32_t* qb = ui[blockIdx.x].qb;
-  for (int a = threadIdx.x; a < min(max(chl, 0), cm); a += 256) o[2 + a] = qb[(size_t)it.b * cm + a];
-  for (int g = threadIdx.x; g < min(max(chr, 0), cm); g += 256) o[2 + cm + g] = qb[(size_t)(it.b + 2) * cm + g];
-}
-
 // grid (kept-count cap, items): kept vector j of item i.  Its block row over
 // s_j is the new right site's row j (V^dag_k, zero off the block's columns),
 // stored in the chain's tensor and in the item's V^dag workspace; lam_{b+1},
@@ -250,6 +236,7 @@ __global__ __launch_bounds__(256) void u1_wb_kernel(const BondItem* __restrict__
   const U1Range rg = ranges[i];
   const SelOut so = sel[i];
   const int d = it.d, cm = it.chi_max, ncols = rg.ncols, chr = ncols / d;
+  if (so.k == 0) return;  // no block: the bond keeps its tensors
   if (j == 0 && threadIdx.x == 0) {
     it.chi[it.b + 1] = so.k;
     it.disc[it.b] += so.disc;
@@ -285,6 +272,269 @@ __global__ __launch_bounds__(256) void u1_wb_kernel(const BondItem* __restrict__
   if (threadIdx.x == 0) {
     it.lam_m[j] = sv / so.nk;
     ui[i].qb[(size_t)(it.b + 1) * cm + j] = B.q;
+  }
+}
+
+// Row blocks of a Jacobi matrix of m rows (32-row blocks, an even count >= 2).
+__device__ __forceinline__ int u1_nb(int m) {
+  int nb = (m + 31) / 32;
+  if (nb < 2) nb = 2;
+  return nb + (nb & 1);
+}
+
+// Largest charge-block row count per item of the device plan, and the most
+// rows (or columns) of the matrix one thread of u1_plan_kernel holds.
+constexpr int kU1PlanCap = 2048;
+constexpr int kU1PerThread = kU1PlanCap / 256;
+
+// Index of v in the ascending keys[0, K), -1 if absent.
+__device__ __forceinline__ int u1_find(const int* keys, int K, int v) {
+  int lo = 0, hi = K - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int x = keys[mid];
+    if (x == v) return mid;
+    if (x < v) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// One workgroup per bond item: the charge blocks of theta' = (rows a s,
+// columns t g) built on the device from the chain's bond charges.  Row (a, s)
+// carries q_b(a) + q(s), column (t, g) carries q_{b+2}(g) - q(t) (reduced
+// modulo n for Z_n); a block is a charge both carry, its rows and columns in
+// their order.  The item's blocks take slots [i m_cap, i m_cap + nblk) of
+// blk and mats (ascending charge), its rows and columns the same range of
+// the row and column lists, its gathered blocks [i m_cap^2, ...) of Xw; the
+// slots after its blocks are empty, already converged matrices.  A bond
+// dimension out of range or no shared charge gives no block and sets
+// MPS_DEV_CHARGE.  Dynamic LDS: 21 m_cap bytes.
+__global__ __launch_bounds__(256) void u1_plan_kernel(const BondItem* __restrict__ items,
+                                                      const U1Item* __restrict__ ui, int m_cap, double2* Xw,
+                                                      int32_t* rmap, double* nrm, U1Block* blk, U1Range* rgs,
+                                                      int32_t* rows, int32_t* cols, JacMat* mats, uint32_t* status) {
+  extern __shared__ int u1_dyn[];
+  int* rq = u1_dyn;          // [m_cap] row charges, then row slots
+  int* cq = rq + m_cap;      // [m_cap] column charges, then column slots (-1: no row has it)
+  int* keys = cq + m_cap;    // [m_cap] distinct row charges ascending, then block index or -1
+  int* nr = keys + m_cap;    // [m_cap] rows per slot, then the block's first row
+  int* nc = nr + m_cap;      // [m_cap] columns per slot, then the block's first column
+  unsigned char* fq = (unsigned char*)(nc + m_cap);  // [m_cap] first row of its charge
+  __shared__ int K_s, nblk_s;
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const BondItem it = items[i];
+  const U1Item u = ui[i];
+  const int d = it.d, cm = it.chi_max;
+  const int chl = it.chi[it.b], chr = it.chi[it.b + 2];
+  const bool bad = chl < 1 || chl > cm || chr < 1 || chr > cm || chl * d > m_cap || chr * d > m_cap;
+  const int M = bad ? 0 : chl * d, N = bad ? 0 : d * chr;
+  const int kb0 = i * m_cap;
+  const size_t x0 = (size_t)i * m_cap * m_cap;
+  const int md = u.modulus;
+  auto red = [md](long long v) -> int { return md == 0 ? (int)v : (int)(((v % md) + md) % md); };
+  for (int r = tid; r < M; r += 256)
+    rq[r] = red((long long)u.qb[(size_t)it.b * cm + r / d] + u.qsite[r % d]);
+  for (int c = tid; c < N; c += 256)
+    cq[c] = red((long long)u.qb[(size_t)(it.b + 2) * cm + c % chr] - u.qsite[c / chr]);
+  if (tid == 0) K_s = 0;
+  __syncthreads();
+  // distinct row charges: the first row of each, ranked by charge
+  for (int r = tid; r < M; r += 256) {
+    const int v = rq[r];
+    bool first = true;
+    for (int t = 0; t < r && first; ++t) first = rq[t] != v;
+    fq[r] = first ? 1 : 0;
+  }
+  __syncthreads();
+  for (int r = tid; r < M; r += 256)
+    if (fq[r]) {
+      const int v = rq[r];
+      int rank = 0;
+      for (int t = 0; t < M; ++t) rank += (fq[t] && rq[t] < v) ? 1 : 0;
+      keys[rank] = v;
+      atomicAdd(&K_s, 1);
+    }
+  __syncthreads();
+  const int K = K_s;
+  // the slot of every row and column, and the counts per slot
+  int kr[kU1PerThread], kc[kU1PerThread];
+#pragma unroll
+  for (int e = 0; e < kU1PerThread; ++e) {
+    const int x = tid + e * 256;
+    kr[e] = x < M ? u1_find(keys, K, rq[x]) : -1;
+    kc[e] = x < N ? u1_find(keys, K, cq[x]) : -1;
+  }
+  for (int k = tid; k < K; k += 256) {
+    nr[k] = 0;
+    nc[k] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kU1PerThread; ++e) {
+    const int x = tid + e * 256;
+    if (x < M) {
+      rq[x] = kr[e];
+      atomicAdd(&nr[kr[e]], 1);
+    }
+    if (x < N) {
+      cq[x] = kc[e];
+      if (kc[e] >= 0) atomicAdd(&nc[kc[e]], 1);
+    }
+  }
+  __syncthreads();
+  // the blocks in ascending charge: descriptors, then first row and column
+  if (tid == 0) {
+    int nb = 0, ro = 0, co = 0;
+    size_t xo = 0;
+    for (int k = 0; k < K; ++k) {
+      const int m = nr[k], n = nc[k];
+      if (m > 0 && n > 0) {
+        U1Block B;
+        B.src = it.X;
+        B.ld = N;
+        B.x_off = (int64_t)(x0 + xo);
+        B.q = keys[k];
+        B.m = m;
+        B.n = n;
+        B.row_off = kb0 + ro;
+        B.col_off = kb0 + co;
+        B.item = i;
+        blk[kb0 + nb] = B;
+        JacMat J;
+        J.X = Xw + x0 + xo;
+        J.rowmap = rmap + kb0 + ro;
+        J.nrm2 = nrm + kb0 + ro;
+        J.m = m;
+        J.n = n;
+        J.ld = n;
+        J.nb = u1_nb(m);
+        J.conv = 0;
+        J.rot = 0;
+        J.kmax = m;
+        J.pad = 0;
+        J.fro2 = 0.0;
+        mats[kb0 + nb] = J;
+        nr[k] = ro;
+        nc[k] = co;
+        keys[k] = nb;
+        ro += m;
+        co += n;
+        xo += (size_t)m * n;
+        ++nb;
+      } else {
+        keys[k] = -1;
+      }
+    }
+    nblk_s = nb;
+    U1Range rg;
+    rg.blk0 = kb0;
+    rg.nblk = nb;
+    rg.row0 = kb0;
+    rg.R = ro;
+    rg.kmax = min(cm, ro);
+    rg.ncols = N;
+    rgs[i] = rg;
+    if (nb == 0) atomicOr(status, MPS_DEV_CHARGE);
+  }
+  __syncthreads();
+  for (int j = nblk_s + tid; j < m_cap; j += 256) {
+    JacMat J;
+    J.X = Xw + x0;
+    J.rowmap = rmap + kb0;
+    J.nrm2 = nrm + kb0;
+    J.m = 0;
+    J.n = 0;
+    J.ld = 1;
+    J.nb = 2;
+    J.conv = 1;
+    J.rot = 0;
+    J.kmax = 0;
+    J.pad = 0;
+    J.fro2 = 0.0;
+    mats[kb0 + j] = J;
+  }
+  // a row's place: its block's first row plus the rows of its slot before it
+  for (int r = tid; r < M; r += 256) {
+    const int k = rq[r];
+    if (keys[k] < 0) continue;
+    int before = 0;
+    for (int t = 0; t < r; ++t) before += rq[t] == k ? 1 : 0;
+    rows[kb0 + nr[k] + before] = r;
+  }
+  for (int c = tid; c < N; c += 256) {
+    const int k = cq[c];
+    if (k < 0 || keys[k] < 0) continue;
+    int before = 0;
+    for (int t = 0; t < c; ++t) before += cq[t] == k ? 1 : 0;
+    cols[kb0 + nc[k] + before] = c;
+  }
+}
+
+// grid (chunks, items): the blocks of item blockIdx.y gathered,
+// X_b[i][j] = src[rows[i]][cols[j]]
+__global__ __launch_bounds__(256) void u1_gather_items_kernel(const U1Range* __restrict__ rgs,
+                                                              const U1Block* __restrict__ blk,
+                                                              const int32_t* __restrict__ rows,
+                                                              const int32_t* __restrict__ cols,
+                                                              double2* __restrict__ Xw) {
+  const U1Range rg = rgs[blockIdx.y];
+  for (int b = rg.blk0; b < rg.blk0 + rg.nblk; ++b) {
+    const U1Block B = blk[b];
+    const int64_t tot = (int64_t)B.m * B.n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+      const int r = (int)(e / B.n), c = (int)(e % B.n);
+      Xw[B.x_off + e] = B.src[(size_t)rows[B.row_off + r] * B.ld + cols[B.col_off + c]];
+    }
+  }
+}
+
+// grid (items, 16): squared row norms of the item's blocks
+__global__ __launch_bounds__(256) void u1_norms_kernel(const U1Range* __restrict__ rgs,
+                                                       const JacMat* __restrict__ mats) {
+  const U1Range rg = rgs[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int b = rg.blk0; b < rg.blk0 + rg.nblk; ++b) {
+    const JacMat& M = mats[b];
+    for (int r = blockIdx.y * 4 + wave; r < M.m; r += 4 * gridDim.y) {
+      const double2* xr = M.X + (size_t)r * M.ld;
+      double a = 0.0;
+      for (int c = lane; c < M.n; c += 64) {
+        const double2 v = xr[c];
+        a += v.x * v.x + v.y * v.y;
+      }
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+      if (lane == 0) M.nrm2[r] = a;
+    }
+  }
+}
+
+// grid (items): |X|_F^2 of every block, the natural row order, the flags
+__global__ __launch_bounds__(256) void u1_fro_kernel(const U1Range* __restrict__ rgs, JacMat* __restrict__ mats,
+                                                     uint32_t* status) {
+  __shared__ double red[256];
+  const U1Range rg = rgs[blockIdx.x];
+  const int tid = threadIdx.x;
+  for (int b = rg.blk0; b < rg.blk0 + rg.nblk; ++b) {
+    JacMat* M = mats + b;
+    const int m = M->m;
+    double a = 0.0;
+    for (int r = tid; r < m; r += 256) a += M->nrm2[r];
+    red[tid] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    const double f2 = red[0];
+    __syncthreads();
+    for (int g = tid; g < m; g += 256) M->rowmap[g] = g;
+    if (tid == 0) {
+      M->fro2 = f2;
+      M->rot = 0;
+      M->conv = (f2 == f2 && f2 < 1e300) ? 0 : 1;
+      if (M->conv) atomicOr(status, MPS_DEV_NONFINITE);
+    }
   }
 }
 
@@ -325,7 +575,7 @@ __global__ __launch_bounds__(256) void u1_rows_kernel(const JacMat* __restrict__
 
 // Workspace of u1_layer for up to n_cap items of at most m_cap rows and columns.
 struct U1Plan {
-  size_t oItems, oRb, oX, oMats, oBlk, oRg, oRows, oCols, oRm, oNrm, oPe, oS2, off;
+  size_t oItems, oRb, oX, oMats, oBlk, oRg, oRows, oCols, oRm, oNrm, oPe, oS2, oList, oCnt, off;
   U1Plan(int n_cap, int m_cap, int chi_cap) {
     WsPlan p;
     const size_t nm = (size_t)n_cap * m_cap;
@@ -341,6 +591,8 @@ struct U1Plan {
     oNrm = p.take<double>(nm);
     oPe = p.take<int32_t>(nm);
     oS2 = p.take<double>(nm);
+    oList = p.take<int32_t>(nm);
+    oCnt = p.take<int32_t>(4);
     off = p.off + 256;
   }
 };
@@ -349,167 +601,45 @@ struct U1Plan {
 
 size_t u1_layer_bytes(int n_cap, int m_cap, int chi_cap) { return U1Plan(n_cap, m_cap, chi_cap).off; }
 
-mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_host, const BondItem* it_dev, const int* chain_of,
-                    int n, const mps_u1_chain* u1c, int n_cap, int m_cap, int chi_cap, double eps, bool c128,
-                    char* region, SelOut* sel, int32_t* unconv, bool fixed) {
+mps_status u1_layer(mps_handle h, hipStream_t s, const BondItem* it_dev, const U1Item* ui_dev, int n, int n_cap,
+                    int m_cap, int chi_cap, double eps, bool c128, char* region, SelOut* sel, int32_t* unconv) {
   if (n <= 0) return MPS_OK;
-  const U1Plan P(n_cap, m_cap, chi_cap);
-  region = (char*)(((uintptr_t)region + 255) & ~(uintptr_t)255);
-  const int stride = 2 + 2 * chi_cap;
-  std::vector<U1Item> ui(n);
-  for (int i = 0; i < n; ++i) ui[i].qb = u1c[chain_of[i]].qbond;
-  MPS_TRY_HIP(h, hipMemcpyAsync(region + P.oItems, ui.data(), n * sizeof(U1Item), hipMemcpyHostToDevice, s));
-  U1Item* dUi = (U1Item*)(region + P.oItems);
-  u1_read_kernel<<<n, 256, 0, s>>>(it_dev, dUi, stride, (int32_t*)(region + P.oRb));
-  MPS_TRY_HIP(h, hipGetLastError());
-  std::vector<int32_t> rb((size_t)n * stride);
-  MPS_TRY_HIP(h, hipMemcpyAsync(rb.data(), region + P.oRb, rb.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  MPS_TRY_HIP(h, hipStreamSynchronize(s));
-  // the charge blocks of every item, ascending charge, rows and columns in order
-  std::vector<U1Block> blocks;
-  std::vector<U1Range> ranges(n);
-  std::vector<int32_t> rows, cols;
-  std::vector<int32_t> rq, cq, keys;     // per item: row and column charges, distinct row charges
-  std::vector<int> nr, nc, pr, pc;       // per charge slot: counts, then fill positions
-  int64_t xw = 0, max_mn = 1;
-  int max_m = 1, max_R = 1, k_cap = 1;
-  for (int i = 0; i < n; ++i) {
-    const BondItem& it = it_host[i];
-    const int d = it.d, cm = it.chi_max;
-    const int32_t* o = rb.data() + (size_t)i * stride;
-    const int chl = o[0], chr = o[1];
-    if (chl < 1 || chl > cm || chr < 1 || chr > cm)
-      return mps_fail(h, MPS_ERR_SHAPE, "bond dimension out of range in a charge-carrying chain");
-    const int32_t* qs = u1c[chain_of[i]].qsite;
-    const int32_t md = u1c[chain_of[i]].modulus;  // 0: U(1); n >= 2: Z_n
-    auto red = [md](int64_t v) -> int32_t { return md == 0 ? (int32_t)v : (int32_t)(((v % md) + md) % md); };
-    const int M = chl * d, N = d * chr;
-    rq.resize(M);
-    cq.resize(N);
-    int32_t lo = INT32_MAX, hi = INT32_MIN;
-    for (int a = 0; a < chl; ++a)
-      for (int s1 = 0; s1 < d; ++s1) {
-        const int32_t v = red((int64_t)o[2 + a] + qs[s1]);
-        rq[a * d + s1] = v;
-        lo = std::min(lo, v);
-        hi = std::max(hi, v);
-      }
-    for (int s2 = 0; s2 < d; ++s2)
-      for (int g = 0; g < chr; ++g) cq[s2 * chr + g] = red((int64_t)o[2 + cm + g] - qs[s2]);
-    // charge slots in ascending order: offsets from the smallest row charge
-    // when the rows' charges are dense, else positions among their sorted
-    // distinct values; a column whose charge no row has gets no slot
-    const bool direct = (int64_t)hi - lo < 4LL * (M + N);
-    keys.clear();
-    if (!direct) {
-      keys.assign(rq.begin(), rq.end());
-      std::sort(keys.begin(), keys.end());
-      keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-    }
-    auto slot = [&](int32_t v) -> int {
-      if (direct) return (v < lo || v > hi) ? -1 : (int)(v - lo);
-      auto f = std::lower_bound(keys.begin(), keys.end(), v);
-      return (f != keys.end() && *f == v) ? (int)(f - keys.begin()) : -1;
-    };
-    const int K = direct ? (int)(hi - lo + 1) : (int)keys.size();
-    nr.assign(K, 0);
-    nc.assign(K, 0);
-    for (int r = 0; r < M; ++r) nr[slot(rq[r])]++;
-    for (int c = 0; c < N; ++c) {
-      const int k = slot(cq[c]);
-      if (k >= 0) nc[k]++;
-    }
-    U1Range& rg = ranges[i];
-    rg.blk0 = (int32_t)blocks.size();
-    rg.row0 = (int32_t)rows.size();
-    rg.ncols = N;
-    pr.assign(K, -1);
-    pc.assign(K, -1);
-    size_t rtot = rows.size(), ctot = cols.size();
-    for (int k = 0; k < K; ++k) {
-      if (nr[k] == 0 || nc[k] == 0) continue;
-      U1Block b;
-      b.src = it.X;
-      b.ld = N;
-      b.q = direct ? lo + k : keys[k];
-      b.m = nr[k];
-      b.n = nc[k];
-      b.row_off = (int32_t)rtot;
-      b.col_off = (int32_t)ctot;
-      b.item = i;
-      b.x_off = xw;
-      pr[k] = (int)rtot;
-      pc[k] = (int)ctot;
-      rtot += b.m;
-      ctot += b.n;
-      xw += (int64_t)b.m * b.n;
-      max_m = std::max(max_m, b.m);
-      max_mn = std::max<int64_t>(max_mn, (int64_t)b.m * b.n);
-      blocks.push_back(b);
-    }
-    rows.resize(rtot);
-    cols.resize(ctot);
-    for (int r = 0; r < M; ++r) {
-      const int k = slot(rq[r]);
-      if (pr[k] >= 0) rows[pr[k]++] = r;
-    }
-    for (int c = 0; c < N; ++c) {
-      const int k = slot(cq[c]);
-      if (k >= 0 && pc[k] >= 0) cols[pc[k]++] = c;
-    }
-    rg.nblk = (int32_t)blocks.size() - rg.blk0;
-    rg.R = (int32_t)rows.size() - rg.row0;
-    if (rg.nblk == 0)
-      return mps_fail(h, MPS_ERR_SHAPE, "no charge is shared across a bond of a charge-carrying chain");
-    rg.kmax = std::min(cm, rg.R);
-    max_R = std::max(max_R, rg.R);
-    k_cap = std::max(k_cap, rg.kmax);
-  }
-  const int nblk = (int)blocks.size();
-  if (nblk > 65535) return mps_fail(h, MPS_ERR_CAPACITY, "more than 65535 charge blocks in one layer");
-  if ((int64_t)xw > (int64_t)n_cap * m_cap * m_cap || (int64_t)nblk > (int64_t)n_cap * m_cap ||
-      (int64_t)rows.size() > (int64_t)n_cap * m_cap || (int64_t)cols.size() > (int64_t)n_cap * m_cap)
+  if (n > n_cap || m_cap > kU1PlanCap || (int64_t)n_cap * m_cap > kSchedCap)
     return mps_fail(h, MPS_ERR_CAPACITY, "charge blocks exceed the layer workspace");
-  char* const ws = region;
-  std::vector<JacMat> hm(nblk);
-  for (int i = 0; i < nblk; ++i) {
-    std::memset(&hm[i], 0, sizeof(JacMat));
-    hm[i].X = (double2*)(ws + P.oX) + blocks[i].x_off;
-    hm[i].rowmap = (int32_t*)(ws + P.oRm) + blocks[i].row_off;
-    hm[i].nrm2 = (double*)(ws + P.oNrm) + blocks[i].row_off;
-    hm[i].m = blocks[i].m;
-    hm[i].n = blocks[i].n;
-    hm[i].ld = blocks[i].n;
-    hm[i].nb = jac_nb(blocks[i].m);
-    hm[i].kmax = blocks[i].m;
-  }
-  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oMats, hm.data(), nblk * sizeof(JacMat), hipMemcpyHostToDevice, s));
-  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oBlk, blocks.data(), nblk * sizeof(U1Block), hipMemcpyHostToDevice, s));
-  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oRg, ranges.data(), n * sizeof(U1Range), hipMemcpyHostToDevice, s));
-  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oRows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  MPS_TRY_HIP(h, hipMemcpyAsync(ws + P.oCols, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  const U1Plan P(n_cap, m_cap, chi_cap);
+  char* const ws = (char*)(((uintptr_t)region + 255) & ~(uintptr_t)255);
+  double2* Xw = (double2*)(ws + P.oX);
   JacMat* mats = (JacMat*)(ws + P.oMats);
-  const U1Block* blk = (const U1Block*)(ws + P.oBlk);
-  const U1Range* rgd = (const U1Range*)(ws + P.oRg);
-  const int gx = (int)std::min<int64_t>((max_mn + 255) / 256, 1024);
-  u1_gather_kernel<<<dim3(gx, nblk), 256, 0, s>>>(blk, (const int32_t*)(ws + P.oRows), (const int32_t*)(ws + P.oCols),
-                                                 (double2*)(ws + P.oX));
+  U1Block* blk = (U1Block*)(ws + P.oBlk);
+  U1Range* rgd = (U1Range*)(ws + P.oRg);
+  int32_t* rows = (int32_t*)(ws + P.oRows);
+  int32_t* cols = (int32_t*)(ws + P.oCols);
+  // the blocks, their rows and columns from the bond charges on the device:
+  // no launch below depends on their number or shapes on the host
+  u1_plan_kernel<<<n, 256, (size_t)m_cap * (5 * sizeof(int) + 1), s>>>(
+      it_dev, ui_dev, m_cap, Xw, (int32_t*)(ws + P.oRm), (double*)(ws + P.oNrm), blk, rgd, rows, cols, mats,
+      h->status_dev);
   MPS_TRY_HIP(h, hipGetLastError());
-  MPS_TRY_HIP(h, launch_jac_prep_plain(s, mats, nblk, h->status_dev));
-  mps_status st = run_jacobi(h, s, mats, nblk, jac_nb(max_m), max_m, unconv, fixed);
+  const int gx = std::max(1, std::min(64, m_cap * m_cap / 4096));
+  u1_gather_items_kernel<<<dim3(gx, n), 256, 0, s>>>(rgd, blk, rows, cols, Xw);
+  MPS_TRY_HIP(h, hipGetLastError());
+  u1_norms_kernel<<<dim3(n, 16), 256, 0, s>>>(rgd, mats);
+  MPS_TRY_HIP(h, hipGetLastError());
+  u1_fro_kernel<<<n, 256, 0, s>>>(rgd, mats, h->status_dev);
+  MPS_TRY_HIP(h, hipGetLastError());
+  mps_status st = run_jacobi_slots(h, s, mats, n * m_cap, jac_nb(m_cap), unconv, (int32_t*)(ws + P.oList),
+                                   (int32_t*)(ws + P.oCnt));
   if (st != MPS_OK) return st;
   int32_t* pe = (int32_t*)(ws + P.oPe);
   double* s2o = (double*)(ws + P.oS2);
-  u1_select_kernel<<<n, 256, (size_t)max_R * (sizeof(double) + sizeof(int)), s>>>(mats, blk, rgd,
-                                                                                   count_rule_eps(h, eps), pe, s2o, sel);
+  u1_select_kernel<<<n, 256, (size_t)m_cap * (sizeof(double) + sizeof(int)), s>>>(mats, blk, rgd,
+                                                                                 count_rule_eps(h, eps), pe, s2o, sel);
   MPS_TRY_HIP(h, hipGetLastError());
-  const int32_t* dcols = (const int32_t*)(ws + P.oCols);
   if (c128)
-    u1_wb_kernel<double2><<<dim3(k_cap, n), 256, 0, s>>>(it_dev, dUi, mats, blk, rgd, dcols, pe, s2o, sel);
+    u1_wb_kernel<double2><<<dim3(chi_cap, n), 256, 0, s>>>(it_dev, ui_dev, mats, blk, rgd, cols, pe, s2o, sel);
   else
-    u1_wb_kernel<float2><<<dim3(k_cap, n), 256, 0, s>>>(it_dev, dUi, mats, blk, rgd, dcols, pe, s2o, sel);
+    u1_wb_kernel<float2><<<dim3(chi_cap, n), 256, 0, s>>>(it_dev, ui_dev, mats, blk, rgd, cols, pe, s2o, sel);
   MPS_TRY_HIP(h, hipGetLastError());
-  MPS_TRY_HIP(h, hipStreamSynchronize(s));  // the host vectors go out of scope at return
   return MPS_OK;
 }
 

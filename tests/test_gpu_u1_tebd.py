@@ -145,18 +145,50 @@ def test_u1_tebd_equals_dense_gpu_tebd(H):
 
 
 def test_u1_tebd_errors(H):
+    """A bond whose rows and columns share no charge: the blocks are found on
+    the device, so its update is skipped there (the bond keeps B_0, lam_1,
+    chi_1 and its charges) and the device status reports MPS_DEV_CHARGE."""
     from paper_1703_00387_amd import api, _lib
     spec = W.xxz_chain(6, 4, 1.0, 0.5)
     ch, q = _chain(spec, [1, 0])
+    H.device_status()
+    q.qbond[0, 0] = 100                  # bond 0's rows carry charges no column has (no update rewrites it)
+    before = (ch.B[0].clone(), ch.lam[1].clone(), ch.chi[1].clone(), q.qbond[1].clone())
+    api.tebd_step_u1(H, [ch], [q], 2, 0.05, 1, 1e-10)
+    code, word = H.device_status()
+    assert code == _lib.MPS_ERR_SHAPE and word & _lib.MPS_DEV_CHARGE
+    for a, b in zip(before, (ch.B[0], ch.lam[1], ch.chi[1], q.qbond[1])):
+        assert torch.equal(a, b)
+
+
+def test_u1_tebd_graph_replay_matches_eager_and_oracle(H):
+    """MPS_FLAG_GRAPH on charge-carrying chains (the charge blocks are built on
+    the device, no host synchronisation inside a step): the step is captured
+    once and replayed 20 times over four calls, with eager torch work on the
+    stream between the calls; the state equals the eager run's (bond
+    dimensions and charges exactly, Schmidt values to 1e-12) and matches the
+    oracle's blockwise TEBD at the bars of this file."""
+    from oracle import u1
+    from paper_1703_00387_amd import api, _lib
+    spec = W.xxz_chain(12, 16, 1.0, 0.5)
+    ref, qref = u1.tebd_run_u1(spec, "tebd2", 0.05, 20, 1e-10, [1, 0])
+    ce, qe = _chain(spec, [1, 0])
+    cg, qg = _chain(spec, [1, 0])
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        with pytest.raises(_lib.MPSError) as e:
-            api.tebd_step_u1(H, [ch], [q], 2, 0.05, 1, 1e-10, _lib.MPS_FLAG_GRAPH)
-    assert e.value.code == _lib.MPS_ERR_INVALID
-    q.qbond[2, 0] = 100                  # bond 0's columns carry charges no row has
-    with pytest.raises(_lib.MPSError) as e:
-        api.tebd_step_u1(H, [ch], [q], 2, 0.05, 1, 1e-10)
-    assert e.value.code == _lib.MPS_ERR_SHAPE
+        api.tebd_step_u1(H, [ce], [qe], 2, 0.05, 20, 1e-10)
+        for _ in range(4):
+            api.tebd_step_u1(H, [cg], [qg], 2, 0.05, 5, 1e-10, _lib.MPS_FLAG_GRAPH)
+            junk = torch.ones(1 << 16, device=cg.B.device, dtype=torch.float64).cumsum(0)
+            assert float(junk[-1].item()) == float(1 << 16)
+    s.synchronize()
+    code, word = H.device_status()
+    assert code == 0, word
+    assert torch.equal(ce.chi, cg.chi) and torch.equal(qe.qbond, qg.qbond)
+    dl = (ce.lam - cg.lam).abs().max().item()
+    print(f"graph vs eager max|d lam| = {dl:.2e}")
+    assert dl <= 1e-12
+    _check(H, cg, qg, ref, qref, spec)
 
 
 def test_u1_tebd_at_the_bench_shape_equals_dense(H):
