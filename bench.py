@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid only for the kernel source
 # it was measured on (hash of its files); otherwise null.
 JAC_ROUND_TRAFFIC = {
-    "sources_sha256": "ad340838f2482566951f889fa490521e77fda120f6924618f43a29b73699ea1e",
-    "bytes_per_launch": 3.8767e10,
+    "sources_sha256": "dd763ca18b8a25194c63f2baba7a3ae6eb00da1771a23e0e75be5b7c2918124d",
+    "bytes_per_launch": 3.8853e10,
     "warmup": 5,   # state: 140 prelude steps + this many warmup steps from the Neel state
 }
 JAC_ROUND_SOURCES = ("svd.hip", "jacobi_small.h", "mfma_tile.h")
