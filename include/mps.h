@@ -388,7 +388,9 @@ mps_status mps_tebd_step_ex(mps_handle h, mps_stream stream, const mps_chain_des
                             void* ckpt_arena, size_t ckpt_bytes, double* disc_log_dev, const void* obs_op,
                             double* obs_log_dev);
 /* Bytes of the checkpoint arena of mps_tebd_step_ex for these chains and
- * n_steps (host only; 0 for bad arguments). */
+ * n_steps, enough for the adjoint of a TEBD2 or a TEBD4 run (the reverse
+ * pass keeps one snapshot per layer of a step; host only; 0 for bad
+ * arguments). */
 size_t mps_tebd_ckpt_bytes(const mps_chain_desc* chains, int32_t n_chains, int32_t n_steps);
 
 /*
@@ -680,14 +682,16 @@ mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* 
                          int32_t n_steps, double eps_local, double eta, const void* op1, int32_t site,
                          const void* op2, void* arena, size_t arena_bytes, double* loss_dev, double* dJ_dev);
 /*
- * The vector-Jacobian product of a batched TEBD2 run recorded by
- * mps_tebd_step_ex with MPS_FLAG_CHECKPOINT (order 2), for any cotangent of
+ * The vector-Jacobian product of a batched TEBD2 or TEBD4 run recorded by
+ * mps_tebd_step_ex with MPS_FLAG_CHECKPOINT (order 2 or 4), for any cotangent of
  * the final states: with dL = sum_c Re <dB_final[c], dB_c> + <dLam_final[c],
  * dlam_c> (the cotangent of a complex entry x is dL/dRe x + i dL/dIm x),
  * dJ_dev[c][b] receives dL/dJ_b of chain c, where that chain's bond terms
  * are h_b = J_b h0[c][b].  The reverse pass is the one of mps_tebd_grad
  * (truncated-SVD backward with the kept/discarded coupling and a Lorentzian
- * broadening eta), run chain by chain on the chain's arena block.
+ * broadening eta), run chain by chain on the chain's arena block; for
+ * TEBD4 it walks the 15 layers of every step (classes of time steps p dt/2,
+ * p dt, (1-4p) dt/2, (1-4p) dt) in reverse.
  *   chains      : the chains of the forward call, holding their final states
  *                 (left so on return)
  *   h0          : HOST array of n_chains device pointers, complex128
@@ -698,7 +702,8 @@ mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* 
  *   dJ_dev      : device FP64 [n_chains][L_max-1], overwritten (entries past
  *                 a chain's L-1 are 0)
  * Synchronises `stream`.  Errors: MPS_ERR_INVALID for an arena not written by
- * an order-2 mps_tebd_step_ex for the same chains, null pointers or eta < 0;
+ * an order-2 or order-4 mps_tebd_step_ex for the same chains, null pointers
+ * or eta < 0;
  * MPS_ERR_CAPACITY for a short arena or d*chi_max > 2560.
  */
 mps_status mps_tebd_step_vjp(mps_handle h, mps_stream stream, const mps_chain_desc* chains, int32_t n_chains,

@@ -277,7 +277,7 @@ def tebd_step_vjp(h: Handle, chains: Sequence[Chain], h0: Sequence[torch.Tensor]
                   dB: Sequence[torch.Tensor], dlam: Sequence[torch.Tensor], eta: float = 1e-12) -> torch.Tensor:
     """mps_tebd_step_vjp: dL/dJ [n_chains, L_max-1] for state cotangents dB
     (complex128, the layout of each chain's B) and dlam (float64, of lam) of a
-    TEBD2 run recorded by tebd_step_ex with MPS_FLAG_CHECKPOINT."""
+    TEBD2 or TEBD4 run recorded by tebd_step_ex with MPS_FLAG_CHECKPOINT."""
     n = len(chains)
     if not (len(h0) == len(dB) == len(dlam) == n):
         raise ValueError("one h0, dB and dlam per chain")
@@ -579,11 +579,12 @@ class TebdObservables(torch.autograd.Function):
 
 
 class TebdStep(torch.autograd.Function):
-    """Final Hastings-form states of a batched TEBD2 run as a differentiable
-    function of the per-bond couplings J [n_chains, L_max-1] (chain c has
-    h_b = J[c, b] h0[c][b]), from product states:
+    """Final Hastings-form states of a batched TEBD2 (order 2) or TEBD4
+    (order 4) run as a differentiable function of the per-bond couplings
+    J [n_chains, L_max-1] (chain c has h_b = J[c, b] h0[c][b]), from product
+    states:
 
-        outs = TebdStep.apply(J, h, vectors, chi_max, h0, dt, n_steps, eps, eta)
+        outs = TebdStep.apply(J, h, vectors, chi_max, h0, dt, n_steps, eps, eta, order)
 
     vectors[c] and h0[c] are chain c's initial site vectors and unit bond
     terms (complex128 [L_c-1][d^2][d^2]).  outs = (B_0, lam_0, chi_0, B_1,
@@ -593,8 +594,10 @@ class TebdStep(torch.autograd.Function):
     B and lam (zero where None).  Complex128 chains only."""
 
     @staticmethod
-    def forward(ctx, J, h, vectors, chi_max, h0, dt, n_steps, eps, eta=1e-12):
+    def forward(ctx, J, h, vectors, chi_max, h0, dt, n_steps, eps, eta=1e-12, order=2):
         n = len(vectors)
+        if order not in (2, 4):
+            raise ValueError("order must be 2 (TEBD2) or 4 (TEBD4)")
         if J.dim() != 2 or J.shape[0] != n:
             raise ValueError("J must be [n_chains, L_max-1]")
         dev = J.device
@@ -607,7 +610,7 @@ class TebdStep(torch.autograd.Function):
             hb = J.detach()[c, :L - 1].to(torch.complex128)[:, None, None] * h0d[c]
             chains.append(Chain.product(vectors[c], chi_max, hb.cpu().numpy(), device=dev, dtype="c128"))
         ck = torch.zeros(tebd_ckpt_bytes(chains, n_steps), dtype=torch.uint8, device=dev)
-        tebd_step_ex(h, chains, 2, dt, n_steps, eps, flags=_lib.MPS_FLAG_CHECKPOINT, ckpt=ck)
+        tebd_step_ex(h, chains, order, dt, n_steps, eps, flags=_lib.MPS_FLAG_CHECKPOINT, ckpt=ck)
         ctx.state = (h, chains, h0d, ck, eta, J.shape[1])
         outs = []
         for ch in chains:
@@ -623,7 +626,7 @@ class TebdStep(torch.autograd.Function):
         dJ = tebd_step_vjp(h, chains, h0d, ck, dB, dl, eta)
         out = torch.zeros((len(chains), width), dtype=torch.float64, device=dJ.device)
         out[:, :dJ.shape[1]] = dJ
-        return (out,) + (None,) * 8
+        return (out,) + (None,) * 9
 
 
 def autotune_gemm(h: Handle, kind: int, dtype: str, M: int, N: int, K: int, batch: int = 1, apply: bool = True):

@@ -1,11 +1,12 @@
-// Reverse-mode gradient of a TEBD2 run with respect to per-bond couplings.
+// Reverse-mode gradient of a TEBD2 or TEBD4 run with respect to per-bond
+// couplings.
 //
 // Loss: sum_i w_i <O1 at site i> + sum_b w_b <O2 on bond b> of the final state
 // (the observables of Sec. "Observables"; one site with weight 1 and every bond
 // with weight 1 for mps_tebd_grad, any weights for mps_tebd_vjp).  The forward run stores the chain at
 // the start of every step (checkpoints); the backward pass restores each step,
-// re-runs its three layers keeping a snapshot before every layer, and walks
-// the updates in reverse.  Per update (Hastings write-back of the forward):
+// re-runs its layers (3 for TEBD2, 15 for TEBD4) keeping a snapshot before
+// every layer, and walks the updates in reverse.  Per update (Hastings write-back of the forward):
 //   B_b' = theta~' V_k / n_k,  B_{b+1}' = V_k^dag,  lam' = s_k / n_k
 //   theta' = lam_b theta~',  theta~' = G theta~,  theta~ = B_b B_{b+1}.
 // The truncated-SVD backward is the full reduced-SVD backward with the
@@ -300,10 +301,12 @@ mps_status gemm128(Ctx& c, const void* A, long long rsA, long long csA, int conj
 
 // Layout of the caller's arena: (n_steps + 1) step checkpoints, three layer
 // snapshots, the site and bond cotangents, the gates and their derivatives.
+// n_layers, n_cls: layers of one step and their time-step classes (3 and 2
+// for TEBD2, 15 and 4 for TEBD4).
 struct GradArena {
   size_t snapB, snapL, snapC, snap;
   size_t oCk, oLay, oBb, oLb, oG, oDG, oGJ, total;
-  GradArena(int L, int d, int cm, int n_steps) {
+  GradArena(int L, int d, int cm, int n_steps, int n_layers = 3, int n_cls = 2) {
     const size_t site_el = (size_t)cm * d * cm, dd = (size_t)d * d;
     snapB = (size_t)L * site_el * sizeof(double2);
     snapL = (size_t)(L + 1) * cm * sizeof(double);
@@ -311,12 +314,12 @@ struct GradArena {
     snap = al(snapB) + al(snapL) + al(snapC);
     WsPlan p;
     oCk = p.take<char>((size_t)(n_steps + 1) * snap);
-    oLay = p.take<char>(3 * snap);
+    oLay = p.take<char>((size_t)n_layers * snap);
     oBb = p.take<double2>((size_t)L * site_el);
     oLb = p.take<double>((size_t)(L + 1) * cm);
-    oG = p.take<double2>((size_t)2 * (L - 1) * dd * dd);
-    oDG = p.take<double2>((size_t)2 * (L - 1) * dd * dd);
-    oGJ = p.take<GateJob>((size_t)2 * (L - 1));
+    oG = p.take<double2>((size_t)n_cls * (L - 1) * dd * dd);
+    oDG = p.take<double2>((size_t)n_cls * (L - 1) * dd * dd);
+    oGJ = p.take<GateJob>((size_t)n_cls * (L - 1));
     total = p.off;
   }
   static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -754,10 +757,16 @@ int64_t ckpt_shape_sum(const mps_chain_desc* chains, int n_chains) {
   return t;
 }
 
+// A chain's block of the checkpoint arena holds the adjoint's arena of the
+// larger scheme (TEBD4: 15 layer snapshots, 4 gate classes), so one arena
+// serves runs of either order.
+size_t ckpt_block_bytes(const mps_chain_desc& ch, int n_steps) {
+  return (GradArena(ch.L, ch.d, ch.chi_max, n_steps, 15, 4).total + 255) & ~size_t(255);
+}
+
 size_t ckpt_block_offset(const mps_chain_desc* chains, int c, int n_steps) {
   size_t off = kCkptHeader;
-  for (int i = 0; i < c; ++i)
-    off += (GradArena(chains[i].L, chains[i].d, chains[i].chi_max, n_steps).total + 255) & ~size_t(255);
+  for (int i = 0; i < c; ++i) off += ckpt_block_bytes(chains[i], n_steps);
   return off;
 }
 
@@ -783,7 +792,7 @@ mps_status grad_ckpt_save(mps_handle h, hipStream_t s, const mps_chain_desc& ch,
   return MPS_OK;
 }
 
-// The adjoint of a TEBD2 run for the weighted loss
+// The adjoint of a TEBD2 (order 2) or TEBD4 (order 4) run for the weighted loss
 //   sum_i w1[i] <op1 at i> + sum_b w2[b] <op2 on bond b>   (host weights);
 // obs_dev (optional) receives the 2L-1 final observables, loss_dev (optional)
 // the loss, dJ_dev the gradient.
@@ -792,7 +801,7 @@ mps_status grad_ckpt_save(mps_handle h, hipStream_t s, const mps_chain_desc& ch,
 // mps_tebd_step_ex with MPS_CHECKPOINT), the chain holds the final state, and
 // the reverse pass starts from these state cotangents instead of the loss.
 static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0,
-                                 double dt, int32_t n_steps, double eps_local, double eta, const void* op1,
+                                 int order, double dt, int32_t n_steps, double eps_local, double eta, const void* op1,
                                  const double* w1, const void* op2, const double* w2, void* arena_ptr,
                                  size_t arena_bytes, double* obs_dev, double* loss_dev, double* dJ_dev,
                                  const void* dB_seed = nullptr, const double* dLam_seed = nullptr) {
@@ -811,8 +820,28 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
         return mps_fail(h, MPS_ERR_INVALID, "non-finite loss weight");
   if (n_steps < 1) return mps_fail(h, MPS_ERR_INVALID, "n_steps must be >= 1");
   if (!(eta >= 0.0) || !(dt > 0.0) || !(eps_local >= 0.0)) return mps_fail(h, MPS_ERR_INVALID, "bad dt, eps or eta");
+  if (order != 2 && order != 4) return mps_fail(h, MPS_ERR_INVALID, "the adjoint covers TEBD2 and TEBD4 runs");
   const int L = ch.L, d = ch.d, cm = ch.chi_max, dd = d * d;
-  const GradArena A(L, d, cm, n_steps);
+  // the layers of one step (parity, time-step class) and the classes' time
+  // steps, as the forward schedules them (Strang: odd tau/2, even tau, odd
+  // tau/2; TEBD4: five Strang steps of weights p, p, 1 - 4p, p, p)
+  std::vector<double> taus;
+  std::vector<std::pair<int, int>> lys;
+  if (order == 2) {
+    taus = {0.5 * dt, dt};
+    lys = {{0, 0}, {1, 1}, {0, 0}};
+  } else {
+    const double pw = 1.0 / (4.0 - std::cbrt(4.0));
+    taus = {0.5 * pw * dt, pw * dt, 0.5 * (1.0 - 4.0 * pw) * dt, (1.0 - 4.0 * pw) * dt};
+    const int cls5[5] = {0, 0, 2, 0, 0};
+    for (int st = 0; st < 5; ++st) {
+      lys.push_back({0, cls5[st]});
+      lys.push_back({1, cls5[st] + 1});
+      lys.push_back({0, cls5[st]});
+    }
+  }
+  const int n_lay = (int)lys.size(), n_cls = (int)taus.size();
+  const GradArena A(L, d, cm, n_steps, n_lay, n_cls);
   if (arena_bytes < A.total)
     return mps_fail(h, MPS_ERR_CAPACITY, "arena smaller than mps_tebd_grad_arena_bytes()");
   hipStream_t s = (hipStream_t)stream;
@@ -853,16 +882,15 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
   if (!seeded) {
     for (int st = 0; st < n_steps; ++st) {
       if ((r = save(arena + A.oCk + (size_t)st * A.snap)) != MPS_OK) return r;
-      if ((r = tebd_impl(h, stream, &ch, 1, 2, dt, 1, eps_local, 0, 0, 3)) != MPS_OK) return r;
+      if ((r = tebd_impl(h, stream, &ch, 1, order, dt, 1, eps_local, 0, 0, n_lay)) != MPS_OK) return r;
     }
     if ((r = save(arena + A.oCk + (size_t)n_steps * A.snap)) != MPS_OK) return r;
   }
 
-  // ---- gates of the two classes (tau = dt/2 on odd layers, dt on the even one) and dG/dJ
-  const double taus[2] = {0.5 * dt, dt};
+  // ---- gates of every class and dG/dJ
   {
     std::vector<GateJob> jobs;
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < n_cls; ++k)
       for (int b = 0; b < L - 1; ++b) {
         GateJob j;
         std::memset(&j, 0, sizeof(j));
@@ -875,7 +903,7 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
     MPS_TRY_HIP(h, hipMemcpyAsync(arena + A.oGJ, jobs.data(), jobs.size() * sizeof(GateJob), hipMemcpyHostToDevice, s));
     MPS_TRY_HIP(h, hipStreamSynchronize(s));
     MPS_TRY_HIP(h, launch_gates(s, (const GateJob*)(arena + A.oGJ), (int)jobs.size(), dd));
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < n_cls; ++k)
       for (int b = 0; b < L - 1; ++b)
         K1((dgate_kernel<<<1, 256, 0, s>>>((const double2*)h0 + (size_t)b * dd * dd, Gp(k, b), taus[k], dd,
                                             dGp(k, b))));
@@ -963,17 +991,17 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
   const double abs_saved = h->jac_abs;
   for (int stp = n_steps - 1; stp >= 0; --stp) {
     if ((r = restore(arena + A.oCk + (size_t)stp * A.snap)) != MPS_OK) return r;
-    for (int li = 0; li < 3; ++li) {
+    for (int li = 0; li < n_lay; ++li) {
       if ((r = save(lay + (size_t)li * A.snap)) != MPS_OK) return r;
-      if ((r = tebd_impl(h, stream, &ch, 1, 2, dt, 1, eps_local, 0, li, li + 1)) != MPS_OK) return r;
+      if ((r = tebd_impl(h, stream, &ch, 1, order, dt, 1, eps_local, 0, li, li + 1)) != MPS_OK) return r;
     }
     if ((r = grad_scratch(h, L, d, cm, g)) != MPS_OK) return r;
-    for (int li = 2; li >= 0; --li) {
+    for (int li = n_lay - 1; li >= 0; --li) {
       double2 *SB, *NB;
       double *SL, *NL;
       int32_t *SC, *NC;
       A.ptrs(lay + (size_t)li * A.snap, SB, SL, SC);
-      if (li < 2) {
+      if (li < n_lay - 1) {
         A.ptrs(lay + (size_t)(li + 1) * A.snap, NB, NL, NC);
       } else {
         NB = (double2*)ch.B;
@@ -984,7 +1012,7 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
       MPS_TRY_HIP(h, hipMemcpyAsync(co.data(), SC, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       MPS_TRY_HIP(h, hipMemcpyAsync(cn.data(), NC, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       MPS_TRY_HIP(h, hipStreamSynchronize(s));
-      const int par = (li == 1) ? 1 : 0, cls = (li == 1) ? 1 : 0;
+      const int par = lys[li].first, cls = lys[li].second;
       std::vector<int> bonds;
       for (int b = par; b < L - 1; b += 2) bonds.push_back(b);
       const int ni = (int)bonds.size();
@@ -1151,8 +1179,8 @@ extern "C" mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_c
   if (site < 0 || site >= chain->L) return mps_fail(h, MPS_ERR_INVALID, "site out of range");
   std::vector<double> w1(chain->L, 0.0), w2(chain->L - 1, 1.0);
   w1[site] = 1.0;
-  return tebd_grad_impl(h, stream, chain, h0, dt, n_steps, eps_local, eta, op1, w1.data(), op2, w2.data(), arena_ptr,
-                        arena_bytes, nullptr, loss_dev, dJ_dev);
+  return tebd_grad_impl(h, stream, chain, h0, 2, dt, n_steps, eps_local, eta, op1, w1.data(), op2, w2.data(),
+                        arena_ptr, arena_bytes, nullptr, loss_dev, dJ_dev);
 }
 
 extern "C" mps_status mps_tebd_vjp(mps_handle h, mps_stream stream, const mps_chain_desc* chain, const void* h0,
@@ -1161,7 +1189,7 @@ extern "C" mps_status mps_tebd_vjp(mps_handle h, mps_stream stream, const mps_ch
                                    size_t arena_bytes, double* obs_dev, double* dJ_dev) {
   if (!h) return MPS_ERR_INVALID;
   if (!chain || chain->L < 2) return mps_fail(h, MPS_ERR_INVALID, "null or short chain");
-  return tebd_grad_impl(h, stream, chain, h0, dt, n_steps, eps_local, eta, op1, w_site, op2, w_bond, arena_ptr,
+  return tebd_grad_impl(h, stream, chain, h0, 2, dt, n_steps, eps_local, eta, op1, w_site, op2, w_bond, arena_ptr,
                         arena_bytes, obs_dev, nullptr, dJ_dev);
 }
 
@@ -1179,7 +1207,8 @@ extern "C" mps_status mps_tebd_step_vjp(mps_handle h, mps_stream stream, const m
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
   if (hd.magic != kCkptMagic || hd.n_chains != n_chains || hd.shape_sum != ckpt_shape_sum(chains, n_chains))
     return mps_fail(h, MPS_ERR_INVALID, "the arena was not written by mps_tebd_step_ex for these chains");
-  if (hd.order != 2) return mps_fail(h, MPS_ERR_INVALID, "the adjoint covers order-2 (TEBD2) runs");
+  if (hd.order != 2 && hd.order != 4)
+    return mps_fail(h, MPS_ERR_INVALID, "the adjoint covers TEBD2 and TEBD4 (order 2 and 4) runs");
   if (ckpt_bytes < mps_tebd_ckpt_bytes(chains, n_chains, hd.n_steps))
     return mps_fail(h, MPS_ERR_CAPACITY, "arena smaller than mps_tebd_ckpt_bytes()");
   int l_max = 2;
@@ -1188,8 +1217,8 @@ extern "C" mps_status mps_tebd_step_vjp(mps_handle h, mps_stream stream, const m
   for (int c = 0; c < n_chains; ++c) {
     if (!h0[c] || !dB_final[c] || !dLam_final[c]) return mps_fail(h, MPS_ERR_INVALID, "null per-chain pointer");
     char* block = (char*)ckpt_arena + ckpt_block_offset(chains, c, hd.n_steps);
-    const size_t bytes = GradArena(chains[c].L, chains[c].d, chains[c].chi_max, hd.n_steps).total;
-    mps_status r = tebd_grad_impl(h, stream, chains + c, h0[c], hd.dt, hd.n_steps, hd.eps_local, eta, nullptr,
+    const size_t bytes = ckpt_block_bytes(chains[c], hd.n_steps);
+    mps_status r = tebd_grad_impl(h, stream, chains + c, h0[c], hd.order, hd.dt, hd.n_steps, hd.eps_local, eta, nullptr,
                                   nullptr, nullptr, nullptr, block, bytes, nullptr, nullptr,
                                   dJ_dev + (size_t)c * (l_max - 1), dB_final[c], dLam_final[c]);
     if (r != MPS_OK) return r;

@@ -196,6 +196,85 @@ def test_checkpointed_vjp_matches_oracle_and_single_chain(H):
         assert np.all(dJ[c, sp.L - 1:] == 0.0)
 
 
+def test_checkpointed_vjp_tebd4_matches_oracle(H):
+    """mps_tebd_step_vjp after a checkpointed batched TEBD4 run (15 layers a
+    step) against the oracle's reverse mode through its own TEBD4 run, for
+    L = sum_i w_i <S^z_i> of the final states; chi_max = 4 cuts on L = 8.
+    Also api.TebdStep with order 4 under torch.autograd."""
+    from oracle import grad, models as om
+    from paper_1703_00387_amd import api, _lib, models
+    dt, n_steps, eps = 0.1, 3, 1e-12
+    specs = [W.xxz_chain(L, chi, 1.0, 0.5, J_b=W.xxz_grad_couplings(L)) for L, chi in ((6, 8), (8, 4))]
+    h0s = []
+    for sp in specs:
+        unit = copy.copy(sp)
+        unit.J_b = np.ones(sp.L - 1)
+        h0s.append(torch.from_numpy(np.ascontiguousarray(models.bond_hamiltonians(unit))).cuda())
+    chains = [_chain(sp) for sp in specs]
+    ck = torch.zeros(api.tebd_ckpt_bytes(chains, n_steps), dtype=torch.uint8, device="cuda")
+    print("[boundary] checkpointed TEBD4 forward", flush=True)
+    api.tebd_step_ex(H, chains, 4, dt, n_steps, eps, flags=_lib.MPS_FLAG_CHECKPOINT, ckpt=ck)
+    torch.cuda.synchronize()
+    sz = 0.5 * om.SZ
+    weights, dBs, dls = [], [], []
+    for c, (sp, ch) in enumerate(zip(specs, chains)):
+        w = W.random_real((sp.L,), (95, c), -1.0, 1.0)
+        weights.append(w)
+        B, lam, chis = ch.B.cpu().numpy(), ch.lam.cpu().numpy(), ch.chi.cpu().numpy()
+        dB, dl = np.zeros_like(B), np.zeros_like(lam)
+        for i in range(sp.L):
+            a, r = chis[i], chis[i + 1]
+            Bi = B[i, :a, :, :r]
+            OB = np.einsum("st,atc->asc", sz, Bi)
+            l = lam[i, :a]
+            dB[i, :a, :, :r] = 2 * w[i] * (l ** 2)[:, None, None] * OB
+            dl[i, :a] += 2 * w[i] * l * np.real(np.einsum("asc,asc->a", Bi.conj(), OB))
+        dBs.append(torch.from_numpy(dB).cuda())
+        dls.append(torch.from_numpy(dl).cuda())
+    print("[boundary] tebd_step_vjp TEBD4", flush=True)
+    dJ = api.tebd_step_vjp(H, chains, h0s, ck, dBs, dls, eta=1e-12).cpu().numpy()
+    code, word = H.device_status()
+    assert code == 0, word
+    refs = []
+    for c, sp in enumerate(specs):
+        J = torch.tensor(np.asarray(sp.J_b, dtype=np.float64), requires_grad=True)
+        Bt, lt = grad.tebd2_state_torch(sp, J, dt, n_steps, sp.chi_max, eps, 1e-12, method="tebd4")
+        loss = sum(weights[c][i] * grad.site_expect_torch(Bt, lt, sz, i) for i in range(sp.L))
+        loss.backward()
+        g_or = J.grad.numpy()
+        refs.append(g_or)
+        rel = np.linalg.norm(dJ[c, :sp.L - 1] - g_or) / np.linalg.norm(g_or)
+        print(f"[boundary] TEBD4 chain L={sp.L} chi={sp.chi_max}: rel vs oracle {rel:.2e}", flush=True)
+        assert rel <= 1e-6
+        assert np.all(dJ[c, sp.L - 1:] == 0.0)
+    # the same through the autograd Function with order 4
+    Jn = np.zeros((2, 7))
+    for c, sp in enumerate(specs):
+        Jn[c, :sp.L - 1] = sp.J_b
+    Jt = torch.tensor(Jn, device="cuda", requires_grad=True)
+    szt = torch.from_numpy(sz.astype(np.complex128)).cuda()
+    outs = []
+    for c, sp in enumerate(specs):
+        o = api.TebdStep.apply(Jt[c:c + 1], H, [W.initial_vectors(sp)], sp.chi_max, [h0s[c].cpu().numpy()], dt,
+                               n_steps, eps, 1e-12, 4)
+        outs.append(o)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    for c, sp in enumerate(specs):
+        B, lam, chis = outs[c][0], outs[c][1], outs[c][2].cpu().numpy()
+        for i in range(sp.L):
+            a, r = int(chis[i]), int(chis[i + 1])
+            Bi = B[i, :a, :, :r]
+            OB = torch.einsum("st,atc->asc", szt, Bi)
+            loss = loss + weights[c][i] * torch.sum(lam[i, :a] ** 2 * torch.real(torch.einsum("asc,asc->a",
+                                                                                              Bi.conj(), OB)))
+    loss.backward()
+    g = Jt.grad.cpu().numpy()
+    for c, sp in enumerate(specs):
+        rel = np.linalg.norm(g[c, :sp.L - 1] - refs[c]) / np.linalg.norm(refs[c])
+        print(f"[boundary] TebdStep order 4 chain L={sp.L}: rel {rel:.2e}", flush=True)
+        assert rel <= 1e-6
+
+
 def _unitary(n, seed):
     q, _ = np.linalg.qr(W.random_complex((n, n), seed))
     return q

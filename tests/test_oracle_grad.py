@@ -74,6 +74,22 @@ def test_reverse_vs_fd_and_ed(L, steps, chi):
         assert np.linalg.norm(g_rev - g_ed) / np.linalg.norm(g_ed) < 1e-7
 
 
+def test_reverse_tebd4_vs_fd_and_ed():
+    """The reverse mode through a TEBD4 run (15 layers per step, four time-step
+    classes) against central differences and the exact circuit's adjoint
+    (nothing cut at chi = 8 on L = 6)."""
+    spec = W.xxz_chain(6, 8, 1.0, 0.5, J_b=W.xxz_grad_couplings(6))
+    loss, g_rev = grad.reverse_gradient(spec, 0.1, 3, 8, 1e-12, method="tebd4")
+    g_fd = grad.fd_gradient(spec, 0.1, 3, 8, 1e-12, method="tebd4")
+    assert np.linalg.norm(g_rev - g_fd) / np.linalg.norm(g_fd) < 1e-7
+    loss_ed, g_ed = grad.ed_gradient(spec, 0.1, 3, method="tebd4")
+    assert abs(loss - loss_ed) < 1e-8
+    assert np.linalg.norm(g_rev - g_ed) / np.linalg.norm(g_ed) < 1e-7
+    # and it is not the TEBD2 gradient of the same run
+    _, g2 = grad.reverse_gradient(spec, 0.1, 3, 8, 1e-12, method="tebd2")
+    assert np.linalg.norm(g2 - g_rev) / np.linalg.norm(g_rev) > 1e-6
+
+
 def test_broadening_sensitivity_small():
     spec = W.xxz_chain(6, 8, 1.0, 0.5, J_b=W.xxz_grad_couplings(6))
     gs = [grad.reverse_gradient(spec, 0.05, 6, 8, 1e-12, eta=eta)[1] for eta in (1e-10, 1e-12, 1e-14)]
