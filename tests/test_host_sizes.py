@@ -32,5 +32,16 @@ def test_checkpoint_arena_bytes():
     chains = [api.Chain.product(W.initial_vectors(sp), 16, models.bond_hamiltonians(sp), device="cpu")
               for sp in specs]
     per = [_lib.lib().mps_tebd_grad_arena_bytes(sp.L, 2, 16, 5) for sp in specs]
-    assert api.tebd_ckpt_bytes(chains, 5) == 256 + sum((b + 255) // 256 * 256 for b in per)
+    # a chain's block is the TEBD2 adjoint arena plus what a TEBD4 reverse pass
+    # needs besides: 12 more layer snapshots (B, lam, chi of the chain each)
+    # and the gates and their derivatives of two more time-step classes
+    extra = []
+    for sp in specs:
+        al = lambda x: (x + 255) // 256 * 256
+        snap = al(sp.L * 16 * 2 * 16 * 16) + al((sp.L + 1) * 16 * 8) + al((sp.L + 1) * 4)
+        gates = 2 * 2 * (sp.L - 1) * 4 * 4 * 16        # two classes, G and dG, (d^2)^2 complex128
+        extra.append(12 * snap + gates)
+    total = api.tebd_ckpt_bytes(chains, 5)
+    lo = 256 + sum((b + e + 255) // 256 * 256 for b, e in zip(per, extra))
+    assert lo <= total <= lo + len(specs) * 4096   # alignment and the gate jobs
     assert api.tebd_ckpt_bytes(chains, 0) == 0
