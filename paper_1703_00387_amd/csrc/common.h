@@ -292,6 +292,24 @@ hipError_t launch_gates(hipStream_t s, const GateJob* jobs, int n, int dd);
 // Workgroups of the list-walking launches (theta and batched GEMM with
 // tile_offs): 8 per CU of the 256-CU device.
 constexpr int kListGrid = 2048;
+// Workgroups are dealt to the chip's 8 XCDs round-robin in launch order, and
+// every XCD has its own L2.  For a batch of products of tiles_cap tiles each,
+// launch index L goes to product xcd + 8 j (xcd = L % 8, j = (L / 8) /
+// tiles_cap) and tile (L / 8) % tiles_cap: every product stays on one XCD, so
+// its tiles, which read the same operand panels, meet in one L2, and the
+// products of a layer (large ones in the bulk of a chain, small ones at its
+// ends) are interleaved over the XCDs.  The grid is xcd_grid(n, tiles_cap);
+// returns false past the last product.
+constexpr int kXcds = 8;
+__device__ __forceinline__ bool xcd_item_tile(int L, int n_items, int tiles_cap, int& item, int& tile) {
+  const int slot = L / kXcds;
+  item = L % kXcds + kXcds * (slot / tiles_cap);
+  tile = slot % tiles_cap;
+  return item < n_items;
+}
+inline long long xcd_grid(long long n_items, long long tiles_cap) {
+  return (n_items + kXcds - 1) / kXcds * kXcds * tiles_cap;
+}
 // tile_offs (optional, n_items + 1 int32 of device scratch): walk the list of
 // the bonds' real tiles with a fixed grid instead of a grid sized for chi_cap
 hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, bool c128,

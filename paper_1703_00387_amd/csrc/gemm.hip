@@ -119,13 +119,16 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int tm, int tn, uns
       }
 }
 
-// Grid over (capacity tiles, problems).
+// 1-D grid over the capacity tiles of all problems, each problem on one XCD
+// (tile row-major within it).
 template <class T, bool BT, int MI, int NJ>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmProb* __restrict__ probs, int ntn_cap,
-                                                   unsigned long long* stats) {
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmProb* __restrict__ probs, int n_probs, int ntn_cap,
+                                                   int tiles_cap, unsigned long long* stats) {
   __shared__ T stage[BGemmLds<T, MI, NJ>::kElems];
-  const GemmProb P = probs[blockIdx.y];
-  gemm_tile<T, BT, MI, NJ>(P, blockIdx.x / ntn_cap, blockIdx.x % ntn_cap, stats, stage);
+  int item, tile;
+  if (!xcd_item_tile(blockIdx.x, n_probs, tiles_cap, item, tile)) return;
+  const GemmProb P = probs[item];
+  gemm_tile<T, BT, MI, NJ>(P, tile / ntn_cap, tile % ntn_cap, stats, stage);
 }
 
 // offs[i] = output tiles (BM x BN) of the problems before i (dimensions read on
@@ -197,8 +200,8 @@ static hipError_t bgemm_go(hipStream_t s, const GemmProb* probs, int n_probs, in
     gemm_list_kernel<T, BT, MI, NJ><<<grid, 256, 0, s>>>(probs, n_probs, tile_offs, stats);
     return hipGetLastError();
   }
-  dim3 grid(ntm * ntn, n_probs);
-  gemm_kernel<T, BT, MI, NJ><<<grid, 256, 0, s>>>(probs, ntn, stats);
+  const int grid = (int)xcd_grid(n_probs, (long long)ntm * ntn);
+  gemm_kernel<T, BT, MI, NJ><<<grid, 256, 0, s>>>(probs, n_probs, ntn, ntm * ntn, stats);
   return hipGetLastError();
 }
 

@@ -137,15 +137,19 @@ __device__ __forceinline__ void theta_tile(const BondItem& it, int d, int TA, in
   }
 }
 
-// Grid over (capacity tiles, items): tiles past an item's dimensions return.
+// 1-D grid over the capacity tiles of all items, each item on one XCD (tile
+// row-major within it); tiles past an item's dimensions return.
 template <class T>
-__global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restrict__ items, int d, int TA,
-                                                         int TC, int ntc_cap, unsigned long long* stats,
+__global__ __launch_bounds__(256) void theta_gate_kernel(const BondItem* __restrict__ items, int n_items, int d,
+                                                         int TA, int TC, int ntc_cap, int tiles_cap,
+                                                         unsigned long long* stats,
                                                          const void* __restrict__ G_override) {
   __shared__ T smem[ThetaLds<T>::kElems];
   __shared__ T Gs[25 * 25];
-  const BondItem it = items[blockIdx.y];
-  theta_tile<T>(it, d, TA, TC, blockIdx.x / ntc_cap, blockIdx.x % ntc_cap, stats, G_override, smem, Gs);
+  int item, tile;
+  if (!xcd_item_tile(blockIdx.x, n_items, tiles_cap, item, tile)) return;
+  const BondItem it = items[item];
+  theta_tile<T>(it, d, TA, TC, tile / ntc_cap, tile % ntc_cap, stats, G_override, smem, Gs);
 }
 
 // Number of output tiles of item i: ceil(chi_l / TA) * ceil(chi_r / TC) from
@@ -221,10 +225,10 @@ hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d
       theta_gate_list_kernel<float2><<<grid, 256, 0, s>>>(items, n_items, tile_offs, d, TA, TC, stats, G_override);
     return hipGetLastError();
   }
-  dim3 grid(nta * ntc, n_items);
+  const int grid = (int)xcd_grid(n_items, (long long)nta * ntc);
   if (c128)
-    theta_gate_kernel<double2><<<grid, 256, 0, s>>>(items, d, TA, TC, ntc, stats, G_override);
+    theta_gate_kernel<double2><<<grid, 256, 0, s>>>(items, n_items, d, TA, TC, ntc, nta * ntc, stats, G_override);
   else
-    theta_gate_kernel<float2><<<grid, 256, 0, s>>>(items, d, TA, TC, ntc, stats, G_override);
+    theta_gate_kernel<float2><<<grid, 256, 0, s>>>(items, n_items, d, TA, TC, ntc, nta * ntc, stats, G_override);
   return hipGetLastError();
 }
