@@ -9,10 +9,11 @@
 // sized for the capacity and tiles beyond a problem's dimensions return at
 // once, or a fixed grid walks a device-built list of the real tiles.  The
 // workgroup tile is (32 MI) x (32 NJ), chosen per precision and shape class
-// from the table the autotuner fills (64 x 64 until then).
+// from the table the autotuner fills (64 x 64 until then); a complex product
+// is three real MFMA products (mfma_3m.h).
 #include <algorithm>
 
-#include "mfma_tile.h"
+#include "mfma_3m.h"
 
 __device__ __forceinline__ int gemm_dim_m(const GemmProb& P) { return P.M_dev ? P.M_mul * *P.M_dev : P.M; }
 __device__ __forceinline__ int gemm_dim_n(const GemmProb& P) { return P.N_dev ? P.N_mul * *P.N_dev : P.N; }
@@ -43,8 +44,8 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int tm, int tn, uns
   T* PC = (T*)P.C;
   T* As = stage;
   T* Bs = stage + TBK * LDA;
-  AccTileT<T, MI, NJ> acc;
-  acc_zero_t<T, MI, NJ>(acc);
+  Acc3<T, MI, NJ> acc;
+  acc3_zero<T, MI, NJ>(acc);
   for (int k0 = 0; k0 < K; k0 += TBK) {
     {
       const int i0 = tid >> 2, kq = (tid & 3) * 4;
@@ -97,7 +98,7 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int tm, int tn, uns
       }
     }
     __syncthreads();
-    mma_chunk_t<T, MI, NJ>(As, LDA, Bs, LDB, acc, wm, wn, lane);
+    mma3_chunk<T, MI, NJ>(As, LDA, Bs, LDB, acc, wm, wn, lane);
     __syncthreads();
   }
   typedef typename Cx<T>::R R;
@@ -111,9 +112,9 @@ __device__ __forceinline__ void gemm_tile(const GemmProb& P, int tm, int tn, uns
         int row = m0 + wm + i * 16 + Cx<T>::acc_row(lane, r);
         int col = n0 + wn + j * 16 + (lane & 15);
         if (row < M && col < N) {
-          T v;
-          v.x = alpha * acc.re[i][j][r];
-          v.y = alpha * acc.im[i][j][r];
+          T v = acc3_get<T, MI, NJ>(acc, i, j, r);
+          v.x *= alpha;
+          v.y *= alpha;
           PC[(size_t)row * P.ldc + col] = v;
         }
       }

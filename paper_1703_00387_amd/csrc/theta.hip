@@ -3,7 +3,8 @@
 // For bond b of a Hastings-form chain (Sec. "Basic concepts": contraction of
 // two neighbouring tensors into Theta; App. "Details of the Krylov method":
 // steps 1 and 3 of the plain TEBD update):
-//   theta~[a,s,t,c]  = sum_beta B_b[a,s,beta] B_{b+1}[beta,t,c]    (FP32 MFMA)
+//   theta~[a,s,t,c]  = sum_beta B_b[a,s,beta] B_{b+1}[beta,t,c]    (MFMA, three real
+//                      products per complex one)
 //   theta~'[a,u,v,c] = sum_{s,t} G[(u v),(s t)] theta~[a,s,t,c]    (epilogue)
 //   theta'[a,u,v,c]  = lam_b[a] theta~'[a,u,v,c]                   (FP64 out)
 // The workgroup tile covers a block of TA left indices a, every s, every t and
@@ -15,13 +16,57 @@
 // The chain precision T is complex64 (FP32 MFMA) or complex128 (FP64 MFMA).
 #include <algorithm>
 
-#include "mfma_tile.h"
+#include "mfma_3m.h"
 
 // two staging buffers (A and B tiles each), reused for the output tile
 template <class T>
 struct ThetaLds {
   static constexpr int kElems = TBM * (TBN + 1) > 4 * TBK * TLD ? TBM * (TBN + 1) : 4 * TBK * TLD;
 };
+
+// Epilogue of one tile for local dimension D: for every (a, c) pair of the
+// tile, the D^2 (s, t) slices from the LDS tile Cs, the gate applied,
+// theta~' to Tt and lam_b[a] theta~' to X.
+template <class T, int D>
+__device__ __forceinline__ void theta_epilogue(const BondItem& it, const T* Cs, const T* Gs, int a0, int c0, int na,
+                                               int nc, int TC, int chr, int n, T* Tt, double2* X) {
+  typedef typename Cx<T>::R R;
+  constexpr int DD = D * D;
+  for (int p = threadIdx.x; p < na * TC; p += 256) {
+    const int al = p / TC, cl = p % TC;
+    if (cl >= nc) continue;
+    const int a = a0 + al, c = c0 + cl;
+    // slice q = s D + t of the pair; held in registers for D <= 3, read from
+    // the LDS tile for larger D (25 complex128 would crowd the registers)
+    constexpr int DR = D <= 3 ? DD : 1, UQ = D <= 3 ? DD : 1;
+    T th[DR];
+    if (D <= 3) {
+#pragma unroll
+      for (int q = 0; q < DR; ++q) th[q] = Cs[(al * D + q / D) * (TBN + 1) + (q % D) * TC + cl];
+    }
+    auto slice = [&](int q) -> T { return D <= 3 ? th[q % DR] : Cs[(al * D + q / D) * (TBN + 1) + (q % D) * TC + cl]; };
+    const double la = it.lam_l[a];
+#pragma unroll 1
+    for (int u = 0; u < D; ++u)
+#pragma unroll 1
+      for (int v = 0; v < D; ++v) {
+        R ar = 0, ai = 0;
+        const T* g = Gs + (u * D + v) * DD;
+#pragma unroll UQ
+        for (int q = 0; q < DD; ++q) {
+          const T x = slice(q);
+          ar += g[q].x * x.x - g[q].y * x.y;
+          ai += g[q].x * x.y + g[q].y * x.x;
+        }
+        T acc2;
+        acc2.x = ar;
+        acc2.y = ai;
+        const size_t off = (size_t)(a * D + u) * n + v * chr + c;
+        Tt[off] = acc2;
+        X[off] = make_double2(la * (double)acc2.x, la * (double)acc2.y);
+      }
+  }
+}
 
 // One output tile (left block ta, right block tc) of item `it`; a tile past
 // the bond's dimensions returns at once.  smem holds ThetaLds<T>::kElems
@@ -43,8 +88,8 @@ __device__ __forceinline__ void theta_tile(const BondItem& it, int d, int TA, in
   const T* Gsrc = G_override ? (const T*)G_override : (const T*)it.G;
   for (int i = tid; i < dd * dd; i += 256) Gs[i] = Gsrc[i];
 
-  AccTile<T> acc;
-  acc_zero<T>(acc);
+  Acc3<T, 2, 2> acc;
+  acc3_zero<T, 2, 2>(acc);
   const int rows_valid = min(TA, chl - a0) * d;    // tile rows i < rows_valid are real
   const int K = chm;
   const T* Abase = (const T*)it.Bl + (size_t)a0 * d * chi_max;
@@ -52,7 +97,8 @@ __device__ __forceinline__ void theta_tile(const BondItem& it, int d, int TA, in
   // A tile: rows i (a = a0 + i/d, s = i%d), k = k0..k0+15, staged as As[k][i];
   // B tile: k, columns j (t = j/TC, c = c0 + j%TC), staged as Bs[k][j].
   // kPf chunks are in flight in registers ahead of the one being multiplied.
-  constexpr int kPf = 3;
+  // (complex128: one, which leaves the registers of the three accumulators)
+  constexpr int kPf = sizeof(T) == 16 ? 1 : 3;
   const int ia = tid >> 2, kqa = (tid & 3) * 4;
   const int kb = tid >> 4, jqb = (tid & 15) * 4;
   T va[kPf][4], vb[kPf][4];
@@ -95,13 +141,20 @@ __device__ __forceinline__ void theta_tile(const BondItem& it, int d, int TA, in
       if (ci < nch) {
         if (ci + kPf < nch) load(ci + kPf, va[u], vb[u]);  // chunk ci's registers were staged already
         const T* As = smem + (ci & 1) * 2 * TBK * TLD;
-        mma_chunk<T>(As, As + TBK * TLD, acc, wm, wn, lane);
+        mma3_chunk<T, 2, 2>(As, TLD, As + TBK * TLD, TLD, acc, wm, wn, lane);
         if (ci + 1 < nch) store((ci + 1) & 1, va[(u + 1) % kPf], vb[(u + 1) % kPf]);
         __syncthreads();
       }
     }
   }
-  acc_to_lds<T>(acc, Cs, TBN + 1, wm, wn, lane);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Cs[(wm + i * 16 + Cx<T>::acc_row(lane, r)) * (TBN + 1) + wn + j * 16 + (lane & 15)] =
+            acc3_get<T, 2, 2>(acc, i, j, r);
   __syncthreads();
 
   // epilogue: gate on the (s,t) slices of every (a, c) pair, then lam scaling
@@ -111,29 +164,12 @@ __device__ __forceinline__ void theta_tile(const BondItem& it, int d, int TA, in
   const int na = min(TA, chl - a0), nc = min(TC, chr - c0);
   if (tid == 0 && stats)  // useful flops: theta GEMM 8*rows*cols*K, gate 8*(d^2)^2 per (a,c)
     atomicAdd(&stats[0], (unsigned long long)(8ull * (na * d) * (nc * d) * K + 8ull * dd * dd * na * nc));
-  for (int p = tid; p < na * TC; p += 256) {
-    int al = p / TC, cl = p % TC;
-    if (cl >= nc) continue;
-    int a = a0 + al, c = c0 + cl;
-    T th[25];
-    for (int s = 0; s < d; ++s)
-      for (int t = 0; t < d; ++t) th[s * d + t] = Cs[(al * d + s) * (TBN + 1) + t * TC + cl];
-    double la = it.lam_l[a];
-    for (int u = 0; u < d; ++u)
-      for (int v = 0; v < d; ++v) {
-        R ar = 0, ai = 0;
-        const T* g = Gs + (u * d + v) * dd;
-        for (int q = 0; q < dd; ++q) {
-          ar += g[q].x * th[q].x - g[q].y * th[q].y;
-          ai += g[q].x * th[q].y + g[q].y * th[q].x;
-        }
-        T acc2;
-        acc2.x = ar;
-        acc2.y = ai;
-        size_t off = (size_t)(a * d + u) * n + v * chr + c;
-        Tt[off] = acc2;
-        X[off] = make_double2(la * (double)acc2.x, la * (double)acc2.y);
-      }
+  switch (d) {  // the slices of a pair in registers: the local dimension fixed at compile time
+    case 1: theta_epilogue<T, 1>(it, Cs, Gs, a0, c0, na, nc, TC, chr, n, Tt, X); break;
+    case 2: theta_epilogue<T, 2>(it, Cs, Gs, a0, c0, na, nc, TC, chr, n, Tt, X); break;
+    case 3: theta_epilogue<T, 3>(it, Cs, Gs, a0, c0, na, nc, TC, chr, n, Tt, X); break;
+    case 4: theta_epilogue<T, 4>(it, Cs, Gs, a0, c0, na, nc, TC, chr, n, Tt, X); break;
+    default: theta_epilogue<T, 5>(it, Cs, Gs, a0, c0, na, nc, TC, chr, n, Tt, X); break;
   }
 }
 
