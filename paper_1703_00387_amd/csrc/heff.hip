@@ -15,8 +15,9 @@
 // reductions / streaming kernels; the exponential of the small tridiagonal
 // matrix uses the LDS Jacobi eigensolver in one workgroup.
 #include <algorithm>
+#include <type_traits>
 
-#include "mfma_tile.h"
+#include "mfma_3m.h"
 #include "jacobi_small.h"
 #include "krylov_small.h"
 
@@ -37,15 +38,18 @@ template <class T, int MI, int NJ>
 __device__ __forceinline__ void sgemm_tile(const SGemm& P, int tm, int tn, T* stage) {
   constexpr int BM = 32 * MI, BN = 32 * NJ, LDA = BM + 4, LDB = BN + 4;
   constexpr int PA = BM >= 64 ? BM / 64 : 1, PB = BN >= 64 ? BN / 64 : 1;
-  constexpr int kPf = MI * NJ > 4 ? 2 : 3;   // chunks in flight in registers
+  // chunks in flight in registers (two for complex128, beside its three accumulators)
+  constexpr int kPf = (MI * NJ > 4 || sizeof(T) == 16) ? 2 : 3;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * MI * 16, wn = (wave & 1) * NJ * 16;
   const T* A = (const T*)P.A;
   const T* B = (const T*)P.B;
   T* C = (T*)P.C;
-  AccTileT<T, MI, NJ> acc;
-  acc_zero_t<T, MI, NJ>(acc);
+  // complex128: three real products per complex one (mfma_3m.h); complex64
+  // keeps four (measured faster there: fewer registers, more waves)
+  typename std::conditional<sizeof(T) == 16, Acc3<T, MI, NJ>, AccTileT<T, MI, NJ>>::type acc;
+  acc_clear(acc);
   const int ia = tid >> 2, kqa = (tid & 3) * 4;
   const int kb = tid >> 4, jqb = (tid & 15) * 4;
   T va[kPf][PA][4], vb[kPf][PB][4];
@@ -112,7 +116,7 @@ __device__ __forceinline__ void sgemm_tile(const SGemm& P, int tm, int tn, T* st
       if (ci < nch) {
         if (ci + kPf < nch) load(ci + kPf, va[u], vb[u]);  // chunk ci's registers were staged already
         const T* As = stage + (ci & 1) * TBK * (LDA + LDB);
-        mma_chunk_t<T, MI, NJ>(As, LDA, As + TBK * LDA, LDB, acc, wm, wn, lane);
+        acc_chunk(As, LDA, As + TBK * LDA, LDB, acc, wm, wn, lane);
         if (ci + 1 < nch) store((ci + 1) & 1, va[(u + 1) % kPf], vb[(u + 1) % kPf]);
         __syncthreads();
       }
@@ -129,9 +133,9 @@ __device__ __forceinline__ void sgemm_tile(const SGemm& P, int tm, int tn, T* st
         int row = m0 + wm + i * 16 + Cx<T>::acc_row(lane, r);
         int col = n0 + wn + j * 16 + (lane & 15);
         if (row < P.M && col < P.N) {
-          T v;
-          v.x = alpha * acc.re[i][j][r];
-          v.y = alpha * acc.im[i][j][r];
+          T v = acc_value(acc, i, j, r);
+          v.x *= alpha;
+          v.y *= alpha;
           C[(long long)row * P.rsC + (long long)col * P.csC] = v;
         }
       }

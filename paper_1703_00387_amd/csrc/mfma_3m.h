@@ -69,3 +69,31 @@ __device__ __forceinline__ T acc3_get(const Acc3<T, MI, NJ>& acc, int i, int j, 
   v.y = acc.t3[i][j][r] - acc.t1[i][j][r] - acc.t2[i][j][r];
   return v;
 }
+
+// One interface over both accumulator forms, for kernels that pick the form
+// per precision: Acc3 (three products) or AccTileT (four).
+template <class T, int MI, int NJ>
+__device__ __forceinline__ void acc_clear(Acc3<T, MI, NJ>& a) { acc3_zero<T, MI, NJ>(a); }
+template <class T, int MI, int NJ>
+__device__ __forceinline__ void acc_clear(AccTileT<T, MI, NJ>& a) { acc_zero_t<T, MI, NJ>(a); }
+template <class T, int MI, int NJ>
+__device__ __forceinline__ void acc_chunk(const T* As, int lda, const T* Bs, int ldb, Acc3<T, MI, NJ>& a, int wm,
+                                          int wn, int lane) {
+  mma3_chunk<T, MI, NJ>(As, lda, Bs, ldb, a, wm, wn, lane);
+}
+template <class T, int MI, int NJ>
+__device__ __forceinline__ void acc_chunk(const T* As, int lda, const T* Bs, int ldb, AccTileT<T, MI, NJ>& a, int wm,
+                                          int wn, int lane) {
+  mma_chunk_t<T, MI, NJ>(As, lda, Bs, ldb, a, wm, wn, lane);
+}
+template <class T, int MI, int NJ>
+__device__ __forceinline__ T acc_value(const Acc3<T, MI, NJ>& a, int i, int j, int r) {
+  return acc3_get<T, MI, NJ>(a, i, j, r);
+}
+template <class T, int MI, int NJ>
+__device__ __forceinline__ T acc_value(const AccTileT<T, MI, NJ>& a, int i, int j, int r) {
+  T v;
+  v.x = a.re[i][j][r];
+  v.y = a.im[i][j][r];
+  return v;
+}
