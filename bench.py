@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--load-state", default=None, help="start from a saved chain instead of the product state")
     ap.add_argument("--workload", default="xxz_tebd4_L64", choices=["xxz_tebd4_L64", "xxz_batch256", "bh_heff_chi512", "xxz_grad_L32",
                              "xxz_sweep_L64", "tfim_quench_L64", "bh_tdvp_L32", "bh_u1_svd_chi320",
-                             "xxz_tebd4_L64_u1"])
+                             "xxz_tebd4_L64_u1", "bh_tdvp_step_chi512"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -117,6 +117,8 @@ def main():
         return bench_u1(args)
     if args.workload == "xxz_tebd4_L64_u1":
         return bench_u1_tebd(args)
+    if args.workload == "bh_tdvp_step_chi512":
+        return bench_tdvp_step(args)
     wl = W.xxz_tebd4_L64()
     spec = wl.chains[0]
     updates_per_step = sum(len(range(p, spec.L - 1, 2)) for p in (0, 1, 0)) * 5
@@ -624,6 +626,60 @@ def bench_tdvp(args):
                                 "s_split": round(t_svd[32], 3)},
         "one_site_heff_chi512": {"ms": round(t_one * 1e3, 3), "flops": f_one,
                                  "tflops": round(f_one / t_one / 1e12, 3), "frac": round(f_one / t_one / 1e12 / peak, 4)},
+        "device_status": [code, word],
+    }
+    print(json.dumps(out))
+    h.close()
+
+
+def bench_tdvp_step(args):
+    """One whole symmetric 2TDVP step (both half-sweeps: 62 two-site
+    exponentials, SVDs of up to 2560 x 2560 truncated to chi = 512, 60
+    backward one-site exponentials, the environment updates) on the
+    Bose-Hubbard chain of bh_tdvp_L32 (L = 32, d = 5, w = 4, dt = 0.02,
+    20 Lanczos vectors, tol 1e-10), from a seeded random mixed-canonical state
+    with every bulk bond at chi = 512 (chi_b = min(5^b, 5^(32-b), 512)):
+    the step at the full shape, which a short evolution from the product
+    state does not reach."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1703_00387_amd import api, models
+
+    wl = W.bh_tdvp2_L32()
+    spec = wl.chains[0]
+    tdt = torch.complex128 if args.dtype == "c128" else torch.complex64
+    chis, Ts = W.random_oc_tensors(spec.L, spec.d, spec.chi_max, (32, 8))
+    h = api.Handle(0)
+    h.set_option(5, args.jac_threads)
+    ch = api.OCChain.product(W.initial_vectors(spec), spec.chi_max, models.mpo(spec), dtype=args.dtype)
+    for i, T in enumerate(Ts):
+        ch.M[i, :T.size] = torch.from_numpy(T.reshape(-1)).to(tdt).to(ch.M.device)
+    ch.chi.copy_(torch.tensor(chis, dtype=torch.int32, device=ch.chi.device))
+    torch.cuda.synchronize()
+    print(f"[bench] random chain at chi {max(chis)}: one 2TDVP step", file=sys.stderr, flush=True)
+    h.set_option(3, 1.0)
+    h.kernel_stats("jac_round", reset=True)
+    t1 = time.perf_counter()
+    kmax = api.tdvp2_step(h, ch, wl.dt, 1, wl.eps_local, wl.n_krylov, wl.krylov_tol)
+    torch.cuda.synchronize()
+    t_step = time.perf_counter() - t1
+    jr = h.kernel_stats("jac_round")
+    h.set_option(3, 0.0)
+    code, word = h.device_status()
+    upd = 2 * (spec.L - 1)
+    out = {
+        "metric": "two-site TDVP updates/s at the full shape (Bose-Hubbard L=32, d=5, chi=512)",
+        "value": round(upd / t_step, 3), "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(t_step * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic (seeded random mixed-canonical chain at chi=512)",
+        "config": {"workload": "bh_tdvp_step_chi512: one symmetric 2TDVP step, BH L=32 d=5 w=4 dt=0.02 "
+                               "n_max=20 tol=1e-10, every bulk bond at chi=512",
+                   "two_site_updates": upd, "chi_after": int(ch.chi.max()),
+                   "krylov_vectors_max": kmax},
+        "jacobi_s": round(jr[0] * 1e-3, 3),
+        "discarded_weight": float(ch.disc.sum().item()),
         "device_status": [code, word],
     }
     print(json.dumps(out))

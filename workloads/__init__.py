@@ -182,6 +182,22 @@ def random_complex(shape, key, scale=1.0) -> np.ndarray:
     return scale * (r.normal(size=shape) + 1j * r.normal(size=shape))
 
 
+def random_oc_tensors(L, d, chi, key):
+    """Seeded random chain in mixed-canonical form at the full bond dimension
+    chi_b = min(d^b, d^(L-b), chi): site 0 holds the (normalised) centre,
+    sites 1..L-1 are right-canonical (orthonormal rows of [chi_i][d chi_{i+1}],
+    from the QR factor of a Gaussian matrix).  For timing whole steps at a bond
+    dimension a short evolution does not reach.  Returns (chis, site tensors
+    [chi_i][d][chi_{i+1}])."""
+    chis = [min(d ** b, d ** (L - b), chi) for b in range(L + 1)]
+    out = []
+    for i in range(L):
+        a, c = chis[i], chis[i + 1]
+        q, _ = np.linalg.qr(random_complex((d * c, a), tuple(key) + (i,)))
+        out.append(np.ascontiguousarray(q.conj().T).reshape(a, d, c))
+    return chis, out
+
+
 def random_real(shape, key, lo=0.0, hi=1.0) -> np.ndarray:
     r = _rng(*key)
     return r.uniform(lo, hi, size=shape)
