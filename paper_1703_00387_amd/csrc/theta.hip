@@ -97,8 +97,15 @@ __device__ __forceinline__ void theta_tile(const BondItem& it, int d, int TA, in
   // A tile: rows i (a = a0 + i/d, s = i%d), k = k0..k0+15, staged as As[k][i];
   // B tile: k, columns j (t = j/TC, c = c0 + j%TC), staged as Bs[k][j].
   // kPf chunks are in flight in registers ahead of the one being multiplied.
-  // (complex128: one, which leaves the registers of the three accumulators)
-  constexpr int kPf = sizeof(T) == 16 ? 1 : 3;
+  // One, in both precisions: it leaves the registers to the three
+  // accumulators, and it is the depth at which the complex64 build keeps them
+  // in AGPRs throughout.  With three in flight that build moves part of them
+  // through VGPR copies at the joins of the unrolled slots, and on the path
+  // that skips the last staging store a copy reads an accumulator three
+  // instructions after the MFMA writing it, well inside the instruction's
+  // result latency (the compiler pads such reads to ten elsewhere); its
+  // imaginary parts then came out wrong.  One in flight also measured faster.
+  constexpr int kPf = 1;
   const int ia = tid >> 2, kqa = (tid & 3) * 4;
   const int kb = tid >> 4, jqb = (tid & 15) * 4;
   T va[kPf][4], vb[kPf][4];
