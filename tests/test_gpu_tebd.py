@@ -328,3 +328,49 @@ def test_plain_form_equals_batched(H):
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x.chi, y.chi) and torch.equal(x.B, y.B) and torch.equal(x.lam, y.lam)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_long_contractions_random_chain(H, dtype):
+    """One TEBD2 step of a seeded random Hastings-form chain whose inner bond
+    dimensions (64, 200) make the theta contraction run over many K-chunks
+    with a ragged last one (200 = 12 * 16 + 8), the regime that the
+    product-state runs above do not reach: bond dimensions identical and
+    Schmidt values within 1e-11 (c128) or 2e-6 (c64) of the oracle's."""
+    from oracle import mps as omps, models as om
+    from paper_1703_00387_amd import api, models
+    L, d, cm = 6, 2, 256
+    prof = [1, 2, 64, 200, 64, 2, 1]
+    spec = W.xxz_chain(L, cm, 1.0, 0.5)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    Bd = np.zeros((L, cm, d, cm), np.complex128)
+    lam = np.zeros((L + 1, cm))
+    Bs, lams = [], []
+    for i in range(L):
+        t = W.random_complex((prof[i], d, prof[i + 1]), (83, i), scale=1.0 / np.sqrt(2 * d * prof[i + 1]))
+        t = torch.from_numpy(t).to(tdt).to(torch.complex128).numpy()   # the oracle starts from the rounded tensors
+        Bd[i, :prof[i], :, :prof[i + 1]] = t
+        Bs.append(t)
+    for j in range(L + 1):
+        v = np.sort(np.abs(W.random_complex((prof[j],), (84, j))))[::-1] ** 3 + 1e-3
+        v /= np.linalg.norm(v)
+        lam[j, :prof[j]] = v
+        lams.append(v.copy())
+    ch = api.Chain(L, d, cm, torch.from_numpy(Bd).to(tdt).cuda(), torch.from_numpy(lam).cuda(),
+                   torch.tensor(prof, dtype=torch.int32).cuda(),
+                   torch.from_numpy(np.ascontiguousarray(models.bond_hamiltonians(spec))).cuda(),
+                   torch.zeros(L - 1, dtype=torch.float64).cuda())
+    api.tebd_step(H, [ch], 2, 0.05, 1, 1e-14)
+    torch.cuda.synchronize()
+    code, word = H.device_status()
+    assert code == 0, word
+    psi = omps.MPS(Bs, lams, d)
+    hs = om.bond_hamiltonians(spec)
+    for bonds, tau in omps.strang_layers(L, 0.05):
+        for b in bonds:
+            omps.apply_bond(psi, b, omps.gate(hs[b], tau), cm, 1e-14)
+    _, lam1, chi1 = ch.to_host()
+    assert list(chi1) == psi.chis()
+    dl = max(np.abs(lam1[j] - psi.lam[j]).max() for j in range(L + 1))
+    print(f"long contractions {dtype}: chis {list(chi1)} max|dlam| {dl:.2e}")
+    assert dl <= (1e-11 if dtype == "c128" else 2e-6), dl
