@@ -134,13 +134,23 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * for the previous round of its own matrix, with convergence decided on the
  * device; 0 = one launch per round and a convergence read-back per sweep.
  * A wait of the persistent launch is bounded (seconds); one that runs out
- * sets MPS_DEV_SCHED_TIMEOUT and the launch ends. */
+ * sets MPS_DEV_SCHED_TIMEOUT and the launch ends,
+ * 9 = warm start of the TEBD splits (default 1; mps_tebd_step and the other
+ * stepping calls of dense chains, SVD split): for a bond of
+ * 64 < d chi_l <= 512 rows the Jacobi runs on Q^dag theta' instead of theta',
+ * with Q the Householder QR factor of Lambda_l B_b (the bond's left Schmidt
+ * vectors before the gate, Sec. "Time evolving block decimation"), whose
+ * rows are then close to orthogonal; the singular values and V^dag are those
+ * of theta' either way (Q is unitary), only the number of sweeps changes.
+ * Its workspace is n_bonds * (d chi_max chi_max + 256 ceil(chi_max/16))
+ * complex128 per layer; 0 = the Jacobi starts from theta' itself. */
 mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
  * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,
  * 3 = right write-back, 4 = left write-back GEMM, 5 = Jacobi preparation,
  * 6 = propagators, 7 = Krylov-TEBD propagators (identity theta build,
- * reduced matrix, local Lanczos).  total_ms = summed event durations, launches = count,
+ * reduced matrix, local Lanczos), 8 = warm start of the Jacobi (option 9:
+ * QR of Lambda_l B_b and Q^dag theta').  total_ms = summed event durations, launches = count,
  * work = flops counted on the device: for kernels 0 and 4 the products'
  * useful flops, for kernel 1 the Jacobi's own Gram and rotation flops, for
  * kernel 5 the algorithmic work of the batched TEBD splits prepared

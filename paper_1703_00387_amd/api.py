@@ -88,7 +88,7 @@ class Handle:
         self.check(lib().mps_reserve(self.h, C.c_size_t(nbytes)))
 
     KERNELS = {"theta": 0, "jac_round": 1, "select": 2, "wb_right": 3, "gemm": 4, "prep": 5, "gates": 6,
-               "krylov": 7}
+               "krylov": 7, "warm": 8}
 
     def kernel_stats(self, kernel: str, reset=False):
         """(total_ms, launches, useful_flops) of a kernel class (timing on via set_option(3, 1))."""

@@ -544,6 +544,10 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
       if (value != 0.0 && value != 1.0) return mps_fail(h, MPS_ERR_INVALID, "persistent Jacobi must be 0 or 1");
       h->jac_persistent = (int)value;
       return MPS_OK;
+    case 9:
+      if (value != 0.0 && value != 1.0) return mps_fail(h, MPS_ERR_INVALID, "warm start must be 0 or 1");
+      h->warm_start = (int)value;
+      return MPS_OK;
     default:
       return mps_fail(h, MPS_ERR_INVALID, "unknown option");
   }
@@ -576,7 +580,7 @@ mps_status mps_kernel_stats(mps_handle h, mps_stream stream, int32_t kernel, dou
   MPS_TRY_HIP(h, hipStreamSynchronize(s));
   unsigned long long w[MPS_NSTATS];
   MPS_TRY_HIP(h, hipMemcpy(w, h->stats_dev, sizeof(w), hipMemcpyDeviceToHost));
-  static const int work_slot[MPS_NKERNELS] = {0, 1, -1, -1, 3, 5, -1, -1};
+  static const int work_slot[MPS_NKERNELS] = {0, 1, -1, -1, 3, 5, -1, -1, -1};
   if (total_ms) *total_ms = h->k_ms[kernel];
   if (launches) *launches = h->k_launches[kernel];
   if (work) *work = work_slot[kernel] >= 0 ? w[work_slot[kernel]] : 0;
@@ -908,6 +912,13 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   size_t oRow = p.take<int32_t>(max_items * m_cap);
   size_t oNrm = p.take<double>(max_items * m_cap);
   size_t oTiles = p.take<int32_t>(max_items + 1);   // tile lists of the fixed-grid launches
+  // warm start of the Jacobi: per item A = Lambda_l B_b and its panels' T
+  const bool warm = h->warm_start && !u1 && !eig_slots && d * chi_cap > 64;
+  size_t oWarmA = 0, oWarmT = 0;
+  if (warm) {
+    oWarmA = p.take<double2>(max_items * warm_a_elems(d, chi_cap));
+    oWarmT = p.take<double2>(max_items * warm_t_elems(chi_cap));
+  }
   // Krylov propagation: identity propagator, one propagator per chain, a job
   // per item, rho partials and Krylov histories per item of a layer
   const int kt_nblk = 32;
@@ -1126,6 +1137,12 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
                                 eps_local, c128, ws + oU1, sel, unconv);
         if (r != MPS_OK) return r;
       } else {
+      if (warm) {
+        if (prof) prof_begin(h, s, MPS_K_WARM);
+        MPS_TRY_HIP(h, launch_warm_start(s, it, n, d, chi_cap, chi_eff, c128, (double2*)(ws + oWarmA),
+                                         (double2*)(ws + oWarmT)));
+        if (prof) prof_end(h, s, MPS_K_WARM);
+      }
       if (prof) prof_begin(h, s, MPS_K_PREP);
       MPS_TRY_HIP(h, launch_jac_prep_bonds(s, it, mats, n, kJacBlock, (int32_t*)(ws + oRow), (double*)(ws + oNrm), m_cap,
                                            h->status_dev, stats));
@@ -1222,6 +1239,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   put((uint64_t)h->jac_split_below);
   put((uint64_t)h->split_method);
   put((uint64_t)h->jac_persistent);
+  put((uint64_t)h->warm_start);
   put(u1 ? 1 : 0);
   for (int c = 0; c < n_chains; ++c) {
     const mps_chain_desc& ch = chains[c];

@@ -9,7 +9,7 @@
 
 #include "../../include/mps.h"
 
-#define MPS_NKERNELS 8
+#define MPS_NKERNELS 9
 #define MPS_NSTATS 8
 // kernel classes timed by the optional profiler (ids of mps_kernel_stats)
 #define MPS_K_THETA 0
@@ -20,6 +20,7 @@
 #define MPS_K_PREP 5
 #define MPS_K_GATES 6
 #define MPS_K_KRYLOV 7
+#define MPS_K_WARM 8
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -47,6 +48,7 @@ struct mps_context {
   size_t split_bytes = 0;
   char* scratch = nullptr;        // this device's address of the no-allocation entry's scratch array
   int jac_persistent = 1;         // batches without a column split: all sweeps in one persistent launch
+  int warm_start = 1;             // TEBD splits: Jacobi on Q^dag theta', Q from the QR of Lambda_l B_b
   int n_cu = 256;                 // compute units of the device (persistent grid size)
   char* sched = nullptr;          // counters of the persistent Jacobi (kSchedBytes)
   // pinned host scratch for small readbacks
@@ -312,6 +314,14 @@ inline long long xcd_grid(long long n_items, long long tiles_cap) {
 }
 // tile_offs (optional, n_items + 1 int32 of device scratch): walk the list of
 // the bonds' real tiles with a fixed grid instead of a grid sized for chi_cap
+// Warm start of a layer's Jacobi (warm.hip): theta' <- Q^dag theta' with Q
+// from the Householder QR of Lambda_l B_b, for the bonds of 64 < d chi_l <=
+// 512 rows.  wsA: n_items * warm_a_elems(d, chi_cap) complex128, wsT:
+// n_items * warm_t_elems(chi_cap).
+size_t warm_a_elems(int d, int chi_cap);
+size_t warm_t_elems(int chi_cap);
+hipError_t launch_warm_start(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, int chi_eff,
+                             bool c128, double2* wsA, double2* wsT);
 hipError_t launch_theta(hipStream_t s, const BondItem* items, int n_items, int d, int chi_cap, bool c128,
                         unsigned long long* stats, const void* G_override = nullptr, int32_t* tile_offs = nullptr);
 hipError_t launch_ktebd_identity(hipStream_t s, void* G, int dd, bool c128);

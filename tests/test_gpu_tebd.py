@@ -330,41 +330,49 @@ def test_plain_form_equals_batched(H):
         assert torch.equal(x.chi, y.chi) and torch.equal(x.B, y.B) and torch.equal(x.lam, y.lam)
 
 
+@pytest.mark.parametrize("warm", [1, 0])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_long_contractions_random_chain(H, dtype):
-    """One TEBD2 step of a seeded random Hastings-form chain whose inner bond
-    dimensions (64, 200) make the theta contraction run over many K-chunks
-    with a ragged last one (200 = 12 * 16 + 8), the regime that the
-    product-state runs above do not reach: bond dimensions identical and
-    Schmidt values within 1e-11 (c128) or 2e-6 (c64) of the oracle's."""
+def test_long_contractions_canonical_chain(H, dtype, warm):
+    """One TEBD2 step of a seeded random Bose-Hubbard state (L = 6, d = 5) put
+    into Hastings form by the oracle: bond dimensions 1, 5, 25, 125, 25, 5, 1,
+    so the middle update contracts over 125 = 7 * 16 + 13 (many K-chunks and a
+    ragged last one, which the product-state runs above do not reach) and its
+    125 x 125 theta' gets the Jacobi's warm start (Q from the QR of
+    Lambda_l B_b, a partial last panel), here on and off.  Bond dimensions
+    identical, Schmidt values within 1e-11 (c128) or 2e-6 (c64) of the
+    oracle's."""
     from oracle import mps as omps, models as om
     from paper_1703_00387_amd import api, models
-    L, d, cm = 6, 2, 256
-    prof = [1, 2, 64, 200, 64, 2, 1]
-    spec = W.xxz_chain(L, cm, 1.0, 0.5)
+    L, nmax, cm = 6, 4, 128
+    spec = W.bh_chain(L, nmax, cm)
+    d = spec.d
+    vec = W.random_complex((d ** L,), (85, 1))
+    psi0 = omps.from_vector(vec / np.linalg.norm(vec), L, d)
+    prof = psi0.chis()
+    assert prof == [1, 5, 25, 125, 25, 5, 1], prof
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
     Bd = np.zeros((L, cm, d, cm), np.complex128)
     lam = np.zeros((L + 1, cm))
-    Bs, lams = [], []
+    Bs = []
     for i in range(L):
-        t = W.random_complex((prof[i], d, prof[i + 1]), (83, i), scale=1.0 / np.sqrt(2 * d * prof[i + 1]))
-        t = torch.from_numpy(t).to(tdt).to(torch.complex128).numpy()   # the oracle starts from the rounded tensors
+        t = torch.from_numpy(psi0.B[i]).to(tdt).to(torch.complex128).numpy()  # the oracle starts from the rounded tensors
         Bd[i, :prof[i], :, :prof[i + 1]] = t
         Bs.append(t)
     for j in range(L + 1):
-        v = np.sort(np.abs(W.random_complex((prof[j],), (84, j))))[::-1] ** 3 + 1e-3
-        v /= np.linalg.norm(v)
-        lam[j, :prof[j]] = v
-        lams.append(v.copy())
+        lam[j, :prof[j]] = psi0.lam[j]
     ch = api.Chain(L, d, cm, torch.from_numpy(Bd).to(tdt).cuda(), torch.from_numpy(lam).cuda(),
                    torch.tensor(prof, dtype=torch.int32).cuda(),
                    torch.from_numpy(np.ascontiguousarray(models.bond_hamiltonians(spec))).cuda(),
                    torch.zeros(L - 1, dtype=torch.float64).cuda())
-    api.tebd_step(H, [ch], 2, 0.05, 1, 1e-14)
-    torch.cuda.synchronize()
+    H.set_option(9, warm)
+    try:
+        api.tebd_step(H, [ch], 2, 0.05, 1, 1e-14)
+        torch.cuda.synchronize()
+    finally:
+        H.set_option(9, 1)
     code, word = H.device_status()
     assert code == 0, word
-    psi = omps.MPS(Bs, lams, d)
+    psi = omps.MPS(Bs, [l.copy() for l in psi0.lam], d)
     hs = om.bond_hamiltonians(spec)
     for bonds, tau in omps.strang_layers(L, 0.05):
         for b in bonds:
@@ -372,5 +380,5 @@ def test_long_contractions_random_chain(H, dtype):
     _, lam1, chi1 = ch.to_host()
     assert list(chi1) == psi.chis()
     dl = max(np.abs(lam1[j] - psi.lam[j]).max() for j in range(L + 1))
-    print(f"long contractions {dtype}: chis {list(chi1)} max|dlam| {dl:.2e}")
+    print(f"long contractions {dtype} warm {warm}: chis {list(chi1)} max|dlam| {dl:.2e}")
     assert dl <= (1e-11 if dtype == "c128" else 2e-6), dl
