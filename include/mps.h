@@ -135,7 +135,7 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * device; 0 = one launch per round and a convergence read-back per sweep.
  * A wait of the persistent launch is bounded (seconds); one that runs out
  * sets MPS_DEV_SCHED_TIMEOUT and the launch ends,
- * 9 = warm start of the TEBD splits (default 1; mps_tebd_step and the other
+ * 9 = warm start of the TEBD splits (default 0; mps_tebd_step and the other
  * stepping calls of dense chains, SVD split): for a bond of
  * 64 < d chi_l <= 512 rows the Jacobi runs on Q^dag theta' instead of theta',
  * with Q the Householder QR factor of Lambda_l B_b (the bond's left Schmidt
@@ -143,7 +143,10 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * rows are then close to orthogonal; the singular values and V^dag are those
  * of theta' either way (Q is unitary), only the number of sweeps changes.
  * Its workspace is n_bonds * (d chi_max chi_max + 256 ceil(chi_max/16))
- * complex128 per layer; 0 = the Jacobi starts from theta' itself. */
+ * complex128 per layer; 0 = the Jacobi starts from theta' itself.  The
+ * Jacobi then does about a quarter less work, but a layer's time follows its
+ * slowest matrix, whose sweeps the start changes little once the bonds sit
+ * at chi_max. */
 mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
  * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,

@@ -369,7 +369,7 @@ def test_long_contractions_canonical_chain(H, dtype, warm):
         api.tebd_step(H, [ch], 2, 0.05, 1, 1e-14)
         torch.cuda.synchronize()
     finally:
-        H.set_option(9, 1)
+        H.set_option(9, 0)
     code, word = H.device_status()
     assert code == 0, word
     psi = omps.MPS(Bs, [l.copy() for l in psi0.lam], d)
