@@ -833,6 +833,7 @@ def bench_sweep(args):
     h = api.Handle(0)
     h.set_option(5, args.jac_threads)
     h.set_option(7, 1.0 if args.split == "eig" else 0.0)
+    h.set_option(9, 1.0 if args.warm else 0.0)
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
     if args.load_state:
         st = torch.load(args.load_state, weights_only=True)
@@ -878,7 +879,8 @@ def bench_sweep(args):
         "warmup": args.warmup, "ms_per_step": round(t_sweep * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "xxz_sweep_L64: one sweep step (126 updates, one bond at a time) from the "
-                               "TEBD4 XXZ L=64 chi_max=256 state", "updates_per_step": upd_sweep},
+                               "TEBD4 XXZ L=64 chi_max=256 state", "updates_per_step": upd_sweep,
+                   "warm_start": bool(args.warm)},
         "even_odd_tebd2": {"updates_per_s": round(upd_eo / t_eo, 2), "ms_per_step": round(t_eo * 1e3, 3),
                            "updates_per_step": upd_eo},
         "krylov_sweep": {"updates_per_s": round(upd_sweep / t_kry, 2), "ms_per_step": round(t_kry * 1e3, 3),
