@@ -72,6 +72,9 @@ def main():
                     help="two-site split of matrices of at most 64 rows: one-sided Jacobi SVD or the "
                          "eigendecomposition of the Gram")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-sweeps", type=int, default=0,
+                    help="cap on the Jacobi sweeps of a split (option 1; 0 = the library default); a capped "
+                         "split that has not converged sets MPS_DEV_NOCONV, reported in device_status")
     ap.add_argument("--warm", action="store_true",
                     help="Jacobi of the TEBD splits from Q^dag theta', Q from the QR of Lambda_l B_b (option 9 = 1)")
     ap.add_argument("--rounds", action="store_true",
@@ -129,6 +132,8 @@ def main():
     h.set_option(7, 1.0 if args.split == "eig" else 0.0)
     h.set_option(8, 0.0 if args.rounds else 1.0)
     h.set_option(9, 1.0 if args.warm else 0.0)
+    if args.max_sweeps:
+        h.set_option(1, args.max_sweeps)
     tuned = api.autotune(h, 32, 512, 512, apply=True, cache=args.autotune) if args.autotune else None
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
 

@@ -38,17 +38,17 @@ template <class T, int MI, int NJ>
 __device__ __forceinline__ void sgemm_tile(const SGemm& P, int tm, int tn, T* stage) {
   constexpr int BM = 32 * MI, BN = 32 * NJ, LDA = BM + 4, LDB = BN + 4;
   constexpr int PA = BM >= 64 ? BM / 64 : 1, PB = BN >= 64 ? BN / 64 : 1;
-  // chunks in flight in registers (two for complex128, beside its three accumulators)
-  constexpr int kPf = (MI * NJ > 4 || sizeof(T) == 16) ? 2 : 3;
+  // chunks in flight in registers: two for complex128, one for complex64
+  // (measured fastest with the three accumulators of either precision)
+  constexpr int kPf = sizeof(T) == 16 ? 2 : 1;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * MI * 16, wn = (wave & 1) * NJ * 16;
   const T* A = (const T*)P.A;
   const T* B = (const T*)P.B;
   T* C = (T*)P.C;
-  // complex128: three real products per complex one (mfma_3m.h); complex64
-  // keeps four (measured faster there: fewer registers, more waves)
-  typename std::conditional<sizeof(T) == 16, Acc3<T, MI, NJ>, AccTileT<T, MI, NJ>>::type acc;
+  // three real products per complex one (mfma_3m.h)
+  Acc3<T, MI, NJ> acc;
   acc_clear(acc);
   const int ia = tid >> 2, kqa = (tid & 3) * 4;
   const int kb = tid >> 4, jqb = (tid & 15) * 4;
