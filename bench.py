@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=0,
                     help="cap on the Jacobi sweeps of a split (option 1; 0 = the library default); a capped "
                          "split that has not converged sets MPS_DEV_NOCONV, reported in device_status")
+    ap.add_argument("--jac-abs", type=float, default=None,
+                    help="absolute floor of the Jacobi's orthogonality test, relative to |theta|_F^2 (option 2; "
+                         "default 1e-15)")
     ap.add_argument("--warm", action="store_true",
                     help="Jacobi of the TEBD splits from Q^dag theta', Q from the QR of Lambda_l B_b (option 9 = 1)")
     ap.add_argument("--rounds", action="store_true",
@@ -134,6 +137,8 @@ def main():
     h.set_option(9, 1.0 if args.warm else 0.0)
     if args.max_sweeps:
         h.set_option(1, args.max_sweeps)
+    if args.jac_abs is not None:
+        h.set_option(2, args.jac_abs)
     tuned = api.autotune(h, 32, 512, 512, apply=True, cache=args.autotune) if args.autotune else None
     ch = api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec), dtype=args.dtype)
 
@@ -233,6 +238,7 @@ def main():
                    "jacobi_threads": args.jac_threads, "autotune": tuned,
                    "jacobi_schedule": "round launches" if args.rounds else "persistent",
                    "warm_start": bool(args.warm),
+                   "jacobi_abs_floor": args.jac_abs if args.jac_abs is not None else 1e-15,
                    "chi_hist": {"max": int(chi.max()), "mean": round(float(chi.mean()), 1),
                                 "n_at_cap": int((chi >= spec.chi_max).sum()), "n_at_cap_start": n_at_cap0}},
         "windows": {"steps": sizes, "updates_per_s": [round(r, 2) for r in rates],
