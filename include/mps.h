@@ -374,8 +374,9 @@ mps_status mps_tebd_step(mps_handle h, mps_stream stream, const mps_chain_desc* 
  * concepts in tensor network techniques", Eq. elocal).
  *   flags       : as mps_tebd_step, plus MPS_FLAG_CHECKPOINT: before every
  *                 step and after the last, every chain (B, lam, chi) is
- *                 copied into ckpt_arena; complex128 chains only, not with
- *                 MPS_FLAG_GRAPH.  mps_tebd_step_vjp reads the arena.
+ *                 copied into ckpt_arena (complex64 B widened exactly to
+ *                 complex128), not with MPS_FLAG_GRAPH.  mps_tebd_step_vjp
+ *                 reads the arena.
  *   ckpt_arena  : device, at least mps_tebd_ckpt_bytes(chains, n_chains,
  *                 n_steps) bytes, owned by the caller (NULL without the flag)
  *   disc_log_dev: device FP64 [n_steps][n_layers][n_chains][L_max-1] or NULL,
@@ -666,7 +667,11 @@ mps_status mps_tdvp2_step_u1(mps_handle h, mps_stream stream, const mps_oc_chain
  * applies the adjoint of every two-site update.  The singular-value backward
  * keeps the coupling between kept and discarded singular triplets and uses a
  * Lorentzian broadening `eta` of 1/(s_j^2 - s_i^2) and of 1/s (eta >= 0; 1e-12
- * is the usual choice).  Only complex128 chains.
+ * is the usual choice).  Complex64 chains: the forward and the reverse
+ * pass's re-runs of each step in the chain's precision (FP32 MFMA
+ * contractions, FP64 SVD), every snapshot widened exactly to complex128 and
+ * the adjoint itself in FP64; the gradient then carries the FP32 rounding of
+ * the forward (about 1e-5 relative against an FP64 run on the test chains).
  *   h0      : device complex128 [L-1][d^2][d^2], the unit bond terms
  *   op1     : device complex128 [d][d];  op2 : device complex128 [d^2][d^2]
  *   arena   : device memory of at least mps_tebd_grad_arena_bytes(L, d,
@@ -710,7 +715,8 @@ mps_status mps_tebd_grad(mps_handle h, mps_stream stream, const mps_chain_desc* 
  *   h0          : HOST array of n_chains device pointers, complex128
  *                 [L-1][d^2][d^2] unit bond terms
  *   ckpt_arena  : the forward's arena (its scratch parts are overwritten)
- *   dB_final    : HOST array of device pointers, complex128 in the layout of B
+ *   dB_final    : HOST array of device pointers, in the chain's dtype and
+ *                 the layout of its B (complex64 cotangents are widened)
  *   dLam_final  : HOST array of device pointers, FP64 in the layout of lam
  *   dJ_dev      : device FP64 [n_chains][L_max-1], overwritten (entries past
  *                 a chain's L-1 are 0)

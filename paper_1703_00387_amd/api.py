@@ -276,14 +276,14 @@ def tebd_step_ex(h: Handle, chains: Sequence[Chain], order: int, dt: float, n_st
 def tebd_step_vjp(h: Handle, chains: Sequence[Chain], h0: Sequence[torch.Tensor], ckpt: torch.Tensor,
                   dB: Sequence[torch.Tensor], dlam: Sequence[torch.Tensor], eta: float = 1e-12) -> torch.Tensor:
     """mps_tebd_step_vjp: dL/dJ [n_chains, L_max-1] for state cotangents dB
-    (complex128, the layout of each chain's B) and dlam (float64, of lam) of a
+    (the dtype and layout of each chain's B) and dlam (float64, of lam) of a
     TEBD2 or TEBD4 run recorded by tebd_step_ex with MPS_FLAG_CHECKPOINT."""
     n = len(chains)
     if not (len(h0) == len(dB) == len(dlam) == n):
         raise ValueError("one h0, dB and dlam per chain")
     for c, hh, b, l in zip(chains, h0, dB, dlam):
-        if b.shape != c.B.shape or b.dtype != torch.complex128 or not b.is_contiguous():
-            raise ValueError("dB must be complex128 in the layout of the chain's B")
+        if b.shape != c.B.shape or b.dtype != c.B.dtype or not b.is_contiguous() or b.device != c.B.device:
+            raise ValueError("dB must have the dtype, layout and device of the chain's B")
         if l.shape != c.lam.shape or l.dtype != torch.float64 or not l.is_contiguous():
             raise ValueError("dlam must be float64 in the layout of the chain's lam")
         if hh.dtype != torch.complex128 or not hh.is_contiguous():
@@ -554,28 +554,29 @@ class TebdObservables(torch.autograd.Function):
     obs[:L] = <op1 at site i>, obs[L:] = <op2 on bond b> (float64, on the GPU).
     The forward runs mps_tebd_step (order 2) and mps_observe; the backward runs
     mps_tebd_vjp with the incoming gradient as the cotangent (it re-runs the
-    forward with a checkpoint per step).  Complex128 chains only."""
+    forward with a checkpoint per step).  dtype "c128" or "c64" (FP32 MFMA
+    contractions in the forward and its re-runs; the reverse pass in FP64)."""
 
     @staticmethod
-    def forward(ctx, J, h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta=1e-12):
+    def forward(ctx, J, h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta=1e-12, dtype="c128"):
         hb = J.detach().to(torch.complex128)[:, None, None] * torch.as_tensor(h0, dtype=torch.complex128).to(J.device)
-        chain = Chain.product(vectors, chi_max, hb.cpu().numpy(), device=J.device, dtype="c128")
+        chain = Chain.product(vectors, chi_max, hb.cpu().numpy(), device=J.device, dtype=dtype)
         tebd_step(h, [chain], 2, dt, n_steps, eps)
         site, bond, _ = observe(h, chain, op1, op2)
-        ctx.args = (h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta)
+        ctx.args = (h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta, dtype)
         ctx.save_for_backward(J.detach())
         return torch.cat([site, bond])
 
     @staticmethod
     def backward(ctx, g):
         (J,) = ctx.saved_tensors
-        h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta = ctx.args
+        h, vectors, chi_max, h0, dt, n_steps, eps, op1, op2, eta, dtype = ctx.args
         L = J.numel() + 1
         hb = J.to(torch.complex128)[:, None, None] * torch.as_tensor(h0, dtype=torch.complex128).to(J.device)
-        chain = Chain.product(vectors, chi_max, hb.cpu().numpy(), device=J.device, dtype="c128")
+        chain = Chain.product(vectors, chi_max, hb.cpu().numpy(), device=J.device, dtype=dtype)
         w = g.detach().double().cpu().numpy()
         _, dJ = tebd_vjp(h, chain, h0, dt, n_steps, eps, op1, op2, w[:L], w[L:], eta)
-        return (dJ.to(J.dtype),) + (None,) * 10
+        return (dJ.to(J.dtype),) + (None,) * 11
 
 
 class TebdStep(torch.autograd.Function):
@@ -591,10 +592,12 @@ class TebdStep(torch.autograd.Function):
     ...) in the capacity layout of Chain; chi_c is not differentiable.  The
     forward runs mps_tebd_step_ex with MPS_FLAG_CHECKPOINT, the backward
     mps_tebd_step_vjp on that checkpoint with the incoming cotangents of the
-    B and lam (zero where None).  Complex128 chains only."""
+    B and lam (zero where None).  dtype "c128" or "c64": the chains' B (FP32
+    MFMA contractions for c64; the reverse pass in FP64 on the checkpointed
+    states widened exactly)."""
 
     @staticmethod
-    def forward(ctx, J, h, vectors, chi_max, h0, dt, n_steps, eps, eta=1e-12, order=2):
+    def forward(ctx, J, h, vectors, chi_max, h0, dt, n_steps, eps, eta=1e-12, order=2, dtype="c128"):
         n = len(vectors)
         if order not in (2, 4):
             raise ValueError("order must be 2 (TEBD2) or 4 (TEBD4)")
@@ -608,7 +611,7 @@ class TebdStep(torch.autograd.Function):
             if h0d[c].shape[0] != L - 1 or J.shape[1] < L - 1:
                 raise ValueError("h0[c] needs L_c-1 bond terms and J at least L_c-1 columns")
             hb = J.detach()[c, :L - 1].to(torch.complex128)[:, None, None] * h0d[c]
-            chains.append(Chain.product(vectors[c], chi_max, hb.cpu().numpy(), device=dev, dtype="c128"))
+            chains.append(Chain.product(vectors[c], chi_max, hb.cpu().numpy(), device=dev, dtype=dtype))
         ck = torch.zeros(tebd_ckpt_bytes(chains, n_steps), dtype=torch.uint8, device=dev)
         tebd_step_ex(h, chains, order, dt, n_steps, eps, flags=_lib.MPS_FLAG_CHECKPOINT, ckpt=ck)
         ctx.state = (h, chains, h0d, ck, eta, J.shape[1])
@@ -626,7 +629,7 @@ class TebdStep(torch.autograd.Function):
         dJ = tebd_step_vjp(h, chains, h0d, ck, dB, dl, eta)
         out = torch.zeros((len(chains), width), dtype=torch.float64, device=dJ.device)
         out[:, :dJ.shape[1]] = dJ
-        return (out,) + (None,) * 9
+        return (out,) + (None,) * 10
 
 
 def autotune_gemm(h: Handle, kind: int, dtype: str, M: int, N: int, K: int, batch: int = 1, apply: bool = True):

@@ -807,8 +807,6 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
     if (!ckpt) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_CHECKPOINT needs an arena");
     if (flags & MPS_FLAG_GRAPH) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_CHECKPOINT excludes MPS_FLAG_GRAPH");
     if (u1 || kry) return mps_fail(h, MPS_ERR_INVALID, "MPS_FLAG_CHECKPOINT is for dense gate TEBD");
-    for (int c = 0; c < n_chains; ++c)
-      if (chains[c].dtype != MPS_C128) return mps_fail(h, MPS_ERR_UNSUPPORTED, "checkpoints need complex128 chains");
     if (n_steps > 0 && ckpt_bytes < mps_tebd_ckpt_bytes(chains, n_chains, n_steps))
       return mps_fail(h, MPS_ERR_CAPACITY, "arena smaller than mps_tebd_ckpt_bytes()");
   }

@@ -18,7 +18,8 @@
 // below 1e-7 |theta'| that are not kept are treated as exact zeros and enter
 // through the projector (1 - V V^dag).  The coupling gradient of the update is
 // J_bar_b += Re <theta~'_bar, dG/dJ_b theta~> with dG/dJ_b = -i tau h0_b G_b.
-// Everything runs in complex128.
+// The reverse pass runs in complex128 (complex64 chains: on their states
+// widened exactly; the forward and its re-runs in the chain's precision).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -786,7 +787,10 @@ mps_status grad_ckpt_save(mps_handle h, hipStream_t s, const mps_chain_desc& ch,
   double* lam;
   int32_t* chi;
   A.ptrs(block + A.oCk + (size_t)st * A.snap, B, lam, chi);
-  MPS_TRY_HIP(h, hipMemcpyAsync(B, ch.B, A.snapB, hipMemcpyDeviceToDevice, s));
+  if (ch.dtype == MPS_C64)   // complex64 chains: the snapshot widened to complex128 (exact)
+    MPS_TRY_HIP(h, launch_convert(s, ch.B, B, (long long)(A.snapB / sizeof(double2)), false));
+  else
+    MPS_TRY_HIP(h, hipMemcpyAsync(B, ch.B, A.snapB, hipMemcpyDeviceToDevice, s));
   MPS_TRY_HIP(h, hipMemcpyAsync(lam, ch.lam, A.snapL, hipMemcpyDeviceToDevice, s));
   MPS_TRY_HIP(h, hipMemcpyAsync(chi, ch.chi, A.snapC, hipMemcpyDeviceToDevice, s));
   return MPS_OK;
@@ -811,7 +815,10 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
   if (!chain || !h0 || (!seeded && (!op1 || !op2 || !w1 || !w2)) || !dJ_dev || !arena_ptr)
     return mps_fail(h, MPS_ERR_INVALID, "null pointer");
   const mps_chain_desc ch = *chain;
-  if (ch.dtype != MPS_C128) return mps_fail(h, MPS_ERR_UNSUPPORTED, "the gradient needs a complex128 chain");
+  if (ch.dtype != MPS_C128 && ch.dtype != MPS_C64) return mps_fail(h, MPS_ERR_INVALID, "bad chain dtype");
+  // complex64 chains: the forward (and its re-runs) in the chain's precision,
+  // the reverse pass in complex128 on the states widened exactly
+  const bool c64 = ch.dtype == MPS_C64;
   if (ch.L < 2 || ch.d < 1 || ch.d > 5 || ch.chi_max < 1) return mps_fail(h, MPS_ERR_SHAPE, "bad chain shape");
   if ((int64_t)ch.d * ch.chi_max > 2560) return mps_fail(h, MPS_ERR_CAPACITY, "d*chi_max is limited to 2560");
   if (!seeded)
@@ -861,7 +868,10 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
     double* lam;
     int32_t* chi;
     A.ptrs(dst, B, lam, chi);
-    MPS_TRY_HIP(h, hipMemcpyAsync(B, ch.B, A.snapB, hipMemcpyDeviceToDevice, s));
+    if (c64)
+      MPS_TRY_HIP(h, launch_convert(s, ch.B, B, (long long)L * site_el, false));
+    else
+      MPS_TRY_HIP(h, hipMemcpyAsync(B, ch.B, A.snapB, hipMemcpyDeviceToDevice, s));
     MPS_TRY_HIP(h, hipMemcpyAsync(lam, ch.lam, A.snapL, hipMemcpyDeviceToDevice, s));
     MPS_TRY_HIP(h, hipMemcpyAsync(chi, ch.chi, A.snapC, hipMemcpyDeviceToDevice, s));
     return MPS_OK;
@@ -871,7 +881,10 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
     double* lam;
     int32_t* chi;
     A.ptrs(src, B, lam, chi);
-    MPS_TRY_HIP(h, hipMemcpyAsync(ch.B, B, A.snapB, hipMemcpyDeviceToDevice, s));
+    if (c64)   // back to complex64: exact, the snapshot was widened from it
+      MPS_TRY_HIP(h, launch_convert(s, B, ch.B, (long long)L * site_el, true));
+    else
+      MPS_TRY_HIP(h, hipMemcpyAsync(ch.B, B, A.snapB, hipMemcpyDeviceToDevice, s));
     MPS_TRY_HIP(h, hipMemcpyAsync(ch.lam, lam, A.snapL, hipMemcpyDeviceToDevice, s));
     MPS_TRY_HIP(h, hipMemcpyAsync(ch.chi, chi, A.snapC, hipMemcpyDeviceToDevice, s));
     return MPS_OK;
@@ -916,6 +929,22 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
   const GradItemBuf& g0 = g.it[0];
   std::vector<int32_t> chi(L + 1);
   MPS_TRY_HIP(h, hipMemcpyAsync(chi.data(), ch.chi, (L + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  // complex64 chains: the final state (or the state cotangent) read through a
+  // complex128 copy in the first layer snapshot's B, which the reverse pass
+  // overwrites only later
+  const double2* Bfin = (const double2*)ch.B;
+  const double2* seedB = (const double2*)dB_seed;
+  if (c64) {
+    double2* tmpB;
+    double* tmpL;
+    int32_t* tmpC;
+    A.ptrs(lay, tmpB, tmpL, tmpC);
+    MPS_TRY_HIP(h, launch_convert(s, seeded ? dB_seed : ch.B, tmpB, (long long)L * site_el, false));
+    if (seeded)
+      seedB = tmpB;
+    else
+      Bfin = tmpB;
+  }
   if (seeded) {
     // the state cotangents as given: site i's block of B (capacity layout
     // [chi_max][d][chi_max]) into the reverse pass's compact [chi_i][d][chi_i+1]
@@ -923,7 +952,7 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
     K1((fill_zero_kernel<<<g1d((long long)L * site_el), 256, 0, s>>>(Bbar, (long long)L * site_el)));
     for (int i = 0; i < L; ++i)
       K1((site_copy_kernel<<<g1d((long long)chi[i] * d * chi[i + 1]), 256, 0, s>>>(
-          (const double2*)dB_seed + (size_t)i * site_el, bbar(i), chi[i], d, chi[i + 1], cm, 1)));
+          seedB + (size_t)i * site_el, bbar(i), chi[i], d, chi[i + 1], cm, 1)));
     MPS_TRY_HIP(h, hipMemcpyAsync(lbar, dLam_seed, (size_t)(L + 1) * cm * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   if (!seeded) {  // seeding from the loss
@@ -945,7 +974,7 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
     if (w1[i] == 0.0) continue;
     // site term w <O1>_i = w sum_a lam_a^2 <B_a|O1|B_a>: B_bar += 2 w lam^2 O1 B, lam_bar += 2 w lam Re<B, O1 B>
     const int a = chi[i], b2 = chi[i + 1];
-    K1((site_copy_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>((const double2*)ch.B + i * site_el, g0.Bbs, a, d,
+    K1((site_copy_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>(Bfin + i * site_el, g0.Bbs, a, d,
                                                                      b2, cm, 1)));
     K1((apply_local_kernel<<<g1d((long long)a * b2), 256, 0, s>>>((const double2*)op1, d, g0.Bbs, g0.T0, a, b2, 0, 0)));
     K1((row_scale_kernel<<<g1d((long long)a * d * b2), 256, 0, s>>>(g0.T0, bbar(i), a * d, b2, ch.lam + (size_t)i * cm,
@@ -958,9 +987,9 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
     for (int b = 0; b < L - 1; ++b) {
       if (w2[b] == 0.0) continue;
       const int chl = chi[b], chm = chi[b + 1], chr = chi[b + 2], m = chl * d, n = d * chr;
-      K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>((const double2*)ch.B + b * site_el, g0.Bbs, chl, d,
+      K1((site_copy_kernel<<<g1d((long long)m * chm), 256, 0, s>>>(Bfin + b * site_el, g0.Bbs, chl, d,
                                                                     chm, cm, 1)));
-      K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>((const double2*)ch.B + (b + 1) * site_el, g0.Bns,
+      K1((site_copy_kernel<<<g1d((long long)chm * n), 256, 0, s>>>(Bfin + (b + 1) * site_el, g0.Bns,
                                                                     chm, d, chr, cm, 1)));
       if ((r = gemm128(c, g0.Bbs, chm, 1, 0, g0.Bns, n, 1, 0, g0.T0, n, m, n, chm, 1.0)) != MPS_OK) return r;
       K1((row_scale_kernel<<<g1d((long long)m * n), 256, 0, s>>>(g0.T0, g0.T1, m, n, ch.lam + (size_t)b * cm, d, 1, 1.0,
@@ -1003,6 +1032,10 @@ static mps_status tebd_grad_impl(mps_handle h, mps_stream stream, const mps_chai
       A.ptrs(lay + (size_t)li * A.snap, SB, SL, SC);
       if (li < n_lay - 1) {
         A.ptrs(lay + (size_t)(li + 1) * A.snap, NB, NL, NC);
+      } else if (c64) {
+        // the state after the step's last layer is the next step's checkpoint
+        // (the re-run is deterministic), there in complex128
+        A.ptrs(arena + A.oCk + (size_t)(stp + 1) * A.snap, NB, NL, NC);
       } else {
         NB = (double2*)ch.B;
         NL = ch.lam;

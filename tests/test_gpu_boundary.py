@@ -264,7 +264,7 @@ def test_checkpointed_vjp_tebd4_matches_oracle(H):
         for i in range(sp.L):
             a, r = int(chis[i]), int(chis[i + 1])
             Bi = B[i, :a, :, :r]
-            OB = torch.einsum("st,atc->asc", szt, Bi)
+            OB = torch.einsum("st,atc->asc", szt.to(Bi.dtype), Bi)
             loss = loss + weights[c][i] * torch.sum(lam[i, :a] ** 2 * torch.real(torch.einsum("asc,asc->a",
                                                                                               Bi.conj(), OB)))
     loss.backward()
@@ -378,10 +378,14 @@ def test_jacobi_absolute_tolerance_floor(H):
         H.set_option(2, 1e-15)
 
 
-def test_tebd_step_autograd_function(H):
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_tebd_step_autograd_function(H, dtype):
     """api.TebdStep (forward: checkpointed batched TEBD2, backward:
     mps_tebd_step_vjp) under torch.autograd, for a loss computed by torch
-    from the final states, against the oracle's reverse-mode gradient."""
+    from the final states, against the oracle's reverse-mode gradient:
+    1e-6 relative for complex128 chains, 1e-4 for complex64 ones (forward on
+    FP32 MFMA, reverse pass in FP64; the bar of the complex64 gradient test;
+    measured 1.9e-5 and 3.9e-5)."""
     from oracle import grad, models as om
     from paper_1703_00387_amd import api, models
     dt, n_steps, chi, eps = 0.05, 5, 8, 1e-12
@@ -399,14 +403,15 @@ def test_tebd_step_autograd_function(H):
     szt = torch.from_numpy(sz.astype(np.complex128)).cuda()
     weights = [W.random_real((sp.L,), (93, c), -1.0, 1.0) for c, sp in enumerate(specs)]
     print("[boundary] TebdStep forward", flush=True)
-    outs = api.TebdStep.apply(J, H, [W.initial_vectors(sp) for sp in specs], chi, h0s, dt, n_steps, eps, 1e-12)
+    outs = api.TebdStep.apply(J, H, [W.initial_vectors(sp) for sp in specs], chi, h0s, dt, n_steps, eps, 1e-12, 2,
+                              dtype)
     loss = torch.zeros((), dtype=torch.float64, device="cuda")
     for c, sp in enumerate(specs):
         B, lam, chis = outs[3 * c], outs[3 * c + 1], outs[3 * c + 2].cpu().numpy()
         for i in range(sp.L):
             a, r = int(chis[i]), int(chis[i + 1])
             Bi = B[i, :a, :, :r]
-            OB = torch.einsum("st,atc->asc", szt, Bi)
+            OB = torch.einsum("st,atc->asc", szt.to(Bi.dtype), Bi)
             loss = loss + weights[c][i] * torch.sum(lam[i, :a] ** 2 * torch.real(torch.einsum("asc,asc->a",
                                                                                               Bi.conj(), OB)))
     print("[boundary] TebdStep backward", flush=True)
@@ -418,8 +423,8 @@ def test_tebd_step_autograd_function(H):
         lo = sum(weights[c][i] * grad.site_expect_torch(Bt, lt, sz, i) for i in range(sp.L))
         lo.backward()
         rel = np.linalg.norm(g[c, :sp.L - 1] - Jt.grad.numpy()) / np.linalg.norm(Jt.grad.numpy())
-        print(f"[boundary] TebdStep chain L={sp.L}: rel {rel:.2e}", flush=True)
-        assert rel <= 1e-6
+        print(f"[boundary] TebdStep {dtype} chain L={sp.L}: rel {rel:.2e}", flush=True)
+        assert rel <= (1e-6 if dtype == "c128" else 1e-4)
         assert np.all(g[c, sp.L - 1:] == 0.0)
 
 
