@@ -24,7 +24,8 @@ element by element, through the C ABI.
   TEBD2 dt = 0.05, 40 steps): dLoss/dJ against the oracle's reverse mode at
   the same broadening (1e-5 relative, the gradient bar), and, with the
   broadening at 1e-16, against central differences of the oracle run on
-  three bonds (1e-5 relative).
+  three bonds (1e-5 relative); a complex64 chain's gradient against the same
+  reverse mode (1e-3 relative: the FP32 forward's rounding).
 * Eight chains of the batched workload at their drawn L and chi_max, one
   batch, ten TEBD2 steps: <S^z_i> of each against its oracle run alone.
 """
@@ -231,8 +232,8 @@ def test_gradient_workload_against_oracle(H):
     unit.J_b = np.ones(L - 1)
     h0 = models.bond_hamiltonians(unit)
     sz = models.sz_operator()
-    def gpu_grad(eta):
-        ch = api.Chain.product(W.initial_vectors(spec), chi, models.bond_hamiltonians(spec))
+    def gpu_grad(eta, dtype="c128"):
+        ch = api.Chain.product(W.initial_vectors(spec), chi, models.bond_hamiltonians(spec), dtype=dtype)
         H.device_status()
         print(f"[fullsize] gradient L={L} chi_max={chi} steps={wl.n_steps} eta={eta:g}", flush=True)
         loss, dJ = api.tebd_grad(H, ch, h0, wl.dt, wl.n_steps, wl.eps_local, sz, L // 2 - 1, np.kron(sz, sz),
@@ -261,6 +262,16 @@ def test_gradient_workload_against_oracle(H):
     assert abs(loss - lo) <= 1e-9
     assert rel <= 1e-5
     assert fd_rel <= 1e-5
+    # complex64 chains (forward on FP32 MFMA, reverse pass in FP64): the
+    # forward's FP32 rounding over about 3,700 updates reaches the loss (63
+    # observables, each within the complex64 bars) and, amplified by the
+    # broadened truncated-SVD backward, the gradient (measured: 3.1e-6 and
+    # 3.6e-4 relative)
+    loss64, dJ64 = gpu_grad(1e-12, "c64")
+    rel64 = np.linalg.norm(dJ64 - g_rev) / np.linalg.norm(g_rev)
+    print(f"[fullsize] gradient complex64: |dloss| {abs(loss64 - lo):.2e}, rel vs reverse {rel64:.2e}", flush=True)
+    assert abs(loss64 - lo) <= 1e-5
+    assert rel64 <= 1e-3
 
 
 @pytest.mark.timeout(600)
