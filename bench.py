@@ -727,7 +727,8 @@ def bench_grad(args):
     h.set_option(7, 1.0 if args.split == "eig" else 0.0)
 
     def fresh():
-        return api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec))
+        return api.Chain.product(W.initial_vectors(spec), spec.chi_max, models.bond_hamiltonians(spec),
+                                 dtype=args.dtype)
 
     ch = fresh()
     torch.cuda.synchronize()
@@ -748,7 +749,8 @@ def bench_grad(args):
         "metric": "differentiated TEBD2 two-site updates/s (forward + adjoint, XXZ L=32, chi_max=128, 40 steps)",
         "value": round(upd / t_grad, 3), "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(t_grad * 1e3 / wl.n_steps, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "vs_baseline": None, "dtype": args.dtype if args.dtype == "c128" else "c64 (FP32 MFMA forward, FP64 reverse pass)",
+        "data": "synthetic",
         "config": {"workload": "xxz_grad_L32: TEBD2 XXZ L=32 chi_max=128 J_b~U(0.8,1.2) Neel dt=0.05 40 steps, "
                                "loss <S^z_16> + sum_b <S^z_b S^z_b+1>", "updates": upd},
         "gradient_s": round(t_grad, 3), "forward_only_s": round(t_fwd, 3),
