@@ -93,8 +93,8 @@ def main():
                     help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: the library runs on one GPU and has no multi-GPU path (asked for --gpus {args.gpus}).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on one GPU and has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -749,7 +749,8 @@ def bench_grad(args):
         "metric": "differentiated TEBD2 two-site updates/s (forward + adjoint, XXZ L=32, chi_max=128, 40 steps)",
         "value": round(upd / t_grad, 3), "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(t_grad * 1e3 / wl.n_steps, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": args.dtype if args.dtype == "c128" else "c64 (FP32 MFMA forward, FP64 reverse pass)",
+        "vs_baseline": None,
+        "dtype": args.dtype if args.dtype == "c128" else "c64 (FP32 MFMA forward, FP64 reverse pass)",
         "data": "synthetic",
         "config": {"workload": "xxz_grad_L32: TEBD2 XXZ L=32 chi_max=128 J_b~U(0.8,1.2) Neel dt=0.05 40 steps, "
                                "loss <S^z_16> + sum_b <S^z_b S^z_b+1>", "updates": upd},
