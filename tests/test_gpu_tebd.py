@@ -330,18 +330,11 @@ def test_plain_form_equals_batched(H):
         assert torch.equal(x.chi, y.chi) and torch.equal(x.B, y.B) and torch.equal(x.lam, y.lam)
 
 
-@pytest.mark.parametrize("warm", [1, 0])
-@pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_long_contractions_canonical_chain(H, dtype, warm):
-    """One TEBD2 step of a seeded random Bose-Hubbard state (L = 6, d = 5) put
-    into Hastings form by the oracle: bond dimensions 1, 5, 25, 125, 25, 5, 1,
-    so the middle update contracts over 125 = 7 * 16 + 13 (many K-chunks and a
-    ragged last one, which the product-state runs above do not reach) and its
-    125 x 125 theta' gets the Jacobi's warm start (Q from the QR of
-    Lambda_l B_b, a partial last panel), here on and off.  Bond dimensions
-    identical, Schmidt values within 1e-11 (c128) or 2e-6 (c64) of the
-    oracle's."""
-    from oracle import mps as omps, models as om
+def _canonical_bh_chain(dtype):
+    """A seeded random Bose-Hubbard state (L = 6, d = 5) in Hastings form from
+    the oracle (bond dimensions 1, 5, 25, 125, 25, 5, 1) as a GPU chain of
+    chi_max = 128, and the oracle's tensors (rounded to the chain precision)."""
+    from oracle import mps as omps
     from paper_1703_00387_amd import api, models
     L, nmax, cm = 6, 4, 128
     spec = W.bh_chain(L, nmax, cm)
@@ -364,6 +357,24 @@ def test_long_contractions_canonical_chain(H, dtype, warm):
                    torch.tensor(prof, dtype=torch.int32).cuda(),
                    torch.from_numpy(np.ascontiguousarray(models.bond_hamiltonians(spec))).cuda(),
                    torch.zeros(L - 1, dtype=torch.float64).cuda())
+    return spec, ch, Bs, [l.copy() for l in psi0.lam]
+
+
+@pytest.mark.parametrize("warm", [1, 0])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_long_contractions_canonical_chain(H, dtype, warm):
+    """One TEBD2 step of a seeded random Bose-Hubbard state (L = 6, d = 5) put
+    into Hastings form by the oracle: bond dimensions 1, 5, 25, 125, 25, 5, 1,
+    so the middle update contracts over 125 = 7 * 16 + 13 (many K-chunks and a
+    ragged last one, which the product-state runs above do not reach) and its
+    125 x 125 theta' gets the Jacobi's warm start (Q from the QR of
+    Lambda_l B_b, a partial last panel), here on and off.  Bond dimensions
+    identical, Schmidt values within 1e-11 (c128) or 2e-6 (c64) of the
+    oracle's."""
+    from oracle import mps as omps, models as om
+    from paper_1703_00387_amd import api
+    spec, ch, Bs, lams = _canonical_bh_chain(dtype)
+    L, d, cm = spec.L, spec.d, spec.chi_max
     H.set_option(9, warm)
     try:
         api.tebd_step(H, [ch], 2, 0.05, 1, 1e-14)
@@ -372,7 +383,7 @@ def test_long_contractions_canonical_chain(H, dtype, warm):
         H.set_option(9, 0)
     code, word = H.device_status()
     assert code == 0, word
-    psi = omps.MPS(Bs, [l.copy() for l in psi0.lam], d)
+    psi = omps.MPS(Bs, lams, d)
     hs = om.bond_hamiltonians(spec)
     for bonds, tau in omps.strang_layers(L, 0.05):
         for b in bonds:
@@ -382,3 +393,29 @@ def test_long_contractions_canonical_chain(H, dtype, warm):
     dl = max(np.abs(lam1[j] - psi.lam[j]).max() for j in range(L + 1))
     print(f"long contractions {dtype} warm {warm}: chis {list(chi1)} max|dlam| {dl:.2e}")
     assert dl <= (1e-11 if dtype == "c128" else 2e-6), dl
+
+
+def test_graph_replay_with_warm_start(H):
+    """The warm start's launches (the QR of Lambda_l B_b and Q^dag theta',
+    sized from capacities, no host synchronisation) captured in the kept
+    graph: two captured TEBD2 steps and a replay equal the same steps run
+    eagerly with fixed sweeps, bit for bit."""
+    from paper_1703_00387_amd import api
+    _, eager, _, _ = _canonical_bh_chain("c128")
+    _, g, _, _ = _canonical_bh_chain("c128")
+    H.set_option(9, 1)
+    try:
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            api.tebd_step(H, [eager], 2, 0.05, 2, 1e-14, flags=0x2)  # fixed sweeps, no host sync
+            api.tebd_step(H, [g], 2, 0.05, 2, 1e-14, flags=0x1)      # captured, replayed
+            api.tebd_step(H, [eager], 2, 0.05, 1, 1e-14, flags=0x2)
+            api.tebd_step(H, [g], 2, 0.05, 1, 1e-14, flags=0x1)      # the kept graph again
+        s.synchronize()
+    finally:
+        H.set_option(9, 0)
+    code, word = H.device_status()
+    assert code == 0, word
+    assert torch.equal(eager.chi, g.chi)
+    assert torch.equal(eager.B, g.B)
+    assert torch.equal(eager.lam, g.lam)
