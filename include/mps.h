@@ -146,7 +146,11 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * complex128 per layer; 0 = the Jacobi starts from theta' itself.  The
  * Jacobi then does about a quarter less work, but a layer's time follows its
  * slowest matrix, whose sweeps the start changes little once the bonds sit
- * at chi_max. */
+ * at chi_max,
+ * 11 = polls a wait of the persistent Jacobi makes before it gives up
+ * (default 1e6, a few seconds; 1 .. 1e8).  A wait that runs out sets
+ * MPS_DEV_SCHED_TIMEOUT and every workgroup of the launch leaves; a tiny
+ * value forces that path, to test its reporting. */
 mps_status mps_set_option(mps_handle h, int option, double value);
 /* Accumulated timing of one kernel class since the last reset:
  * kernel 0 = theta build + gate, 1 = Jacobi round, 2 = selection,

@@ -14,7 +14,6 @@ constexpr int kJacBlock = 32;   // rows per Jacobi block
 constexpr int kFixedSweeps = 20;  // sweeps queued when the host may not synchronise
 constexpr int kLoopInner = 4;     // inner sweeps per outer sweep for single-panel matrices
 constexpr int kEigSweeps = 40;    // eigen split: sweeps of the 64x64 Hermitian Jacobi (it stops when converged)
-constexpr int kSpinLimit = 1000000;  // polls of a persistent Jacobi wait before it gives up (a few seconds)
 constexpr int kSlotGrid = 1024;      // workgroup rows of a slot-mode loop launch
 
 }  // namespace
@@ -131,7 +130,7 @@ mps_status run_jacobi(mps_handle h, hipStream_t s, JacMat* mats, int n, int nb_c
     sc.n = n;
     sc.nb_cap = nb;
     sc.max_sweeps = h->jac_max_sweeps;
-    sc.spin_limit = kSpinLimit;
+    sc.spin_limit = h->jac_spin_limit;
     sc.list = nullptr;
     sc.act = nullptr;
     const int grid = std::max(1, std::min(h->n_cu, n * (nb / 2)));
@@ -193,7 +192,7 @@ mps_status run_jacobi_slots(mps_handle h, hipStream_t s, JacMat* mats, int n_slo
   sc.n = n_slots;
   sc.nb_cap = nb_cap;
   sc.max_sweeps = h->jac_max_sweeps;
-  sc.spin_limit = kSpinLimit;
+  sc.spin_limit = h->jac_spin_limit;
   sc.list = list;
   sc.act = cnt;
   PROF_LAUNCH(h, s, MPS_K_JAC_ROUND,
@@ -547,6 +546,10 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
     case 9:
       if (value != 0.0 && value != 1.0) return mps_fail(h, MPS_ERR_INVALID, "warm start must be 0 or 1");
       h->warm_start = (int)value;
+      return MPS_OK;
+    case 11:
+      if (!(value >= 1.0 && value <= 1.0e8)) return mps_fail(h, MPS_ERR_INVALID, "spin limit must be in [1,1e8]");
+      h->jac_spin_limit = (int)value;
       return MPS_OK;
     default:
       return mps_fail(h, MPS_ERR_INVALID, "unknown option");
@@ -1238,6 +1241,7 @@ mps_status tebd_impl(mps_handle h, mps_stream stream, const mps_chain_desc* chai
   put((uint64_t)h->split_method);
   put((uint64_t)h->jac_persistent);
   put((uint64_t)h->warm_start);
+  put((uint64_t)h->jac_spin_limit);
   put(u1 ? 1 : 0);
   for (int c = 0; c < n_chains; ++c) {
     const mps_chain_desc& ch = chains[c];

@@ -48,6 +48,7 @@ struct mps_context {
   size_t split_bytes = 0;
   char* scratch = nullptr;        // this device's address of the no-allocation entry's scratch array
   int jac_persistent = 1;         // batches without a column split: all sweeps in one persistent launch
+  int jac_spin_limit = 1000000;   // polls of a persistent Jacobi wait before it gives up (a few seconds)
   int warm_start = 0;             // TEBD splits: Jacobi on Q^dag theta', Q from the QR of Lambda_l B_b
   int n_cu = 256;                 // compute units of the device (persistent grid size)
   char* sched = nullptr;          // counters of the persistent Jacobi (kSchedBytes)

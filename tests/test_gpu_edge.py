@@ -188,3 +188,38 @@ def test_nonfinite_bond_in_a_batched_layer_is_flagged(H):
     assert code == _lib.MPS_ERR_NONFINITE and word & _lib.MPS_DEV_NONFINITE, (code, word)
     site, _, _ = api.observe(H, cg, models.sz_operator())
     assert np.abs(site.cpu().numpy() - omps.local_expect(ref, 0.5 * om.SZ)).max() <= 1e-9
+
+
+def test_persistent_wait_timeout_reported_and_handle_recovers(H):
+    """The persistent Jacobi's bounded waits, forced to run out from the host
+    (option 11 = one poll; option 6 = 0, so that no round takes the column
+    split and the batch runs in the persistent launch): the call returns, every
+    workgroup having left; the status word carries MPS_DEV_SCHED_TIMEOUT,
+    reported as MPS_ERR_NOCONV (MPS_ERR_NONFINITE where the incomplete
+    rotations also left a non-finite value); with the options restored the same handle
+    steps a fresh chain cleanly.  Chain: the canonical Bose-Hubbard state of
+    the long-contraction test (a 125-row bond of four row blocks)."""
+    from paper_1703_00387_amd import api, _lib
+    from test_gpu_tebd import _canonical_bh_chain
+    H.device_status()
+    H.set_option(6, 0)
+    H.set_option(11, 1)
+    try:
+        _, ch, _, _ = _canonical_bh_chain("c128")
+        api.tebd_step(H, [ch], 2, 0.05, 1, 1e-14)
+        torch.cuda.synchronize()
+        code, word = H.device_status()
+    finally:
+        H.set_option(11, 1e6)
+        H.set_option(6, 32)
+    print(f"[edge] forced wait timeout: code {code} word {word:#x}", flush=True)
+    assert word & _lib.MPS_DEV_SCHED_TIMEOUT, word
+    assert code in (_lib.MPS_ERR_NOCONV, _lib.MPS_ERR_NONFINITE), code   # the results are incomplete
+    _, ch, _, _ = _canonical_bh_chain("c128")
+    api.tebd_step(H, [ch], 2, 0.05, 1, 1e-14)
+    torch.cuda.synchronize()
+    code, word = H.device_status()
+    assert code == 0 and word == 0, (code, word)
+    _, lam, chi = ch.to_host()
+    assert int(max(chi)) <= 128
+    assert all(np.isfinite(l).all() for l in lam)

@@ -21,7 +21,7 @@ import pytest
 
 from paper_1703_00387_amd import build as B
 
-MFMA_SOURCES = ["theta.hip", "gemm.hip", "heff.hip", "svd.hip"]
+MFMA_SOURCES = ["theta.hip", "gemm.hip", "heff.hip", "svd.hip", "warm.hip"]
 MIN_WAIT = 10
 SEARCH = 30
 
