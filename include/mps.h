@@ -147,7 +147,7 @@ mps_status mps_device_status(mps_handle h, mps_stream stream, uint32_t* word);
  * Jacobi then does about a quarter less work, but a layer's time follows its
  * slowest matrix, whose sweeps the start changes little once the bonds sit
  * at chi_max,
- * 11 = polls a wait of the persistent Jacobi makes before it gives up
+ * 10 = polls a wait of the persistent Jacobi makes before it gives up
  * (default 1e6, a few seconds; 1 .. 1e8).  A wait that runs out sets
  * MPS_DEV_SCHED_TIMEOUT and every workgroup of the launch leaves; a tiny
  * value forces that path, to test its reporting. */

@@ -547,7 +547,7 @@ mps_status mps_set_option(mps_handle h, int option, double value) {
       if (value != 0.0 && value != 1.0) return mps_fail(h, MPS_ERR_INVALID, "warm start must be 0 or 1");
       h->warm_start = (int)value;
       return MPS_OK;
-    case 11:
+    case 10:
       if (!(value >= 1.0 && value <= 1.0e8)) return mps_fail(h, MPS_ERR_INVALID, "spin limit must be in [1,1e8]");
       h->jac_spin_limit = (int)value;
       return MPS_OK;

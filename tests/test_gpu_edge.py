@@ -192,7 +192,7 @@ def test_nonfinite_bond_in_a_batched_layer_is_flagged(H):
 
 def test_persistent_wait_timeout_reported_and_handle_recovers(H):
     """The persistent Jacobi's bounded waits, forced to run out from the host
-    (option 11 = one poll; option 6 = 0, so that no round takes the column
+    (option 10 = one poll; option 6 = 0, so that no round takes the column
     split and the batch runs in the persistent launch): the call returns, every
     workgroup having left; the status word carries MPS_DEV_SCHED_TIMEOUT,
     reported as MPS_ERR_NOCONV (MPS_ERR_NONFINITE where the incomplete
@@ -201,16 +201,20 @@ def test_persistent_wait_timeout_reported_and_handle_recovers(H):
     the long-contraction test (a 125-row bond of four row blocks)."""
     from paper_1703_00387_amd import api, _lib
     from test_gpu_tebd import _canonical_bh_chain
+    for opt, val in [(10, 0), (10, 2e8), (11, 1)]:   # out of range, and no option 11
+        with pytest.raises(_lib.MPSError) as e:
+            H.set_option(opt, val)
+        assert e.value.code == _lib.MPS_ERR_INVALID
     H.device_status()
     H.set_option(6, 0)
-    H.set_option(11, 1)
+    H.set_option(10, 1)
     try:
         _, ch, _, _ = _canonical_bh_chain("c128")
         api.tebd_step(H, [ch], 2, 0.05, 1, 1e-14)
         torch.cuda.synchronize()
         code, word = H.device_status()
     finally:
-        H.set_option(11, 1e6)
+        H.set_option(10, 1e6)
         H.set_option(6, 32)
     print(f"[edge] forced wait timeout: code {code} word {word:#x}", flush=True)
     assert word & _lib.MPS_DEV_SCHED_TIMEOUT, word
